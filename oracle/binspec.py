@@ -1,0 +1,176 @@
+"""Float32 binning: depth keys, tile rectangles, (tile, depth) keys and per-tile ranges.
+
+Appendix A ("Details of the Rasterizer") and Algorithm 2 (CreateTiles,
+DuplicateWithKeys, SortByKeys, IdentifyTileRanges): the image is cut into 16x16
+tiles, every Gaussian is duplicated once per tile it overlaps, each copy gets a
+64-bit key whose upper 32 bits hold the tile index and whose lower 32 bits hold
+the depth, one radix sort orders all copies, and a second pass finds the
+[start, end) range of every tile.
+
+The keys are integers decided by float32 arithmetic, so this module fixes the
+float32 operation order (every step below is one IEEE float32 operation with
+round-to-nearest; no fused multiply-add) and evaluates it with numpy float32
+arrays, which round every operation exactly that way:
+
+  p_r     = ((R_r0 * mx + R_r1 * my) + R_r2 * mz) + t_r          r = x, y, z
+  depth   = p_z;  visible iff depth > 0.2f
+  u       = (fx * p_x) / p_z + cx;   v = (fy * p_y) / p_z + cy
+  n       = ((qw*qw + qx*qx) + qy*qy) + qz*qz;  k = 2 / n
+  Rq      = [[1 - k (qy qy + qz qz), k (qx qy - qw qz), k (qx qz + qw qy)],
+             [k (qx qy + qw qz), 1 - k (qx qx + qz qz), k (qy qz - qw qx)],
+             [k (qx qz - qw qy), k (qy qz + qw qx), 1 - k (qx qx + qy qy)]]
+  M_ij    = Rq_ij * s_j
+  j00 = fx / p_z;  j11 = fy / p_z;  j02 = -(j00 * p_x) / p_z;  j12 = -(j11 * p_y) / p_z
+  T0_k = j00 * R_0k + j02 * R_2k;   T1_k = j11 * R_1k + j12 * R_2k     (R = camera rotation)
+  W0_l = (T0_0 M_0l + T0_1 M_1l) + T0_2 M_2l;   W1_l likewise with T1
+  a   = ((W0_0^2 + W0_1^2) + W0_2^2) + 0.3f;     c likewise with W1
+  e_x = sqrt(KAPPA * a);  e_y = sqrt(KAPPA * c)                     (KAPPA = 11.1f)
+  tx in [max(0, floor((u - e_x)/16)), min(TX-1, floor((u + e_x)/16))], ty likewise
+  culled if not visible, if any of u, v, e_x, e_y is not finite, or if the rect is empty
+
+The products inside a parenthesised pair are rounded before the add.  The box
+half-extent sqrt(KAPPA Sigma2_ii) bounds every point where
+-1/2 d^T Sigma2^-1 d >= -ln 255 (KAPPA > 2 ln 255 = 11.08), so no pixel where
+alpha can reach 1/255 is outside the rect and tiling never changes a result.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import consts
+
+f32 = np.float32
+
+
+def _dot3(r, x, y, z):
+    """((r0*x + r1*y) + r2*z) in float32, r a length-3 float32 vector."""
+    return ((r[0] * x + r[1] * y) + r[2] * z)
+
+
+def bin_quantities(g: dict, cam) -> dict:
+    """Per-Gaussian float32 depth, rect and tile count for one camera."""
+    mu = np.asarray(g["means"], f32)
+    s = np.asarray(g["scales"], f32)
+    q = np.asarray(g["quats"], f32)
+    R = np.asarray(cam.R, f32)
+    t = np.asarray(cam.t, f32)
+    fx, fy, cx, cy = f32(cam.fx), f32(cam.fy), f32(cam.cx), f32(cam.cy)
+    W, H = int(cam.width), int(cam.height)
+    TX, TY = (W + consts.TILE - 1) // consts.TILE, (H + consts.TILE - 1) // consts.TILE
+    mx, my, mz = mu[:, 0], mu[:, 1], mu[:, 2]
+
+    with np.errstate(all="ignore"):
+        px = _dot3(R[0], mx, my, mz) + t[0]
+        py = _dot3(R[1], mx, my, mz) + t[1]
+        pz = _dot3(R[2], mx, my, mz) + t[2]
+        depth = pz
+        visible = depth > consts.Z_NEAR_F32
+        u = (fx * px) / pz + cx
+        v = (fy * py) / pz + cy
+
+        qw, qx, qy, qz = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+        n = ((qw * qw + qx * qx) + qy * qy) + qz * qz
+        k = f32(2.0) / n
+        one = f32(1.0)
+        Rq = np.empty((mu.shape[0], 3, 3), f32)
+        Rq[:, 0, 0] = one - k * (qy * qy + qz * qz)
+        Rq[:, 0, 1] = k * (qx * qy - qw * qz)
+        Rq[:, 0, 2] = k * (qx * qz + qw * qy)
+        Rq[:, 1, 0] = k * (qx * qy + qw * qz)
+        Rq[:, 1, 1] = one - k * (qx * qx + qz * qz)
+        Rq[:, 1, 2] = k * (qy * qz - qw * qx)
+        Rq[:, 2, 0] = k * (qx * qz - qw * qy)
+        Rq[:, 2, 1] = k * (qy * qz + qw * qx)
+        Rq[:, 2, 2] = one - k * (qx * qx + qy * qy)
+        M = Rq * s[:, None, :]
+
+        j00 = fx / pz
+        j11 = fy / pz
+        j02 = -(j00 * px) / pz
+        j12 = -(j11 * py) / pz
+        T0 = [j00 * R[0, kk] + j02 * R[2, kk] for kk in range(3)]
+        T1 = [j11 * R[1, kk] + j12 * R[2, kk] for kk in range(3)]
+        W0 = [(T0[0] * M[:, 0, l] + T0[1] * M[:, 1, l]) + T0[2] * M[:, 2, l] for l in range(3)]
+        W1 = [(T1[0] * M[:, 0, l] + T1[1] * M[:, 1, l]) + T1[2] * M[:, 2, l] for l in range(3)]
+        a = ((W0[0] * W0[0] + W0[1] * W0[1]) + W0[2] * W0[2]) + consts.LOWPASS_F32
+        c = ((W1[0] * W1[0] + W1[1] * W1[1]) + W1[2] * W1[2]) + consts.LOWPASS_F32
+        ex = np.sqrt(consts.KAPPA_F32 * a)
+        ey = np.sqrt(consts.KAPPA_F32 * c)
+
+        ts = f32(consts.TILE)
+        x0f = np.floor((u - ex) / ts)
+        x1f = np.floor((u + ex) / ts)
+        y0f = np.floor((v - ey) / ts)
+        y1f = np.floor((v + ey) / ts)
+        finite = np.isfinite(u) & np.isfinite(v) & np.isfinite(ex) & np.isfinite(ey)
+        ok = visible & finite
+        x0 = np.where(ok, np.maximum(x0f, f32(0)), f32(0))
+        x1 = np.where(ok, np.minimum(x1f, f32(TX - 1)), f32(-1))
+        y0 = np.where(ok, np.maximum(y0f, f32(0)), f32(0))
+        y1 = np.where(ok, np.minimum(y1f, f32(TY - 1)), f32(-1))
+    x0, x1, y0, y1 = (np.asarray(z, np.float64).astype(np.int64) for z in (x0, x1, y0, y1))
+    nonempty = ok & (x0 <= x1) & (y0 <= y1)
+    ntiles = np.where(nonempty, (x1 - x0 + 1) * (y1 - y0 + 1), 0).astype(np.int64)
+    return dict(depth=depth.astype(f32), visible=visible & finite, binned=nonempty,
+                x0=x0, x1=x1, y0=y0, y1=y1, ntiles=ntiles, tiles_x=TX, tiles_y=TY,
+                u32=u.astype(f32), v32=v.astype(f32), ex=ex.astype(f32), ey=ey.astype(f32))
+
+
+def duplicate_with_keys(bq_list: list) -> dict:
+    """Instances of all views, in (view, Gaussian index, row-major tile) order.
+
+    Returns keys (uint64, tile << 32 | depth bits), the Gaussian index of every
+    instance, and the global tile offset of every view.
+    """
+    keys, gids, views = [], [], []
+    tile_off = 0
+    offsets = []
+    for vi, bq in enumerate(bq_list):
+        offsets.append(tile_off)
+        idx = np.nonzero(bq["binned"])[0]
+        nt = bq["ntiles"][idx]
+        gid = np.repeat(idx, nt)
+        # position of each instance within its Gaussian's rect, row-major
+        starts = np.cumsum(nt) - nt
+        local = np.arange(int(nt.sum()), dtype=np.int64) - np.repeat(starts, nt)
+        wdt = (bq["x1"] - bq["x0"] + 1)[gid]
+        tx = bq["x0"][gid] + local % wdt
+        ty = bq["y0"][gid] + local // wdt
+        tile = tile_off + ty * bq["tiles_x"] + tx
+        dbits = bq["depth"].view(np.uint32)[gid].astype(np.uint64)
+        keys.append((tile.astype(np.uint64) << np.uint64(32)) | dbits)
+        gids.append(gid.astype(np.int64))
+        views.append(np.full(gid.shape, vi, np.int64))
+        tile_off += bq["tiles_x"] * bq["tiles_y"]
+    return dict(keys=np.concatenate(keys) if keys else np.zeros(0, np.uint64),
+                gids=np.concatenate(gids) if gids else np.zeros(0, np.int64),
+                views=np.concatenate(views) if views else np.zeros(0, np.int64),
+                tile_offsets=np.asarray(offsets, np.int64), num_tiles=tile_off)
+
+
+def sort_and_ranges(inst: dict) -> dict:
+    """Stable sort by key, then [start, end) of every tile ((0, 0) if empty)."""
+    order = np.argsort(inst["keys"], kind="stable")
+    skeys = inst["keys"][order]
+    sgids = inst["gids"][order]
+    ntl = int(inst["num_tiles"])
+    tiles = (skeys >> np.uint64(32)).astype(np.int64)
+    ranges = np.zeros((ntl, 2), np.int64)
+    if skeys.size:
+        first = np.ones(skeys.size, bool)
+        first[1:] = tiles[1:] != tiles[:-1]
+        last = np.ones(skeys.size, bool)
+        last[:-1] = tiles[1:] != tiles[:-1]
+        pos = np.arange(skeys.size)
+        ranges[tiles[first], 0] = pos[first]
+        ranges[tiles[last], 1] = pos[last] + 1
+    return dict(keys=skeys, gids=sgids, order=order, ranges=ranges)
+
+
+def bin_views(g: dict, cams: list) -> dict:
+    """The whole binning step for a list of cameras."""
+    bq = [bin_quantities(g, c) for c in cams]
+    inst = duplicate_with_keys(bq)
+    srt = sort_and_ranges(inst)
+    return dict(per_view=bq, tile_offsets=inst["tile_offsets"], num_tiles=inst["num_tiles"],
+                keys=srt["keys"], gids=srt["gids"], ranges=srt["ranges"])

@@ -1,0 +1,106 @@
+"""Per-pixel brute force without tiles, in torch float64 on the CPU.
+
+The plain definition of what the tiled method computes: for every pixel, take
+every visible Gaussian (camera depth beyond the near plane, float32 depth as
+the binning decides it), order them by (depth, index), and composite front to
+back (Section 3.1: c = sum_i c_i w_i, w_i = alpha_i T_i, T_i = prod_{j<i}
+(1 - alpha_j)) with the skip and stop rules of the rasterizer.  No tiles, no
+keys, no ranges.  Written with torch float64 operations so that autograd gives
+gradients that do not depend on the hand-written adjoint; intended for scenes
+of at most a few hundred Gaussians and a few thousand pixels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binspec, consts, sh
+
+
+def _sh_torch(degree: int, d: torch.Tensor) -> torch.Tensor:
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    cols = []
+    for b in range(sh.num_bases(degree)):
+        acc = torch.zeros_like(x)
+        for (i, j, k), c in sh._POLYS[b].items():
+            acc = acc + c * x ** i * y ** j * z ** k
+        cols.append(acc)
+    return torch.stack(cols, 1)
+
+
+def _rot(qn: torch.Tensor) -> torch.Tensor:
+    w, x, y, z = qn.unbind(1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1),
+    ], 1)
+
+
+def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
+    """params: float64 torch leaves means [N,3], scales [N,3], quats [N,4],
+    opacity [N], sh [N,B,3].  Returns C [P,3], F [P,D] or None, T [P], niter [P]."""
+    bq = binspec.bin_quantities(g_meta, cam)
+    vis = np.nonzero(bq["visible"])[0]
+    order = vis[np.lexsort((vis, bq["depth"][vis]))]
+
+    mu, s, q, op, shc = (params[k] for k in ("means", "scales", "quats", "opacity", "sh"))
+    Rc = torch.tensor(np.asarray(cam.R, np.float64))
+    tc = torch.tensor(np.asarray(cam.t, np.float64))
+    fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    p = mu @ Rc.T + tc
+    u = fx * p[:, 0] / p[:, 2] + cx
+    v = fy * p[:, 1] / p[:, 2] + cy
+    qn = q / q.norm(dim=1, keepdim=True)
+    M = _rot(qn) * s[:, None, :]
+    S3 = M @ M.transpose(1, 2)
+    zero = torch.zeros_like(p[:, 2])
+    J = torch.stack([torch.stack([fx / p[:, 2], zero, -fx * p[:, 0] / p[:, 2] ** 2], 1),
+                     torch.stack([zero, fy / p[:, 2], -fy * p[:, 1] / p[:, 2] ** 2], 1)], 1)
+    Tm = J @ Rc
+    S2 = Tm @ S3 @ Tm.transpose(1, 2)
+    a = S2[:, 0, 0] + consts.LOWPASS
+    b = S2[:, 0, 1]
+    c = S2[:, 1, 1] + consts.LOWPASS
+    det = a * c - b * b
+    A, B, C = c / det, -b / det, a / det
+    campos = -Rc.T @ tc
+    dv = mu - campos
+    dirn = dv / dv.norm(dim=1, keepdim=True)
+    Y = _sh_torch(int(g_meta["sh_degree"]), dirn)
+    rgb = torch.clamp(torch.einsum("nb,nbc->nc", Y, shc) + 0.5, min=0.0)
+
+    W, H = int(cam.width), int(cam.height)
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64), torch.arange(W, dtype=torch.float64),
+                            indexing="ij")
+    x = xx.reshape(-1) + 0.5
+    y = yy.reshape(-1) + 0.5
+    P = W * H
+    T = torch.ones(P, dtype=torch.float64)
+    col = torch.zeros(P, 3, dtype=torch.float64)
+    featt = None if feat is None else torch.tensor(np.asarray(feat, np.float64))
+    F = None if featt is None else torch.zeros(P, featt.shape[1], dtype=torch.float64)
+    done = torch.zeros(P, dtype=torch.bool)
+    niter = torch.zeros(P, dtype=torch.int64)
+    for pos, gi in enumerate(order.tolist()):
+        dx = x - u[gi]
+        dy = y - v[gi]
+        power = -0.5 * (A[gi] * dx * dx + 2.0 * B[gi] * dx * dy + C[gi] * dy * dy)
+        alpha = torch.clamp(op[gi] * torch.exp(power), max=consts.ALPHA_MAX)
+        ok = (alpha.detach() >= consts.ALPHA_MIN) & ~done
+        Tn = T * (1.0 - alpha)
+        stop = ok & (Tn.detach() < consts.T_MIN)
+        done = done | stop
+        contrib = ok & ~stop
+        w = torch.where(contrib, alpha * T, torch.zeros_like(T))
+        col = col + w[:, None] * rgb[gi][None, :]
+        if F is not None:
+            F = F + w[:, None] * featt[gi][None, :]
+        T = torch.where(contrib, Tn, T)
+        niter = torch.where(contrib, torch.full_like(niter, pos + 1), niter)
+    return col, F, T, niter, order
+
+
+def leaves(g: dict) -> dict:
+    return {k: torch.tensor(np.asarray(g[k], np.float64), requires_grad=True)
+            for k in ("means", "scales", "quats", "opacity", "sh")}

@@ -1,0 +1,81 @@
+"""The whole oracle path for one scene: bin (float32), project (FP64), composite
+and adjoint per pixel (FP64, C), chain the adjoint back to the 3D parameters.
+
+Algorithm 2's order: screen-space Gaussians, tile grid, duplicate with keys,
+sort, tile ranges, then the per-tile, per-pixel traversal.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import binspec, project, raster
+
+
+def view_slice(bins: dict, vi: int, cam) -> np.ndarray:
+    """This view's block of the global per-tile ranges."""
+    t0 = int(bins["tile_offsets"][vi])
+    ntl = bins["per_view"][vi]["tiles_x"] * bins["per_view"][vi]["tiles_y"]
+    return bins["ranges"][t0:t0 + ntl]
+
+
+def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = False,
+        tile_sel: list | None = None, want_F: bool = True, want_dfeat: bool = False,
+        want_Fmag: bool = False, magnitudes: bool = True) -> dict:
+    """Forward (and adjoint when view_tensors is given) for every camera.
+
+    view_tensors[v] holds dC [P,3], dF [P,D], dT [P] and, for fusion, target [P,D].
+    tile_sel[v] optionally restricts the traversal to some of view v's tiles.
+    """
+    bins = binspec.bin_views(g, cams)
+    feat = np.asarray(g["feat"], np.float64) if g["feat"] is not None else None
+    n = g["means"].shape[0]
+    views = []
+    grads = None
+    grads_mag = None
+    fsum = wsum = fsum_mag = dfeat = None
+    gflags = np.zeros(n, np.int32)
+    counts = np.zeros(3, np.int64)
+    for vi, cam in enumerate(cams):
+        pr = project.project(g, cam)
+        vt = view_tensors[vi] if view_tensors is not None else None
+        out = raster.render_view(
+            cam, view_slice(bins, vi, cam), bins["gids"], pr, feat=feat,
+            dC=None if vt is None else vt["dC"], dF=None if vt is None else vt["dF"],
+            dT=None if vt is None else vt["dT"],
+            target=None if (vt is None or not fusion) else vt["target"],
+            tile_sel=None if tile_sel is None else tile_sel[vi], want_F=want_F,
+            want_Fmag=want_Fmag, want_fusion=fusion, want_dfeat=want_dfeat)
+        counts += out["counts"]
+        gflags |= out["gflags"]
+        rec = dict(C=out["C"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
+                   flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"])
+        if vt is not None:
+            up = _unpack(out["g2d"])
+            gv = project.project_bwd(pr, up)
+            grads = gv if grads is None else {k: grads[k] + gv[k] for k in grads}
+            if magnitudes:
+                upm = _unpack(out["g2d_mag"])
+                gm = project.project_bwd(pr, upm, magnitude=True)
+                grads_mag = gm if grads_mag is None else {k: grads_mag[k] + gm[k] for k in grads_mag}
+            if fusion:
+                fsum = out["fsum"] if fsum is None else fsum + out["fsum"]
+                fsum_mag = out["fsum_mag"] if fsum_mag is None else fsum_mag + out["fsum_mag"]
+                wsum = out["wsum"] if wsum is None else wsum + out["wsum"]
+            if want_dfeat:
+                dfeat = out["dfeat"] if dfeat is None else dfeat + out["dfeat"]
+        views.append(rec)
+    return dict(bins=bins, views=views, grads=grads, grads_mag=grads_mag, fsum=fsum,
+                fsum_mag=fsum_mag, wsum=wsum, dfeat=dfeat, gflags=gflags, counts=counts)
+
+
+def _unpack(g2d: np.ndarray) -> dict:
+    return dict(u=g2d[:, 0], v=g2d[:, 1], A=g2d[:, 2], B=g2d[:, 3], C=g2d[:, 4],
+                opacity=g2d[:, 5], rgb=g2d[:, 6:9])
+
+
+def finalize_fusion(fsum: np.ndarray, wsum: np.ndarray, feat_in: np.ndarray) -> np.ndarray:
+    """f_hat = fsum / wsum where wsum > 0; Gaussians never blended keep their feature."""
+    out = np.array(feat_in, np.float64, copy=True)
+    hit = wsum > 0
+    out[hit] = fsum[hit] / wsum[hit, None]
+    return out

@@ -1,0 +1,261 @@
+/*
+ * FP64 per-pixel compositing, adjoint and feature fusion for the CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY: called through ctypes by the oracle package; the
+ * product library never links or calls it, and it includes nothing of it.
+ *
+ * Traversal (Algorithm 2): for every tile, for every pixel of the tile, walk
+ * the tile's depth-sorted range front to back.  For Gaussian g at pixel centre
+ * (x, y) = (px + 1/2, py + 1/2):
+ *     dx = x - u_g, dy = y - v_g
+ *     G  = exp(-1/2 (A dx^2 + 2 B dx dy + C dy^2))
+ *     alpha = min(ALPHA_MAX, o_g G);  skip the blend if alpha < ALPHA_MIN
+ *     T' = T (1 - alpha);  if T' < T_MIN stop (this Gaussian is excluded)
+ *     w = alpha T;  C += w rgb_g;  F += w f_g;  T = T';  n_iter = position + 1
+ * This is the colour equation of Section 3.1 with w_i = alpha_i T_i and
+ * T_i = prod_{j<i} (1 - alpha_j), nearest Gaussian first.
+ *
+ * Adjoint (Appendix A.2, derivative of the loss with respect to alpha_k, plus
+ * the final-transmittance term): with g_k = rgb_k . dC + f_k . dF,
+ *     dL/dalpha_k = T_k g_k - (S_k + T_final dT) / (1 - alpha_k),
+ *     S_k = sum_{i > k} w_i g_i,
+ * then dL/dpower = alpha dL/dalpha and dL/do = G dL/dalpha where alpha is not
+ * clamped, and power's partials in (u, v, A, B, C).  dL/drgb_k = w_k dC.
+ *
+ * Fusion (w-weighted transpose of feature rendering): fsum_g += w_g(p) t(p),
+ * wsum_g += w_g(p).
+ *
+ * Every floating-point operation is FP64.  Magnitude companions (sums of the
+ * absolute values of the same terms) are accumulated alongside.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ALPHA_MAX 0.99
+#define ALPHA_MIN (1.0 / 255.0)
+#define T_MIN 1e-4
+
+typedef struct {
+    /* image and tiling */
+    int64_t width, height, tile, tiles_x, tiles_y;
+    int64_t d;                       /* feature channels (0 allowed) */
+    double ambig_rel;                /* relative threshold distance called ambiguous */
+    /* binning result for this view */
+    const int64_t *ranges;           /* [tiles, 2] */
+    const int64_t *list;             /* [M] Gaussian index per sorted instance */
+    /* per-Gaussian projected quantities (FP64) */
+    const double *u, *v, *A, *B, *C, *opac;
+    const double *rgb;               /* [N, 3] */
+    const double *feat;              /* [N, d] or NULL */
+    /* per-pixel upstream adjoints (NULL: forward only) */
+    const double *dC;                /* [P, 3] */
+    const double *dF;                /* [P, d] or NULL */
+    const double *dT;                /* [P] or NULL */
+    const double *target;            /* [P, d] or NULL: fusion target */
+    /* tiles to process (NULL: all) */
+    const int64_t *tile_sel;
+    int64_t n_tile_sel;
+    /* per-pixel outputs */
+    double *out_C;                   /* [P, 3] */
+    double *out_F;                   /* [P, d] or NULL */
+    double *out_Fmag;                /* [P, d] or NULL */
+    double *out_T;                   /* [P] */
+    int64_t *out_niter;              /* [P] */
+    int32_t *out_flags;              /* [P] bit0: decision near a threshold, bit1: alpha near the clamp */
+    /* per-Gaussian outputs, accumulated (caller zeroes) */
+    double *g2d;                     /* [N, 9]: u v A B C o r g b, or NULL */
+    double *g2d_mag;                 /* [N, 9] or NULL */
+    double *fsum;                    /* [N, d] or NULL */
+    double *fsum_mag;                /* [N, d] or NULL */
+    double *wsum;                    /* [N] or NULL */
+    double *dfeat;                   /* [N, d] or NULL: dL/df = sum_p w dF */
+    int32_t *gflags;                 /* [N] or NULL: OR of flags of pixels whose walk reached g */
+    int64_t *counts;                 /* [3]: sum n_iter, contributing blends, alpha evaluations */
+} oracle_args;
+
+typedef struct {
+    int64_t g;
+    double alpha, T, G, dx, dy;
+    int clamped;
+} blend_rec;
+
+static void atomic_add(double *p, double x) {
+#pragma omp atomic
+    *p += x;
+}
+
+static int near_rel(double x, double thr, double rel) { return fabs(x - thr) <= rel * thr; }
+
+static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, double *gvec, double *gmag) {
+    const int64_t ty = tile / a->tiles_x, tx = tile % a->tiles_x;
+    const int64_t start = a->ranges[2 * tile], end = a->ranges[2 * tile + 1];
+    const int64_t d = a->d;
+    int64_t local_counts[3] = {0, 0, 0};
+    for (int64_t py = ty * a->tile; py < (ty + 1) * a->tile && py < a->height; ++py) {
+        for (int64_t px = tx * a->tile; px < (tx + 1) * a->tile && px < a->width; ++px) {
+            const int64_t pix = py * a->width + px;
+            const double x = (double)px + 0.5, y = (double)py + 0.5;
+            double T = 1.0, col[3] = {0, 0, 0};
+            double *F = a->out_F ? a->out_F + pix * d : NULL;
+            double *Fm = a->out_Fmag ? a->out_Fmag + pix * d : NULL;
+            if (F) memset(F, 0, sizeof(double) * d);
+            if (Fm) memset(Fm, 0, sizeof(double) * d);
+            int64_t niter = 0, nrec = 0, last_eval = start - 1;
+            int32_t flags = 0;
+            /* ---- forward, front to back ---- */
+            for (int64_t pos = start; pos < end; ++pos) {
+                const int64_t g = a->list[pos];
+                const double dx = x - a->u[g], dy = y - a->v[g];
+                const double power = -0.5 * (a->A[g] * dx * dx + 2.0 * a->B[g] * dx * dy + a->C[g] * dy * dy);
+                const double G = exp(power);
+                const double raw = a->opac[g] * G;
+                const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
+                last_eval = pos;
+                local_counts[2]++;
+                if (near_rel(raw, ALPHA_MAX, a->ambig_rel)) flags |= 2;
+                if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) flags |= 1;
+                if (alpha < ALPHA_MIN) continue;
+                const double Tn = T * (1.0 - alpha);
+                if (near_rel(Tn, T_MIN, a->ambig_rel)) flags |= 1;
+                if (Tn < T_MIN) break;
+                const double w = alpha * T;
+                for (int c = 0; c < 3; ++c) col[c] += w * a->rgb[3 * g + c];
+                if (F && a->feat)
+                    for (int64_t k = 0; k < d; ++k) F[k] += w * a->feat[g * d + k];
+                if (Fm && a->feat)
+                    for (int64_t k = 0; k < d; ++k) Fm[k] += w * fabs(a->feat[g * d + k]);
+                blend_rec *r = &recs[nrec++];
+                r->g = g; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
+                r->clamped = raw >= ALPHA_MAX;
+                T = Tn;
+                niter = pos - start + 1;
+                local_counts[1]++;
+            }
+            local_counts[0] += niter;
+            for (int c = 0; c < 3; ++c) a->out_C[3 * pix + c] = col[c];
+            a->out_T[pix] = T;
+            a->out_niter[pix] = niter;
+            if (a->out_flags) a->out_flags[pix] = flags;
+            if (flags && a->gflags)
+                for (int64_t pos = start; pos <= last_eval; ++pos) {
+#pragma omp atomic
+                    a->gflags[a->list[pos]] |= flags;
+                }
+            if (!a->dC) continue;
+            /* ---- adjoint, back to front over the contributing blends ---- */
+            const double *dC = a->dC + 3 * pix;
+            const double *dF = (a->dF && a->feat) ? a->dF + pix * d : NULL;
+            const double dT = a->dT ? a->dT[pix] : 0.0;
+            const double *tgt = a->target ? a->target + pix * d : NULL;
+            const double Tfin = T;
+            double S = 0.0, Sm = 0.0;
+            for (int64_t i = nrec - 1; i >= 0; --i) {
+                const blend_rec *r = &recs[i];
+                const int64_t g = r->g;
+                const double w = r->alpha * r->T;
+                double gk = 0.0, gkm = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    gk += a->rgb[3 * g + c] * dC[c];
+                    gkm += fabs(a->rgb[3 * g + c] * dC[c]);
+                }
+                if (dF)
+                    for (int64_t k = 0; k < d; ++k) {
+                        gk += a->feat[g * d + k] * dF[k];
+                        gkm += fabs(a->feat[g * d + k] * dF[k]);
+                    }
+                const double inv1ma = 1.0 / (1.0 - r->alpha);
+                const double dalpha = r->T * gk - (S + Tfin * dT) * inv1ma;
+                const double dalpham = r->T * gkm + (Sm + Tfin * fabs(dT)) * inv1ma;
+                S += w * gk;
+                Sm += w * gkm;
+                double dpow = 0.0, dpowm = 0.0, dop = 0.0, dopm = 0.0;
+                if (!r->clamped) {
+                    dpow = dalpha * r->alpha;
+                    dpowm = dalpham * r->alpha;
+                    dop = dalpha * r->G;
+                    dopm = dalpham * r->G;
+                }
+                const double dx = r->dx, dy = r->dy;
+                const double A = a->A[g], B = a->B[g], Cc = a->C[g];
+                /* power = -1/2 (A dx^2 + 2 B dx dy + C dy^2), dx = x - u */
+                gvec[0] = dpow * (A * dx + B * dy);
+                gvec[1] = dpow * (B * dx + Cc * dy);
+                gvec[2] = dpow * (-0.5 * dx * dx);
+                gvec[3] = dpow * (-dx * dy);
+                gvec[4] = dpow * (-0.5 * dy * dy);
+                gvec[5] = dop;
+                gmag[0] = dpowm * (fabs(A * dx) + fabs(B * dy));
+                gmag[1] = dpowm * (fabs(B * dx) + fabs(Cc * dy));
+                gmag[2] = dpowm * 0.5 * dx * dx;
+                gmag[3] = dpowm * fabs(dx * dy);
+                gmag[4] = dpowm * 0.5 * dy * dy;
+                gmag[5] = dopm;
+                for (int c = 0; c < 3; ++c) {
+                    gvec[6 + c] = w * dC[c];
+                    gmag[6 + c] = fabs(w * dC[c]);
+                }
+                if (a->g2d)
+                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d[9 * g + k], gvec[k]);
+                if (a->g2d_mag)
+                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_mag[9 * g + k], gmag[k]);
+                if (a->dfeat && dF)
+                    for (int64_t k = 0; k < d; ++k) atomic_add(&a->dfeat[g * d + k], w * dF[k]);
+                if (tgt) {
+                    if (a->fsum)
+                        for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum[g * d + k], w * tgt[k]);
+                    if (a->fsum_mag)
+                        for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_mag[g * d + k], fabs(w * tgt[k]));
+                    if (a->wsum) atomic_add(&a->wsum[g], w);
+                }
+            }
+        }
+    }
+    if (a->counts)
+        for (int k = 0; k < 3; ++k) {
+#pragma omp atomic
+            a->counts[k] += local_counts[k];
+        }
+}
+
+int oracle_raster(const oracle_args *a) {
+    const int64_t ntiles = a->tiles_x * a->tiles_y;
+    const int64_t nsel = a->tile_sel ? a->n_tile_sel : ntiles;
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < nsel; ++i) {
+        const int64_t t = a->tile_sel ? a->tile_sel[i] : i;
+        const int64_t len = a->ranges[2 * t + 1] - a->ranges[2 * t];
+        if (len > maxlen) maxlen = len;
+    }
+    int err = 0;
+#pragma omp parallel
+    {
+        blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
+        double gvec[9], gmag[9];
+        if (!recs) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t i = 0; i < nsel; ++i) do_tile(a, a->tile_sel ? a->tile_sel[i] : i, recs, gvec, gmag);
+        }
+        free(recs);
+    }
+    return err;
+}
+
+int oracle_num_threads(void) {
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            n = omp_get_num_threads();
+#endif
+        }
+    }
+    return n;
+}

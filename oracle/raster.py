@@ -1,0 +1,139 @@
+"""ctypes front end of the FP64 C compositing oracle (raster.c).
+
+The shared object is built with gcc into oracle/_build/ (by the package's build
+step, or here on first use).  Compile flags keep IEEE FP64 semantics: no
+fast-math, no contraction of a*b+c into fma.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import consts
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "raster.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_BUILD, "liboracle_raster.so")
+
+GCC_CMD = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-shared", "-fPIC", _SRC, "-o", _LIB, "-lm"]
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        os.makedirs(_BUILD, exist_ok=True)
+        subprocess.run(GCC_CMD, check=True)
+    return _LIB
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int64
+
+
+class _Args(ctypes.Structure):
+    _fields_ = [
+        ("width", _I), ("height", _I), ("tile", _I), ("tiles_x", _I), ("tiles_y", _I),
+        ("d", _I), ("ambig_rel", ctypes.c_double),
+        ("ranges", _P), ("list", _P),
+        ("u", _P), ("v", _P), ("A", _P), ("B", _P), ("C", _P), ("opac", _P),
+        ("rgb", _P), ("feat", _P),
+        ("dC", _P), ("dF", _P), ("dT", _P), ("target", _P),
+        ("tile_sel", _P), ("n_tile_sel", _I),
+        ("out_C", _P), ("out_F", _P), ("out_Fmag", _P), ("out_T", _P), ("out_niter", _P),
+        ("out_flags", _P),
+        ("g2d", _P), ("g2d_mag", _P), ("fsum", _P), ("fsum_mag", _P), ("wsum", _P),
+        ("dfeat", _P), ("gflags", _P), ("counts", _P),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        _lib.oracle_raster.argtypes = [ctypes.POINTER(_Args)]
+        _lib.oracle_raster.restype = ctypes.c_int
+        _lib.oracle_num_threads.restype = ctypes.c_int
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def _ptr(x):
+    return None if x is None else x.ctypes.data
+
+
+def _f64(x):
+    return None if x is None else np.ascontiguousarray(x, np.float64)
+
+
+def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, target=None,
+                tile_sel=None, want_F=True, want_Fmag=False, want_fusion=True, want_dfeat=False):
+    """Composite one view (and its adjoint when dC is given).
+
+    ranges [tiles, 2] and glist [M] are this view's slice of the binning (tile
+    indices local to the view).  proj holds FP64 per-Gaussian u, v, A, B, C,
+    opacity and rgb [N, 3].  Returns a dict of per-pixel and per-Gaussian arrays.
+    """
+    lib = _load()
+    W, H = int(cam.width), int(cam.height)
+    TX = (W + consts.TILE - 1) // consts.TILE
+    TY = (H + consts.TILE - 1) // consts.TILE
+    P = W * H
+    n = proj["u"].shape[0]
+    d = 0 if feat is None else int(feat.shape[1])
+    keep = {}
+
+    def k(name, arr):
+        keep[name] = arr
+        return arr
+
+    ranges = k("ranges", np.ascontiguousarray(ranges, np.int64))
+    glist = k("glist", np.ascontiguousarray(glist, np.int64))
+    u, v, A, B, C, op = (k(nm, _f64(proj[src])) for nm, src in
+                         (("u", "u"), ("v", "v"), ("A", "A"), ("B", "B"), ("C", "C"), ("op", "opacity")))
+    rgb = k("rgb", _f64(proj["rgb"]))
+    featd = k("feat", _f64(feat))
+    dCd, dFd, dTd, tg = (k(nm, _f64(x)) for nm, x in (("dC", dC), ("dF", dF), ("dT", dT), ("tg", target)))
+    sel = k("sel", None if tile_sel is None else np.ascontiguousarray(tile_sel, np.int64))
+
+    out = dict(C=np.zeros((P, 3)), T=np.zeros(P), niter=np.zeros(P, np.int64),
+               flags=np.zeros(P, np.int32), counts=np.zeros(3, np.int64))
+    out["F"] = np.zeros((P, d)) if (want_F and d) else None
+    out["Fmag"] = np.zeros((P, d)) if (want_Fmag and d) else None
+    bwd = dC is not None
+    out["g2d"] = np.zeros((n, 9)) if bwd else None
+    out["g2d_mag"] = np.zeros((n, 9)) if bwd else None
+    fus = bwd and target is not None and want_fusion and d > 0
+    out["fsum"] = np.zeros((n, d)) if fus else None
+    out["fsum_mag"] = np.zeros((n, d)) if fus else None
+    out["wsum"] = np.zeros(n) if (bwd and target is not None) else None
+    out["dfeat"] = np.zeros((n, d)) if (bwd and want_dfeat and d) else None
+    out["gflags"] = np.zeros(n, np.int32)
+
+    args = _Args(
+        width=W, height=H, tile=consts.TILE, tiles_x=TX, tiles_y=TY, d=d,
+        ambig_rel=consts.AMBIG_REL,
+        ranges=_ptr(ranges), list=_ptr(glist),
+        u=_ptr(u), v=_ptr(v), A=_ptr(A), B=_ptr(B), C=_ptr(C), opac=_ptr(op),
+        rgb=_ptr(rgb), feat=_ptr(featd),
+        dC=_ptr(dCd), dF=_ptr(dFd), dT=_ptr(dTd), target=_ptr(tg),
+        tile_sel=_ptr(sel), n_tile_sel=0 if sel is None else sel.size,
+        out_C=_ptr(out["C"]), out_F=_ptr(out["F"]), out_Fmag=_ptr(out["Fmag"]),
+        out_T=_ptr(out["T"]), out_niter=_ptr(out["niter"]), out_flags=_ptr(out["flags"]),
+        g2d=_ptr(out["g2d"]), g2d_mag=_ptr(out["g2d_mag"]), fsum=_ptr(out["fsum"]),
+        fsum_mag=_ptr(out["fsum_mag"]), wsum=_ptr(out["wsum"]), dfeat=_ptr(out["dfeat"]),
+        gflags=_ptr(out["gflags"]), counts=_ptr(out["counts"]),
+    )
+    rc = lib.oracle_raster(ctypes.byref(args))
+    if rc != 0:
+        raise MemoryError("oracle_raster: allocation failed")
+    return out

@@ -1,0 +1,137 @@
+"""Pins of the FP64 compositing oracle (oracle/raster.c) and of brute force vs tiles."""
+import json
+import os
+
+import numpy as np
+import torch
+
+import scenegen
+from oracle import brute, consts, pipeline, raster
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+class _Cam:
+    def __init__(self, w, h):
+        self.width, self.height = w, h
+
+
+def _one_tile(us, vs, A, B, C, op, rgb, feat=None, w=16, h=16, **kw):
+    """Composite Gaussians listed nearest-first in a single 16x16 tile."""
+    n = len(us)
+    proj = dict(u=np.asarray(us, float), v=np.asarray(vs, float), A=np.asarray(A, float),
+                B=np.asarray(B, float), C=np.asarray(C, float), opacity=np.asarray(op, float),
+                rgb=np.asarray(rgb, float).reshape(n, 3))
+    ranges = np.array([[0, n]])
+    return raster.render_view(_Cam(w, h), ranges, np.arange(n), proj, feat=feat, **kw)
+
+
+def test_single_gaussian_closed_form():
+    gold = GOLD["single_isotropic"]
+    o = gold["opacity"]
+    u0, v0 = 7.5, 7.5   # centre on pixel (7, 7)
+    out = _one_tile([u0], [v0], [1.0], [0.0], [1.0], [o], [[0.2, 0.5, 1.0]],
+                    feat=np.array([[2.0, -1.0]]))
+    for case in gold["cases"]:
+        px, py = int(7 + case["dx"]), int(7 + case["dy"])
+        p = py * 16 + px
+        a = case["alpha"]
+        assert np.allclose(out["C"][p], np.array([0.2, 0.5, 1.0]) * a, rtol=1e-14, atol=1e-300)
+        assert np.allclose(out["F"][p], np.array([2.0, -1.0]) * a, rtol=1e-14, atol=1e-300)
+        assert np.isclose(out["T"][p], 1 - a, rtol=1e-14)
+        assert out["niter"][p] == (1 if a > 0 else 0)
+
+
+def test_stack_termination():
+    gold = GOLD["stack_095"]
+    n = gold["n_gaussians"]
+    out = _one_tile([7.5] * n, [7.5] * n, [1.0] * n, [0.0] * n, [1.0] * n, [gold["alpha"]] * n,
+                    [[1.0, 1.0, 1.0]] * n, feat=np.ones((n, 1)))
+    p = 7 * 16 + 7
+    assert np.isclose(out["T"][p], gold["T_final"], rtol=1e-12)
+    assert out["niter"][p] == gold["n_iter"]
+    assert np.isclose(out["C"][p, 0], gold["sum_w"], rtol=1e-12)
+    assert np.isclose(out["F"][p, 0], gold["sum_w"], rtol=1e-12)
+
+
+def test_two_concentric_order():
+    gold = GOLD["two_concentric"]
+    out = _one_tile([7.5, 7.5], [7.5, 7.5], [1, 1], [0, 0], [1, 1],
+                    [gold["alpha_near"], gold["alpha_far"]], [gold["rgb_near"], gold["rgb_far"]])
+    p = 7 * 16 + 7
+    assert np.allclose(out["C"][p], gold["C"], rtol=1e-14)
+    assert np.isclose(out["T"][p], gold["T_final"], rtol=1e-14)
+
+
+def test_clamp():
+    gold = GOLD["clamp"]
+    out = _one_tile([7.5], [7.5], [1], [0], [1], [1.0], [[1, 1, 1]])
+    p = 7 * 16 + 7
+    assert np.isclose(out["T"][p], gold["T_final"], rtol=1e-14)
+    assert np.isclose(out["C"][p, 0], gold["alpha"], rtol=1e-14)
+
+
+def _random_scene_oracle(seed, n=120, d=5, recipe="front48x40", deg=1):
+    g = scenegen.make_gaussians(n, 1.0, deg, d, seed=seed)
+    cams = scenegen.make_cameras(recipe)
+    o = pipeline.run(g, cams)
+    return g, cams, o
+
+
+def test_weight_sum_invariant_and_ones_features():
+    g, cams, _ = _random_scene_oracle(3)
+    g["feat"] = np.ones((g["means"].shape[0], 1), np.float32)
+    o = pipeline.run(g, cams)
+    v = o["views"][0]
+    # all-ones features: F = sum w = 1 - T_final
+    assert np.allclose(v["F"][:, 0], 1 - v["T"], atol=1e-14)
+
+
+def test_linear_in_features_and_colour():
+    g, cams, o1 = _random_scene_oracle(4)
+    g2 = dict(g)
+    g2["feat"] = 2.0 * g["feat"]          # exact in float32
+    o2 = pipeline.run(g2, cams)
+    assert np.allclose(o2["views"][0]["F"], 2.0 * o1["views"][0]["F"], rtol=1e-14, atol=1e-300)
+    # colour: scale the per-Gaussian rgb at the compositing level
+    rng = np.random.default_rng(9)
+    n = 5
+    args = ([7.5 + rng.normal() for _ in range(n)], [7.5 + rng.normal() for _ in range(n)],
+            [0.3] * n, [0.05] * n, [0.2] * n, list(rng.uniform(0.2, 0.9, n)))
+    rgb = rng.uniform(0, 1, (n, 3))
+    c1 = _one_tile(*args, rgb)["C"]
+    c2 = _one_tile(*args, 0.5 * rgb)["C"]
+    assert np.allclose(c2, 0.5 * c1, rtol=1e-14, atol=1e-300)
+
+
+def test_permutation_invariance():
+    g, cams, o1 = _random_scene_oracle(5)
+    perm = np.random.default_rng(0).permutation(g["means"].shape[0])
+    g2 = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape[:1] == (g["means"].shape[0],) else v)
+          for k, v in g.items()}
+    o2 = pipeline.run(g2, cams)
+    v1, v2 = o1["views"][0], o2["views"][0]
+    assert np.allclose(v1["C"], v2["C"], atol=1e-13)
+    assert np.allclose(v1["F"], v2["F"], atol=1e-13)
+    assert np.allclose(v1["T"], v2["T"], atol=1e-13)
+
+
+def test_brute_force_equals_tiled():
+    for seed, recipe in ((6, "front48x40"), (7, "front33x21"), (8, "front70x50")):
+        g, cams, o = _random_scene_oracle(seed, n=150, recipe=recipe, deg=2)
+        L = brute.leaves(g)
+        with torch.no_grad():
+            C, F, T, niter, order = brute.render(L, g, cams[0], g["feat"])
+        v = o["views"][0]
+        assert np.allclose(C.numpy(), v["C"], atol=1e-13)
+        assert np.allclose(F.numpy(), v["F"], atol=1e-13)
+        assert np.allclose(T.numpy(), v["T"], atol=1e-13)
+        # the last contributor is the same Gaussian
+        ranges = pipeline.view_slice(o["bins"], 0, cams[0])
+        W = cams[0].width
+        tx = (np.arange(T.numel()) % W) // 16
+        ty = (np.arange(T.numel()) // W) // 16
+        tile = ty * ((W + 15) // 16) + tx
+        tiled_last = np.where(v["niter"] > 0, o["bins"]["gids"][np.maximum(ranges[tile, 0] + v["niter"] - 1, 0)], -1)
+        brute_last = np.where(niter.numpy() > 0, order[np.maximum(niter.numpy() - 1, 0)], -1)
+        assert np.array_equal(tiled_last, brute_last)
