@@ -1,0 +1,252 @@
+/*
+ * fhgs.h -- C ABI of the MI355X (gfx950) tile-based Gaussian-splatting
+ * rasterizer with w-weighted feature fusion (FHGS, arXiv 2505.19154).
+ *
+ * The path, in the order of Algorithm 2 of the paper:
+ *   fh_project        screen-space Gaussians (EWA projection, conic, SH colour,
+ *                     depth key and tile rectangle) for every (view, Gaussian)
+ *   fh_bin_sort       DuplicateWithKeys + SortByKeys + IdentifyTileRanges: one
+ *                     instance per (Gaussian, overlapped 16x16 tile), ordered by
+ *                     (tile, depth, Gaussian index), and each tile's [start, end)
+ *   fh_render_fwd     front-to-back alpha compositing of colour and of the
+ *                     D-channel feature (Section 3.1: c = sum_i c_i w_i,
+ *                     w_i = alpha_i T_i)
+ *   fh_render_bwd     the adjoint through w (Appendix A.2, dL/dalpha_k), chained
+ *                     to means, scales, rotations, opacities and SH; optionally
+ *                     fused with feature fusion
+ *   fh_fuse_features  w-weighted scatter of a per-pixel target map into
+ *                     per-Gaussian accumulators (compensated FP32 sums)
+ *   fh_fuse_finalize  accumulators -> fused per-Gaussian features
+ *
+ * Conventions
+ *   - Every data pointer is a DEVICE pointer unless its comment says host.
+ *     The caller allocates every buffer (inputs, outputs, accumulators and the
+ *     workspace); the library never allocates or frees device memory and keeps
+ *     no device state between calls.
+ *   - All calls are asynchronous on the given HIP stream (NULL = the default
+ *     stream) and never synchronise the host, except fh_read_counters, which
+ *     waits for the stream.  Calls that only launch kernels can be captured
+ *     into a HIP graph.
+ *   - Return value: FH_OK, or a negative fh_status for errors detected on the
+ *     host (bad arguments, launch failure).  Conditions only known on the
+ *     device (instance capacity exceeded, non-finite Gaussians culled) are
+ *     recorded in the workspace and read back by fh_read_counters.
+ *   - Cameras: pinhole, OpenCV axes (x right, y down, z forward);
+ *     p_cam = R p_world + t with R row-major.  Pixel (px, py) samples the
+ *     point (px + 1/2, py + 1/2).
+ *   - Views are concatenated: per-pixel arrays of view v start at pixel
+ *     offset sum_{u<v} W_u H_u, row-major within the view.
+ */
+#ifndef FHGS_H
+#define FHGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FH_VERSION 1
+#define FH_MAX_VIEWS 32
+#define FH_TILE 16
+
+typedef enum {
+    FH_OK = 0,
+    FH_E_INVALID = -1,      /* null pointer, size or layout error */
+    FH_E_UNSUPPORTED = -2,  /* e.g. sh_degree > 3, too many views */
+    FH_E_HIP = -3,          /* a HIP launch or runtime call failed */
+    FH_E_CAPACITY = -4      /* device-side: instance or visit capacity exceeded */
+} fh_status;
+
+typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
+
+/* Arithmetic form of the compositing kernels. */
+typedef enum {
+    FH_FORM_F32 = 0,        /* FP32 features, FP32 VALU blending */
+    FH_FORM_BF16 = 1        /* BF16 features, (pixels x K)(K x D) blends on MFMA, FP32 accumulation */
+} fh_form;
+
+/* The Gaussians theta_i (Section 3.1), structure of arrays, activated values.
+ * means [n,3], scales [n,3] (> 0), quats [n,4] (w, x, y, z; normalised inside,
+ * gradients include the normalisation), opacity [n] in (0, 1),
+ * sh [n, (sh_degree+1)^2, 3], feat [n, d] (FP32 or BF16 per feat_dtype; the
+ * frozen semantic feature f_i, never differentiated). */
+typedef struct {
+    const float *means;
+    const float *scales;
+    const float *quats;
+    const float *opacity;
+    const float *sh;
+    const void *feat;
+    int64_t n;
+    int32_t sh_degree;      /* 0..3 */
+    int32_t d;              /* feature channels, 0..1024 */
+    int32_t feat_dtype;     /* fh_dtype */
+    int32_t reserved;
+} fh_gaussians;
+
+/* One pinhole camera (the world-to-camera transform W of Section 3.1). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];             /* row-major world->camera rotation */
+    float t[3];
+} fh_camera;
+
+/* Host-side description of one batch of views: sizes, capacities and the
+ * workspace layout.  Filled by fh_plan_init; plain data, may be copied. */
+typedef struct {
+    int64_t n;                       /* Gaussians */
+    int32_t n_views, d, sh_degree, feat_dtype;
+    int32_t form;                    /* fh_form */
+    int32_t rank_bits, tile_bits;    /* key layout of the instance sort */
+    int32_t packed_keys;             /* 1: one u32 key (tile << rank_bits | rank); 0: u32 tile + u32 rank */
+    int64_t inst_capacity;           /* max (Gaussian, tile) instances over all views */
+    int64_t visit_capacity;          /* max instances visited by the backward (per-instance partials) */
+    int64_t n_pixels, n_tiles;
+    fh_camera cams[FH_MAX_VIEWS];
+    int64_t pix_off[FH_MAX_VIEWS + 1];
+    int64_t tile_off[FH_MAX_VIEWS + 1];
+    int32_t tiles_x[FH_MAX_VIEWS], tiles_y[FH_MAX_VIEWS];
+    /* workspace layout: byte offsets of the sub-buffers, and the total */
+    size_t off[32];
+    size_t ws_bytes;
+} fh_plan;
+
+/* Per-pixel outputs of fh_render_fwd (caller-owned, FP32 unless noted).
+ * C [P,3], F [P,d] (may be NULL when d == 0), T [P] (final transmittance),
+ * n_iter [P] (u32: 1 + position within the tile's list of the last
+ * contributing Gaussian, 0 if none). */
+typedef struct {
+    float *C;
+    float *F;
+    float *T;
+    uint32_t *n_iter;
+} fh_image;
+
+/* Upstream adjoints for fh_render_bwd: dC [P,3], dF [P,d] (NULL = 0),
+ * dT [P] (NULL = 0). FP32. */
+typedef struct {
+    const float *dC;
+    const float *dF;
+    const float *dT;
+} fh_upstream;
+
+/* Gradients written by fh_render_bwd (caller-owned, FP32, overwritten):
+ * means [n,3], scales [n,3], quats [n,4], opacity [n], sh [n,B,3]. */
+typedef struct {
+    float *means;
+    float *scales;
+    float *quats;
+    float *opacity;
+    float *sh;
+} fh_grads;
+
+/* Fusion accumulators (caller-owned, FP32, persistent across calls and views;
+ * zero them once before the first view).  Neumaier-compensated pairs:
+ * the running value is sum + comp.  sum, comp [n,d]; wsum, wcomp [n]. */
+typedef struct {
+    float *sum;
+    float *comp;
+    float *wsum;
+    float *wcomp;
+} fh_fusion;
+
+/* Device-side counters, read back by fh_read_counters (host struct). */
+typedef struct {
+    int64_t n_instances;     /* instances the binning produced (may exceed capacity) */
+    int64_t n_visited;       /* instances the forward traversal reached (backward partials) */
+    int64_t n_culled_nonfinite;
+    int32_t inst_overflow;   /* 1 if n_instances > inst_capacity: bin_sort results invalid */
+    int32_t visit_overflow;  /* 1 if n_visited > visit_capacity: render_bwd results invalid */
+} fh_counters;
+
+/* Buffers inside the workspace that callers may inspect (fh_get_buffer). */
+typedef enum {
+    FH_BUF_RECORDS = 0,      /* float4 [V*n*3] screen-space records */
+    FH_BUF_DEPTH_KEY = 1,    /* u32 [V*n] float32 depth bits, 0xFFFFFFFF if culled */
+    FH_BUF_RECT = 2,         /* i32 [V*n*4] tile rect x0, y0, x1, y1 (inclusive; x0 > x1 if culled) */
+    FH_BUF_DEPTH_ORDER = 3,  /* u32 [V*n] Gaussian index, per view sorted by (depth, index) */
+    FH_BUF_RANGES = 4,       /* u32 [tiles,2] [start, end) into the sorted instances */
+    FH_BUF_TILE_NITER = 5,   /* u32 [tiles] max n_iter over the tile's pixels (after render_fwd) */
+    FH_BUF_GRAD2D = 6        /* float [V*n,12] per-(view, Gaussian) screen-space adjoints (after render_bwd) */
+} fh_buffer;
+
+/* Fill `plan` for n Gaussians and n_views cameras (host array `cams`).
+ * inst_capacity / visit_capacity bound the data-dependent instance counts;
+ * pass 0 to get a plan whose workspace holds only the projection and the
+ * counters (enough for fh_project + fh_bin_count).  Errors: FH_E_INVALID for
+ * null/negative sizes, FH_E_UNSUPPORTED for sh_degree > 3, n_views >
+ * FH_MAX_VIEWS, d > 1024, or a BF16 form with FP32 features. */
+fh_status fh_plan_init(fh_plan *plan, int64_t n, int32_t sh_degree, int32_t d, fh_dtype feat_dtype,
+                       fh_form form, const fh_camera *cams, int32_t n_views,
+                       int64_t inst_capacity, int64_t visit_capacity);
+
+/* Project every (view, Gaussian) (Algorithm 2: Homogenization and
+ * 2DScreenGaussians; the screen-space Gaussian of Section 3.1).  Writes the
+ * records, depth keys and tile rects into the workspace and clears the
+ * counters.  Gaussians with float32 depth <= 0.2 or a non-finite projection
+ * are culled. */
+fh_status fh_project(const fh_plan *plan, const fh_gaussians *g, void *ws, hipStream_t stream);
+
+/* Count the instances (sum of tile-rect areas) after fh_project, so that the
+ * caller can size inst_capacity; the count is read with fh_read_counters. */
+fh_status fh_bin_count(const fh_plan *plan, void *ws, hipStream_t stream);
+
+/* Tile binning (Appendix A, "Details of the Rasterizer"; Algorithm 2:
+ * CreateTiles, DuplicateWithKeys, SortByKeys, IdentifyTileRanges).  Produces
+ * the instances in (tile, depth, Gaussian index) order and every tile's
+ * range.  Requires inst_capacity > 0; if the instance count exceeds it the
+ * overflow counter is set and the ranges are left empty. */
+fh_status fh_bin_sort(const fh_plan *plan, void *ws, hipStream_t stream);
+
+/* The paper's 64-bit keys of the sorted instances, (global tile << 32) | depth
+ * bits, and the Gaussian index of each: keys_out u64 [n_inst], gid_out u32
+ * [n_inst] (either may be NULL), n_inst = the instance count (<= capacity). */
+fh_status fh_bin_keys(const fh_plan *plan, const void *ws, uint64_t *keys_out, uint32_t *gid_out,
+                      int64_t n_inst, hipStream_t stream);
+
+/* Front-to-back compositing of every pixel of every view (Section 3.1).
+ * Reads the projection and the binning from the workspace and feat from g.
+ * Also records per-tile traversal lengths for the backward pass. */
+fh_status fh_render_fwd(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *out,
+                        hipStream_t stream);
+
+/* Adjoint of fh_render_fwd (Appendix A.2) chained through the projection.
+ * Recomputes transmittance back to front from T and n_iter of `fwd`.
+ * If fusion_target (per-pixel [P,d], dtype target_dtype) and acc are given,
+ * the same sweep also accumulates feature fusion into acc.
+ * Gradients are written (not accumulated) into `out`. */
+fh_status fh_render_bwd(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
+                        const fh_upstream *up, const void *fusion_target, fh_dtype target_dtype,
+                        const fh_fusion *acc, const fh_grads *out, hipStream_t stream);
+
+/* Feature fusion alone: acc.sum += sum_p w_g(p) target(p), acc.wsum += sum_p
+ * w_g(p) for every Gaussian g, Neumaier-compensated; needs fh_render_fwd's
+ * T and n_iter for the same views. */
+fh_status fh_fuse_features(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
+                           const void *target, fh_dtype target_dtype, const fh_fusion *acc,
+                           hipStream_t stream);
+
+/* feat_out[g] = (sum + comp) / (wsum + wcomp) where wsum + wcomp > 0, else
+ * feat_in[g] (NULL feat_in: 0).  feat_in, feat_out [n,d] of dtype. */
+fh_status fh_fuse_finalize(const fh_fusion *acc, int64_t n, int32_t d, const void *feat_in, void *feat_out,
+                           fh_dtype dtype, hipStream_t stream);
+
+/* Wait for `stream` and copy the device counters into *out (host). */
+fh_status fh_read_counters(const fh_plan *plan, const void *ws, fh_counters *out, hipStream_t stream);
+
+/* Device pointer and element count of a workspace buffer (no device access). */
+fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **ptr, int64_t *count);
+
+const char *fh_status_string(fh_status s);
+int32_t fh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHGS_H */

@@ -1,0 +1,460 @@
+// Host side of the C ABI declared in include/fhgs.h: plan and workspace
+// layout, argument checks, and the launch sequence of every call.
+#include <string.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace fh {
+
+// ---------------------------------------------------------------------------
+static int ceil_log2(int64_t x) {
+    int b = 0;
+    while (((int64_t)1 << b) < x) ++b;
+    return b < 1 ? 1 : b;
+}
+
+static ViewTable view_table(const fh_plan& p) {
+    ViewTable vt;
+    memset(&vt, 0, sizeof(vt));
+    vt.n_views = p.n_views;
+    vt.n_tiles = (int)p.n_tiles;
+    for (int v = 0; v < p.n_views; ++v) {
+        vt.tiles_x[v] = p.tiles_x[v];
+        vt.tiles_y[v] = p.tiles_y[v];
+        vt.width[v] = p.cams[v].width;
+        vt.height[v] = p.cams[v].height;
+    }
+    for (int v = 0; v <= p.n_views; ++v) {
+        vt.tile_off[v] = (int)p.tile_off[v];
+        vt.pix_off[v] = p.pix_off[v];
+    }
+    return vt;
+}
+
+static CamTable cam_table(const fh_plan& p) {
+    CamTable ct;
+    memset(&ct, 0, sizeof(ct));
+    for (int v = 0; v < p.n_views; ++v) ct.cam[v] = p.cams[v];
+    return ct;
+}
+
+template <typename T>
+static T* buf(const fh_plan* p, void* ws, int which) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + p->off[which]);
+}
+template <typename T>
+static const T* cbuf(const fh_plan* p, const void* ws, int which) {
+    return reinterpret_cast<const T*>(static_cast<const char*>(ws) + p->off[which]);
+}
+
+static int inst_sort_passes(const fh_plan* p) { return (p->tile_bits + 7) / 8; }
+static int final_keys_buf(const fh_plan* p) { return (inst_sort_passes(p) % 2) ? WS_KEYS_B : WS_KEYS_A; }
+static int final_vals_buf(const fh_plan* p) { return (inst_sort_passes(p) % 2) ? WS_VALS_B : WS_VALS_A; }
+
+static fh_status launch_status() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FH_OK : FH_E_HIP;
+}
+
+static bool gaussians_ok(const fh_plan* p, const fh_gaussians* g) {
+    if (!g || !g->means || !g->scales || !g->quats || !g->opacity || !g->sh) return false;
+    if (g->n != p->n || g->sh_degree != p->sh_degree || g->d != p->d) return false;
+    if (p->d > 0 && !g->feat) return false;
+    if (g->feat_dtype != p->feat_dtype) return false;
+    return true;
+}
+
+__global__ void k_reset_bin_counters(Counters* c) {
+    if (threadIdx.x == 0) {
+        c->n_instances = 0;
+        c->inst_overflow = 0;
+        c->n_visited = 0;
+        c->visit_overflow = 0;
+    }
+}
+
+__global__ void k_reset_all_counters(Counters* c) {
+    if (threadIdx.x == 0) {
+        c->n_instances = 0;
+        c->n_visited = 0;
+        c->n_culled_nonfinite = 0;
+        c->inst_overflow = 0;
+        c->visit_overflow = 0;
+    }
+}
+
+// depth sort, tiles per rank, their scan, the instance count and the overflow flag
+static void bin_count_impl(const fh_plan* p, void* ws, hipStream_t s) {
+    const int64_t total = (int64_t)p->n_views * p->n;
+    Counters* c = buf<Counters>(p, ws, WS_COUNTERS);
+    hipLaunchKernelGGL(k_reset_bin_counters, dim3(1), dim3(64), 0, s, c);
+    if (total == 0) return;
+    uint32_t* hist = buf<uint32_t>(p, ws, WS_HIST);
+    uint32_t* scan_tmp = buf<uint32_t>(p, ws, WS_SCAN_TMP);
+    radix_sort(cbuf<uint32_t>(p, ws, WS_DEPTH_KEY), nullptr, buf<uint32_t>(p, ws, WS_DKEY_TMP2),
+               buf<uint32_t>(p, ws, WS_ORDER), buf<uint32_t>(p, ws, WS_DKEY_TMP), buf<uint32_t>(p, ws, WS_ORDER_TMP),
+               true, p->n_views, p->n, nullptr, 0, 0, 32, hist, scan_tmp, s);
+    uint32_t* ntiles = buf<uint32_t>(p, ws, WS_DKEY_TMP);
+    launch_tiles_by_rank(cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<int4>(p, ws, WS_RECT), p->n, total, ntiles, c, s);
+    device_exclusive_scan(ntiles, buf<uint32_t>(p, ws, WS_INST_OFF), total, scan_tmp, 1, s);
+    launch_check_capacity(c, p->inst_capacity, s);
+    launch_rank_of(cbuf<uint32_t>(p, ws, WS_ORDER), p->n, total, buf<uint32_t>(p, ws, WS_RANK_OF), s);
+}
+
+}  // namespace fh
+
+using namespace fh;
+
+extern "C" {
+
+fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, fh_dtype feat_dtype, fh_form form,
+                       const fh_camera* cams, int32_t n_views, int64_t inst_capacity, int64_t visit_capacity) {
+    if (!plan || !cams || n < 0 || d < 0 || n_views < 1 || inst_capacity < 0 || visit_capacity < 0)
+        return FH_E_INVALID;
+    if (sh_degree < 0 || sh_degree > 3 || n_views > FH_MAX_VIEWS || d > 1024) return FH_E_UNSUPPORTED;
+    if (feat_dtype != FH_F32 && feat_dtype != FH_BF16) return FH_E_INVALID;
+    if (form != FH_FORM_F32 && form != FH_FORM_BF16) return FH_E_INVALID;
+    if (form == FH_FORM_BF16 && feat_dtype != FH_BF16) return FH_E_UNSUPPORTED;
+    if (inst_capacity > 0xFFFFFFFFll || visit_capacity > 0xFFFFFFFFll) return FH_E_UNSUPPORTED;
+    if ((int64_t)n * n_views >= ((int64_t)1 << 32)) return FH_E_UNSUPPORTED;
+    memset(plan, 0, sizeof(*plan));
+    plan->n = n;
+    plan->n_views = n_views;
+    plan->d = d;
+    plan->sh_degree = sh_degree;
+    plan->feat_dtype = feat_dtype;
+    plan->form = form;
+    plan->inst_capacity = inst_capacity;
+    plan->visit_capacity = visit_capacity;
+    int64_t pix = 0, tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const fh_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384) return FH_E_INVALID;
+        plan->cams[v] = c;
+        plan->pix_off[v] = pix;
+        plan->tile_off[v] = tiles;
+        plan->tiles_x[v] = (c.width + FH_TILE - 1) / FH_TILE;
+        plan->tiles_y[v] = (c.height + FH_TILE - 1) / FH_TILE;
+        pix += (int64_t)c.width * c.height;
+        tiles += (int64_t)plan->tiles_x[v] * plan->tiles_y[v];
+    }
+    plan->pix_off[n_views] = pix;
+    plan->tile_off[n_views] = tiles;
+    plan->n_pixels = pix;
+    plan->n_tiles = tiles;
+    if (tiles >= ((int64_t)1 << 31)) return FH_E_UNSUPPORTED;
+    const int64_t total = (int64_t)n * n_views;
+    plan->rank_bits = ceil_log2(total > 1 ? total : 2);
+    plan->tile_bits = ceil_log2(tiles > 1 ? tiles : 2);
+    plan->packed_keys = (plan->rank_bits + plan->tile_bits) <= 32 ? 1 : 0;
+
+    size_t sz[WS_COUNT];
+    memset(sz, 0, sizeof(sz));
+    const size_t u4 = sizeof(uint32_t);
+    sz[WS_COUNTERS] = 256;
+    sz[WS_REC] = (size_t)total * 3 * 16;
+    sz[WS_DEPTH_KEY] = (size_t)total * u4;
+    sz[WS_RECT] = (size_t)total * 16;
+    sz[WS_ORDER] = sz[WS_ORDER_TMP] = sz[WS_DKEY_TMP] = sz[WS_DKEY_TMP2] = (size_t)total * u4;
+    sz[WS_INST_OFF] = (size_t)(total + 1) * u4;
+    const size_t hist_depth = radix_hist_u32(n_views, n);
+    const size_t hist_inst = radix_hist_u32(1, inst_capacity);
+    const size_t hist = std::max(hist_depth, hist_inst);
+    sz[WS_HIST] = hist * u4;
+    sz[WS_SCAN_TMP] = scan_scratch_u32(std::max<int64_t>({(int64_t)hist, total + 1, tiles + 1})) * u4;
+    sz[WS_RANGES] = (size_t)tiles * 2 * u4;
+    sz[WS_TILE_NITER] = (size_t)tiles * u4;
+    sz[WS_TILE_VOFF] = (size_t)(tiles + 1) * u4;
+    sz[WS_TILE_LAST] = (size_t)tiles * u4;
+    sz[WS_GRAD2D] = (size_t)total * 12 * sizeof(float);
+    sz[WS_RANK_OF] = (size_t)total * u4;
+    sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
+    sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
+    sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
+    sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
+    size_t off = 0;
+    for (int i = 0; i < WS_COUNT; ++i) {
+        plan->off[i] = off;
+        off += (sz[i] + 255) & ~(size_t)255;
+    }
+    plan->ws_bytes = off;
+    return FH_OK;
+}
+
+fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStream_t s) {
+    if (!p || !ws || !gaussians_ok(p, g)) return FH_E_INVALID;
+    Counters* c = buf<Counters>(p, ws, WS_COUNTERS);
+    hipLaunchKernelGGL(k_reset_all_counters, dim3(1), dim3(64), 0, s, c);
+    if (p->n == 0) return launch_status();
+    ProjectArgs a;
+    a.means = g->means;
+    a.scales = g->scales;
+    a.quats = g->quats;
+    a.opacity = g->opacity;
+    a.sh = g->sh;
+    a.n = (int)p->n;
+    a.sh_degree = p->sh_degree;
+    a.rec = buf<float4>(p, ws, WS_REC);
+    a.depth_key = buf<uint32_t>(p, ws, WS_DEPTH_KEY);
+    a.rect = buf<int4>(p, ws, WS_RECT);
+    a.counters = c;
+    launch_project(a, cam_table(*p), view_table(*p), p->n_views, s);
+    return launch_status();
+}
+
+fh_status fh_bin_count(const fh_plan* p, void* ws, hipStream_t s) {
+    if (!p || !ws) return FH_E_INVALID;
+    bin_count_impl(p, ws, s);
+    return launch_status();
+}
+
+fh_status fh_bin_sort(const fh_plan* p, void* ws, hipStream_t s) {
+    if (!p || !ws) return FH_E_INVALID;
+    if (p->inst_capacity <= 0) return FH_E_INVALID;
+    bin_count_impl(p, ws, s);
+    const int64_t total = (int64_t)p->n_views * p->n;
+    const Counters* c = cbuf<Counters>(p, ws, WS_COUNTERS);
+    uint32_t* ranges = buf<uint32_t>(p, ws, WS_RANGES);
+    launch_fill_u32(ranges, p->n_tiles * 2, 0u, s);
+    if (total == 0) return launch_status();
+    DupArgs da;
+    da.inst_off = cbuf<uint32_t>(p, ws, WS_INST_OFF);
+    da.order = cbuf<uint32_t>(p, ws, WS_ORDER);
+    da.rect = cbuf<int4>(p, ws, WS_RECT);
+    da.n = p->n;
+    da.total_ranks = total;
+    da.cap = p->inst_capacity;
+    da.counters = c;
+    da.keys = buf<uint32_t>(p, ws, WS_KEYS_A);
+    da.vals = p->packed_keys ? nullptr : buf<uint32_t>(p, ws, WS_VALS_A);
+    da.rank_bits = p->rank_bits;
+    da.packed = p->packed_keys;
+    da.vt = view_table(*p);
+    launch_duplicate(da, s);
+    const int lo = p->packed_keys ? p->rank_bits : 0;
+    radix_sort(buf<uint32_t>(p, ws, WS_KEYS_A), p->packed_keys ? nullptr : buf<uint32_t>(p, ws, WS_VALS_A),
+               buf<uint32_t>(p, ws, WS_KEYS_A), p->packed_keys ? nullptr : buf<uint32_t>(p, ws, WS_VALS_A),
+               buf<uint32_t>(p, ws, WS_KEYS_B), p->packed_keys ? nullptr : buf<uint32_t>(p, ws, WS_VALS_B),
+               !p->packed_keys, 1, 0, &c->n_instances, p->inst_capacity, lo, lo + p->tile_bits,
+               buf<uint32_t>(p, ws, WS_HIST), buf<uint32_t>(p, ws, WS_SCAN_TMP), s);
+    launch_ranges(cbuf<uint32_t>(p, ws, final_keys_buf(p)), c, p->inst_capacity, p->rank_bits, p->packed_keys, ranges,
+                  s);
+    return launch_status();
+}
+
+fh_status fh_bin_keys(const fh_plan* p, const void* ws, uint64_t* keys_out, uint32_t* gid_out, int64_t n_inst,
+                      hipStream_t s) {
+    if (!p || !ws || n_inst < 0 || n_inst > p->inst_capacity) return FH_E_INVALID;
+    launch_bin_keys(cbuf<uint32_t>(p, ws, final_keys_buf(p)),
+                    p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p)),
+                    cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<uint32_t>(p, ws, WS_DEPTH_KEY), n_inst, p->n, p->rank_bits,
+                    p->packed_keys, keys_out, gid_out, s);
+    return launch_status();
+}
+
+fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* out, hipStream_t s) {
+    if (!p || !ws || !out || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (!out->C || !out->T || !out->n_iter || (p->d > 0 && !out->F)) return FH_E_INVALID;
+    if (p->inst_capacity <= 0) return FH_E_INVALID;
+    RenderArgs a;
+    a.rec = cbuf<float4>(p, ws, WS_REC);
+    a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
+    a.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
+    a.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
+    a.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
+    a.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
+    a.rank_bits = p->rank_bits;
+    a.packed = p->packed_keys;
+    a.n = p->n;
+    a.feat = g->feat;
+    a.d = p->d;
+    a.feat_bf16 = p->feat_dtype == FH_BF16;
+    a.C = out->C;
+    a.F = out->F;
+    a.T = out->T;
+    a.n_iter = out->n_iter;
+    uint32_t* tile_niter = buf<uint32_t>(p, ws, WS_TILE_NITER);
+    a.tile_niter = tile_niter;
+    const ViewTable vt = view_table(*p);
+    launch_render_fwd_f32(a, vt, (int)p->n_tiles, s);
+    launch_tile_last(a.ranges, tile_niter, a.keys, a.vals, p->rank_bits, p->packed_keys, (int)p->n_tiles,
+                     buf<uint32_t>(p, ws, WS_TILE_LAST), s);
+    uint32_t* voff = buf<uint32_t>(p, ws, WS_TILE_VOFF);
+    device_exclusive_scan(tile_niter, voff, p->n_tiles, buf<uint32_t>(p, ws, WS_SCAN_TMP), 1, s);
+    launch_check_visits(voff, (int)p->n_tiles, buf<Counters>(p, ws, WS_COUNTERS), p->visit_capacity, s);
+    return launch_status();
+}
+
+static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, BwdArgs& a) {
+    a.rec = cbuf<float4>(p, ws, WS_REC);
+    a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
+    a.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
+    a.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
+    a.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
+    a.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
+    a.tile_voff = cbuf<uint32_t>(p, ws, WS_TILE_VOFF);
+    a.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
+    a.rank_bits = p->rank_bits;
+    a.packed = p->packed_keys;
+    a.n = p->n;
+    a.feat = g->feat;
+    a.d = p->d;
+    a.feat_bf16 = p->feat_dtype == FH_BF16;
+    a.T_final = fwd->T;
+    a.n_iter = fwd->n_iter;
+    a.dC = nullptr;
+    a.dF = nullptr;
+    a.dT = nullptr;
+    a.target = nullptr;
+    a.target_bf16 = 0;
+    a.part_geom = buf<float>(p, ws, WS_PART_GEOM);
+    a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
+}
+
+static void fill_reduce_args(const fh_plan* p, void* ws, ReduceArgs& r) {
+    r.order = cbuf<uint32_t>(p, ws, WS_ORDER);
+    r.rect = cbuf<int4>(p, ws, WS_RECT);
+    r.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
+    r.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
+    r.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
+    r.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
+    r.tile_voff = cbuf<uint32_t>(p, ws, WS_TILE_VOFF);
+    r.tile_last = cbuf<uint32_t>(p, ws, WS_TILE_LAST);
+    r.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
+    r.rank_bits = p->rank_bits;
+    r.packed = p->packed_keys;
+    r.n = p->n;
+    r.total = (int64_t)p->n * p->n_views;
+    r.part_geom = cbuf<float>(p, ws, WS_PART_GEOM);
+    r.grad2d = buf<float>(p, ws, WS_GRAD2D);
+    r.rank_of = cbuf<uint32_t>(p, ws, WS_RANK_OF);
+    r.part_fuse = cbuf<float>(p, ws, WS_PART_FUSE);
+    r.d = p->d;
+    r.n_views = p->n_views;
+    r.acc_sum = r.acc_comp = r.acc_wsum = r.acc_wcomp = nullptr;
+}
+
+fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const fh_upstream* up,
+                        const void* fusion_target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* out,
+                        hipStream_t s) {
+    if (!p || !ws || !fwd || !up || !out || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (!fwd->T || !fwd->n_iter || !up->dC) return FH_E_INVALID;
+    if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh) return FH_E_INVALID;
+    const bool fuse = fusion_target != nullptr;
+    if (fuse && (!acc || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)) return FH_E_INVALID;
+    if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
+    BwdArgs a;
+    fill_bwd_args(p, g, ws, fwd, a);
+    a.dC = up->dC;
+    a.dF = p->d > 0 ? up->dF : nullptr;
+    a.dT = up->dT;
+    a.target = fusion_target;
+    a.target_bf16 = target_dtype == FH_BF16;
+    const ViewTable vt = view_table(*p);
+    launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, s);
+    ReduceArgs r;
+    fill_reduce_args(p, ws, r);
+    launch_reduce_geom(r, vt, s);
+    ProjectBwdArgs pb;
+    pb.means = g->means;
+    pb.scales = g->scales;
+    pb.quats = g->quats;
+    pb.opacity = g->opacity;
+    pb.sh = g->sh;
+    pb.n = (int)p->n;
+    pb.sh_degree = p->sh_degree;
+    pb.grad2d = r.grad2d;
+    pb.depth_key = cbuf<uint32_t>(p, ws, WS_DEPTH_KEY);
+    pb.g_means = out->means;
+    pb.g_scales = out->scales;
+    pb.g_quats = out->quats;
+    pb.g_opacity = out->opacity;
+    pb.g_sh = out->sh;
+    if (p->n > 0) launch_project_bwd(pb, cam_table(*p), p->n_views, s);
+    if (fuse) {
+        r.acc_sum = acc->sum;
+        r.acc_comp = acc->comp;
+        r.acc_wsum = acc->wsum;
+        r.acc_wcomp = acc->wcomp;
+        launch_reduce_fuse(r, vt, s);
+    }
+    return launch_status();
+}
+
+fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const void* target,
+                           fh_dtype target_dtype, const fh_fusion* acc, hipStream_t s) {
+    if (!p || !ws || !fwd || !target || !acc || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (!fwd->T || !fwd->n_iter || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)
+        return FH_E_INVALID;
+    if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
+    BwdArgs a;
+    fill_bwd_args(p, g, ws, fwd, a);
+    a.target = target;
+    a.target_bf16 = target_dtype == FH_BF16;
+    const ViewTable vt = view_table(*p);
+    launch_render_bwd_f32(a, vt, (int)p->n_tiles, true, s);
+    ReduceArgs r;
+    fill_reduce_args(p, ws, r);
+    r.acc_sum = acc->sum;
+    r.acc_comp = acc->comp;
+    r.acc_wsum = acc->wsum;
+    r.acc_wcomp = acc->wcomp;
+    launch_reduce_fuse(r, vt, s);
+    return launch_status();
+}
+
+fh_status fh_fuse_finalize(const fh_fusion* acc, int64_t n, int32_t d, const void* feat_in, void* feat_out,
+                           fh_dtype dtype, hipStream_t s) {
+    if (!acc || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || !feat_out || n < 0 || d <= 0)
+        return FH_E_INVALID;
+    if (dtype != FH_F32 && dtype != FH_BF16) return FH_E_INVALID;
+    launch_fuse_finalize(acc->sum, acc->comp, acc->wsum, acc->wcomp, n, d, feat_in, feat_out, dtype == FH_BF16, s);
+    return launch_status();
+}
+
+fh_status fh_read_counters(const fh_plan* p, const void* ws, fh_counters* out, hipStream_t s) {
+    if (!p || !ws || !out) return FH_E_INVALID;
+    Counters c;
+    if (hipStreamSynchronize(s) != hipSuccess) return FH_E_HIP;
+    if (hipMemcpy(&c, cbuf<Counters>(p, ws, WS_COUNTERS), sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+        return FH_E_HIP;
+    out->n_instances = (int64_t)c.n_instances;
+    out->n_visited = (int64_t)c.n_visited;
+    out->n_culled_nonfinite = (int64_t)c.n_culled_nonfinite;
+    out->inst_overflow = (int32_t)c.inst_overflow;
+    out->visit_overflow = (int32_t)c.visit_overflow;
+    return FH_OK;
+}
+
+fh_status fh_get_buffer(const fh_plan* p, void* ws, fh_buffer which, void** ptr, int64_t* count) {
+    if (!p || !ws || !ptr || !count) return FH_E_INVALID;
+    const int64_t total = (int64_t)p->n * p->n_views;
+    switch (which) {
+        case FH_BUF_RECORDS: *ptr = buf<void>(p, ws, WS_REC); *count = total * 3; break;
+        case FH_BUF_DEPTH_KEY: *ptr = buf<void>(p, ws, WS_DEPTH_KEY); *count = total; break;
+        case FH_BUF_RECT: *ptr = buf<void>(p, ws, WS_RECT); *count = total * 4; break;
+        case FH_BUF_DEPTH_ORDER: *ptr = buf<void>(p, ws, WS_ORDER); *count = total; break;
+        case FH_BUF_RANGES: *ptr = buf<void>(p, ws, WS_RANGES); *count = p->n_tiles * 2; break;
+        case FH_BUF_TILE_NITER: *ptr = buf<void>(p, ws, WS_TILE_NITER); *count = p->n_tiles; break;
+        case FH_BUF_GRAD2D: *ptr = buf<void>(p, ws, WS_GRAD2D); *count = total * 12; break;
+        default: return FH_E_INVALID;
+    }
+    return FH_OK;
+}
+
+const char* fh_status_string(fh_status s) {
+    switch (s) {
+        case FH_OK: return "ok";
+        case FH_E_INVALID: return "invalid argument";
+        case FH_E_UNSUPPORTED: return "unsupported configuration";
+        case FH_E_HIP: return "HIP runtime or launch error";
+        case FH_E_CAPACITY: return "capacity exceeded";
+    }
+    return "unknown status";
+}
+
+int32_t fh_version(void) { return FH_VERSION; }
+
+}  // extern "C"

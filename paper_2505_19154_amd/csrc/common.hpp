@@ -1,0 +1,166 @@
+// Device-side definitions shared by the HIP kernels of the rasterizer.
+// gfx950 (CDNA4): 64-lane wavefronts, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fhgs.h"
+
+namespace fh {
+
+// ---------------------------------------------------------------------------
+// Method constants.  The paper fixes the 16x16 tile and the (tile, depth) key
+// (Appendix A, "Details of the Rasterizer"); the rest are the 3DGS rules the
+// paper's rasterizer inherits without restating them.
+constexpr int TILE = FH_TILE;
+constexpr int TILE_PIX = TILE * TILE;
+constexpr float Z_NEAR = 0.2f;          // near-plane cull on float32 camera depth
+constexpr float LOWPASS = 0.3f;         // px^2 added to the 2D covariance diagonal
+constexpr double LOWPASS_D = 0.3;
+constexpr float ALPHA_MAX = 0.99f;      // alpha clamp
+constexpr float ALPHA_MIN = 1.0f / 255.0f;  // blends below are skipped
+constexpr float T_MIN = 1e-4f;          // a pixel stops before T would drop below this
+constexpr float KAPPA = 11.1f;          // binning box: sqrt(KAPPA * Sigma2_ii) > 2 ln 255
+constexpr uint32_t CULLED_KEY = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Workspace sub-buffers (indices into fh_plan::off).
+enum WsBuf {
+    WS_COUNTERS = 0,   // Counters
+    WS_REC,            // float4 [V*N*3]
+    WS_DEPTH_KEY,      // u32 [V*N]
+    WS_RECT,           // int4 [V*N]
+    WS_ORDER,          // u32 [V*N]  depth-sorted Gaussian index per view
+    WS_ORDER_TMP,      // u32 [V*N]
+    WS_DKEY_TMP,       // u32 [V*N]  radix ping-pong for the depth keys
+    WS_DKEY_TMP2,      // u32 [V*N]
+    WS_INST_OFF,       // u32 [V*N + 1] exclusive scan of tiles per rank
+    WS_SCAN_TMP,       // u32 scratch for multi-level scans
+    WS_HIST,           // u32 radix histograms
+    WS_RANGES,         // u32 [tiles*2]
+    WS_TILE_NITER,     // u32 [tiles]
+    WS_TILE_VOFF,      // u32 [tiles+1]
+    WS_TILE_LAST,      // u32 [tiles] rank of the last visited instance
+    WS_GRAD2D,         // float [V*N*12]
+    WS_RANK_OF,        // u32 [V*N]  depth rank of every (view, Gaussian)
+    WS_KEYS_A,         // u32 [cap]
+    WS_KEYS_B,         // u32 [cap]
+    WS_VALS_A,         // u32 [cap] (unpacked keys only)
+    WS_VALS_B,         // u32 [cap]
+    WS_PART_GEOM,      // float4 [visit_cap * 3]
+    WS_PART_FUSE,      // float [visit_cap * d]
+    WS_COUNT
+};
+
+struct Counters {
+    unsigned long long n_instances;
+    unsigned long long n_visited;
+    unsigned long long n_culled_nonfinite;
+    unsigned int inst_overflow;
+    unsigned int visit_overflow;
+    unsigned int pad[8];
+};
+
+// Per-view constants passed by value to kernels.
+struct ViewTable {
+    int n_views;
+    int n_tiles;
+    int tiles_x[FH_MAX_VIEWS];
+    int tiles_y[FH_MAX_VIEWS];
+    int width[FH_MAX_VIEWS];
+    int height[FH_MAX_VIEWS];
+    int tile_off[FH_MAX_VIEWS + 1];
+    long long pix_off[FH_MAX_VIEWS + 1];
+};
+
+struct CamTable {
+    fh_camera cam[FH_MAX_VIEWS];
+};
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int t) {
+    int v = 0;
+    while (v + 1 < vt.n_views && t >= vt.tile_off[v + 1]) ++v;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Screen-space record of one (view, Gaussian), three float4:
+//   r0 = (u_hi, v_hi, u_lo, v_lo)      mean, as an unevaluated float pair
+//   r1 = (e_x, e_y, q1, q2)            eigenframe of the conic: unit e1 and
+//                                      q_i = -lambda_i log2(e) / 2
+//   r2 = (opacity, r, g, b)
+// The screen density is G = exp2(q1 a^2 + q2 b^2) with a = e1 . d,
+// b = e1 x d, d = pixel - mean; this equals exp(-1/2 d^T Sigma2^-1 d).
+struct Rec {
+    float4 r0, r1, r2;
+};
+
+// alpha = min(ALPHA_MAX, o G) at pixel centre (x, y), evaluated with explicit
+// fused operations so that every kernel gets the same bits.
+struct AlphaEval {
+    float dx, dy, a, b, G, raw, alpha;
+};
+
+__device__ __forceinline__ AlphaEval eval_alpha(const Rec& r, float x, float y) {
+#pragma clang fp contract(off)
+    AlphaEval e;
+    e.dx = (x - r.r0.x) - r.r0.z;
+    e.dy = (y - r.r0.y) - r.r0.w;
+    const float ex = r.r1.x, ey = r.r1.y;
+    e.a = __builtin_fmaf(ex, e.dx, ey * e.dy);
+    e.b = __builtin_fmaf(ex, e.dy, -(ey * e.dx));
+    const float p2 = __builtin_fmaf(r.r1.z, e.a * e.a, r.r1.w * (e.b * e.b));
+    e.G = __builtin_amdgcn_exp2f(p2);
+    e.raw = r.r2.x * e.G;
+    e.alpha = fminf(ALPHA_MAX, e.raw);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (64 lanes).
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        unsigned int o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Neumaier compensated addition: (s, c) += x.
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float x) {
+#pragma clang fp contract(off)
+    const float t = s + x;
+    if (fabsf(s) >= fabsf(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ T* ws_ptr(const fh_plan& p, void* ws, int which) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + p.off[which]);
+}
+
+}  // namespace fh

@@ -1,0 +1,127 @@
+// Kernel argument structs and launchers shared by the HIP translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace fh {
+// project.hip
+struct ProjectArgs {
+    const float *means, *scales, *quats, *opacity, *sh;
+    int n, sh_degree;
+    float4* rec;
+    uint32_t* depth_key;
+    int4* rect;
+    Counters* counters;
+};
+struct ProjectBwdArgs {
+    const float *means, *scales, *quats, *opacity, *sh;
+    int n, sh_degree;
+    const float* grad2d;
+    const uint32_t* depth_key;
+    float *g_means, *g_scales, *g_quats, *g_opacity, *g_sh;
+};
+void launch_project(const ProjectArgs&, const CamTable&, const ViewTable&, int, hipStream_t);
+void launch_project_bwd(const ProjectBwdArgs&, const CamTable&, int, hipStream_t);
+// sort.hip
+size_t scan_scratch_u32(int64_t n);
+void device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, int write_total,
+                           hipStream_t s);
+int radix_sort(const uint32_t* keys_src, const uint32_t* vals_src, uint32_t* ka, uint32_t* va, uint32_t* kb,
+               uint32_t* vb, bool with_vals, int64_t segs, int64_t seg_len, const unsigned long long* dev_len,
+               int64_t cap, int lo, int hi, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+size_t radix_hist_u32(int64_t segs, int64_t span);
+struct DupArgs {
+    const uint32_t* inst_off;
+    const uint32_t* order;
+    const int4* rect;
+    int64_t n, total_ranks;
+    int64_t cap;
+    const Counters* counters;
+    uint32_t* keys;
+    uint32_t* vals;
+    int rank_bits;
+    int packed;
+    ViewTable vt;
+};
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+void launch_tiles_by_rank(const uint32_t* order, const int4* rect, int64_t n, int64_t total, uint32_t* ntiles,
+                          Counters* c, hipStream_t s);
+void launch_check_capacity(Counters* c, int64_t cap, hipStream_t s);
+void launch_duplicate(const DupArgs& a, hipStream_t s);
+void launch_ranges(const uint32_t* keys, const Counters* c, int64_t cap, int rank_bits, int packed, uint32_t* ranges,
+                   hipStream_t s);
+void launch_bin_keys(const uint32_t* keys, const uint32_t* vals, const uint32_t* order, const uint32_t* depth_key,
+                     int64_t n_inst, int64_t n, int rank_bits, int packed, uint64_t* ko, uint32_t* go, hipStream_t s);
+// render_f32.hip
+struct RenderArgs {
+    const float4* rec;
+    const uint32_t* order;
+    const uint32_t* keys;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    const Counters* counters;
+    int rank_bits, packed;
+    int64_t n;
+    const void* feat;
+    int d, feat_bf16;
+    float* C;
+    float* F;
+    float* T;
+    uint32_t* n_iter;
+    uint32_t* tile_niter;
+};
+struct BwdArgs {
+    const float4* rec;
+    const uint32_t* order;
+    const uint32_t* keys;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    const uint32_t* tile_niter;
+    const uint32_t* tile_voff;
+    const Counters* counters;
+    int rank_bits, packed;
+    int64_t n;
+    const void* feat;
+    int d, feat_bf16;
+    const float* T_final;
+    const uint32_t* n_iter;
+    const float* dC;
+    const float* dF;
+    const float* dT;
+    const void* target;
+    int target_bf16;
+    float* part_geom;
+    float* part_fuse;
+};
+struct ReduceArgs {
+    const uint32_t* order;
+    const int4* rect;
+    const uint32_t* keys;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    const uint32_t* tile_niter;
+    const uint32_t* tile_voff;
+    const uint32_t* tile_last;
+    const Counters* counters;
+    int rank_bits, packed;
+    int64_t n, total;
+    const float* part_geom;
+    float* grad2d;
+    const uint32_t* rank_of;
+    const float* part_fuse;
+    int d;
+    int n_views;
+    float *acc_sum, *acc_comp, *acc_wsum, *acc_wcomp;
+};
+void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
+void launch_tile_last(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* keys, const uint32_t* vals,
+                      int rank_bits, int packed, int n_tiles, uint32_t* tile_last, hipStream_t s);
+void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
+void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s);
+void launch_reduce_geom(const ReduceArgs& a, const ViewTable& vt, hipStream_t s);
+void launch_reduce_fuse(const ReduceArgs& a, const ViewTable& vt, hipStream_t s);
+void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s);
+void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
+                          const void* feat_in, void* feat_out, int bf16, hipStream_t s);
+
+}  // namespace fh

@@ -1,0 +1,412 @@
+// Projection of every (view, Gaussian) to the screen, and its adjoint.
+//
+// Forward (Algorithm 2, Homogenization + 2DScreenGaussians; the screen-space
+// Gaussian of Section 3.1):
+//   * binning quantities (depth key, tile rect) in float32 with a fixed
+//     operation order and no contraction, so that the keys are reproducible
+//     bit for bit;
+//   * the 2D covariance Sigma2 = J W Sigma3 W^T J^T + 0.3 I, its inverse and
+//     the inverse's eigenframe in FP64 (the one FP64 block of the path: the
+//     covariance can be nearly singular for thin, edge-on Gaussians);
+//   * the mean (u, v) from the FP64 camera-space centre, stored as a float
+//     pair hi + lo so that pixel offsets keep full FP32 accuracy at 1080p;
+//   * view-dependent colour from real SH of degree <= 3 in FP32.
+// One thread per (view, Gaussian); SoA inputs, coalesced record writes.
+#include "kernels.hpp"
+
+namespace fh {
+
+struct BinQ {
+    float depth, u, v, ex, ey;
+    int x0, y0, x1, y1;
+    bool binned;
+};
+
+// The float32 binning chain.  Every line is one IEEE float32 operation in the
+// written order; contraction into FMA is disabled.
+__device__ BinQ binning_f32(float mx, float my, float mz, float sx, float sy, float sz, float qw, float qx,
+                            float qy, float qz, const fh_camera& c, int tiles_x, int tiles_y) {
+#pragma clang fp contract(off)
+    const float* R = c.R;
+    const float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + c.t[0];
+    const float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + c.t[1];
+    const float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + c.t[2];
+    BinQ b;
+    b.depth = pz;
+    const bool visible = pz > Z_NEAR;
+    b.u = (c.fx * px) / pz + c.cx;
+    b.v = (c.fy * py) / pz + c.cy;
+
+    const float n = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    const float k = 2.0f / n;
+    float Rq[9];
+    Rq[0] = 1.0f - k * (qy * qy + qz * qz);
+    Rq[1] = k * (qx * qy - qw * qz);
+    Rq[2] = k * (qx * qz + qw * qy);
+    Rq[3] = k * (qx * qy + qw * qz);
+    Rq[4] = 1.0f - k * (qx * qx + qz * qz);
+    Rq[5] = k * (qy * qz - qw * qx);
+    Rq[6] = k * (qx * qz - qw * qy);
+    Rq[7] = k * (qy * qz + qw * qx);
+    Rq[8] = 1.0f - k * (qx * qx + qy * qy);
+    const float s[3] = {sx, sy, sz};
+    float M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * s[j];
+
+    const float j00 = c.fx / pz;
+    const float j11 = c.fy / pz;
+    const float j02 = -(j00 * px) / pz;
+    const float j12 = -(j11 * py) / pz;
+    float T0[3], T1[3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        T0[kk] = j00 * R[kk] + j02 * R[6 + kk];
+        T1[kk] = j11 * R[3 + kk] + j12 * R[6 + kk];
+    }
+    float W0[3], W1[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        W0[l] = (T0[0] * M[l] + T0[1] * M[3 + l]) + T0[2] * M[6 + l];
+        W1[l] = (T1[0] * M[l] + T1[1] * M[3 + l]) + T1[2] * M[6 + l];
+    }
+    const float a = ((W0[0] * W0[0] + W0[1] * W0[1]) + W0[2] * W0[2]) + LOWPASS;
+    const float cc = ((W1[0] * W1[0] + W1[1] * W1[1]) + W1[2] * W1[2]) + LOWPASS;
+    b.ex = sqrtf(KAPPA * a);
+    b.ey = sqrtf(KAPPA * cc);
+
+    const float ts = (float)TILE;
+    const float x0f = floorf((b.u - b.ex) / ts);
+    const float x1f = floorf((b.u + b.ex) / ts);
+    const float y0f = floorf((b.v - b.ey) / ts);
+    const float y1f = floorf((b.v + b.ey) / ts);
+    const bool finite = isfinite(b.u) && isfinite(b.v) && isfinite(b.ex) && isfinite(b.ey);
+    const bool ok = visible && finite;
+    b.x0 = ok ? (int)fmaxf(x0f, 0.0f) : 0;
+    b.x1 = ok ? (int)fminf(x1f, (float)(tiles_x - 1)) : -1;
+    b.y0 = ok ? (int)fmaxf(y0f, 0.0f) : 0;
+    b.y1 = ok ? (int)fminf(y1f, (float)(tiles_y - 1)) : -1;
+    b.binned = ok && b.x0 <= b.x1 && b.y0 <= b.y1;
+    return b;
+}
+
+// Real spherical harmonics (orthonormal, Condon-Shortley phase, index
+// l*l + m + l) as Cartesian polynomials of the unit direction (x, y, z).
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+    Y[0] = 0.28209479177387814f;
+    if (deg < 1) return;
+    Y[1] = -0.48860251190291992f * y;
+    Y[2] = 0.48860251190291992f * z;
+    Y[3] = -0.48860251190291992f * x;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.54627421529603959f * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+    Y[10] = 2.8906114426405538f * x * y * z;
+    Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);
+    Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
+// Gradient of the polynomials above with respect to (x, y, z): G[b][0..2].
+__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, float (*G)[3]) {
+    G[0][0] = G[0][1] = G[0][2] = 0.0f;
+    if (deg < 1) return;
+    const float c1 = 0.48860251190291992f;
+    G[1][0] = 0.0f; G[1][1] = -c1; G[1][2] = 0.0f;
+    G[2][0] = 0.0f; G[2][1] = 0.0f; G[2][2] = c1;
+    G[3][0] = -c1; G[3][1] = 0.0f; G[3][2] = 0.0f;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.54627421529603959f;
+    G[4][0] = c2a * y; G[4][1] = c2a * x; G[4][2] = 0.0f;
+    G[5][0] = 0.0f; G[5][1] = -c2a * z; G[5][2] = -c2a * y;
+    G[6][0] = -2.0f * c2b * x; G[6][1] = -2.0f * c2b * y; G[6][2] = 4.0f * c2b * z;
+    G[7][0] = -c2a * z; G[7][1] = 0.0f; G[7][2] = -c2a * x;
+    G[8][0] = 2.0f * c2c * x; G[8][1] = -2.0f * c2c * y; G[8][2] = 0.0f;
+    if (deg < 3) return;
+    const float c3a = 0.59004358992664352f, c3b = 2.8906114426405538f, c3c = 0.45704579946446572f,
+                c3d = 0.37317633259011540f, c3e = 1.4453057213202769f;
+    // Y9 = -c3a (3 x^2 y - y^3)
+    G[9][0] = -c3a * 6.0f * x * y; G[9][1] = -c3a * (3.0f * xx - 3.0f * yy); G[9][2] = 0.0f;
+    // Y10 = c3b x y z
+    G[10][0] = c3b * y * z; G[10][1] = c3b * x * z; G[10][2] = c3b * x * y;
+    // Y11 = -c3c (4 y z^2 - x^2 y - y^3)
+    G[11][0] = c3c * 2.0f * x * y; G[11][1] = -c3c * (4.0f * zz - xx - 3.0f * yy); G[11][2] = -c3c * 8.0f * y * z;
+    // Y12 = c3d (2 z^3 - 3 x^2 z - 3 y^2 z)
+    G[12][0] = -c3d * 6.0f * x * z; G[12][1] = -c3d * 6.0f * y * z; G[12][2] = c3d * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+    // Y13 = -c3c (4 x z^2 - x^3 - x y^2)
+    G[13][0] = -c3c * (4.0f * zz - 3.0f * xx - yy); G[13][1] = c3c * 2.0f * x * y; G[13][2] = -c3c * 8.0f * x * z;
+    // Y14 = c3e (x^2 z - y^2 z)
+    G[14][0] = c3e * 2.0f * x * z; G[14][1] = -c3e * 2.0f * y * z; G[14][2] = c3e * (xx - yy);
+    // Y15 = -c3a (x^3 - 3 x y^2)
+    G[15][0] = -c3a * (3.0f * xx - 3.0f * yy); G[15][1] = c3a * 6.0f * x * y; G[15][2] = 0.0f;
+}
+
+// FP64 screen-space covariance for one (camera, Gaussian): camera-space
+// centre p, Sigma2 entries (a, b, c) including the low-pass, and the pieces
+// the adjoint reuses.
+struct Cov64 {
+    double p[3];
+    double T[2][3];   // J R_c
+    double M[3][3];   // R_q diag(s)
+    double Rq[3][3];
+    double qn[4], qnorm;
+    double W[2][3];   // T M
+    double a, b, c;
+};
+
+__device__ Cov64 cov64(const float* mu, const float* sc, const float* q, const fh_camera& cam) {
+    Cov64 o;
+    const float* R = cam.R;
+    for (int r = 0; r < 3; ++r)
+        o.p[r] = (double)R[3 * r] * mu[0] + (double)R[3 * r + 1] * mu[1] + (double)R[3 * r + 2] * mu[2] + (double)cam.t[r];
+    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    o.qnorm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / o.qnorm, x = qx / o.qnorm, y = qy / o.qnorm, z = qz / o.qnorm;
+    o.qn[0] = w; o.qn[1] = x; o.qn[2] = y; o.qn[3] = z;
+    o.Rq[0][0] = 1 - 2 * (y * y + z * z); o.Rq[0][1] = 2 * (x * y - w * z); o.Rq[0][2] = 2 * (x * z + w * y);
+    o.Rq[1][0] = 2 * (x * y + w * z); o.Rq[1][1] = 1 - 2 * (x * x + z * z); o.Rq[1][2] = 2 * (y * z - w * x);
+    o.Rq[2][0] = 2 * (x * z - w * y); o.Rq[2][1] = 2 * (y * z + w * x); o.Rq[2][2] = 1 - 2 * (x * x + y * y);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) o.M[i][j] = o.Rq[i][j] * (double)sc[j];
+    const double fx = cam.fx, fy = cam.fy, pz = o.p[2];
+    const double j00 = fx / pz, j02 = -fx * o.p[0] / (pz * pz);
+    const double j11 = fy / pz, j12 = -fy * o.p[1] / (pz * pz);
+    for (int k = 0; k < 3; ++k) {
+        o.T[0][k] = j00 * R[k] + j02 * R[6 + k];
+        o.T[1][k] = j11 * R[3 + k] + j12 * R[6 + k];
+    }
+    for (int r = 0; r < 2; ++r)
+        for (int l = 0; l < 3; ++l) o.W[r][l] = o.T[r][0] * o.M[0][l] + o.T[r][1] * o.M[1][l] + o.T[r][2] * o.M[2][l];
+    o.a = o.W[0][0] * o.W[0][0] + o.W[0][1] * o.W[0][1] + o.W[0][2] * o.W[0][2] + LOWPASS_D;
+    o.b = o.W[0][0] * o.W[1][0] + o.W[0][1] * o.W[1][1] + o.W[0][2] * o.W[1][2];
+    o.c = o.W[1][0] * o.W[1][0] + o.W[1][1] * o.W[1][1] + o.W[1][2] * o.W[1][2] + LOWPASS_D;
+    return o;
+}
+
+__device__ __forceinline__ void cam_centre(const fh_camera& c, float* cp) {
+    const float* R = c.R;
+    for (int k = 0; k < 3; ++k) cp[k] = -(R[k] * c.t[0] + R[3 + k] * c.t[1] + R[6 + k] * c.t[2]);
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, ViewTable vt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (g >= a.n) return;
+    const fh_camera& cam = ct.cam[v];
+    const float mu[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
+    const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
+    const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const BinQ bq = binning_f32(mu[0], mu[1], mu[2], sc[0], sc[1], sc[2], q[0], q[1], q[2], q[3], cam,
+                                vt.tiles_x[v], vt.tiles_y[v]);
+    const size_t j = (size_t)v * a.n + g;
+    const float op = a.opacity[g];
+    const bool binned = bq.binned;
+    float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0;
+    if (binned) {
+        const Cov64 cv = cov64(mu, sc, q, cam);
+        const double det = cv.a * cv.c - cv.b * cv.b;
+        const double A = cv.c / det, B = -cv.b / det, C = cv.a / det;
+        const double tr = A + C, df = A - C;
+        const double disc = sqrt(df * df + 4.0 * B * B);
+        const double l1 = 0.5 * (tr + disc);
+        const double l2 = (1.0 / det) / l1;
+        const double th = 0.5 * atan2(2.0 * B, df);
+        const double LOG2E = 1.4426950408889634;
+        const double u = (double)cam.fx * cv.p[0] / cv.p[2] + (double)cam.cx;
+        const double vv = (double)cam.fy * cv.p[1] / cv.p[2] + (double)cam.cy;
+        const float uh = (float)u, vh = (float)vv;
+        // a degenerate FP64 covariance keeps its instances but never blends (opacity 0)
+        const bool fin = isfinite(det) && det > 0.0 && isfinite(l1) && isfinite(l2) && l2 > 0.0;
+        r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
+        r1 = make_float4((float)cos(th), (float)sin(th), (float)(-0.5 * LOG2E * l1), (float)(-0.5 * LOG2E * l2));
+        // colour
+        float cp[3];
+        cam_centre(cam, cp);
+        float dx = mu[0] - cp[0], dy = mu[1] - cp[1], dz = mu[2] - cp[2];
+        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= il; dy *= il; dz *= il;
+        float Y[16];
+        sh_basis(a.sh_degree, dx, dy, dz, Y);
+        const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+        const float* shg = a.sh + (size_t)g * nb * 3;
+        float col[3] = {0.5f, 0.5f, 0.5f};
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) col[ch] += shg[3 * b + ch] * Y[b];
+        r2 = make_float4(fin ? op : 0.0f, fmaxf(col[0], 0.0f), fmaxf(col[1], 0.0f), fmaxf(col[2], 0.0f));
+    }
+    if (v == 0) {
+        bool bad = !(isfinite(op));
+        for (int k = 0; k < 3; ++k) bad |= !isfinite(mu[k]) || !isfinite(sc[k]);
+        for (int k = 0; k < 4; ++k) bad |= !isfinite(q[k]);
+        if (bad) atomicAdd(&a.counters->n_culled_nonfinite, 1ull);
+    }
+    a.rec[3 * j] = r0;
+    a.rec[3 * j + 1] = r1;
+    a.rec[3 * j + 2] = r2;
+    a.depth_key[j] = binned ? __float_as_uint(bq.depth) : CULLED_KEY;
+    a.rect[j] = binned ? make_int4(bq.x0, bq.y0, bq.x1, bq.y1) : make_int4(0, 0, -1, -1);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the projection, summed over views in view order (deterministic).
+// grad2d[(v*N + g)*12 + k], k: 0 u, 1 v, 2 A, 3 B, 4 C, 5 sum dL/dpower,
+// 6..8 rgb, 9 sum w.
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable ct, int n_views) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const float mu[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
+    const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
+    const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float op = a.opacity[g];
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    const float* shg = a.sh + (size_t)g * nb * 3;
+
+    float gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f;
+    float gsh[16][3];
+    for (int b = 0; b < 16; ++b) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
+
+    for (int v = 0; v < n_views; ++v) {
+        const size_t j = (size_t)v * a.n + g;
+        if (a.depth_key[j] == CULLED_KEY) continue;
+        const float* g2 = a.grad2d + j * 12;
+        const fh_camera& cam = ct.cam[v];
+        const Cov64 cv = cov64(mu, sc, q, cam);
+
+        // opacity: alpha = o G, so dL/do = (sum_p dL/dpower) / o
+        gop += g2[5] / op;
+
+        // conic (A, B, C) = (c, -b, a)/det  ->  Sigma2 entries (a, b, c), FP64
+        const double a_ = cv.a, b_ = cv.b, c_ = cv.c;
+        const double det = a_ * c_ - b_ * b_;
+        const double d2 = det * det;
+        const double uA = g2[2], uB = g2[3], uC = g2[4];
+        const double up_a = (-c_ * c_ * uA + b_ * c_ * uB - b_ * b_ * uC) / d2;
+        const double up_b = (2.0 * b_ * c_ * uA - (a_ * c_ + b_ * b_) * uB + 2.0 * a_ * b_ * uC) / d2;
+        const double up_c = (-b_ * b_ * uA + a_ * b_ * uB - a_ * a_ * uC) / d2;
+
+        // a = |W0|^2, b = W0 . W1, c = |W1|^2 with W = T M (2x3)
+        float upW[2][3];
+        for (int l = 0; l < 3; ++l) {
+            upW[0][l] = (float)(2.0 * up_a * cv.W[0][l] + up_b * cv.W[1][l]);
+            upW[1][l] = (float)(up_b * cv.W[0][l] + 2.0 * up_c * cv.W[1][l]);
+        }
+        // W = T M: dT = dW M^T, dM = T^T dW
+        float upT[2][3], upM[3][3];
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k)
+                upT[r][k] = upW[r][0] * (float)cv.M[k][0] + upW[r][1] * (float)cv.M[k][1] + upW[r][2] * (float)cv.M[k][2];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) upM[k][l] = (float)cv.T[0][k] * upW[0][l] + (float)cv.T[1][k] * upW[1][l];
+
+        // T = J R_c
+        const float* R = cam.R;
+        const float uJ00 = upT[0][0] * R[0] + upT[0][1] * R[1] + upT[0][2] * R[2];
+        const float uJ02 = upT[0][0] * R[6] + upT[0][1] * R[7] + upT[0][2] * R[8];
+        const float uJ11 = upT[1][0] * R[3] + upT[1][1] * R[4] + upT[1][2] * R[5];
+        const float uJ12 = upT[1][0] * R[6] + upT[1][1] * R[7] + upT[1][2] * R[8];
+
+        // J, (u, v) -> camera-space centre
+        const float px = (float)cv.p[0], py = (float)cv.p[1], pz = (float)cv.p[2];
+        const float fx = cam.fx, fy = cam.fy;
+        const float iz = 1.0f / pz, iz2 = iz * iz, iz3 = iz2 * iz;
+        const float uu = g2[0], uv = g2[1];
+        const float upx = fx * iz * uu - fx * iz2 * uJ02;
+        const float upy = fy * iz * uv - fy * iz2 * uJ12;
+        const float upz = -fx * px * iz2 * uu - fy * py * iz2 * uv - fx * iz2 * uJ00 + 2.0f * fx * px * iz3 * uJ02
+                          - fy * iz2 * uJ11 + 2.0f * fy * py * iz3 * uJ12;
+        // p = R_c mu + t
+        for (int k = 0; k < 3; ++k) gmu[k] += R[k] * upx + R[3 + k] * upy + R[6 + k] * upz;
+
+        // M = R_q diag(s)
+        float upR[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) upR[k][l] = upM[k][l] * sc[l];
+        for (int l = 0; l < 3; ++l)
+            gs[l] += upM[0][l] * (float)cv.Rq[0][l] + upM[1][l] * (float)cv.Rq[1][l] + upM[2][l] * (float)cv.Rq[2][l];
+
+        // R_q(qn)
+        const float w = (float)cv.qn[0], x = (float)cv.qn[1], y = (float)cv.qn[2], z = (float)cv.qn[3];
+        const float gw = 2.0f * (-z * upR[0][1] + y * upR[0][2] + z * upR[1][0] - x * upR[1][2] - y * upR[2][0] + x * upR[2][1]);
+        const float gx = 2.0f * (y * upR[0][1] + z * upR[0][2] + y * upR[1][0] - 2.0f * x * upR[1][1] - w * upR[1][2]
+                                 + z * upR[2][0] + w * upR[2][1] - 2.0f * x * upR[2][2]);
+        const float gy = 2.0f * (-2.0f * y * upR[0][0] + x * upR[0][1] + w * upR[0][2] + x * upR[1][0] + z * upR[1][2]
+                                 - w * upR[2][0] + z * upR[2][1] - 2.0f * y * upR[2][2]);
+        const float gz = 2.0f * (-2.0f * z * upR[0][0] - w * upR[0][1] + x * upR[0][2] + w * upR[1][0] - 2.0f * z * upR[1][1]
+                                 + y * upR[1][2] + x * upR[2][0] + y * upR[2][1]);
+        // qn = q / |q|
+        const float dotq = w * gw + x * gx + y * gy + z * gz;
+        const float iq = (float)(1.0 / cv.qnorm);
+        gq[0] += (gw - w * dotq) * iq;
+        gq[1] += (gx - x * dotq) * iq;
+        gq[2] += (gy - y * dotq) * iq;
+        gq[3] += (gz - z * dotq) * iq;
+
+        // colour: rgb = max(0, sum_b sh_b Y_b(dir) + 1/2), dir = (mu - cam) / |mu - cam|
+        float cp[3];
+        cam_centre(cam, cp);
+        float ddx = mu[0] - cp[0], ddy = mu[1] - cp[1], ddz = mu[2] - cp[2];
+        const float il = 1.0f / sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+        const float dx = ddx * il, dy = ddy * il, dz = ddz * il;
+        float Y[16];
+        sh_basis(a.sh_degree, dx, dy, dz, Y);
+        float raw[3] = {0.5f, 0.5f, 0.5f};
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) raw[ch] += shg[3 * b + ch] * Y[b];
+        float urgb[3];
+        for (int ch = 0; ch < 3; ++ch) urgb[ch] = raw[ch] > 0.0f ? g2[6 + ch] : 0.0f;
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) gsh[b][ch] += Y[b] * urgb[ch];
+        if (a.sh_degree > 0) {
+            float GY[16][3];
+            sh_basis_grad(a.sh_degree, dx, dy, dz, GY);
+            float udir[3] = {0, 0, 0};
+            for (int b = 1; b < nb; ++b) {
+                const float s = shg[3 * b] * urgb[0] + shg[3 * b + 1] * urgb[1] + shg[3 * b + 2] * urgb[2];
+                udir[0] += GY[b][0] * s;
+                udir[1] += GY[b][1] * s;
+                udir[2] += GY[b][2] * s;
+            }
+            const float dd = dx * udir[0] + dy * udir[1] + dz * udir[2];
+            gmu[0] += (udir[0] - dx * dd) * il;
+            gmu[1] += (udir[1] - dy * dd) * il;
+            gmu[2] += (udir[2] - dz * dd) * il;
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        a.g_means[3 * g + k] = gmu[k];
+        a.g_scales[3 * g + k] = gs[k];
+    }
+    reinterpret_cast<float4*>(a.g_quats)[g] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    a.g_opacity[g] = gop;
+    float* gsho = a.g_sh + (size_t)g * nb * 3;
+    for (int b = 0; b < nb; ++b)
+        for (int ch = 0; ch < 3; ++ch) gsho[3 * b + ch] = gsh[b][ch];
+}
+
+// ---------------------------------------------------------------------------
+void launch_project(const ProjectArgs& a, const CamTable& ct, const ViewTable& vt, int n_views, hipStream_t s) {
+    dim3 grid((a.n + 255) / 256, n_views);
+    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, a, ct, vt);
+}
+
+void launch_project_bwd(const ProjectBwdArgs& a, const CamTable& ct, int n_views, hipStream_t s) {
+    hipLaunchKernelGGL(k_project_bwd, dim3((a.n + 255) / 256), dim3(256), 0, s, a, ct, n_views);
+}
+
+}  // namespace fh

@@ -1,0 +1,249 @@
+"""Python front end of the HIP rasterizer: device memory and streams from PyTorch,
+every computation in libfhgs.so.
+
+`Rasterizer` owns one plan (sizes, capacities, workspace layout) and its
+workspace tensor for a fixed set of cameras, and exposes the C-ABI calls with
+the same names: project, bin_sort, render_fwd, render_bwd, fuse_features,
+fuse_finalize.  Capacities for the data-dependent instance and visit counts
+grow on demand (eager use reads the device counters once per call); callers
+that must not synchronise (graph capture, the benchmark's timed loop) fix the
+capacities up front with `reserve` and check the counters afterwards.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+# indices of workspace sub-buffers (order of the WsBuf enum in csrc/common.hpp)
+_WS = {name: i for i, name in enumerate(
+    ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
+     "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "tile_last", "grad2d", "rank_of", "keys_a",
+     "keys_b", "vals_a", "vals_b", "part_geom", "part_fuse"])}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Gaussians:
+    """Device tensors of the Gaussians (activated parameters, see include/fhgs.h)."""
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacity: torch.Tensor
+    sh: torch.Tensor
+    feat: torch.Tensor | None
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def d(self) -> int:
+        return 0 if self.feat is None else int(self.feat.shape[1])
+
+    @property
+    def feat_dtype(self) -> int:
+        return L.FH_BF16 if (self.feat is not None and self.feat.dtype == torch.bfloat16) else L.FH_F32
+
+    def struct(self) -> L.FhGaussians:
+        for name in ("means", "scales", "quats", "opacity", "sh"):
+            t = getattr(self, name)
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise L.FhError(f"{name} must be a contiguous float32 CUDA tensor")
+        if self.feat is not None and (not self.feat.is_contiguous() or self.feat.dtype not in (torch.float32, torch.bfloat16)):
+            raise L.FhError("feat must be contiguous float32 or bfloat16")
+        return L.FhGaussians(_ptr(self.means), _ptr(self.scales), _ptr(self.quats), _ptr(self.opacity),
+                             _ptr(self.sh), _ptr(self.feat), self.n, self.sh_degree, self.d, self.feat_dtype, 0)
+
+
+@dataclass
+class Image:
+    C: torch.Tensor
+    F: torch.Tensor | None
+    T: torch.Tensor
+    n_iter: torch.Tensor
+
+    def struct(self) -> L.FhImage:
+        return L.FhImage(_ptr(self.C), _ptr(self.F), _ptr(self.T), _ptr(self.n_iter))
+
+
+@dataclass
+class FusionAcc:
+    """Neumaier-compensated per-Gaussian fusion accumulators (running value = sum + comp)."""
+    sum: torch.Tensor
+    comp: torch.Tensor
+    wsum: torch.Tensor
+    wcomp: torch.Tensor
+
+    @staticmethod
+    def zeros(n: int, d: int, device) -> "FusionAcc":
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=device)
+        return FusionAcc(z(n, d), z(n, d), z(n), z(n))
+
+    def struct(self) -> L.FhFusion:
+        return L.FhFusion(_ptr(self.sum), _ptr(self.comp), _ptr(self.wsum), _ptr(self.wcomp))
+
+
+def camera_struct(cam) -> L.FhCamera:
+    R = [float(x) for x in list(cam.R.reshape(-1))]
+    t = [float(x) for x in list(cam.t.reshape(-1))]
+    return L.FhCamera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                      (ctypes.c_float * 9)(*R), (ctypes.c_float * 3)(*t))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Rasterizer:
+    """Plan + workspace for one batch of cameras and one Gaussian set size."""
+
+    def __init__(self, cams, n: int, sh_degree: int, d: int, feat_dtype: str = "f32", form: str = "f32",
+                 device="cuda", inst_capacity: int = 0, visit_capacity: int = 0):
+        self.lib = L.load()
+        self.cams = list(cams)
+        self.cam_arr = (L.FhCamera * len(self.cams))(*[camera_struct(c) for c in self.cams])
+        self.n, self.sh_degree, self.d = int(n), int(sh_degree), int(d)
+        self.feat_dtype = L.FH_BF16 if feat_dtype == "bf16" else L.FH_F32
+        self.form = L.FH_FORM_BF16 if form == "bf16" else L.FH_FORM_F32
+        self.device = torch.device(device)
+        self.plan = None
+        self.ws = None
+        self._plan(inst_capacity, visit_capacity)
+
+    # -- plan and workspace -------------------------------------------------
+    def _plan(self, inst_cap: int, visit_cap: int) -> None:
+        plan = L.FhPlan()
+        L.check(self.lib.fh_plan_init(ctypes.byref(plan), self.n, self.sh_degree, self.d, self.feat_dtype, self.form,
+                                      self.cam_arr, len(self.cams), int(inst_cap), int(visit_cap)), "fh_plan_init")
+        self.plan = plan
+        self.ws = torch.empty(max(int(plan.ws_bytes), 256), dtype=torch.uint8, device=self.device)
+
+    def reserve(self, inst_capacity: int, visit_capacity: int) -> None:
+        if inst_capacity != self.plan.inst_capacity or visit_capacity != self.plan.visit_capacity:
+            self._plan(inst_capacity, visit_capacity)
+
+    @property
+    def n_pixels(self) -> int:
+        return int(self.plan.n_pixels)
+
+    @property
+    def n_tiles(self) -> int:
+        return int(self.plan.n_tiles)
+
+    def ws_view(self, name: str, dtype, count: int) -> torch.Tensor:
+        off = int(self.plan.off[_WS[name]])
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype)
+
+    def counters(self) -> L.FhCounters:
+        c = L.FhCounters()
+        L.check(self.lib.fh_read_counters(ctypes.byref(self.plan), _ptr(self.ws), ctypes.byref(c), _stream()),
+                "fh_read_counters")
+        return c
+
+    # -- the C-ABI calls ----------------------------------------------------
+    def project(self, g: Gaussians) -> None:
+        gs = g.struct()
+        L.check(self.lib.fh_project(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), _stream()), "fh_project")
+
+    def bin_count(self) -> None:
+        L.check(self.lib.fh_bin_count(ctypes.byref(self.plan), _ptr(self.ws), _stream()), "fh_bin_count")
+
+    def bin_sort(self) -> None:
+        L.check(self.lib.fh_bin_sort(ctypes.byref(self.plan), _ptr(self.ws), _stream()), "fh_bin_sort")
+
+    def bin_keys(self, n_inst: int):
+        keys = torch.empty(n_inst, dtype=torch.int64, device=self.device)
+        gids = torch.empty(n_inst, dtype=torch.int32, device=self.device)
+        L.check(self.lib.fh_bin_keys(ctypes.byref(self.plan), _ptr(self.ws), _ptr(keys), _ptr(gids), n_inst,
+                                     _stream()), "fh_bin_keys")
+        return keys, gids
+
+    def new_image(self) -> Image:
+        P, d = self.n_pixels, self.d
+        dev = self.device
+        return Image(torch.empty(P, 3, dtype=torch.float32, device=dev),
+                     torch.empty(P, d, dtype=torch.float32, device=dev) if d else None,
+                     torch.empty(P, dtype=torch.float32, device=dev),
+                     torch.empty(P, dtype=torch.int32, device=dev))
+
+    def render_fwd(self, g: Gaussians, out: Image | None = None) -> Image:
+        out = out or self.new_image()
+        gs, im = g.struct(), out.struct()
+        L.check(self.lib.fh_render_fwd(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
+                                       _stream()), "fh_render_fwd")
+        return out
+
+    def new_grads(self) -> dict:
+        n, nb, dev = self.n, (self.sh_degree + 1) ** 2, self.device
+        e = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)
+        return dict(means=e(n, 3), scales=e(n, 3), quats=e(n, 4), opacity=e(n), sh=e(n, nb, 3))
+
+    def render_bwd(self, g: Gaussians, fwd: Image, dC, dF=None, dT=None, target=None, acc: FusionAcc | None = None,
+                   grads: dict | None = None) -> dict:
+        grads = grads or self.new_grads()
+        gs, im = g.struct(), fwd.struct()
+        up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT))
+        gr = L.FhGrads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
+                       _ptr(grads["sh"]))
+        tdt = L.FH_BF16 if (target is not None and target.dtype == torch.bfloat16) else L.FH_F32
+        fu = acc.struct() if acc is not None else None
+        L.check(self.lib.fh_render_bwd(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
+                                       ctypes.byref(up), _ptr(target), tdt,
+                                       ctypes.byref(fu) if fu is not None else None, ctypes.byref(gr), _stream()),
+                "fh_render_bwd")
+        return grads
+
+    def fuse_features(self, g: Gaussians, fwd: Image, target: torch.Tensor, acc: FusionAcc) -> None:
+        gs, im, fu = g.struct(), fwd.struct(), acc.struct()
+        tdt = L.FH_BF16 if target.dtype == torch.bfloat16 else L.FH_F32
+        L.check(self.lib.fh_fuse_features(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
+                                          _ptr(target), tdt, ctypes.byref(fu), _stream()), "fh_fuse_features")
+
+    # -- eager helpers with capacity management ------------------------------
+    def prepare(self, g: Gaussians, margin: float = 1.05) -> L.FhCounters:
+        """project + bin_sort, growing the instance capacity until it fits."""
+        if self.plan.inst_capacity <= 0:
+            self.project(g)
+            self.bin_count()
+            c = self.counters()
+            self._plan(max(int(c.n_instances * margin) + 1024, 1024), self.plan.visit_capacity)
+        while True:
+            self.project(g)
+            self.bin_sort()
+            c = self.counters()
+            if not c.inst_overflow:
+                return c
+            self._plan(int(c.n_instances * margin) + 1024, self.plan.visit_capacity)
+
+    def forward(self, g: Gaussians, margin: float = 1.05) -> Image:
+        """prepare + render_fwd, growing the visit capacity until it fits."""
+        self.prepare(g, margin)
+        while True:
+            img = self.render_fwd(g)
+            c = self.counters()
+            if not c.visit_overflow and self.plan.visit_capacity > 0:
+                return img
+            self._plan(self.plan.inst_capacity, max(int(c.n_visited * margin) + 1024, 1024))
+            self.prepare(g, margin)
+
+
+def fuse_finalize(acc: FusionAcc, feat_in: torch.Tensor | None, out_dtype=torch.float32) -> torch.Tensor:
+    lib = L.load()
+    n, d = acc.sum.shape
+    out = torch.empty(n, d, dtype=out_dtype, device=acc.sum.device)
+    dt = L.FH_BF16 if out_dtype == torch.bfloat16 else L.FH_F32
+    if feat_in is not None and feat_in.dtype != out_dtype:
+        raise L.FhError("feat_in must have the output dtype")
+    fu = acc.struct()
+    L.check(lib.fh_fuse_finalize(ctypes.byref(fu), n, d, _ptr(feat_in), _ptr(out), dt, _stream()), "fh_fuse_finalize")
+    return out

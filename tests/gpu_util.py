@@ -1,0 +1,96 @@
+"""Helpers shared by the GPU parity tests: move a scenegen scene to the device,
+run the HIP path through the C ABI, run the oracle on the same inputs, and
+compare under the tolerance rule.
+
+Tolerance rule (FP32 path vs FP64 oracle), per output x with reference r:
+  * elementwise  |x - r| <= rtol * M + atol, where M is the oracle's magnitude
+    companion (the same sums with every term replaced by its absolute value),
+    checked on pixels/Gaussians whose float decisions are not ambiguous
+    (no alpha within 1e-4 relative of 1/255 or of the 0.99 clamp, no T'
+    within 1e-4 relative of 1e-4 along the pixel's walk);
+  * normwise     ||x - r||_2 <= rtol * ||r||_2 over everything.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import scenegen
+from oracle import pipeline
+
+RTOL = 1e-5
+
+
+def device_gaussians(g: dict, device="cuda"):
+    from paper_2505_19154_amd.raster import Gaussians
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+    feat = None
+    if g["d"] > 0:
+        if g.get("feat_dtype") == "bf16":
+            feat = torch.from_numpy(g["feat_bits"].view(np.int16)).to(device).view(torch.bfloat16)
+        else:
+            feat = t(g["feat"])
+    return Gaussians(t(g["means"]), t(g["scales"]), t(g["quats"]), t(g["opacity"]), t(g["sh"]), feat,
+                     int(g["sh_degree"]))
+
+
+def view_maps(cams, d, with_dT=True, target_dtype="f32"):
+    return [scenegen.make_view_tensors(i, c.npix, d, with_dT=with_dT, target_dtype=target_dtype)
+            for i, c in enumerate(cams)]
+
+
+def concat(vts, key, device="cuda"):
+    if key == "target_bits":
+        a = np.concatenate([v[key] for v in vts]).view(np.int16)
+        return torch.from_numpy(a).to(device).view(torch.bfloat16)
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate([v[key] for v in vts]), np.float32)).to(device)
+
+
+def run_gpu(g: dict, cams, vts=None, fusion=False, form="f32", margin=1.05):
+    from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
+    dg = device_gaussians(g)
+    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=g.get("feat_dtype", "f32"), form=form)
+    img = r.forward(dg, margin)
+    out = dict(r=r, g=dg, img=img)
+    if vts is not None:
+        dC = concat(vts, "dC")
+        dF = concat(vts, "dF") if dg.d else None
+        dT = concat(vts, "dT")
+        acc = None
+        target = None
+        if fusion:
+            acc = FusionAcc.zeros(dg.n, dg.d, "cuda")
+            target = concat(vts, "target_bits") if "target_bits" in vts[0] else concat(vts, "target")
+        grads = r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc)
+        out.update(grads=grads, acc=acc)
+    torch.cuda.synchronize()
+    out["counters"] = r.counters()
+    return out
+
+
+def run_oracle(g: dict, cams, vts=None, fusion=False):
+    return pipeline.run(g, cams, vts, fusion=fusion, want_Fmag=True)
+
+
+def split_views(arr, cams):
+    offs = np.cumsum([0] + [c.npix for c in cams])
+    return [arr[offs[i]:offs[i + 1]] for i in range(len(cams))]
+
+
+def elementwise(got, ref, mag, rtol=RTOL, mask=None, atol=1e-30):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    mag = np.asarray(mag, np.float64)
+    err = np.abs(got - ref)
+    bound = rtol * mag + atol
+    ratio = err / np.maximum(bound, 1e-300)
+    if mask is not None:
+        ratio = ratio[mask]
+    return float(ratio.max()) if ratio.size else 0.0, float(ratio.mean()) if ratio.size else 0.0
+
+
+def normwise(got, ref):
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    nr = np.linalg.norm(ref)
+    return float(np.linalg.norm(got - ref) / nr) if nr > 0 else float(np.linalg.norm(got - ref))

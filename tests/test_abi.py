@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every entry point declared in include/fhgs.h,
+and the ctypes mirror matches the header's struct layout.  CPU only: no compute call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fhgs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fh_[a-z_0-9]+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_path():
+    names = _declared()
+    for need in ("fh_project", "fh_bin_sort", "fh_render_fwd", "fh_render_bwd", "fh_fuse_features",
+                 "fh_fuse_finalize", "fh_plan_init"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2505_19154_amd import _lib
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(_lib.SIGNATURES), "ctypes signature table out of sync with the header"
+    assert lib.fh_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_2505_19154_amd import _lib
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fhgs.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fh_plan), offsetof(fh_plan, cams),
+         offsetof(fh_plan, off), offsetof(fh_plan, ws_bytes), sizeof(fh_camera), sizeof(fh_gaussians),
+         sizeof(fh_counters), offsetof(fh_plan, tiles_x), offsetof(fh_plan, inst_capacity));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", "-I/opt/rocm/include", str(prog), "-o",
+                    str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    P = _lib.FhPlan
+    want = [ctypes.sizeof(P), P.cams.offset, P.off.offset, P.ws_bytes.offset, ctypes.sizeof(_lib.FhCamera),
+            ctypes.sizeof(_lib.FhGaussians), ctypes.sizeof(_lib.FhCounters), P.tiles_x.offset,
+            P.inst_capacity.offset]
+    assert got == want
+
+
+def test_plan_init_validates_on_host():
+    # fh_plan_init touches no device memory
+    from paper_2505_19154_amd import _lib
+    lib = _lib.load()
+    cam = _lib.FhCamera(64, 48, 50.0, 50.0, 32.0, 24.0, (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1),
+                        (ctypes.c_float * 3)(0, 0, 4))
+    cams = (_lib.FhCamera * 1)(cam)
+    plan = _lib.FhPlan()
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 0, cams, 1, 5000, 1000) == 0
+    assert plan.n_tiles == 4 * 3 and plan.n_pixels == 64 * 48 and plan.packed_keys == 1
+    assert plan.ws_bytes > 0
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 4, 16, 0, 0, cams, 1, 0, 0) == -2   # sh degree 4
+    assert lib.fh_plan_init(ctypes.byref(plan), -1, 3, 16, 0, 0, cams, 1, 0, 0) == -1
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 1, cams, 1, 0, 0) == -2   # bf16 form, f32 feat
+    assert lib.fh_status_string(-4) == b"capacity exceeded"
