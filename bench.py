@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = project -> bin_sort -> render_fwd -> render_bwd (+ feature
+fusion) over one batch of synthetic views, all through the C ABI on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--form f32|bf16]
+
+Prints ONE JSON line: Gaussian-pixel blends per second (sum over pixels of the
+list positions each pixel walks, n_iter) with inputs resident in HBM, the
+roofline position of the dominant kernel (timed live with HIP events on its
+own stream), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/view and Gaussian-pixel blends/s, 1080p D=256, BF16 vs FP32"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--form", default="auto", choices=["auto", "f32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="render_bwd",
+                    choices=["project", "bin", "render_fwd", "render_bwd", "reduce", "project_bwd"])
+    return ap.parse_args()
+
+
+def alg_bytes(kernel: str, wl, P: int, n_vis: int, n_inst: int, feat_b: int, tgt_b: int) -> tuple[float, str]:
+    """Algorithmic bytes one launch of `kernel` must move (measurement)."""
+    D = wl.d
+    nsh = 3 * (wl.sh_degree + 1) ** 2
+    if kernel == "render_bwd":
+        per_pix = 24 + 4 * D + (D * tgt_b if wl.fusion else 0)
+        per_g = 48 + D * feat_b + 48 + (4 * D + 4 if wl.fusion else 0)
+        return P * per_pix + n_vis * per_g, f"{per_pix} B/pixel + {per_g} B/visible Gaussian"
+    if kernel == "render_fwd":
+        per_pix = 20 + 4 * D
+        per_g = 48 + D * feat_b
+        return P * per_pix + n_vis * per_g + 8 * n_inst, f"{per_pix} B/pixel + {per_g} B/visible Gaussian + 8 B/instance"
+    if kernel == "bin":
+        return 44 * n_inst + 24 * wl.n, "44 B/instance + 24 B/Gaussian"
+    if kernel in ("project", "project_bwd"):
+        per_g = 44 + 4 * nsh + 64
+        return per_g * wl.n, f"{per_g} B/Gaussian"
+    if kernel == "reduce":
+        per_g = 48 + (8 * D + 8 if wl.fusion else 0) * 2
+        return per_g * n_vis, f"{per_g} B/visible Gaussian"
+    raise ValueError(kernel)
+
+
+def kernel_src_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_19154_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, form: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is
+    for the current kernel sources; else None."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}_{form}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_digest") != kernel_src_digest():
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(g, cams, vts, wl, target_seconds: float):
+    """The FP64 oracle on a random sample of tiles (fwd + bwd + fusion), with the
+    O(N) stages (binning, projection, projection adjoint) run in full."""
+    import numpy as np
+
+    from oracle import binspec, pipeline, project, raster
+
+    cam = cams[0]
+    feat = np.asarray(g["feat"], np.float64)
+    vt = vts[0]
+    dC = np.asarray(vt["dC"], np.float64)
+    dF = np.asarray(vt["dF"], np.float64)
+    dT = np.asarray(vt["dT"], np.float64)
+    tgt = np.asarray(vt["target"], np.float64) if wl.fusion else None
+    t0 = time.perf_counter()
+    bins = binspec.bin_views(g, [cam])
+    t1 = time.perf_counter()
+    pr = project.project(g, cam)
+    t2 = time.perf_counter()
+    ntiles = int(bins["num_tiles"])
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(ntiles)
+    # calibrate on a few tiles, then size the sample to the time target
+    probe = perm[:8]
+    tp0 = time.perf_counter()
+    raster.render_view(cam, pipeline.view_slice(bins, 0, cam), bins["gids"], pr, feat=feat, dC=dC, dF=dF, dT=dT,
+                       target=tgt, tile_sel=probe, want_F=True, want_fusion=wl.fusion)
+    per_tile = max((time.perf_counter() - tp0) / len(probe), 1e-4)
+    k = int(min(ntiles, max(16, target_seconds / per_tile)))
+    sel = perm[:k]
+    t3 = time.perf_counter()
+    out = raster.render_view(cam, pipeline.view_slice(bins, 0, cam), bins["gids"], pr, feat=feat, dC=dC, dF=dF,
+                             dT=dT, target=tgt, tile_sel=sel, want_F=True, want_fusion=wl.fusion)
+    t4 = time.perf_counter()
+    project.project_bwd(pr, pipeline._unpack(out["g2d"]))
+    t5 = time.perf_counter()
+    frac = k / ntiles
+    t_equiv = (t1 - t0) + (t2 - t1) + (t5 - t4) + (t4 - t3) / frac
+    blends = float(out["counts"][0]) / frac
+    return dict(value=blends / t_equiv, unit="Gaussian-pixel blends/s", cores=raster.num_threads(), kind="oracle",
+                sample=(f"{k} of {ntiles} tiles (random, seed 7) composited fwd+bwd{'+fusion' if wl.fusion else ''} "
+                        f"in FP64 ({t4 - t3:.1f} s), scaled by the tile fraction; binning {t1 - t0:.1f} s, "
+                        f"projection {t2 - t1:.1f} s and its adjoint {t5 - t4:.1f} s run on all Gaussians"),
+                ms_per_view=1000.0 * t_equiv)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2505_19154_amd import _lib as L
+    from paper_2505_19154_amd.raster import FusionAcc, Gaussians, Rasterizer
+
+    wl = scenegen.WORKLOADS[args.workload]
+    form = args.form if args.form != "auto" else "f32"
+    print(f"[bench] workload {wl.name}: {wl.description}; form {form}", file=sys.stderr, flush=True)
+
+    g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
+    cams = scenegen.make_cameras(wl.views)
+    tdt = wl.feat_dtype
+    vts = [scenegen.make_view_tensors(i, c.npix, wl.d, with_dT=False, target_dtype=tdt) for i, c in enumerate(cams)]
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    feat = (torch.from_numpy(g["feat_bits"].view(np.int16)).to(dev).view(torch.bfloat16) if wl.feat_dtype == "bf16"
+            else t(g["feat"]))
+    dg = Gaussians(t(g["means"]), t(g["scales"]), t(g["quats"]), t(g["opacity"]), t(g["sh"]), feat, wl.sh_degree)
+    cat = lambda k: np.concatenate([v[k] for v in vts])
+    dC, dF, dT = t(cat("dC")), t(cat("dF")), t(cat("dT"))
+    if wl.fusion:
+        target = (torch.from_numpy(cat("target_bits").view(np.int16)).to(dev).view(torch.bfloat16) if tdt == "bf16"
+                  else t(cat("target")))
+    else:
+        target = None
+    print("[bench] inputs resident on the GPU", file=sys.stderr, flush=True)
+
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form, device=dev)
+    img = r.forward(dg, margin=1.02)
+    c = r.counters()
+    acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
+    grads = r.new_grads()
+
+    def step():
+        r.project(dg)
+        r.bin_sort()
+        r.render_fwd(dg, img)
+        r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    c = r.counters()
+    if c.inst_overflow or c.visit_overflow:
+        raise RuntimeError("capacity overflow during warm-up")
+    print(f"[bench] warm-up done: {c.n_instances} instances, {c.n_visited} visited", file=sys.stderr, flush=True)
+
+    K = args.steps
+    kid = {"project": L.FH_K_PROJECT, "bin": L.FH_K_BIN, "render_fwd": L.FH_K_RENDER_FWD,
+           "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}[args.kernel]
+    ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in ks + ke:
+        e.record()
+    torch.cuda.synchronize()
+    arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
+    arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
+    L.check(r.lib.fh_set_kernel_events(kid, arr_s, arr_e, K), "fh_set_kernel_events")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(K):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    L.check(r.lib.fh_set_kernel_events(kid, None, None, 0), "fh_set_kernel_events")
+    ms = t0.elapsed_time(t1) / K
+    kms = sum(a.elapsed_time(b) for a, b in zip(ks, ke)) / K
+    c = r.counters()
+    if c.inst_overflow or c.visit_overflow:
+        raise RuntimeError("capacity overflow during the timed steps")
+
+    blends = int(img.n_iter.to(torch.int64).sum().item())
+    n_vis = int((r.ws_view("depth_key", torch.int32, wl.n * len(cams)) != -1).sum().item())
+    feat_b = 2 if wl.feat_dtype == "bf16" else 4
+    ab, per_unit = alg_bytes(args.kernel, wl, r.n_pixels, n_vis, int(c.n_instances), feat_b, feat_b)
+    achieved = ab / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(args.kernel, wl.name, form)
+    res = {
+        "metric": METRIC,
+        "value": blends / (ms * 1e-3),
+        "unit": "Gaussian-pixel blends/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if form == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: {wl.description}",
+            "gaussians": wl.n, "views": len(cams), "resolution": f"{cams[0].width}x{cams[0].height}",
+            "d": wl.d, "feat_storage": wl.feat_dtype, "form": form, "fusion": wl.fusion,
+            "instances": int(c.n_instances), "visited_instances": int(c.n_visited), "visible_gaussians": n_vis,
+            "blends": blends, "ms_per_view": ms / len(cams),
+        },
+        "roofline": {
+            "kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel_ms": kms,
+            "algorithmic_bytes": ab, "per_unit": per_unit,
+        },
+    }
+    print(f"[bench] {ms:.3f} ms/step, {args.kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(g, cams, vts, wl, args.cpu_seconds)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -242,6 +242,23 @@ fh_status fh_read_counters(const fh_plan *plan, const void *ws, fh_counters *out
 /* Device pointer and element count of a workspace buffer (no device access). */
 fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **ptr, int64_t *count);
 
+/* Kernels that fh_set_kernel_events can bracket with events. */
+typedef enum {
+    FH_K_PROJECT = 0,       /* the projection kernel of fh_project */
+    FH_K_BIN = 1,           /* all of fh_bin_sort */
+    FH_K_RENDER_FWD = 2,    /* the compositing kernel of fh_render_fwd */
+    FH_K_RENDER_BWD = 3,    /* the adjoint (+ fusion) compositing kernel of fh_render_bwd / fh_fuse_features */
+    FH_K_REDUCE = 4,        /* the per-Gaussian reductions of the per-instance partials */
+    FH_K_PROJECT_BWD = 5    /* the projection adjoint of fh_render_bwd */
+} fh_kernel;
+
+/* Profiling hook for benchmarks: for the next n launches of `which`, record
+ * start[i] before and stop[i] after the i-th launch, on the launch's stream.
+ * start/stop are host arrays of n caller-created HIP events and must stay
+ * valid until those launches are issued; n = 0 switches the hook off.
+ * Process-wide host state, not thread-safe. */
+fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t *start, hipEvent_t *stop, int32_t n);
+
 const char *fh_status_string(fh_status s);
 int32_t fh_version(void);
 

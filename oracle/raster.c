@@ -71,7 +71,8 @@ typedef struct {
     double *fsum_mag;                /* [N, d] or NULL */
     double *wsum;                    /* [N] or NULL */
     double *dfeat;                   /* [N, d] or NULL: dL/df = sum_p w dF */
-    int32_t *gflags;                 /* [N] or NULL: OR of flags of pixels whose walk reached g */
+    int32_t *gflags;                 /* [N] or NULL: bit0 contributes to (or decides) a pixel with a
+                                        near-threshold skip/stop decision, bit1 alpha near the clamp */
     int64_t *counts;                 /* [3]: sum n_iter, contributing blends, alpha evaluations */
 } oracle_args;
 
@@ -88,7 +89,8 @@ static void atomic_add(double *p, double x) {
 
 static int near_rel(double x, double thr, double rel) { return fabs(x - thr) <= rel * thr; }
 
-static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, double *gvec, double *gmag) {
+static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t *amb, double *gvec,
+                    double *gmag) {
     const int64_t ty = tile / a->tiles_x, tx = tile % a->tiles_x;
     const int64_t start = a->ranges[2 * tile], end = a->ranges[2 * tile + 1];
     const int64_t d = a->d;
@@ -102,7 +104,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, double 
             double *Fm = a->out_Fmag ? a->out_Fmag + pix * d : NULL;
             if (F) memset(F, 0, sizeof(double) * d);
             if (Fm) memset(Fm, 0, sizeof(double) * d);
-            int64_t niter = 0, nrec = 0, last_eval = start - 1;
+            int64_t niter = 0, nrec = 0, namb = 0;
             int32_t flags = 0;
             /* ---- forward, front to back ---- */
             for (int64_t pos = start; pos < end; ++pos) {
@@ -112,13 +114,25 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, double 
                 const double G = exp(power);
                 const double raw = a->opac[g] * G;
                 const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
-                last_eval = pos;
                 local_counts[2]++;
-                if (near_rel(raw, ALPHA_MAX, a->ambig_rel)) flags |= 2;
-                if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) flags |= 1;
+                /* a decision this close to its threshold may go either way in FP32:
+                   the clamp only changes g's own gradient (bit 1); the skip and stop
+                   rules change the whole pixel (bit 0) */
+                if (near_rel(raw, ALPHA_MAX, a->ambig_rel) && a->gflags) {
+#pragma omp atomic
+                    a->gflags[g] |= 2;
+                    flags |= 2;
+                }
+                if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) {
+                    flags |= 1;
+                    amb[namb++] = g;
+                }
                 if (alpha < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - alpha);
-                if (near_rel(Tn, T_MIN, a->ambig_rel)) flags |= 1;
+                if (near_rel(Tn, T_MIN, a->ambig_rel)) {
+                    flags |= 1;
+                    amb[namb++] = g;
+                }
                 if (Tn < T_MIN) break;
                 const double w = alpha * T;
                 for (int c = 0; c < 3; ++c) col[c] += w * a->rgb[3 * g + c];
@@ -138,11 +152,17 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, double 
             a->out_T[pix] = T;
             a->out_niter[pix] = niter;
             if (a->out_flags) a->out_flags[pix] = flags;
-            if (flags && a->gflags)
-                for (int64_t pos = start; pos <= last_eval; ++pos) {
+            /* a value-ambiguous pixel perturbs every contributor's adjoint */
+            if ((flags & 1) && a->gflags) {
+                for (int64_t i = 0; i < nrec; ++i) {
 #pragma omp atomic
-                    a->gflags[a->list[pos]] |= flags;
+                    a->gflags[recs[i].g] |= 1;
                 }
+                for (int64_t i = 0; i < namb; ++i) {
+#pragma omp atomic
+                    a->gflags[amb[i]] |= 1;
+                }
+            }
             if (!a->dC) continue;
             /* ---- adjoint, back to front over the contributing blends ---- */
             const double *dC = a->dC + 3 * pix;
@@ -232,15 +252,17 @@ int oracle_raster(const oracle_args *a) {
 #pragma omp parallel
     {
         blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
+        int64_t *amb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * maxlen + 2));
         double gvec[9], gmag[9];
-        if (!recs) {
+        if (!recs || !amb) {
 #pragma omp atomic write
             err = 1;
         } else {
 #pragma omp for schedule(dynamic, 1)
-            for (int64_t i = 0; i < nsel; ++i) do_tile(a, a->tile_sel ? a->tile_sel[i] : i, recs, gvec, gmag);
+            for (int64_t i = 0; i < nsel; ++i) do_tile(a, a->tile_sel ? a->tile_sel[i] : i, recs, amb, gvec, gmag);
         }
         free(recs);
+        free(amb);
     }
     return err;
 }

@@ -18,6 +18,7 @@ FH_TILE = 16
 FH_OK, FH_E_INVALID, FH_E_UNSUPPORTED, FH_E_HIP, FH_E_CAPACITY = 0, -1, -2, -3, -4
 FH_F32, FH_BF16 = 0, 1
 FH_FORM_F32, FH_FORM_BF16 = 0, 1
+(FH_K_PROJECT, FH_K_BIN, FH_K_RENDER_FWD, FH_K_RENDER_BWD, FH_K_REDUCE, FH_K_PROJECT_BWD) = range(6)
 (FH_BUF_RECORDS, FH_BUF_DEPTH_KEY, FH_BUF_RECT, FH_BUF_DEPTH_ORDER, FH_BUF_RANGES,
  FH_BUF_TILE_NITER, FH_BUF_GRAD2D) = range(7)
 
@@ -79,6 +80,7 @@ SIGNATURES = {
     "fh_fuse_finalize": (_i32, [_P(FhFusion), _i64, _i32, _vp, _vp, _i32, _vp]),
     "fh_read_counters": (_i32, [_P(FhPlan), _vp, _P(FhCounters), _vp]),
     "fh_get_buffer": (_i32, [_P(FhPlan), _vp, _i32, _P(_vp), _P(_i64)]),
+    "fh_set_kernel_events": (_i32, [_i32, _vp, _vp, _i32]),
     "fh_status_string": (ctypes.c_char_p, [_i32]),
     "fh_version": (_i32, []),
 }

@@ -58,6 +58,21 @@ static fh_status launch_status() {
     return e == hipSuccess ? FH_OK : FH_E_HIP;
 }
 
+// Benchmark hook (fh_set_kernel_events): events around the next n launches of one kernel.
+static struct {
+    int which = -1;
+    hipEvent_t* start = nullptr;
+    hipEvent_t* stop = nullptr;
+    int n = 0, i = 0;
+} g_prof;
+
+static void prof_begin(int which, hipStream_t s) {
+    if (g_prof.which == which && g_prof.i < g_prof.n) (void)hipEventRecord(g_prof.start[g_prof.i], s);
+}
+static void prof_end(int which, hipStream_t s) {
+    if (g_prof.which == which && g_prof.i < g_prof.n) (void)hipEventRecord(g_prof.stop[g_prof.i++], s);
+}
+
 static bool gaussians_ok(const fh_plan* p, const fh_gaussians* g) {
     if (!g || !g->means || !g->scales || !g->quats || !g->opacity || !g->sh) return false;
     if (g->n != p->n || g->sh_degree != p->sh_degree || g->d != p->d) return false;
@@ -200,7 +215,9 @@ fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStrea
     a.depth_key = buf<uint32_t>(p, ws, WS_DEPTH_KEY);
     a.rect = buf<int4>(p, ws, WS_RECT);
     a.counters = c;
+    prof_begin(FH_K_PROJECT, s);
     launch_project(a, cam_table(*p), view_table(*p), p->n_views, s);
+    prof_end(FH_K_PROJECT, s);
     return launch_status();
 }
 
@@ -213,12 +230,16 @@ fh_status fh_bin_count(const fh_plan* p, void* ws, hipStream_t s) {
 fh_status fh_bin_sort(const fh_plan* p, void* ws, hipStream_t s) {
     if (!p || !ws) return FH_E_INVALID;
     if (p->inst_capacity <= 0) return FH_E_INVALID;
+    prof_begin(FH_K_BIN, s);
     bin_count_impl(p, ws, s);
     const int64_t total = (int64_t)p->n_views * p->n;
     const Counters* c = cbuf<Counters>(p, ws, WS_COUNTERS);
     uint32_t* ranges = buf<uint32_t>(p, ws, WS_RANGES);
     launch_fill_u32(ranges, p->n_tiles * 2, 0u, s);
-    if (total == 0) return launch_status();
+    if (total == 0) {
+        prof_end(FH_K_BIN, s);
+        return launch_status();
+    }
     DupArgs da;
     da.inst_off = cbuf<uint32_t>(p, ws, WS_INST_OFF);
     da.order = cbuf<uint32_t>(p, ws, WS_ORDER);
@@ -241,6 +262,7 @@ fh_status fh_bin_sort(const fh_plan* p, void* ws, hipStream_t s) {
                buf<uint32_t>(p, ws, WS_HIST), buf<uint32_t>(p, ws, WS_SCAN_TMP), s);
     launch_ranges(cbuf<uint32_t>(p, ws, final_keys_buf(p)), c, p->inst_capacity, p->rank_bits, p->packed_keys, ranges,
                   s);
+    prof_end(FH_K_BIN, s);
     return launch_status();
 }
 
@@ -278,7 +300,9 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     uint32_t* tile_niter = buf<uint32_t>(p, ws, WS_TILE_NITER);
     a.tile_niter = tile_niter;
     const ViewTable vt = view_table(*p);
+    prof_begin(FH_K_RENDER_FWD, s);
     launch_render_fwd_f32(a, vt, (int)p->n_tiles, s);
+    prof_end(FH_K_RENDER_FWD, s);
     launch_tile_last(a.ranges, tile_niter, a.keys, a.vals, p->rank_bits, p->packed_keys, (int)p->n_tiles,
                      buf<uint32_t>(p, ws, WS_TILE_LAST), s);
     uint32_t* voff = buf<uint32_t>(p, ws, WS_TILE_VOFF);
@@ -353,10 +377,21 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.target = fusion_target;
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
+    prof_begin(FH_K_RENDER_BWD, s);
     launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, s);
+    prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
+    prof_begin(FH_K_REDUCE, s);
     launch_reduce_geom(r, vt, s);
+    if (fuse) {
+        r.acc_sum = acc->sum;
+        r.acc_comp = acc->comp;
+        r.acc_wsum = acc->wsum;
+        r.acc_wcomp = acc->wcomp;
+        launch_reduce_fuse(r, vt, s);
+    }
+    prof_end(FH_K_REDUCE, s);
     ProjectBwdArgs pb;
     pb.means = g->means;
     pb.scales = g->scales;
@@ -372,14 +407,9 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     pb.g_quats = out->quats;
     pb.g_opacity = out->opacity;
     pb.g_sh = out->sh;
+    prof_begin(FH_K_PROJECT_BWD, s);
     if (p->n > 0) launch_project_bwd(pb, cam_table(*p), p->n_views, s);
-    if (fuse) {
-        r.acc_sum = acc->sum;
-        r.acc_comp = acc->comp;
-        r.acc_wsum = acc->wsum;
-        r.acc_wcomp = acc->wcomp;
-        launch_reduce_fuse(r, vt, s);
-    }
+    prof_end(FH_K_PROJECT_BWD, s);
     return launch_status();
 }
 
@@ -394,15 +424,30 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     a.target = target;
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
+    prof_begin(FH_K_RENDER_BWD, s);
     launch_render_bwd_f32(a, vt, (int)p->n_tiles, true, s);
+    prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
     r.acc_sum = acc->sum;
     r.acc_comp = acc->comp;
     r.acc_wsum = acc->wsum;
     r.acc_wcomp = acc->wcomp;
+    prof_begin(FH_K_REDUCE, s);
     launch_reduce_fuse(r, vt, s);
+    prof_end(FH_K_REDUCE, s);
     return launch_status();
+}
+
+fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t* start, hipEvent_t* stop, int32_t n) {
+    if (n < 0 || (n > 0 && (!start || !stop))) return FH_E_INVALID;
+    if ((int)which < FH_K_PROJECT || (int)which > FH_K_PROJECT_BWD) return FH_E_INVALID;
+    g_prof.which = n > 0 ? (int)which : -1;
+    g_prof.start = start;
+    g_prof.stop = stop;
+    g_prof.n = n;
+    g_prof.i = 0;
+    return FH_OK;
 }
 
 fh_status fh_fuse_finalize(const fh_fusion* acc, int64_t n, int32_t d, const void* feat_in, void* feat_out,

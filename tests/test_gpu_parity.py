@@ -73,7 +73,9 @@ def test_binning_bit_exact(case):
 
 def _pixel_masks(case):
     flags = np.concatenate([v["flags"] for v in case["ora"]["views"]])
-    return flags == 0, flags
+    # bit 0: a skip/stop decision near its threshold (value ambiguous); bit 1
+    # (alpha near the clamp) leaves the pixel's value continuous
+    return (flags & 1) == 0, flags
 
 
 def test_forward_parity(case):
