@@ -167,6 +167,40 @@ def sort_and_ranges(inst: dict) -> dict:
     return dict(keys=skeys, gids=sgids, order=order, ranges=ranges)
 
 
+def tile_counts(bq: dict) -> np.ndarray:
+    """Instances per tile of one view, [tiles_y * tiles_x] row-major, without
+    generating the instances: each binned Gaussian adds 1 over its tile rect
+    (a 2D difference array, then prefix sums along both axes)."""
+    TX, TY = bq["tiles_x"], bq["tiles_y"]
+    diff = np.zeros((TY + 1, TX + 1), np.int64)
+    b = np.nonzero(bq["binned"])[0]
+    x0, x1, y0, y1 = bq["x0"][b], bq["x1"][b], bq["y0"][b], bq["y1"][b]
+    np.add.at(diff, (y0, x0), 1)
+    np.add.at(diff, (y0, x1 + 1), -1)
+    np.add.at(diff, (y1 + 1, x0), -1)
+    np.add.at(diff, (y1 + 1, x1 + 1), 1)
+    return np.cumsum(np.cumsum(diff, 0), 1)[:TY, :TX].reshape(-1)
+
+
+def ranges_from_counts(counts_per_view: list) -> np.ndarray:
+    """[start, end) of every global tile from per-view instance counts, in the
+    order of the sorted key array ((0, 0) for an empty tile)."""
+    cnt = np.concatenate(counts_per_view).astype(np.int64)
+    end = np.cumsum(cnt)
+    start = end - cnt
+    ranges = np.stack([start, end], 1)
+    ranges[cnt == 0] = 0
+    return ranges
+
+
+def tile_list(bq: dict, tx: int, ty: int) -> np.ndarray:
+    """Gaussian indices of one tile's sorted list: every binned Gaussian whose
+    rect holds the tile, ordered by (depth bits, index)."""
+    hit = np.nonzero(bq["binned"] & (bq["x0"] <= tx) & (bq["x1"] >= tx) & (bq["y0"] <= ty) & (bq["y1"] >= ty))[0]
+    dbits = bq["depth"].view(np.uint32)[hit]
+    return hit[np.lexsort((hit, dbits))].astype(np.int64)
+
+
 def bin_views(g: dict, cams: list) -> dict:
     """The whole binning step for a list of cameras."""
     bq = [bin_quantities(g, c) for c in cams]

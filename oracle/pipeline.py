@@ -47,7 +47,9 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
             want_Fmag=want_Fmag, want_fusion=fusion, want_dfeat=want_dfeat)
         counts += out["counts"]
         gflags |= out["gflags"]
-        rec = dict(C=out["C"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
+        # bit 2: the colour clamp of a Gaussian that this view binned is ambiguous
+        gflags |= np.where(pr["clamp_amb"] & bins["per_view"][vi]["binned"], 4, 0).astype(np.int32)
+        rec = dict(C=out["C"], Cmag=out["Cmag"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
                    flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"])
         if vt is not None:
             up = _unpack(out["g2d"])

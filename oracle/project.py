@@ -106,10 +106,15 @@ def project(g: dict, cam) -> dict:
     Y = sh.eval_sh(degree, dirn)
     raw = np.einsum("nb,nbc->nc", Y, shc) + 0.5
     rgb = np.maximum(raw, 0.0)
+    # magnitude companion of the colour sum, and the Gaussians whose clamp
+    # decision (raw > 0) sits within rounding reach of its threshold
+    rgb_mag = np.einsum("nb,nbc->nc", np.abs(Y), np.abs(shc)) + 0.5
+    clamp_amb = (np.abs(raw) <= consts.AMBIG_REL * rgb_mag).any(axis=1)
 
     return dict(p=p, u=u, v=v, depth=pz, qn=qn, qnorm=qnorm, Rq=Rq, M=M, Sigma3=Sigma3,
                 J=J, T=T, a=a, b=b, c=c, det=det, A=A, B=B, C=C, opacity=op,
-                dirn=dirn, dlen=dlen, Y=Y, raw=raw, rgb=rgb, scales=s, Rc=Rc,
+                dirn=dirn, dlen=dlen, Y=Y, raw=raw, rgb=rgb, rgb_mag=rgb_mag, clamp_amb=clamp_amb,
+                scales=s, Rc=Rc,
                 fx=fx, fy=fy, sh=shc, degree=degree)
 
 

@@ -48,6 +48,8 @@ typedef struct {
     /* per-Gaussian projected quantities (FP64) */
     const double *u, *v, *A, *B, *C, *opac;
     const double *rgb;               /* [N, 3] */
+    const double *rgb_mag;           /* [N, 3] or NULL: magnitude companion of rgb (the SH sum's
+                                        terms in absolute value, plus 1/2); NULL: |rgb| */
     const double *feat;              /* [N, d] or NULL */
     /* per-pixel upstream adjoints (NULL: forward only) */
     const double *dC;                /* [P, 3] */
@@ -59,6 +61,7 @@ typedef struct {
     int64_t n_tile_sel;
     /* per-pixel outputs */
     double *out_C;                   /* [P, 3] */
+    double *out_Cmag;                /* [P, 3] or NULL: sum of w rgb_mag */
     double *out_F;                   /* [P, d] or NULL */
     double *out_Fmag;                /* [P, d] or NULL */
     double *out_T;                   /* [P] */
@@ -89,6 +92,11 @@ static void atomic_add(double *p, double x) {
 
 static int near_rel(double x, double thr, double rel) { return fabs(x - thr) <= rel * thr; }
 
+/* magnitude companion of rgb_g[c]: rgb is itself a sum (of SH terms) */
+static double rgbm(const oracle_args *a, int64_t g, int c) {
+    return a->rgb_mag ? a->rgb_mag[3 * g + c] : fabs(a->rgb[3 * g + c]);
+}
+
 static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t *amb, double *gvec,
                     double *gmag) {
     const int64_t ty = tile / a->tiles_x, tx = tile % a->tiles_x;
@@ -99,7 +107,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
         for (int64_t px = tx * a->tile; px < (tx + 1) * a->tile && px < a->width; ++px) {
             const int64_t pix = py * a->width + px;
             const double x = (double)px + 0.5, y = (double)py + 0.5;
-            double T = 1.0, col[3] = {0, 0, 0};
+            double T = 1.0, col[3] = {0, 0, 0}, colm[3] = {0, 0, 0};
             double *F = a->out_F ? a->out_F + pix * d : NULL;
             double *Fm = a->out_Fmag ? a->out_Fmag + pix * d : NULL;
             if (F) memset(F, 0, sizeof(double) * d);
@@ -135,7 +143,10 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                 }
                 if (Tn < T_MIN) break;
                 const double w = alpha * T;
-                for (int c = 0; c < 3; ++c) col[c] += w * a->rgb[3 * g + c];
+                for (int c = 0; c < 3; ++c) {
+                    col[c] += w * a->rgb[3 * g + c];
+                    colm[c] += w * rgbm(a, g, c);
+                }
                 if (F && a->feat)
                     for (int64_t k = 0; k < d; ++k) F[k] += w * a->feat[g * d + k];
                 if (Fm && a->feat)
@@ -149,6 +160,8 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
             }
             local_counts[0] += niter;
             for (int c = 0; c < 3; ++c) a->out_C[3 * pix + c] = col[c];
+            if (a->out_Cmag)
+                for (int c = 0; c < 3; ++c) a->out_Cmag[3 * pix + c] = colm[c];
             a->out_T[pix] = T;
             a->out_niter[pix] = niter;
             if (a->out_flags) a->out_flags[pix] = flags;
@@ -178,7 +191,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                 double gk = 0.0, gkm = 0.0;
                 for (int c = 0; c < 3; ++c) {
                     gk += a->rgb[3 * g + c] * dC[c];
-                    gkm += fabs(a->rgb[3 * g + c] * dC[c]);
+                    gkm += rgbm(a, g, c) * fabs(dC[c]);
                 }
                 if (dF)
                     for (int64_t k = 0; k < d; ++k) {

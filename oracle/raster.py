@@ -40,10 +40,10 @@ class _Args(ctypes.Structure):
         ("d", _I), ("ambig_rel", ctypes.c_double),
         ("ranges", _P), ("list", _P),
         ("u", _P), ("v", _P), ("A", _P), ("B", _P), ("C", _P), ("opac", _P),
-        ("rgb", _P), ("feat", _P),
+        ("rgb", _P), ("rgb_mag", _P), ("feat", _P),
         ("dC", _P), ("dF", _P), ("dT", _P), ("target", _P),
         ("tile_sel", _P), ("n_tile_sel", _I),
-        ("out_C", _P), ("out_F", _P), ("out_Fmag", _P), ("out_T", _P), ("out_niter", _P),
+        ("out_C", _P), ("out_Cmag", _P), ("out_F", _P), ("out_Fmag", _P), ("out_T", _P), ("out_niter", _P),
         ("out_flags", _P),
         ("g2d", _P), ("g2d_mag", _P), ("fsum", _P), ("fsum_mag", _P), ("wsum", _P),
         ("dfeat", _P), ("gflags", _P), ("counts", _P),
@@ -81,7 +81,8 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
 
     ranges [tiles, 2] and glist [M] are this view's slice of the binning (tile
     indices local to the view).  proj holds FP64 per-Gaussian u, v, A, B, C,
-    opacity and rgb [N, 3].  Returns a dict of per-pixel and per-Gaussian arrays.
+    opacity and rgb [N, 3] (and rgb_mag [N, 3], the magnitude companion of rgb,
+    when present).  Returns a dict of per-pixel and per-Gaussian arrays.
     """
     lib = _load()
     W, H = int(cam.width), int(cam.height)
@@ -101,11 +102,12 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     u, v, A, B, C, op = (k(nm, _f64(proj[src])) for nm, src in
                          (("u", "u"), ("v", "v"), ("A", "A"), ("B", "B"), ("C", "C"), ("op", "opacity")))
     rgb = k("rgb", _f64(proj["rgb"]))
+    rgbm = k("rgbm", _f64(proj.get("rgb_mag")))
     featd = k("feat", _f64(feat))
     dCd, dFd, dTd, tg = (k(nm, _f64(x)) for nm, x in (("dC", dC), ("dF", dF), ("dT", dT), ("tg", target)))
     sel = k("sel", None if tile_sel is None else np.ascontiguousarray(tile_sel, np.int64))
 
-    out = dict(C=np.zeros((P, 3)), T=np.zeros(P), niter=np.zeros(P, np.int64),
+    out = dict(C=np.zeros((P, 3)), Cmag=np.zeros((P, 3)), T=np.zeros(P), niter=np.zeros(P, np.int64),
                flags=np.zeros(P, np.int32), counts=np.zeros(3, np.int64))
     out["F"] = np.zeros((P, d)) if (want_F and d) else None
     out["Fmag"] = np.zeros((P, d)) if (want_Fmag and d) else None
@@ -124,10 +126,10 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         ambig_rel=consts.AMBIG_REL,
         ranges=_ptr(ranges), list=_ptr(glist),
         u=_ptr(u), v=_ptr(v), A=_ptr(A), B=_ptr(B), C=_ptr(C), opac=_ptr(op),
-        rgb=_ptr(rgb), feat=_ptr(featd),
+        rgb=_ptr(rgb), rgb_mag=_ptr(rgbm), feat=_ptr(featd),
         dC=_ptr(dCd), dF=_ptr(dFd), dT=_ptr(dTd), target=_ptr(tg),
         tile_sel=_ptr(sel), n_tile_sel=0 if sel is None else sel.size,
-        out_C=_ptr(out["C"]), out_F=_ptr(out["F"]), out_Fmag=_ptr(out["Fmag"]),
+        out_C=_ptr(out["C"]), out_Cmag=_ptr(out["Cmag"]), out_F=_ptr(out["F"]), out_Fmag=_ptr(out["Fmag"]),
         out_T=_ptr(out["T"]), out_niter=_ptr(out["niter"]), out_flags=_ptr(out["flags"]),
         g2d=_ptr(out["g2d"]), g2d_mag=_ptr(out["g2d_mag"]), fsum=_ptr(out["fsum"]),
         fsum_mag=_ptr(out["fsum_mag"]), wsum=_ptr(out["wsum"]), dfeat=_ptr(out["dfeat"]),

@@ -33,6 +33,7 @@ __all__ = [
     "make_gaussians",
     "make_cameras",
     "make_view_tensors",
+    "make_view_tensors_device",
     "look_at_camera",
     "to_bf16_bits",
     "bf16_bits_to_f32",
@@ -191,3 +192,24 @@ def make_view_tensors(view_index: int, npix: int, d: int, with_dT: bool = False,
         out["target_bits"] = bits
         out["target"] = bf16_bits_to_f32(bits)
     return out
+
+
+def make_view_tensors_device(view_index: int, npix: int, d: int, device, with_dT: bool = False,
+                             target_dtype: str = "f32") -> dict:
+    """The per-view maps of make_view_tensors' distributions, drawn on the device
+    with torch's seeded generator (seed 100 + v) for workloads whose maps are too
+    large to draw on the host.  dC, dF, dT, target ~ N(0, 1) in float32; a BF16
+    target is the round-to-nearest-even of the float32 draw.  Consumers that
+    need values on the host copy the rows they use."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(100 + view_index)
+    f32 = torch.float32
+    dC = torch.randn((npix, 3), generator=gen, device=device, dtype=f32)
+    dF = torch.randn((npix, d), generator=gen, device=device, dtype=f32)
+    dT_draw = torch.randn((npix,), generator=gen, device=device, dtype=f32)
+    dT = dT_draw if with_dT else torch.zeros_like(dT_draw)
+    target = torch.randn((npix, d), generator=gen, device=device, dtype=f32)
+    if target_dtype == "bf16":
+        target = target.to(torch.bfloat16)
+    return dict(dC=dC, dF=dF, dT=dT, target=target)

@@ -104,3 +104,21 @@ def test_near_plane_and_nonfinite_culled():
     bq = binspec.bin_quantities(g, cam)
     assert not bq["binned"][0] and not bq["binned"][1] and not bq["binned"][2]
     assert bq["ntiles"][:3].tolist() == [0, 0, 0]
+
+
+def test_per_tile_form_equals_full_binning():
+    # counts by difference array, ranges from counts and one tile's list by a
+    # filter + lexsort reproduce the full duplicate/sort/ranges path on a
+    # two-view scene (the form the large-batch GPU tests sample from)
+    g = _scene(600, 5, 2.0)
+    cams = [scenegen.look_at_camera(p, w, h) for p, w, h in (((0, -4, 0), 96, 64), ((2.5, -3, 1), 80, 72))]
+    bins = binspec.bin_views(g, cams)
+    counts = [binspec.tile_counts(bq) for bq in bins["per_view"]]
+    assert sum(int(c.sum()) for c in counts) == bins["keys"].size
+    assert np.array_equal(binspec.ranges_from_counts(counts), bins["ranges"])
+    for vi, bq in enumerate(bins["per_view"]):
+        off = int(bins["tile_offsets"][vi])
+        for t in range(bq["tiles_x"] * bq["tiles_y"]):
+            lst = binspec.tile_list(bq, t % bq["tiles_x"], t // bq["tiles_x"])
+            s, e = bins["ranges"][off + t]
+            assert np.array_equal(lst, bins["gids"][s:e])

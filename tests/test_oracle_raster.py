@@ -135,3 +135,27 @@ def test_brute_force_equals_tiled():
         tiled_last = np.where(v["niter"] > 0, o["bins"]["gids"][np.maximum(ranges[tile, 0] + v["niter"] - 1, 0)], -1)
         brute_last = np.where(niter.numpy() > 0, order[np.maximum(niter.numpy() - 1, 0)], -1)
         assert np.array_equal(tiled_last, brute_last)
+
+
+def test_colour_magnitude_companion():
+    # rgb_mag bounds |rgb| (so Cmag bounds |C|) and equals rgb when every SH
+    # term is non-negative; the clamp is flagged ambiguous exactly near raw = 0
+    from oracle import project
+    g = scenegen.make_gaussians(400, 1.2, 2, 0, seed=8)
+    cam = scenegen.make_cameras("front64x48")[0]
+    ora = pipeline.run(g, [cam])
+    v = ora["views"][0]
+    assert np.all(v["Cmag"] >= np.abs(v["C"]) * (1 - 1e-15))
+    pr = v["proj"]
+    assert np.all(pr["rgb_mag"] >= np.abs(pr["rgb"]))
+    g0 = scenegen.make_gaussians(300, 1.2, 0, 0, seed=9)
+    g0["sh"] = np.abs(g0["sh"])
+    ora0 = pipeline.run(g0, [cam])
+    assert np.array_equal(ora0["views"][0]["Cmag"], ora0["views"][0]["C"])
+    # a DC coefficient that puts raw exactly at 0 (and one clearly away from it)
+    g1 = scenegen.make_gaussians(2, 1.0, 0, 0, seed=10)
+    y00 = 0.5 / np.sqrt(np.pi)
+    g1["sh"][0, 0, :] = np.float32(-0.5 / y00)
+    g1["sh"][1, 0, :] = np.float32(0.3 / y00)
+    pr1 = project.project(g1, cam)
+    assert pr1["clamp_amb"][0] and not pr1["clamp_amb"][1]
