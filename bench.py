@@ -37,13 +37,21 @@ def parse():
     ap.add_argument("--form", default="auto", choices=["auto", "f32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", type=int, default=1, help="also time the other arithmetic form")
     ap.add_argument("--kernel", default="render_bwd",
                     choices=["project", "bin", "render_fwd", "render_bwd", "reduce", "project_bwd"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB read + 1 GiB write kernel (for scaling HBM counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration run into profiles/traffic_<kernel>_<workload>_<form>.json")
+    ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with --traffic-from")
     return ap.parse_args()
 
 
 def alg_bytes(kernel: str, wl, P: int, n_vis: int, n_inst: int, feat_b: int, tgt_b: int) -> tuple[float, str]:
-    """Algorithmic bytes one launch of `kernel` must move (measurement)."""
+    """Algorithmic bytes one launch of `kernel` must move: each input it needs read
+    once and each output written once, per pixel and per visible Gaussian."""
     D = wl.d
     nsh = 3 * (wl.sh_degree + 1) ** 2
     if kernel == "render_bwd":
@@ -72,6 +80,70 @@ def kernel_src_digest() -> str:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+# the kernels each event bracket of the C ABI launches (base names), for the
+# brackets whose kernels no other bracket launches
+BRACKET_KERNELS = {
+    ("project", "f32"): ("k_project",), ("project", "bf16"): ("k_project",),
+    ("render_fwd", "f32"): ("k_render_fwd_f32",), ("render_fwd", "bf16"): ("k_render_fwd_bf16",),
+    ("render_bwd", "f32"): ("k_render_bwd_f32",), ("render_bwd", "bf16"): ("k_render_bwd_bf16", "k_fuse_bf16"),
+    ("project_bwd", "f32"): ("k_project_bwd",), ("project_bwd", "bf16"): ("k_project_bwd",),
+}
+COPY_BYTES = 1 << 30       # the calibration kernel reads and writes this many bytes
+
+
+def _short_name(kname: str) -> str:
+    n = kname.split("(")[0]
+    n = n.replace("void ", "").strip()
+    return n.split("::")[-1]
+
+
+def _counter_rows(path: str):
+    import csv
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            yield row
+
+
+def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, form: str, command: str):
+    """HBM bytes per launch of the `kernel` bracket from two rocprofv3 --pmc runs,
+    each counter scaled by what it reads for the 1 GiB calibration copy."""
+    if (kernel, form) not in BRACKET_KERNELS:
+        raise SystemExit(f"no counter attribution for the {kernel} bracket")
+    pats = BRACKET_KERNELS[(kernel, form)]
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per_kernel: dict[str, list[float]] = {}
+        calib = []
+        for row in _counter_rows(path):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = _short_name(row["Kernel_Name"])
+            val = float(row["Counter_Value"])
+            if "neg_kernel" in row["Kernel_Name"] or "neg" == name:
+                calib.append(val)
+            elif name.split("<")[0] in pats:
+                per_kernel.setdefault(name, []).append(val)
+        if not calib:
+            raise SystemExit(f"{path}: no calibration copy kernel found")
+        # the largest neg dispatch is the 1 GiB copy
+        kib = max(calib)
+        scale = COPY_BYTES / (kib * 1024.0)
+        launch_kib = sum(sum(v) / len(v) for v in per_kernel.values())
+        out[counter] = dict(calibration_kib=kib, scale=scale, kib_per_launch=launch_kib,
+                            per_kernel={k: sum(v) / len(v) for k, v in per_kernel.items()},
+                            dispatches={k: len(v) for k, v in per_kernel.items()})
+    hbm = sum(out[c]["kib_per_launch"] * 1024.0 * out[c]["scale"] for c in out)
+    res = dict(kernel=kernel, workload=workload, form=form, kernel_src_digest=kernel_src_digest(),
+               hbm_bytes_per_launch=hbm, counters=out, command=command,
+               note="FETCH_SIZE and WRITE_SIZE from separate rocprofv3 --pmc runs, KiB per dispatch averaged over "
+                    "dispatches and summed over the kernels of the bracket; each scaled by calibration bytes / "
+                    "counter bytes of a plain copy (torch.neg) of 1 GiB in, 1 GiB out")
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}_{form}.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(dict(path=path, hbm_bytes_per_launch=hbm)))
 
 
 def measured_traffic(kernel: str, workload: str, form: str):
@@ -135,8 +207,15 @@ def cpu_baseline(g, cams, vts, wl, target_seconds: float):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        import scenegen
+        wl = scenegen.WORKLOADS[args.workload]
+        form = args.form if args.form != "auto" else ("bf16" if wl.feat_dtype == "bf16" else "f32")
+        traffic_from(*args.traffic_from, args.kernel, wl.name, form, args.traffic_command)
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus}: runs over several GPUs are not implemented",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -146,7 +225,8 @@ def main():
     from paper_2505_19154_amd.raster import FusionAcc, Gaussians, Rasterizer
 
     wl = scenegen.WORKLOADS[args.workload]
-    form = args.form if args.form != "auto" else "f32"
+    mfma_ok = wl.feat_dtype == "bf16" and (wl.d in (32, 64, 96) or (wl.d > 0 and wl.d % 128 == 0))
+    form = args.form if args.form != "auto" else ("bf16" if mfma_ok else "f32")
     print(f"[bench] workload {wl.name}: {wl.description}; form {form}", file=sys.stderr, flush=True)
 
     g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
@@ -168,54 +248,75 @@ def main():
     else:
         target = None
     print("[bench] inputs resident on the GPU", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        print(f"[bench] calibration copy of {COPY_BYTES} bytes done", file=sys.stderr, flush=True)
 
-    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form, device=dev)
-    img = r.forward(dg, margin=1.02)
-    c = r.counters()
-    acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
-    grads = r.new_grads()
-
-    def step():
-        r.project(dg)
-        r.bin_sort()
-        r.render_fwd(dg, img)
-        r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    c = r.counters()
-    if c.inst_overflow or c.visit_overflow:
-        raise RuntimeError("capacity overflow during warm-up")
-    print(f"[bench] warm-up done: {c.n_instances} instances, {c.n_visited} visited", file=sys.stderr, flush=True)
-
-    K = args.steps
     kid = {"project": L.FH_K_PROJECT, "bin": L.FH_K_BIN, "render_fwd": L.FH_K_RENDER_FWD,
-           "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}[args.kernel]
-    ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    for e in ks + ke:
-        e.record()
-    torch.cuda.synchronize()
-    arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
-    arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
-    L.check(r.lib.fh_set_kernel_events(kid, arr_s, arr_e, K), "fh_set_kernel_events")
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(K):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    L.check(r.lib.fh_set_kernel_events(kid, None, None, 0), "fh_set_kernel_events")
-    ms = t0.elapsed_time(t1) / K
-    kms = sum(a.elapsed_time(b) for a, b in zip(ks, ke)) / K
-    c = r.counters()
-    if c.inst_overflow or c.visit_overflow:
-        raise RuntimeError("capacity overflow during the timed steps")
+           "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}
 
-    blends = int(img.n_iter.to(torch.int64).sum().item())
+    def run_form(form_name: str, kernel: str):
+        """Warm up, then time K steps of one arithmetic form; the chosen kernel is
+        bracketed by HIP events on its own stream."""
+        r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev)
+        img = r.forward(dg, margin=1.02)
+        acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
+        grads = r.new_grads()
+
+        def step():
+            r.project(dg)
+            r.bin_sort()
+            r.render_fwd(dg, img)
+            r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        c = r.counters()
+        if c.inst_overflow or c.visit_overflow:
+            raise RuntimeError("capacity overflow during warm-up")
+        print(f"[bench] {form_name}: warm-up done, {c.n_instances} instances, {c.n_visited} visited",
+              file=sys.stderr, flush=True)
+        K = args.steps
+        ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for e in ks + ke:
+            e.record()
+        torch.cuda.synchronize()
+        arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
+        arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
+        L.check(r.lib.fh_set_kernel_events(kid[kernel], arr_s, arr_e, K), "fh_set_kernel_events")
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(K):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+        L.check(r.lib.fh_set_kernel_events(kid[kernel], None, None, 0), "fh_set_kernel_events")
+        ms = t0.elapsed_time(t1) / K
+        kms = sum(a.elapsed_time(b) for a, b in zip(ks, ke)) / K
+        c = r.counters()
+        if c.inst_overflow or c.visit_overflow:
+            raise RuntimeError("capacity overflow during the timed steps")
+        blends = int(img.n_iter.to(torch.int64).sum().item())
+        print(f"[bench] {form_name}: {ms:.3f} ms/step, {kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
+        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends)
+
+    other = {"bf16": "f32", "f32": "bf16"}[form]
+    res_other = None
+    if args.compare and (other == "f32" or wl.feat_dtype == "bf16"):
+        res_other = run_form(other, args.kernel)
+        del res_other["r"], res_other["img"]
+        torch.cuda.empty_cache()
+    main_run = run_form(form, args.kernel)
+    r, img, c, ms, kms, blends = (main_run[k] for k in ("r", "img", "c", "ms", "kms", "blends"))
     n_vis = int((r.ws_view("depth_key", torch.int32, wl.n * len(cams)) != -1).sum().item())
     feat_b = 2 if wl.feat_dtype == "bf16" else 4
     ab, per_unit = alg_bytes(args.kernel, wl, r.n_pixels, n_vis, int(c.n_instances), feat_b, feat_b)
@@ -240,6 +341,10 @@ def main():
             "d": wl.d, "feat_storage": wl.feat_dtype, "form": form, "fusion": wl.fusion,
             "instances": int(c.n_instances), "visited_instances": int(c.n_visited), "visible_gaussians": n_vis,
             "blends": blends, "ms_per_view": ms / len(cams),
+            "other_form": None if res_other is None else {
+                "form": other, "ms_per_step": res_other["ms"], "ms_per_view": res_other["ms"] / len(cams),
+                "blends_per_s": res_other["blends"] / (res_other["ms"] * 1e-3),
+                f"{args.kernel}_ms": res_other["kms"]},
         },
         "roofline": {
             "kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -247,7 +352,6 @@ def main():
             "algorithmic_bytes": ab, "per_unit": per_unit,
         },
     }
-    print(f"[bench] {ms:.3f} ms/step, {args.kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(g, cams, vts, wl, args.cpu_seconds)

@@ -132,6 +132,8 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     if (feat_dtype != FH_F32 && feat_dtype != FH_BF16) return FH_E_INVALID;
     if (form != FH_FORM_F32 && form != FH_FORM_BF16) return FH_E_INVALID;
     if (form == FH_FORM_BF16 && feat_dtype != FH_BF16) return FH_E_UNSUPPORTED;
+    // the MFMA form tiles channels by 32 (and by 128 beyond 96)
+    if (form == FH_FORM_BF16 && !(d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0))) return FH_E_UNSUPPORTED;
     if (inst_capacity > 0xFFFFFFFFll || visit_capacity > 0xFFFFFFFFll) return FH_E_UNSUPPORTED;
     if ((int64_t)n * n_views >= ((int64_t)1 << 32)) return FH_E_UNSUPPORTED;
     memset(plan, 0, sizeof(*plan));
@@ -176,17 +178,20 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     sz[WS_INST_OFF] = (size_t)(total + 1) * u4;
     const size_t hist_depth = radix_hist_u32(n_views, n);
     const size_t hist_inst = radix_hist_u32(1, inst_capacity);
-    const size_t hist = std::max(hist_depth, hist_inst);
+    const size_t hist_visit = radix_hist_u32(1, visit_capacity);
+    const size_t hist = std::max(std::max(hist_depth, hist_inst), hist_visit);
     sz[WS_HIST] = hist * u4;
     sz[WS_SCAN_TMP] = scan_scratch_u32(std::max<int64_t>({(int64_t)hist, total + 1, tiles + 1})) * u4;
     sz[WS_RANGES] = (size_t)tiles * 2 * u4;
     sz[WS_TILE_NITER] = (size_t)tiles * u4;
     sz[WS_TILE_VOFF] = (size_t)(tiles + 1) * u4;
-    sz[WS_TILE_LAST] = (size_t)tiles * u4;
     sz[WS_GRAD2D] = (size_t)total * 12 * sizeof(float);
     sz[WS_RANK_OF] = (size_t)total * u4;
     sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
     sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
+    sz[WS_VSEG] = (size_t)total * 2 * u4;
+    sz[WS_LONG] = (size_t)(total + n) * u4;
+    sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
     sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
     sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
     size_t off = 0;
@@ -301,10 +306,11 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.tile_niter = tile_niter;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_FWD, s);
-    launch_render_fwd_f32(a, vt, (int)p->n_tiles, s);
+    if (p->form == FH_FORM_BF16)
+        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, s);
+    else
+        launch_render_fwd_f32(a, vt, (int)p->n_tiles, s);
     prof_end(FH_K_RENDER_FWD, s);
-    launch_tile_last(a.ranges, tile_niter, a.keys, a.vals, p->rank_bits, p->packed_keys, (int)p->n_tiles,
-                     buf<uint32_t>(p, ws, WS_TILE_LAST), s);
     uint32_t* voff = buf<uint32_t>(p, ws, WS_TILE_VOFF);
     device_exclusive_scan(tile_niter, voff, p->n_tiles, buf<uint32_t>(p, ws, WS_SCAN_TMP), 1, s);
     launch_check_visits(voff, (int)p->n_tiles, buf<Counters>(p, ws, WS_COUNTERS), p->visit_capacity, s);
@@ -337,18 +343,42 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
 }
 
+static int visit_sort_passes(const fh_plan* p) { return (p->rank_bits + 7) / 8; }
+
+// The BF16-MFMA backward covers d <= 256; wider features use the FP32-VALU
+// backward with BF16 feature loads.
+static void launch_bwd(const fh_plan* p, const BwdArgs& a, const ViewTable& vt, bool fuse, hipStream_t s) {
+    if (p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d))
+        launch_render_bwd_bf16(a, vt, (int)p->n_tiles, a.dC != nullptr, fuse, s);
+    else
+        launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, s);
+}
+
+// Visited instances sorted stably by rank: each (view, Gaussian) gets a
+// contiguous segment of visit indices in row-major tile order.
+static void visit_sort(const fh_plan* p, void* ws, hipStream_t s) {
+    Counters* c = buf<Counters>(p, ws, WS_COUNTERS);
+    const int64_t total = (int64_t)p->n * p->n_views;
+    uint32_t* vka = buf<uint32_t>(p, ws, WS_VKEY_A);
+    launch_visit_keys(cbuf<uint32_t>(p, ws, WS_RANGES), cbuf<uint32_t>(p, ws, WS_TILE_NITER),
+                      cbuf<uint32_t>(p, ws, WS_TILE_VOFF), cbuf<uint32_t>(p, ws, final_keys_buf(p)),
+                      p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p)), p->rank_bits,
+                      p->packed_keys, c, (int)p->n_tiles, vka, s);
+    radix_sort(vka, nullptr, vka, buf<uint32_t>(p, ws, WS_VVAL_A), buf<uint32_t>(p, ws, WS_VKEY_B),
+               buf<uint32_t>(p, ws, WS_VVAL_B), true, 1, 0, &c->n_visited, p->visit_capacity, 0, p->rank_bits,
+               buf<uint32_t>(p, ws, WS_HIST), buf<uint32_t>(p, ws, WS_SCAN_TMP), s);
+    const bool odd = visit_sort_passes(p) % 2;
+    uint32_t* vseg = buf<uint32_t>(p, ws, WS_VSEG);
+    launch_fill_u32(vseg, total * 2, 0u, s);
+    launch_vseg(cbuf<uint32_t>(p, ws, odd ? WS_VKEY_B : WS_VKEY_A), c, p->visit_capacity, vseg, s);
+}
+
 static void fill_reduce_args(const fh_plan* p, void* ws, ReduceArgs& r) {
     r.order = cbuf<uint32_t>(p, ws, WS_ORDER);
-    r.rect = cbuf<int4>(p, ws, WS_RECT);
-    r.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
-    r.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
-    r.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
-    r.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
-    r.tile_voff = cbuf<uint32_t>(p, ws, WS_TILE_VOFF);
-    r.tile_last = cbuf<uint32_t>(p, ws, WS_TILE_LAST);
-    r.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
-    r.rank_bits = p->rank_bits;
-    r.packed = p->packed_keys;
+    r.vseg = cbuf<uint32_t>(p, ws, WS_VSEG);
+    r.vsorted = cbuf<uint32_t>(p, ws, (visit_sort_passes(p) % 2) ? WS_VVAL_B : WS_VVAL_A);
+    r.counters = buf<Counters>(p, ws, WS_COUNTERS);
+    r.long_list = buf<uint32_t>(p, ws, WS_LONG);
     r.n = p->n;
     r.total = (int64_t)p->n * p->n_views;
     r.part_geom = cbuf<float>(p, ws, WS_PART_GEOM);
@@ -378,18 +408,19 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
-    launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, s);
+    launch_bwd(p, a, vt, fuse, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
     prof_begin(FH_K_REDUCE, s);
-    launch_reduce_geom(r, vt, s);
+    visit_sort(p, ws, s);
+    launch_reduce_geom(r, s);
     if (fuse) {
         r.acc_sum = acc->sum;
         r.acc_comp = acc->comp;
         r.acc_wsum = acc->wsum;
         r.acc_wcomp = acc->wcomp;
-        launch_reduce_fuse(r, vt, s);
+        launch_reduce_fuse(r, s);
     }
     prof_end(FH_K_REDUCE, s);
     ProjectBwdArgs pb;
@@ -425,7 +456,7 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
-    launch_render_bwd_f32(a, vt, (int)p->n_tiles, true, s);
+    launch_bwd(p, a, vt, true, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
@@ -434,7 +465,8 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     r.acc_wsum = acc->wsum;
     r.acc_wcomp = acc->wcomp;
     prof_begin(FH_K_REDUCE, s);
-    launch_reduce_fuse(r, vt, s);
+    visit_sort(p, ws, s);
+    launch_reduce_fuse(r, s);
     prof_end(FH_K_REDUCE, s);
     return launch_status();
 }

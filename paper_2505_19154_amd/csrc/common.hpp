@@ -41,15 +41,20 @@ enum WsBuf {
     WS_RANGES,         // u32 [tiles*2]
     WS_TILE_NITER,     // u32 [tiles]
     WS_TILE_VOFF,      // u32 [tiles+1]
-    WS_TILE_LAST,      // u32 [tiles] rank of the last visited instance
     WS_GRAD2D,         // float [V*N*12]
     WS_RANK_OF,        // u32 [V*N]  depth rank of every (view, Gaussian)
     WS_KEYS_A,         // u32 [cap]
     WS_KEYS_B,         // u32 [cap]
     WS_VALS_A,         // u32 [cap] (unpacked keys only)
     WS_VALS_B,         // u32 [cap]
-    WS_PART_GEOM,      // float4 [visit_cap * 3]
+    WS_VSEG,           // u32 [V*N*2] per-rank [start, end) into the rank-sorted visits
+    WS_PART_GEOM,      // float [visit_cap * 12]
     WS_PART_FUSE,      // float [visit_cap * d]
+    WS_VKEY_A,         // u32 [visit_cap] rank of each visited instance (ping-pong)
+    WS_VKEY_B,
+    WS_VVAL_A,         // u32 [visit_cap] visit index, sorted by rank
+    WS_VVAL_B,
+    WS_LONG,           // u32 [V*N + N] lists of long reduction segments
     WS_COUNT
 };
 
@@ -59,7 +64,9 @@ struct Counters {
     unsigned long long n_culled_nonfinite;
     unsigned int inst_overflow;
     unsigned int visit_overflow;
-    unsigned int pad[8];
+    unsigned int n_long_geom;   // ranks whose visit segment goes to the workgroup-wide reduction
+    unsigned int n_long_fuse;   // Gaussians whose fusion goes to the workgroup-wide reduction
+    unsigned int pad[6];
 };
 
 // Per-view constants passed by value to kernels.

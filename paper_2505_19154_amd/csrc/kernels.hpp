@@ -95,15 +95,10 @@ struct BwdArgs {
 };
 struct ReduceArgs {
     const uint32_t* order;
-    const int4* rect;
-    const uint32_t* keys;
-    const uint32_t* vals;
-    const uint32_t* ranges;
-    const uint32_t* tile_niter;
-    const uint32_t* tile_voff;
-    const uint32_t* tile_last;
-    const Counters* counters;
-    int rank_bits, packed;
+    const uint32_t* vseg;      // [V*N][2] per-rank [start, end) into vsorted
+    const uint32_t* vsorted;   // visit indices sorted by rank (stable: row-major tiles)
+    Counters* counters;
+    uint32_t* long_list;       // [total] ranks, then [n] Gaussians, queued for workgroup-wide sums
     int64_t n, total;
     const float* part_geom;
     float* grad2d;
@@ -114,12 +109,18 @@ struct ReduceArgs {
     float *acc_sum, *acc_comp, *acc_wsum, *acc_wcomp;
 };
 void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
-void launch_tile_last(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* keys, const uint32_t* vals,
-                      int rank_bits, int packed, int n_tiles, uint32_t* tile_last, hipStream_t s);
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
+bool render_bwd_bf16_supported(int d);
+void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,
+                            hipStream_t s);
+void launch_visit_keys(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* tile_voff,
+                       const uint32_t* keys, const uint32_t* vals, int rank_bits, int packed, Counters* c,
+                       int n_tiles, uint32_t* vkey, hipStream_t s);
+void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s);
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
 void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s);
-void launch_reduce_geom(const ReduceArgs& a, const ViewTable& vt, hipStream_t s);
-void launch_reduce_fuse(const ReduceArgs& a, const ViewTable& vt, hipStream_t s);
+void launch_reduce_geom(const ReduceArgs& a, hipStream_t s);
+void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
 void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
                           const void* feat_in, void* feat_out, int bf16, hipStream_t s);

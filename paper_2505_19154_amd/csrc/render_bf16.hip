@@ -1,0 +1,208 @@
+// Compositing with BF16 features on MFMA (gfx950), FP32 accumulation.
+//
+// The feature part of the forward pass is a dense contraction per tile:
+//   F[256 px x D] += W[256 px x K] . Feat[K x D]     (w = alpha T, Section 3.1)
+// computed with v_mfma_f32_16x16x32_bf16.  W is split into two BF16 terms,
+// W = hi + lo (hi = bf16(w), lo = bf16(w - hi)), so the product keeps about 16
+// bits of w; the features are BF16 already.  Everything else (alpha, the
+// transmittance walk, colour) stays on the VALU in FP32.
+//
+// Work mapping: one 1024-thread workgroup per (tile, channel slice); wave w is
+// pixel row w of the 16x16 tile; lane l handles pixel x = l % 16 and Gaussians
+// 8 (l / 16) .. 8 (l / 16) + 7 of each 32-Gaussian chunk.  The lane's eight
+// weights are exactly its MFMA A-operand (rows = pixels, k = Gaussians).  The
+// four lanes of a pixel combine their transmittance with an exclusive product
+// scan, which reproduces the sequential walk (skip rule, stop rule) up to
+// rounding.
+#include "kernels.hpp"
+
+namespace fh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int FK = 32;        // Gaussians per chunk
+constexpr int FKP = 40;       // padded k-stride of the transposed feature tile (80 B rows)
+
+__device__ __forceinline__ uint32_t rank_at(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
+                                            int packed) {
+    return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
+}
+
+template <int DS>
+__global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
+    constexpr int NB = DS / 16;
+    __shared__ Rec srec[FK];
+    __shared__ uint32_t sg[FK];
+    __shared__ __attribute__((aligned(16))) __bf16 sft[DS * FKP];
+    __shared__ uint32_t smax[16];
+    if (a.counters->inst_overflow) return;
+    const int t = blockIdx.x, slice = blockIdx.y, d0 = slice * DS;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int px = tx * TILE + xi, py = ty * TILE + w;
+    const bool inside = px < vt.width[v] && py < vt.height[v];
+    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
+    const uint32_t s = a.ranges[2 * t], e = a.ranges[2 * t + 1];
+    const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
+
+    f32x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    bool done = !inside;
+    uint32_t last = 0;
+
+    for (uint32_t base = s; base < e; base += FK) {
+        const int cnt = (e - base) < (uint32_t)FK ? (int)(e - base) : FK;
+        if (threadIdx.x < FK) {
+            if ((int)threadIdx.x < cnt) {
+                const int64_t i = (int64_t)base + threadIdx.x;
+                const uint32_t g = a.order[rank_at(a.keys, a.vals, i, a.rank_bits, a.packed)];
+                const int64_t ri = ((int64_t)v * a.n + g) * 3;
+                srec[threadIdx.x].r0 = a.rec[ri];
+                srec[threadIdx.x].r1 = a.rec[ri + 1];
+                srec[threadIdx.x].r2 = a.rec[ri + 2];
+                sg[threadIdx.x] = g;
+            } else {
+                // padding: opacity 0 never blends
+                srec[threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                srec[threadIdx.x].r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+                srec[threadIdx.x].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                sg[threadIdx.x] = 0xFFFFFFFFu;
+            }
+        }
+        __syncthreads();
+        // transposed feature tile sft[d][k] for this chunk and channel slice
+        for (int idx = threadIdx.x; idx < FK * (DS / 8); idx += 1024) {
+            const int k = idx % FK, dg = idx / FK;
+            const uint32_t g = sg[k];
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (g != 0xFFFFFFFFu) raw = *reinterpret_cast<const uint4*>(feat + (int64_t)g * a.d + d0 + dg * 8);
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw);
+            uint16_t* dst = reinterpret_cast<uint16_t*>(sft);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + k] = h[m];
+        }
+        __syncthreads();
+
+        // alpha of this lane's eight Gaussians and their transmittance product
+        float al[8];
+        float P = 1.0f;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const AlphaEval ae = eval_alpha(srec[8 * q + m], x, y);
+            al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
+            P *= (1.0f - al[m]);
+        }
+        const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64);
+        const float excl = q == 0 ? 1.0f : (q == 1 ? P0 : (q == 2 ? P0 * P1 : (P0 * P1) * P2));
+        float Tl = T * excl;
+        bool dl = done || Tl < T_MIN;
+        bool term = false;
+        uint32_t mylast = 0;
+        // W (this lane's 8 weights) goes straight into its MFMA A operand as BF16 hi + lo
+        bf16x8 ahi, alo;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            float wv = 0.0f;
+            if (!dl && al[m] > 0.0f) {
+                const float Tn = Tl * (1.0f - al[m]);
+                if (Tn < T_MIN) {
+                    dl = true;
+                    term = true;
+                } else {
+                    wv = al[m] * Tl;
+                    const Rec& r = srec[8 * q + m];
+                    c0 += wv * r.r2.y;
+                    c1 += wv * r.r2.z;
+                    c2 += wv * r.r2.w;
+                    Tl = Tn;
+                    mylast = base - s + 8 * q + m + 1;
+                }
+            }
+            const __bf16 h = (__bf16)wv;
+            ahi[m] = h;
+            alo[m] = (__bf16)(wv - (float)h);
+        }
+        // pixel state after the chunk: the first lane that stopped, else lane 3
+        const uint64_t tb = ballot64(term);
+        const float Tq0 = __shfl(Tl, xi, 64), Tq1 = __shfl(Tl, xi + 16, 64), Tq2 = __shfl(Tl, xi + 32, 64),
+                    Tq3 = __shfl(Tl, xi + 48, 64);
+        const bool t0 = (tb >> xi) & 1, t1 = (tb >> (xi + 16)) & 1, t2 = (tb >> (xi + 32)) & 1,
+                   t3 = (tb >> (xi + 48)) & 1;
+        if (!done) {
+            T = t0 ? Tq0 : (t1 ? Tq1 : (t2 ? Tq2 : Tq3));
+            done = t0 || t1 || t2 || t3;
+        }
+        uint32_t lm = mylast;
+        lm = max(lm, (uint32_t)__shfl_xor((int)lm, 16, 64));
+        lm = max(lm, (uint32_t)__shfl_xor((int)lm, 32, 64));
+        last = max(last, lm);
+
+        // W times the feature chunk
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sft[(j * 16 + xi) * FKP + 8 * q]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, b, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[j], 0, 0, 0);
+        }
+        if (__syncthreads_count(!done) == 0) break;
+    }
+
+    // colour: the four lanes of a pixel hold partial sums
+    c0 += __shfl_xor(c0, 16, 64);
+    c0 += __shfl_xor(c0, 32, 64);
+    c1 += __shfl_xor(c1, 16, 64);
+    c1 += __shfl_xor(c1, 32, 64);
+    c2 += __shfl_xor(c2, 16, 64);
+    c2 += __shfl_xor(c2, 32, 64);
+    const int64_t rowp = vt.pix_off[v] + (int64_t)py * vt.width[v];
+    if (slice == 0 && q == 0 && inside) {
+        const int64_t p = rowp + px;
+        a.C[3 * p] = c0;
+        a.C[3 * p + 1] = c1;
+        a.C[3 * p + 2] = c2;
+        a.T[p] = T;
+        a.n_iter[p] = last;
+    }
+    // F: lane holds F[pixel 4q + r of this row][channel 16 j + xi]
+    if (py < vt.height[v]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pxr = tx * TILE + 4 * q + r;
+            if (pxr < vt.width[v]) {
+                float* fo = a.F + (rowp + pxr) * a.d + d0 + xi;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) fo[16 * j] = acc[j][r];
+            }
+        }
+    }
+    if (slice == 0) {
+        const uint32_t m = wave_max_u32(last);
+        if (lane == 0) smax[w] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t mm = 0;
+            for (int k = 0; k < 16; ++k) mm = smax[k] > mm ? smax[k] : mm;
+            a.tile_niter[t] = mm;
+        }
+    }
+}
+
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
+    switch (a.d) {
+        case 32: hipLaunchKernelGGL(k_render_fwd_bf16<32>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
+        case 64: hipLaunchKernelGGL(k_render_fwd_bf16<64>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
+        case 96: hipLaunchKernelGGL(k_render_fwd_bf16<96>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
+        default:
+            // d is a multiple of 128 (checked by the plan)
+            hipLaunchKernelGGL(k_render_fwd_bf16<128>, dim3(n_tiles, a.d / 128), dim3(1024), 0, s, a, vt);
+            break;
+    }
+}
+
+}  // namespace fh

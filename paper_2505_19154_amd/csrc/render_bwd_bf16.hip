@@ -1,0 +1,420 @@
+// Adjoint and feature fusion of the compositing pass with BF16 features on
+// MFMA (gfx950).
+//
+// Gradient kernel, per tile, back to front over the tile's visited list in
+// chunks of 32 Gaussians (Appendix A.2: dL/dalpha_k = T_k g_k - (S_k + T_final
+// dT)/(1 - alpha_k), S_k = sum_{i>k} w_i g_i, g_k = rgb_k . dC + f_k . dF):
+//   1. the feature part of g for all (pixel, Gaussian) pairs of the chunk is
+//      one MFMA contraction G^T[k x px] = Feat[k x D] . dF^T[D x px]; its result
+//      lands in exactly the lanes that walk those (pixel, Gaussian) pairs;
+//   2. each pixel's four lanes walk four consecutive positions each; the
+//      back-to-front transmittance division and the suffix sum S are combined
+//      across the lanes with a scan of (product of (1 - alpha), sum of w g
+//      relative to the entry transmittance) pairs;
+//   3. w and dL/dpower per (Gaussian, pixel) go to LDS, and a Gaussian-parallel
+//      pass sums the ten screen-space adjoint terms over the tile's pixels
+//      (fixed order) into one partial per instance: no atomics.
+// dF enters the contraction rounded to BF16 (round to nearest even).
+//
+// Fusion kernel: the same back-to-front walk needs only w = alpha T; the
+// per-instance partial sum_p w(p) target(p) is the MFMA contraction
+// W^T[k x px] . Target[px x D] with W split into BF16 hi + lo and the tile's
+// target held in registers for the whole tile.  Kept apart from the gradient
+// kernel so that each keeps its own per-tile operand (dF or the target)
+// resident without spilling.
+#include "kernels.hpp"
+
+namespace fh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 32;   // positions per chunk
+
+__device__ __forceinline__ uint32_t rank_at_b(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
+                                              int packed) {
+    return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
+}
+
+__device__ __forceinline__ float ld_val(const void* p, int bf16, int64_t idx) {
+    return bf16 ? bf16_to_f32(static_cast<const uint16_t*>(p)[idx]) : static_cast<const float*>(p)[idx];
+}
+
+// Stage the chunk's records (threads 0..31); padding records never blend.
+__device__ __forceinline__ void stage_records(const BwdArgs& a, int v, uint32_t s, int cs, int cnt, Rec* srec,
+                                              uint32_t* sg) {
+    if (threadIdx.x < BK) {
+        if ((int)threadIdx.x < cnt) {
+            const int64_t i = (int64_t)s + cs + threadIdx.x;
+            const uint32_t g = a.order[rank_at_b(a.keys, a.vals, i, a.rank_bits, a.packed)];
+            const int64_t ri = ((int64_t)v * a.n + g) * 3;
+            srec[threadIdx.x].r0 = a.rec[ri];
+            srec[threadIdx.x].r1 = a.rec[ri + 1];
+            srec[threadIdx.x].r2 = a.rec[ri + 2];
+            if (sg) sg[threadIdx.x] = g;
+        } else {
+            srec[threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            srec[threadIdx.x].r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+            srec[threadIdx.x].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (sg) sg[threadIdx.x] = 0xFFFFFFFFu;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient kernel.  512 threads (8 waves; 256 VGPRs per lane so that dF stays
+// resident); wave w owns pixel rows 2w and 2w + 1; lane (xi, q) = pixel x = xi
+// of both rows, positions 4q..4q+3 of each 16-position half-chunk.
+template <int D>
+__global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt) {
+    constexpr int DP = D + 8;            // padded row stride (bf16) of the feature chunk
+    constexpr int NS = D / 32;           // MFMA steps over channels
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __bf16* sfeat = reinterpret_cast<__bf16*>(smem);                         // [BK][DP]
+    float* sw = reinterpret_cast<float*>(sfeat + BK * DP);                   // [BK][256] w
+    float* sdp = sw + BK * TILE_PIX;                                         // [BK][256] dL/dpower
+    float* sdc = sdp + BK * TILE_PIX;                                        // [256][3] dC of the tile
+    __shared__ Rec srec[BK];
+    __shared__ uint32_t sg[BK];
+
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int t = blockIdx.x;
+    const uint32_t nt = a.tile_niter[t];
+    if (nt == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int W = vt.width[v], H = vt.height[v];
+    const uint32_t s = a.ranges[2 * t];
+    const uint32_t voff = a.tile_voff[t];
+    const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
+    const bool has_df = a.dF != nullptr;
+    const float LN2 = 0.69314718055994531f;
+    const int px = tx * TILE + xi;
+    const float x = (float)px + 0.5f;
+
+    // per-pixel state of this lane's two pixels (identical in the pixel's four lanes)
+    float T[2], S[2], Tfin[2], dTp[2], dCp[2][3];
+    uint32_t nit[2];
+    bf16x8 dfo[2][NS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int py = ty * TILE + 2 * w + h;
+        const bool inside = px < W && py < H;
+        const int64_t p = vt.pix_off[v] + (int64_t)py * W + px;
+        nit[h] = inside ? a.n_iter[p] : 0u;
+        T[h] = inside ? a.T_final[p] : 1.0f;
+        Tfin[h] = T[h];
+        S[h] = 0.0f;
+        dCp[h][0] = dCp[h][1] = dCp[h][2] = 0.0f;
+        if (inside && a.dC) {
+            dCp[h][0] = a.dC[3 * p];
+            dCp[h][1] = a.dC[3 * p + 1];
+            dCp[h][2] = a.dC[3 * p + 2];
+        }
+        dTp[h] = (inside && a.dT) ? a.dT[p] : 0.0f;
+        if (q == 0) {
+            const int n = (2 * w + h) * TILE + xi;
+            sdc[3 * n] = dCp[h][0];
+            sdc[3 * n + 1] = dCp[h][1];
+            sdc[3 * n + 2] = dCp[h][2];
+        }
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) dfo[h][st][m] = (__bf16)0.0f;
+            if (has_df && inside) {
+                const float4* src = reinterpret_cast<const float4*>(a.dF + p * D + 32 * st + 8 * q);
+                const float4 lo4 = src[0], hi4 = src[1];
+                dfo[h][st][0] = (__bf16)lo4.x; dfo[h][st][1] = (__bf16)lo4.y;
+                dfo[h][st][2] = (__bf16)lo4.z; dfo[h][st][3] = (__bf16)lo4.w;
+                dfo[h][st][4] = (__bf16)hi4.x; dfo[h][st][5] = (__bf16)hi4.y;
+                dfo[h][st][6] = (__bf16)hi4.z; dfo[h][st][7] = (__bf16)hi4.w;
+            }
+        }
+    }
+
+    for (int ce = (int)nt; ce > 0; ce -= BK) {
+        const int cs = ce - BK > 0 ? ce - BK : 0;
+        const int cnt = ce - cs;
+        stage_records(a, v, s, cs, cnt, srec, sg);
+        __syncthreads();
+        if (has_df) {
+            for (int idx = threadIdx.x; idx < BK * (D / 8); idx += 512) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                const uint32_t g = sg[k];
+                uint4 raw = make_uint4(0, 0, 0, 0);
+                if (g != 0xFFFFFFFFu) raw = *reinterpret_cast<const uint4*>(feat + (int64_t)g * D + dg * 8);
+                *reinterpret_cast<uint4*>(&sfeat[k * DP + dg * 8]) = raw;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // keep the two rows' LDS reads apart (no hoisting of the chunk records
+            // across the unrolled rows, which would pin them in registers)
+            asm volatile("" ::: "memory");
+            const float y = (float)(ty * TILE + 2 * w + h) + 0.5f;
+            const int n = (2 * w + h) * TILE + xi;
+            // 1. G^T[k][px] = f_k . dF(px): lane gets k = 16 kb + 4 q + r for its pixel
+            f32x4 gk[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+            if (has_df) {
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                    for (int st = 0; st < NS; ++st) {
+                        const bf16x8 fa =
+                            *reinterpret_cast<const bf16x8*>(&sfeat[(16 * kb + xi) * DP + 32 * st + 8 * q]);
+                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfo[h][st], gk[kb], 0, 0, 0);
+                    }
+            }
+            // 2. back to front: half-chunk kb = 1 (positions 16..31), then kb = 0
+#pragma unroll
+            for (int kb = 1; kb >= 0; --kb) {
+                asm volatile("" ::: "memory");
+                float al[4], gg[4];
+                bool on[4];
+                float P = 1.0f, R = 0.0f, trel = 1.0f;
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const int k = 16 * kb + 4 * q + r;
+                    const Rec& rc = srec[k];
+                    const AlphaEval ae = eval_alpha(rc, x, y);
+                    on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && ae.alpha >= ALPHA_MIN;
+                    al[r] = ae.alpha;
+                    gg[r] = rc.r2.y * dCp[h][0] + rc.r2.z * dCp[h][1] + rc.r2.w * dCp[h][2] + gk[kb][r];
+                    if (on[r]) {
+                        trel = trel / (1.0f - al[r]);
+                        R += al[r] * trel * gg[r];
+                        P *= (1.0f - al[r]);
+                    }
+                }
+                // entry state of every lane, scanning from the back (lane q = 3 first)
+                const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
+                            P3 = __shfl(P, xi + 48, 64);
+                const float R0 = __shfl(R, xi, 64), R1 = __shfl(R, xi + 16, 64), R2 = __shfl(R, xi + 32, 64),
+                            R3 = __shfl(R, xi + 48, 64);
+                const float Te3 = T[h], Se3 = S[h];
+                const float Te2 = Te3 / P3, Se2 = Se3 + Te3 * R3;
+                const float Te1 = Te2 / P2, Se1 = Se2 + Te2 * R2;
+                const float Te0 = Te1 / P1, Se0 = Se1 + Te1 * R1;
+                float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
+                float Sc = q == 3 ? Se3 : (q == 2 ? Se2 : (q == 1 ? Se1 : Se0));
+                T[h] = Te0 / P0;
+                S[h] = Se0 + Te0 * R0;
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const int k = 16 * kb + 4 * q + r;
+                    float wv = 0.0f, dpow = 0.0f;
+                    if (on[r]) {
+                        const float inv = 1.0f / (1.0f - al[r]);
+                        const float Tk = Tc * inv;
+                        wv = al[r] * Tk;
+                        const float dalpha = Tk * gg[r] - (Sc + Tfin[h] * dTp[h]) * inv;
+                        Sc += wv * gg[r];
+                        Tc = Tk;
+                        // alpha < ALPHA_MAX exactly when o G was not clamped
+                        dpow = al[r] < ALPHA_MAX ? dalpha * al[r] : 0.0f;
+                    }
+                    sw[k * TILE_PIX + n] = wv;
+                    sdp[k * TILE_PIX + n] = dpow;
+                }
+            }
+        }
+        __syncthreads();
+
+        // 3. Gaussian-parallel sums over the tile's pixels: thread = (k, 16 pixels)
+        {
+            const int k = threadIdx.x >> 4, pg = threadIdx.x & 15;
+            const Rec rc = srec[k];
+            float qv[10];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) qv[m] = 0.0f;
+            const float ex = rc.r1.x, ey = rc.r1.y;
+            for (int m = 0; m < 16; ++m) {
+                const int n = pg * 16 + m;
+                const float dp = sdp[k * TILE_PIX + n], wv = sw[k * TILE_PIX + n];
+                if (dp != 0.0f || wv != 0.0f) {
+                    const float xx = (float)(tx * TILE + (n & 15)) + 0.5f, yy = (float)(ty * TILE + (n >> 4)) + 0.5f;
+                    const AlphaEval ae = eval_alpha(rc, xx, yy);
+                    const float qa = rc.r1.z * ae.a, qb = rc.r1.w * ae.b;
+                    qv[0] += dp * (-2.0f * LN2 * (qa * ex - qb * ey));
+                    qv[1] += dp * (-2.0f * LN2 * (qa * ey + qb * ex));
+                    qv[2] += dp * (-0.5f * ae.dx * ae.dx);
+                    qv[3] += dp * (-ae.dx * ae.dy);
+                    qv[4] += dp * (-0.5f * ae.dy * ae.dy);
+                    qv[5] += dp;
+                    qv[6] += wv * sdc[3 * n];
+                    qv[7] += wv * sdc[3 * n + 1];
+                    qv[8] += wv * sdc[3 * n + 2];
+                    qv[9] += wv;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 10; ++m) {
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) qv[m] += __shfl_xor(qv[m], off, 64);
+            }
+            if (pg == 0 && k < cnt) {
+                float4* o = reinterpret_cast<float4*>(a.part_geom + ((int64_t)voff + cs + k) * 12);
+                o[0] = make_float4(qv[0], qv[1], qv[2], qv[3]);
+                o[1] = make_float4(qv[4], qv[5], qv[6], qv[7]);
+                o[2] = make_float4(qv[8], qv[9], 0.0f, 0.0f);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fusion kernel.  1024 threads; wave w = pixel row w; lane (xi, q) = pixel
+// x = xi, positions 4q..4q+3 of each half-chunk; wave w < D/16 owns channel
+// block w of the contraction and keeps that block of the tile's target in
+// registers.  Writes the fusion partial row of every visited instance and its
+// weight sum (the tenth geometry partial).
+template <int D>
+__global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
+    constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
+    constexpr int NDB = D / 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __bf16* swh = reinterpret_cast<__bf16*>(smem);                           // [BK][PP] W^T hi
+    __bf16* swl = swh + BK * PP;                                             // [BK][PP] W^T lo
+    float* sw = reinterpret_cast<float*>(swl + BK * PP);                     // [BK][256] w
+    __shared__ Rec srec[BK];
+
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int t = blockIdx.x;
+    const uint32_t nt = a.tile_niter[t];
+    if (nt == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int W = vt.width[v], H = vt.height[v];
+    const uint32_t s = a.ranges[2 * t];
+    const uint32_t voff = a.tile_voff[t];
+    const int px = tx * TILE + xi, py = ty * TILE + w;
+    const bool inside = px < W && py < H;
+    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
+    const int64_t p = vt.pix_off[v] + (int64_t)py * W + px;
+    const uint32_t nit = inside ? a.n_iter[p] : 0u;
+    float T = inside ? a.T_final[p] : 1.0f;
+
+    // target[px = 32 st + 8 q + m][16 w + xi]: B operands of this wave's block
+    bf16x8 tgo[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        const int n0 = 32 * st + 8 * q;   // 8 consecutive pixels of one tile row
+        const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
+        const int64_t base = (vt.pix_off[v] + (int64_t)qy * W + qx0) * D + 16 * w + xi;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            float val = 0.0f;
+            if (w < NDB && qy < H && qx0 + m < W) val = ld_val(a.target, a.target_bf16, base + (int64_t)m * D);
+            tgo[st][m] = (__bf16)val;
+        }
+    }
+
+    for (int ce = (int)nt; ce > 0; ce -= BK) {
+        const int cs = ce - BK > 0 ? ce - BK : 0;
+        const int cnt = ce - cs;
+        stage_records(a, v, s, cs, cnt, srec, nullptr);
+        __syncthreads();
+        const int n = w * TILE + xi;
+#pragma unroll
+        for (int kb = 1; kb >= 0; --kb) {
+            float al[4];
+            bool on[4];
+            float P = 1.0f;
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int k = 16 * kb + 4 * q + r;
+                const AlphaEval ae = eval_alpha(srec[k], x, y);
+                on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
+                al[r] = ae.alpha;
+                if (on[r]) P *= (1.0f - al[r]);
+            }
+            const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
+                        P3 = __shfl(P, xi + 48, 64);
+            const float Te3 = T, Te2 = Te3 / P3, Te1 = Te2 / P2, Te0 = Te1 / P1;
+            float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
+            T = Te0 / P0;
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int k = 16 * kb + 4 * q + r;
+                float wv = 0.0f;
+                if (on[r]) {
+                    const float Tk = Tc / (1.0f - al[r]);
+                    wv = al[r] * Tk;
+                    Tc = Tk;
+                }
+                sw[k * TILE_PIX + n] = wv;
+                const __bf16 hh = (__bf16)wv;
+                swh[k * PP + n] = hh;
+                swl[k * PP + n] = (__bf16)(wv - (float)hh);
+            }
+        }
+        __syncthreads();
+        // weight sums per instance: thread = (k, 8 pixels)
+        {
+            const int k = threadIdx.x >> 5, pg = threadIdx.x & 31;
+            float ws = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) ws += sw[k * TILE_PIX + pg * 8 + m];
+#pragma unroll
+            for (int off = 1; off < 32; off <<= 1) ws += __shfl_xor(ws, off, 64);
+            if (pg == 0 && k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + 9] = ws;
+        }
+        // out[k][d] = sum_px W^T[k][px] target[px][d], W = hi + lo
+        if (w < NDB) {
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < 8; ++st) {
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&swh[(16 * kb + xi) * PP + 32 * st + 8 * q]);
+                    const bf16x8 alo = *reinterpret_cast<const bf16x8*>(&swl[(16 * kb + xi) * PP + 32 * st + 8 * q]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, tgo[st], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, tgo[st], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * kb + 4 * q + r;
+                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * D + 16 * w + xi] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D>
+static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+    if (grads) {
+        const size_t lds = sizeof(__bf16) * (size_t)BK * (D + 8) + sizeof(float) * (2 * (size_t)BK * TILE_PIX + 3 * TILE_PIX);
+        hipLaunchKernelGGL(k_render_bwd_bf16<D>, dim3(n_tiles), dim3(512), lds, s, a, vt);
+    }
+    if (fuse) {
+        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (TILE_PIX + 8) + sizeof(float) * (size_t)BK * TILE_PIX;
+        hipLaunchKernelGGL(k_fuse_bf16<D>, dim3(n_tiles), dim3(1024), lds, s, a, vt);
+    }
+}
+
+bool render_bwd_bf16_supported(int d) { return d == 32 || d == 64 || d == 96 || d == 128 || d == 256; }
+
+// grads: the gradient kernel (needs dC); fuse: the fusion kernel (needs the target)
+void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+    switch (a.d) {
+        case 32: launch_bf16_d<32>(a, vt, n_tiles, grads, fuse, s); break;
+        case 64: launch_bf16_d<64>(a, vt, n_tiles, grads, fuse, s); break;
+        case 96: launch_bf16_d<96>(a, vt, n_tiles, grads, fuse, s); break;
+        case 128: launch_bf16_d<128>(a, vt, n_tiles, grads, fuse, s); break;
+        default: launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s); break;
+    }
+}
+
+}  // namespace fh

@@ -118,16 +118,6 @@ __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable 
 
 // ---------------------------------------------------------------------------
 // Per-tile traversal bookkeeping after the forward pass.
-__global__ __launch_bounds__(256) void k_tile_last(const uint32_t* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ tile_niter,
-                                                   const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                                   int rank_bits, int packed, int n_tiles, uint32_t* tile_last) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint32_t nt = tile_niter[t];
-    tile_last[t] = nt ? inst_rank(keys, vals, (int64_t)ranges[2 * t] + nt - 1, rank_bits, packed) + 1u : 0u;
-}
-
 __global__ void k_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap) {
     if (threadIdx.x == 0) {
         const unsigned long long tot = tile_voff[n_tiles];
@@ -304,105 +294,6 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Deterministic reductions of the per-instance partials.
-
-// Position of rank j in tile t's visited prefix, or -1.
-__device__ __forceinline__ int64_t find_in_tile(const uint32_t* keys, const uint32_t* vals, int rank_bits, int packed,
-                                                uint32_t s, uint32_t nt, uint32_t j) {
-    uint32_t lo = 0, hi = nt;   // first position with rank >= j
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (inst_rank(keys, vals, (int64_t)s + mid, rank_bits, packed) < j) lo = mid + 1; else hi = mid;
-    }
-    if (lo < nt && inst_rank(keys, vals, (int64_t)s + lo, rank_bits, packed) == j) return lo;
-    return -1;
-}
-
-
-// One thread per (view, rank): sum its visited instances in row-major tile order.
-__global__ __launch_bounds__(256) void k_reduce_geom(ReduceArgs a, ViewTable vt) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= a.total) return;
-    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const int v = (int)(j / a.n);
-    const uint32_t g = a.order[j];
-    const int4 r = a.rect[(int64_t)v * a.n + g];
-    float acc[12];
-#pragma unroll
-    for (int m = 0; m < 12; ++m) acc[m] = 0.0f;
-    for (int ty = r.y; ty <= r.w; ++ty)
-        for (int tx = r.x; tx <= r.z; ++tx) {
-            const int t = vt.tile_off[v] + ty * vt.tiles_x[v] + tx;
-            const uint32_t last = a.tile_last[t];
-            if (last == 0 || (uint32_t)j + 1u > last) continue;
-            const int64_t pos = find_in_tile(a.keys, a.vals, a.rank_bits, a.packed, a.ranges[2 * t], a.tile_niter[t],
-                                             (uint32_t)j);
-            if (pos < 0) continue;
-            const float* pg = a.part_geom + ((int64_t)a.tile_voff[t] + pos) * 12;
-#pragma unroll
-            for (int m = 0; m < 10; ++m) acc[m] += pg[m];
-        }
-    float* o = a.grad2d + ((int64_t)v * a.n + g) * 12;
-#pragma unroll
-    for (int m = 0; m < 12; ++m) o[m] = acc[m];
-}
-
-// One wavefront per Gaussian: Neumaier-add its partials of every view into
-// the persistent accumulators (views ascending, tiles row-major).
-__global__ __launch_bounds__(256) void k_reduce_fuse(ReduceArgs a, ViewTable vt) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= a.n) return;
-    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    constexpr int MAXC = 16;   // d <= 1024
-    float sm[MAXC], cp[MAXC];
-    const int D = a.d;
-#pragma unroll
-    for (int m = 0; m < MAXC; ++m) {
-        const int c = lane + 64 * m;
-        sm[m] = c < D ? a.acc_sum[g * D + c] : 0.0f;
-        cp[m] = c < D ? a.acc_comp[g * D + c] : 0.0f;
-    }
-    float ws = a.acc_wsum[g], wc = a.acc_wcomp[g];
-    bool touched = false;
-    for (int v = 0; v < a.n_views; ++v) {
-        const uint32_t rr = a.rank_of[(int64_t)v * a.n + g];
-        const int64_t j = (int64_t)v * a.n + rr;
-        const int4 r = a.rect[(int64_t)v * a.n + g];
-        for (int ty = r.y; ty <= r.w; ++ty)
-            for (int tx = r.x; tx <= r.z; ++tx) {
-                const int t = vt.tile_off[v] + ty * vt.tiles_x[v] + tx;
-                const uint32_t last = a.tile_last[t];
-                if (last == 0 || (uint32_t)j + 1u > last) continue;
-                const int64_t pos = find_in_tile(a.keys, a.vals, a.rank_bits, a.packed, a.ranges[2 * t],
-                                                 a.tile_niter[t], (uint32_t)j);
-                if (pos < 0) continue;
-                const int64_t idx = (int64_t)a.tile_voff[t] + pos;
-                touched = true;
-#pragma unroll
-                for (int m = 0; m < MAXC; ++m) {
-                    const int c = lane + 64 * m;
-                    if (c < D) neumaier_add(sm[m], cp[m], a.part_fuse[idx * D + c]);
-                }
-                neumaier_add(ws, wc, a.part_geom[idx * 12 + 9]);
-            }
-    }
-    if (!touched) return;
-#pragma unroll
-    for (int m = 0; m < MAXC; ++m) {
-        const int c = lane + 64 * m;
-        if (c < D) {
-            a.acc_sum[g * D + c] = sm[m];
-            a.acc_comp[g * D + c] = cp[m];
-        }
-    }
-    if (lane == 0) {
-        a.acc_wsum[g] = ws;
-        a.acc_wcomp[g] = wc;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_rank_of(const uint32_t* __restrict__ order, int64_t n, int64_t total,
                                                  uint32_t* rank_of) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -442,14 +333,11 @@ void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles
     } else if (a.d <= 16) {
         hipLaunchKernelGGL(k_render_fwd_f32<16>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
     } else {
-        hipLaunchKernelGGL(k_render_fwd_f32<32>, dim3(n_tiles, (a.d + 31) / 32), dim3(256), 0, s, a, vt);
+        if (a.d <= 32)
+            hipLaunchKernelGGL(k_render_fwd_f32<32>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
+        else
+            hipLaunchKernelGGL(k_render_fwd_f32<64>, dim3(n_tiles, (a.d + 63) / 64), dim3(256), 0, s, a, vt);
     }
-}
-
-void launch_tile_last(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* keys, const uint32_t* vals,
-                      int rank_bits, int packed, int n_tiles, uint32_t* tile_last, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_last, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, tile_niter, keys, vals,
-                       rank_bits, packed, n_tiles, tile_last);
 }
 
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s) {
@@ -470,14 +358,6 @@ void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, b
         launch_bwd_k<32>(a, vt, n_tiles, fuse, s);
     else
         launch_bwd_k<16>(a, vt, n_tiles, fuse, s);
-}
-
-void launch_reduce_geom(const ReduceArgs& a, const ViewTable& vt, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_geom, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, s, a, vt);
-}
-
-void launch_reduce_fuse(const ReduceArgs& a, const ViewTable& vt, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_fuse, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a, vt);
 }
 
 void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s) {

@@ -304,38 +304,69 @@ __global__ void k_check_capacity(Counters* counters, int64_t cap) {
     if (threadIdx.x == 0) counters->inst_overflow = counters->n_instances > (unsigned long long)cap ? 1u : 0u;
 }
 
-// One wave per 64 consecutive ranks expands their instances in rank order.
+// Instance generation.  Each workgroup writes a fixed range of 4096 output
+// instances (so that the few huge Gaussians at the front of the depth order
+// spread over many workgroups); the ranks covering the range are found by a
+// binary search of the tiles-per-rank scan, staged in LDS when they fit.
+constexpr int DUP_TILE = 4096;
+constexpr int DUP_WIN = 1024;
+
+// largest r in [lo, hi] with off[r] <= i (off non-decreasing, off[lo] <= i)
+__device__ __forceinline__ int64_t last_le(const uint32_t* off, int64_t lo, int64_t hi, uint32_t i) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
-    __shared__ uint32_t offs[4][WAVE + 1];
-    __shared__ int4 rects[4][WAVE];
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    __shared__ uint32_t offs[DUP_WIN + 1];
+    __shared__ int4 rects[DUP_WIN];
+    __shared__ long long s_r0;
+    __shared__ int s_win;
     if (a.counters->inst_overflow) return;   // uniform over the block
-    const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * WAVE;
-    // waves past the last rank keep going to the barrier with an empty range
-    const int64_t j0c = j0 < a.total_ranks ? j0 : a.total_ranks;
-    const int64_t jl = j0 + lane;
-    const int64_t jc = jl < a.total_ranks ? jl : a.total_ranks;
-    offs[w][lane] = a.inst_off[jc];
-    if (lane == 0) {
-        const int64_t je = j0c + WAVE < a.total_ranks ? j0c + WAVE : a.total_ranks;
-        offs[w][WAVE] = a.inst_off[je];
+    const int64_t m = (int64_t)a.counters->n_instances;
+    const int64_t ib = (int64_t)blockIdx.x * DUP_TILE;
+    if (ib >= m) return;                      // uniform over the block
+    const int64_t ie = ib + DUP_TILE < m ? ib + DUP_TILE : m;
+    if (threadIdx.x == 0) {
+        const int64_t r0 = last_le(a.inst_off, 0, a.total_ranks - 1, (uint32_t)ib);
+        const int64_t r1 = last_le(a.inst_off, r0, a.total_ranks - 1, (uint32_t)(ie - 1));
+        s_r0 = r0;
+        s_win = (r1 - r0 + 1 <= DUP_WIN) ? (int)(r1 - r0 + 1) : -1;
     }
-    if (jl < a.total_ranks) rects[w][lane] = a.rect[(jl / a.n) * a.n + a.order[jl]];
     __syncthreads();
-    const uint32_t base = offs[w][0];
-    const uint32_t cnt = j0 < a.total_ranks ? offs[w][WAVE] - base : 0u;
-    for (uint32_t e = lane; e < cnt; e += WAVE) {
-        const uint32_t i = base + e;
-        int lo = 0, hi = WAVE - 1;   // largest r with offs[r] <= i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (offs[w][mid] <= i) lo = mid; else hi = mid - 1;
+    const int64_t r0 = s_r0;
+    const int win = s_win;
+    if (win > 0) {
+        for (int k = threadIdx.x; k <= win; k += 256) offs[k] = a.inst_off[r0 + k];
+        for (int k = threadIdx.x; k < win; k += 256) {
+            const int64_t j = r0 + k;
+            rects[k] = a.rect[(j / a.n) * a.n + a.order[j]];
         }
-        const int64_t j = j0 + lo;
+    }
+    __syncthreads();
+    for (int64_t ii = ib + threadIdx.x; ii < ie; ii += 256) {
+        const uint32_t i = (uint32_t)ii;
+        int64_t j;
+        int4 r;
+        uint32_t local;
+        if (win > 0) {
+            int lo = 0, hi = win - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            j = r0 + lo;
+            r = rects[lo];
+            local = i - offs[lo];
+        } else {
+            j = last_le(a.inst_off, r0, a.total_ranks - 1, i);
+            r = a.rect[(j / a.n) * a.n + a.order[j]];
+            local = i - a.inst_off[j];
+        }
         const int v = (int)(j / a.n);
-        const int4 r = rects[w][lo];
-        const uint32_t local = i - offs[w][lo];
         const uint32_t wdt = (uint32_t)(r.z - r.x + 1);
         const uint32_t tx = (uint32_t)r.x + local % wdt;
         const uint32_t ty = (uint32_t)r.y + local / wdt;
@@ -400,8 +431,8 @@ void launch_check_capacity(Counters* c, int64_t cap, hipStream_t s) {
 }
 
 void launch_duplicate(const DupArgs& a, hipStream_t s) {
-    const int64_t waves = (a.total_ranks + WAVE - 1) / WAVE;
-    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
+    if (a.cap <= 0 || a.total_ranks <= 0) return;
+    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((a.cap + DUP_TILE - 1) / DUP_TILE)), dim3(256), 0, s, a);
 }
 
 void launch_ranges(const uint32_t* keys, const Counters* c, int64_t cap, int rank_bits, int packed, uint32_t* ranges,

@@ -22,8 +22,9 @@ from . import _lib as L
 # indices of workspace sub-buffers (order of the WsBuf enum in csrc/common.hpp)
 _WS = {name: i for i, name in enumerate(
     ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
-     "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "tile_last", "grad2d", "rank_of", "keys_a",
-     "keys_b", "vals_a", "vals_b", "part_geom", "part_fuse"])}
+     "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
+     "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
+     "long"])}
 
 
 def _ptr(t):
@@ -224,6 +225,32 @@ class Rasterizer:
             if not c.inst_overflow:
                 return c
             self._plan(int(c.n_instances * margin) + 1024, self.plan.visit_capacity)
+
+    def capture_step(self, g: Gaussians, img: Image, dC, dF=None, dT=None, target=None,
+                     acc: FusionAcc | None = None, grads: dict | None = None):
+        """Capture project -> bin_sort -> render_fwd -> render_bwd (+ fusion) into
+        a HIP graph on the current capacities (call `forward` or `reserve` first).
+        Returns (graph, grads); graph.replay() re-runs the whole step without host
+        synchronisation or launch overhead.  Overflow is checked afterwards with
+        `counters()`."""
+        grads = grads or self.new_grads()
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            # one eager pass on the capture stream first (allocator and code objects)
+            self.project(g)
+            self.bin_sort()
+            self.render_fwd(g, img)
+            self.render_bwd(g, img, dC, dF, dT, grads=grads)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            self.project(g)
+            self.bin_sort()
+            self.render_fwd(g, img)
+            self.render_bwd(g, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+        return graph, grads
 
     def forward(self, g: Gaussians, margin: float = 1.05) -> Image:
         """prepare + render_fwd, growing the visit capacity until it fits."""

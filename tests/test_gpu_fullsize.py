@@ -1,0 +1,134 @@
+"""GPU vs oracle at the benchmark's full sizes, in the launch configuration
+bench.py times, on outputs the oracle can compute in seconds:
+
+* binning: every key and every tile range, bit for bit (the oracle's float32
+  binning runs on all Gaussians);
+* forward: every pixel of a block of tiles;
+* gradients and fusion: every Gaussian whose tile rect lies inside that block
+  (so the oracle's walk over the block covers all of its contributions).
+"""
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import binspec, pipeline, project, raster
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+# workload, form, tile block (x0, y0, size)
+CASES = [
+    ("c2", "f32", (22, 20, 6)),
+    ("c3", "f32", (56, 30, 5)),
+    ("c3", "bf16", (56, 30, 5)),
+]
+# elementwise bounds (units of the magnitude companion); the BF16 form blends
+# F on MFMA with the weight split into two BF16 terms and rounds dF to BF16
+RT = {"f32": dict(F=1e-5, grad=1e-5, fuse=1e-5), "bf16": dict(F=1e-4, grad=2e-3, fuse=1e-4)}
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[f"{w}-{f}" for w, f, _ in CASES])
+def run(request):
+    wname, form, (bx, by, bs) = request.param
+    wl = scenegen.WORKLOADS[wname]
+    print(f"\n[full {wname} {form}] generating", flush=True)
+    g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
+    cams = scenegen.make_cameras(wl.views)
+    vts = [scenegen.make_view_tensors(0, cams[0].npix, wl.d, with_dT=True,
+                                      target_dtype="bf16" if wl.feat_dtype == "bf16" else "f32")]
+    gpu = U.run_gpu(g, cams, vts, fusion=wl.fusion, form=form, margin=1.02)
+    print(f"[full {wname} {form}] gpu done: {gpu['counters'].n_instances} instances", flush=True)
+    bins = binspec.bin_views(g, cams)
+    cam = cams[0]
+    tiles_x = bins["per_view"][0]["tiles_x"]
+    sel = np.array([(by + j) * tiles_x + (bx + i) for j in range(bs) for i in range(bs)], np.int64)
+    pr = project.project(g, cam)
+    vt = vts[0]
+    out = raster.render_view(cam, pipeline.view_slice(bins, 0, cam), bins["gids"], pr,
+                             feat=np.asarray(g["feat"], np.float64), dC=vt["dC"], dF=vt["dF"], dT=vt["dT"],
+                             target=vt["target"] if wl.fusion else None, tile_sel=sel, want_F=True,
+                             want_Fmag=True, want_fusion=wl.fusion)
+    print(f"[full {wname} {form}] oracle done", flush=True)
+    return dict(wl=wl, form=form, g=g, cams=cams, gpu=gpu, bins=bins, out=out, pr=pr,
+                block=(bx, by, bs), sel=sel)
+
+
+def test_binning_bit_exact_full(run):
+    gpu, bins = run["gpu"], run["bins"]
+    c = gpu["counters"]
+    assert c.n_instances == bins["keys"].size
+    keys, gids = gpu["r"].bin_keys(int(c.n_instances))
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), bins["keys"])
+    assert np.array_equal(gids.cpu().numpy().astype(np.int64), bins["gids"])
+    ranges = gpu["r"].ws_view("ranges", torch.int32, gpu["r"].n_tiles * 2).cpu().numpy().reshape(-1, 2)
+    assert np.array_equal(ranges.astype(np.int64), bins["ranges"])
+
+
+def _block_pixels(run):
+    cam = run["cams"][0]
+    bx, by, bs = run["block"]
+    ys, xs = np.mgrid[by * 16:(by + bs) * 16, bx * 16:(bx + bs) * 16]
+    ok = (xs < cam.width) & (ys < cam.height)
+    return (ys[ok] * cam.width + xs[ok]).astype(np.int64)
+
+
+def test_forward_block(run):
+    gpu, out = run["gpu"], run["out"]
+    pix = _block_pixels(run)
+    img = gpu["img"]
+    flags = out["flags"][pix]
+    ok = (flags & 1) == 0
+    print(f"[full] ambiguous pixels in block {1 - ok.mean():.2e}", flush=True)
+    C, T = img.C.cpu().numpy()[pix], img.T.cpu().numpy()[pix]
+    nit = img.n_iter.cpu().numpy()[pix].astype(np.int64)
+    assert np.array_equal(nit[ok], out["niter"][pix][ok])
+    assert U.elementwise(C, out["C"][pix], out["Cmag"][pix], mask=ok[:, None].repeat(3, 1))[0] <= 1.0
+    assert U.elementwise(T, out["T"][pix], out["T"][pix], mask=ok)[0] <= 1.0
+    F = img.F.cpu().numpy()[pix]
+    rt = RT[run["form"]]["F"]
+    mF, aF = U.elementwise(F, out["F"][pix], out["Fmag"][pix], rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1))
+    err = np.abs(F - out["F"][pix])[ok] / np.maximum(out["Fmag"][pix][ok], 1e-30)
+    print(f"[full] F ratio max/mean {mF:.3f}/{aF:.3f}; |dF|/M max {err.max():.2e} mean {err.mean():.2e}", flush=True)
+    assert mF <= 1.0
+
+
+def _inner_gaussians(run):
+    bq = run["bins"]["per_view"][0]
+    bx, by, bs = run["block"]
+    inner = (bq["binned"] & (bq["x0"] >= bx) & (bq["x1"] < bx + bs) & (bq["y0"] >= by) & (bq["y1"] < by + bs))
+    out = run["out"]
+    touched = np.abs(out["g2d"]).sum(1) > 0
+    return np.nonzero(inner & touched & (out["gflags"] == 0) & ~run["pr"]["clamp_amb"])[0]
+
+
+def test_gradients_of_inner_gaussians(run):
+    gpu, out, pr = run["gpu"], run["out"], run["pr"]
+    idx = _inner_gaussians(run)
+    print(f"[full] {idx.size} Gaussians inside the block", flush=True)
+    assert idx.size >= 20
+    up = pipeline._unpack(out["g2d"])
+    upm = pipeline._unpack(out["g2d_mag"])
+    ref = project.project_bwd(pr, up)
+    mag = project.project_bwd(pr, upm, magnitude=True)
+    rt = RT[run["form"]]["grad"]
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        got = gpu["grads"][k].cpu().numpy()[idx]
+        mx, mean = U.elementwise(got, ref[k][idx], mag[k][idx], rtol=rt)
+        print(f"[full] grad {k}: ratio max/mean {mx:.3f}/{mean:.3f} (rtol {rt:g})", flush=True)
+        assert mx <= 1.0, k
+
+
+def test_fusion_of_inner_gaussians(run):
+    if not run["wl"].fusion:
+        pytest.skip("workload without fusion")
+    gpu, out = run["gpu"], run["out"]
+    idx = _inner_gaussians(run)
+    acc = gpu["acc"]
+    s = (acc.sum + acc.comp).cpu().numpy()[idx]
+    w = (acc.wsum + acc.wcomp).cpu().numpy()[idx]
+    rt = RT[run["form"]]["fuse"]
+    mx, mean = U.elementwise(s, out["fsum"][idx], out["fsum_mag"][idx], rtol=rt)
+    mw, _ = U.elementwise(w, out["wsum"][idx], out["wsum"][idx], rtol=rt)
+    print(f"[full] fusion ratio max/mean {mx:.3f}/{mean:.3f}, wsum {mw:.3f} (rtol {rt:g})", flush=True)
+    assert mx <= 1.0 and mw <= 1.0

@@ -16,16 +16,22 @@ from tests import gpu_util as U
 pytestmark = pytest.mark.gpu
 
 SCENES = {
-    # name: (n, half_extent, sh_degree, d, feat_dtype, cameras)
-    "c1": (1000, 1.0, 0, 16, "f32", "front128"),
-    "sh3_ragged": (3000, 1.5, 3, 32, "f32", "front200x150"),
-    "bf16_feat": (2000, 1.5, 2, 24, "bf16", "front100x70"),
-    "multiview": (1500, 1.2, 1, 8, "f32", "three"),
+    # name: (n, half_extent, sh_degree, d, feat_dtype, cameras, form)
+    "c1": (1000, 1.0, 0, 16, "f32", "front128", "f32"),
+    "sh3_ragged": (3000, 1.5, 3, 32, "f32", "front200x150", "f32"),
+    "bf16_feat": (2000, 1.5, 2, 24, "bf16", "front100x70", "f32"),
+    "multiview": (1500, 1.2, 1, 8, "f32", "three", "f32"),
+    "mfma_d32": (2500, 1.5, 3, 32, "bf16", "front120x90", "bf16"),
+    "mfma_d128_multiview": (1500, 1.2, 1, 128, "bf16", "three", "bf16"),
 }
+# BF16-MFMA form: F is blended from BF16 features with the weight split into
+# two BF16 terms (about 16 significant bits), so its elementwise bound is
+# looser; every other output is computed as in the FP32 form.
+F_RTOL = {"f32": U.RTOL, "bf16": 1e-4}
 
 
 def _scene(name, seed=0):
-    n, h, deg, d, fdt, camr = SCENES[name]
+    n, h, deg, d, fdt, camr, _ = SCENES[name]
     g = scenegen.make_gaussians(n, h, deg, d, seed=seed, feat_dtype=fdt)
     if camr == "three":
         cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in
@@ -40,9 +46,10 @@ def case(request):
     g, cams = _scene(request.param)
     vts = U.view_maps(cams, g["d"], with_dT=True)
     print(f"\n[case {request.param}] n={g['means'].shape[0]} views={len(cams)}", flush=True)
-    gpu = U.run_gpu(g, cams, vts, fusion=g["d"] > 0)
+    form = SCENES[request.param][6]
+    gpu = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=form)
     ora = U.run_oracle(g, cams, vts, fusion=g["d"] > 0)
-    return dict(name=request.param, g=g, cams=cams, vts=vts, gpu=gpu, ora=ora)
+    return dict(name=request.param, g=g, cams=cams, vts=vts, gpu=gpu, ora=ora, form=form)
 
 
 def test_binning_bit_exact(case):
@@ -85,6 +92,7 @@ def test_forward_parity(case):
     T = img.T.cpu().numpy()
     nit = img.n_iter.cpu().numpy().astype(np.int64)
     Cr = np.concatenate([v["C"] for v in ora["views"]])
+    Cm = np.concatenate([v["Cmag"] for v in ora["views"]])
     Tr = np.concatenate([v["T"] for v in ora["views"]])
     nr = np.concatenate([v["niter"] for v in ora["views"]])
     ok, flags = _pixel_masks(case)
@@ -92,7 +100,7 @@ def test_forward_parity(case):
     print(f"[{case['name']}] ambiguous pixels {amb:.2e}", flush=True)
     assert amb < 1e-2
     assert np.array_equal(nit[ok], nr[ok])
-    mC, aC = U.elementwise(C, Cr, Cr, mask=ok[:, None].repeat(3, 1))
+    mC, aC = U.elementwise(C, Cr, Cm, mask=ok[:, None].repeat(3, 1))
     mT, aT = U.elementwise(T, Tr, Tr, mask=ok)
     print(f"[{case['name']}] C max/mean ratio {mC:.3f}/{aC:.3f}  T {mT:.3f}/{aT:.3f}  "
           f"norm C {U.normwise(C, Cr):.2e} T {U.normwise(T, Tr):.2e}", flush=True)
@@ -102,9 +110,12 @@ def test_forward_parity(case):
         F = img.F.cpu().numpy()
         Fr = np.concatenate([v["F"] for v in ora["views"]])
         Fm = np.concatenate([v["Fmag"] for v in ora["views"]])
-        mF, aF = U.elementwise(F, Fr, Fm, mask=ok[:, None].repeat(F.shape[1], 1))
-        print(f"[{case['name']}] F max/mean ratio {mF:.3f}/{aF:.3f} norm {U.normwise(F, Fr):.2e}", flush=True)
-        assert mF <= 1.0 and U.normwise(F, Fr) <= U.RTOL
+        rt = F_RTOL[case["form"]]
+        mF, aF = U.elementwise(F, Fr, Fm, rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1))
+        err = np.abs(F - Fr)[ok] / np.maximum(Fm[ok], 1e-30)
+        print(f"[{case['name']}] F max/mean ratio {mF:.3f}/{aF:.3f} (rtol {rt:g}) norm {U.normwise(F, Fr):.2e} "
+              f"max/mean |dF|/M {err.max():.2e}/{err.mean():.2e}", flush=True)
+        assert mF <= 1.0 and U.normwise(F, Fr) <= rt
 
 
 def test_backward_parity(case):
@@ -141,7 +152,7 @@ def test_fusion_parity(case):
 
 def test_deterministic_rerun(case):
     g, cams, vts = case["g"], case["cams"], case["vts"]
-    again = U.run_gpu(g, cams, vts, fusion=g["d"] > 0)
+    again = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=case["form"])
     a, b = case["gpu"], again
     assert torch.equal(a["img"].C, b["img"].C) and torch.equal(a["img"].T, b["img"].T)
     for k in a["grads"]:
