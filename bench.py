@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--compare", type=int, default=1, help="also time the other arithmetic form")
     ap.add_argument("--kernel", default="render_bwd",
                     choices=["project", "bin", "render_fwd", "render_bwd", "reduce", "project_bwd"])
+    ap.add_argument("--autotune", type=int, default=1, help="pick the launch shape by timing before the steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB read + 1 GiB write kernel (for scaling HBM counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -265,6 +266,7 @@ def main():
         bracketed by HIP events on its own stream."""
         r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev)
         img = r.forward(dg, margin=1.02)
+        tuning = r.autotune(dg, img, dC, dF, dT, target=target, reps=2) if args.autotune else None
         acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
         grads = r.new_grads()
 
@@ -307,7 +309,8 @@ def main():
             raise RuntimeError("capacity overflow during the timed steps")
         blends = int(img.n_iter.to(torch.int64).sum().item())
         print(f"[bench] {form_name}: {ms:.3f} ms/step, {kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
-        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends)
+        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends,
+                    tuning=tuning or {"fwd_slice": int(r.plan.tuning.fwd_slice), "bwd_chunk": int(r.plan.tuning.bwd_chunk)})
 
     other = {"bf16": "f32", "f32": "bf16"}[form]
     res_other = None
@@ -340,11 +343,11 @@ def main():
             "gaussians": wl.n, "views": len(cams), "resolution": f"{cams[0].width}x{cams[0].height}",
             "d": wl.d, "feat_storage": wl.feat_dtype, "form": form, "fusion": wl.fusion,
             "instances": int(c.n_instances), "visited_instances": int(c.n_visited), "visible_gaussians": n_vis,
-            "blends": blends, "ms_per_view": ms / len(cams),
+            "blends": blends, "ms_per_view": ms / len(cams), "tuning": main_run["tuning"],
             "other_form": None if res_other is None else {
                 "form": other, "ms_per_step": res_other["ms"], "ms_per_view": res_other["ms"] / len(cams),
                 "blends_per_s": res_other["blends"] / (res_other["ms"] * 1e-3),
-                f"{args.kernel}_ms": res_other["kms"]},
+                f"{args.kernel}_ms": res_other["kms"], "tuning": res_other["tuning"]},
         },
         "roofline": {
             "kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -96,6 +96,23 @@ typedef struct {
     float t[3];
 } fh_camera;
 
+/* Launch shape of the compositing kernels.  No result depends on it: every
+ * pixel's walk and every instance's partial sums are computed in the same
+ * order for every setting.
+ *   fwd_slice  channels per forward workgroup (the feature dimension is cut
+ *              into ceil(d / fwd_slice) slices, each re-walking the tile).
+ *              FP32 form: 8, 16, 32 or 64.  BF16 form: 32, 64, 96 or 128,
+ *              dividing d.  0 when d == 0.
+ *   bwd_chunk  Gaussians per back-to-front chunk of the FP32-form adjoint:
+ *              16 or 32 (32 needs d <= 512).  The BF16-form adjoint always
+ *              takes 32 (the MFMA k).
+ * fh_plan_init fills defaults; fh_autotune picks the fastest by timing. */
+typedef struct {
+    int32_t fwd_slice;
+    int32_t bwd_chunk;
+    int32_t reserved[2];
+} fh_tuning;
+
 /* Host-side description of one batch of views: sizes, capacities and the
  * workspace layout.  Filled by fh_plan_init; plain data, may be copied. */
 typedef struct {
@@ -111,6 +128,7 @@ typedef struct {
     int64_t pix_off[FH_MAX_VIEWS + 1];
     int64_t tile_off[FH_MAX_VIEWS + 1];
     int32_t tiles_x[FH_MAX_VIEWS], tiles_y[FH_MAX_VIEWS];
+    fh_tuning tuning;                /* launch shape (see fh_tuning) */
     /* workspace layout: byte offsets of the sub-buffers, and the total */
     size_t off[32];
     size_t ws_bytes;
@@ -218,7 +236,9 @@ fh_status fh_render_fwd(const fh_plan *plan, const fh_gaussians *g, void *ws, co
 /* Adjoint of fh_render_fwd (Appendix A.2) chained through the projection.
  * Recomputes transmittance back to front from T and n_iter of `fwd`.
  * If fusion_target (per-pixel [P,d], dtype target_dtype) and acc are given,
- * the same sweep also accumulates feature fusion into acc.
+ * the same sweep also accumulates feature fusion into acc.  In the BF16 form
+ * the target must be BF16 (FH_E_UNSUPPORTED otherwise): it is an MFMA
+ * operand as stored.
  * Gradients are written (not accumulated) into `out`. */
 fh_status fh_render_bwd(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
                         const fh_upstream *up, const void *fusion_target, fh_dtype target_dtype,
@@ -226,7 +246,7 @@ fh_status fh_render_bwd(const fh_plan *plan, const fh_gaussians *g, void *ws, co
 
 /* Feature fusion alone: acc.sum += sum_p w_g(p) target(p), acc.wsum += sum_p
  * w_g(p) for every Gaussian g, Neumaier-compensated; needs fh_render_fwd's
- * T and n_iter for the same views. */
+ * T and n_iter for the same views.  BF16 form: target must be BF16. */
 fh_status fh_fuse_features(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
                            const void *target, fh_dtype target_dtype, const fh_fusion *acc,
                            hipStream_t stream);
@@ -241,6 +261,27 @@ fh_status fh_read_counters(const fh_plan *plan, const void *ws, fh_counters *out
 
 /* Device pointer and element count of a workspace buffer (no device access). */
 fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **ptr, int64_t *count);
+
+/* Valid launch shapes for this plan: writes up to `max` settings into out
+ * (host array) and their number into *count (host).  Each differs from
+ * plan->tuning in the field that the kernel `which` uses (FH_K_RENDER_FWD:
+ * fwd_slice; FH_K_RENDER_BWD: bwd_chunk); for other kernels, or when only one
+ * setting is valid, the one entry is plan->tuning.  Host only. */
+fh_status fh_tuning_candidates(const fh_plan *plan, int32_t which, fh_tuning *out, int32_t max, int32_t *count);
+
+/* Autotuner (the batched form picks its launch shape on the real workload):
+ * times every candidate of fh_tuning_candidates for FH_K_RENDER_FWD, then for
+ * FH_K_RENDER_BWD, `reps` calls each after one warm-up, with HIP events on
+ * `stream`, and writes the fastest into plan->tuning.  Needs the state of a
+ * completed fh_project + fh_bin_sort + fh_render_fwd in ws with no capacity
+ * overflow.  fwd, grads and acc are written as by the calls they time (acc is
+ * accumulated into: pass a scratch accumulator, or NULL to time without
+ * fusion); up, target as for fh_render_bwd (up may be NULL to tune only the
+ * forward).  Synchronises the stream.  Errors: those of the timed calls, and
+ * FH_E_HIP if an event call fails. */
+fh_status fh_autotune(fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
+                      const fh_upstream *up, const void *target, fh_dtype target_dtype, const fh_fusion *acc,
+                      const fh_grads *grads, int32_t reps, hipStream_t stream);
 
 /* Kernels that fh_set_kernel_events can bracket with events. */
 typedef enum {

@@ -36,13 +36,17 @@ class FhCamera(ctypes.Structure):
                 ("R", _f32 * 9), ("t", _f32 * 3)]
 
 
+class FhTuning(ctypes.Structure):
+    _fields_ = [("fwd_slice", _i32), ("bwd_chunk", _i32), ("reserved", _i32 * 2)]
+
+
 class FhPlan(ctypes.Structure):
     _fields_ = [("n", _i64), ("n_views", _i32), ("d", _i32), ("sh_degree", _i32), ("feat_dtype", _i32),
                 ("form", _i32), ("rank_bits", _i32), ("tile_bits", _i32), ("packed_keys", _i32),
                 ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
                 ("cams", FhCamera * FH_MAX_VIEWS), ("pix_off", _i64 * (FH_MAX_VIEWS + 1)),
                 ("tile_off", _i64 * (FH_MAX_VIEWS + 1)), ("tiles_x", _i32 * FH_MAX_VIEWS),
-                ("tiles_y", _i32 * FH_MAX_VIEWS), ("off", _sz * 32), ("ws_bytes", _sz)]
+                ("tiles_y", _i32 * FH_MAX_VIEWS), ("tuning", FhTuning), ("off", _sz * 32), ("ws_bytes", _sz)]
 
 
 class FhImage(ctypes.Structure):
@@ -81,6 +85,9 @@ SIGNATURES = {
     "fh_read_counters": (_i32, [_P(FhPlan), _vp, _P(FhCounters), _vp]),
     "fh_get_buffer": (_i32, [_P(FhPlan), _vp, _i32, _P(_vp), _P(_i64)]),
     "fh_set_kernel_events": (_i32, [_i32, _vp, _vp, _i32]),
+    "fh_tuning_candidates": (_i32, [_P(FhPlan), _i32, _P(FhTuning), _i32, _P(_i32)]),
+    "fh_autotune": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _P(FhUpstream), _vp, _i32, _P(FhFusion),
+                           _P(FhGrads), _i32, _vp]),
     "fh_status_string": (ctypes.c_char_p, [_i32]),
     "fh_version": (_i32, []),
 }

@@ -100,6 +100,53 @@ __global__ void k_reset_all_counters(Counters* c) {
     }
 }
 
+// Average duration of `reps` calls of f (after one warm-up), by HIP events on s.
+template <typename Fn>
+static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FH_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FH_E_HIP;
+    }
+    fh_status st = f();
+    if (st == FH_OK && hipEventRecord(e0, s) != hipSuccess) st = FH_E_HIP;
+    for (int r = 0; r < reps && st == FH_OK; ++r) st = f();
+    if (st == FH_OK && hipEventRecord(e1, s) != hipSuccess) st = FH_E_HIP;
+    if (st == FH_OK && hipEventSynchronize(e1) != hipSuccess) st = FH_E_HIP;
+    if (st == FH_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) st = FH_E_HIP;
+    if (st == FH_OK) *ms /= (float)reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+// Launch shapes (fh_tuning): defaults and validity.
+static fh_tuning default_tuning(int d, int form) {
+    fh_tuning t;
+    memset(&t, 0, sizeof(t));
+    if (d > 0) {
+        if (form == FH_FORM_BF16)
+            t.fwd_slice = (d == 32 || d == 64 || d == 96) ? d : 128;
+        else
+            t.fwd_slice = d <= 8 ? 8 : (d <= 16 ? 16 : (d <= 32 ? 32 : 64));
+    }
+    t.bwd_chunk = d <= 512 ? 32 : 16;
+    return t;
+}
+
+static bool fwd_slice_ok(int d, int form, int slice) {
+    if (d == 0) return slice == 0;
+    if (form == FH_FORM_BF16) return (slice == 32 || slice == 64 || slice == 96 || slice == 128) && d % slice == 0;
+    return slice == 8 || slice == 16 || slice == 32 || slice == 64;
+}
+
+static bool bwd_chunk_ok(int d, int chunk) { return chunk == 16 || (chunk == 32 && d <= 512); }
+
+static bool tuning_ok(const fh_plan* p) {
+    return fwd_slice_ok(p->d, p->form, p->tuning.fwd_slice) && bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
+}
+
 // depth sort, tiles per rank, their scan, the instance count and the overflow flag
 static void bin_count_impl(const fh_plan* p, void* ws, hipStream_t s) {
     const int64_t total = (int64_t)p->n_views * p->n;
@@ -166,6 +213,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     plan->rank_bits = ceil_log2(total > 1 ? total : 2);
     plan->tile_bits = ceil_log2(tiles > 1 ? tiles : 2);
     plan->packed_keys = (plan->rank_bits + plan->tile_bits) <= 32 ? 1 : 0;
+    plan->tuning = default_tuning(d, form);
 
     size_t sz[WS_COUNT];
     memset(sz, 0, sizeof(sz));
@@ -285,6 +333,7 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     if (!p || !ws || !out || !gaussians_ok(p, g)) return FH_E_INVALID;
     if (!out->C || !out->T || !out->n_iter || (p->d > 0 && !out->F)) return FH_E_INVALID;
     if (p->inst_capacity <= 0) return FH_E_INVALID;
+    if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
     RenderArgs a;
     a.rec = cbuf<float4>(p, ws, WS_REC);
     a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
@@ -307,9 +356,9 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_FWD, s);
     if (p->form == FH_FORM_BF16)
-        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, s);
+        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
     else
-        launch_render_fwd_f32(a, vt, (int)p->n_tiles, s);
+        launch_render_fwd_f32(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
     prof_end(FH_K_RENDER_FWD, s);
     uint32_t* voff = buf<uint32_t>(p, ws, WS_TILE_VOFF);
     device_exclusive_scan(tile_niter, voff, p->n_tiles, buf<uint32_t>(p, ws, WS_SCAN_TMP), 1, s);
@@ -351,7 +400,7 @@ static void launch_bwd(const fh_plan* p, const BwdArgs& a, const ViewTable& vt, 
     if (p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d))
         launch_render_bwd_bf16(a, vt, (int)p->n_tiles, a.dC != nullptr, fuse, s);
     else
-        launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, s);
+        launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, p->tuning.bwd_chunk, s);
 }
 
 // Visited instances sorted stably by rank: each (view, Gaussian) gets a
@@ -398,7 +447,10 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh) return FH_E_INVALID;
     const bool fuse = fusion_target != nullptr;
     if (fuse && (!acc || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)) return FH_E_INVALID;
+    // the BF16 form feeds the target to the MFMA as is: it must be BF16
+    if (fuse && p->form == FH_FORM_BF16 && target_dtype != FH_BF16) return FH_E_UNSUPPORTED;
     if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
+    if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
     BwdArgs a;
     fill_bwd_args(p, g, ws, fwd, a);
     a.dC = up->dC;
@@ -449,7 +501,9 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     if (!p || !ws || !fwd || !target || !acc || !gaussians_ok(p, g)) return FH_E_INVALID;
     if (!fwd->T || !fwd->n_iter || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)
         return FH_E_INVALID;
+    if (p->form == FH_FORM_BF16 && target_dtype != FH_BF16) return FH_E_UNSUPPORTED;
     if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
+    if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
     BwdArgs a;
     fill_bwd_args(p, g, ws, fwd, a);
     a.target = target;
@@ -469,6 +523,65 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     launch_reduce_fuse(r, s);
     prof_end(FH_K_REDUCE, s);
     return launch_status();
+}
+
+fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, int32_t max, int32_t* count) {
+    if (!p || !out || !count || max < 1) return FH_E_INVALID;
+    int n = 0;
+    if (which == FH_K_RENDER_FWD && p->d > 0) {
+        static const int slices[] = {8, 16, 32, 64, 96, 128};
+        for (int sl : slices)
+            if (fwd_slice_ok(p->d, p->form, sl) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
+                out[n] = p->tuning;
+                out[n++].fwd_slice = sl;
+            }
+    } else if (which == FH_K_RENDER_BWD && p->form == FH_FORM_F32) {
+        static const int chunks[] = {16, 32};
+        for (int ch : chunks)
+            if (bwd_chunk_ok(p->d, ch) && n < max) {
+                out[n] = p->tuning;
+                out[n++].bwd_chunk = ch;
+            }
+    }
+    if (n == 0) {
+        out[0] = p->tuning;
+        n = 1;
+    }
+    *count = n;
+    return FH_OK;
+}
+
+fh_status fh_autotune(fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const fh_upstream* up,
+                      const void* target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* grads,
+                      int32_t reps, hipStream_t s) {
+    if (!p || !ws || !fwd || reps < 1) return FH_E_INVALID;
+    fh_tuning cand[8];
+    int32_t nc = 0;
+    for (int which : {(int)FH_K_RENDER_FWD, (int)FH_K_RENDER_BWD}) {
+        if (which == FH_K_RENDER_BWD && (!up || !grads)) break;
+        fh_status st = fh_tuning_candidates(p, which, cand, 8, &nc);
+        if (st != FH_OK) return st;
+        if (nc < 2) continue;
+        int best = -1;
+        float best_ms = 0.0f;
+        for (int c = 0; c < nc; ++c) {
+            fh_plan q = *p;
+            q.tuning = cand[c];
+            float ms = 0.0f;
+            if (which == FH_K_RENDER_FWD)
+                st = time_calls([&] { return fh_render_fwd(&q, g, ws, fwd, s); }, reps, s, &ms);
+            else
+                st = time_calls([&] { return fh_render_bwd(&q, g, ws, fwd, up, target, target_dtype, acc, grads, s); },
+                                reps, s, &ms);
+            if (st != FH_OK) return st;
+            if (best < 0 || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+        p->tuning = cand[best];
+    }
+    return FH_OK;
 }
 
 fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t* start, hipEvent_t* stop, int32_t n) {

@@ -108,8 +108,10 @@ struct ReduceArgs {
     int n_views;
     float *acc_sum, *acc_comp, *acc_wsum, *acc_wcomp;
 };
-void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
-void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
+// slice: channels per workgroup (8, 16, 32 or 64)
+void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s);
+// slice: channels per workgroup (32, 64, 96 or 128, dividing d)
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s);
 bool render_bwd_bf16_supported(int d);
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,
                             hipStream_t s);
@@ -118,7 +120,8 @@ void launch_visit_keys(const uint32_t* ranges, const uint32_t* tile_niter, const
                        int n_tiles, uint32_t* vkey, hipStream_t s);
 void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s);
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
-void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s);
+// chunk: Gaussians per back-to-front chunk (16, or 32 when d <= 512)
+void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s);
 void launch_reduce_geom(const ReduceArgs& a, hipStream_t s);
 void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
 void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s);

@@ -193,15 +193,13 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
     }
 }
 
-void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
-    switch (a.d) {
-        case 32: hipLaunchKernelGGL(k_render_fwd_bf16<32>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
-        case 64: hipLaunchKernelGGL(k_render_fwd_bf16<64>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
-        case 96: hipLaunchKernelGGL(k_render_fwd_bf16<96>, dim3(n_tiles, 1), dim3(1024), 0, s, a, vt); break;
-        default:
-            // d is a multiple of 128 (checked by the plan)
-            hipLaunchKernelGGL(k_render_fwd_bf16<128>, dim3(n_tiles, a.d / 128), dim3(1024), 0, s, a, vt);
-            break;
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
+    const unsigned ns = (unsigned)(a.d / slice);   // slice divides d (checked by the caller)
+    switch (slice) {
+        case 32: hipLaunchKernelGGL(k_render_fwd_bf16<32>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
+        case 64: hipLaunchKernelGGL(k_render_fwd_bf16<64>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
+        case 96: hipLaunchKernelGGL(k_render_fwd_bf16<96>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
+        default: hipLaunchKernelGGL(k_render_fwd_bf16<128>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
     }
 }
 

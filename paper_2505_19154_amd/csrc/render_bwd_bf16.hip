@@ -14,7 +14,8 @@
 //   3. w and dL/dpower per (Gaussian, pixel) go to LDS, and a Gaussian-parallel
 //      pass sums the ten screen-space adjoint terms over the tile's pixels
 //      (fixed order) into one partial per instance: no atomics.
-// dF enters the contraction rounded to BF16 (round to nearest even).
+// dF enters the contraction as two BF16 terms, hi = bf16(dF), lo = bf16(dF - hi)
+// (about 16 significant bits), both resident in registers for the whole tile.
 //
 // Fusion kernel: the same back-to-front walk needs only w = alpha T; the
 // per-instance partial sum_p w(p) target(p) is the MFMA contraction
@@ -62,8 +63,8 @@ __device__ __forceinline__ void stage_records(const BwdArgs& a, int v, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Gradient kernel.  512 threads (8 waves; 256 VGPRs per lane so that dF stays
-// resident); wave w owns pixel rows 2w and 2w + 1; lane (xi, q) = pixel x = xi
+// Gradient kernel.  512 threads (8 waves; 256 VGPRs per lane so that dF (hi and
+// lo) stays resident); wave w owns pixel rows 2w and 2w + 1; lane (xi, q) = pixel x = xi
 // of both rows, positions 4q..4q+3 of each 16-position half-chunk.
 template <int D>
 __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt) {
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     // per-pixel state of this lane's two pixels (identical in the pixel's four lanes)
     float T[2], S[2], Tfin[2], dTp[2], dCp[2][3];
     uint32_t nit[2];
-    bf16x8 dfo[2][NS];
+    bf16x8 dfh[2][NS], dfl[2][NS];     // dF = hi + lo, both BF16
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int py = ty * TILE + 2 * w + h;
@@ -123,15 +124,20 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         }
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
+            float vals[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) dfo[h][st][m] = (__bf16)0.0f;
+            for (int m = 0; m < 8; ++m) vals[m] = 0.0f;
             if (has_df && inside) {
                 const float4* src = reinterpret_cast<const float4*>(a.dF + p * D + 32 * st + 8 * q);
                 const float4 lo4 = src[0], hi4 = src[1];
-                dfo[h][st][0] = (__bf16)lo4.x; dfo[h][st][1] = (__bf16)lo4.y;
-                dfo[h][st][2] = (__bf16)lo4.z; dfo[h][st][3] = (__bf16)lo4.w;
-                dfo[h][st][4] = (__bf16)hi4.x; dfo[h][st][5] = (__bf16)hi4.y;
-                dfo[h][st][6] = (__bf16)hi4.z; dfo[h][st][7] = (__bf16)hi4.w;
+                vals[0] = lo4.x; vals[1] = lo4.y; vals[2] = lo4.z; vals[3] = lo4.w;
+                vals[4] = hi4.x; vals[5] = hi4.y; vals[6] = hi4.z; vals[7] = hi4.w;
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const __bf16 hb = (__bf16)vals[m];
+                dfh[h][st][m] = hb;
+                dfl[h][st][m] = (__bf16)(vals[m] - (float)hb);
             }
         }
     }
@@ -168,7 +174,8 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     for (int st = 0; st < NS; ++st) {
                         const bf16x8 fa =
                             *reinterpret_cast<const bf16x8*>(&sfeat[(16 * kb + xi) * DP + 32 * st + 8 * q]);
-                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfo[h][st], gk[kb], 0, 0, 0);
+                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfh[h][st], gk[kb], 0, 0, 0);
+                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfl[h][st], gk[kb], 0, 0, 0);
                     }
             }
             // 2. back to front: half-chunk kb = 1 (positions 16..31), then kb = 0

@@ -277,13 +277,24 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
                 float acc[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) acc[k] = 0.0f;
-                for (int pp = 0; pp < TILE_PIX; ++pp) {
-                    const int qx = tx * TILE + (pp % TILE), qy = ty * TILE + (pp / TILE);
-                    if (qx >= W || qy >= H) continue;
-                    const int64_t qp = vt.pix_off[v] + (int64_t)qy * W + qx;
-                    const float tv = load_feat(a.target, a.target_bf16, qp * D + c);
+                // one tile row (16 pixels) of target values in flight at a time
+                for (int row = 0; row < TILE; ++row) {
+                    const int qy = ty * TILE + row;
+                    float tv[TILE];
 #pragma unroll
-                    for (int k = 0; k < K; ++k) acc[k] += sW[pp * (K + 1) + k] * tv;
+                    for (int m = 0; m < TILE; ++m) {
+                        const int qx = tx * TILE + m;
+                        tv[m] = (qx < W && qy < H)
+                                    ? load_feat(a.target, a.target_bf16,
+                                                (vt.pix_off[v] + (int64_t)qy * W + qx) * D + c)
+                                    : 0.0f;
+                    }
+#pragma unroll
+                    for (int m = 0; m < TILE; ++m) {
+                        const int pp = row * TILE + m;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) acc[k] += sW[pp * (K + 1) + k] * tv[m];
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k)
@@ -325,18 +336,17 @@ __global__ __launch_bounds__(256) void k_fuse_finalize(const float* sum, const f
 }
 
 // ---------------------------------------------------------------------------
-void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
+void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
     if (a.d == 0) {
         hipLaunchKernelGGL(k_render_fwd_f32<0>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
-    } else if (a.d <= 8) {
-        hipLaunchKernelGGL(k_render_fwd_f32<8>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
-    } else if (a.d <= 16) {
-        hipLaunchKernelGGL(k_render_fwd_f32<16>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
-    } else {
-        if (a.d <= 32)
-            hipLaunchKernelGGL(k_render_fwd_f32<32>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
-        else
-            hipLaunchKernelGGL(k_render_fwd_f32<64>, dim3(n_tiles, (a.d + 63) / 64), dim3(256), 0, s, a, vt);
+        return;
+    }
+    const unsigned ns = (unsigned)((a.d + slice - 1) / slice);
+    switch (slice) {
+        case 8: hipLaunchKernelGGL(k_render_fwd_f32<8>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        case 16: hipLaunchKernelGGL(k_render_fwd_f32<16>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        case 32: hipLaunchKernelGGL(k_render_fwd_f32<32>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        default: hipLaunchKernelGGL(k_render_fwd_f32<64>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
     }
 }
 
@@ -353,8 +363,8 @@ static void launch_bwd_k(const BwdArgs& a, const ViewTable& vt, int n_tiles, boo
         hipLaunchKernelGGL((k_render_bwd_f32<K, false>), dim3(n_tiles), dim3(256), dyn, s, a, vt);
 }
 
-void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s) {
-    if (a.d <= 512)
+void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s) {
+    if (chunk == 32 && a.d <= 512)
         launch_bwd_k<32>(a, vt, n_tiles, fuse, s);
     else
         launch_bwd_k<16>(a, vt, n_tiles, fuse, s);

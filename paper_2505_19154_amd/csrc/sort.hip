@@ -304,12 +304,16 @@ __global__ void k_check_capacity(Counters* counters, int64_t cap) {
     if (threadIdx.x == 0) counters->inst_overflow = counters->n_instances > (unsigned long long)cap ? 1u : 0u;
 }
 
-// Instance generation.  Each workgroup writes a fixed range of 4096 output
+// Instance generation.  Each workgroup writes a fixed range of 2048 output
 // instances (so that the few huge Gaussians at the front of the depth order
 // spread over many workgroups); the ranks covering the range are found by a
-// binary search of the tiles-per-rank scan, staged in LDS when they fit.
-constexpr int DUP_TILE = 4096;
-constexpr int DUP_WIN = 1024;
+// binary search of the tiles-per-rank scan staged in LDS.  Every binned rank
+// owns at least one instance, so within one view a range spans at most 2048
+// ranks and the LDS window always holds them; only a range that crosses a
+// view boundary with culled (zero-instance) ranks can need more, and then
+// searches the scan in global memory.
+constexpr int DUP_TILE = 2048;
+constexpr int DUP_WIN = 2048;
 
 // largest r in [lo, hi] with off[r] <= i (off non-decreasing, off[lo] <= i)
 __device__ __forceinline__ int64_t last_le(const uint32_t* off, int64_t lo, int64_t hi, uint32_t i) {

@@ -118,6 +118,7 @@ class Rasterizer:
         self.device = torch.device(device)
         self.plan = None
         self.ws = None
+        self.tuning = None          # launch shape chosen by autotune (kept across re-plans)
         self._plan(inst_capacity, visit_capacity)
 
     # -- plan and workspace -------------------------------------------------
@@ -125,6 +126,8 @@ class Rasterizer:
         plan = L.FhPlan()
         L.check(self.lib.fh_plan_init(ctypes.byref(plan), self.n, self.sh_degree, self.d, self.feat_dtype, self.form,
                                       self.cam_arr, len(self.cams), int(inst_cap), int(visit_cap)), "fh_plan_init")
+        if self.tuning is not None:
+            plan.tuning = self.tuning
         self.plan = plan
         self.ws = torch.empty(max(int(plan.ws_bytes), 256), dtype=torch.uint8, device=self.device)
 
@@ -251,6 +254,66 @@ class Rasterizer:
             self.render_fwd(g, img)
             self.render_bwd(g, img, dC, dF, dT, target=target, acc=acc, grads=grads)
         return graph, grads
+
+    def tuning_key(self) -> str:
+        """Autotune cache key: device arch, arithmetic form, feature width and
+        dtype, view count, and power-of-two classes of pixels and Gaussians."""
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        return (f"{arch}|form{self.form}|d{self.d}|feat{self.feat_dtype}|views{len(self.cams)}|"
+                f"px2^{max(self.n_pixels, 1).bit_length()}|n2^{max(self.n, 1).bit_length()}")
+
+    def autotune(self, g: Gaussians, img: Image, dC=None, dF=None, dT=None, target=None, reps: int = 3,
+                 cache: str | None = None) -> dict:
+        """Choose the launch shape (fh_tuning) for this workload: from `cache`
+        (a JSON file) when it holds this tuning_key, else by timing every
+        candidate with fh_autotune (after `forward`, with the step's real
+        inputs; outputs are recomputed, fusion goes to a scratch accumulator).
+        Returns the chosen {"fwd_slice", "bwd_chunk"}."""
+        import json
+        import os
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]))
+        else:
+            gs, im = g.struct(), img.struct()
+            up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT)) if dC is not None else None
+            grads = self.new_grads() if dC is not None else None
+            gr = (L.FhGrads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]),
+                            _ptr(grads["opacity"]), _ptr(grads["sh"])) if grads is not None else None)
+            acc = FusionAcc.zeros(self.n, self.d, self.device) if (target is not None and dC is not None) else None
+            fu = acc.struct() if acc is not None else None
+            tdt = L.FH_BF16 if (target is not None and target.dtype == torch.bfloat16) else L.FH_F32
+            L.check(self.lib.fh_autotune(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
+                                         ctypes.byref(up) if up is not None else None,
+                                         _ptr(target) if acc is not None else None, tdt,
+                                         ctypes.byref(fu) if fu is not None else None,
+                                         ctypes.byref(gr) if gr is not None else None, int(reps), _stream()),
+                    "fh_autotune")
+            t = self.plan.tuning
+            if cache:
+                table[key] = {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk)}
+                os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+                with open(cache, "w") as f:
+                    json.dump(table, f, indent=1, sort_keys=True)
+        self.tuning = L.FhTuning(int(t.fwd_slice), int(t.bwd_chunk))
+        self.plan.tuning = self.tuning
+        return {"fwd_slice": int(self.tuning.fwd_slice), "bwd_chunk": int(self.tuning.bwd_chunk)}
+
+    def set_tuning(self, fwd_slice: int, bwd_chunk: int) -> None:
+        """Set the launch shape by hand (validated by the next call)."""
+        self.tuning = L.FhTuning(int(fwd_slice), int(bwd_chunk))
+        self.plan.tuning = self.tuning
+
+    def tuning_candidates(self, which: int) -> list:
+        out = (L.FhTuning * 8)()
+        n = ctypes.c_int32()
+        L.check(self.lib.fh_tuning_candidates(ctypes.byref(self.plan), int(which), out, 8, ctypes.byref(n)),
+                "fh_tuning_candidates")
+        return [(int(out[i].fwd_slice), int(out[i].bwd_chunk)) for i in range(n.value)]
 
     def forward(self, g: Gaussians, margin: float = 1.05) -> Image:
         """prepare + render_fwd, growing the visit capacity until it fits."""

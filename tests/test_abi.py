@@ -40,9 +40,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "fhgs.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fh_plan), offsetof(fh_plan, cams),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fh_plan), offsetof(fh_plan, cams),
          offsetof(fh_plan, off), offsetof(fh_plan, ws_bytes), sizeof(fh_camera), sizeof(fh_gaussians),
-         sizeof(fh_counters), offsetof(fh_plan, tiles_x), offsetof(fh_plan, inst_capacity));
+         sizeof(fh_counters), offsetof(fh_plan, tiles_x), offsetof(fh_plan, inst_capacity),
+         offsetof(fh_plan, tuning), sizeof(fh_tuning));
   return 0;
 }
 ''')
@@ -53,7 +54,7 @@ int main(void) {
     P = _lib.FhPlan
     want = [ctypes.sizeof(P), P.cams.offset, P.off.offset, P.ws_bytes.offset, ctypes.sizeof(_lib.FhCamera),
             ctypes.sizeof(_lib.FhGaussians), ctypes.sizeof(_lib.FhCounters), P.tiles_x.offset,
-            P.inst_capacity.offset]
+            P.inst_capacity.offset, P.tuning.offset, ctypes.sizeof(_lib.FhTuning)]
     assert got == want
 
 
@@ -72,3 +73,37 @@ def test_plan_init_validates_on_host():
     assert lib.fh_plan_init(ctypes.byref(plan), -1, 3, 16, 0, 0, cams, 1, 0, 0) == -1
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 1, cams, 1, 0, 0) == -2   # bf16 form, f32 feat
     assert lib.fh_status_string(-4) == b"capacity exceeded"
+
+
+def test_tuning_defaults_and_candidates_on_host():
+    from paper_2505_19154_amd import _lib
+    lib = _lib.load()
+    cam = _lib.FhCamera(64, 48, 50.0, 50.0, 32.0, 24.0, (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1),
+                        (ctypes.c_float * 3)(0, 0, 4))
+    cams = (_lib.FhCamera * 1)(cam)
+
+    def cands(plan, which):
+        out = (_lib.FhTuning * 8)()
+        n = ctypes.c_int32()
+        assert lib.fh_tuning_candidates(ctypes.byref(plan), which, out, 8, ctypes.byref(n)) == 0
+        return [(out[i].fwd_slice, out[i].bwd_chunk) for i in range(n.value)]
+
+    plan = _lib.FhPlan()
+    # FP32 form, d = 256: forward slices 8..64, backward chunks 16 and 32
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 0, cams, 1, 0, 0) == 0
+    assert (plan.tuning.fwd_slice, plan.tuning.bwd_chunk) == (64, 32)
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(8, 32), (16, 32), (32, 32), (64, 32)]
+    assert cands(plan, _lib.FH_K_RENDER_BWD) == [(64, 16), (64, 32)]
+    assert cands(plan, _lib.FH_K_PROJECT) == [(64, 32)]
+    # BF16 form, d = 256: slices dividing d; one backward shape
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 0, 0) == 0
+    assert plan.tuning.fwd_slice == 128
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32), (64, 32), (128, 32)]
+    assert cands(plan, _lib.FH_K_RENDER_BWD) == [(128, 32)]
+    # BF16 form, d = 96; FP32 form, d = 16; d = 1024 takes 16-Gaussian chunks
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 96, 1, 1, cams, 1, 0, 0) == 0
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32), (96, 32)]
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 0, cams, 1, 0, 0) == 0
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(8, 32), (16, 32)]
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 1024, 0, 0, cams, 1, 0, 0) == 0
+    assert plan.tuning.bwd_chunk == 16 and cands(plan, _lib.FH_K_RENDER_BWD) == [(64, 16)]

@@ -25,7 +25,7 @@ from tests import sampled as S
 pytestmark = pytest.mark.gpu
 
 CASES = [("c4", "bf16"), ("c4", "f32"), ("c5", "bf16")]
-RT = {"f32": dict(F=1e-5, grad=1e-5, fuse=1e-5), "bf16": dict(F=1e-4, grad=2e-3, fuse=1e-4)}
+RT = {f: dict(F=r, grad=r, fuse=r) for f, r in U.RTOL_FORM.items()}
 N_SAMPLE = 12          # Gaussians whose gradients and fusion sums are checked
 EXTRA_TILES = 2        # further random non-empty tiles per view for the forward check
 

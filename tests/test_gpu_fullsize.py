@@ -23,9 +23,8 @@ CASES = [
     ("c3", "f32", (56, 30, 5)),
     ("c3", "bf16", (56, 30, 5)),
 ]
-# elementwise bounds (units of the magnitude companion); the BF16 form blends
-# F on MFMA with the weight split into two BF16 terms and rounds dF to BF16
-RT = {"f32": dict(F=1e-5, grad=1e-5, fuse=1e-5), "bf16": dict(F=1e-4, grad=2e-3, fuse=1e-4)}
+# elementwise bounds (units of the magnitude companion), per arithmetic form
+RT = {f: dict(F=r, grad=r, fuse=r) for f, r in U.RTOL_FORM.items()}
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[f"{w}-{f}" for w, f, _ in CASES])

@@ -98,6 +98,8 @@ def test_fusion_accumulates_across_calls_and_finalises(form):
         r = Rasterizer([cam], dg.n, dg.sh_degree, dg.d, feat_dtype="bf16", form=form)
         img = r.forward(dg)
         tgt = torch.from_numpy(np.tile(const, (cam.npix, 1))).cuda()
+        if form == "bf16":
+            tgt = tgt.to(torch.bfloat16)      # exact: const is representable
         r.fuse_features(dg, img, tgt, acc)
     fin = fuse_finalize(acc, torch.from_numpy(g["feat"]).cuda())
     torch.cuda.synchronize()
@@ -106,14 +108,14 @@ def test_fusion_accumulates_across_calls_and_finalises(form):
     assert hit.sum() > 50
     # a constant target map fuses to that constant; unseen Gaussians keep their feature
     f = fin.cpu().numpy()
-    rt = 1e-6 if form == "f32" else 1e-4
+    rt = 1e-6 if form == "f32" else U.RTOL_FORM["bf16"]
     assert np.allclose(f[hit], const[None, :], rtol=rt, atol=rt)
     assert np.array_equal(f[~hit], g["feat"][~hit])
     # the two calls equal one two-view call (oracle sums)
     vts = [dict(scenegen.make_view_tensors(i, c.npix, 32), target=np.tile(const, (c.npix, 1))) for i, c in enumerate(cams)]
     ora = pipeline.run(g, cams, vts, fusion=True)
     keep = ora["gflags"] == 0
-    assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=1e-5 if form == "f32" else 1e-4, mask=keep)[0] <= 1.0
+    assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=U.RTOL_FORM[form], mask=keep)[0] <= 1.0
 
 
 def test_autograd_function_against_central_differences():
