@@ -71,7 +71,8 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
     """The oracle over the planned tiles of every view.
 
     rows(vi, key, pix) -> float rows of map `key` in ("dC", "dF", "dT", "target")
-    of view vi at view-local pixels pix.  Adds to each entry of `views` its
+    of view vi at view-local pixels pix, or None for a map not given (no dT:
+    zero; no target: no fusion).  Adds to each entry of `views` its
     oracle tile lists ("lists") and forward outputs ("fwd"); returns the sampled
     Gaussians' gradient sums, magnitude companions, fusion sums and flags.
     """
@@ -86,7 +87,9 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
     gflag = np.zeros(cand.size, np.int32)
     for vi, (cam, bq, vw) in enumerate(zip(cams, bqs, views)):
         tx_n = bq["tiles_x"]
-        lists = {int(t): binspec.tile_list(bq, int(t) % tx_n, int(t) // tx_n) for t in vw["tiles"]}
+        given = vw.get("lists_in", {})
+        lists = {int(t): given[int(t)] if int(t) in given else binspec.tile_list(bq, int(t) % tx_n, int(t) // tx_n)
+                 for t in vw["tiles"]}
         vw["lists"] = lists
         need = np.unique(np.concatenate(list(lists.values()) + [np.zeros(0, np.int64)]))
         ranges = np.zeros((bq["tiles_x"] * bq["tiles_y"], 2), np.int64)
@@ -102,12 +105,16 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
         pix = tile_pixels(cam, tx_n, vw["tiles"])
         maps = {}
         for key, width in (("dC", 3), ("dF", d), ("dT", 0), ("target", d)):
+            r = rows(vi, key, pix)
+            if r is None:
+                maps[key] = None
+                continue
             full = np.zeros((cam.npix, width) if width else cam.npix)   # rows never written stay unallocated
-            full[pix] = rows(vi, key, pix)
+            full[pix] = r
             maps[key] = full
         out = raster.render_view(cam, ranges, glist, pr, feat=np.asarray(gsub["feat"], np.float64), dC=maps["dC"],
                                  dF=maps["dF"], dT=maps["dT"], target=maps["target"], tile_sel=vw["tiles"],
-                                 want_F=True, want_Fmag=True, want_fusion=True)
+                                 want_F=True, want_Fmag=True, want_fusion=maps["target"] is not None)
         vw["fwd"] = dict(pix=pix, C=out["C"][pix], Cmag=out["Cmag"][pix], T=out["T"][pix],
                          niter=out["niter"][pix], F=out["F"][pix], Fmag=out["Fmag"][pix], flags=out["flags"][pix])
         li = np.searchsorted(need, cand)
@@ -122,10 +129,88 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
             for k in GRAD_KEYS:
                 sums[k][present] += ref[k]
                 mags[k][present] += mag[k]
-            fsum[present] += out["fsum"][sel]
-            fsum_mag[present] += out["fsum_mag"][sel]
-            wsum[present] += out["wsum"][sel]
+            if maps["target"] is not None:
+                fsum[present] += out["fsum"][sel]
+                fsum_mag[present] += out["fsum_mag"][sel]
+                wsum[present] += out["wsum"][sel]
             gflag[present] |= out["gflags"][sel] | np.where(pr["clamp_amb"][sel], 4, 0).astype(np.int32)
         if log:
             log(f"oracle view {vi}: {vw['tiles'].size} tiles, {need.size} Gaussians")
     return dict(sums=sums, mags=mags, fsum=fsum, fsum_mag=fsum_mag, wsum=wsum, gflag=gflag)
+
+
+def _with_rect_of(bq: dict, bq1: dict, gi: int) -> dict:
+    """bq with Gaussian gi's binning replaced by that of the one-Gaussian bq1."""
+    out = dict(bq)
+    for k in ("binned", "x0", "x1", "y0", "y1", "depth"):
+        a = np.array(bq[k], copy=True)
+        a[gi] = bq1[k][0]
+        out[k] = a
+    return out
+
+
+def _rect_tiles(bq: dict, gi: int) -> set:
+    if not bq["binned"][gi]:
+        return set()
+    return {int(ty * bq["tiles_x"] + tx) for ty in range(bq["y0"][gi], bq["y1"][gi] + 1)
+            for tx in range(bq["x0"][gi], bq["x1"][gi] + 1)}
+
+
+def footprint_outputs(g: dict, cam, bq: dict, tiles: set, rows, d: int, lists: dict | None = None) -> dict:
+    """FP64 oracle forward (C, F per pixel) over the pixels of `tiles` (one view;
+    lists given, or from bq's float32 rects), pixels in tile order."""
+    views = [dict(tiles=np.array(sorted(tiles), np.int64), tile_off=0, pix_off=0, lists_in=lists or {})]
+    run(g, [cam], [bq], np.zeros(0, np.int64), views, rows, d)
+    return views[0]["fwd"]
+
+
+def _lists_with(bq: dict, base: dict, gi: int, rect_bq: dict) -> dict:
+    """Tile lists of `base` with Gaussian gi present exactly in the tiles of its
+    rect in rect_bq (its depth, and so its place in each list, unchanged)."""
+    inside = _rect_tiles(rect_bq, gi)
+    dbits = bq["depth"].view(np.uint32)
+    out = {}
+    for t, lst in base.items():
+        has = bool(np.any(lst == gi))
+        if (t in inside) == has:
+            out[t] = lst
+        elif has:
+            out[t] = lst[lst != gi]
+        else:
+            ext = np.append(lst, gi)
+            out[t] = ext[np.lexsort((ext, dbits[ext]))]
+    return out
+
+
+def central_difference(g: dict, cam, bq: dict, rows, d: int, gi: int, key: str, comp: int, h: float,
+                       cache: dict | None = None) -> float:
+    """(L(x + h) - L(x - h)) / 2h for parameter g[key][gi].flat[comp] with
+    L = sum_p dC(p) . C(p) + dF(p) . F(p), over every tile Gaussian gi touches in
+    either state (all other pixels are unchanged).  The two states' outputs
+    are subtracted pixel by pixel before the weighted sum, so the quotient is
+    not limited by the rounding of L itself.  The perturbed value is kept in
+    FP64; the step must not change gi's depth (its list positions are kept).
+    `cache` (a dict) keeps the unperturbed tile lists between calls."""
+    n = g["means"].shape[0]
+    states = []
+    for sgn in (1.0, -1.0):
+        arr = np.array(g[key], np.float64, copy=True)
+        arr.reshape(n, -1)[gi, comp] += sgn * h
+        gs = dict(g)
+        gs[key] = arr
+        one = {k: (v[gi:gi + 1] if isinstance(v, np.ndarray) and v.shape[:1] == (n,) else v) for k, v in gs.items()}
+        states.append((gs, _with_rect_of(bq, binspec.bin_quantities(one, cam), gi)))
+    tiles = _rect_tiles(bq, gi) | _rect_tiles(states[0][1], gi) | _rect_tiles(states[1][1], gi)
+    cache = {} if cache is None else cache
+    tx_n = bq["tiles_x"]
+    for t in tiles:
+        if t not in cache:
+            cache[t] = binspec.tile_list(bq, t % tx_n, t // tx_n)
+    base = {t: cache[t] for t in tiles}
+    fp = footprint_outputs(states[0][0], cam, bq, tiles, rows, d, _lists_with(bq, base, gi, states[0][1]))
+    fm = footprint_outputs(states[1][0], cam, bq, tiles, rows, d, _lists_with(bq, base, gi, states[1][1]))
+    p = fp["pix"]
+    dL = float(np.sum((fp["C"] - fm["C"]) * rows(0, "dC", p)))
+    if d:
+        dL += float(np.sum((fp["F"] - fm["F"]) * rows(0, "dF", p)))
+    return dL / (2.0 * h)
