@@ -330,7 +330,7 @@ def main():
         "value": blends / (ms * 1e-3),
         "unit": "Gaussian-pixel blends/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True,

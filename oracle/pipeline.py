@@ -25,6 +25,9 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
 
     view_tensors[v] holds dC [P,3], dF [P,D], dT [P] and, for fusion, target [P,D].
     tile_sel[v] optionally restricts the traversal to some of view v's tiles.
+    gflags: bit 0 the Gaussian decides a near-threshold skip/stop decision,
+    bit 2 its colour clamp is near-threshold; grads_amb / fsum_amb / wsum_amb
+    bound what near-threshold decisions of other Gaussians could change.
     """
     bins = binspec.bin_views(g, cams)
     feat = np.asarray(g["feat"], np.float64) if g["feat"] is not None else None
@@ -32,7 +35,8 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
     views = []
     grads = None
     grads_mag = None
-    fsum = wsum = fsum_mag = dfeat = None
+    grads_amb = None
+    fsum = wsum = fsum_mag = dfeat = fsum_amb = wsum_amb = None
     gflags = np.zeros(n, np.int32)
     counts = np.zeros(3, np.int64)
     for vi, cam in enumerate(cams):
@@ -59,15 +63,20 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
                 upm = _unpack(out["g2d_mag"])
                 gm = project.project_bwd(pr, upm, magnitude=True)
                 grads_mag = gm if grads_mag is None else {k: grads_mag[k] + gm[k] for k in grads_mag}
+                ga = project.project_bwd(pr, _unpack(out["g2d_amb"]), magnitude=True)
+                grads_amb = ga if grads_amb is None else {k: grads_amb[k] + ga[k] for k in grads_amb}
             if fusion:
                 fsum = out["fsum"] if fsum is None else fsum + out["fsum"]
                 fsum_mag = out["fsum_mag"] if fsum_mag is None else fsum_mag + out["fsum_mag"]
                 wsum = out["wsum"] if wsum is None else wsum + out["wsum"]
+                fsum_amb = out["fsum_amb"] if fsum_amb is None else fsum_amb + out["fsum_amb"]
+                wsum_amb = out["wsum_amb"] if wsum_amb is None else wsum_amb + out["wsum_amb"]
             if want_dfeat:
                 dfeat = out["dfeat"] if dfeat is None else dfeat + out["dfeat"]
         views.append(rec)
-    return dict(bins=bins, views=views, grads=grads, grads_mag=grads_mag, fsum=fsum,
-                fsum_mag=fsum_mag, wsum=wsum, dfeat=dfeat, gflags=gflags, counts=counts)
+    return dict(bins=bins, views=views, grads=grads, grads_mag=grads_mag, grads_amb=grads_amb, fsum=fsum,
+                fsum_mag=fsum_mag, fsum_amb=fsum_amb, wsum=wsum, wsum_amb=wsum_amb, dfeat=dfeat, gflags=gflags,
+                counts=counts)
 
 
 def _unpack(g2d: np.ndarray) -> dict:

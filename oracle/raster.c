@@ -27,6 +27,16 @@
  *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
  * absolute values of the same terms) are accumulated alongside.
+ *
+ * Decisions within ambig_rel (relative) of a threshold may be taken the other
+ * way by an FP32 implementation.  Such a pixel is flagged, and so is the
+ * Gaussian that decides it (gflags bit 0).  Into g2d_amb / fsum_amb /
+ * wsum_amb go the magnitudes of everything the other decision could change:
+ * every contributor's terms from that pixel, and the terms the decider would
+ * add if it were blended (its w = alpha T at the decision, with the pixel's
+ * whole suffix magnitude for its S).  An alpha near the 0.99 clamp only
+ * switches that Gaussian's power/opacity terms in that pixel; their unclamped
+ * magnitudes go to g2d_amb as well.
  */
 #include <math.h>
 #include <stdint.h>
@@ -74,16 +84,26 @@ typedef struct {
     double *fsum_mag;                /* [N, d] or NULL */
     double *wsum;                    /* [N] or NULL */
     double *dfeat;                   /* [N, d] or NULL: dL/df = sum_p w dF */
-    int32_t *gflags;                 /* [N] or NULL: bit0 contributes to (or decides) a pixel with a
-                                        near-threshold skip/stop decision, bit1 alpha near the clamp */
+    double *g2d_amb;                 /* [N, 9] or NULL: magnitudes of the terms that a near-threshold
+                                        decision could change (see below) */
+    double *fsum_amb;                /* [N, d] or NULL: the same for the fusion sums */
+    double *wsum_amb;                /* [N] or NULL: the same for the weight sums */
+    int32_t *gflags;                 /* [N] or NULL: bit0 decides a near-threshold skip/stop decision
+                                        (informational: bounded through the *_amb companions) */
     int64_t *counts;                 /* [3]: sum n_iter, contributing blends, alpha evaluations */
 } oracle_args;
 
 typedef struct {
     int64_t g;
     double alpha, T, G, dx, dy;
-    int clamped;
+    int clamped, near_clamp;
 } blend_rec;
+
+/* a near-threshold decision: the deciding Gaussian and its state there */
+typedef struct {
+    int64_t g;
+    double alpha, T, G, dx, dy;
+} amb_rec;
 
 static void atomic_add(double *p, double x) {
 #pragma omp atomic
@@ -97,7 +117,7 @@ static double rgbm(const oracle_args *a, int64_t g, int c) {
     return a->rgb_mag ? a->rgb_mag[3 * g + c] : fabs(a->rgb[3 * g + c]);
 }
 
-static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t *amb, double *gvec,
+static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec *amb, double *gvec,
                     double *gmag) {
     const int64_t ty = tile / a->tiles_x, tx = tile % a->tiles_x;
     const int64_t start = a->ranges[2 * tile], end = a->ranges[2 * tile + 1];
@@ -124,22 +144,19 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                 const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
                 local_counts[2]++;
                 /* a decision this close to its threshold may go either way in FP32:
-                   the clamp only changes g's own gradient (bit 1); the skip and stop
-                   rules change the whole pixel (bit 0) */
-                if (near_rel(raw, ALPHA_MAX, a->ambig_rel) && a->gflags) {
-#pragma omp atomic
-                    a->gflags[g] |= 2;
-                    flags |= 2;
-                }
+                   the clamp only changes g's own terms in this pixel (pixel bit 1,
+                   bounded through g2d_amb); the skip and stop rules change the
+                   whole pixel (pixel bit 0) */
+                if (near_rel(raw, ALPHA_MAX, a->ambig_rel)) flags |= 2;
                 if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = g;
+                    amb[namb++] = (amb_rec){g, alpha, T, G, dx, dy};
                 }
                 if (alpha < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - alpha);
                 if (near_rel(Tn, T_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = g;
+                    amb[namb++] = (amb_rec){g, alpha, T, G, dx, dy};
                 }
                 if (Tn < T_MIN) break;
                 const double w = alpha * T;
@@ -154,6 +171,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                 blend_rec *r = &recs[nrec++];
                 r->g = g; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
                 r->clamped = raw >= ALPHA_MAX;
+                r->near_clamp = near_rel(raw, ALPHA_MAX, a->ambig_rel);
                 T = Tn;
                 niter = pos - start + 1;
                 local_counts[1]++;
@@ -165,15 +183,13 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
             a->out_T[pix] = T;
             a->out_niter[pix] = niter;
             if (a->out_flags) a->out_flags[pix] = flags;
-            /* a value-ambiguous pixel perturbs every contributor's adjoint */
+            /* the Gaussians that decide a near-threshold skip/stop may gain or lose
+               this pixel's whole contribution: flag them; the other contributors of
+               such a pixel are bounded through the *_amb companions below */
             if ((flags & 1) && a->gflags) {
-                for (int64_t i = 0; i < nrec; ++i) {
-#pragma omp atomic
-                    a->gflags[recs[i].g] |= 1;
-                }
                 for (int64_t i = 0; i < namb; ++i) {
 #pragma omp atomic
-                    a->gflags[amb[i]] |= 1;
+                    a->gflags[amb[i].g] |= 1;
                 }
             }
             if (!a->dC) continue;
@@ -233,6 +249,22 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                     for (int k = 0; k < 9; ++k) atomic_add(&a->g2d[9 * g + k], gvec[k]);
                 if (a->g2d_mag)
                     for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_mag[9 * g + k], gmag[k]);
+                /* a decision that may go the other way in FP32 changes this pixel's
+                   terms for every contributor (ambiguous pixel), or switches this
+                   Gaussian's alpha between clamped and not (near the clamp): record
+                   the magnitude of the terms it can change, unclamped */
+                if (a->g2d_amb && ((flags & 1) || r->near_clamp)) {
+                    const double um = dalpham * r->alpha, om = dalpham * r->G;
+                    double am[9];
+                    am[0] = um * (fabs(A * dx) + fabs(B * dy));
+                    am[1] = um * (fabs(B * dx) + fabs(Cc * dy));
+                    am[2] = um * 0.5 * dx * dx;
+                    am[3] = um * fabs(dx * dy);
+                    am[4] = um * 0.5 * dy * dy;
+                    am[5] = om;
+                    for (int c = 0; c < 3; ++c) am[6 + c] = (flags & 1) ? gmag[6 + c] : 0.0;
+                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_amb[9 * g + k], am[k]);
+                }
                 if (a->dfeat && dF)
                     for (int64_t k = 0; k < d; ++k) atomic_add(&a->dfeat[g * d + k], w * dF[k]);
                 if (tgt) {
@@ -241,6 +273,42 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, int64_t
                     if (a->fsum_mag)
                         for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_mag[g * d + k], fabs(w * tgt[k]));
                     if (a->wsum) atomic_add(&a->wsum[g], w);
+                    if (flags & 1) {
+                        if (a->fsum_amb)
+                            for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_amb[g * d + k], fabs(w * tgt[k]));
+                        if (a->wsum_amb) atomic_add(&a->wsum_amb[g], w);
+                    }
+                }
+            }
+            /* each decider may gain (or keep) a blend here in FP32 that FP64 did
+               not take: bound the terms such a blend would add, with the whole
+               suffix magnitude of the pixel standing in for its S */
+            for (int64_t i = 0; i < namb; ++i) {
+                const amb_rec *e = &amb[i];
+                const int64_t g = e->g;
+                double gkm = 0.0;
+                for (int c = 0; c < 3; ++c) gkm += rgbm(a, g, c) * fabs(dC[c]);
+                if (dF)
+                    for (int64_t k = 0; k < d; ++k) gkm += fabs(a->feat[g * d + k] * dF[k]);
+                const double w = e->alpha * e->T;
+                const double dalpham = e->T * gkm + (Sm + Tfin * fabs(dT)) / (1.0 - e->alpha);
+                const double um = dalpham * e->alpha, om = dalpham * e->G;
+                const double A = a->A[g], B = a->B[g], Cc = a->C[g], dx = e->dx, dy = e->dy;
+                if (a->g2d_amb) {
+                    double am[9];
+                    am[0] = um * (fabs(A * dx) + fabs(B * dy));
+                    am[1] = um * (fabs(B * dx) + fabs(Cc * dy));
+                    am[2] = um * 0.5 * dx * dx;
+                    am[3] = um * fabs(dx * dy);
+                    am[4] = um * 0.5 * dy * dy;
+                    am[5] = om;
+                    for (int c = 0; c < 3; ++c) am[6 + c] = w * fabs(dC[c]);
+                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_amb[9 * g + k], am[k]);
+                }
+                if (tgt) {
+                    if (a->fsum_amb)
+                        for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_amb[g * d + k], fabs(w * tgt[k]));
+                    if (a->wsum_amb) atomic_add(&a->wsum_amb[g], w);
                 }
             }
         }
@@ -265,7 +333,7 @@ int oracle_raster(const oracle_args *a) {
 #pragma omp parallel
     {
         blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
-        int64_t *amb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * maxlen + 2));
+        amb_rec *amb = (amb_rec *)malloc(sizeof(amb_rec) * (size_t)(2 * maxlen + 2));
         double gvec[9], gmag[9];
         if (!recs || !amb) {
 #pragma omp atomic write

@@ -46,7 +46,7 @@ class _Args(ctypes.Structure):
         ("out_C", _P), ("out_Cmag", _P), ("out_F", _P), ("out_Fmag", _P), ("out_T", _P), ("out_niter", _P),
         ("out_flags", _P),
         ("g2d", _P), ("g2d_mag", _P), ("fsum", _P), ("fsum_mag", _P), ("wsum", _P),
-        ("dfeat", _P), ("gflags", _P), ("counts", _P),
+        ("dfeat", _P), ("g2d_amb", _P), ("fsum_amb", _P), ("wsum_amb", _P), ("gflags", _P), ("counts", _P),
     ]
 
 
@@ -118,6 +118,9 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     out["fsum"] = np.zeros((n, d)) if fus else None
     out["fsum_mag"] = np.zeros((n, d)) if fus else None
     out["wsum"] = np.zeros(n) if (bwd and target is not None) else None
+    out["g2d_amb"] = np.zeros((n, 9)) if bwd else None
+    out["fsum_amb"] = np.zeros((n, d)) if fus else None
+    out["wsum_amb"] = np.zeros(n) if (bwd and target is not None) else None
     out["dfeat"] = np.zeros((n, d)) if (bwd and want_dfeat and d) else None
     out["gflags"] = np.zeros(n, np.int32)
 
@@ -133,6 +136,7 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         out_T=_ptr(out["T"]), out_niter=_ptr(out["niter"]), out_flags=_ptr(out["flags"]),
         g2d=_ptr(out["g2d"]), g2d_mag=_ptr(out["g2d_mag"]), fsum=_ptr(out["fsum"]),
         fsum_mag=_ptr(out["fsum_mag"]), wsum=_ptr(out["wsum"]), dfeat=_ptr(out["dfeat"]),
+        g2d_amb=_ptr(out["g2d_amb"]), fsum_amb=_ptr(out["fsum_amb"]), wsum_amb=_ptr(out["wsum_amb"]),
         gflags=_ptr(out["gflags"]), counts=_ptr(out["counts"]),
     )
     rc = lib.oracle_raster(ctypes.byref(args))

@@ -33,6 +33,26 @@ def pick_gaussians(bqs: list, n: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(cand, size=min(n, cand.size), replace=False))
 
 
+def pick_front(bq: dict, max_side: int, n_near: int, max_tiles: int | None = None) -> np.ndarray:
+    """Gaussians of one view that the walk reaches at high density: the n_near
+    nearest binned ones with a rect of at most max_side x max_side tiles,
+    stopping early once the union of their rects would exceed max_tiles
+    (sorted indices)."""
+    small = bq["binned"] & (bq["x1"] - bq["x0"] < max_side) & (bq["y1"] - bq["y0"] < max_side)
+    cand = np.nonzero(small)[0]
+    cand = cand[np.argsort(bq["depth"][cand], kind="stable")[:n_near]]
+    if max_tiles is not None:
+        tiles, keep = set(), []
+        for gi in cand:
+            t = _rect_tiles(bq, int(gi))
+            if len(tiles | t) > max_tiles:
+                break
+            tiles |= t
+            keep.append(int(gi))
+        cand = np.asarray(keep, np.int64)
+    return np.sort(cand)
+
+
 def plan(bqs: list, counts: list, cams: list, cand: np.ndarray, extra_tiles: int, seed: int) -> list:
     """Per view: the tiles to walk, the view's global tile offset and pixel offset."""
     rng = np.random.default_rng(seed)
@@ -74,13 +94,17 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
     of view vi at view-local pixels pix, or None for a map not given (no dT:
     zero; no target: no fusion).  Adds to each entry of `views` its
     oracle tile lists ("lists") and forward outputs ("fwd"); returns the sampled
-    Gaussians' gradient sums, magnitude companions, fusion sums and flags.
+    Gaussians' gradient sums, magnitude companions, ambiguity bounds (as
+    pipeline.run's grads_amb), fusion sums and flags.
     """
     n = g["means"].shape[0]
     nb = (int(g["sh_degree"]) + 1) ** 2
     shapes = dict(means=(3,), scales=(3,), quats=(4,), opacity=(), sh=(nb, 3))
     sums = {k: np.zeros((cand.size,) + shapes[k]) for k in GRAD_KEYS}
     mags = {k: np.zeros((cand.size,) + shapes[k]) for k in GRAD_KEYS}
+    ambs = {k: np.zeros((cand.size,) + shapes[k]) for k in GRAD_KEYS}
+    fsum_amb = np.zeros((cand.size, d))
+    wsum_amb = np.zeros(cand.size)
     fsum = np.zeros((cand.size, d))
     fsum_mag = np.zeros((cand.size, d))
     wsum = np.zeros(cand.size)
@@ -126,17 +150,22 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
                    for k, v in pr.items()}
             ref = project.project_bwd(sub, pipeline._unpack(out["g2d"][sel]))
             mag = project.project_bwd(sub, pipeline._unpack(out["g2d_mag"][sel]), magnitude=True)
+            amb = project.project_bwd(sub, pipeline._unpack(out["g2d_amb"][sel]), magnitude=True)
             for k in GRAD_KEYS:
                 sums[k][present] += ref[k]
                 mags[k][present] += mag[k]
+                ambs[k][present] += amb[k]
             if maps["target"] is not None:
                 fsum[present] += out["fsum"][sel]
                 fsum_mag[present] += out["fsum_mag"][sel]
                 wsum[present] += out["wsum"][sel]
+                fsum_amb[present] += out["fsum_amb"][sel]
+                wsum_amb[present] += out["wsum_amb"][sel]
             gflag[present] |= out["gflags"][sel] | np.where(pr["clamp_amb"][sel], 4, 0).astype(np.int32)
         if log:
             log(f"oracle view {vi}: {vw['tiles'].size} tiles, {need.size} Gaussians")
-    return dict(sums=sums, mags=mags, fsum=fsum, fsum_mag=fsum_mag, wsum=wsum, gflag=gflag)
+    return dict(sums=sums, mags=mags, ambs=ambs, fsum=fsum, fsum_mag=fsum_mag, fsum_amb=fsum_amb, wsum=wsum,
+                wsum_amb=wsum_amb, gflag=gflag)
 
 
 def _with_rect_of(bq: dict, bq1: dict, gi: int) -> dict:

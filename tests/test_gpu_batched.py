@@ -8,7 +8,8 @@ oracle computes one by one:
 Binning: the instance count and every tile range of every view, bit for bit
 (per-tile counts from the oracle's float32 rects), and the full sorted key and
 Gaussian lists of every sampled tile.  Forward: every pixel of the sampled
-tiles.  Gradients and fusion: a seeded sample of small Gaussians, with the
+tiles.  Gradients and fusion: Gaussians of view 0's front layer (nearest
+first, rects of at most 16x16 tiles, within a 1200-tile budget), with the
 oracle walking every tile that each of them touches in every view, so their
 sums over views are complete.  Per-view maps are drawn on the device
 (scenegen.make_view_tensors_device); the oracle reads the rows it needs.
@@ -26,7 +27,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("c4", "bf16"), ("c4", "f32"), ("c5", "bf16")]
 RT = {f: dict(F=r, grad=r, fuse=r) for f, r in U.RTOL_FORM.items()}
-N_SAMPLE = 12          # Gaussians whose gradients and fusion sums are checked
+N_SAMPLE = 32          # Gaussians whose gradients and fusion sums are checked (at most)
 EXTRA_TILES = 2        # further random non-empty tiles per view for the forward check
 
 
@@ -70,7 +71,8 @@ def run(request):
     bqs = [binspec.bin_quantities(g, cam) for cam in cams]
     counts = [binspec.tile_counts(bq) for bq in bqs]
     print(f"{tag} oracle binning quantities done", flush=True)
-    cand = S.pick_gaussians(bqs, 4 * N_SAMPLE, seed=11)
+    # the front layer of view 0 (the only Gaussians its walk reaches at this density)
+    cand = S.pick_front(bqs[0], 16, 20000, 1200)
     views = S.plan(bqs, counts, cams, cand, EXTRA_TILES, seed=12)
 
     # the GPU's key and Gaussian lists of the sampled tiles
@@ -131,22 +133,23 @@ def test_forward_sampled_tiles(run):
 
 
 def test_gradients_and_fusion_of_sample(run):
-    keep = run["gflag"] == 0
+    keep = U.checkable(run["gflag"])
     touched = run["wsum"] > 0
     idx = np.nonzero(keep & touched)[0][:N_SAMPLE]
     print(f"[batched] {idx.size} sampled Gaussians checked", flush=True)
-    assert idx.size >= N_SAMPLE // 2
+    assert idx.size >= 16
     gid = torch.from_numpy(run["cand"][idx]).cuda()
     rt = RT[run["form"]]
     for k in run["sums"]:
         got = run["grads"][k][gid].cpu().numpy()
-        mx, mean = U.elementwise(got, run["sums"][k][idx], run["mags"][k][idx], rtol=rt["grad"])
+        mx, mean = U.elementwise(got, run["sums"][k][idx], run["mags"][k][idx], rtol=rt["grad"],
+                                 amb=run["ambs"][k][idx])
         print(f"[batched] grad {k}: ratio max/mean {mx:.3f}/{mean:.3f}", flush=True)
         assert mx <= 1.0, k
     acc = run["acc"]
     s = (acc.sum[gid] + acc.comp[gid]).cpu().numpy()
     w = (acc.wsum[gid] + acc.wcomp[gid]).cpu().numpy()
-    mx, _ = U.elementwise(s, run["fsum"][idx], run["fsum_mag"][idx], rtol=rt["fuse"])
-    mw, _ = U.elementwise(w, run["wsum"][idx], run["wsum"][idx], rtol=rt["fuse"])
+    mx, _ = U.elementwise(s, run["fsum"][idx], run["fsum_mag"][idx], rtol=rt["fuse"], amb=run["fsum_amb"][idx])
+    mw, _ = U.elementwise(w, run["wsum"][idx], run["wsum"][idx], rtol=rt["fuse"], amb=run["wsum_amb"][idx])
     print(f"[batched] fusion ratio max {mx:.3f}, wsum {mw:.3f}", flush=True)
     assert mx <= 1.0 and mw <= 1.0

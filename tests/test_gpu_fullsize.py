@@ -4,8 +4,11 @@ bench.py times, on outputs the oracle can compute in seconds:
 * binning: every key and every tile range, bit for bit (the oracle's float32
   binning runs on all Gaussians);
 * forward: every pixel of a block of tiles;
-* gradients and fusion: every Gaussian whose tile rect lies inside that block
-  (so the oracle's walk over the block covers all of its contributions).
+* gradients and fusion: Gaussians of the front layer (the only ones the walk
+  reaches at this density: the nearest with a rect of at most 12x12 tiles at
+  800x800, or of at most 20x20 tiles within a 1500-tile budget at 1080p), with
+  the oracle walking every tile of their rects, so their sums are complete
+  (tests/sampled.py); up to 64 that contribute are compared.
 """
 import numpy as np
 import pytest
@@ -14,15 +17,18 @@ import torch
 import scenegen
 from oracle import binspec, pipeline, project, raster
 from tests import gpu_util as U
+from tests import sampled as S
 
 pytestmark = pytest.mark.gpu
 
-# workload, form, tile block (x0, y0, size)
+# workload, form, tile block (x0, y0, size) for the forward check
 CASES = [
     ("c2", "f32", (22, 20, 6)),
     ("c3", "f32", (56, 30, 5)),
     ("c3", "bf16", (56, 30, 5)),
 ]
+# front-layer sample per workload: (max rect side in tiles, nearest count, tile budget)
+FRONT = {"c2": (12, 5000, None), "c3": (20, 100000, 1500)}
 # elementwise bounds (units of the magnitude companion), per arithmetic form
 RT = {f: dict(F=r, grad=r, fuse=r) for f, r in U.RTOL_FORM.items()}
 
@@ -49,7 +55,7 @@ def run(request):
                              target=vt["target"] if wl.fusion else None, tile_sel=sel, want_F=True,
                              want_Fmag=True, want_fusion=wl.fusion)
     print(f"[full {wname} {form}] oracle done", flush=True)
-    return dict(wl=wl, form=form, g=g, cams=cams, gpu=gpu, bins=bins, out=out, pr=pr,
+    return dict(wl=wl, form=form, g=g, cams=cams, gpu=gpu, bins=bins, out=out, pr=pr, vt=vt,
                 block=(bx, by, bs), sel=sel)
 
 
@@ -92,42 +98,48 @@ def test_forward_block(run):
     assert mF <= 1.0
 
 
-def _inner_gaussians(run):
+@pytest.fixture(scope="module")
+def front(run):
+    """The sampled oracle over the front layer's tiles (see the module docstring)."""
+    g, cam = run["g"], run["cams"][0]
     bq = run["bins"]["per_view"][0]
-    bx, by, bs = run["block"]
-    inner = (bq["binned"] & (bq["x0"] >= bx) & (bq["x1"] < bx + bs) & (bq["y0"] >= by) & (bq["y1"] < by + bs))
-    out = run["out"]
-    touched = np.abs(out["g2d"]).sum(1) > 0
-    return np.nonzero(inner & touched & (out["gflags"] == 0) & ~run["pr"]["clamp_amb"])[0]
+    wl = run["wl"]
+    vt = run["vt"]
+    cand = S.pick_front(bq, *FRONT[wl.name])
+    views = [dict(tiles=np.array(sorted(set().union(*[S._rect_tiles(bq, int(i)) for i in cand]))), tile_off=0,
+                  pix_off=0)]
+    rows = lambda vi, key, pix: vt[key][pix] if (key != "target" or wl.fusion) else None
+    ora = S.run(g, [cam], [bq], cand, views, rows, wl.d)
+    keep = np.nonzero(U.checkable(ora["gflag"]) & (np.abs(ora["sums"]["opacity"]) > 0))[0][:64]
+    print(f"[full] front layer: {cand.size} Gaussians over {views[0]['tiles'].size} tiles, {keep.size} compared",
+          flush=True)
+    return dict(cand=cand, keep=keep, **ora)
 
 
-def test_gradients_of_inner_gaussians(run):
-    gpu, out, pr = run["gpu"], run["out"], run["pr"]
-    idx = _inner_gaussians(run)
-    print(f"[full] {idx.size} Gaussians inside the block", flush=True)
-    assert idx.size >= 20
-    up = pipeline._unpack(out["g2d"])
-    upm = pipeline._unpack(out["g2d_mag"])
-    ref = project.project_bwd(pr, up)
-    mag = project.project_bwd(pr, upm, magnitude=True)
+def test_gradients_of_front_gaussians(run, front):
+    gpu = run["gpu"]
+    keep = front["keep"]
+    assert keep.size >= 8
+    gid = front["cand"][keep]
     rt = RT[run["form"]]["grad"]
-    for k in ("means", "scales", "quats", "opacity", "sh"):
-        got = gpu["grads"][k].cpu().numpy()[idx]
-        mx, mean = U.elementwise(got, ref[k][idx], mag[k][idx], rtol=rt)
+    for k in S.GRAD_KEYS:
+        got = gpu["grads"][k].cpu().numpy()[gid]
+        mx, mean = U.elementwise(got, front["sums"][k][keep], front["mags"][k][keep], rtol=rt,
+                                 amb=front["ambs"][k][keep])
         print(f"[full] grad {k}: ratio max/mean {mx:.3f}/{mean:.3f} (rtol {rt:g})", flush=True)
         assert mx <= 1.0, k
 
 
-def test_fusion_of_inner_gaussians(run):
+def test_fusion_of_front_gaussians(run, front):
     if not run["wl"].fusion:
         pytest.skip("workload without fusion")
-    gpu, out = run["gpu"], run["out"]
-    idx = _inner_gaussians(run)
-    acc = gpu["acc"]
-    s = (acc.sum + acc.comp).cpu().numpy()[idx]
-    w = (acc.wsum + acc.wcomp).cpu().numpy()[idx]
+    acc = run["gpu"]["acc"]
+    keep = front["keep"]
+    gid = front["cand"][keep]
+    s = (acc.sum + acc.comp).cpu().numpy()[gid]
+    w = (acc.wsum + acc.wcomp).cpu().numpy()[gid]
     rt = RT[run["form"]]["fuse"]
-    mx, mean = U.elementwise(s, out["fsum"][idx], out["fsum_mag"][idx], rtol=rt)
-    mw, _ = U.elementwise(w, out["wsum"][idx], out["wsum"][idx], rtol=rt)
+    mx, mean = U.elementwise(s, front["fsum"][keep], front["fsum_mag"][keep], rtol=rt, amb=front["fsum_amb"][keep])
+    mw, _ = U.elementwise(w, front["wsum"][keep], front["wsum"][keep], rtol=rt, amb=front["wsum_amb"][keep])
     print(f"[full] fusion ratio max/mean {mx:.3f}/{mean:.3f}, wsum {mw:.3f} (rtol {rt:g})", flush=True)
     assert mx <= 1.0 and mw <= 1.0

@@ -46,7 +46,8 @@ def test_single_gaussian_matches_oracle():
     ok = (v["flags"] & 1) == 0
     assert U.elementwise(gpu["img"].C.cpu().numpy(), v["C"], v["Cmag"], mask=ok[:, None].repeat(3, 1))[0] <= 1.0
     for k in ("means", "scales", "quats", "opacity"):
-        assert U.elementwise(gpu["grads"][k].cpu().numpy(), ora["grads"][k], ora["grads_mag"][k])[0] <= 1.0, k
+        assert U.elementwise(gpu["grads"][k].cpu().numpy(), ora["grads"][k], ora["grads_mag"][k],
+                             amb=ora["grads_amb"][k])[0] <= 1.0, k
 
 
 def test_nonfinite_gaussians_are_culled_and_counted():
@@ -114,8 +115,8 @@ def test_fusion_accumulates_across_calls_and_finalises(form):
     # the two calls equal one two-view call (oracle sums)
     vts = [dict(scenegen.make_view_tensors(i, c.npix, 32), target=np.tile(const, (c.npix, 1))) for i, c in enumerate(cams)]
     ora = pipeline.run(g, cams, vts, fusion=True)
-    keep = ora["gflags"] == 0
-    assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=U.RTOL_FORM[form], mask=keep)[0] <= 1.0
+    keep = U.checkable(ora["gflags"])
+    assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=U.RTOL_FORM[form], mask=keep, amb=ora["wsum_amb"])[0] <= 1.0
 
 
 def test_autograd_function_against_central_differences():
@@ -148,14 +149,12 @@ def test_autograd_function_against_central_differences():
 
     bq = binspec.bin_quantities(g, cam)
     rows = lambda vi, key, pix: None if key in ("target", "dT") else vt[key][pix]
-    small = bq["binned"] & (bq["x1"] - bq["x0"] < 12) & (bq["y1"] - bq["y0"] < 12)
     # the nearest such Gaussians (most of the far ones are never reached before pixels saturate)
-    cand = np.nonzero(small)[0]
-    first = np.sort(cand[np.argsort(bq["depth"][cand], kind="stable")[:5000]])
+    first = S.pick_front(bq, 12, 5000)
     views = [dict(tiles=np.array(sorted(set().union(*[S._rect_tiles(bq, i) for i in first]))), tile_off=0,
                   pix_off=0)]
     ora = S.run(g, [cam], [bq], first, views, rows, wl.d)
-    ok = (ora["gflag"] == 0) & (np.abs(ora["sums"]["opacity"]) > 0)
+    ok = U.checkable(ora["gflag"]) & (np.abs(ora["sums"]["opacity"]) > 0)
     subset = first[ok][:64]
     assert subset.size == 64
     depth_axis = np.abs(np.asarray(cam.R, np.float64)[2])
@@ -180,8 +179,10 @@ def test_autograd_function_against_central_differences():
             spread = max(abs(fd - fd_small), abs(fd - fd_big))
             an = float(grads[key][gi, comp])
             mag = float(ora["mags"][key].reshape(first.size, -1)[k, comp])
-            # the FP32 gradient's bound (1e-5 M, doubled) plus the quotient's error
-            ratio = abs(an - fd) / (2e-5 * mag + 2 * spread + 1e-30)
+            amb = float(ora["ambs"][key].reshape(first.size, -1)[k, comp])
+            # the FP32 gradient's bound (1e-5 M, doubled; ambiguous decisions as in the
+            # parity tests) plus the quotient's error
+            ratio = abs(an - fd) / (2e-5 * mag + U.AMB_FACTOR * amb + 2 * spread + 1e-30)
             worst = max(worst, ratio)
             total += 1
             tight += 2 * spread <= 2e-5 * mag

@@ -120,15 +120,15 @@ def test_forward_parity(case):
 
 def test_backward_parity(case):
     gpu, ora = case["gpu"], case["ora"]
-    keep = ora["gflags"] == 0
-    print(f"[{case['name']}] Gaussians excluded (ambiguous) {1 - keep.mean():.2e}", flush=True)
+    keep = U.checkable(ora["gflags"])
+    print(f"[{case['name']}] Gaussians excluded (ambiguous colour clamp) {1 - keep.mean():.2e}", flush=True)
     for k in ("means", "scales", "quats", "opacity", "sh"):
         got = gpu["grads"][k].cpu().numpy()
         ref = ora["grads"][k]
         mag = ora["grads_mag"][k]
         m = keep.reshape((-1,) + (1,) * (ref.ndim - 1)) & np.ones(ref.shape, bool)
         rt = U.RTOL_FORM[case["form"]]
-        mx, mean = U.elementwise(got, ref, mag, rtol=rt, mask=m)
+        mx, mean = U.elementwise(got, ref, mag, rtol=rt, mask=m, amb=ora["grads_amb"][k])
         nw = U.normwise(got, ref)
         print(f"[{case['name']}] grad {k}: max/mean ratio {mx:.3f}/{mean:.3f} (rtol {rt:g}) norm {nw:.2e}",
               flush=True)
@@ -143,10 +143,11 @@ def test_fusion_parity(case):
     acc = gpu["acc"]
     s = (acc.sum + acc.comp).cpu().numpy()
     w = (acc.wsum + acc.wcomp).cpu().numpy()
-    keep = ora["gflags"] == 0
+    keep = U.checkable(ora["gflags"])
     rt = U.RTOL_FORM[case["form"]]
-    mx, mean = U.elementwise(s, ora["fsum"], ora["fsum_mag"], rtol=rt, mask=keep[:, None] & np.ones(s.shape, bool))
-    mw, _ = U.elementwise(w, ora["wsum"], ora["wsum"], rtol=rt, mask=keep)
+    mx, mean = U.elementwise(s, ora["fsum"], ora["fsum_mag"], rtol=rt, mask=keep[:, None] & np.ones(s.shape, bool),
+                             amb=ora["fsum_amb"])
+    mw, _ = U.elementwise(w, ora["wsum"], ora["wsum"], rtol=rt, mask=keep, amb=ora["wsum_amb"])
     print(f"[{case['name']}] fusion sum max/mean ratio {mx:.3f}/{mean:.3f} wsum {mw:.3f} "
           f"norm {U.normwise(s, ora['fsum']):.2e}", flush=True)
     assert mx <= 1.0 and mw <= 1.0

@@ -159,3 +159,30 @@ def test_colour_magnitude_companion():
     g1["sh"][1, 0, :] = np.float32(0.3 / y00)
     pr1 = project.project(g1, cam)
     assert pr1["clamp_amb"][0] and not pr1["clamp_amb"][1]
+
+
+def test_ambiguity_companions():
+    # two concentric Gaussians, the front one's alpha at the centre pixel within
+    # rounding of 1/255: that pixel is flagged, the front Gaussian (the decider)
+    # is flagged, the back one keeps its terms and gets a non-zero g2d_amb;
+    # an alpha just above the 0.99 clamp contributes unclamped magnitudes
+    u = v = 7.5
+    a_front = (1.0 / 255.0) * (1.0 + 1e-7)
+    out = _one_tile([u, u], [v, v], [0.02, 0.02], [0.0, 0.0], [0.02, 0.02], [a_front, 0.6],
+                    [[0.2, 0.5, 1.0], [1.0, 0.3, 0.1]], dC=np.ones((256, 3)), dT=np.zeros(256))
+    p = 7 * 16 + 7
+    assert out["flags"][p] & 1
+    assert out["gflags"][0] & 1 and not out["gflags"][1] & 1
+    assert np.all(out["g2d_amb"] >= 0) and np.any(out["g2d_amb"][1] > 0)
+    assert out["g2d_amb"][0, 5] > 0          # the decider's would-be opacity term
+    assert np.all(out["g2d_amb"][1] <= out["g2d_mag"][1] * (1 + 1e-12))
+    # no near-threshold decision: nothing to bound
+    out = _one_tile([u], [v], [0.02], [0.0], [0.02], [0.5], [[0.2, 0.5, 1.0]], dC=np.ones((256, 3)),
+                    dT=np.zeros(256))
+    assert not np.any(out["flags"] & 1) and np.all(out["g2d_amb"] == 0)
+    # alpha clamped at the centre by a hair: its power/opacity terms there are
+    # zero in the FP64 adjoint but bounded by their unclamped magnitude
+    out = _one_tile([u], [v], [0.02], [0.0], [0.02], [0.99 * (1 + 1e-7)], [[0.2, 0.5, 1.0]],
+                    dC=np.ones((256, 3)), dT=np.zeros(256))
+    assert out["flags"][p] & 2
+    assert out["g2d_amb"][0, 5] > 0 and out["g2d_amb"][0, 0:5].sum() >= 0
