@@ -31,12 +31,15 @@
  * Decisions within ambig_rel (relative) of a threshold may be taken the other
  * way by an FP32 implementation.  Such a pixel is flagged, and so is the
  * Gaussian that decides it (gflags bit 0).  Into g2d_amb / fsum_amb /
- * wsum_amb go the magnitudes of everything the other decision could change:
- * every contributor's terms from that pixel, and the terms the decider would
- * add if it were blended (its w = alpha T at the decision, with the pixel's
- * whole suffix magnitude for its S).  An alpha near the 0.99 clamp only
- * switches that Gaussian's power/opacity terms in that pixel; their unclamped
- * magnitudes go to g2d_amb as well.
+ * wsum_amb go the magnitudes of everything the other decision could change,
+ * to first order: the terms the deciding Gaussian would add if it were blended
+ * (its w = alpha T at the decision, with the pixel's whole suffix magnitude
+ * for its S); for every contributor, the blends of deciders behind it in its
+ * S, and a fraction q of its own terms, q = sum over deciders of
+ * alpha / (1 - alpha) (skip rule: later transmittances scale by 1 - alpha) or
+ * 1 (stop rule: the final transmittance may change entirely), at most 1.  An
+ * alpha near the 0.99 clamp only switches that Gaussian's power/opacity terms
+ * in that pixel; their unclamped magnitudes go to g2d_amb as well.
  */
 #include <math.h>
 #include <stdint.h>
@@ -94,15 +97,18 @@ typedef struct {
 } oracle_args;
 
 typedef struct {
-    int64_t g;
+    int64_t g, pos;
     double alpha, T, G, dx, dy;
     int clamped, near_clamp;
 } blend_rec;
 
-/* a near-threshold decision: the deciding Gaussian and its state there */
+/* a near-threshold decision: the deciding Gaussian, its list position, its
+   state there, and whether it is the stop rule (else the skip rule) */
 typedef struct {
-    int64_t g;
+    int64_t g, pos;
     double alpha, T, G, dx, dy;
+    int stop;
+    double gkm;      /* magnitude of its g_k in this pixel (filled by the adjoint) */
 } amb_rec;
 
 static void atomic_add(double *p, double x) {
@@ -150,13 +156,13 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 if (near_rel(raw, ALPHA_MAX, a->ambig_rel)) flags |= 2;
                 if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = (amb_rec){g, alpha, T, G, dx, dy};
+                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, 0, 0.0};
                 }
                 if (alpha < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - alpha);
                 if (near_rel(Tn, T_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = (amb_rec){g, alpha, T, G, dx, dy};
+                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, 1, 0.0};
                 }
                 if (Tn < T_MIN) break;
                 const double w = alpha * T;
@@ -169,7 +175,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 if (Fm && a->feat)
                     for (int64_t k = 0; k < d; ++k) Fm[k] += w * fabs(a->feat[g * d + k]);
                 blend_rec *r = &recs[nrec++];
-                r->g = g; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
+                r->g = g; r->pos = pos; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
                 r->clamped = raw >= ALPHA_MAX;
                 r->near_clamp = near_rel(raw, ALPHA_MAX, a->ambig_rel);
                 T = Tn;
@@ -200,6 +206,23 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             const double *tgt = a->target ? a->target + pix * d : NULL;
             const double Tfin = T;
             double S = 0.0, Sm = 0.0;
+            /* another skip decision by decider j scales every later T (and T_final)
+               by (1 - alpha_j), i.e. changes them by at most alpha_j / (1 - alpha_j)
+               relative; another stop decision changes T_final by up to 100%; q is
+               the sum over the pixel's deciders (at most 1) */
+            double q = 0.0;
+            if (flags & 1) {
+                for (int64_t i = 0; i < namb; ++i) {
+                    amb_rec *e = &amb[i];
+                    q += e->stop ? 1.0 : e->alpha / (1.0 - e->alpha);
+                    double gkm = 0.0;
+                    for (int c = 0; c < 3; ++c) gkm += rgbm(a, e->g, c) * fabs(dC[c]);
+                    if (dF)
+                        for (int64_t k = 0; k < d; ++k) gkm += fabs(a->feat[e->g * d + k] * dF[k]);
+                    e->gkm = gkm;
+                }
+                if (q > 1.0) q = 1.0;
+            }
             for (int64_t i = nrec - 1; i >= 0; --i) {
                 const blend_rec *r = &recs[i];
                 const int64_t g = r->g;
@@ -249,12 +272,21 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     for (int k = 0; k < 9; ++k) atomic_add(&a->g2d[9 * g + k], gvec[k]);
                 if (a->g2d_mag)
                     for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_mag[9 * g + k], gmag[k]);
-                /* a decision that may go the other way in FP32 changes this pixel's
-                   terms for every contributor (ambiguous pixel), or switches this
-                   Gaussian's alpha between clamped and not (near the clamp): record
-                   the magnitude of the terms it can change, unclamped */
+                /* what a decision taken the other way in FP32 can change in this
+                   contributor's terms: in an ambiguous pixel, q of its dL/dalpha
+                   magnitude plus the blend each decider behind it would add to its
+                   S, and q of its colour terms; near the clamp, its unclamped
+                   power/opacity terms */
                 if (a->g2d_amb && ((flags & 1) || r->near_clamp)) {
-                    const double um = dalpham * r->alpha, om = dalpham * r->G;
+                    double damb = 0.0;
+                    if (flags & 1) {
+                        double extra = 0.0;
+                        for (int64_t j = 0; j < namb; ++j)
+                            if (amb[j].pos > r->pos) extra += amb[j].alpha * amb[j].T * amb[j].gkm;
+                        damb += q * dalpham + extra * inv1ma;
+                    }
+                    if (r->near_clamp) damb += dalpham;
+                    const double um = damb * r->alpha, om = damb * r->G;
                     double am[9];
                     am[0] = um * (fabs(A * dx) + fabs(B * dy));
                     am[1] = um * (fabs(B * dx) + fabs(Cc * dy));
@@ -262,7 +294,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     am[3] = um * fabs(dx * dy);
                     am[4] = um * 0.5 * dy * dy;
                     am[5] = om;
-                    for (int c = 0; c < 3; ++c) am[6 + c] = (flags & 1) ? gmag[6 + c] : 0.0;
+                    for (int c = 0; c < 3; ++c) am[6 + c] = (flags & 1) ? q * gmag[6 + c] : 0.0;
                     for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_amb[9 * g + k], am[k]);
                 }
                 if (a->dfeat && dF)
@@ -275,8 +307,8 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     if (a->wsum) atomic_add(&a->wsum[g], w);
                     if (flags & 1) {
                         if (a->fsum_amb)
-                            for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_amb[g * d + k], fabs(w * tgt[k]));
-                        if (a->wsum_amb) atomic_add(&a->wsum_amb[g], w);
+                            for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_amb[g * d + k], q * fabs(w * tgt[k]));
+                        if (a->wsum_amb) atomic_add(&a->wsum_amb[g], q * w);
                     }
                 }
             }
@@ -286,10 +318,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             for (int64_t i = 0; i < namb; ++i) {
                 const amb_rec *e = &amb[i];
                 const int64_t g = e->g;
-                double gkm = 0.0;
-                for (int c = 0; c < 3; ++c) gkm += rgbm(a, g, c) * fabs(dC[c]);
-                if (dF)
-                    for (int64_t k = 0; k < d; ++k) gkm += fabs(a->feat[g * d + k] * dF[k]);
+                const double gkm = e->gkm;
                 const double w = e->alpha * e->T;
                 const double dalpham = e->T * gkm + (Sm + Tfin * fabs(dT)) / (1.0 - e->alpha);
                 const double um = dalpham * e->alpha, om = dalpham * e->G;

@@ -16,7 +16,6 @@ namespace fh {
 
 constexpr uint32_t LONG_GEOM = 64;    // visits above which a rank goes to the workgroup reduction
 constexpr uint32_t LONG_FUSE = 32;    // same for fusion (per Gaussian, all views)
-constexpr int MAXC = 16;              // feature channels per lane (d <= 1024)
 
 __device__ __forceinline__ uint32_t rank_of_inst(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
                                                  int packed) {
@@ -120,8 +119,61 @@ __global__ __launch_bounds__(256) void k_reduce_geom_long(ReduceArgs a) {
     }
 }
 
+// The visits of one wavefront, in its fixed order, Neumaier-added into the
+// lane's channels c = lane + 64 m (m < NC) and the weight pair.  `stride` and
+// `phase` select the wavefront's share: positions phase, phase + stride, ... of
+// the concatenation of the per-view segments (views ascending).  Loads are
+// issued B visits at a time (visit indices first, then their rows), and the
+// additions then run in visit order, so batching changes no result.
+template <int NC, int B>
+__device__ __forceinline__ void accumulate_visits(const ReduceArgs& a, int64_t g, int lane, uint32_t stride,
+                                                  uint32_t phase, float* sm, float* cp, float& ws, float& wc) {
+    const int D = a.d;
+    uint32_t off = 0;   // visits of earlier views
+    for (int v = 0; v < a.n_views; ++v) {
+        const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
+        const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
+        // first k in [b0, b1) whose position in the concatenation is phase mod stride
+        const uint32_t first = b0 + (phase + stride - off % stride) % stride;
+        for (uint32_t k0 = first; k0 < b1; k0 += stride * B) {
+            // visit indices of the batch: lane l < B loads the l-th
+            int64_t my = -1;
+            float myw = 0.0f;
+            if (lane < B) {
+                const uint32_t k = k0 + stride * (uint32_t)lane;
+                if (k < b1) {
+                    my = a.vsorted[k];
+                    myw = a.part_geom[my * 12 + 9];
+                }
+            }
+            float rows[B][NC];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int64_t idx = __shfl(my, b, 64);
+#pragma unroll
+                for (int m = 0; m < NC; ++m) {
+                    const int c = lane + 64 * m;
+                    rows[b][m] = (idx >= 0 && c < D) ? a.part_fuse[idx * D + c] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int64_t idx = __shfl(my, b, 64);
+                const float wb = __shfl(myw, b, 64);
+                if (idx >= 0) {
+#pragma unroll
+                    for (int m = 0; m < NC; ++m) neumaier_add(sm[m], cp[m], rows[b][m]);
+                    neumaier_add(ws, wc, wb);
+                }
+            }
+        }
+        off += b1 - b0;
+    }
+}
+
 // One wavefront per Gaussian: Neumaier-add its partials of every view, views
 // ascending and tiles row-major, into the persistent accumulators.
+template <int NC, int B>
 __global__ __launch_bounds__(256) void k_reduce_fuse(ReduceArgs a) {
     const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -141,29 +193,17 @@ __global__ __launch_bounds__(256) void k_reduce_fuse(ReduceArgs a) {
         return;
     }
     const int D = a.d;
-    float sm[MAXC], cp[MAXC];
+    float sm[NC], cp[NC];
 #pragma unroll
-    for (int m = 0; m < MAXC; ++m) {
+    for (int m = 0; m < NC; ++m) {
         const int c = lane + 64 * m;
         sm[m] = c < D ? a.acc_sum[g * D + c] : 0.0f;
         cp[m] = c < D ? a.acc_comp[g * D + c] : 0.0f;
     }
     float ws = a.acc_wsum[g], wc = a.acc_wcomp[g];
-    for (int v = 0; v < a.n_views; ++v) {
-        const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
-        const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
-        for (uint32_t k = b0; k < b1; ++k) {
-            const int64_t idx = a.vsorted[k];
+    accumulate_visits<NC, B>(a, g, lane, 1u, 0u, sm, cp, ws, wc);
 #pragma unroll
-            for (int m = 0; m < MAXC; ++m) {
-                const int c = lane + 64 * m;
-                if (c < D) neumaier_add(sm[m], cp[m], a.part_fuse[idx * D + c]);
-            }
-            neumaier_add(ws, wc, a.part_geom[idx * 12 + 9]);
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < MAXC; ++m) {
+    for (int m = 0; m < NC; ++m) {
         const int c = lane + 64 * m;
         if (c < D) {
             a.acc_sum[g * D + c] = sm[m];
@@ -179,6 +219,7 @@ __global__ __launch_bounds__(256) void k_reduce_fuse(ReduceArgs a) {
 // One 1024-thread workgroup per long Gaussian: wave w takes every 16th visit
 // of the concatenated per-view segments, keeping its own compensated sums;
 // the 16 waves are then added into the accumulators in wave order.
+template <int NC, int B>
 __global__ __launch_bounds__(1024) void k_reduce_fuse_long(ReduceArgs a) {
     extern __shared__ float sred[];   // [16][2][d] then [16][2] for the weights
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
@@ -188,29 +229,13 @@ __global__ __launch_bounds__(1024) void k_reduce_fuse_long(ReduceArgs a) {
     float* sw = sred + 16 * 2 * D;
     for (uint32_t li = blockIdx.x; li < nlong; li += gridDim.x) {
         const int64_t g = a.long_list[a.total + li];
-        float sm[MAXC], cp[MAXC];
+        float sm[NC], cp[NC];
 #pragma unroll
-        for (int m = 0; m < MAXC; ++m) sm[m] = cp[m] = 0.0f;
+        for (int m = 0; m < NC; ++m) sm[m] = cp[m] = 0.0f;
         float ws = 0.0f, wc = 0.0f;
-        uint32_t off = 0;   // visits of earlier views
-        for (int v = 0; v < a.n_views; ++v) {
-            const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
-            const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
-            // first k in [b0, b1) with (off + k - b0) % 16 == w
-            const uint32_t first = b0 + (uint32_t)((w - (int)(off % 16u) + 16) % 16);
-            for (uint32_t k = first; k < b1; k += 16) {
-                const int64_t idx = a.vsorted[k];
+        accumulate_visits<NC, B>(a, g, lane, 16u, (uint32_t)w, sm, cp, ws, wc);
 #pragma unroll
-                for (int m = 0; m < MAXC; ++m) {
-                    const int c = lane + 64 * m;
-                    if (c < D) neumaier_add(sm[m], cp[m], a.part_fuse[idx * D + c]);
-                }
-                neumaier_add(ws, wc, a.part_geom[idx * 12 + 9]);
-            }
-            off += b1 - b0;
-        }
-#pragma unroll
-        for (int m = 0; m < MAXC; ++m) {
+        for (int m = 0; m < NC; ++m) {
             const int c = lane + 64 * m;
             if (c < D) {
                 sred[(w * 2) * D + c] = sm[m];
@@ -260,10 +285,21 @@ void launch_reduce_geom(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_geom_long, dim3(512), dim3(256), 0, s, a);
 }
 
-void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_fuse, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
+template <int NC, int B>
+static void launch_reduce_fuse_nc(const ReduceArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_fuse<NC, B>), dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
     const size_t lds = sizeof(float) * (16 * 2 * (size_t)a.d + 32);
-    hipLaunchKernelGGL(k_reduce_fuse_long, dim3(256), dim3(1024), lds, s, a);
+    hipLaunchKernelGGL((k_reduce_fuse_long<NC, B>), dim3(256), dim3(1024), lds, s, a);
+}
+
+// channels per lane NC = ceil(d / 64); visits per batch B keep B * NC <= 32 registers of rows
+void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s) {
+    const int nc = (a.d + 63) / 64;
+    if (nc <= 1) launch_reduce_fuse_nc<1, 8>(a, s);
+    else if (nc <= 2) launch_reduce_fuse_nc<2, 8>(a, s);
+    else if (nc <= 4) launch_reduce_fuse_nc<4, 8>(a, s);
+    else if (nc <= 8) launch_reduce_fuse_nc<8, 4>(a, s);
+    else launch_reduce_fuse_nc<16, 2>(a, s);
 }
 
 }  // namespace fh

@@ -29,12 +29,41 @@ __device__ __forceinline__ uint32_t rank_at(const uint32_t* keys, const uint32_t
     return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
 }
 
+// Chunk records are fetched two chunks ahead (threads 0..31, into registers)
+// and chunk features one chunk ahead (every thread, into registers), both
+// double-buffered in LDS, so their global latency overlaps the current chunk's
+// alpha walk and MFMA work.
+struct RecFetch {
+    Rec r;
+    uint32_t g;
+};
+
+__device__ __forceinline__ RecFetch fetch_rec(const RenderArgs& a, int v, uint32_t base, uint32_t e, int k) {
+    RecFetch f;
+    const uint32_t i = base + (uint32_t)k;
+    if (i < e) {
+        f.g = a.order[rank_at(a.keys, a.vals, (int64_t)i, a.rank_bits, a.packed)];
+        const int64_t ri = ((int64_t)v * a.n + f.g) * 3;
+        f.r.r0 = a.rec[ri];
+        f.r.r1 = a.rec[ri + 1];
+        f.r.r2 = a.rec[ri + 2];
+    } else {
+        // padding: opacity 0 never blends
+        f.g = 0xFFFFFFFFu;
+        f.r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        f.r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+        f.r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return f;
+}
+
 template <int DS>
 __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
-    __shared__ Rec srec[FK];
-    __shared__ uint32_t sg[FK];
-    __shared__ __attribute__((aligned(16))) __bf16 sft[DS * FKP];
+    constexpr int NIT = (FK * (DS / 8) + 1023) / 1024;   // feature items per thread
+    __shared__ Rec srec[2][FK];
+    __shared__ uint32_t sg[2][FK];
+    __shared__ __attribute__((aligned(16))) __bf16 sft[2][DS * FKP];
     __shared__ uint32_t smax[16];
     if (a.counters->inst_overflow) return;
     const int t = blockIdx.x, slice = blockIdx.y, d0 = slice * DS;
@@ -49,6 +78,50 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
     const uint32_t s = a.ranges[2 * t], e = a.ranges[2 * t + 1];
     const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
 
+    // feature items of one chunk: item = k + FK * dg, 8 channels each
+    auto load_feats = [&](const uint32_t* gl, uint4* fr) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = (int)threadIdx.x + 1024 * it;
+            fr[it] = make_uint4(0, 0, 0, 0);
+            if (idx < FK * (DS / 8)) {
+                const int k = idx % FK, dg = idx / FK;
+                const uint32_t g = gl[k];
+                if (g != 0xFFFFFFFFu) fr[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)g * a.d + d0 + dg * 8);
+            }
+        }
+    };
+    auto store_feats = [&](const uint4* fr, __bf16* dstb) {
+        uint16_t* dst = reinterpret_cast<uint16_t*>(dstb);
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = (int)threadIdx.x + 1024 * it;
+            if (idx < FK * (DS / 8)) {
+                const int k = idx % FK, dg = idx / FK;
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&fr[it]);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + k] = h[m];
+            }
+        }
+    };
+
+    // prologue: chunk 0 into buffer 0, chunk 1's records into registers and its g into sg[1]
+    RecFetch nxt;
+    if (threadIdx.x < FK) {
+        const RecFetch f0 = fetch_rec(a, v, s, e, threadIdx.x);
+        srec[0][threadIdx.x] = f0.r;
+        sg[0][threadIdx.x] = f0.g;
+        nxt = fetch_rec(a, v, s + FK, e, threadIdx.x);
+        sg[1][threadIdx.x] = nxt.g;
+    }
+    __syncthreads();
+    {
+        uint4 fr[NIT];
+        load_feats(sg[0], fr);
+        store_feats(fr, sft[0]);
+    }
+    __syncthreads();
+
     f32x4 acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -56,45 +129,24 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
     bool done = !inside;
     uint32_t last = 0;
 
-    for (uint32_t base = s; base < e; base += FK) {
-        const int cnt = (e - base) < (uint32_t)FK ? (int)(e - base) : FK;
+    int b = 0;
+    for (uint32_t base = s; base < e; base += FK, b ^= 1) {
+        const int nb = b ^ 1;
+        // chunk c+1's records to LDS; chunk c+2's records and chunk c+1's features in flight
+        RecFetch nxt2;
         if (threadIdx.x < FK) {
-            if ((int)threadIdx.x < cnt) {
-                const int64_t i = (int64_t)base + threadIdx.x;
-                const uint32_t g = a.order[rank_at(a.keys, a.vals, i, a.rank_bits, a.packed)];
-                const int64_t ri = ((int64_t)v * a.n + g) * 3;
-                srec[threadIdx.x].r0 = a.rec[ri];
-                srec[threadIdx.x].r1 = a.rec[ri + 1];
-                srec[threadIdx.x].r2 = a.rec[ri + 2];
-                sg[threadIdx.x] = g;
-            } else {
-                // padding: opacity 0 never blends
-                srec[threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-                srec[threadIdx.x].r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-                srec[threadIdx.x].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-                sg[threadIdx.x] = 0xFFFFFFFFu;
-            }
+            srec[nb][threadIdx.x] = nxt.r;
+            nxt2 = fetch_rec(a, v, base + 2 * FK, e, threadIdx.x);
         }
-        __syncthreads();
-        // transposed feature tile sft[d][k] for this chunk and channel slice
-        for (int idx = threadIdx.x; idx < FK * (DS / 8); idx += 1024) {
-            const int k = idx % FK, dg = idx / FK;
-            const uint32_t g = sg[k];
-            uint4 raw = make_uint4(0, 0, 0, 0);
-            if (g != 0xFFFFFFFFu) raw = *reinterpret_cast<const uint4*>(feat + (int64_t)g * a.d + d0 + dg * 8);
-            const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw);
-            uint16_t* dst = reinterpret_cast<uint16_t*>(sft);
-#pragma unroll
-            for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + k] = h[m];
-        }
-        __syncthreads();
+        uint4 fr[NIT];
+        load_feats(sg[nb], fr);
 
         // alpha of this lane's eight Gaussians and their transmittance product
         float al[8];
         float P = 1.0f;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const AlphaEval ae = eval_alpha(srec[8 * q + m], x, y);
+            const AlphaEval ae = eval_alpha(srec[b][8 * q + m], x, y);
             al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
             P *= (1.0f - al[m]);
         }
@@ -116,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
                     term = true;
                 } else {
                     wv = al[m] * Tl;
-                    const Rec& r = srec[8 * q + m];
+                    const Rec& r = srec[b][8 * q + m];
                     c0 += wv * r.r2.y;
                     c1 += wv * r.r2.z;
                     c2 += wv * r.r2.w;
@@ -146,9 +198,15 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
         // W times the feature chunk
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sft[(j * 16 + xi) * FKP + 8 * q]);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, b, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[j], 0, 0, 0);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sft[b][(j * 16 + xi) * FKP + 8 * q]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv, acc[j], 0, 0, 0);
+        }
+        // chunk c+1's features to LDS; chunk c+2's g for the next prefetch
+        store_feats(fr, sft[nb]);
+        if (threadIdx.x < FK) {
+            sg[b][threadIdx.x] = nxt2.g;
+            nxt = nxt2;
         }
         if (__syncthreads_count(!done) == 0) break;
     }
