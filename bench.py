@@ -74,10 +74,23 @@ def alg_bytes(kernel: str, wl, P: int, n_vis: int, n_inst: int, feat_b: int, tgt
     raise ValueError(kernel)
 
 
-def kernel_src_digest() -> str:
+# the source files that define each bracket's kernels (plus the shared headers)
+BRACKET_SOURCES = {
+    ("project", "f32"): ("project.hip",), ("project", "bf16"): ("project.hip",),
+    ("render_fwd", "f32"): ("render_f32.hip",), ("render_fwd", "bf16"): ("render_bf16.hip",),
+    ("render_bwd", "f32"): ("render_f32.hip",), ("render_bwd", "bf16"): ("render_bwd_bf16.hip",),
+    ("project_bwd", "f32"): ("project.hip",), ("project_bwd", "bf16"): ("project.hip",),
+}
+
+
+def kernel_src_digest(kernel: str, form: str) -> str:
+    """Digest of the sources of one bracket's kernels (all kernel sources when
+    the bracket has no entry)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2505_19154_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    files = BRACKET_SOURCES.get((kernel, form))
+    names = sorted(os.listdir(csrc)) if files is None else sorted(("common.hpp", "kernels.hpp") + files)
+    for f in names:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -136,7 +149,7 @@ def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, for
                             per_kernel={k: sum(v) / len(v) for k, v in per_kernel.items()},
                             dispatches={k: len(v) for k, v in per_kernel.items()})
     hbm = sum(out[c]["kib_per_launch"] * 1024.0 * out[c]["scale"] for c in out)
-    res = dict(kernel=kernel, workload=workload, form=form, kernel_src_digest=kernel_src_digest(),
+    res = dict(kernel=kernel, workload=workload, form=form, kernel_src_digest=kernel_src_digest(kernel, form),
                hbm_bytes_per_launch=hbm, counters=out, command=command,
                note="FETCH_SIZE and WRITE_SIZE from separate rocprofv3 --pmc runs, KiB per dispatch averaged over "
                     "dispatches and summed over the kernels of the bracket; each scaled by calibration bytes / "
@@ -155,7 +168,7 @@ def measured_traffic(kernel: str, workload: str, form: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_src_digest") != kernel_src_digest():
+    if t.get("kernel_src_digest") != kernel_src_digest(kernel, form):
         return None
     return float(t["hbm_bytes_per_launch"])
 
