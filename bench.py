@@ -322,8 +322,7 @@ def main():
             raise RuntimeError("capacity overflow during the timed steps")
         blends = int(img.n_iter.to(torch.int64).sum().item())
         print(f"[bench] {form_name}: {ms:.3f} ms/step, {kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
-        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends,
-                    tuning=tuning or {"fwd_slice": int(r.plan.tuning.fwd_slice), "bwd_chunk": int(r.plan.tuning.bwd_chunk)})
+        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends, tuning=tuning or r.tuning_dict())
 
     other = {"bf16": "f32", "f32": "bf16"}[form]
     res_other = None

@@ -101,8 +101,11 @@ typedef struct {
  * order for every setting.
  *   fwd_slice  channels per forward workgroup (the feature dimension is cut
  *              into ceil(d / fwd_slice) slices, each re-walking the tile).
- *              FP32 form: 8, 16, 32 or 64.  BF16 form: 32, 64, 96 or 128,
- *              dividing d.  0 when d == 0.
+ *              FP32 form: 8, 16, 32 or 64.  BF16 form: dividing d, and 32,
+ *              64, 96 or 128 with fwd_rows 16, or 64, 128 or 256 with
+ *              fwd_rows 8.  0 when d == 0.
+ *   fwd_rows   pixel rows per forward workgroup (BF16 form: 16, or 8 for two
+ *              workgroups per tile with twice the registers each; FP32 form: 16).
  *   bwd_chunk  Gaussians per back-to-front chunk of the FP32-form adjoint:
  *              16 or 32 (32 needs d <= 512).  The BF16-form adjoint always
  *              takes 32 (the MFMA k).
@@ -110,7 +113,8 @@ typedef struct {
 typedef struct {
     int32_t fwd_slice;
     int32_t bwd_chunk;
-    int32_t reserved[2];
+    int32_t fwd_rows;
+    int32_t reserved;
 } fh_tuning;
 
 /* Host-side description of one batch of views: sizes, capacities and the
@@ -266,7 +270,8 @@ fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **p
  * (host array) and their number into *count (host).  Each differs from
  * plan->tuning in the field that the kernel `which` uses (FH_K_RENDER_FWD:
  * fwd_slice; FH_K_RENDER_BWD: bwd_chunk); for other kernels, or when only one
- * setting is valid, the one entry is plan->tuning.  Host only. */
+ * setting is valid, the one entry is plan->tuning.  For FH_K_RENDER_FWD the
+ * entries differ in fwd_slice and fwd_rows.  Host only. */
 fh_status fh_tuning_candidates(const fh_plan *plan, int32_t which, fh_tuning *out, int32_t max, int32_t *count);
 
 /* Autotuner (the batched form picks its launch shape on the real workload):

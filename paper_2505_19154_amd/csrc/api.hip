@@ -125,26 +125,33 @@ static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
 static fh_tuning default_tuning(int d, int form) {
     fh_tuning t;
     memset(&t, 0, sizeof(t));
+    t.fwd_rows = 16;
     if (d > 0) {
-        if (form == FH_FORM_BF16)
-            t.fwd_slice = (d == 32 || d == 64 || d == 96) ? d : 128;
-        else
+        if (form == FH_FORM_BF16) {
+            if (d == 32 || d == 64 || d == 96) {
+                t.fwd_slice = d;
+            } else {
+                t.fwd_slice = d % 256 == 0 ? 256 : 128;
+                t.fwd_rows = 8;
+            }
+        } else {
             t.fwd_slice = d <= 8 ? 8 : (d <= 16 ? 16 : (d <= 32 ? 32 : 64));
+        }
     }
     t.bwd_chunk = d <= 512 ? 32 : 16;
     return t;
 }
 
-static bool fwd_slice_ok(int d, int form, int slice) {
-    if (d == 0) return slice == 0;
-    if (form == FH_FORM_BF16) return (slice == 32 || slice == 64 || slice == 96 || slice == 128) && d % slice == 0;
-    return slice == 8 || slice == 16 || slice == 32 || slice == 64;
+static bool fwd_shape_ok(int d, int form, int slice, int rows) {
+    if (d == 0) return slice == 0 && rows == 16;
+    if (form == FH_FORM_BF16) return render_fwd_bf16_shape_ok(d, slice, rows);
+    return rows == 16 && (slice == 8 || slice == 16 || slice == 32 || slice == 64);
 }
 
 static bool bwd_chunk_ok(int d, int chunk) { return chunk == 16 || (chunk == 32 && d <= 512); }
 
 static bool tuning_ok(const fh_plan* p) {
-    return fwd_slice_ok(p->d, p->form, p->tuning.fwd_slice) && bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
+    return fwd_shape_ok(p->d, p->form, p->tuning.fwd_slice, p->tuning.fwd_rows) && bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
 }
 
 // depth sort, tiles per rank, their scan, the instance count and the overflow flag
@@ -353,10 +360,12 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.n_iter = out->n_iter;
     uint32_t* tile_niter = buf<uint32_t>(p, ws, WS_TILE_NITER);
     a.tile_niter = tile_niter;
+    // several row groups of a tile combine their traversal lengths with atomicMax
+    launch_fill_u32(tile_niter, p->n_tiles, 0u, s);
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_FWD, s);
     if (p->form == FH_FORM_BF16)
-        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
+        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, s);
     else
         launch_render_fwd_f32(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
     prof_end(FH_K_RENDER_FWD, s);
@@ -529,12 +538,14 @@ fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, 
     if (!p || !out || !count || max < 1) return FH_E_INVALID;
     int n = 0;
     if (which == FH_K_RENDER_FWD && p->d > 0) {
-        static const int slices[] = {8, 16, 32, 64, 96, 128};
-        for (int sl : slices)
-            if (fwd_slice_ok(p->d, p->form, sl) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
-                out[n] = p->tuning;
-                out[n++].fwd_slice = sl;
-            }
+        static const int slices[] = {8, 16, 32, 64, 96, 128, 256};
+        for (int rows : {16, 8})
+            for (int sl : slices)
+                if (fwd_shape_ok(p->d, p->form, sl, rows) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
+                    out[n] = p->tuning;
+                    out[n].fwd_slice = sl;
+                    out[n++].fwd_rows = rows;
+                }
     } else if (which == FH_K_RENDER_BWD && p->form == FH_FORM_F32) {
         static const int chunks[] = {16, 32};
         for (int ch : chunks)
@@ -555,11 +566,11 @@ fh_status fh_autotune(fh_plan* p, const fh_gaussians* g, void* ws, const fh_imag
                       const void* target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* grads,
                       int32_t reps, hipStream_t s) {
     if (!p || !ws || !fwd || reps < 1) return FH_E_INVALID;
-    fh_tuning cand[8];
+    fh_tuning cand[16];
     int32_t nc = 0;
     for (int which : {(int)FH_K_RENDER_FWD, (int)FH_K_RENDER_BWD}) {
         if (which == FH_K_RENDER_BWD && (!up || !grads)) break;
-        fh_status st = fh_tuning_candidates(p, which, cand, 8, &nc);
+        fh_status st = fh_tuning_candidates(p, which, cand, 16, &nc);
         if (st != FH_OK) return st;
         if (nc < 2) continue;
         int best = -1;

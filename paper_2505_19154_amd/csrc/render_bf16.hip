@@ -7,9 +7,12 @@
 // bits of w; the features are BF16 already.  Everything else (alpha, the
 // transmittance walk, colour) stays on the VALU in FP32.
 //
-// Work mapping: one 1024-thread workgroup per (tile, channel slice); wave w is
-// pixel row w of the 16x16 tile; lane l handles pixel x = l % 16 and Gaussians
-// 8 (l / 16) .. 8 (l / 16) + 7 of each 32-Gaussian chunk.  The lane's eight
+// Work mapping: one workgroup per (tile, group of ROWS pixel rows, channel
+// slice of DS); wave w is pixel row w of its group; lane l handles pixel
+// x = l % 16 and Gaussians 8 (l / 16) .. 8 (l / 16) + 7 of each 32-Gaussian
+// chunk.  The F accumulator takes DS / 4 registers per lane whatever ROWS is,
+// so 8-row (512-thread) workgroups, with twice the register budget of 16-row
+// ones, carry 256 channels and evaluate alpha once per pixel and Gaussian.  The lane's eight
 // weights are exactly its MFMA A-operand (rows = pixels, k = Gaussians).  The
 // four lanes of a pixel combine their transmittance with an exclusive product
 // scan, which reproduces the sequential walk (skip rule, stop rule) up to
@@ -57,22 +60,24 @@ __device__ __forceinline__ RecFetch fetch_rec(const RenderArgs& a, int v, uint32
     return f;
 }
 
-template <int DS>
-__global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
+template <int DS, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
-    constexpr int NIT = (FK * (DS / 8) + 1023) / 1024;   // feature items per thread
+    constexpr int NT = 64 * ROWS;                        // threads
+    constexpr int NIT = (FK * (DS / 8) + NT - 1) / NT;   // feature items per thread
     __shared__ Rec srec[2][FK];
     __shared__ uint32_t sg[2][FK];
     __shared__ __attribute__((aligned(16))) __bf16 sft[2][DS * FKP];
-    __shared__ uint32_t smax[16];
+    __shared__ uint32_t smax[ROWS];
     if (a.counters->inst_overflow) return;
-    const int t = blockIdx.x, slice = blockIdx.y, d0 = slice * DS;
+    constexpr int NG = TILE / ROWS;                      // row groups per tile
+    const int t = blockIdx.x, grp = blockIdx.y % NG, slice = blockIdx.y / NG, d0 = slice * DS;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q = lane >> 4, xi = lane & 15;
     const int v = view_of_tile(vt, t);
     const int lt = t - vt.tile_off[v];
     const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
-    const int px = tx * TILE + xi, py = ty * TILE + w;
+    const int px = tx * TILE + xi, py = ty * TILE + grp * ROWS + w;
     const bool inside = px < vt.width[v] && py < vt.height[v];
     const float x = (float)px + 0.5f, y = (float)py + 0.5f;
     const uint32_t s = a.ranges[2 * t], e = a.ranges[2 * t + 1];
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
     auto load_feats = [&](const uint32_t* gl, uint4* fr) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int idx = (int)threadIdx.x + 1024 * it;
+            const int idx = (int)threadIdx.x + NT * it;
             fr[it] = make_uint4(0, 0, 0, 0);
             if (idx < FK * (DS / 8)) {
                 const int k = idx % FK, dg = idx / FK;
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
         uint16_t* dst = reinterpret_cast<uint16_t*>(dstb);
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int idx = (int)threadIdx.x + 1024 * it;
+            const int idx = (int)threadIdx.x + NT * it;
             if (idx < FK * (DS / 8)) {
                 const int k = idx % FK, dg = idx / FK;
                 const uint16_t* h = reinterpret_cast<const uint16_t*>(&fr[it]);
@@ -240,24 +245,45 @@ __global__ __launch_bounds__(1024) void k_render_fwd_bf16(RenderArgs a, ViewTabl
         }
     }
     if (slice == 0) {
+        // the tile's traversal length: max over its row groups (tile_niter is
+        // zeroed before the launch)
         const uint32_t m = wave_max_u32(last);
         if (lane == 0) smax[w] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t mm = 0;
-            for (int k = 0; k < 16; ++k) mm = smax[k] > mm ? smax[k] : mm;
-            a.tile_niter[t] = mm;
+            for (int k = 0; k < ROWS; ++k) mm = smax[k] > mm ? smax[k] : mm;
+            if (NG == 1)
+                a.tile_niter[t] = mm;
+            else
+                atomicMax(&a.tile_niter[t], mm);
         }
     }
 }
 
-void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
-    const unsigned ns = (unsigned)(a.d / slice);   // slice divides d (checked by the caller)
+bool render_fwd_bf16_shape_ok(int d, int slice, int rows) {
+    if (rows == 16) return (slice == 32 || slice == 64 || slice == 96 || slice == 128) && d % slice == 0;
+    if (rows == 8) return (slice == 64 || slice == 128 || slice == 256) && d % slice == 0;
+    return false;
+}
+
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, hipStream_t s) {
+    // slice and rows form a valid shape for d (checked by the caller)
+    const unsigned ns = (unsigned)(a.d / slice);
+    const dim3 g16(n_tiles, ns), g8(n_tiles, 2 * ns);
+    if (rows == 8) {
+        switch (slice) {
+            case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8>), g8, dim3(512), 0, s, a, vt); break;
+            case 128: hipLaunchKernelGGL((k_render_fwd_bf16<128, 8>), g8, dim3(512), 0, s, a, vt); break;
+            default: hipLaunchKernelGGL((k_render_fwd_bf16<256, 8>), g8, dim3(512), 0, s, a, vt); break;
+        }
+        return;
+    }
     switch (slice) {
-        case 32: hipLaunchKernelGGL(k_render_fwd_bf16<32>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
-        case 64: hipLaunchKernelGGL(k_render_fwd_bf16<64>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
-        case 96: hipLaunchKernelGGL(k_render_fwd_bf16<96>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
-        default: hipLaunchKernelGGL(k_render_fwd_bf16<128>, dim3(n_tiles, ns), dim3(1024), 0, s, a, vt); break;
+        case 32: hipLaunchKernelGGL((k_render_fwd_bf16<32, 16>), g16, dim3(1024), 0, s, a, vt); break;
+        case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 16>), g16, dim3(1024), 0, s, a, vt); break;
+        case 96: hipLaunchKernelGGL((k_render_fwd_bf16<96, 16>), g16, dim3(1024), 0, s, a, vt); break;
+        default: hipLaunchKernelGGL((k_render_fwd_bf16<128, 16>), g16, dim3(1024), 0, s, a, vt); break;
     }
 }
 

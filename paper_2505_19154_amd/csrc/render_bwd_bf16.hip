@@ -347,15 +347,16 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
             }
             const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
                         P3 = __shfl(P, xi + 48, 64);
-            const float Te3 = T, Te2 = Te3 / P3, Te1 = Te2 / P2, Te0 = Te1 / P1;
+            const float Te3 = T, Te2 = Te3 * __builtin_amdgcn_rcpf(P3), Te1 = Te2 * __builtin_amdgcn_rcpf(P2),
+                        Te0 = Te1 * __builtin_amdgcn_rcpf(P1);
             float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
-            T = Te0 / P0;
+            T = Te0 * __builtin_amdgcn_rcpf(P0);
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
                 float wv = 0.0f;
                 if (on[r]) {
-                    const float Tk = Tc / (1.0f - al[r]);
+                    const float Tk = Tc * __builtin_amdgcn_rcpf(1.0f - al[r]);
                     wv = al[r] * Tk;
                     Tc = Tk;
                 }

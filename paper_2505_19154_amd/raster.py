@@ -268,7 +268,7 @@ class Rasterizer:
         (a JSON file) when it holds this tuning_key, else by timing every
         candidate with fh_autotune (after `forward`, with the step's real
         inputs; outputs are recomputed, fusion goes to a scratch accumulator).
-        Returns the chosen {"fwd_slice", "bwd_chunk"}."""
+        Returns the chosen {"fwd_slice", "bwd_chunk", "fwd_rows"}."""
         import json
         import os
         key = self.tuning_key()
@@ -277,7 +277,7 @@ class Rasterizer:
             with open(cache) as f:
                 table = json.load(f)
         if key in table:
-            t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]))
+            t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]), int(table[key]["fwd_rows"]))
         else:
             gs, im = g.struct(), img.struct()
             up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT)) if dC is not None else None
@@ -295,25 +295,30 @@ class Rasterizer:
                     "fh_autotune")
             t = self.plan.tuning
             if cache:
-                table[key] = {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk)}
+                table[key] = {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows)}
                 os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
                 with open(cache, "w") as f:
                     json.dump(table, f, indent=1, sort_keys=True)
-        self.tuning = L.FhTuning(int(t.fwd_slice), int(t.bwd_chunk))
+        self.tuning = L.FhTuning(int(t.fwd_slice), int(t.bwd_chunk), int(t.fwd_rows))
         self.plan.tuning = self.tuning
-        return {"fwd_slice": int(self.tuning.fwd_slice), "bwd_chunk": int(self.tuning.bwd_chunk)}
+        return self.tuning_dict()
 
-    def set_tuning(self, fwd_slice: int, bwd_chunk: int) -> None:
+    def tuning_dict(self) -> dict:
+        t = self.plan.tuning
+        return {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows)}
+
+    def set_tuning(self, fwd_slice: int, bwd_chunk: int, fwd_rows: int = 16) -> None:
         """Set the launch shape by hand (validated by the next call)."""
-        self.tuning = L.FhTuning(int(fwd_slice), int(bwd_chunk))
+        self.tuning = L.FhTuning(int(fwd_slice), int(bwd_chunk), int(fwd_rows))
         self.plan.tuning = self.tuning
 
     def tuning_candidates(self, which: int) -> list:
-        out = (L.FhTuning * 8)()
+        """[(fwd_slice, bwd_chunk, fwd_rows), ...] for kernel `which`."""
+        out = (L.FhTuning * 16)()
         n = ctypes.c_int32()
-        L.check(self.lib.fh_tuning_candidates(ctypes.byref(self.plan), int(which), out, 8, ctypes.byref(n)),
+        L.check(self.lib.fh_tuning_candidates(ctypes.byref(self.plan), int(which), out, 16, ctypes.byref(n)),
                 "fh_tuning_candidates")
-        return [(int(out[i].fwd_slice), int(out[i].bwd_chunk)) for i in range(n.value)]
+        return [(int(out[i].fwd_slice), int(out[i].bwd_chunk), int(out[i].fwd_rows)) for i in range(n.value)]
 
     def forward(self, g: Gaussians, margin: float = 1.05) -> Image:
         """prepare + render_fwd, growing the visit capacity until it fits."""
