@@ -31,6 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;   // positions per chunk
+constexpr int SK = BK + 1;   // padded per-pixel stride of the (pixel, position) LDS arrays
 
 __device__ __forceinline__ uint32_t rank_at_b(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
                                               int packed) {
@@ -62,6 +63,24 @@ __device__ __forceinline__ void stage_records(const BwdArgs& a, int v, uint32_t 
     }
 }
 
+// One chunk record (position cs + k of the tile's list, or padding past cnt).
+__device__ __forceinline__ Rec fetch_record(const BwdArgs& a, int v, uint32_t s, int cs, int cnt, int k) {
+    Rec r;
+    if (k < cnt) {
+        const int64_t i = (int64_t)s + cs + k;
+        const uint32_t g = a.order[rank_at_b(a.keys, a.vals, i, a.rank_bits, a.packed)];
+        const int64_t ri = ((int64_t)v * a.n + g) * 3;
+        r.r0 = a.rec[ri];
+        r.r1 = a.rec[ri + 1];
+        r.r2 = a.rec[ri + 2];
+    } else {
+        r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+        r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Gradient kernel.  512 threads (8 waves; 256 VGPRs per lane so that dF (hi and
 // lo) stays resident); wave w owns pixel rows 2w and 2w + 1; lane (xi, q) = pixel x = xi
@@ -72,9 +91,12 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     constexpr int NS = D / 32;           // MFMA steps over channels
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16* sfeat = reinterpret_cast<__bf16*>(smem);                         // [BK][DP]
-    float* sw = reinterpret_cast<float*>(sfeat + BK * DP);                   // [BK][256] w
-    float* sdp = sw + BK * TILE_PIX;                                         // [BK][256] dL/dpower
-    float* sdc = sdp + BK * TILE_PIX;                                        // [256][3] dC of the tile
+    // per (pixel, position) values, pixel-major with a padded stride SK so that
+    // the walk's stores and the Gaussian-parallel reads spread over the banks
+    float* sw = reinterpret_cast<float*>(sfeat + BK * DP);                   // [256][SK] w
+    float* sdp = sw + TILE_PIX * SK;                                         // [256][SK] dL/dpower
+    float* sdc = sdp + TILE_PIX * SK;                                        // [256][3] dC of the tile
+    float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][10][BK] partial sums
     __shared__ Rec srec[BK];
     __shared__ uint32_t sg[BK];
 
@@ -97,7 +119,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     const float x = (float)px + 0.5f;
 
     // per-pixel state of this lane's two pixels (identical in the pixel's four lanes)
-    float T[2], S[2], Tfin[2], dTp[2], dCp[2][3];
+    float T[2], S[2], TdT[2], dCp[2][3];     // TdT = T_final dT
     uint32_t nit[2];
     bf16x8 dfh[2][NS], dfl[2][NS];     // dF = hi + lo, both BF16
 #pragma unroll
@@ -107,7 +129,6 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         const int64_t p = vt.pix_off[v] + (int64_t)py * W + px;
         nit[h] = inside ? a.n_iter[p] : 0u;
         T[h] = inside ? a.T_final[p] : 1.0f;
-        Tfin[h] = T[h];
         S[h] = 0.0f;
         dCp[h][0] = dCp[h][1] = dCp[h][2] = 0.0f;
         if (inside && a.dC) {
@@ -115,7 +136,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             dCp[h][1] = a.dC[3 * p + 1];
             dCp[h][2] = a.dC[3 * p + 2];
         }
-        dTp[h] = (inside && a.dT) ? a.dT[p] : 0.0f;
+        TdT[h] = T[h] * ((inside && a.dT) ? a.dT[p] : 0.0f);
         if (q == 0) {
             const int n = (2 * w + h) * TILE + xi;
             sdc[3 * n] = dCp[h][0];
@@ -220,22 +241,25 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                         const float inv = 1.0f / (1.0f - al[r]);
                         const float Tk = Tc * inv;
                         wv = al[r] * Tk;
-                        const float dalpha = Tk * gg[r] - (Sc + Tfin[h] * dTp[h]) * inv;
+                        const float dalpha = Tk * gg[r] - (Sc + TdT[h]) * inv;
                         Sc += wv * gg[r];
                         Tc = Tk;
                         // alpha < ALPHA_MAX exactly when o G was not clamped
                         dpow = al[r] < ALPHA_MAX ? dalpha * al[r] : 0.0f;
                     }
-                    sw[k * TILE_PIX + n] = wv;
-                    sdp[k * TILE_PIX + n] = dpow;
+                    sw[n * SK + k] = wv;
+                    sdp[n * SK + k] = dpow;
                 }
             }
         }
         __syncthreads();
 
-        // 3. Gaussian-parallel sums over the tile's pixels: thread = (k, 16 pixels)
+        // 3. Gaussian-parallel sums over the tile's pixels: lane = position k
+        //    (consecutive lanes read consecutive addresses), each half-wave a
+        //    group of 16 pixels; then the 16 groups are added in a fixed order
+        //    (the two of a wave, then the waves in order).
         {
-            const int k = threadIdx.x >> 4, pg = threadIdx.x & 15;
+            const int k = lane & 31, pg = 2 * w + (lane >> 5);
             const Rec rc = srec[k];
             float qv[10];
 #pragma unroll
@@ -243,7 +267,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             const float ex = rc.r1.x, ey = rc.r1.y;
             for (int m = 0; m < 16; ++m) {
                 const int n = pg * 16 + m;
-                const float dp = sdp[k * TILE_PIX + n], wv = sw[k * TILE_PIX + n];
+                const float dp = sdp[n * SK + k], wv = sw[n * SK + k];
                 if (dp != 0.0f || wv != 0.0f) {
                     const float xx = (float)(tx * TILE + (n & 15)) + 0.5f, yy = (float)(ty * TILE + (n >> 4)) + 0.5f;
                     const AlphaEval ae = eval_alpha(rc, xx, yy);
@@ -262,15 +286,20 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             }
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
+                qv[m] += __shfl_xor(qv[m], 32, 64);
+                if (lane < 32) sred[(w * 10 + m) * BK + k] = qv[m];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 12 * BK) {
+            // terms 10 and 11 of a partial are padding: written as zero
+            const int k = threadIdx.x % BK, m = threadIdx.x / BK;
+            float sum = 0.0f;
+            if (m < 10) {
 #pragma unroll
-                for (int off = 1; off < 16; off <<= 1) qv[m] += __shfl_xor(qv[m], off, 64);
+                for (int ww = 0; ww < 8; ++ww) sum += sred[(ww * 10 + m) * BK + k];
             }
-            if (pg == 0 && k < cnt) {
-                float4* o = reinterpret_cast<float4*>(a.part_geom + ((int64_t)voff + cs + k) * 12);
-                o[0] = make_float4(qv[0], qv[1], qv[2], qv[3]);
-                o[1] = make_float4(qv[4], qv[5], qv[6], qv[7]);
-                o[2] = make_float4(qv[8], qv[9], 0.0f, 0.0f);
-            }
+            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + m] = sum;
         }
         __syncthreads();
     }
@@ -289,8 +318,8 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16* swh = reinterpret_cast<__bf16*>(smem);                           // [BK][PP] W^T hi
     __bf16* swl = swh + BK * PP;                                             // [BK][PP] W^T lo
-    float* sw = reinterpret_cast<float*>(swl + BK * PP);                     // [BK][256] w
-    __shared__ Rec srec[BK];
+    __shared__ float swsum[16][BK];     // per wave (pixel row): sum over its pixels of w, per position
+    __shared__ Rec srecb[2][BK];        // chunk records, double-buffered (the next chunk's fetched ahead)
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -326,11 +355,20 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         }
     }
 
-    for (int ce = (int)nt; ce > 0; ce -= BK) {
+    if (threadIdx.x < BK) {
+        const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
+        srecb[0][threadIdx.x] = fetch_record(a, v, s, cs0, (int)nt - cs0, threadIdx.x);
+    }
+    __syncthreads();
+    int b = 0;
+    for (int ce = (int)nt; ce > 0; ce -= BK, b ^= 1) {
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
-        stage_records(a, v, s, cs, cnt, srec, nullptr);
-        __syncthreads();
+        const Rec* srec = srecb[b];
+        // the next chunk's records, in flight during this chunk
+        const int ncs = cs - BK > 0 ? cs - BK : 0;
+        Rec nxt;
+        if (threadIdx.x < BK && cs > 0) nxt = fetch_record(a, v, s, ncs, cs - ncs, threadIdx.x);
         const int n = w * TILE + xi;
 #pragma unroll
         for (int kb = 1; kb >= 0; --kb) {
@@ -360,22 +398,24 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                     wv = al[r] * Tk;
                     Tc = Tk;
                 }
-                sw[k * TILE_PIX + n] = wv;
                 const __bf16 hh = (__bf16)wv;
                 swh[k * PP + n] = hh;
                 swl[k * PP + n] = (__bf16)(wv - (float)hh);
+                // the row's weight sum of position k: butterfly over the 16 pixels
+                float rs = wv;
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) rs += __shfl_xor(rs, off, 64);
+                if (xi == 0) swsum[w][k] = rs;
             }
         }
         __syncthreads();
-        // weight sums per instance: thread = (k, 8 pixels)
-        {
-            const int k = threadIdx.x >> 5, pg = threadIdx.x & 31;
+        // weight sums per instance: the 16 rows in order
+        if (threadIdx.x < BK) {
+            const int k = threadIdx.x;
             float ws = 0.0f;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) ws += sw[k * TILE_PIX + pg * 8 + m];
-#pragma unroll
-            for (int off = 1; off < 32; off <<= 1) ws += __shfl_xor(ws, off, 64);
-            if (pg == 0 && k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + 9] = ws;
+            for (int ww = 0; ww < 16; ++ww) ws += swsum[ww][k];
+            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + 9] = ws;
         }
         // out[k][d] = sum_px W^T[k][px] target[px][d], W = hi + lo
         if (w < NDB) {
@@ -396,6 +436,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 }
             }
         }
+        if (threadIdx.x < BK && cs > 0) srecb[b ^ 1][threadIdx.x] = nxt;
         __syncthreads();
     }
 }
@@ -403,11 +444,12 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 template <int D>
 static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     if (grads) {
-        const size_t lds = sizeof(__bf16) * (size_t)BK * (D + 8) + sizeof(float) * (2 * (size_t)BK * TILE_PIX + 3 * TILE_PIX);
+        const size_t lds = sizeof(__bf16) * (size_t)BK * (D + 8) +
+                           sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * 10 * BK);
         hipLaunchKernelGGL(k_render_bwd_bf16<D>, dim3(n_tiles), dim3(512), lds, s, a, vt);
     }
     if (fuse) {
-        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (TILE_PIX + 8) + sizeof(float) * (size_t)BK * TILE_PIX;
+        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (TILE_PIX + 8);
         hipLaunchKernelGGL(k_fuse_bf16<D>, dim3(n_tiles), dim3(1024), lds, s, a, vt);
     }
 }

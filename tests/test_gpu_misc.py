@@ -125,8 +125,9 @@ def test_autograd_function_against_central_differences():
     against central differences of the FP64 forward, taken over each
     Gaussian's footprint tiles (all other pixels are unchanged by the step).
     The subset: among the 5000 nearest Gaussians with a footprint of at most
-    12x12 tiles, the first 64 (by index) with no near-threshold decision (oracle
-    flags) and a non-zero opacity gradient (at this density only the front
+    12x12 tiles, the first 64 (by index) with no near-threshold decision in any
+    pixel they touch (oracle flags and ambiguity bound) and a non-zero opacity
+    gradient (at this density only the front
     layer is ever reached).  Steps keep the depth order (mean components across the view
     axis, scales, rotation, opacity, SH); a step along the view axis reorders
     Gaussians at this density and has no central difference."""
@@ -154,7 +155,10 @@ def test_autograd_function_against_central_differences():
     views = [dict(tiles=np.array(sorted(set().union(*[S._rect_tiles(bq, i) for i in first]))), tile_off=0,
                   pix_off=0)]
     ora = S.run(g, [cam], [bq], first, views, rows, wl.d)
-    ok = U.checkable(ora["gflag"]) & (np.abs(ora["sums"]["opacity"]) > 0)
+    # no near-threshold decision in any pixel they touch (a step could cross it:
+    # no flag and a zero ambiguity bound) and a contribution
+    amb_any = sum(np.abs(ora["ambs"][k]).reshape(first.size, -1).sum(1) for k in S.GRAD_KEYS)
+    ok = (ora["gflag"] == 0) & (amb_any == 0) & (np.abs(ora["sums"]["opacity"]) > 0)
     subset = first[ok][:64]
     assert subset.size == 64
     depth_axis = np.abs(np.asarray(cam.R, np.float64)[2])
