@@ -249,6 +249,8 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
     sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
     sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
+    sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
+    sz[WS_VGID] = (size_t)visit_capacity * u4;
     size_t off = 0;
     for (int i = 0; i < WS_COUNT; ++i) {
         plan->off[i] = off;
@@ -397,6 +399,8 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.dT = nullptr;
     a.target = nullptr;
     a.target_bf16 = 0;
+    a.vrec = cbuf<float4>(p, ws, WS_VREC);
+    a.vgid = cbuf<uint32_t>(p, ws, WS_VGID);
     a.part_geom = buf<float>(p, ws, WS_PART_GEOM);
     a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
 }
@@ -412,16 +416,33 @@ static void launch_bwd(const fh_plan* p, const BwdArgs& a, const ViewTable& vt, 
         launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, p->tuning.bwd_chunk, s);
 }
 
-// Visited instances sorted stably by rank: each (view, Gaussian) gets a
-// contiguous segment of visit indices in row-major tile order.
+// Rank, Gaussian and record of every visited instance, in visit order.
+static void visit_stage(const fh_plan* p, void* ws, const ViewTable& vt, hipStream_t s) {
+    VisitStageArgs a;
+    a.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
+    a.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
+    a.tile_voff = cbuf<uint32_t>(p, ws, WS_TILE_VOFF);
+    a.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
+    a.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
+    a.rank_bits = p->rank_bits;
+    a.packed = p->packed_keys;
+    a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
+    a.rec = cbuf<float4>(p, ws, WS_REC);
+    a.n = p->n;
+    a.counters = buf<Counters>(p, ws, WS_COUNTERS);
+    a.vkey = buf<uint32_t>(p, ws, WS_VKEY_A);
+    a.vgid = buf<uint32_t>(p, ws, WS_VGID);
+    a.vrec = buf<float4>(p, ws, WS_VREC);
+    launch_visit_stage(a, vt, (int)p->n_tiles, s);
+}
+
+// Visited instances sorted stably by rank (the keys visit_stage wrote): each
+// (view, Gaussian) gets a contiguous segment of visit indices in row-major
+// tile order.
 static void visit_sort(const fh_plan* p, void* ws, hipStream_t s) {
     Counters* c = buf<Counters>(p, ws, WS_COUNTERS);
     const int64_t total = (int64_t)p->n * p->n_views;
     uint32_t* vka = buf<uint32_t>(p, ws, WS_VKEY_A);
-    launch_visit_keys(cbuf<uint32_t>(p, ws, WS_RANGES), cbuf<uint32_t>(p, ws, WS_TILE_NITER),
-                      cbuf<uint32_t>(p, ws, WS_TILE_VOFF), cbuf<uint32_t>(p, ws, final_keys_buf(p)),
-                      p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p)), p->rank_bits,
-                      p->packed_keys, c, (int)p->n_tiles, vka, s);
     radix_sort(vka, nullptr, vka, buf<uint32_t>(p, ws, WS_VVAL_A), buf<uint32_t>(p, ws, WS_VKEY_B),
                buf<uint32_t>(p, ws, WS_VVAL_B), true, 1, 0, &c->n_visited, p->visit_capacity, 0, p->rank_bits,
                buf<uint32_t>(p, ws, WS_HIST), buf<uint32_t>(p, ws, WS_SCAN_TMP), s);
@@ -469,6 +490,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
+    visit_stage(p, ws, vt, s);
     launch_bwd(p, a, vt, fuse, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
@@ -519,6 +541,7 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
+    visit_stage(p, ws, vt, s);
     launch_bwd(p, a, vt, true, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;

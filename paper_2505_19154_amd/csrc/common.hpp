@@ -55,6 +55,8 @@ enum WsBuf {
     WS_VVAL_A,         // u32 [visit_cap] visit index, sorted by rank
     WS_VVAL_B,
     WS_LONG,           // u32 [V*N + N] lists of long reduction segments
+    WS_VREC,           // float4 [visit_cap * 3] screen record of each visited instance
+    WS_VGID,           // u32 [visit_cap] Gaussian of each visited instance
     WS_COUNT
 };
 
@@ -102,6 +104,7 @@ __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int t) {
 struct Rec {
     float4 r0, r1, r2;
 };
+static_assert(sizeof(Rec) == 48, "records are read and written as 12 consecutive dwords");
 
 // alpha = min(ALPHA_MAX, o G) at pixel centre (x, y), evaluated with explicit
 // fused operations so that every kernel gets the same bits.

@@ -90,8 +90,25 @@ struct BwdArgs {
     const float* dT;
     const void* target;
     int target_bf16;
+    const float4* vrec;        // [visits * 3] staged records, in visit order
+    const uint32_t* vgid;      // [visits] staged Gaussians
     float* part_geom;
     float* part_fuse;
+};
+struct VisitStageArgs {
+    const uint32_t* ranges;
+    const uint32_t* tile_niter;
+    const uint32_t* tile_voff;
+    const uint32_t* keys;
+    const uint32_t* vals;
+    int rank_bits, packed;
+    const uint32_t* order;
+    const float4* rec;
+    int64_t n;
+    Counters* counters;
+    uint32_t* vkey;     // [visits] rank of the visited instance
+    uint32_t* vgid;     // [visits] its Gaussian
+    float4* vrec;       // [visits * 3] its screen record
 };
 struct ReduceArgs {
     const uint32_t* order;
@@ -117,9 +134,7 @@ void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tile
 bool render_bwd_bf16_supported(int d);
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,
                             hipStream_t s);
-void launch_visit_keys(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* tile_voff,
-                       const uint32_t* keys, const uint32_t* vals, int rank_bits, int packed, Counters* c,
-                       int n_tiles, uint32_t* vkey, hipStream_t s);
+void launch_visit_stage(const VisitStageArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
 void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s);
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
 // chunk: Gaussians per back-to-front chunk (16, or 32 when d <= 512)

@@ -22,23 +22,33 @@ __device__ __forceinline__ uint32_t rank_of_inst(const uint32_t* keys, const uin
     return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
 }
 
-// vkey[visit index] = rank of the visited instance; one workgroup per tile.
-__global__ __launch_bounds__(256) void k_visit_keys(const uint32_t* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ tile_niter,
-                                                    const uint32_t* __restrict__ tile_voff,
-                                                    const uint32_t* __restrict__ keys,
-                                                    const uint32_t* __restrict__ vals, int rank_bits, int packed,
-                                                    Counters* counters, uint32_t* __restrict__ vkey) {
+// Visit staging, one workgroup per tile, run once the forward pass has fixed
+// every tile's traversal length: for visit index vo + pos (position pos of
+// tile t's list, pos < tile_niter[t]) it writes the instance's rank (the key
+// of the visit sort), its Gaussian and its screen record.  The backward
+// kernels then read a chunk's records and Gaussians with one contiguous load
+// each instead of a chain of dependent gathers (list -> rank -> record).
+__global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a, ViewTable vt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counters->n_long_geom = 0;
-        counters->n_long_fuse = 0;
+        a.counters->n_long_geom = 0;
+        a.counters->n_long_fuse = 0;
     }
-    if (counters->inst_overflow || counters->visit_overflow) return;
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
-    const uint32_t nt = tile_niter[t];
-    const uint32_t s = ranges[2 * t], vo = tile_voff[t];
-    for (uint32_t pos = threadIdx.x; pos < nt; pos += 256)
-        vkey[vo + pos] = rank_of_inst(keys, vals, (int64_t)s + pos, rank_bits, packed);
+    const uint32_t nt = a.tile_niter[t];
+    const uint32_t s = a.ranges[2 * t], vo = a.tile_voff[t];
+    const int v = view_of_tile(vt, t);
+    for (uint32_t pos = threadIdx.x; pos < nt; pos += 256) {
+        const uint32_t j = rank_of_inst(a.keys, a.vals, (int64_t)s + pos, a.rank_bits, a.packed);
+        const uint32_t g = a.order[j];
+        const int64_t ri = ((int64_t)v * a.n + g) * 3;
+        const int64_t vi = (int64_t)vo + pos;
+        a.vkey[vi] = j;
+        a.vgid[vi] = g;
+        a.vrec[3 * vi] = a.rec[ri];
+        a.vrec[3 * vi + 1] = a.rec[ri + 1];
+        a.vrec[3 * vi + 2] = a.rec[ri + 2];
+    }
 }
 
 // vseg[2j], vseg[2j+1] = [first, end) of rank j in the rank-sorted visits.
@@ -269,11 +279,8 @@ __global__ __launch_bounds__(1024) void k_reduce_fuse_long(ReduceArgs a) {
     }
 }
 
-void launch_visit_keys(const uint32_t* ranges, const uint32_t* tile_niter, const uint32_t* tile_voff,
-                       const uint32_t* keys, const uint32_t* vals, int rank_bits, int packed, Counters* c,
-                       int n_tiles, uint32_t* vkey, hipStream_t s) {
-    hipLaunchKernelGGL(k_visit_keys, dim3(n_tiles), dim3(256), 0, s, ranges, tile_niter, tile_voff, keys, vals,
-                       rank_bits, packed, c, vkey);
+void launch_visit_stage(const VisitStageArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_visit_stage, dim3(n_tiles), dim3(256), 0, s, a, vt);
 }
 
 void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s) {
@@ -289,7 +296,7 @@ template <int NC, int B>
 static void launch_reduce_fuse_nc(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_reduce_fuse<NC, B>), dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
     const size_t lds = sizeof(float) * (16 * 2 * (size_t)a.d + 32);
-    hipLaunchKernelGGL((k_reduce_fuse_long<NC, B>), dim3(256), dim3(1024), lds, s, a);
+    hipLaunchKernelGGL((k_reduce_fuse_long<NC, B>), dim3(512), dim3(1024), lds, s, a);
 }
 
 // channels per lane NC = ceil(d / 64); visits per batch B keep B * NC <= 32 registers of rows

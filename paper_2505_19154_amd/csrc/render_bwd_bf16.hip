@@ -29,31 +29,22 @@ namespace fh {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BK = 32;   // positions per chunk
 constexpr int SK = BK + 1;   // padded per-pixel stride of the (pixel, position) LDS arrays
 
-__device__ __forceinline__ uint32_t rank_at_b(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
-                                              int packed) {
-    return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
-}
-
-__device__ __forceinline__ float ld_val(const void* p, int bf16, int64_t idx) {
-    return bf16 ? bf16_to_f32(static_cast<const uint16_t*>(p)[idx]) : static_cast<const float*>(p)[idx];
-}
-
-// Stage the chunk's records (threads 0..31); padding records never blend.
-__device__ __forceinline__ void stage_records(const BwdArgs& a, int v, uint32_t s, int cs, int cnt, Rec* srec,
+// Stage the chunk's records (threads 0..31) from the visit-ordered copies;
+// padding records never blend.
+__device__ __forceinline__ void stage_records(const BwdArgs& a, uint32_t voff, int cs, int cnt, Rec* srec,
                                               uint32_t* sg) {
     if (threadIdx.x < BK) {
         if ((int)threadIdx.x < cnt) {
-            const int64_t i = (int64_t)s + cs + threadIdx.x;
-            const uint32_t g = a.order[rank_at_b(a.keys, a.vals, i, a.rank_bits, a.packed)];
-            const int64_t ri = ((int64_t)v * a.n + g) * 3;
-            srec[threadIdx.x].r0 = a.rec[ri];
-            srec[threadIdx.x].r1 = a.rec[ri + 1];
-            srec[threadIdx.x].r2 = a.rec[ri + 2];
-            if (sg) sg[threadIdx.x] = g;
+            const int64_t vi = (int64_t)voff + cs + threadIdx.x;
+            srec[threadIdx.x].r0 = a.vrec[3 * vi];
+            srec[threadIdx.x].r1 = a.vrec[3 * vi + 1];
+            srec[threadIdx.x].r2 = a.vrec[3 * vi + 2];
+            if (sg) sg[threadIdx.x] = a.vgid[vi];
         } else {
             srec[threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
             srec[threadIdx.x].r1 = make_float4(1.f, 0.f, -1.f, -1.f);
@@ -64,15 +55,13 @@ __device__ __forceinline__ void stage_records(const BwdArgs& a, int v, uint32_t 
 }
 
 // One chunk record (position cs + k of the tile's list, or padding past cnt).
-__device__ __forceinline__ Rec fetch_record(const BwdArgs& a, int v, uint32_t s, int cs, int cnt, int k) {
+__device__ __forceinline__ Rec fetch_record(const BwdArgs& a, uint32_t voff, int cs, int cnt, int k) {
     Rec r;
     if (k < cnt) {
-        const int64_t i = (int64_t)s + cs + k;
-        const uint32_t g = a.order[rank_at_b(a.keys, a.vals, i, a.rank_bits, a.packed)];
-        const int64_t ri = ((int64_t)v * a.n + g) * 3;
-        r.r0 = a.rec[ri];
-        r.r1 = a.rec[ri + 1];
-        r.r2 = a.rec[ri + 2];
+        const int64_t vi = (int64_t)voff + cs + k;
+        r.r0 = a.vrec[3 * vi];
+        r.r1 = a.vrec[3 * vi + 1];
+        r.r2 = a.vrec[3 * vi + 2];
     } else {
         r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
         r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
@@ -97,8 +86,8 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     float* sdp = sw + TILE_PIX * SK;                                         // [256][SK] dL/dpower
     float* sdc = sdp + TILE_PIX * SK;                                        // [256][3] dC of the tile
     float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][10][BK] partial sums
-    __shared__ Rec srec[BK];
-    __shared__ uint32_t sg[BK];
+    __shared__ Rec srecb[2][BK];        // chunk records and Gaussians, double-buffered:
+    __shared__ uint32_t sgb[2][BK];     // the next chunk's arrive during this one
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -110,7 +99,6 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     const int lt = t - vt.tile_off[v];
     const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
     const int W = vt.width[v], H = vt.height[v];
-    const uint32_t s = a.ranges[2 * t];
     const uint32_t voff = a.tile_voff[t];
     const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
     const bool has_df = a.dF != nullptr;
@@ -163,18 +151,58 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         }
     }
 
-    for (int ce = (int)nt; ce > 0; ce -= BK) {
+    {
+        const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
+        stage_records(a, voff, cs0, (int)nt - cs0, srecb[0], sgb[0]);
+    }
+    __syncthreads();
+    int b = 0;
+    for (int ce = (int)nt; ce > 0; ce -= BK, b ^= 1) {
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
-        stage_records(a, v, s, cs, cnt, srec, sg);
-        __syncthreads();
+        const Rec* srec = srecb[b];
+        const uint32_t* sg = sgb[b];
+        // the next chunk's records (12 dwords each, threads 0..12 BK-1) and
+        // Gaussians (threads 12 BK..13 BK-1): one dword per thread, stored at
+        // the end of this chunk; padding positions get the padding record
+        const int ncs = cs - BK > 0 ? cs - BK : 0;
+        const int ncnt = cs - ncs;
+        // (positions ncs .. ncs + BK - 1 all lie in this tile's visits, as the
+        // current chunk is full whenever there is a next one, so the load needs
+        // no guard; padding is selected after it)
+        const bool pre_on = cs > 0 && threadIdx.x < 13 * BK;
+        const bool pre_g = threadIdx.x >= 12 * BK;
+        const int pre_k = pre_g ? (int)threadIdx.x - 12 * BK : (int)threadIdx.x / 12;
+        uint32_t pre = 0u;
+        if (pre_on) {
+            const uint32_t* src = pre_g ? a.vgid + ((int64_t)voff + ncs)
+                                        : reinterpret_cast<const uint32_t*>(a.vrec) + ((int64_t)voff + ncs) * 12;
+            pre = src[pre_g ? pre_k : (int)threadIdx.x];
+        }
         if (has_df) {
-            for (int idx = threadIdx.x; idx < BK * (D / 8); idx += 512) {
-                const int k = idx / (D / 8), dg = idx % (D / 8);
-                const uint32_t g = sg[k];
-                uint4 raw = make_uint4(0, 0, 0, 0);
-                if (g != 0xFFFFFFFFu) raw = *reinterpret_cast<const uint4*>(feat + (int64_t)g * D + dg * 8);
-                *reinterpret_cast<uint4*>(&sfeat[k * DP + dg * 8]) = raw;
+            // all of this thread's feature rows are requested before any is stored
+            constexpr int ITEMS = BK * (D / 8), NI = (ITEMS + 511) / 512;
+            uint4 raw[NI];
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                const int idx = threadIdx.x + 512 * it;
+                raw[it] = make_uint4(0, 0, 0, 0);
+                if (idx < ITEMS) {
+                    // a padding position reads Gaussian 0: its contraction row
+                    // is only used by positions that blend, which it never does
+                    const int k = idx / (D / 8), dg = idx % (D / 8);
+                    const uint32_t g = sg[k];
+                    const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
+                    raw[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * D + dg * 8);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                const int idx = threadIdx.x + 512 * it;
+                if (idx < ITEMS) {
+                    const int k = idx / (D / 8), dg = idx % (D / 8);
+                    *reinterpret_cast<uint4*>(&sfeat[k * DP + dg * 8]) = raw[it];
+                }
             }
         }
         __syncthreads();
@@ -251,6 +279,18 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     sdp[n * SK + k] = dpow;
                 }
             }
+        }
+        // the next chunk's records and Gaussians go to the other buffer now,
+        // before this chunk's partial stores are issued (a wait for the
+        // prefetch placed after them would also wait for the stores)
+        if (pre_on) {
+            const int j = (int)threadIdx.x % 12;
+            const uint32_t pad = pre_g ? 0xFFFFFFFFu : (j == 4 ? 0x3f800000u : ((j == 6 || j == 7) ? 0xbf800000u : 0u));
+            const uint32_t val = pre_k < ncnt ? pre : pad;
+            if (pre_g)
+                sgb[b ^ 1][pre_k] = val;
+            else
+                reinterpret_cast<uint32_t*>(srecb[b ^ 1])[threadIdx.x] = val;
         }
         __syncthreads();
 
@@ -331,7 +371,6 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     const int lt = t - vt.tile_off[v];
     const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
     const int W = vt.width[v], H = vt.height[v];
-    const uint32_t s = a.ranges[2 * t];
     const uint32_t voff = a.tile_voff[t];
     const int px = tx * TILE + xi, py = ty * TILE + w;
     const bool inside = px < W && py < H;
@@ -341,24 +380,49 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     float T = inside ? a.T_final[p] : 1.0f;
 
     // target[px = 32 st + 8 q + m][16 w + xi]: B operands of this wave's block
+    // (BF16 target).  All 64 loads are issued before any is used: addresses of
+    // pixels outside the image are clamped into it and the values zeroed after.
     bf16x8 tgo[8];
+    if (w < NDB) {
+        const uint16_t* tg = static_cast<const uint16_t*>(a.target);
+        u16x8 raw[8];
 #pragma unroll
-    for (int st = 0; st < 8; ++st) {
-        const int n0 = 32 * st + 8 * q;   // 8 consecutive pixels of one tile row
-        const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
-        const int64_t base = (vt.pix_off[v] + (int64_t)qy * W + qx0) * D + 16 * w + xi;
+        for (int st = 0; st < 8; ++st) {
+            const int n0 = 32 * st + 8 * q;   // 8 consecutive pixels of one tile row
+            const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
+            const int64_t row = vt.pix_off[v] + (int64_t)(qy < H ? qy : H - 1) * W;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            float val = 0.0f;
-            if (w < NDB && qy < H && qx0 + m < W) val = ld_val(a.target, a.target_bf16, base + (int64_t)m * D);
-            tgo[st][m] = (__bf16)val;
+            for (int m = 0; m < 8; ++m) {
+                const int qx = qx0 + m < W ? qx0 + m : W - 1;
+                raw[st][m] = tg[(row + qx) * D + 16 * w + xi];
+            }
         }
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int n0 = 32 * st + 8 * q;
+            const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (qy >= H || qx0 + m >= W) raw[st][m] = 0;
+            tgo[st] = __builtin_bit_cast(bf16x8, raw[st]);
+        }
+    } else {
+#pragma unroll
+        for (int st = 0; st < 8; ++st) tgo[st] = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
     }
 
     if (threadIdx.x < BK) {
         const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
-        srecb[0][threadIdx.x] = fetch_record(a, v, s, cs0, (int)nt - cs0, threadIdx.x);
+        srecb[0][threadIdx.x] = fetch_record(a, voff, cs0, (int)nt - cs0, threadIdx.x);
     }
+    // the tile's staged records as a buffer (raw, dword data format): reads
+    // past its nt visits return zero instead of touching other memory
+    const __amdgpu_buffer_rsrc_t vrec_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float4*>(a.vrec + 3 * (int64_t)voff), (short)0,
+        (int)(nt < 0x7fffffffu / 48u ? nt * 48u : 0x7fffffffu), 0x00020000);
+    // the pixel's state is complete before the loop (its loads are not
+    // carried into the loop's waits)
+    asm volatile("" ::"v"(nit), "v"(T));
     __syncthreads();
     int b = 0;
     for (int ce = (int)nt; ce > 0; ce -= BK, b ^= 1) {
@@ -367,8 +431,18 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         const Rec* srec = srecb[b];
         // the next chunk's records, in flight during this chunk
         const int ncs = cs - BK > 0 ? cs - BK : 0;
+        // (positions ncs .. ncs + BK - 1 all lie in this tile's visits when
+        // there is a next chunk, as the current one is then full; padding is
+        // selected when the record is stored)
         Rec nxt;
-        if (threadIdx.x < BK && cs > 0) nxt = fetch_record(a, v, s, ncs, cs - ncs, threadIdx.x);
+        if (threadIdx.x < BK && cs > 0) {
+            // buffer loads: a uniform chunk offset and a fixed lane offset, so the
+            // loop needs no address registers that could alias the pending loads
+            const int lo = (int)threadIdx.x * 48, so = ncs * 48;
+            nxt.r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo, so, 0));
+            nxt.r1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo + 16, so, 0));
+            nxt.r2 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo + 32, so, 0));
+        }
         const int n = w * TILE + xi;
 #pragma unroll
         for (int kb = 1; kb >= 0; --kb) {
@@ -408,6 +482,16 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 if (xi == 0) swsum[w][k] = rs;
             }
         }
+        // the next chunk's records go to the other buffer before this chunk's
+        // stores are issued (a wait placed after them would also wait for those)
+        if (threadIdx.x < BK && cs > 0) {
+            if ((int)threadIdx.x >= cs - ncs) {
+                nxt.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                nxt.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+                nxt.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            srecb[b ^ 1][threadIdx.x] = nxt;
+        }
         __syncthreads();
         // weight sums per instance: the 16 rows in order
         if (threadIdx.x < BK) {
@@ -436,7 +520,6 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 }
             }
         }
-        if (threadIdx.x < BK && cs > 0) srecb[b ^ 1][threadIdx.x] = nxt;
         __syncthreads();
     }
 }

@@ -148,7 +148,6 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
     const int px = tx * TILE + (threadIdx.x % TILE), py = ty * TILE + (threadIdx.x / TILE);
     const bool inside = px < vt.width[v] && py < vt.height[v];
     const float x = (float)px + 0.5f, y = (float)py + 0.5f;
-    const uint32_t s = a.ranges[2 * t];
     const uint32_t voff = a.tile_voff[t];
     const int64_t p = vt.pix_off[v] + (int64_t)py * vt.width[v] + px;
 
@@ -169,14 +168,11 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
         const int cs = ce - K > 0 ? ce - K : 0;
         const int cnt = ce - cs;
         if (threadIdx.x < cnt) {
-            const int64_t i = (int64_t)s + cs + threadIdx.x;
-            const uint32_t j = inst_rank(a.keys, a.vals, i, a.rank_bits, a.packed);
-            const uint32_t g = a.order[j];
-            const int64_t ri = ((int64_t)v * a.n + g) * 3;
-            srec[threadIdx.x].r0 = a.rec[ri];
-            srec[threadIdx.x].r1 = a.rec[ri + 1];
-            srec[threadIdx.x].r2 = a.rec[ri + 2];
-            sg[threadIdx.x] = g;
+            const int64_t vi = (int64_t)voff + cs + threadIdx.x;
+            srec[threadIdx.x].r0 = a.vrec[3 * vi];
+            srec[threadIdx.x].r1 = a.vrec[3 * vi + 1];
+            srec[threadIdx.x].r2 = a.vrec[3 * vi + 2];
+            sg[threadIdx.x] = a.vgid[vi];
         }
         __syncthreads();
         if (D > 0 && (a.dF || FUSE)) {
