@@ -169,7 +169,8 @@ static void bin_count_impl(const fh_plan* p, void* ws, hipStream_t s) {
     launch_tiles_by_rank(cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<int4>(p, ws, WS_RECT), p->n, total, ntiles, c, s);
     device_exclusive_scan(ntiles, buf<uint32_t>(p, ws, WS_INST_OFF), total, scan_tmp, 1, s);
     launch_check_capacity(c, p->inst_capacity, s);
-    launch_rank_of(cbuf<uint32_t>(p, ws, WS_ORDER), p->n, total, buf<uint32_t>(p, ws, WS_RANK_OF), s);
+    launch_rank_tables(cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<float4>(p, ws, WS_REC), p->n, total,
+                       buf<uint32_t>(p, ws, WS_RANK_OF), buf<float4>(p, ws, WS_RREC), s);
 }
 
 }  // namespace fh
@@ -251,6 +252,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
     sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
     sz[WS_VGID] = (size_t)visit_capacity * u4;
+    sz[WS_RREC] = (size_t)total * 3 * 16;
     size_t off = 0;
     for (int i = 0; i < WS_COUNT; ++i) {
         plan->off[i] = off;
@@ -345,6 +347,7 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
     RenderArgs a;
     a.rec = cbuf<float4>(p, ws, WS_REC);
+    a.rrec = cbuf<float4>(p, ws, WS_RREC);
     a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
     a.keys = cbuf<uint32_t>(p, ws, final_keys_buf(p));
     a.vals = p->packed_keys ? nullptr : cbuf<uint32_t>(p, ws, final_vals_buf(p));
@@ -417,7 +420,7 @@ static void launch_bwd(const fh_plan* p, const BwdArgs& a, const ViewTable& vt, 
 }
 
 // Rank, Gaussian and record of every visited instance, in visit order.
-static void visit_stage(const fh_plan* p, void* ws, const ViewTable& vt, hipStream_t s) {
+static void visit_stage(const fh_plan* p, void* ws, hipStream_t s) {
     VisitStageArgs a;
     a.ranges = cbuf<uint32_t>(p, ws, WS_RANGES);
     a.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
@@ -427,13 +430,12 @@ static void visit_stage(const fh_plan* p, void* ws, const ViewTable& vt, hipStre
     a.rank_bits = p->rank_bits;
     a.packed = p->packed_keys;
     a.order = cbuf<uint32_t>(p, ws, WS_ORDER);
-    a.rec = cbuf<float4>(p, ws, WS_REC);
-    a.n = p->n;
+    a.rrec = cbuf<float4>(p, ws, WS_RREC);
     a.counters = buf<Counters>(p, ws, WS_COUNTERS);
     a.vkey = buf<uint32_t>(p, ws, WS_VKEY_A);
     a.vgid = buf<uint32_t>(p, ws, WS_VGID);
     a.vrec = buf<float4>(p, ws, WS_VREC);
-    launch_visit_stage(a, vt, (int)p->n_tiles, s);
+    launch_visit_stage(a, (int)p->n_tiles, s);
 }
 
 // Visited instances sorted stably by rank (the keys visit_stage wrote): each
@@ -490,7 +492,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
-    visit_stage(p, ws, vt, s);
+    visit_stage(p, ws, s);
     launch_bwd(p, a, vt, fuse, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
@@ -541,7 +543,7 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     a.target_bf16 = target_dtype == FH_BF16;
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
-    visit_stage(p, ws, vt, s);
+    visit_stage(p, ws, s);
     launch_bwd(p, a, vt, true, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;

@@ -57,6 +57,7 @@ enum WsBuf {
     WS_LONG,           // u32 [V*N + N] lists of long reduction segments
     WS_VREC,           // float4 [visit_cap * 3] screen record of each visited instance
     WS_VGID,           // u32 [visit_cap] Gaussian of each visited instance
+    WS_RREC,           // float4 [V*N*3] screen records in depth-rank order
     WS_COUNT
 };
 

@@ -55,6 +55,7 @@ void launch_bin_keys(const uint32_t* keys, const uint32_t* vals, const uint32_t*
 // render_f32.hip
 struct RenderArgs {
     const float4* rec;
+    const float4* rrec;       // [V*N*3] records in depth-rank order
     const uint32_t* order;
     const uint32_t* keys;
     const uint32_t* vals;
@@ -103,8 +104,7 @@ struct VisitStageArgs {
     const uint32_t* vals;
     int rank_bits, packed;
     const uint32_t* order;
-    const float4* rec;
-    int64_t n;
+    const float4* rrec;
     Counters* counters;
     uint32_t* vkey;     // [visits] rank of the visited instance
     uint32_t* vgid;     // [visits] its Gaussian
@@ -134,14 +134,15 @@ void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tile
 bool render_bwd_bf16_supported(int d);
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,
                             hipStream_t s);
-void launch_visit_stage(const VisitStageArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s);
+void launch_visit_stage(const VisitStageArgs& a, int n_tiles, hipStream_t s);
 void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s);
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
 // chunk: Gaussians per back-to-front chunk (16, or 32 when d <= 512)
 void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s);
 void launch_reduce_geom(const ReduceArgs& a, hipStream_t s);
 void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
-void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s);
+void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
+                        float4* rrec, hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
                           const void* feat_in, void* feat_out, int bf16, hipStream_t s);
 

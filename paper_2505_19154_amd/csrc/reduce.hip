@@ -28,7 +28,7 @@ __device__ __forceinline__ uint32_t rank_of_inst(const uint32_t* keys, const uin
 // of the visit sort), its Gaussian and its screen record.  The backward
 // kernels then read a chunk's records and Gaussians with one contiguous load
 // each instead of a chain of dependent gathers (list -> rank -> record).
-__global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a, ViewTable vt) {
+__global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.counters->n_long_geom = 0;
         a.counters->n_long_fuse = 0;
@@ -37,17 +37,14 @@ __global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a, ViewTable
     const int t = blockIdx.x;
     const uint32_t nt = a.tile_niter[t];
     const uint32_t s = a.ranges[2 * t], vo = a.tile_voff[t];
-    const int v = view_of_tile(vt, t);
     for (uint32_t pos = threadIdx.x; pos < nt; pos += 256) {
         const uint32_t j = rank_of_inst(a.keys, a.vals, (int64_t)s + pos, a.rank_bits, a.packed);
-        const uint32_t g = a.order[j];
-        const int64_t ri = ((int64_t)v * a.n + g) * 3;
         const int64_t vi = (int64_t)vo + pos;
         a.vkey[vi] = j;
-        a.vgid[vi] = g;
-        a.vrec[3 * vi] = a.rec[ri];
-        a.vrec[3 * vi + 1] = a.rec[ri + 1];
-        a.vrec[3 * vi + 2] = a.rec[ri + 2];
+        a.vgid[vi] = a.order[j];
+        a.vrec[3 * vi] = a.rrec[3 * (int64_t)j];
+        a.vrec[3 * vi + 1] = a.rrec[3 * (int64_t)j + 1];
+        a.vrec[3 * vi + 2] = a.rrec[3 * (int64_t)j + 2];
     }
 }
 
@@ -279,8 +276,8 @@ __global__ __launch_bounds__(1024) void k_reduce_fuse_long(ReduceArgs a) {
     }
 }
 
-void launch_visit_stage(const VisitStageArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_visit_stage, dim3(n_tiles), dim3(256), 0, s, a, vt);
+void launch_visit_stage(const VisitStageArgs& a, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_visit_stage, dim3(n_tiles), dim3(256), 0, s, a);
 }
 
 void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t* vseg, hipStream_t s) {

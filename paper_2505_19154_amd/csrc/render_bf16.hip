@@ -27,37 +27,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int FK = 32;        // Gaussians per chunk
 constexpr int FKP = 40;       // padded k-stride of the transposed feature tile (80 B rows)
 
-__device__ __forceinline__ uint32_t rank_at(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
-                                            int packed) {
-    return packed ? (keys[i] & ((1u << rank_bits) - 1u)) : vals[i];
-}
+// Software pipeline over the tile's chunks of FK list positions.  While chunk
+// c is composited, threads 0..FK-1 hold in registers the list entries (depth
+// ranks) of chunk c+3 and the records and Gaussians of chunk c+2 (one load each,
+// from the rank-ordered records), and every thread holds its share of chunk
+// c+1's features.  All of them are requested at the top of the chunk and only
+// stored to LDS at its end, so no global latency sits between two chunks.
+// Records and Gaussians are triple-buffered in LDS, features double-buffered.
+constexpr uint32_t BUF_DWORD3 = 0x00020000u;   // raw buffer, 32-bit data format
 
-// Chunk records are fetched two chunks ahead (threads 0..31, into registers)
-// and chunk features one chunk ahead (every thread, into registers), both
-// double-buffered in LDS, so their global latency overlaps the current chunk's
-// alpha walk and MFMA work.
-struct RecFetch {
-    Rec r;
-    uint32_t g;
-};
-
-__device__ __forceinline__ RecFetch fetch_rec(const RenderArgs& a, int v, uint32_t base, uint32_t e, int k) {
-    RecFetch f;
-    const uint32_t i = base + (uint32_t)k;
-    if (i < e) {
-        f.g = a.order[rank_at(a.keys, a.vals, (int64_t)i, a.rank_bits, a.packed)];
-        const int64_t ri = ((int64_t)v * a.n + f.g) * 3;
-        f.r.r0 = a.rec[ri];
-        f.r.r1 = a.rec[ri + 1];
-        f.r.r2 = a.rec[ri + 2];
-    } else {
-        // padding: opacity 0 never blends
-        f.g = 0xFFFFFFFFu;
-        f.r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        f.r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-        f.r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    return f;
+__device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_t pos) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(pos * 4u), 0, 0);
 }
 
 template <int DS, int ROWS>
@@ -65,10 +45,11 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
     constexpr int NB = DS / 16;
     constexpr int NT = 64 * ROWS;                        // threads
     constexpr int NIT = (FK * (DS / 8) + NT - 1) / NT;   // feature items per thread
-    __shared__ Rec srec[2][FK];
-    __shared__ uint32_t sg[2][FK];
+    __shared__ Rec srec[3][FK];
+    __shared__ uint32_t sg[3][FK];
     __shared__ __attribute__((aligned(16))) __bf16 sft[2][DS * FKP];
     __shared__ uint32_t smax[ROWS];
+    __shared__ __attribute__((aligned(16))) uint8_t sbusy[2][16];   // per wave: a pixel still walking
     if (a.counters->inst_overflow) return;
     constexpr int NG = TILE / ROWS;                      // row groups per tile
     const int t = blockIdx.x, grp = blockIdx.y % NG, slice = blockIdx.y / NG, d0 = slice * DS;
@@ -81,49 +62,87 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
     const bool inside = px < vt.width[v] && py < vt.height[v];
     const float x = (float)px + 0.5f, y = (float)py + 0.5f;
     const uint32_t s = a.ranges[2 * t], e = a.ranges[2 * t + 1];
+    const uint32_t len = e - s;
     const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
+    // the tile's list as a range-checked buffer: positions past its end read 0
+    // (rank 0, a valid index; such positions become padding when stored)
+    const uint32_t* list = a.packed ? a.keys : a.vals;
+    const __amdgpu_buffer_rsrc_t list_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(list + s), (short)0, (int)(len < 0x1fffffffu ? len * 4u : 0x7ffffffcu), BUF_DWORD3);
+    const uint32_t rmask = a.packed ? ((1u << a.rank_bits) - 1u) : 0xFFFFFFFFu;
+    const int k = (int)threadIdx.x;   // list position within a chunk (threads 0..FK-1)
 
-    // feature items of one chunk: item = k + FK * dg, 8 channels each
+    auto put_rec = [&](int buf, uint32_t pos, const Rec& r, uint32_t g) {
+        const bool real = pos < len;
+        Rec o = r;
+        if (!real) {
+            // padding: opacity 0 never blends
+            o.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            o.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+            o.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        srec[buf][k] = o;
+        sg[buf][k] = real ? g : 0xFFFFFFFFu;
+    };
+    // e: a raw list entry (masked here, where it is used, so that its load is
+    // not waited for where it is issued)
+    auto get_rec = [&](uint32_t e, Rec& r, uint32_t& g) {
+        const uint32_t j = e & rmask;
+        const float4* src = a.rrec + 3 * (int64_t)j;
+        r.r0 = src[0];
+        r.r1 = src[1];
+        r.r2 = src[2];
+        g = a.order[j];
+    };
+    // feature items of one chunk: item = k + FK * dg, 8 channels each; padding
+    // positions read Gaussian 0 and are zeroed when stored
     auto load_feats = [&](const uint32_t* gl, uint4* fr) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = (int)threadIdx.x + NT * it;
-            fr[it] = make_uint4(0, 0, 0, 0);
             if (idx < FK * (DS / 8)) {
-                const int k = idx % FK, dg = idx / FK;
-                const uint32_t g = gl[k];
-                if (g != 0xFFFFFFFFu) fr[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)g * a.d + d0 + dg * 8);
+                const int kk = idx % FK, dg = idx / FK;
+                const uint32_t g = gl[kk];
+                const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
+                fr[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * a.d + d0 + dg * 8);
             }
         }
     };
-    auto store_feats = [&](const uint4* fr, __bf16* dstb) {
+    auto store_feats = [&](const uint32_t* gl, const uint4* fr, __bf16* dstb) {
         uint16_t* dst = reinterpret_cast<uint16_t*>(dstb);
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = (int)threadIdx.x + NT * it;
             if (idx < FK * (DS / 8)) {
-                const int k = idx % FK, dg = idx / FK;
-                const uint16_t* h = reinterpret_cast<const uint16_t*>(&fr[it]);
+                const int kk = idx % FK, dg = idx / FK;
+                uint4 f = fr[it];
+                if (gl[kk] == 0xFFFFFFFFu) f = make_uint4(0, 0, 0, 0);
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&f);
 #pragma unroll
-                for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + k] = h[m];
+                for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + kk] = h[m];
             }
         }
     };
 
-    // prologue: chunk 0 into buffer 0, chunk 1's records into registers and its g into sg[1]
-    RecFetch nxt;
-    if (threadIdx.x < FK) {
-        const RecFetch f0 = fetch_rec(a, v, s, e, threadIdx.x);
-        srec[0][threadIdx.x] = f0.r;
-        sg[0][threadIdx.x] = f0.g;
-        nxt = fetch_rec(a, v, s + FK, e, threadIdx.x);
-        sg[1][threadIdx.x] = nxt.g;
+    // prologue: chunks 0 and 1 into LDS, chunk 2's ranks into registers, then chunk 0's features
+    uint32_t rk2 = 0u;
+    if (k < FK && len > 0) {
+        const uint32_t j0 = list_load(list_rs, (uint32_t)k);
+        const uint32_t j1 = list_load(list_rs, (uint32_t)(FK + k));
+        rk2 = list_load(list_rs, (uint32_t)(2 * FK + k));
+        Rec r0, r1;
+        uint32_t g0, g1;
+        get_rec(j0, r0, g0);
+        get_rec(j1, r1, g1);
+        put_rec(0, (uint32_t)k, r0, g0);
+        put_rec(1, (uint32_t)(FK + k), r1, g1);
     }
+    if (threadIdx.x < 32) reinterpret_cast<uint8_t*>(sbusy)[threadIdx.x] = 0;
     __syncthreads();
-    {
+    if (len > 0) {   // (an empty list stages nothing: sg holds no Gaussians then)
         uint4 fr[NIT];
         load_feats(sg[0], fr);
-        store_feats(fr, sft[0]);
+        store_feats(sg[0], fr, sft[0]);
     }
     __syncthreads();
 
@@ -134,24 +153,25 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
     bool done = !inside;
     uint32_t last = 0;
 
-    int b = 0;
-    for (uint32_t base = s; base < e; base += FK, b ^= 1) {
-        const int nb = b ^ 1;
-        // chunk c+1's records to LDS; chunk c+2's records and chunk c+1's features in flight
-        RecFetch nxt2;
-        if (threadIdx.x < FK) {
-            srec[nb][threadIdx.x] = nxt.r;
-            nxt2 = fetch_rec(a, v, base + 2 * FK, e, threadIdx.x);
+    int b3 = 0, b2 = 0;   // chunk index mod 3 and mod 2
+    for (uint32_t cpos = 0; cpos < len; cpos += FK) {
+        const int n3 = b3 == 2 ? 0 : b3 + 1, nn3 = n3 == 2 ? 0 : n3 + 1;
+        // chunk c+2's records and Gaussians, chunk c+3's ranks, chunk c+1's features: all in flight now
+        Rec r2;
+        uint32_t g2 = 0u, rk3 = 0u;
+        if (k < FK) {
+            get_rec(rk2, r2, g2);
+            rk3 = list_load(list_rs, cpos + (uint32_t)(3 * FK + k));
         }
         uint4 fr[NIT];
-        load_feats(sg[nb], fr);
+        load_feats(sg[n3], fr);
 
         // alpha of this lane's eight Gaussians and their transmittance product
         float al[8];
         float P = 1.0f;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const AlphaEval ae = eval_alpha(srec[b][8 * q + m], x, y);
+            const AlphaEval ae = eval_alpha(srec[b3][8 * q + m], x, y);
             al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
             P *= (1.0f - al[m]);
         }
@@ -173,12 +193,12 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
                     term = true;
                 } else {
                     wv = al[m] * Tl;
-                    const Rec& r = srec[b][8 * q + m];
+                    const Rec& r = srec[b3][8 * q + m];
                     c0 += wv * r.r2.y;
                     c1 += wv * r.r2.z;
                     c2 += wv * r.r2.w;
                     Tl = Tn;
-                    mylast = base - s + 8 * q + m + 1;
+                    mylast = cpos + 8 * q + m + 1;
                 }
             }
             const __bf16 h = (__bf16)wv;
@@ -203,17 +223,23 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
         // W times the feature chunk
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sft[b][(j * 16 + xi) * FKP + 8 * q]);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sft[b2][(j * 16 + xi) * FKP + 8 * q]);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv, acc[j], 0, 0, 0);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv, acc[j], 0, 0, 0);
         }
-        // chunk c+1's features to LDS; chunk c+2's g for the next prefetch
-        store_feats(fr, sft[nb]);
-        if (threadIdx.x < FK) {
-            sg[b][threadIdx.x] = nxt2.g;
-            nxt = nxt2;
+        // chunk c+1's features and chunk c+2's records to LDS
+        store_feats(sg[n3], fr, sft[b2 ^ 1]);
+        if (k < FK) {
+            put_rec(nn3, cpos + (uint32_t)(2 * FK + k), r2, g2);
+            rk2 = rk3;
         }
-        if (__syncthreads_count(!done) == 0) break;
+        // leave when every pixel of the workgroup has stopped (flags double-buffered by chunk parity)
+        if (lane == 0) sbusy[b2][w] = ballot64(!done) != 0 ? 1 : 0;
+        __syncthreads();
+        const uint4 bz = *reinterpret_cast<const uint4*>(sbusy[b2]);
+        if ((bz.x | bz.y | bz.z | bz.w) == 0u) break;
+        b3 = n3;
+        b2 ^= 1;
     }
 
     // colour: the four lanes of a pixel hold partial sums

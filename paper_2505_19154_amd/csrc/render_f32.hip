@@ -55,10 +55,9 @@ __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable 
             const int64_t i = base + threadIdx.x;
             const uint32_t j = inst_rank(a.keys, a.vals, i, a.rank_bits, a.packed);
             const uint32_t g = a.order[j];
-            const int64_t ri = ((int64_t)v * a.n + g) * 3;
-            srec[threadIdx.x].r0 = a.rec[ri];
-            srec[threadIdx.x].r1 = a.rec[ri + 1];
-            srec[threadIdx.x].r2 = a.rec[ri + 2];
+            srec[threadIdx.x].r0 = a.rrec[3 * (int64_t)j];
+            srec[threadIdx.x].r1 = a.rrec[3 * (int64_t)j + 1];
+            srec[threadIdx.x].r2 = a.rrec[3 * (int64_t)j + 2];
             if (DS > 0) {
 #pragma unroll
                 for (int c = 0; c < DS; ++c)
@@ -301,12 +300,20 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
     }
 }
 
-__global__ __launch_bounds__(256) void k_rank_of(const uint32_t* __restrict__ order, int64_t n, int64_t total,
-                                                 uint32_t* rank_of) {
+// Per depth rank j (view v = j / n): the rank of each (view, Gaussian) and the
+// screen records in rank order, so that a tile list entry (a rank) reaches its
+// record with one load.
+__global__ __launch_bounds__(256) void k_rank_tables(const uint32_t* __restrict__ order, const float4* __restrict__ rec,
+                                                     int64_t n, int64_t total, uint32_t* __restrict__ rank_of,
+                                                     float4* __restrict__ rrec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= total) return;
     const int64_t v = j / n;
-    rank_of[v * n + order[j]] = (uint32_t)(j - v * n);
+    const int64_t i = v * n + order[j];
+    rank_of[i] = (uint32_t)(j - v * n);
+    rrec[3 * j] = rec[3 * i];
+    rrec[3 * j + 1] = rec[3 * i + 1];
+    rrec[3 * j + 2] = rec[3 * i + 2];
 }
 
 __global__ __launch_bounds__(256) void k_fuse_finalize(const float* sum, const float* comp, const float* wsum,
@@ -366,8 +373,10 @@ void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, b
         launch_bwd_k<16>(a, vt, n_tiles, fuse, s);
 }
 
-void launch_rank_of(const uint32_t* order, int64_t n, int64_t total, uint32_t* rank_of, hipStream_t s) {
-    hipLaunchKernelGGL(k_rank_of, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, order, n, total, rank_of);
+void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
+                        float4* rrec, hipStream_t s) {
+    hipLaunchKernelGGL(k_rank_tables, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, order, rec, n, total,
+                       rank_of, rrec);
 }
 
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
