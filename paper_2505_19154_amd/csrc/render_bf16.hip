@@ -43,6 +43,7 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
 template <int DS, int ROWS>
 __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
+    static_assert(NB % 2 == 0, "channel blocks are processed in pairs");
     constexpr int NT = 64 * ROWS;                        // threads
     constexpr int NIT = (FK * (DS / 8) + NT - 1) / NT;   // feature items per thread
     __shared__ Rec srec[3][FK];
@@ -220,12 +221,16 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
         lm = max(lm, (uint32_t)__shfl_xor((int)lm, 32, 64));
         last = max(last, lm);
 
-        // W times the feature chunk
+        // W times the feature chunk (channel blocks in pairs, so that the hi and
+        // lo products of one block are not issued back to back)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sft[b2][(j * 16 + xi) * FKP + 8 * q]);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv, acc[j], 0, 0, 0);
+        for (int j = 0; j < NB; j += 2) {
+            const bf16x8 bv0 = *reinterpret_cast<const bf16x8*>(&sft[b2][(j * 16 + xi) * FKP + 8 * q]);
+            const bf16x8 bv1 = *reinterpret_cast<const bf16x8*>(&sft[b2][((j + 1) * 16 + xi) * FKP + 8 * q]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv0, acc[j], 0, 0, 0);
+            acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv1, acc[j + 1], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv0, acc[j], 0, 0, 0);
+            acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv1, acc[j + 1], 0, 0, 0);
         }
         // chunk c+1's features and chunk c+2's records to LDS
         store_feats(sg[n3], fr, sft[b2 ^ 1]);

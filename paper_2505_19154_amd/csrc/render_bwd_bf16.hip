@@ -215,23 +215,25 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             const float y = (float)(ty * TILE + 2 * w + h) + 0.5f;
             const int n = (2 * w + h) * TILE + xi;
             // 1. G^T[k][px] = f_k . dF(px): lane gets k = 16 kb + 4 q + r for its pixel
+            // (the two half-chunks' accumulations are interleaved: two
+            // independent MFMA chains instead of one chain twice as long)
             f32x4 gk[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
             if (has_df) {
 #pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-                    for (int st = 0; st < NS; ++st) {
-                        const bf16x8 fa =
-                            *reinterpret_cast<const bf16x8*>(&sfeat[(16 * kb + xi) * DP + 32 * st + 8 * q]);
-                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfh[h][st], gk[kb], 0, 0, 0);
-                        gk[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, dfl[h][st], gk[kb], 0, 0, 0);
-                    }
+                for (int st = 0; st < NS; ++st) {
+                    const bf16x8 fa0 = *reinterpret_cast<const bf16x8*>(&sfeat[xi * DP + 32 * st + 8 * q]);
+                    const bf16x8 fa1 = *reinterpret_cast<const bf16x8*>(&sfeat[(16 + xi) * DP + 32 * st + 8 * q]);
+                    gk[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, dfh[h][st], gk[0], 0, 0, 0);
+                    gk[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, dfh[h][st], gk[1], 0, 0, 0);
+                    gk[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, dfl[h][st], gk[0], 0, 0, 0);
+                    gk[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, dfl[h][st], gk[1], 0, 0, 0);
+                }
             }
             // 2. back to front: half-chunk kb = 1 (positions 16..31), then kb = 0
 #pragma unroll
             for (int kb = 1; kb >= 0; --kb) {
                 asm volatile("" ::: "memory");
-                float al[4], gg[4];
+                float al[4], gg[4], iv[4];   // iv = 1 / (1 - alpha), by the hardware reciprocal
                 bool on[4];
                 float P = 1.0f, R = 0.0f, trel = 1.0f;
 #pragma unroll
@@ -242,8 +244,9 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && ae.alpha >= ALPHA_MIN;
                     al[r] = ae.alpha;
                     gg[r] = rc.r2.y * dCp[h][0] + rc.r2.z * dCp[h][1] + rc.r2.w * dCp[h][2] + gk[kb][r];
+                    iv[r] = __builtin_amdgcn_rcpf(1.0f - al[r]);
                     if (on[r]) {
-                        trel = trel / (1.0f - al[r]);
+                        trel = trel * iv[r];
                         R += al[r] * trel * gg[r];
                         P *= (1.0f - al[r]);
                     }
@@ -254,19 +257,19 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                 const float R0 = __shfl(R, xi, 64), R1 = __shfl(R, xi + 16, 64), R2 = __shfl(R, xi + 32, 64),
                             R3 = __shfl(R, xi + 48, 64);
                 const float Te3 = T[h], Se3 = S[h];
-                const float Te2 = Te3 / P3, Se2 = Se3 + Te3 * R3;
-                const float Te1 = Te2 / P2, Se1 = Se2 + Te2 * R2;
-                const float Te0 = Te1 / P1, Se0 = Se1 + Te1 * R1;
+                const float Te2 = Te3 * __builtin_amdgcn_rcpf(P3), Se2 = Se3 + Te3 * R3;
+                const float Te1 = Te2 * __builtin_amdgcn_rcpf(P2), Se1 = Se2 + Te2 * R2;
+                const float Te0 = Te1 * __builtin_amdgcn_rcpf(P1), Se0 = Se1 + Te1 * R1;
                 float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
                 float Sc = q == 3 ? Se3 : (q == 2 ? Se2 : (q == 1 ? Se1 : Se0));
-                T[h] = Te0 / P0;
+                T[h] = Te0 * __builtin_amdgcn_rcpf(P0);
                 S[h] = Se0 + Te0 * R0;
 #pragma unroll
                 for (int r = 3; r >= 0; --r) {
                     const int k = 16 * kb + 4 * q + r;
                     float wv = 0.0f, dpow = 0.0f;
                     if (on[r]) {
-                        const float inv = 1.0f / (1.0f - al[r]);
+                        const float inv = iv[r];
                         const float Tk = Tc * inv;
                         wv = al[r] * Tk;
                         const float dalpha = Tk * gg[r] - (Sc + TdT[h]) * inv;
@@ -295,35 +298,49 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         __syncthreads();
 
         // 3. Gaussian-parallel sums over the tile's pixels: lane = position k
-        //    (consecutive lanes read consecutive addresses), each half-wave a
-        //    group of 16 pixels; then the 16 groups are added in a fixed order
-        //    (the two of a wave, then the waves in order).
+        //    (consecutive lanes read consecutive addresses), each half-wave one
+        //    pixel row; then the 16 rows are added in a fixed order (the two of
+        //    a wave, then the waves in order).  The screen-space terms are
+        //    moments of dL/dpower over the row: with a = e.d and b = e x d
+        //    linear in d = (dx, dy), and dy fixed along a row,
+        //      sum dp (q1 a e_x - q2 b e_y) = A Sx + B dy S0,
+        //      sum dp (q1 a e_y + q2 b e_x) = B Sx + C dy S0,
+        //    A = q1 e_x^2 + q2 e_y^2, B = (q1 - q2) e_x e_y, C = q1 e_y^2 + q2 e_x^2,
+        //    S0 = sum dp, Sx = sum dp dx, Sxx = sum dp dx^2.
         {
             const int k = lane & 31, pg = 2 * w + (lane >> 5);
             const Rec rc = srec[k];
-            float qv[10];
-#pragma unroll
-            for (int m = 0; m < 10; ++m) qv[m] = 0.0f;
-            const float ex = rc.r1.x, ey = rc.r1.y;
+            const float ex = rc.r1.x, ey = rc.r1.y, q1 = rc.r1.z, q2 = rc.r1.w;
+            const float dy = (((float)(ty * TILE + pg) + 0.5f) - rc.r0.y) - rc.r0.w;
+            const float dx0 = (((float)(tx * TILE) + 0.5f) - rc.r0.x) - rc.r0.z;
+            float s0 = 0.0f, sx = 0.0f, sxx = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, ws = 0.0f;
+#pragma unroll 4
             for (int m = 0; m < 16; ++m) {
                 const int n = pg * 16 + m;
                 const float dp = sdp[n * SK + k], wv = sw[n * SK + k];
-                if (dp != 0.0f || wv != 0.0f) {
-                    const float xx = (float)(tx * TILE + (n & 15)) + 0.5f, yy = (float)(ty * TILE + (n >> 4)) + 0.5f;
-                    const AlphaEval ae = eval_alpha(rc, xx, yy);
-                    const float qa = rc.r1.z * ae.a, qb = rc.r1.w * ae.b;
-                    qv[0] += dp * (-2.0f * LN2 * (qa * ex - qb * ey));
-                    qv[1] += dp * (-2.0f * LN2 * (qa * ey + qb * ex));
-                    qv[2] += dp * (-0.5f * ae.dx * ae.dx);
-                    qv[3] += dp * (-ae.dx * ae.dy);
-                    qv[4] += dp * (-0.5f * ae.dy * ae.dy);
-                    qv[5] += dp;
-                    qv[6] += wv * sdc[3 * n];
-                    qv[7] += wv * sdc[3 * n + 1];
-                    qv[8] += wv * sdc[3 * n + 2];
-                    qv[9] += wv;
-                }
+                const float dx = dx0 + (float)m;
+                const float pdx = dp * dx;
+                s0 += dp;
+                sx += pdx;
+                sxx = __builtin_fmaf(pdx, dx, sxx);
+                c0 = __builtin_fmaf(wv, sdc[3 * n], c0);
+                c1 = __builtin_fmaf(wv, sdc[3 * n + 1], c1);
+                c2 = __builtin_fmaf(wv, sdc[3 * n + 2], c2);
+                ws += wv;
             }
+            const float A = q1 * ex * ex + q2 * ey * ey, B = (q1 - q2) * ex * ey, C = q1 * ey * ey + q2 * ex * ex;
+            const float sy = dy * s0;
+            float qv[10];
+            qv[0] = -2.0f * LN2 * (A * sx + B * sy);
+            qv[1] = -2.0f * LN2 * (B * sx + C * sy);
+            qv[2] = -0.5f * sxx;
+            qv[3] = -dy * sx;
+            qv[4] = -0.5f * dy * sy;
+            qv[5] = s0;
+            qv[6] = c0;
+            qv[7] = c1;
+            qv[8] = c2;
+            qv[9] = ws;
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
                 qv[m] += __shfl_xor(qv[m], 32, 64);
