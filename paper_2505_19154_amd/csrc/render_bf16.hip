@@ -186,20 +186,39 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
         bf16x8 ahi, alo;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
+            // Both forms of the step give the same bits (colour by explicit
+            // fused multiply-adds; a Gaussian that does not blend adds w = 0
+            // exactly).  The branch-free form needs more registers than the
+            // 1024-thread shapes have.
             float wv = 0.0f;
-            if (!dl && al[m] > 0.0f) {
+            const Rec& r = srec[b3][8 * q + m];
+            if constexpr (ROWS == 8) {
                 const float Tn = Tl * (1.0f - al[m]);
-                if (Tn < T_MIN) {
-                    dl = true;
-                    term = true;
-                } else {
-                    wv = al[m] * Tl;
-                    const Rec& r = srec[b3][8 * q + m];
-                    c0 += wv * r.r2.y;
-                    c1 += wv * r.r2.z;
-                    c2 += wv * r.r2.w;
-                    Tl = Tn;
-                    mylast = cpos + 8 * q + m + 1;
+                const bool act = !dl && al[m] > 0.0f;
+                const bool stop = act && Tn < T_MIN;
+                const bool blend = act && !stop;
+                wv = blend ? al[m] * Tl : 0.0f;
+                c0 = __builtin_fmaf(wv, r.r2.y, c0);
+                c1 = __builtin_fmaf(wv, r.r2.z, c1);
+                c2 = __builtin_fmaf(wv, r.r2.w, c2);
+                Tl = blend ? Tn : Tl;
+                mylast = blend ? cpos + 8 * q + m + 1 : mylast;
+                dl = dl || stop;
+                term = term || stop;
+            } else {
+                if (!dl && al[m] > 0.0f) {
+                    const float Tn = Tl * (1.0f - al[m]);
+                    if (Tn < T_MIN) {
+                        dl = true;
+                        term = true;
+                    } else {
+                        wv = al[m] * Tl;
+                        c0 = __builtin_fmaf(wv, r.r2.y, c0);
+                        c1 = __builtin_fmaf(wv, r.r2.z, c1);
+                        c2 = __builtin_fmaf(wv, r.r2.w, c2);
+                        Tl = Tn;
+                        mylast = cpos + 8 * q + m + 1;
+                    }
                 }
             }
             const __bf16 h = (__bf16)wv;

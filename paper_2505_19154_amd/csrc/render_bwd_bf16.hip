@@ -245,11 +245,11 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     al[r] = ae.alpha;
                     gg[r] = rc.r2.y * dCp[h][0] + rc.r2.z * dCp[h][1] + rc.r2.w * dCp[h][2] + gk[kb][r];
                     iv[r] = __builtin_amdgcn_rcpf(1.0f - al[r]);
-                    if (on[r]) {
-                        trel = trel * iv[r];
-                        R += al[r] * trel * gg[r];
-                        P *= (1.0f - al[r]);
-                    }
+                    // (branch-free: a position that does not blend leaves the state as is)
+                    const float tn = trel * iv[r];
+                    R = on[r] ? __builtin_fmaf(al[r] * tn, gg[r], R) : R;
+                    P = on[r] ? P * (1.0f - al[r]) : P;
+                    trel = on[r] ? tn : trel;
                 }
                 // entry state of every lane, scanning from the back (lane q = 3 first)
                 const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
@@ -267,17 +267,15 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 #pragma unroll
                 for (int r = 3; r >= 0; --r) {
                     const int k = 16 * kb + 4 * q + r;
-                    float wv = 0.0f, dpow = 0.0f;
-                    if (on[r]) {
-                        const float inv = iv[r];
-                        const float Tk = Tc * inv;
-                        wv = al[r] * Tk;
-                        const float dalpha = Tk * gg[r] - (Sc + TdT[h]) * inv;
-                        Sc += wv * gg[r];
-                        Tc = Tk;
-                        // alpha < ALPHA_MAX exactly when o G was not clamped
-                        dpow = al[r] < ALPHA_MAX ? dalpha * al[r] : 0.0f;
-                    }
+                    const float inv = iv[r];
+                    const float Tk = Tc * inv;
+                    const float wb = al[r] * Tk;
+                    const float dalpha = Tk * gg[r] - (Sc + TdT[h]) * inv;
+                    const float wv = on[r] ? wb : 0.0f;
+                    // alpha < ALPHA_MAX exactly when o G was not clamped
+                    const float dpow = (on[r] && al[r] < ALPHA_MAX) ? dalpha * al[r] : 0.0f;
+                    Sc = on[r] ? __builtin_fmaf(wb, gg[r], Sc) : Sc;
+                    Tc = on[r] ? Tk : Tc;
                     sw[n * SK + k] = wv;
                     sdp[n * SK + k] = dpow;
                 }
@@ -472,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 const AlphaEval ae = eval_alpha(srec[k], x, y);
                 on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
                 al[r] = ae.alpha;
-                if (on[r]) P *= (1.0f - al[r]);
+                P = on[r] ? P * (1.0f - al[r]) : P;
             }
             const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
                         P3 = __shfl(P, xi + 48, 64);
@@ -483,12 +481,9 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
-                float wv = 0.0f;
-                if (on[r]) {
-                    const float Tk = Tc * __builtin_amdgcn_rcpf(1.0f - al[r]);
-                    wv = al[r] * Tk;
-                    Tc = Tk;
-                }
+                const float Tk = Tc * __builtin_amdgcn_rcpf(1.0f - al[r]);
+                const float wv = on[r] ? al[r] * Tk : 0.0f;
+                Tc = on[r] ? Tk : Tc;
                 const __bf16 hh = (__bf16)wv;
                 swh[k * PP + n] = hh;
                 swl[k * PP + n] = (__bf16)(wv - (float)hh);
