@@ -51,6 +51,7 @@ extern "C" {
 
 #define FH_VERSION 1
 #define FH_MAX_VIEWS 32
+#define FH_WS_SLOTS 48   /* capacity of fh_plan.off (workspace sub-buffers in use: fh_plan.n_ws) */
 #define FH_TILE 16
 
 typedef enum {
@@ -133,8 +134,10 @@ typedef struct {
     int64_t tile_off[FH_MAX_VIEWS + 1];
     int32_t tiles_x[FH_MAX_VIEWS], tiles_y[FH_MAX_VIEWS];
     fh_tuning tuning;                /* launch shape (see fh_tuning) */
-    /* workspace layout: byte offsets of the sub-buffers, and the total */
-    size_t off[32];
+    /* workspace layout: byte offsets of the n_ws sub-buffers (each 256-byte
+     * aligned, ascending, the last one ending at or before ws_bytes), the total */
+    int32_t n_ws;
+    size_t off[FH_WS_SLOTS];
     size_t ws_bytes;
 } fh_plan;
 

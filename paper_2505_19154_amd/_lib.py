@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfhgs.so")
 
 FH_MAX_VIEWS = 32
+FH_WS_SLOTS = 48
 FH_TILE = 16
 
 FH_OK, FH_E_INVALID, FH_E_UNSUPPORTED, FH_E_HIP, FH_E_CAPACITY = 0, -1, -2, -3, -4
@@ -46,7 +47,8 @@ class FhPlan(ctypes.Structure):
                 ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
                 ("cams", FhCamera * FH_MAX_VIEWS), ("pix_off", _i64 * (FH_MAX_VIEWS + 1)),
                 ("tile_off", _i64 * (FH_MAX_VIEWS + 1)), ("tiles_x", _i32 * FH_MAX_VIEWS),
-                ("tiles_y", _i32 * FH_MAX_VIEWS), ("tuning", FhTuning), ("off", _sz * 32), ("ws_bytes", _sz)]
+                ("tiles_y", _i32 * FH_MAX_VIEWS), ("tuning", FhTuning), ("n_ws", _i32), ("off", _sz * FH_WS_SLOTS),
+                ("ws_bytes", _sz)]
 
 
 class FhImage(ctypes.Structure):

@@ -246,14 +246,18 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
     sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
     sz[WS_VSEG] = (size_t)total * 2 * u4;
-    sz[WS_LONG] = (size_t)(total + n) * u4;
+    sz[WS_LONG] = (size_t)(total + 3 * n) * u4;
     sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
     sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
     sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
     sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
     sz[WS_VGID] = (size_t)visit_capacity * u4;
     sz[WS_RREC] = (size_t)total * 3 * 16;
+    sz[WS_UNIT_OWNER] = (size_t)fuse_unit_capacity(visit_capacity) * u4;
+    sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
+    static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
     size_t off = 0;
+    plan->n_ws = WS_COUNT;
     for (int i = 0; i < WS_COUNT; ++i) {
         plan->off[i] = off;
         off += (sz[i] + 255) & ~(size_t)255;
@@ -460,6 +464,9 @@ static void fill_reduce_args(const fh_plan* p, void* ws, ReduceArgs& r) {
     r.vsorted = cbuf<uint32_t>(p, ws, (visit_sort_passes(p) % 2) ? WS_VVAL_B : WS_VVAL_A);
     r.counters = buf<Counters>(p, ws, WS_COUNTERS);
     r.long_list = buf<uint32_t>(p, ws, WS_LONG);
+    r.unit_owner = buf<uint32_t>(p, ws, WS_UNIT_OWNER);
+    r.upart = buf<float>(p, ws, WS_UPART);
+    r.unit_cap = fuse_unit_capacity(p->visit_capacity);
     r.n = p->n;
     r.total = (int64_t)p->n * p->n_views;
     r.part_geom = cbuf<float>(p, ws, WS_PART_GEOM);

@@ -54,10 +54,12 @@ enum WsBuf {
     WS_VKEY_B,
     WS_VVAL_A,         // u32 [visit_cap] visit index, sorted by rank
     WS_VVAL_B,
-    WS_LONG,           // u32 [V*N + N] lists of long reduction segments
+    WS_LONG,           // u32 [V*N + 3N] lists of long reduction segments (+ unit bases), short fusion list
     WS_VREC,           // float4 [visit_cap * 3] screen record of each visited instance
     WS_VGID,           // u32 [visit_cap] Gaussian of each visited instance
     WS_RREC,           // float4 [V*N*3] screen records in depth-rank order
+    WS_UNIT_OWNER,     // u32 [unit_cap] long-fusion slot of each unit
+    WS_UPART,          // float [unit_cap * (2 d + 2)] compensated partial sums of each unit
     WS_COUNT
 };
 
@@ -68,8 +70,10 @@ struct Counters {
     unsigned int inst_overflow;
     unsigned int visit_overflow;
     unsigned int n_long_geom;   // ranks whose visit segment goes to the workgroup-wide reduction
-    unsigned int n_long_fuse;   // Gaussians whose fusion goes to the workgroup-wide reduction
-    unsigned int pad[6];
+    unsigned int n_long_fuse;   // Gaussians whose fusion goes to the unit-wise reduction
+    unsigned int n_fuse_units;  // units (runs of consecutive visits) of those Gaussians
+    unsigned int n_short_fuse;  // Gaussians whose fusion is summed by one wavefront
+    unsigned int pad[4];
 };
 
 // Per-view constants passed by value to kernels.

@@ -115,7 +115,11 @@ struct ReduceArgs {
     const uint32_t* vseg;      // [V*N][2] per-rank [start, end) into vsorted
     const uint32_t* vsorted;   // visit indices sorted by rank (stable: row-major tiles)
     Counters* counters;
-    uint32_t* long_list;       // [total] ranks, then [n] Gaussians, queued for workgroup-wide sums
+    uint32_t* long_list;       // [total] ranks (geometry), [n] long Gaussians (fusion), [n] their first unit,
+                               // [n] short Gaussians (fusion)
+    uint32_t* unit_owner;      // [unit_cap] long-fusion slot of each unit
+    float* upart;              // [unit_cap][2 d + 2] unit partials (sum, compensation per channel; weight pair)
+    int64_t unit_cap;
     int64_t n, total;
     const float* part_geom;
     float* grad2d;
@@ -141,6 +145,8 @@ void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, in
 void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s);
 void launch_reduce_geom(const ReduceArgs& a, hipStream_t s);
 void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
+// units available for the long fusion reduction at a visit capacity (see reduce.hip)
+int64_t fuse_unit_capacity(int64_t visit_capacity);
 void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
                         float4* rrec, hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,

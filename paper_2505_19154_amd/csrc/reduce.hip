@@ -16,6 +16,7 @@ namespace fh {
 
 constexpr uint32_t LONG_GEOM = 64;    // visits above which a rank goes to the workgroup reduction
 constexpr uint32_t LONG_FUSE = 32;    // same for fusion (per Gaussian, all views)
+constexpr uint32_t FUSE_UNIT = 64;    // visits per unit of the long fusion reduction
 
 __device__ __forceinline__ uint32_t rank_of_inst(const uint32_t* keys, const uint32_t* vals, int64_t i, int rank_bits,
                                                  int packed) {
@@ -32,6 +33,8 @@ __global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.counters->n_long_geom = 0;
         a.counters->n_long_fuse = 0;
+        a.counters->n_fuse_units = 0;
+        a.counters->n_short_fuse = 0;
     }
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -126,154 +129,244 @@ __global__ __launch_bounds__(256) void k_reduce_geom_long(ReduceArgs a) {
     }
 }
 
-// The visits of one wavefront, in its fixed order, Neumaier-added into the
-// lane's channels c = lane + 64 m (m < NC) and the weight pair.  `stride` and
-// `phase` select the wavefront's share: positions phase, phase + stride, ... of
-// the concatenation of the per-view segments (views ascending).  Loads are
+// Visits k0 .. k1-1 of the rank-sorted list, in order, Neumaier-added into
+// the lane's channels c = lane + 64 m (m < NC) and the weight pair.  Loads are
 // issued B visits at a time (visit indices first, then their rows), and the
 // additions then run in visit order, so batching changes no result.
 template <int NC, int B>
-__device__ __forceinline__ void accumulate_visits(const ReduceArgs& a, int64_t g, int lane, uint32_t stride,
-                                                  uint32_t phase, float* sm, float* cp, float& ws, float& wc) {
+__device__ __forceinline__ void accumulate_span(const ReduceArgs& a, int lane, uint32_t k0, uint32_t k1, float* sm,
+                                                float* cp, float& ws, float& wc) {
     const int D = a.d;
-    uint32_t off = 0;   // visits of earlier views
-    for (int v = 0; v < a.n_views; ++v) {
-        const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
-        const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
-        // first k in [b0, b1) whose position in the concatenation is phase mod stride
-        const uint32_t first = b0 + (phase + stride - off % stride) % stride;
-        for (uint32_t k0 = first; k0 < b1; k0 += stride * B) {
-            // visit indices of the batch: lane l < B loads the l-th
-            int64_t my = -1;
-            float myw = 0.0f;
-            if (lane < B) {
-                const uint32_t k = k0 + stride * (uint32_t)lane;
-                if (k < b1) {
-                    my = a.vsorted[k];
-                    myw = a.part_geom[my * 12 + 9];
-                }
-            }
-            float rows[B][NC];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int64_t idx = __shfl(my, b, 64);
-#pragma unroll
-                for (int m = 0; m < NC; ++m) {
-                    const int c = lane + 64 * m;
-                    rows[b][m] = (idx >= 0 && c < D) ? a.part_fuse[idx * D + c] : 0.0f;
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int64_t idx = __shfl(my, b, 64);
-                const float wb = __shfl(myw, b, 64);
-                if (idx >= 0) {
-#pragma unroll
-                    for (int m = 0; m < NC; ++m) neumaier_add(sm[m], cp[m], rows[b][m]);
-                    neumaier_add(ws, wc, wb);
-                }
+    for (uint32_t kb = k0; kb < k1; kb += B) {
+        // visit indices of the batch: lane l < B loads the l-th
+        int64_t my = -1;
+        float myw = 0.0f;
+        if (lane < B) {
+            const uint32_t k = kb + (uint32_t)lane;
+            if (k < k1) {
+                my = a.vsorted[k];
+                myw = a.part_geom[my * 12 + 9];
             }
         }
-        off += b1 - b0;
+        float rows[B][NC];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t idx = __shfl(my, b, 64);
+#pragma unroll
+            for (int m = 0; m < NC; ++m) {
+                const int c = lane + 64 * m;
+                rows[b][m] = (idx >= 0 && c < D) ? a.part_fuse[idx * D + c] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t idx = __shfl(my, b, 64);
+            const float wb = __shfl(myw, b, 64);
+            if (idx >= 0) {
+#pragma unroll
+                for (int m = 0; m < NC; ++m) neumaier_add(sm[m], cp[m], rows[b][m]);
+                neumaier_add(ws, wc, wb);
+            }
+        }
     }
 }
 
-// One wavefront per Gaussian: Neumaier-add its partials of every view, views
-// ascending and tiles row-major, into the persistent accumulators.
+// Positions p0 .. p1-1 of the concatenation of a Gaussian's per-view visit
+// segments (views ascending, tiles row-major within a view).
 template <int NC, int B>
-__global__ __launch_bounds__(256) void k_reduce_fuse(ReduceArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= a.n) return;
-    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+__device__ __forceinline__ void accumulate_positions(const ReduceArgs& a, int64_t g, int lane, uint32_t p0,
+                                                     uint32_t p1, float* sm, float* cp, float& ws, float& wc) {
+    uint32_t off = 0;   // visits of earlier views
+    for (int v = 0; v < a.n_views && off < p1; ++v) {
+        const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
+        const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
+        const uint32_t len = b1 - b0;
+        const uint32_t lo = p0 > off ? p0 : off, hi = p1 < off + len ? p1 : off + len;
+        if (lo < hi) accumulate_span<NC, B>(a, lane, b0 + (lo - off), b0 + (hi - off), sm, cp, ws, wc);
+        off += len;
+    }
+}
+
+__device__ __forceinline__ uint32_t fuse_visit_total(const ReduceArgs& a, int64_t g) {
     uint32_t total = 0;
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t j = (int64_t)v * a.n + a.rank_of[(int64_t)v * a.n + g];
         total += a.vseg[2 * j + 1] - a.vseg[2 * j];
     }
-    if (total == 0) return;
-    if (total > LONG_FUSE) {
-        if (lane == 0) {
-            const uint32_t slot = atomicAdd(&a.counters->n_long_fuse, 1u);
-            a.long_list[a.total + slot] = (uint32_t)g;
-        }
-        return;
-    }
-    const int D = a.d;
-    float sm[NC], cp[NC];
-#pragma unroll
-    for (int m = 0; m < NC; ++m) {
-        const int c = lane + 64 * m;
-        sm[m] = c < D ? a.acc_sum[g * D + c] : 0.0f;
-        cp[m] = c < D ? a.acc_comp[g * D + c] : 0.0f;
-    }
-    float ws = a.acc_wsum[g], wc = a.acc_wcomp[g];
-    accumulate_visits<NC, B>(a, g, lane, 1u, 0u, sm, cp, ws, wc);
-#pragma unroll
-    for (int m = 0; m < NC; ++m) {
-        const int c = lane + 64 * m;
-        if (c < D) {
-            a.acc_sum[g * D + c] = sm[m];
-            a.acc_comp[g * D + c] = cp[m];
-        }
-    }
-    if (lane == 0) {
-        a.acc_wsum[g] = ws;
-        a.acc_wcomp[g] = wc;
-    }
+    return total;
 }
 
-// One 1024-thread workgroup per long Gaussian: wave w takes every 16th visit
-// of the concatenated per-view segments, keeping its own compensated sums;
-// the 16 waves are then added into the accumulators in wave order.
-template <int NC, int B>
-__global__ __launch_bounds__(1024) void k_reduce_fuse_long(ReduceArgs a) {
-    extern __shared__ float sred[];   // [16][2][d] then [16][2] for the weights
+// One thread per Gaussian: its visit count over all views decides the
+// reduction.  Up to LONG_FUSE visits it is queued for one wavefront; beyond,
+// it is queued with its run of units of FUSE_UNIT consecutive visits.  (Queue
+// order does not matter: each Gaussian's sums depend on its own visits only.)
+__global__ __launch_bounds__(256) void k_fuse_classify(ReduceArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= a.n) return;
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t total = fuse_visit_total(a, g);
+    if (total == 0) return;
+    if (total <= LONG_FUSE) {
+        const uint32_t slot = atomicAdd(&a.counters->n_short_fuse, 1u);
+        a.long_list[a.total + 2 * a.n + slot] = (uint32_t)g;
+        return;
+    }
+    const uint32_t nu = (total + FUSE_UNIT - 1) / FUSE_UNIT;
+    const uint32_t slot = atomicAdd(&a.counters->n_long_fuse, 1u);
+    const uint32_t ub = atomicAdd(&a.counters->n_fuse_units, nu);
+    a.long_list[a.total + slot] = (uint32_t)g;
+    a.long_list[a.total + a.n + slot] = ub;
+    // (cannot happen: the units never exceed the capacity that the visit
+    // capacity implies; flagged as a visit overflow if they did)
+    if ((int64_t)ub + nu > a.unit_cap) {
+        a.counters->visit_overflow = 1u;
+        return;
+    }
+    for (uint32_t i = 0; i < nu; ++i) a.unit_owner[ub + i] = slot;
+}
+
+// One wavefront per queued short Gaussian: Neumaier-add its partials of every
+// view, views ascending and tiles row-major, into the persistent accumulators.
+template <int NC, int B>
+__global__ __launch_bounds__(256) void k_reduce_fuse_short(ReduceArgs a) {
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int lane = threadIdx.x & 63;
     const int D = a.d;
-    const uint32_t nlong = a.counters->n_long_fuse;
-    float* sw = sred + 16 * 2 * D;
-    for (uint32_t li = blockIdx.x; li < nlong; li += gridDim.x) {
-        const int64_t g = a.long_list[a.total + li];
+    const uint32_t ns = a.counters->n_short_fuse;
+    for (uint32_t si = blockIdx.x * 4 + (threadIdx.x >> 6); si < ns; si += gridDim.x * 4) {
+        const int64_t g = a.long_list[a.total + 2 * a.n + si];
+        const uint32_t total = fuse_visit_total(a, g);
         float sm[NC], cp[NC];
 #pragma unroll
-        for (int m = 0; m < NC; ++m) sm[m] = cp[m] = 0.0f;
-        float ws = 0.0f, wc = 0.0f;
-        accumulate_visits<NC, B>(a, g, lane, 16u, (uint32_t)w, sm, cp, ws, wc);
+        for (int m = 0; m < NC; ++m) {
+            const int c = lane + 64 * m;
+            sm[m] = c < D ? a.acc_sum[g * D + c] : 0.0f;
+            cp[m] = c < D ? a.acc_comp[g * D + c] : 0.0f;
+        }
+        float ws = a.acc_wsum[g], wc = a.acc_wcomp[g];
+        accumulate_positions<NC, B>(a, g, lane, 0u, total, sm, cp, ws, wc);
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
             const int c = lane + 64 * m;
             if (c < D) {
-                sred[(w * 2) * D + c] = sm[m];
-                sred[(w * 2 + 1) * D + c] = cp[m];
+                a.acc_sum[g * D + c] = sm[m];
+                a.acc_comp[g * D + c] = cp[m];
             }
         }
         if (lane == 0) {
-            sw[2 * w] = ws;
-            sw[2 * w + 1] = wc;
+            a.acc_wsum[g] = ws;
+            a.acc_wcomp[g] = wc;
         }
-        __syncthreads();
-        for (int c = threadIdx.x; c < D; c += 1024) {
-            float s = a.acc_sum[g * D + c], cc = a.acc_comp[g * D + c];
-            for (int k = 0; k < 16; ++k) {
-                neumaier_add(s, cc, sred[(k * 2) * D + c]);
-                neumaier_add(s, cc, sred[(k * 2 + 1) * D + c]);
-            }
-            a.acc_sum[g * D + c] = s;
-            a.acc_comp[g * D + c] = cc;
-        }
-        if (threadIdx.x == 0) {
-            float s = a.acc_wsum[g], cc = a.acc_wcomp[g];
-            for (int k = 0; k < 16; ++k) {
-                neumaier_add(s, cc, sw[2 * k]);
-                neumaier_add(s, cc, sw[2 * k + 1]);
-            }
-            a.acc_wsum[g] = s;
-            a.acc_wcomp[g] = cc;
-        }
-        __syncthreads();
     }
+}
+
+// One wavefront per unit: the compensated sums (from zero) of the unit's
+// FUSE_UNIT visits, written to the unit's partial row.
+template <int NC, int B>
+__global__ __launch_bounds__(256) void k_reduce_fuse_units(ReduceArgs a) {
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int lane = threadIdx.x & 63;
+    const int D = a.d;
+    const uint32_t nlong = a.counters->n_long_fuse;
+    const uint32_t nu = (int64_t)a.counters->n_fuse_units < a.unit_cap ? a.counters->n_fuse_units : (uint32_t)a.unit_cap;
+    for (uint32_t u = blockIdx.x * 4 + (threadIdx.x >> 6); u < nu; u += gridDim.x * 4) {
+        const uint32_t slot = a.unit_owner[u];
+        if (slot >= nlong) continue;
+        const int64_t g = a.long_list[a.total + slot];
+        const uint32_t i = u - a.long_list[a.total + a.n + slot];
+        float sm[NC], cp[NC];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) sm[m] = cp[m] = 0.0f;
+        float ws = 0.0f, wc = 0.0f;
+        accumulate_positions<NC, B>(a, g, lane, i * FUSE_UNIT, (i + 1) * FUSE_UNIT, sm, cp, ws, wc);
+        float* row = a.upart + (int64_t)u * (2 * D + 2);
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const int c = lane + 64 * m;
+            if (c < D) {
+                row[c] = sm[m];
+                row[D + c] = cp[m];
+            }
+        }
+        if (lane == 0) {
+            row[2 * D] = ws;
+            row[2 * D + 1] = wc;
+        }
+    }
+}
+
+// One wavefront per long Gaussian: its units' sums and compensations are
+// Neumaier-added into the accumulators, units in order.
+template <int NC, int UB>
+__global__ __launch_bounds__(256) void k_reduce_fuse_combine(ReduceArgs a) {
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int lane = threadIdx.x & 63;
+    const int D = a.d;
+    const uint32_t nlong = a.counters->n_long_fuse;
+    for (uint32_t li = blockIdx.x * 4 + (threadIdx.x >> 6); li < nlong; li += gridDim.x * 4) {
+        const int64_t g = a.long_list[a.total + li];
+        const uint32_t ub = a.long_list[a.total + a.n + li];
+        const uint32_t nu = (fuse_visit_total(a, g) + FUSE_UNIT - 1) / FUSE_UNIT;
+        if ((int64_t)ub + nu > a.unit_cap) continue;
+        float sm[NC], cp[NC];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const int c = lane + 64 * m;
+            sm[m] = c < D ? a.acc_sum[g * D + c] : 0.0f;
+            cp[m] = c < D ? a.acc_comp[g * D + c] : 0.0f;
+        }
+        float ws = a.acc_wsum[g], wc = a.acc_wcomp[g];
+        // units are read UB at a time (all loads issued, then the additions in unit order)
+        for (uint32_t i0 = 0; i0 < nu; i0 += UB) {
+            float us[UB][NC], uc[UB][NC], uw[UB][2];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                const bool have = i0 + b < nu;
+                const float* row = a.upart + (int64_t)(ub + i0 + (have ? b : 0)) * (2 * D + 2);
+#pragma unroll
+                for (int m = 0; m < NC; ++m) {
+                    const int c = lane + 64 * m;
+                    us[b][m] = c < D ? row[c] : 0.0f;
+                    uc[b][m] = c < D ? row[D + c] : 0.0f;
+                }
+                uw[b][0] = row[2 * D];
+                uw[b][1] = row[2 * D + 1];
+            }
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                if (i0 + b < nu) {
+#pragma unroll
+                    for (int m = 0; m < NC; ++m) {
+                        if (lane + 64 * m < D) {
+                            neumaier_add(sm[m], cp[m], us[b][m]);
+                            neumaier_add(sm[m], cp[m], uc[b][m]);
+                        }
+                    }
+                    neumaier_add(ws, wc, uw[b][0]);
+                    neumaier_add(ws, wc, uw[b][1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const int c = lane + 64 * m;
+            if (c < D) {
+                a.acc_sum[g * D + c] = sm[m];
+                a.acc_comp[g * D + c] = cp[m];
+            }
+        }
+        if (lane == 0) {
+            a.acc_wsum[g] = ws;
+            a.acc_wcomp[g] = wc;
+        }
+    }
+}
+
+// Upper bound of the units: a long Gaussian has more than LONG_FUSE visits, so
+// sum ceil(len / FUSE_UNIT) <= V / FUSE_UNIT + V / (LONG_FUSE + 1) <= 3 V / 64.
+int64_t fuse_unit_capacity(int64_t visit_capacity) {
+    static_assert(FUSE_UNIT == 64 && LONG_FUSE == 32, "capacity bound below assumes these");
+    return visit_capacity * 3 / 64 + 1;
 }
 
 void launch_visit_stage(const VisitStageArgs& a, int n_tiles, hipStream_t s) {
@@ -291,9 +384,11 @@ void launch_reduce_geom(const ReduceArgs& a, hipStream_t s) {
 
 template <int NC, int B>
 static void launch_reduce_fuse_nc(const ReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_reduce_fuse<NC, B>), dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
-    const size_t lds = sizeof(float) * (16 * 2 * (size_t)a.d + 32);
-    hipLaunchKernelGGL((k_reduce_fuse_long<NC, B>), dim3(512), dim3(1024), lds, s, a);
+    if (a.n == 0) return;
+    hipLaunchKernelGGL(k_fuse_classify, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reduce_fuse_short<NC, B>), dim3(2048), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reduce_fuse_units<NC, B>), dim3(2048), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reduce_fuse_combine<NC, B>), dim3(512), dim3(256), 0, s, a);
 }
 
 // channels per lane NC = ceil(d / 64); visits per batch B keep B * NC <= 32 registers of rows

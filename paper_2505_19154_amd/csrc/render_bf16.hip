@@ -258,7 +258,8 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
             rk2 = rk3;
         }
         // leave when every pixel of the workgroup has stopped (flags double-buffered by chunk parity)
-        if (lane == 0) sbusy[b2][w] = ballot64(!done) != 0 ? 1 : 0;
+        const bool wave_busy = ballot64(!done) != 0;   // (all lanes vote, outside the lane-0 store)
+        if (lane == 0) sbusy[b2][w] = wave_busy ? 1 : 0;
         __syncthreads();
         const uint4 bz = *reinterpret_cast<const uint4*>(sbusy[b2]);
         if ((bz.x | bz.y | bz.z | bz.w) == 0u) break;

@@ -24,7 +24,7 @@ _WS = {name: i for i, name in enumerate(
     ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
      "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
      "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
-     "long", "vrec", "vgid", "rrec"])}
+     "long", "vrec", "vgid", "rrec", "unit_owner", "upart"])}
 
 
 def _ptr(t):

@@ -70,6 +70,30 @@ def test_plan_init_validates_on_host():
     assert plan.n_tiles == 4 * 3 and plan.n_pixels == 64 * 48 and plan.packed_keys == 1
     assert plan.ws_bytes > 0
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 4, 16, 0, 0, cams, 1, 0, 0) == -2   # sh degree 4
+
+
+def test_workspace_regions_lie_inside_the_workspace():
+    # every sub-buffer offset is recorded (none dropped past the table's end),
+    # ascending, aligned, and inside ws_bytes; the Python names cover them all
+    from paper_2505_19154_amd import _lib, raster
+    lib = _lib.load()
+    cam = _lib.FhCamera(1920, 1080, 1000.0, 1000.0, 960.0, 540.0, (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1),
+                        (ctypes.c_float * 3)(0, 0, 4))
+    cams = (_lib.FhCamera * 1)(cam)
+    for d, form, feat in ((256, 1, 1), (64, 0, 0), (0, 0, 0)):
+        plan = _lib.FhPlan()
+        assert lib.fh_plan_init(ctypes.byref(plan), 500000, 3, d, feat, form, cams, 1, 23_000_000, 1_200_000) == 0
+        n = plan.n_ws
+        assert 0 < n <= _lib.FH_WS_SLOTS
+        assert len(raster._WS) == n
+        offs = [plan.off[i] for i in range(n)]
+        assert offs[0] == 0
+        assert all(o % 256 == 0 for o in offs)
+        assert all(b >= a for a, b in zip(offs, offs[1:]))
+        assert offs[-1] <= plan.ws_bytes
+        # the unit partials (the last region) are sized for the unit bound at this visit capacity
+        upart = plan.ws_bytes - offs[raster._WS["upart"]]
+        assert upart >= (1_200_000 * 3 // 64 + 1) * (2 * d + 2) * 4
     assert lib.fh_plan_init(ctypes.byref(plan), -1, 3, 16, 0, 0, cams, 1, 0, 0) == -1
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 1, cams, 1, 0, 0) == -2   # bf16 form, f32 feat
     assert lib.fh_status_string(-4) == b"capacity exceeded"

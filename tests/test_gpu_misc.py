@@ -232,3 +232,54 @@ def test_graph_replay_matches_eager(form):
             assert torch.equal(grads[k], grads_e[k]), (rep, k)
         assert torch.equal(acc.sum, acc_e.sum) and torch.equal(acc.wsum, acc_e.wsum), rep
         _ = (dC * 2).sum().item()   # unrelated eager work between replays
+
+
+def _column_wall_scene(d):
+    """32x16 view (two tiles).  In front, four layers of near-opaque Gaussians,
+    narrow in x, cover pixel column 0 of every row, which stops within the
+    first chunk of 32; behind, 96 faint wide Gaussians keep every other pixel
+    walking for several chunks.  A workgroup must not stop while any of its
+    pixels walks."""
+    rng = np.random.default_rng(11)
+    cam = scenegen.Camera(width=32, height=16, fx=50.0, fy=50.0, cx=16.0, cy=8.0,
+                          R=np.eye(3, dtype=np.float32), t=np.float32([0.0, 0.0, 4.0]))
+    means, scales, opac = [], [], []
+    for layer in range(4):
+        zc = 2.0 + 0.01 * layer
+        for i in range(8):
+            u, v = 0.5, 1.0 + 2.0 * i
+            means.append([(u - 16.0) * zc / 50.0, (v - 8.0) * zc / 50.0, zc - 4.0])
+            scales.append([0.2 * zc / 50.0, 2.0 * zc / 50.0, 0.2 * zc / 50.0])
+            opac.append(0.99)
+    for i in range(96):
+        zc = 4.0 + 0.005 * i
+        u, v = rng.uniform(0, 32), rng.uniform(0, 16)
+        means.append([(u - 16.0) * zc / 50.0, (v - 8.0) * zc / 50.0, zc - 4.0])
+        s = 12.0 * zc / 50.0
+        scales.append([s, s, s])
+        opac.append(0.06)
+    n = len(means)
+    g = scenegen.make_gaussians(n, 1.0, 0, d, seed=12, feat_dtype="bf16")
+    g["means"] = np.float32(means)
+    g["scales"] = np.float32(scales)
+    g["quats"] = np.tile(np.float32([1.0, 0.0, 0.0, 0.0]), (n, 1))
+    g["opacity"] = np.float32(opac)
+    return g, [cam]
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_forward_runs_until_every_pixel_stops(form):
+    g, cams = _column_wall_scene(32)
+    gpu = U.run_gpu(g, cams, None, form=form)
+    ora = U.run_oracle(g, cams)
+    v = ora["views"][0]
+    niter = v["niter"].reshape(16, 32)
+    # the premise: column 0 stops within the first chunk, the other columns walk past several
+    assert niter[:, 0].max() <= 32 and niter[:, 2:].min() > 64
+    ok = (v["flags"] & 1) == 0
+    img = gpu["img"]
+    assert np.array_equal(img.n_iter.cpu().numpy().astype(np.int64)[ok], v["niter"][ok])
+    assert U.elementwise(img.C.cpu().numpy(), v["C"], v["Cmag"], mask=ok[:, None].repeat(3, 1))[0] <= 1.0
+    assert U.elementwise(img.T.cpu().numpy(), v["T"], v["T"], mask=ok)[0] <= 1.0
+    assert U.elementwise(img.F.cpu().numpy(), v["F"], v["Fmag"], rtol=U.RTOL_FORM[form],
+                         mask=ok[:, None].repeat(32, 1))[0] <= 1.0
