@@ -78,7 +78,7 @@ def alg_bytes(kernel: str, wl, P: int, n_vis: int, n_inst: int, feat_b: int, tgt
 BRACKET_SOURCES = {
     ("project", "f32"): ("project.hip",), ("project", "bf16"): ("project.hip",),
     ("render_fwd", "f32"): ("render_f32.hip",), ("render_fwd", "bf16"): ("render_bf16.hip",),
-    ("render_bwd", "f32"): ("render_f32.hip",), ("render_bwd", "bf16"): ("render_bwd_bf16.hip",),
+    ("render_bwd", "f32"): ("render_f32.hip", "reduce.hip"), ("render_bwd", "bf16"): ("render_bwd_bf16.hip", "reduce.hip"),
     ("project_bwd", "f32"): ("project.hip",), ("project_bwd", "bf16"): ("project.hip",),
 }
 
@@ -101,7 +101,8 @@ def kernel_src_digest(kernel: str, form: str) -> str:
 BRACKET_KERNELS = {
     ("project", "f32"): ("k_project",), ("project", "bf16"): ("k_project",),
     ("render_fwd", "f32"): ("k_render_fwd_f32",), ("render_fwd", "bf16"): ("k_render_fwd_bf16",),
-    ("render_bwd", "f32"): ("k_render_bwd_f32",), ("render_bwd", "bf16"): ("k_render_bwd_bf16", "k_fuse_bf16"),
+    ("render_bwd", "f32"): ("k_visit_stage", "k_render_bwd_f32"),
+    ("render_bwd", "bf16"): ("k_visit_stage", "k_render_bwd_bf16", "k_fuse_bf16"),
     ("project_bwd", "f32"): ("k_project_bwd",), ("project_bwd", "bf16"): ("k_project_bwd",),
 }
 COPY_BYTES = 1 << 30       # the calibration kernel reads and writes this many bytes

@@ -41,7 +41,8 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
 }
 
 template <int DS, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
+// (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per CU)
+__global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
     static_assert(NB % 2 == 0, "channel blocks are processed in pairs");
     constexpr int NT = 64 * ROWS;                        // threads
@@ -189,10 +190,10 @@ __global__ __launch_bounds__(64 * ROWS) void k_render_fwd_bf16(RenderArgs a, Vie
             // Both forms of the step give the same bits (colour by explicit
             // fused multiply-adds; a Gaussian that does not blend adds w = 0
             // exactly).  The branch-free form needs more registers than the
-            // 1024-thread shapes have.
+            // shapes that keep four waves per SIMD have.
             float wv = 0.0f;
             const Rec& r = srec[b3][8 * q + m];
-            if constexpr (ROWS == 8) {
+            if constexpr (ROWS == 8 && DS > 128) {
                 const float Tn = Tl * (1.0f - al[m]);
                 const bool act = !dl && al[m] > 0.0f;
                 const bool stop = act && Tn < T_MIN;

@@ -79,15 +79,15 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     constexpr int DP = D + 8;            // padded row stride (bf16) of the feature chunk
     constexpr int NS = D / 32;           // MFMA steps over channels
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16* sfeat = reinterpret_cast<__bf16*>(smem);                         // [BK][DP]
+    __bf16* sfeat2 = reinterpret_cast<__bf16*>(smem);                        // [2][BK][DP], double-buffered
     // per (pixel, position) values, pixel-major with a padded stride SK so that
     // the walk's stores and the Gaussian-parallel reads spread over the banks
-    float* sw = reinterpret_cast<float*>(sfeat + BK * DP);                   // [256][SK] w
+    float* sw = reinterpret_cast<float*>(sfeat2 + 2 * BK * DP);              // [256][SK] w
     float* sdp = sw + TILE_PIX * SK;                                         // [256][SK] dL/dpower
     float* sdc = sdp + TILE_PIX * SK;                                        // [256][3] dC of the tile
     float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][10][BK] partial sums
-    __shared__ Rec srecb[2][BK];        // chunk records and Gaussians, double-buffered:
-    __shared__ uint32_t sgb[2][BK];     // the next chunk's arrive during this one
+    __shared__ Rec srecb[3][BK];        // chunk records and Gaussians, triple-buffered:
+    __shared__ uint32_t sgb[3][BK];     // those two chunks ahead arrive during this one
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -151,61 +151,78 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         }
     }
 
+    // all of a thread's feature rows of one chunk are requested before any is
+    // stored; a padding position reads Gaussian 0 (its contraction row is only
+    // used by positions that blend, which it never does)
+    constexpr int ITEMS = BK * (D / 8), NI = (ITEMS + 511) / 512;
+    auto load_feats = [&](const uint32_t* gl, uint4* raw) {
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int idx = threadIdx.x + 512 * it;
+            raw[it] = make_uint4(0, 0, 0, 0);
+            if (idx < ITEMS) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                const uint32_t g = gl[k];
+                const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
+                raw[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * D + dg * 8);
+            }
+        }
+    };
+    auto store_feats = [&](const uint4* raw, __bf16* dst) {
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int idx = threadIdx.x + 512 * it;
+            if (idx < ITEMS) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                *reinterpret_cast<uint4*>(&dst[k * DP + dg * 8]) = raw[it];
+            }
+        }
+    };
+
+    // prologue: records and Gaussians of the first two chunks, features of the first
     {
         const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
         stage_records(a, voff, cs0, (int)nt - cs0, srecb[0], sgb[0]);
+        if (cs0 > 0) {
+            const int cs1 = cs0 - BK > 0 ? cs0 - BK : 0;
+            stage_records(a, voff, cs1, cs0 - cs1, srecb[1], sgb[1]);
+        }
     }
     __syncthreads();
-    int b = 0;
-    for (int ce = (int)nt; ce > 0; ce -= BK, b ^= 1) {
+    if (has_df) {
+        uint4 raw[NI];
+        load_feats(sgb[0], raw);
+        store_feats(raw, sfeat2);
+    }
+    __syncthreads();
+    int b3 = 0, f2 = 0;   // this chunk's record buffer (mod 3) and feature buffer (mod 2)
+    for (int ce = (int)nt; ce > 0; ce -= BK) {
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
-        const Rec* srec = srecb[b];
-        const uint32_t* sg = sgb[b];
-        // the next chunk's records (12 dwords each, threads 0..12 BK-1) and
-        // Gaussians (threads 12 BK..13 BK-1): one dword per thread, stored at
-        // the end of this chunk; padding positions get the padding record
+        const int n3 = b3 == 2 ? 0 : b3 + 1, nn3 = n3 == 2 ? 0 : n3 + 1;
+        const Rec* srec = srecb[b3];
+        const __bf16* sfeat = sfeat2 + f2 * BK * DP;
+        // records (12 dwords each, threads 0..12 BK-1) and Gaussians (threads
+        // 12 BK..13 BK-1) of the chunk after next: one dword per thread, stored
+        // after this chunk's walk; padding positions get the padding record.
+        // (Positions nncs .. nncs + BK - 1 all lie in this tile's visits: that
+        // chunk exists only when this one and the next are full.)
         const int ncs = cs - BK > 0 ? cs - BK : 0;
-        const int ncnt = cs - ncs;
-        // (positions ncs .. ncs + BK - 1 all lie in this tile's visits, as the
-        // current chunk is full whenever there is a next one, so the load needs
-        // no guard; padding is selected after it)
-        const bool pre_on = cs > 0 && threadIdx.x < 13 * BK;
+        const int nncs = ncs - BK > 0 ? ncs - BK : 0;
+        const int nncnt = ncs - nncs;
+        const bool pre_on = ncs > 0 && threadIdx.x < 13 * BK;
         const bool pre_g = threadIdx.x >= 12 * BK;
         const int pre_k = pre_g ? (int)threadIdx.x - 12 * BK : (int)threadIdx.x / 12;
         uint32_t pre = 0u;
         if (pre_on) {
-            const uint32_t* src = pre_g ? a.vgid + ((int64_t)voff + ncs)
-                                        : reinterpret_cast<const uint32_t*>(a.vrec) + ((int64_t)voff + ncs) * 12;
+            const uint32_t* src = pre_g ? a.vgid + ((int64_t)voff + nncs)
+                                        : reinterpret_cast<const uint32_t*>(a.vrec) + ((int64_t)voff + nncs) * 12;
             pre = src[pre_g ? pre_k : (int)threadIdx.x];
         }
-        if (has_df) {
-            // all of this thread's feature rows are requested before any is stored
-            constexpr int ITEMS = BK * (D / 8), NI = (ITEMS + 511) / 512;
-            uint4 raw[NI];
-#pragma unroll
-            for (int it = 0; it < NI; ++it) {
-                const int idx = threadIdx.x + 512 * it;
-                raw[it] = make_uint4(0, 0, 0, 0);
-                if (idx < ITEMS) {
-                    // a padding position reads Gaussian 0: its contraction row
-                    // is only used by positions that blend, which it never does
-                    const int k = idx / (D / 8), dg = idx % (D / 8);
-                    const uint32_t g = sg[k];
-                    const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
-                    raw[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * D + dg * 8);
-                }
-            }
-#pragma unroll
-            for (int it = 0; it < NI; ++it) {
-                const int idx = threadIdx.x + 512 * it;
-                if (idx < ITEMS) {
-                    const int k = idx / (D / 8), dg = idx % (D / 8);
-                    *reinterpret_cast<uint4*>(&sfeat[k * DP + dg * 8]) = raw[it];
-                }
-            }
-        }
-        __syncthreads();
+        // the next chunk's features, stored after this chunk's walk
+        uint4 fnext[NI];
+        const bool fnext_on = has_df && cs > 0;
+        if (fnext_on) load_feats(sgb[n3], fnext);
 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -287,12 +304,13 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         if (pre_on) {
             const int j = (int)threadIdx.x % 12;
             const uint32_t pad = pre_g ? 0xFFFFFFFFu : (j == 4 ? 0x3f800000u : ((j == 6 || j == 7) ? 0xbf800000u : 0u));
-            const uint32_t val = pre_k < ncnt ? pre : pad;
+            const uint32_t val = pre_k < nncnt ? pre : pad;
             if (pre_g)
-                sgb[b ^ 1][pre_k] = val;
+                sgb[nn3][pre_k] = val;
             else
-                reinterpret_cast<uint32_t*>(srecb[b ^ 1])[threadIdx.x] = val;
+                reinterpret_cast<uint32_t*>(srecb[nn3])[threadIdx.x] = val;
         }
+        if (fnext_on) store_feats(fnext, sfeat2 + (f2 ^ 1) * BK * DP);
         __syncthreads();
 
         // 3. Gaussian-parallel sums over the tile's pixels: lane = position k
@@ -357,6 +375,8 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + m] = sum;
         }
         __syncthreads();
+        b3 = n3;
+        f2 ^= 1;
     }
 }
 
@@ -539,7 +559,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 template <int D>
 static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     if (grads) {
-        const size_t lds = sizeof(__bf16) * (size_t)BK * (D + 8) +
+        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (D + 8) +
                            sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * 10 * BK);
         hipLaunchKernelGGL(k_render_bwd_bf16<D>, dim3(n_tiles), dim3(512), lds, s, a, vt);
     }
