@@ -131,6 +131,7 @@ struct RadixPass {
     int64_t seg_len;
     int64_t cap;
     int blocks_per_seg;
+    int tiles_per_block;       // consecutive RADIX_TILE-key tiles one workgroup handles, in order
     int shift, bits;
 };
 
@@ -153,84 +154,115 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits
     return m;
 }
 
+// Digit counts of a workgroup's tiles (LDS atomics; counts are exact whatever
+// their order), one histogram entry per (segment, digit, workgroup).
 __global__ __launch_bounds__(RADIX_BLOCK) void k_radix_upsweep(RadixPass p) {
-    __shared__ uint32_t cnt[RADIX_BLOCK / WAVE][256];
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    __shared__ uint32_t cnt[256];
     const int seg = blockIdx.x / p.blocks_per_seg, blk = blockIdx.x % p.blocks_per_seg;
     const int radix = 1 << p.bits;
     const uint32_t mask = (uint32_t)radix - 1u;
-    for (int t = threadIdx.x; t < (RADIX_BLOCK / WAVE) * 256; t += RADIX_BLOCK) (&cnt[0][0])[t] = 0u;
+    for (int t = threadIdx.x; t < 256; t += RADIX_BLOCK) cnt[t] = 0u;
     __syncthreads();
     const int64_t len = seg_valid_len(p);
     const int64_t seg_base = (int64_t)seg * p.seg_len;
-    const int64_t wbase = (int64_t)blk * RADIX_TILE + (int64_t)w * (RADIX_ITEMS * WAVE);
-    for (int i = 0; i < RADIX_ITEMS; ++i) {
-        const int64_t pos = wbase + (int64_t)i * WAVE + lane;
-        const bool valid = pos < len;
-        if (!__any(valid)) break;
-        const uint32_t d = valid ? ((p.keys_in[seg_base + pos] >> p.shift) & mask) : 0u;
-        const uint64_t m = match_digit(d, valid, p.bits);
-        if (valid && lane == (int)__builtin_ctzll(m)) cnt[w][d] += (uint32_t)__builtin_popcountll(m);
-    }
+    const int64_t b0 = (int64_t)blk * p.tiles_per_block * RADIX_TILE;
+    const int64_t b1 = b0 + (int64_t)p.tiles_per_block * RADIX_TILE < len ? b0 + (int64_t)p.tiles_per_block * RADIX_TILE
+                                                                         : len;
+    for (int64_t pos = b0 + threadIdx.x; pos < b1; pos += RADIX_BLOCK)
+        atomicAdd(&cnt[(p.keys_in[seg_base + pos] >> p.shift) & mask], 1u);
     __syncthreads();
-    for (int t = threadIdx.x; t < radix; t += RADIX_BLOCK) {
-        uint32_t s = 0;
-        for (int k = 0; k < RADIX_BLOCK / WAVE; ++k) s += cnt[k][t];
-        p.hist[((int64_t)seg * radix + t) * p.blocks_per_seg + blk] = s;
-    }
+    for (int t = threadIdx.x; t < radix; t += RADIX_BLOCK)
+        p.hist[((int64_t)seg * radix + t) * p.blocks_per_seg + blk] = cnt[t];
 }
 
-__global__ __launch_bounds__(RADIX_BLOCK) void k_radix_downsweep(RadixPass p) {
+// Scatter of a workgroup's tiles, in order.  Per tile: stable ranks within
+// each wave by ballot matching, per-digit prefixes over the waves and over the
+// digits, the keys placed in LDS in digit order, then written out so that
+// consecutive threads write consecutive positions of each digit's run.
+__global__ __launch_bounds__(RADIX_BLOCK, 4) void k_radix_downsweep(RadixPass p) {
     __shared__ uint32_t cnt[RADIX_BLOCK / WAVE][256];
-    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t gbase[256];     // global position of the next key of each digit
+    __shared__ uint32_t lstart[256];    // block-local position of the tile's first key of each digit
+    __shared__ uint32_t wsum[RADIX_BLOCK / WAVE];
+    __shared__ uint32_t skey[RADIX_TILE];
+    __shared__ uint32_t sval[RADIX_TILE];
+    static_assert(RADIX_BLOCK == 256, "one thread per digit");
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int seg = blockIdx.x / p.blocks_per_seg, blk = blockIdx.x % p.blocks_per_seg;
     const int radix = 1 << p.bits;
     const uint32_t mask = (uint32_t)radix - 1u;
     const int64_t len = seg_valid_len(p);
-    if ((int64_t)blk * RADIX_TILE >= len) return;   // whole block past the end: nothing to move
-    for (int t = threadIdx.x; t < (RADIX_BLOCK / WAVE) * 256; t += RADIX_BLOCK) (&cnt[0][0])[t] = 0u;
-    for (int t = threadIdx.x; t < radix; t += RADIX_BLOCK)
-        gbase[t] = p.hist[((int64_t)seg * radix + t) * p.blocks_per_seg + blk];
-    __syncthreads();
     const int64_t seg_base = (int64_t)seg * p.seg_len;
-    const int64_t wbase = (int64_t)blk * RADIX_TILE + (int64_t)w * (RADIX_ITEMS * WAVE);
-    uint32_t key[RADIX_ITEMS], val[RADIX_ITEMS], rank[RADIX_ITEMS];
+    if ((int64_t)blk * p.tiles_per_block * RADIX_TILE >= len) return;   // nothing to move (uniform)
+    if ((int)threadIdx.x < radix) gbase[threadIdx.x] = p.hist[((int64_t)seg * radix + threadIdx.x) * p.blocks_per_seg + blk];
+    for (int tt = 0; tt < p.tiles_per_block; ++tt) {
+        const int64_t tb = ((int64_t)blk * p.tiles_per_block + tt) * RADIX_TILE;
+        if (tb >= len) break;                                          // uniform over the block
+        for (int t = threadIdx.x; t < (RADIX_BLOCK / WAVE) * 256; t += RADIX_BLOCK) (&cnt[0][0])[t] = 0u;
+        __syncthreads();
+        const int64_t wbase = tb + (int64_t)w * (RADIX_ITEMS * WAVE);
+        uint32_t key[RADIX_ITEMS], val[RADIX_ITEMS], rank[RADIX_ITEMS];
 #pragma unroll
-    for (int i = 0; i < RADIX_ITEMS; ++i) {
-        const int64_t pos = wbase + (int64_t)i * WAVE + lane;
-        const bool valid = pos < len;
-        key[i] = valid ? p.keys_in[seg_base + pos] : 0u;
-        if (p.vals_out) val[i] = valid ? (p.vals_in ? p.vals_in[seg_base + pos] : (uint32_t)pos) : 0u;
-        const uint32_t d = (key[i] >> p.shift) & mask;
-        const uint64_t m = match_digit(d, valid, p.bits);
-        uint32_t before = 0;
-        if (valid) before = cnt[w][d];
-        rank[i] = before + (uint32_t)__builtin_popcountll(m & lanemask_lt());
-        if (valid && lane == (int)__builtin_ctzll(m)) cnt[w][d] = before + (uint32_t)__builtin_popcountll(m);
-    }
-    __syncthreads();
-    // per-digit exclusive prefix over the block's waves, folded into rank
-    __shared__ uint32_t wpre[RADIX_BLOCK / WAVE][256];
-    for (int t = threadIdx.x; t < radix; t += RADIX_BLOCK) {
-        uint32_t run = gbase[t];
-        for (int k = 0; k < RADIX_BLOCK / WAVE; ++k) {
-            wpre[k][t] = run;
-            run += cnt[k][t];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RADIX_ITEMS; ++i) {
-        const int64_t pos = wbase + (int64_t)i * WAVE + lane;
-        if (pos < len) {
+        for (int i = 0; i < RADIX_ITEMS; ++i) {
+            const int64_t pos = wbase + (int64_t)i * WAVE + lane;
+            const bool valid = pos < len;
+            key[i] = valid ? p.keys_in[seg_base + pos] : 0u;
+            if (p.vals_out) val[i] = valid ? (p.vals_in ? p.vals_in[seg_base + pos] : (uint32_t)pos) : 0u;
             const uint32_t d = (key[i] >> p.shift) & mask;
-            // the scanned histogram already holds absolute positions (earlier
-            // segments are counted in full before this one)
-            const int64_t dst = (int64_t)wpre[w][d] + rank[i];
-            p.keys_out[dst] = key[i];
-            if (p.vals_out) p.vals_out[dst] = val[i];
+            const uint64_t m = match_digit(d, valid, p.bits);
+            uint32_t before = 0;
+            if (valid) before = cnt[w][d];
+            rank[i] = before + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+            if (valid && lane == (int)__builtin_ctzll(m)) cnt[w][d] = before + (uint32_t)__builtin_popcountll(m);
         }
+        __syncthreads();
+        // per digit (one thread each): the waves' counts become exclusive
+        // prefixes in place; the tile's count of the digit is scanned over digits
+        uint32_t tot = 0;
+        if ((int)threadIdx.x < radix) {
+            for (int k = 0; k < RADIX_BLOCK / WAVE; ++k) {
+                const uint32_t c = cnt[k][threadIdx.x];
+                cnt[k][threadIdx.x] = tot;
+                tot += c;
+            }
+        }
+        uint32_t incl = tot;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, off, WAVE);
+            if (lane >= off) incl += t;
+        }
+        if (lane == WAVE - 1) wsum[w] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        if ((int)threadIdx.x < radix) lstart[threadIdx.x] = before + incl - tot;
+        __syncthreads();
+        // keys to LDS in digit order (stable: waves, then items and lanes, in order)
+#pragma unroll
+        for (int i = 0; i < RADIX_ITEMS; ++i) {
+            const int64_t pos = wbase + (int64_t)i * WAVE + lane;
+            if (pos < len) {
+                const uint32_t d = (key[i] >> p.shift) & mask;
+                const uint32_t lp = lstart[d] + cnt[w][d] + rank[i];
+                skey[lp] = key[i];
+                if (p.vals_out) sval[lp] = val[i];
+            }
+        }
+        __syncthreads();
+        const int64_t nvalid = len - tb;
+        const int nb = nvalid < RADIX_TILE ? (int)nvalid : RADIX_TILE;
+        for (int lp = threadIdx.x; lp < nb; lp += RADIX_BLOCK) {
+            const uint32_t k = skey[lp];
+            const uint32_t d = (k >> p.shift) & mask;
+            // the scanned histogram holds absolute positions (earlier segments
+            // are counted in full before this one)
+            const int64_t dst = (int64_t)gbase[d] + (uint32_t)(lp - (int)lstart[d]);
+            p.keys_out[dst] = k;
+            if (p.vals_out) p.vals_out[dst] = sval[lp];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < radix) gbase[threadIdx.x] += tot;
     }
 }
 
@@ -242,11 +274,19 @@ int radix_sort(const uint32_t* keys_src, const uint32_t* vals_src, uint32_t* ka,
                uint32_t* vb, bool with_vals, int64_t segs, int64_t seg_len, const unsigned long long* dev_len,
                int64_t cap, int lo, int hi, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
     const int64_t span = dev_len ? cap : seg_len;
-    const int bps = (int)((span + RADIX_TILE - 1) / RADIX_TILE);
-    if (bps == 0 || segs == 0) return 0;
+    const int64_t tiles = (span + RADIX_TILE - 1) / RADIX_TILE;
+    if (tiles == 0 || segs == 0) return 0;
+    // several tiles per workgroup once there are more than ~2048 workgroups'
+    // worth: fewer histogram entries, which are written and read scattered
+    const int tpb = (int)std::min<int64_t>(8, std::max<int64_t>(1, (segs * tiles + 2047) / 2048));
+    const int bps = (int)((tiles + tpb - 1) / tpb);
+    // digits of at most 8 bits, as even as the bit count allows (13 bits: 7 + 6,
+    // so that each digit's run per tile is long enough to fill whole lines)
+    const int npass = (hi - lo + 7) / 8;
+    const int width = npass > 0 ? (hi - lo + npass - 1) / npass : 8;
     int pass = 0;
-    for (int shift = lo; shift < hi; shift += 8, ++pass) {
-        const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
+    for (int shift = lo; shift < hi; shift += width, ++pass) {
+        const int bits = (hi - shift) < width ? (hi - shift) : width;
         RadixPass p;
         const bool first = (pass == 0);
         const bool to_b = (pass % 2 == 0);
@@ -259,6 +299,7 @@ int radix_sort(const uint32_t* keys_src, const uint32_t* vals_src, uint32_t* ka,
         p.seg_len = seg_len;
         p.cap = cap;
         p.blocks_per_seg = bps;
+        p.tiles_per_block = tpb;
         p.shift = shift;
         p.bits = bits;
         const unsigned nblk = (unsigned)(segs * bps);
@@ -306,12 +347,14 @@ __global__ void k_check_capacity(Counters* counters, int64_t cap) {
 
 // Instance generation.  Each workgroup writes a fixed range of 2048 output
 // instances (so that the few huge Gaussians at the front of the depth order
-// spread over many workgroups); the ranks covering the range are found by a
-// binary search of the tiles-per-rank scan staged in LDS.  Every binned rank
-// owns at least one instance, so within one view a range spans at most 2048
-// ranks and the LDS window always holds them; only a range that crosses a
-// view boundary with culled (zero-instance) ranks can need more, and then
-// searches the scan in global memory.
+// spread over many workgroups).  The ranks covering the range are staged in
+// LDS with their first instance; every rank marks the position where its
+// instances start (the largest rank wins: a rank with no instance starts where
+// the next one does), and a prefix maximum over the range gives every
+// instance its rank.  Every binned rank owns at least one instance, so within
+// one view a range spans at most 2048 ranks and the LDS window holds them;
+// only a range that crosses a view boundary with culled (zero-instance) ranks
+// can need more, and then searches the scan in global memory.
 constexpr int DUP_TILE = 2048;
 constexpr int DUP_WIN = 2048;
 
@@ -324,9 +367,47 @@ __device__ __forceinline__ int64_t last_le(const uint32_t* off, int64_t lo, int6
     return lo;
 }
 
+// The same search by all 256 threads of a workgroup (uniform arguments): each
+// round probes 256 evenly spaced entries and keeps the interval after the last
+// one <= i (the probes' test is true for a prefix of the threads), so a search
+// over R entries takes log_256(R) rounds of parallel loads instead of log2(R)
+// dependent ones.
+__device__ __forceinline__ int64_t block_last_le(const uint32_t* off, int64_t lo, int64_t hi, uint32_t i) {
+    while (hi - lo >= 256) {
+        const int64_t step = (hi - lo + 256) / 256;
+        const int64_t pr = lo + (int64_t)threadIdx.x * step;
+        const int cnt = __syncthreads_count(pr <= hi && off[pr] <= i);
+        lo += (int64_t)(cnt - 1) * step;
+        hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+    }
+    const int64_t pr = lo + (int64_t)threadIdx.x;
+    const int cnt = __syncthreads_count(pr <= hi && off[pr] <= i);
+    return lo + cnt - 1;
+}
+
+// q = a / b, r = a % b for a < 2^22, 1 <= b < 2^12: the float estimate is
+// within one of the quotient (relative error below 2^-22), then corrected.
+__device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q, uint32_t& r) {
+    uint32_t qq = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+    int32_t rr = (int32_t)a - (int32_t)(qq * b);
+    if (rr < 0) {
+        qq -= 1u;
+        rr += (int32_t)b;
+    }
+    if (rr >= (int32_t)b) {
+        qq += 1u;
+        rr -= (int32_t)b;
+    }
+    q = qq;
+    r = (uint32_t)rr;
+}
+
 __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
+    constexpr int PER = DUP_TILE / 256;   // positions per thread in the prefix maximum
     __shared__ uint32_t offs[DUP_WIN + 1];
     __shared__ int4 rects[DUP_WIN];
+    __shared__ uint32_t owner[DUP_TILE];  // window index + 1 of the rank owning each position
+    __shared__ uint32_t wmax[4];
     __shared__ long long s_r0;
     __shared__ int s_win;
     if (a.counters->inst_overflow) return;   // uniform over the block
@@ -334,12 +415,15 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     const int64_t ib = (int64_t)blockIdx.x * DUP_TILE;
     if (ib >= m) return;                      // uniform over the block
     const int64_t ie = ib + DUP_TILE < m ? ib + DUP_TILE : m;
-    if (threadIdx.x == 0) {
-        const int64_t r0 = last_le(a.inst_off, 0, a.total_ranks - 1, (uint32_t)ib);
-        const int64_t r1 = last_le(a.inst_off, r0, a.total_ranks - 1, (uint32_t)(ie - 1));
-        s_r0 = r0;
-        s_win = (r1 - r0 + 1 <= DUP_WIN) ? (int)(r1 - r0 + 1) : -1;
+    {
+        const int64_t q0 = block_last_le(a.inst_off, 0, a.total_ranks - 1, (uint32_t)ib);
+        const int64_t q1 = block_last_le(a.inst_off, q0, a.total_ranks - 1, (uint32_t)(ie - 1));
+        if (threadIdx.x == 0) {
+            s_r0 = q0;
+            s_win = (q1 - q0 + 1 <= DUP_WIN) ? (int)(q1 - q0 + 1) : -1;
+        }
     }
+    for (int k = threadIdx.x; k < DUP_TILE; k += 256) owner[k] = 0u;
     __syncthreads();
     const int64_t r0 = s_r0;
     const int win = s_win;
@@ -349,6 +433,35 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
             const int64_t j = r0 + k;
             rects[k] = a.rect[(j / a.n) * a.n + a.order[j]];
         }
+        __syncthreads();
+        for (int k = threadIdx.x; k < win; k += 256) {
+            const uint32_t st = offs[k];
+            if (st >= (uint64_t)ib && st < (uint64_t)ie) atomicMax(&owner[st - (uint32_t)ib], (uint32_t)k + 1u);
+        }
+        if (threadIdx.x == 0) atomicMax(&owner[0], 1u);   // the first rank owns the range's first instance
+        __syncthreads();
+        // inclusive prefix maximum: PER consecutive positions per thread, then over threads
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        uint32_t run = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) run = max(run, owner[threadIdx.x * PER + e]);
+        uint32_t incl = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl = max(incl, t);
+        }
+        if (lane == 63) wmax[w] = incl;
+        uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, 64);
+        if (lane == 0) excl = 0u;
+        __syncthreads();
+        for (int k = 0; k < w; ++k) excl = max(excl, wmax[k]);
+        uint32_t cur = excl;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            cur = max(cur, owner[threadIdx.x * PER + e]);
+            owner[threadIdx.x * PER + e] = cur;
+        }
     }
     __syncthreads();
     for (int64_t ii = ib + threadIdx.x; ii < ie; ii += 256) {
@@ -357,14 +470,10 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         int4 r;
         uint32_t local;
         if (win > 0) {
-            int lo = 0, hi = win - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (offs[mid] <= i) lo = mid; else hi = mid - 1;
-            }
-            j = r0 + lo;
-            r = rects[lo];
-            local = i - offs[lo];
+            const int wi = (int)owner[ii - ib] - 1;
+            j = r0 + wi;
+            r = rects[wi];
+            local = i - offs[wi];
         } else {
             j = last_le(a.inst_off, r0, a.total_ranks - 1, i);
             r = a.rect[(j / a.n) * a.n + a.order[j]];
@@ -372,8 +481,10 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         }
         const int v = (int)(j / a.n);
         const uint32_t wdt = (uint32_t)(r.z - r.x + 1);
-        const uint32_t tx = (uint32_t)r.x + local % wdt;
-        const uint32_t ty = (uint32_t)r.y + local / wdt;
+        uint32_t qy, qx;
+        divmod_small(local, wdt, qy, qx);
+        const uint32_t tx = (uint32_t)r.x + qx;
+        const uint32_t ty = (uint32_t)r.y + qy;
         const uint32_t tile = (uint32_t)a.vt.tile_off[v] + ty * (uint32_t)a.vt.tiles_x[v] + tx;
         if (a.packed) {
             a.keys[i] = (tile << a.rank_bits) | (uint32_t)j;
@@ -393,15 +504,38 @@ __device__ __forceinline__ uint32_t inst_tile(const uint32_t* keys, int64_t i, i
     return packed ? (keys[i] >> rank_bits) : keys[i];
 }
 
+// [start, end) of every non-empty tile's run in the sorted instances; each
+// thread checks 8 consecutive instances against their neighbours.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const Counters* counters,
                                                 int64_t cap, int rank_bits, int packed, uint32_t* ranges) {
     if (counters->inst_overflow) return;
-    const int64_t m = (int64_t)counters->n_instances;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m || i >= cap) return;
-    const uint32_t t = inst_tile(keys, i, rank_bits, packed);
-    if (i == 0 || inst_tile(keys, i - 1, rank_bits, packed) != t) ranges[2 * t] = (uint32_t)i;
-    if (i == m - 1 || inst_tile(keys, i + 1, rank_bits, packed) != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+    const int64_t n_inst = (int64_t)counters->n_instances;
+    const int64_t m = n_inst < cap ? n_inst : cap;
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+    if (i0 >= m) return;
+    uint32_t t[8];
+    if (i0 + 8 <= m) {
+        const uint4 a0 = *reinterpret_cast<const uint4*>(keys + i0);
+        const uint4 a1 = *reinterpret_cast<const uint4*>(keys + i0 + 4);
+        t[0] = a0.x; t[1] = a0.y; t[2] = a0.z; t[3] = a0.w;
+        t[4] = a1.x; t[5] = a1.y; t[6] = a1.z; t[7] = a1.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = i0 + e < m ? keys[i0 + e] : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = packed ? (t[e] >> rank_bits) : t[e];
+    uint32_t prev = i0 > 0 ? inst_tile(keys, i0 - 1, rank_bits, packed) : 0xFFFFFFFFu;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t i = i0 + e;
+        if (i >= m) break;
+        if (i == 0 || prev != t[e]) ranges[2 * t[e]] = (uint32_t)i;
+        const uint32_t next = e < 7 ? (i + 1 < m ? t[e + 1] : 0xFFFFFFFFu)
+                                    : (i + 1 < m ? inst_tile(keys, i + 1, rank_bits, packed) : 0xFFFFFFFFu);
+        if (i == m - 1 || next != t[e]) ranges[2 * t[e] + 1] = (uint32_t)(i + 1);
+        prev = t[e];
+    }
 }
 
 // The paper's 64-bit keys of the sorted instances.
@@ -441,8 +575,10 @@ void launch_duplicate(const DupArgs& a, hipStream_t s) {
 
 void launch_ranges(const uint32_t* keys, const Counters* c, int64_t cap, int rank_bits, int packed, uint32_t* ranges,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, c, cap, rank_bits, packed,
-                       ranges);
+    const int64_t threads = (cap + 7) / 8;
+    if (threads > 0)
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, keys, c, cap, rank_bits,
+                           packed, ranges);
 }
 
 void launch_bin_keys(const uint32_t* keys, const uint32_t* vals, const uint32_t* order, const uint32_t* depth_key,
