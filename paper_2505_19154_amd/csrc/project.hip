@@ -266,9 +266,25 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, Vie
 // grad2d[(v*N + g)*12 + k], k: 0 u, 1 v, 2 A, 3 B, 4 C, 5 sum dL/dpower,
 // 6..8 rgb, 9 sum w.
 
+__device__ __forceinline__ bool upstream_zero(const float* grad2d, size_t j) {
+    const float4* g4 = reinterpret_cast<const float4*>(grad2d + j * 12);
+    const float4 z0 = g4[0], z1 = g4[1], z2 = g4[2];
+    return z0.x == 0.f && z0.y == 0.f && z0.z == 0.f && z0.w == 0.f && z1.x == 0.f && z1.y == 0.f && z1.z == 0.f &&
+           z1.w == 0.f && z2.x == 0.f && z2.y == 0.f && z2.z == 0.f && z2.w == 0.f;
+}
+
+// The outputs are zero-filled before the launch; a Gaussian whose views all
+// pass zero upstream terms (no visited instance reached it) keeps them: every
+// chained term would be zero.
 __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable ct, int n_views) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.n) return;
+    bool any = false;
+    for (int v = 0; v < n_views && !any; ++v) {
+        const size_t j = (size_t)v * a.n + g;
+        any = a.depth_key[j] != CULLED_KEY && !upstream_zero(a.grad2d, j);
+    }
+    if (!any) return;
     const float mu[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
     const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
     const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
@@ -283,7 +299,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable 
 
     for (int v = 0; v < n_views; ++v) {
         const size_t j = (size_t)v * a.n + g;
-        if (a.depth_key[j] == CULLED_KEY) continue;
+        // (a view that no visited instance of this Gaussian reached passes zero
+        // upstream terms: every chained term below is then zero)
+        if (a.depth_key[j] == CULLED_KEY || upstream_zero(a.grad2d, j)) continue;
         const float* g2 = a.grad2d + j * 12;
         const fh_camera& cam = ct.cam[v];
         const Cov64 cv = cov64(mu, sc, q, cam);
@@ -395,8 +413,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable 
     reinterpret_cast<float4*>(a.g_quats)[g] = make_float4(gq[0], gq[1], gq[2], gq[3]);
     a.g_opacity[g] = gop;
     float* gsho = a.g_sh + (size_t)g * nb * 3;
-    for (int b = 0; b < nb; ++b)
-        for (int ch = 0; ch < 3; ++ch) gsho[3 * b + ch] = gsh[b][ch];
+    if (nb == 16) {
+        // 48 floats per Gaussian (192 B, 16-B aligned): as twelve float4
+        const float* f = &gsh[0][0];
+        float4* o4 = reinterpret_cast<float4*>(gsho);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o4[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+    } else {
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) gsho[3 * b + ch] = gsh[b][ch];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -406,6 +432,12 @@ void launch_project(const ProjectArgs& a, const CamTable& ct, const ViewTable& v
 }
 
 void launch_project_bwd(const ProjectBwdArgs& a, const CamTable& ct, int n_views, hipStream_t s) {
+    const int64_t nsh = (int64_t)(a.sh_degree + 1) * (a.sh_degree + 1) * 3;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_means), (int64_t)a.n * 3, 0u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_scales), (int64_t)a.n * 3, 0u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_quats), (int64_t)a.n * 4, 0u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_opacity), (int64_t)a.n, 0u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_sh), (int64_t)a.n * nsh, 0u, s);
     hipLaunchKernelGGL(k_project_bwd, dim3((a.n + 255) / 256), dim3(256), 0, s, a, ct, n_views);
 }
 
