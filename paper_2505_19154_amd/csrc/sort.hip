@@ -86,6 +86,34 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t* __rest
     if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) out[n] = run;
 }
 
+// The same, with the block's offset formed in place: the sum of the block sums
+// before it (integer sums, so the order of the additions does not matter).
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down_sums(const uint32_t* __restrict__ in, int64_t n,
+                                                               const uint32_t* __restrict__ block_sums,
+                                                               uint32_t* __restrict__ out, int write_total) {
+    __shared__ uint32_t sh_wave[SCAN_BLOCK / WAVE];
+    uint32_t part = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += SCAN_BLOCK) part += block_sums[k];
+    uint32_t offset;
+    block_exclusive_scan(part, &offset, sh_wave);
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot, sh_wave) + offset;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) out[n] = run;
+}
+
 // Scratch (in u32) needed by device_exclusive_scan for n items.
 size_t scan_scratch_u32(int64_t n) {
     size_t tot = 0;
@@ -112,6 +140,12 @@ void device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
     uint32_t* offs = scratch + nb + 64;
     uint32_t* next = offs + nb + 64;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, sums);
+    if (nb <= 16 * SCAN_BLOCK) {
+        // few blocks: each adds up the sums before it (two launches instead of three)
+        hipLaunchKernelGGL(k_scan_down_sums, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, (const uint32_t*)sums,
+                           out, write_total);
+        return;
+    }
     device_exclusive_scan(sums, offs, nb, next, 0, s);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, (const uint32_t*)offs, out,
                        write_total);
