@@ -384,9 +384,10 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 // Fusion kernel.  1024 threads; wave w = pixel row w; lane (xi, q) = pixel
 // x = xi, positions 4q..4q+3 of each half-chunk; wave w < D/16 owns channel
 // block w of the contraction and keeps that block of the tile's target in
-// registers.  Writes the fusion partial row of every visited instance and its
-// weight sum (the tenth geometry partial).
-template <int D>
+// registers.  Writes the fusion partial row of every visited instance and,
+// with WS, its weight sum (the tenth geometry partial; without WS the gradient
+// kernel of the same call has written it).
+template <int D, bool WS>
 __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
     constexpr int NDB = D / 16;
@@ -507,11 +508,13 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 const __bf16 hh = (__bf16)wv;
                 swh[k * PP + n] = hh;
                 swl[k * PP + n] = (__bf16)(wv - (float)hh);
-                // the row's weight sum of position k: butterfly over the 16 pixels
-                float rs = wv;
+                if (WS) {
+                    // the row's weight sum of position k: butterfly over the 16 pixels
+                    float rs = wv;
 #pragma unroll
-                for (int off = 1; off < 16; off <<= 1) rs += __shfl_xor(rs, off, 64);
-                if (xi == 0) swsum[w][k] = rs;
+                    for (int off = 1; off < 16; off <<= 1) rs += __shfl_xor(rs, off, 64);
+                    if (xi == 0) swsum[w][k] = rs;
+                }
             }
         }
         // the next chunk's records go to the other buffer before this chunk's
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         }
         __syncthreads();
         // weight sums per instance: the 16 rows in order
-        if (threadIdx.x < BK) {
+        if (WS && threadIdx.x < BK) {
             const int k = threadIdx.x;
             float ws = 0.0f;
 #pragma unroll
@@ -565,7 +568,10 @@ static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bo
     }
     if (fuse) {
         const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (TILE_PIX + 8);
-        hipLaunchKernelGGL(k_fuse_bf16<D>, dim3(n_tiles), dim3(1024), lds, s, a, vt);
+        if (grads)
+            hipLaunchKernelGGL((k_fuse_bf16<D, false>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
+        else
+            hipLaunchKernelGGL((k_fuse_bf16<D, true>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
     }
 }
 
