@@ -153,6 +153,25 @@ __device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// A wave's four 16-lane rows: every lane gets the values of lanes xi, xi + 16,
+// xi + 32 and xi + 48 (xi = lane % 16) from three cross-row swaps (gfx950
+// v_permlane16_swap / v_permlane32_swap, VALU) instead of four LDS permutes.
+// All 64 lanes must be active.
+struct Rows4 {
+    float r0, r1, r2, r3;
+};
+__device__ __forceinline__ Rows4 rows4(float v) {
+    const unsigned u = __float_as_uint(v);
+    // odd rows of one copy trade places with even rows of the other:
+    // a[0] = (row 0, row 0, row 2, row 2), a[1] = (row 1, row 1, row 3, row 3)
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    // upper half of one copy with lower half of the other:
+    // b = (row 0 everywhere, row 2 everywhere), c = (row 1 ..., row 3 ...)
+    const auto b = __builtin_amdgcn_permlane32_swap(a[0], a[0], false, false);
+    const auto c = __builtin_amdgcn_permlane32_swap(a[1], a[1], false, false);
+    return Rows4{__uint_as_float(b[0]), __uint_as_float(c[0]), __uint_as_float(b[1]), __uint_as_float(c[1])};
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));

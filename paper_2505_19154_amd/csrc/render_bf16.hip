@@ -177,7 +177,8 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
             P *= (1.0f - al[m]);
         }
-        const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64);
+        const Rows4 Pr = rows4(P);
+        const float P0 = Pr.r0, P1 = Pr.r1, P2 = Pr.r2;
         const float excl = q == 0 ? 1.0f : (q == 1 ? P0 : (q == 2 ? P0 * P1 : (P0 * P1) * P2));
         float Tl = T * excl;
         bool dl = done || Tl < T_MIN;
@@ -228,17 +229,17 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
         }
         // pixel state after the chunk: the first lane that stopped, else lane 3
         const uint64_t tb = ballot64(term);
-        const float Tq0 = __shfl(Tl, xi, 64), Tq1 = __shfl(Tl, xi + 16, 64), Tq2 = __shfl(Tl, xi + 32, 64),
-                    Tq3 = __shfl(Tl, xi + 48, 64);
+        const Rows4 Tr = rows4(Tl);
+        const float Tq0 = Tr.r0, Tq1 = Tr.r1, Tq2 = Tr.r2, Tq3 = Tr.r3;
         const bool t0 = (tb >> xi) & 1, t1 = (tb >> (xi + 16)) & 1, t2 = (tb >> (xi + 32)) & 1,
                    t3 = (tb >> (xi + 48)) & 1;
         if (!done) {
             T = t0 ? Tq0 : (t1 ? Tq1 : (t2 ? Tq2 : Tq3));
             done = t0 || t1 || t2 || t3;
         }
-        uint32_t lm = mylast;
-        lm = max(lm, (uint32_t)__shfl_xor((int)lm, 16, 64));
-        lm = max(lm, (uint32_t)__shfl_xor((int)lm, 32, 64));
+        const Rows4 Lr = rows4(__uint_as_float(mylast));
+        const uint32_t lm = max(max(__float_as_uint(Lr.r0), __float_as_uint(Lr.r1)),
+                                max(__float_as_uint(Lr.r2), __float_as_uint(Lr.r3)));
         last = max(last, lm);
 
         // W times the feature chunk (channel blocks in pairs, so that the hi and

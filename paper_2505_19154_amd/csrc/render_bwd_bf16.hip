@@ -22,7 +22,8 @@
 // W^T[k x px] . Target[px x D] with W split into BF16 hi + lo and the tile's
 // target held in registers for the whole tile.  Kept apart from the gradient
 // kernel so that each keeps its own per-tile operand (dF or the target)
-// resident without spilling.
+// resident without spilling; when both run, the per-instance weight sums come
+// from the gradient kernel alone.
 #include "kernels.hpp"
 
 namespace fh {
@@ -269,10 +270,9 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     trel = on[r] ? tn : trel;
                 }
                 // entry state of every lane, scanning from the back (lane q = 3 first)
-                const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
-                            P3 = __shfl(P, xi + 48, 64);
-                const float R0 = __shfl(R, xi, 64), R1 = __shfl(R, xi + 16, 64), R2 = __shfl(R, xi + 32, 64),
-                            R3 = __shfl(R, xi + 48, 64);
+                const Rows4 Pr = rows4(P), Rr = rows4(R);
+                const float P0 = Pr.r0, P1 = Pr.r1, P2 = Pr.r2, P3 = Pr.r3;
+                const float R0 = Rr.r0, R1 = Rr.r1, R2 = Rr.r2, R3 = Rr.r3;
                 const float Te3 = T[h], Se3 = S[h];
                 const float Te2 = Te3 * __builtin_amdgcn_rcpf(P3), Se2 = Se3 + Te3 * R3;
                 const float Te1 = Te2 * __builtin_amdgcn_rcpf(P2), Se1 = Se2 + Te2 * R2;
@@ -359,7 +359,10 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             qv[9] = ws;
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
-                qv[m] += __shfl_xor(qv[m], 32, 64);
+                // (the two half-waves' values, added in the same order in both halves)
+                const auto hv = __builtin_amdgcn_permlane32_swap(__float_as_uint(qv[m]), __float_as_uint(qv[m]),
+                                                                 false, false);
+                qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
                 if (lane < 32) sred[(w * 10 + m) * BK + k] = qv[m];
             }
         }
@@ -374,7 +377,11 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             }
             if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + m] = sum;
         }
-        __syncthreads();
+        // No barrier here: the next chunk's LDS writes before its first
+        // barrier (w and dL/dpower, the chunk after next's records and
+        // Gaussians, the next features) go to arrays whose last readers all
+        // passed the barrier above, and the partial sums (sred) are written
+        // only after the next first barrier, which these threads reach last.
         b3 = n3;
         f2 ^= 1;
     }
@@ -391,11 +398,14 @@ template <int D, bool WS>
 __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
     constexpr int NDB = D / 16;
+    // W^T and the weight sums are double-buffered by chunk parity, so that one
+    // barrier per chunk suffices: a wave may walk chunk c + 1 while others
+    // still contract chunk c
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16* swh = reinterpret_cast<__bf16*>(smem);                           // [BK][PP] W^T hi
-    __bf16* swl = swh + BK * PP;                                             // [BK][PP] W^T lo
-    __shared__ float swsum[16][BK];     // per wave (pixel row): sum over its pixels of w, per position
-    __shared__ Rec srecb[2][BK];        // chunk records, double-buffered (the next chunk's fetched ahead)
+    __bf16* swh2 = reinterpret_cast<__bf16*>(smem);                          // [2][BK][PP] W^T hi
+    __bf16* swl2 = swh2 + 2 * BK * PP;                                       // [2][BK][PP] W^T lo
+    __shared__ float swsum2[2][16][BK];   // per wave (pixel row): sum over its pixels of w, per position
+    __shared__ Rec srecb[2][BK];          // chunk records, double-buffered (the next chunk's fetched ahead)
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -465,6 +475,9 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
         const Rec* srec = srecb[b];
+        __bf16* swh = swh2 + b * BK * PP;
+        __bf16* swl = swl2 + b * BK * PP;
+        float(*swsum)[BK] = swsum2[b];
         // the next chunk's records, in flight during this chunk
         const int ncs = cs - BK > 0 ? cs - BK : 0;
         // (positions ncs .. ncs + BK - 1 all lie in this tile's visits when
@@ -493,8 +506,8 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 al[r] = ae.alpha;
                 P = on[r] ? P * (1.0f - al[r]) : P;
             }
-            const float P0 = __shfl(P, xi, 64), P1 = __shfl(P, xi + 16, 64), P2 = __shfl(P, xi + 32, 64),
-                        P3 = __shfl(P, xi + 48, 64);
+            const Rows4 Pr = rows4(P);
+            const float P0 = Pr.r0, P1 = Pr.r1, P2 = Pr.r2, P3 = Pr.r3;
             const float Te3 = T, Te2 = Te3 * __builtin_amdgcn_rcpf(P3), Te1 = Te2 * __builtin_amdgcn_rcpf(P2),
                         Te0 = Te1 * __builtin_amdgcn_rcpf(P1);
             float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
@@ -555,7 +568,10 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 }
             }
         }
-        __syncthreads();
+        // No barrier here: before its barrier the next chunk writes the other
+        // W^T and weight-sum buffers and this chunk's record buffer, whose last
+        // readers (the chunk before this one, and this chunk's walk) all
+        // passed the barrier above.
     }
 }
 
@@ -567,7 +583,7 @@ static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bo
         hipLaunchKernelGGL(k_render_bwd_bf16<D>, dim3(n_tiles), dim3(512), lds, s, a, vt);
     }
     if (fuse) {
-        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (TILE_PIX + 8);
+        const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + 8);
         if (grads)
             hipLaunchKernelGGL((k_fuse_bf16<D, false>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
         else
