@@ -111,6 +111,31 @@ struct Rec {
 };
 static_assert(sizeof(Rec) == 48, "records are read and written as 12 consecutive dwords");
 
+// A chunk's records staged in LDS as float4 triples with one float4 of padding
+// after every G records.  Lanes that read records G apart at the same time (one
+// per 16-lane row) then start 3G + 1 float4s apart, i.e. in different groups
+// of four banks, instead of all in the same one (records are 12 dwords).
+template <int G>
+__device__ __forceinline__ int rec_slot(int k) {
+    return 3 * k + k / G;
+}
+template <int G>
+__device__ __forceinline__ Rec lds_rec(const float4* base, int k) {
+    const float4* p = base + rec_slot<G>(k);
+    Rec r;
+    r.r0 = p[0];
+    r.r1 = p[1];
+    r.r2 = p[2];
+    return r;
+}
+template <int G>
+__device__ __forceinline__ void lds_put_rec(float4* base, int k, const Rec& r) {
+    float4* p = base + rec_slot<G>(k);
+    p[0] = r.r0;
+    p[1] = r.r1;
+    p[2] = r.r2;
+}
+
 // alpha = min(ALPHA_MAX, o G) at pixel centre (x, y), evaluated with explicit
 // fused operations so that every kernel gets the same bits.
 struct AlphaEval {

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
     static_assert(NB % 2 == 0, "channel blocks are processed in pairs");
     constexpr int NT = 64 * ROWS;                        // threads
     constexpr int NIT = (FK * (DS / 8) + NT - 1) / NT;   // feature items per thread
-    __shared__ Rec srec[3][FK];
+    constexpr int RG = 8;                                 // record padding group (lanes read records 8 apart)
+    __shared__ float4 srec4[3][3 * FK + FK / RG];
     __shared__ uint32_t sg[3][FK];
     __shared__ __attribute__((aligned(16))) __bf16 sft[2][DS * FKP];
     __shared__ uint32_t smax[ROWS];
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             o.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
             o.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        srec[buf][k] = o;
+        lds_put_rec<RG>(srec4[buf], k, o);
         sg[buf][k] = real ? g : 0xFFFFFFFFu;
     };
     // e: a raw list entry (masked here, where it is used, so that its load is
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
         float P = 1.0f;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const AlphaEval ae = eval_alpha(srec[b3][8 * q + m], x, y);
+            const AlphaEval ae = eval_alpha(lds_rec<RG>(srec4[b3], 8 * q + m), x, y);
             al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
             P *= (1.0f - al[m]);
         }
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             // exactly).  The branch-free form needs more registers than the
             // shapes that keep four waves per SIMD have.
             float wv = 0.0f;
-            const Rec& r = srec[b3][8 * q + m];
+            const Rec r = lds_rec<RG>(srec4[b3], 8 * q + m);
             if constexpr (ROWS == 8 && DS > 128) {
                 const float Tn = Tl * (1.0f - al[m]);
                 const bool act = !dl && al[m] > 0.0f;

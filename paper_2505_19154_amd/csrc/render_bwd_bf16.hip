@@ -34,24 +34,28 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BK = 32;   // positions per chunk
 constexpr int SK = BK + 1;   // padded per-pixel stride of the (pixel, position) LDS arrays
+constexpr int RG = 4;        // record padding group: the walk's lane rows read records 4 apart
+constexpr int RSLOTS = 3 * BK + BK / RG;   // float4 slots of one chunk's staged records
 
 // Stage the chunk's records (threads 0..31) from the visit-ordered copies;
 // padding records never blend.
-__device__ __forceinline__ void stage_records(const BwdArgs& a, uint32_t voff, int cs, int cnt, Rec* srec,
+__device__ __forceinline__ void stage_records(const BwdArgs& a, uint32_t voff, int cs, int cnt, float4* srec,
                                               uint32_t* sg) {
     if (threadIdx.x < BK) {
+        Rec r;
         if ((int)threadIdx.x < cnt) {
             const int64_t vi = (int64_t)voff + cs + threadIdx.x;
-            srec[threadIdx.x].r0 = a.vrec[3 * vi];
-            srec[threadIdx.x].r1 = a.vrec[3 * vi + 1];
-            srec[threadIdx.x].r2 = a.vrec[3 * vi + 2];
+            r.r0 = a.vrec[3 * vi];
+            r.r1 = a.vrec[3 * vi + 1];
+            r.r2 = a.vrec[3 * vi + 2];
             if (sg) sg[threadIdx.x] = a.vgid[vi];
         } else {
-            srec[threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            srec[threadIdx.x].r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-            srec[threadIdx.x].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+            r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
             if (sg) sg[threadIdx.x] = 0xFFFFFFFFu;
         }
+        lds_put_rec<RG>(srec, threadIdx.x, r);
     }
 }
 
@@ -87,8 +91,8 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     float* sdp = sw + TILE_PIX * SK;                                         // [256][SK] dL/dpower
     float* sdc = sdp + TILE_PIX * SK;                                        // [256][3] dC of the tile
     float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][10][BK] partial sums
-    __shared__ Rec srecb[3][BK];        // chunk records and Gaussians, triple-buffered:
-    __shared__ uint32_t sgb[3][BK];     // those two chunks ahead arrive during this one
+    __shared__ float4 srecb[3][RSLOTS];   // chunk records and Gaussians, triple-buffered:
+    __shared__ uint32_t sgb[3][BK];       // those two chunks ahead arrive during this one
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
         const int n3 = b3 == 2 ? 0 : b3 + 1, nn3 = n3 == 2 ? 0 : n3 + 1;
-        const Rec* srec = srecb[b3];
+        const float4* srec = srecb[b3];
         const __bf16* sfeat = sfeat2 + f2 * BK * DP;
         // records (12 dwords each, threads 0..12 BK-1) and Gaussians (threads
         // 12 BK..13 BK-1) of the chunk after next: one dword per thread, stored
@@ -257,7 +261,9 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 #pragma unroll
                 for (int r = 3; r >= 0; --r) {
                     const int k = 16 * kb + 4 * q + r;
-                    const Rec& rc = srec[k];
+                    // (slot of k = 16 kb + 4 q + r: 52 kb + 13 q + 3 r)
+                    const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
+                    const Rec rc = {rp[0], rp[1], rp[2]};
                     const AlphaEval ae = eval_alpha(rc, x, y);
                     on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && ae.alpha >= ALPHA_MIN;
                     al[r] = ae.alpha;
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             if (pre_g)
                 sgb[nn3][pre_k] = val;
             else
-                reinterpret_cast<uint32_t*>(srecb[nn3])[threadIdx.x] = val;
+                reinterpret_cast<uint32_t*>(srecb[nn3])[4 * rec_slot<RG>(pre_k) + j] = val;
         }
         if (fnext_on) store_feats(fnext, sfeat2 + (f2 ^ 1) * BK * DP);
         __syncthreads();
@@ -325,7 +331,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         //    S0 = sum dp, Sx = sum dp dx, Sxx = sum dp dx^2.
         {
             const int k = lane & 31, pg = 2 * w + (lane >> 5);
-            const Rec rc = srec[k];
+            const Rec rc = lds_rec<RG>(srec, k);
             const float ex = rc.r1.x, ey = rc.r1.y, q1 = rc.r1.z, q2 = rc.r1.w;
             const float dy = (((float)(ty * TILE + pg) + 0.5f) - rc.r0.y) - rc.r0.w;
             const float dx0 = (((float)(tx * TILE) + 0.5f) - rc.r0.x) - rc.r0.z;
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     __bf16* swh2 = reinterpret_cast<__bf16*>(smem);                          // [2][BK][PP] W^T hi
     __bf16* swl2 = swh2 + 2 * BK * PP;                                       // [2][BK][PP] W^T lo
     __shared__ float swsum2[2][16][BK];   // per wave (pixel row): sum over its pixels of w, per position
-    __shared__ Rec srecb[2][BK];          // chunk records, double-buffered (the next chunk's fetched ahead)
+    __shared__ float4 srecb[2][RSLOTS];   // chunk records, double-buffered (the next chunk's fetched ahead)
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 
     if (threadIdx.x < BK) {
         const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
-        srecb[0][threadIdx.x] = fetch_record(a, voff, cs0, (int)nt - cs0, threadIdx.x);
+        lds_put_rec<RG>(srecb[0], threadIdx.x, fetch_record(a, voff, cs0, (int)nt - cs0, threadIdx.x));
     }
     // the tile's staged records as a buffer (raw, dword data format): reads
     // past its nt visits return zero instead of touching other memory
@@ -474,7 +480,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     for (int ce = (int)nt; ce > 0; ce -= BK, b ^= 1) {
         const int cs = ce - BK > 0 ? ce - BK : 0;
         const int cnt = ce - cs;
-        const Rec* srec = srecb[b];
+        const float4* srec = srecb[b];
         __bf16* swh = swh2 + b * BK * PP;
         __bf16* swl = swl2 + b * BK * PP;
         float(*swsum)[BK] = swsum2[b];
@@ -501,7 +507,8 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
-                const AlphaEval ae = eval_alpha(srec[k], x, y);
+                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;   // slot of k
+                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
                 on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
                 al[r] = ae.alpha;
                 P = on[r] ? P * (1.0f - al[r]) : P;
@@ -538,7 +545,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 nxt.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
                 nxt.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            srecb[b ^ 1][threadIdx.x] = nxt;
+            lds_put_rec<RG>(srecb[b ^ 1], threadIdx.x, nxt);
         }
         __syncthreads();
         // weight sums per instance: the 16 rows in order
