@@ -33,7 +33,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BK = 32;   // positions per chunk
-constexpr int SK = BK + 1;   // padded per-pixel stride of the (pixel, position) LDS arrays
+// padded per-pixel stride of the (pixel, position) LDS arrays: the walk's stores
+// (lane (xi, q) at 35 xi + 4 q + r) hit each bank at most 3 times, the
+// Gaussian-parallel reads (consecutive positions per lane) twice
+constexpr int SK = BK + 3;
 constexpr int RG = 4;        // record padding group: the walk's lane rows read records 4 apart
 constexpr int RSLOTS = 3 * BK + BK / RG;   // float4 slots of one chunk's staged records
 
