@@ -390,7 +390,7 @@ __global__ void k_check_capacity(Counters* counters, int64_t cap) {
 // only a range that crosses a view boundary with culled (zero-instance) ranks
 // can need more, and then searches the scan in global memory.
 constexpr int DUP_TILE = 2048;
-constexpr int DUP_WIN = 2048;
+constexpr int DUP_WIN = 1024;
 
 // largest r in [lo, hi] with off[r] <= i (off non-decreasing, off[lo] <= i)
 __device__ __forceinline__ int64_t last_le(const uint32_t* off, int64_t lo, int64_t hi, uint32_t i) {
@@ -438,8 +438,9 @@ __device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q
 
 __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     constexpr int PER = DUP_TILE / 256;   // positions per thread in the prefix maximum
+    // (20 KB of LDS per workgroup, so that eight are resident per CU)
     __shared__ uint32_t offs[DUP_WIN + 1];
-    __shared__ int4 rects[DUP_WIN];
+    __shared__ uint2 rects[DUP_WIN];      // tile rect origin (x0 | y0 << 16: views are at most 1024 tiles wide) and width
     __shared__ uint32_t owner[DUP_TILE];  // window index + 1 of the rank owning each position
     __shared__ uint32_t wmax[4];
     __shared__ long long s_r0;
@@ -465,7 +466,8 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         for (int k = threadIdx.x; k <= win; k += 256) offs[k] = a.inst_off[r0 + k];
         for (int k = threadIdx.x; k < win; k += 256) {
             const int64_t j = r0 + k;
-            rects[k] = a.rect[(j / a.n) * a.n + a.order[j]];
+            const int4 rc = a.rect[(j / a.n) * a.n + a.order[j]];
+            rects[k] = make_uint2((uint32_t)rc.x | ((uint32_t)rc.y << 16), (uint32_t)(rc.z - rc.x + 1));
         }
         __syncthreads();
         for (int k = threadIdx.x; k < win; k += 256) {
@@ -501,24 +503,28 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     for (int64_t ii = ib + threadIdx.x; ii < ie; ii += 256) {
         const uint32_t i = (uint32_t)ii;
         int64_t j;
-        int4 r;
-        uint32_t local;
+        uint32_t x0, y0, wdt, local;
         if (win > 0) {
             const int wi = (int)owner[ii - ib] - 1;
             j = r0 + wi;
-            r = rects[wi];
+            const uint2 r = rects[wi];
+            x0 = r.x & 0xFFFFu;
+            y0 = r.x >> 16;
+            wdt = r.y;
             local = i - offs[wi];
         } else {
             j = last_le(a.inst_off, r0, a.total_ranks - 1, i);
-            r = a.rect[(j / a.n) * a.n + a.order[j]];
+            const int4 r = a.rect[(j / a.n) * a.n + a.order[j]];
+            x0 = (uint32_t)r.x;
+            y0 = (uint32_t)r.y;
+            wdt = (uint32_t)(r.z - r.x + 1);
             local = i - a.inst_off[j];
         }
         const int v = (int)(j / a.n);
-        const uint32_t wdt = (uint32_t)(r.z - r.x + 1);
         uint32_t qy, qx;
         divmod_small(local, wdt, qy, qx);
-        const uint32_t tx = (uint32_t)r.x + qx;
-        const uint32_t ty = (uint32_t)r.y + qy;
+        const uint32_t tx = x0 + qx;
+        const uint32_t ty = y0 + qy;
         const uint32_t tile = (uint32_t)a.vt.tile_off[v] + ty * (uint32_t)a.vt.tiles_x[v] + tx;
         if (a.packed) {
             a.keys[i] = (tile << a.rank_bits) | (uint32_t)j;
