@@ -23,6 +23,9 @@ SCENES = {
     "multiview": (1500, 1.2, 1, 8, "f32", "three", "f32"),
     "mfma_d32": (2500, 1.5, 3, 32, "bf16", "front120x90", "bf16"),
     "mfma_d128_multiview": (1500, 1.2, 1, 128, "bf16", "three", "bf16"),
+    # splats of 1-2 tiles: some 2048-instance duplication ranges span more
+    # than 1024 ranks (up to 1260) and take the per-instance rank search
+    "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
 }
 # BF16-MFMA form: F, the feature part of the adjoint and the fusion sums are
 # contractions over two-term BF16 splits (tests/gpu_util.py: RTOL_FORM).
