@@ -63,12 +63,68 @@ __global__ __launch_bounds__(256) void k_vseg(const uint32_t* __restrict__ skeys
     if (k == m - 1 || skeys[k + 1] != j) vseg[2 * (int64_t)j + 1] = (uint32_t)(k + 1);
 }
 
+// Queue slots for a wave: lanes with `take` get consecutive slots of *counter
+// (in lane order) from one atomic per wave.  All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_slot(unsigned int* counter, bool take) {
+    const uint64_t m = ballot64(take);
+    if (m == 0) return 0u;
+    const int leader = __builtin_ctzll(m);
+    uint32_t base = 0u;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned int)__builtin_popcountll(m));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    return base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+}
+
+// The same for n slots per lane (n = 0 takes none): the lane's first slot.
+__device__ __forceinline__ uint32_t wave_slots(unsigned int* counter, uint32_t n) {
+    const int lane = lane_id();
+    uint32_t incl = n;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    const uint32_t tot = (uint32_t)__shfl((int)incl, 63, 64);
+    if (tot == 0) return 0u;
+    uint32_t base = 0u;
+    if (lane == 63) base = atomicAdd(counter, tot);
+    base = (uint32_t)__shfl((int)base, 63, 64);
+    return base + incl - n;
+}
+
 __device__ __forceinline__ void add_geom(float* acc, const float* part_geom, uint32_t idx) {
     const float4* pg = reinterpret_cast<const float4*>(part_geom + (int64_t)idx * 12);
     const float4 q0 = pg[0], q1 = pg[1], q2 = pg[2];
     acc[0] += q0.x; acc[1] += q0.y; acc[2] += q0.z; acc[3] += q0.w;
     acc[4] += q1.x; acc[5] += q1.y; acc[6] += q1.z; acc[7] += q1.w;
     acc[8] += q2.x; acc[9] += q2.y;
+}
+
+// acc += the partials of visits k0, k0 + st, k0 + 2 st, ... below k1 (of the
+// rank-sorted list), added in that order; their indices and rows are loaded
+// four at a time, so that the loads do not wait for one another.
+__device__ __forceinline__ void add_geom_run(float* acc, const ReduceArgs& a, uint32_t k0, uint32_t k1, uint32_t st) {
+    uint32_t k = k0;
+    for (; k + 3 * st < k1; k += 4 * st) {
+        uint32_t idx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) idx[i] = a.vsorted[k + (uint32_t)i * st];
+        float4 r[4][3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4* pg = reinterpret_cast<const float4*>(a.part_geom + (int64_t)idx[i] * 12);
+            r[i][0] = pg[0];
+            r[i][1] = pg[1];
+            r[i][2] = pg[2];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            acc[0] += r[i][0].x; acc[1] += r[i][0].y; acc[2] += r[i][0].z; acc[3] += r[i][0].w;
+            acc[4] += r[i][1].x; acc[5] += r[i][1].y; acc[6] += r[i][1].z; acc[7] += r[i][1].w;
+            acc[8] += r[i][2].x; acc[9] += r[i][2].y;
+        }
+    }
+    for (; k < k1; k += st) add_geom(acc, a.part_geom, a.vsorted[k]);
 }
 
 __device__ __forceinline__ void store_geom(float* grad2d, int64_t row, const float* acc) {
@@ -80,21 +136,24 @@ __device__ __forceinline__ void store_geom(float* grad2d, int64_t row, const flo
 
 // One thread per (view, rank): the screen-space adjoint of that (view, Gaussian).
 __global__ __launch_bounds__(256) void k_reduce_geom(ReduceArgs a) {
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;   // (uniform)
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= a.total) return;
-    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const int64_t v = j / a.n;
-    const uint32_t g = a.order[j];
-    const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
-    if (b1 - b0 > LONG_GEOM) {
-        const uint32_t slot = atomicAdd(&a.counters->n_long_geom, 1u);
+    const bool valid = j < a.total;
+    // every lane stays active for the wave-wide slot allocation
+    const uint32_t b0 = valid ? a.vseg[2 * j] : 0u, b1 = valid ? a.vseg[2 * j + 1] : 0u;
+    const bool is_long = b1 - b0 > LONG_GEOM;
+    const uint32_t slot = wave_slot(&a.counters->n_long_geom, is_long);
+    if (!valid) return;
+    if (is_long) {
         a.long_list[slot] = (uint32_t)j;
         return;
     }
+    const int64_t v = j / a.n;
+    const uint32_t g = a.order[j];
     float acc[12];
 #pragma unroll
     for (int m = 0; m < 12; ++m) acc[m] = 0.0f;
-    for (uint32_t k = b0; k < b1; ++k) add_geom(acc, a.part_geom, a.vsorted[k]);
+    add_geom_run(acc, a, b0, b1, 1u);
     store_geom(a.grad2d, v * a.n + g, acc);
 }
 
@@ -110,7 +169,7 @@ __global__ __launch_bounds__(256) void k_reduce_geom_long(ReduceArgs a) {
         float acc[12];
 #pragma unroll
         for (int m = 0; m < 12; ++m) acc[m] = 0.0f;
-        for (uint32_t k = b0 + threadIdx.x; k < b1; k += 256) add_geom(acc, a.part_geom, a.vsorted[k]);
+        add_geom_run(acc, a, b0 + threadIdx.x, b1, 256u);
 #pragma unroll
         for (int m = 0; m < 10; ++m) red[threadIdx.x][m] = acc[m];
         __syncthreads();
@@ -201,19 +260,17 @@ __device__ __forceinline__ uint32_t fuse_visit_total(const ReduceArgs& a, int64_
 // it is queued with its run of units of FUSE_UNIT consecutive visits.  (Queue
 // order does not matter: each Gaussian's sums depend on its own visits only.)
 __global__ __launch_bounds__(256) void k_fuse_classify(ReduceArgs a) {
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;   // (uniform)
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= a.n) return;
-    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const uint32_t total = fuse_visit_total(a, g);
-    if (total == 0) return;
-    if (total <= LONG_FUSE) {
-        const uint32_t slot = atomicAdd(&a.counters->n_short_fuse, 1u);
-        a.long_list[a.total + 2 * a.n + slot] = (uint32_t)g;
-        return;
-    }
-    const uint32_t nu = (total + FUSE_UNIT - 1) / FUSE_UNIT;
-    const uint32_t slot = atomicAdd(&a.counters->n_long_fuse, 1u);
-    const uint32_t ub = atomicAdd(&a.counters->n_fuse_units, nu);
+    // every lane stays active for the wave-wide slot allocation
+    const uint32_t total = g < a.n ? fuse_visit_total(a, g) : 0u;
+    const bool is_short = total > 0 && total <= LONG_FUSE, is_long = total > LONG_FUSE;
+    const uint32_t nu = is_long ? (total + FUSE_UNIT - 1) / FUSE_UNIT : 0u;
+    const uint32_t sslot = wave_slot(&a.counters->n_short_fuse, is_short);
+    const uint32_t slot = wave_slot(&a.counters->n_long_fuse, is_long);
+    const uint32_t ub = wave_slots(&a.counters->n_fuse_units, nu);
+    if (is_short) a.long_list[a.total + 2 * a.n + sslot] = (uint32_t)g;
+    if (!is_long) return;
     a.long_list[a.total + slot] = (uint32_t)g;
     a.long_list[a.total + a.n + slot] = ub;
     // (cannot happen: the units never exceed the capacity that the visit
