@@ -436,7 +436,8 @@ void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t
 
 void launch_reduce_geom(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_geom, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_reduce_geom_long, dim3(512), dim3(256), 0, s, a);
+    // (long ranks are few: at 500k Gaussians at 1080p about 1,900, one per workgroup)
+    hipLaunchKernelGGL(k_reduce_geom_long, dim3(4096), dim3(256), 0, s, a);
 }
 
 template <int NC, int B>
@@ -444,7 +445,12 @@ static void launch_reduce_fuse_nc(const ReduceArgs& a, hipStream_t s) {
     if (a.n == 0) return;
     hipLaunchKernelGGL(k_fuse_classify, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_reduce_fuse_short<NC, B>), dim3(2048), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_reduce_fuse_units<NC, B>), dim3(2048), dim3(256), 0, s, a);
+    // one wavefront per unit where the capacity allows (the unit count is only
+    // known on the device; waves past it exit at once), so that the hardware
+    // balances the units instead of a fixed stride over a smaller grid
+    const int64_t ub = (a.unit_cap + 3) / 4;
+    const unsigned ugrid = (unsigned)(ub < 2048 ? 2048 : (ub > 32768 ? 32768 : ub));
+    hipLaunchKernelGGL((k_reduce_fuse_units<NC, B>), dim3(ugrid), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_reduce_fuse_combine<NC, B>), dim3(512), dim3(256), 0, s, a);
 }
 
