@@ -5,11 +5,13 @@
 // visited instances of all tiles get consecutive visit indices (tile-major).
 // Sorting the visits stably by rank gives every (view, Gaussian) a contiguous
 // segment of visit indices in row-major tile order.  Short segments are summed
-// by one thread (geometry) or one wavefront (fusion, lanes over channels);
-// Gaussians visited in many tiles (large splats near the camera) are queued and
-// summed by a whole workgroup with a fixed-order tree, so that one long
-// segment does not serialise the launch.  Every sum has a fixed order, so the
-// results are bitwise reproducible.
+// by one thread (geometry) or one wavefront (fusion, lanes over channels).
+// Gaussians visited in many tiles (large splats near the camera) are queued:
+// a long geometry segment is summed by a whole workgroup with a fixed-order
+// tree; a long fusion segment is cut into units of consecutive visits, each
+// summed by a wavefront with compensation, and the units are combined in
+// order.  So one long segment does not serialise the launch, and every sum
+// has a fixed order: the results are bitwise reproducible.
 #include "kernels.hpp"
 
 namespace fh {
