@@ -122,12 +122,18 @@ static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
 }
 
 // Launch shapes (fh_tuning): defaults and validity.
+// The MFMA forward serves the BF16 form, and the FP32 form for the feature
+// widths its channel slices divide (FP32 features as three BF16 terms).
+static bool mfma_forward(int d, int form) {
+    return form == FH_FORM_BF16 || d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0);
+}
+
 static fh_tuning default_tuning(int d, int form) {
     fh_tuning t;
     memset(&t, 0, sizeof(t));
     t.fwd_rows = 16;
     if (d > 0) {
-        if (form == FH_FORM_BF16) {
+        if (mfma_forward(d, form)) {
             if (d == 32 || d == 64 || d == 96) {
                 t.fwd_slice = d;
             } else {
@@ -144,7 +150,9 @@ static fh_tuning default_tuning(int d, int form) {
 
 static bool fwd_shape_ok(int d, int form, int slice, int rows) {
     if (d == 0) return slice == 0 && rows == 16;
-    if (form == FH_FORM_BF16) return render_fwd_bf16_shape_ok(d, slice, rows);
+    // (FP32 features: 16 rows of 128 channels is not offered, it would spill)
+    if (mfma_forward(d, form))
+        return render_fwd_bf16_shape_ok(d, slice, rows) && !(form == FH_FORM_F32 && rows == 16 && slice == 128);
     return rows == 16 && (slice == 8 || slice == 16 || slice == 32 || slice == 64);
 }
 
@@ -373,8 +381,8 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     launch_fill_u32(tile_niter, p->n_tiles, 0u, s);
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_FWD, s);
-    if (p->form == FH_FORM_BF16)
-        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, s);
+    if (mfma_forward(p->d, p->form))
+        launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, !a.feat_bf16, s);
     else
         launch_render_fwd_f32(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
     prof_end(FH_K_RENDER_FWD, s);

@@ -133,7 +133,7 @@ struct ReduceArgs {
 void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s);
 // slice: channels per workgroup; rows: pixel rows per workgroup (16 or 8)
 bool render_fwd_bf16_shape_ok(int d, int slice, int rows);
-void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows,
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, bool fsplit,
                             hipStream_t s);
 bool render_bwd_bf16_supported(int d);
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,

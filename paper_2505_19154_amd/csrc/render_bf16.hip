@@ -40,9 +40,14 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
     return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(pos * 4u), 0, 0);
 }
 
-template <int DS, int ROWS>
+// FS: FP32 features (the FP32 form).  Weights and features are each split
+// into three BF16 terms (x = h + m + l, h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m)) and F takes the six products hh, hm, mh, hl, lh, mm:
+// what is left out is below 2^-24 of w f, so F keeps FP32 accuracy on MFMA.
+template <int DS, int ROWS, bool FS>
 // (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per CU)
-__global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k_render_fwd_bf16(RenderArgs a, ViewTable vt) {
+__global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128 && !FS) ? 4 : 1) void k_render_fwd_bf16(
+    RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
     static_assert(NB % 2 == 0, "channel blocks are processed in pairs");
     constexpr int NT = 64 * ROWS;                        // threads
@@ -50,7 +55,9 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
     constexpr int RG = 8;                                 // record padding group (lanes read records 8 apart)
     __shared__ float4 srec4[3][3 * FK + FK / RG];
     __shared__ uint32_t sg[3][FK];
-    __shared__ __attribute__((aligned(16))) __bf16 sft[2][DS * FKP];
+    constexpr int NFT = FS ? 3 : 1;                       // feature tiles: h (+ m, l)
+    constexpr int NFR = FS ? 2 * NIT : NIT;               // 16-byte registers of one chunk's feature items
+    __shared__ __attribute__((aligned(16))) __bf16 sft[2][NFT * DS * FKP];
     __shared__ uint32_t smax[ROWS];
     __shared__ __attribute__((aligned(16))) uint8_t sbusy[2][16];   // per wave: a pixel still walking
     if (a.counters->inst_overflow) return;
@@ -107,7 +114,14 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
                 const int kk = idx % FK, dg = idx / FK;
                 const uint32_t g = gl[kk];
                 const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
-                fr[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * a.d + d0 + dg * 8);
+                if constexpr (FS) {
+                    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const float*>(a.feat) +
+                                                                      (int64_t)ga * a.d + d0 + dg * 8);
+                    fr[2 * it] = src[0];
+                    fr[2 * it + 1] = src[1];
+                } else {
+                    fr[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * a.d + d0 + dg * 8);
+                }
             }
         }
     };
@@ -118,11 +132,30 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             const int idx = (int)threadIdx.x + NT * it;
             if (idx < FK * (DS / 8)) {
                 const int kk = idx % FK, dg = idx / FK;
-                uint4 f = fr[it];
-                if (gl[kk] == 0xFFFFFFFFu) f = make_uint4(0, 0, 0, 0);
-                const uint16_t* h = reinterpret_cast<const uint16_t*>(&f);
+                const bool pad = gl[kk] == 0xFFFFFFFFu;
+                if constexpr (FS) {
+                    const float4 f0 = __builtin_bit_cast(float4, fr[2 * it]);
+                    const float4 f1 = __builtin_bit_cast(float4, fr[2 * it + 1]);
+                    const float v[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
 #pragma unroll
-                for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + kk] = h[m];
+                    for (int m = 0; m < 8; ++m) {
+                        const float x = pad ? 0.0f : v[m];
+                        const __bf16 hb = (__bf16)x;
+                        const float r = x - (float)hb;
+                        const __bf16 mb = (__bf16)r;
+                        const __bf16 lb = (__bf16)(r - (float)mb);
+                        const int o = (dg * 8 + m) * FKP + kk;
+                        dst[o] = __builtin_bit_cast(uint16_t, hb);
+                        dst[DS * FKP + o] = __builtin_bit_cast(uint16_t, mb);
+                        dst[2 * DS * FKP + o] = __builtin_bit_cast(uint16_t, lb);
+                    }
+                } else {
+                    uint4 f = fr[it];
+                    if (pad) f = make_uint4(0, 0, 0, 0);
+                    const uint16_t* h = reinterpret_cast<const uint16_t*>(&f);
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) dst[(dg * 8 + m) * FKP + kk] = h[m];
+                }
             }
         }
     };
@@ -143,7 +176,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
     if (threadIdx.x < 32) reinterpret_cast<uint8_t*>(sbusy)[threadIdx.x] = 0;
     __syncthreads();
     if (len > 0) {   // (an empty list stages nothing: sg holds no Gaussians then)
-        uint4 fr[NIT];
+        uint4 fr[NFR];
         load_feats(sg[0], fr);
         store_feats(sg[0], fr, sft[0]);
     }
@@ -166,7 +199,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             get_rec(rk2, r2, g2);
             rk3 = list_load(list_rs, cpos + (uint32_t)(3 * FK + k));
         }
-        uint4 fr[NIT];
+        uint4 fr[NFR];
         load_feats(sg[n3], fr);
 
         // alpha of this lane's eight Gaussians and their transmittance product
@@ -186,7 +219,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
         bool term = false;
         uint32_t mylast = 0;
         // W (this lane's 8 weights) goes straight into its MFMA A operand as BF16 hi + lo
-        bf16x8 ahi, alo;
+        bf16x8 ahi, alo, amid;   // (amid: FS only; then alo holds the third term)
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             // Both forms of the step give the same bits (colour by explicit
@@ -226,7 +259,14 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
             }
             const __bf16 h = (__bf16)wv;
             ahi[m] = h;
-            alo[m] = (__bf16)(wv - (float)h);
+            if constexpr (FS) {
+                const float r = wv - (float)h;
+                const __bf16 mb = (__bf16)r;
+                amid[m] = mb;
+                alo[m] = (__bf16)(r - (float)mb);
+            } else {
+                alo[m] = (__bf16)(wv - (float)h);
+            }
         }
         // pixel state after the chunk: the first lane that stopped, else lane 3
         const uint64_t tb = ballot64(term);
@@ -249,10 +289,33 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128) ? 4 : 1) void k
         for (int j = 0; j < NB; j += 2) {
             const bf16x8 bv0 = *reinterpret_cast<const bf16x8*>(&sft[b2][(j * 16 + xi) * FKP + 8 * q]);
             const bf16x8 bv1 = *reinterpret_cast<const bf16x8*>(&sft[b2][((j + 1) * 16 + xi) * FKP + 8 * q]);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv0, acc[j], 0, 0, 0);
-            acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv1, acc[j + 1], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv0, acc[j], 0, 0, 0);
-            acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv1, acc[j + 1], 0, 0, 0);
+            if constexpr (FS) {
+                // the six products, smallest first: lh, hl, mm, mh, hm, hh
+                const bf16x8 bm0 = *reinterpret_cast<const bf16x8*>(&sft[b2][DS * FKP + (j * 16 + xi) * FKP + 8 * q]);
+                const bf16x8 bm1 =
+                    *reinterpret_cast<const bf16x8*>(&sft[b2][DS * FKP + ((j + 1) * 16 + xi) * FKP + 8 * q]);
+                const bf16x8 bl0 =
+                    *reinterpret_cast<const bf16x8*>(&sft[b2][2 * DS * FKP + (j * 16 + xi) * FKP + 8 * q]);
+                const bf16x8 bl1 =
+                    *reinterpret_cast<const bf16x8*>(&sft[b2][2 * DS * FKP + ((j + 1) * 16 + xi) * FKP + 8 * q]);
+                f32x4 s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                f32x4 s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv1, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bl0, s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bl1, s1, 0, 0, 0);
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, bm0, s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, bm1, s1, 0, 0, 0);
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, bv0, s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, bv1, s1, 0, 0, 0);
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bm0, s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bm1, s1, 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv0, acc[j] + s0, 0, 0, 0);
+                acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv1, acc[j + 1] + s1, 0, 0, 0);
+            } else {
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv0, acc[j], 0, 0, 0);
+                acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bv1, acc[j + 1], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv0, acc[j], 0, 0, 0);
+                acc[j + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bv1, acc[j + 1], 0, 0, 0);
+            }
         }
         // chunk c+1's features and chunk c+2's records to LDS
         store_feats(sg[n3], fr, sft[b2 ^ 1]);
@@ -321,24 +384,37 @@ bool render_fwd_bf16_shape_ok(int d, int slice, int rows) {
     return false;
 }
 
-void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, hipStream_t s) {
+template <bool FS>
+static void launch_fwd_mfma(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, hipStream_t s) {
     // slice and rows form a valid shape for d (checked by the caller)
     const unsigned ns = (unsigned)(a.d / slice);
     const dim3 g16(n_tiles, ns), g8(n_tiles, 2 * ns);
     if (rows == 8) {
         switch (slice) {
-            case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8>), g8, dim3(512), 0, s, a, vt); break;
-            case 128: hipLaunchKernelGGL((k_render_fwd_bf16<128, 8>), g8, dim3(512), 0, s, a, vt); break;
-            default: hipLaunchKernelGGL((k_render_fwd_bf16<256, 8>), g8, dim3(512), 0, s, a, vt); break;
+            case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
+            case 128: hipLaunchKernelGGL((k_render_fwd_bf16<128, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
+            default: hipLaunchKernelGGL((k_render_fwd_bf16<256, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
         }
         return;
     }
     switch (slice) {
-        case 32: hipLaunchKernelGGL((k_render_fwd_bf16<32, 16>), g16, dim3(1024), 0, s, a, vt); break;
-        case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 16>), g16, dim3(1024), 0, s, a, vt); break;
-        case 96: hipLaunchKernelGGL((k_render_fwd_bf16<96, 16>), g16, dim3(1024), 0, s, a, vt); break;
-        default: hipLaunchKernelGGL((k_render_fwd_bf16<128, 16>), g16, dim3(1024), 0, s, a, vt); break;
+        case 32: hipLaunchKernelGGL((k_render_fwd_bf16<32, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
+        case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
+        case 96: hipLaunchKernelGGL((k_render_fwd_bf16<96, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
+        default:
+            // (16 rows of 128 channels is not an FP32-feature shape: it would spill)
+            if constexpr (!FS) hipLaunchKernelGGL((k_render_fwd_bf16<128, 16, false>), g16, dim3(1024), 0, s, a, vt);
+            break;
     }
+}
+
+// BF16 features enter the MFMA as stored; FP32 features (fsplit) as three terms
+void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, bool fsplit,
+                            hipStream_t s) {
+    if (fsplit)
+        launch_fwd_mfma<true>(a, vt, n_tiles, slice, rows, s);
+    else
+        launch_fwd_mfma<false>(a, vt, n_tiles, slice, rows, s);
 }
 
 }  // namespace fh
