@@ -66,8 +66,8 @@ typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
 
 /* Arithmetic form of the compositing kernels. */
 typedef enum {
-    FH_FORM_F32 = 0,        /* FP32 features; the adjoint and fusion on the FP32 VALU, the forward on MFMA with
-                               three-term BF16 splits of w and f where d allows (else on the VALU) */
+    FH_FORM_F32 = 0,        /* FP32 blending; the adjoint and fusion on the FP32 VALU; the forward on MFMA with
+                               three-term BF16 splits of w and f for FP32 features where d allows, else on the VALU */
     FH_FORM_BF16 = 1        /* BF16 features, (pixels x K)(K x D) blends on MFMA, FP32 accumulation */
 } fh_form;
 
@@ -103,9 +103,9 @@ typedef struct {
  * order for every setting.
  *   fwd_slice  channels per forward workgroup (the feature dimension is cut
  *              into ceil(d / fwd_slice) slices, each re-walking the tile).
- *              BF16 form, and FP32 form with d = 32, 64, 96 or a multiple of
- *              128 (the MFMA forward; FP32 features enter it as three BF16
- *              terms): dividing d, and 32, 64, 96 or 128 (BF16 form only) with
+ *              BF16 form, and FP32 form with FP32 features and d = 32, 64,
+ *              96 or a multiple of 128 (the MFMA forward; the features enter
+ *              it as three BF16 terms): dividing d, and 32, 64, 96 or 128 (BF16 form only) with
  *              fwd_rows 16, or 64, 128 or 256 with fwd_rows 8.  Other
  *              FP32-form widths: 8, 16, 32 or 64.  0 when d == 0.
  *   fwd_rows   pixel rows per forward workgroup (BF16 form: 16, or 8 for two

@@ -122,18 +122,21 @@ static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
 }
 
 // Launch shapes (fh_tuning): defaults and validity.
-// The MFMA forward serves the BF16 form, and the FP32 form for the feature
-// widths its channel slices divide (FP32 features as three BF16 terms).
-static bool mfma_forward(int d, int form) {
-    return form == FH_FORM_BF16 || d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0);
+// The MFMA forward serves the BF16 form, and the FP32 form with FP32 features
+// at the widths its channel slices divide (the features enter as three BF16
+// terms).  FP32-form runs with BF16-stored features keep the VALU forward: with
+// only the weights split the error would reach ~0.8 of the FP32 rule.
+static bool mfma_forward(int d, int form, int feat_dtype) {
+    return form == FH_FORM_BF16 ||
+           (feat_dtype == FH_F32 && (d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0)));
 }
 
-static fh_tuning default_tuning(int d, int form) {
+static fh_tuning default_tuning(int d, int form, int feat_dtype) {
     fh_tuning t;
     memset(&t, 0, sizeof(t));
     t.fwd_rows = 16;
     if (d > 0) {
-        if (mfma_forward(d, form)) {
+        if (mfma_forward(d, form, feat_dtype)) {
             if (d == 32 || d == 64 || d == 96) {
                 t.fwd_slice = d;
             } else {
@@ -148,10 +151,10 @@ static fh_tuning default_tuning(int d, int form) {
     return t;
 }
 
-static bool fwd_shape_ok(int d, int form, int slice, int rows) {
+static bool fwd_shape_ok(int d, int form, int feat_dtype, int slice, int rows) {
     if (d == 0) return slice == 0 && rows == 16;
     // (FP32 features: 16 rows of 128 channels is not offered, it would spill)
-    if (mfma_forward(d, form))
+    if (mfma_forward(d, form, feat_dtype))
         return render_fwd_bf16_shape_ok(d, slice, rows) && !(form == FH_FORM_F32 && rows == 16 && slice == 128);
     return rows == 16 && (slice == 8 || slice == 16 || slice == 32 || slice == 64);
 }
@@ -159,7 +162,8 @@ static bool fwd_shape_ok(int d, int form, int slice, int rows) {
 static bool bwd_chunk_ok(int d, int chunk) { return chunk == 16 || (chunk == 32 && d <= 512); }
 
 static bool tuning_ok(const fh_plan* p) {
-    return fwd_shape_ok(p->d, p->form, p->tuning.fwd_slice, p->tuning.fwd_rows) && bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
+    return fwd_shape_ok(p->d, p->form, p->feat_dtype, p->tuning.fwd_slice, p->tuning.fwd_rows) &&
+           bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
 }
 
 // depth sort, tiles per rank, their scan, the instance count and the overflow flag
@@ -229,7 +233,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     plan->rank_bits = ceil_log2(total > 1 ? total : 2);
     plan->tile_bits = ceil_log2(tiles > 1 ? tiles : 2);
     plan->packed_keys = (plan->rank_bits + plan->tile_bits) <= 32 ? 1 : 0;
-    plan->tuning = default_tuning(d, form);
+    plan->tuning = default_tuning(d, form, feat_dtype);
 
     size_t sz[WS_COUNT];
     memset(sz, 0, sizeof(sz));
@@ -381,7 +385,7 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     launch_fill_u32(tile_niter, p->n_tiles, 0u, s);
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_FWD, s);
-    if (mfma_forward(p->d, p->form))
+    if (mfma_forward(p->d, p->form, p->feat_dtype))
         launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, !a.feat_bf16, s);
     else
         launch_render_fwd_f32(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
@@ -581,7 +585,7 @@ fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, 
         static const int slices[] = {8, 16, 32, 64, 96, 128, 256};
         for (int rows : {16, 8})
             for (int sl : slices)
-                if (fwd_shape_ok(p->d, p->form, sl, rows) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
+                if (fwd_shape_ok(p->d, p->form, p->feat_dtype, sl, rows) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
                     out[n] = p->tuning;
                     out[n].fwd_slice = sl;
                     out[n++].fwd_rows = rows;

@@ -113,14 +113,20 @@ def test_tuning_defaults_and_candidates_on_host():
         return [(out[i].fwd_slice, out[i].bwd_chunk, out[i].fwd_rows) for i in range(n.value)]
 
     plan = _lib.FhPlan()
-    # FP32 form, d = 256: the MFMA forward's shapes (without 16 rows of 128
-    # channels), backward chunks 16 and 32
+    # FP32 form, d = 256, BF16-stored features: the VALU forward's slices 8..64,
+    # backward chunks 16 and 32
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 0, cams, 1, 0, 0) == 0
+    assert (plan.tuning.fwd_slice, plan.tuning.bwd_chunk, plan.tuning.fwd_rows) == (64, 32, 16)
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(8, 32, 16), (16, 32, 16), (32, 32, 16), (64, 32, 16)]
+    assert cands(plan, _lib.FH_K_RENDER_BWD) == [(64, 16, 16), (64, 32, 16)]
+    assert cands(plan, _lib.FH_K_PROJECT) == [(64, 32, 16)]
+    # FP32 form, d = 256, FP32 features: the MFMA forward's shapes (without 16
+    # rows of 128 channels)
+    assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 0, 0, cams, 1, 0, 0) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.bwd_chunk, plan.tuning.fwd_rows) == (256, 32, 8)
     assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32, 16), (64, 32, 16), (64, 32, 8), (128, 32, 8),
                                                (256, 32, 8)]
     assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 16, 8), (256, 32, 8)]
-    assert cands(plan, _lib.FH_K_PROJECT) == [(256, 32, 8)]
     # BF16 form, d = 256: slices dividing d for 16-row and 8-row workgroups; one backward shape
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 0, 0) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.fwd_rows) == (256, 8)
