@@ -250,7 +250,9 @@ fh_status fh_render_fwd(const fh_plan *plan, const fh_gaussians *g, void *ws, co
  * the same sweep also accumulates feature fusion into acc.  In the BF16 form
  * the target must be BF16 (FH_E_UNSUPPORTED otherwise): it is an MFMA
  * operand as stored.
- * Gradients are written (not accumulated) into `out`. */
+ * Gradients are written (not accumulated) into `out`.  After an instance or
+ * visit overflow (fh_read_counters) the gradients are all zero and acc is
+ * left unchanged. */
 fh_status fh_render_bwd(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd,
                         const fh_upstream *up, const void *fusion_target, fh_dtype target_dtype,
                         const fh_fusion *acc, const fh_grads *out, hipStream_t stream);

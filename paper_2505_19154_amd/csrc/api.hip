@@ -537,6 +537,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     pb.sh_degree = p->sh_degree;
     pb.grad2d = r.grad2d;
     pb.depth_key = cbuf<uint32_t>(p, ws, WS_DEPTH_KEY);
+    pb.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
     pb.g_means = out->means;
     pb.g_scales = out->scales;
     pb.g_quats = out->quats;

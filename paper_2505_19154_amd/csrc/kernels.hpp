@@ -18,6 +18,7 @@ struct ProjectBwdArgs {
     int n, sh_degree;
     const float* grad2d;
     const uint32_t* depth_key;
+    const Counters* counters;   // an instance or visit overflow leaves the (zero-filled) outputs zero
     float *g_means, *g_scales, *g_quats, *g_opacity, *g_sh;
 };
 void launch_project(const ProjectArgs&, const CamTable&, const ViewTable&, int, hipStream_t);

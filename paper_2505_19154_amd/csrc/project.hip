@@ -279,6 +279,9 @@ __device__ __forceinline__ bool upstream_zero(const float* grad2d, size_t j) {
 __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable ct, int n_views) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.n) return;
+    // after an overflow the per-(view, Gaussian) adjoints were not recomputed
+    // (they hold an earlier call's values): leave the gradients zero
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     bool any = false;
     for (int v = 0; v < n_views && !any; ++v) {
         const size_t j = (size_t)v * a.n + g;

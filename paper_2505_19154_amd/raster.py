@@ -31,6 +31,38 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _same_device(a, b) -> bool:
+    a, b = torch.device(a), torch.device(b)
+    if a.type != b.type:
+        return False
+    if a.type != "cuda":
+        return True
+    cur = lambda d: d.index if d.index is not None else torch.cuda.current_device()
+    return cur(a) == cur(b)
+
+
+def check_tensor(t, name: str, shape: tuple, dtypes: tuple, device) -> None:
+    """Raise FhError unless `t` can be handed to a kernel as `name`: a tensor on
+    `device`, contiguous, of one of `dtypes`, of exactly `shape`, and with its
+    data 16-byte aligned (the kernels index rows by the stated shape and load
+    four floats at a time)."""
+    if not isinstance(t, torch.Tensor):
+        raise L.FhError(f"{name} must be a tensor")
+    if not _same_device(t.device, device):
+        raise L.FhError(f"{name} must be on {device}, not {t.device}")
+    if t.dtype not in dtypes:
+        raise L.FhError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, not {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise L.FhError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise L.FhError(f"{name} must be contiguous")
+    if t.numel() and t.data_ptr() % 16:
+        raise L.FhError(f"{name} must be 16-byte aligned")
+
+
+_F32 = (torch.float32,)
+
+
 @dataclass
 class Gaussians:
     """Device tensors of the Gaussians (activated parameters, see include/fhgs.h)."""
@@ -119,6 +151,10 @@ class Rasterizer:
         self.plan = None
         self.ws = None
         self.tuning = None          # launch shape chosen by autotune (kept across re-plans)
+        # bumped by every call that rewrites the forward state held in the
+        # workspace (projection, binning, traversal lengths) or replaces the
+        # workspace: a backward checks that its forward's state is still there
+        self.generation = 0
         self._plan(inst_capacity, visit_capacity)
 
     # -- plan and workspace -------------------------------------------------
@@ -130,6 +166,7 @@ class Rasterizer:
             plan.tuning = self.tuning
         self.plan = plan
         self.ws = torch.empty(max(int(plan.ws_bytes), 256), dtype=torch.uint8, device=self.device)
+        self.generation += 1
 
     def reserve(self, inst_capacity: int, visit_capacity: int) -> None:
         if inst_capacity != self.plan.inst_capacity or visit_capacity != self.plan.visit_capacity:
@@ -155,7 +192,36 @@ class Rasterizer:
         return c
 
     # -- the C-ABI calls ----------------------------------------------------
+    def _check_image(self, img: "Image", name: str) -> None:
+        P, d, dev = self.n_pixels, self.d, self.device
+        check_tensor(img.C, f"{name}.C", (P, 3), _F32, dev)
+        check_tensor(img.T, f"{name}.T", (P,), _F32, dev)
+        check_tensor(img.n_iter, f"{name}.n_iter", (P,), (torch.int32,), dev)
+        if d:
+            if img.F is None:
+                raise L.FhError(f"{name}.F is required when d > 0")
+            check_tensor(img.F, f"{name}.F", (P, d), _F32, dev)
+
+    def _check_target(self, target) -> int:
+        """The fusion target's dtype code; BF16 form: BF16 only (an MFMA operand)."""
+        ok = (torch.bfloat16,) if self.form == L.FH_FORM_BF16 else (torch.float32, torch.bfloat16)
+        check_tensor(target, "target", (self.n_pixels, self.d), ok, self.device)
+        return L.FH_BF16 if target.dtype == torch.bfloat16 else L.FH_F32
+
+    def _check_acc(self, acc: "FusionAcc") -> None:
+        for nm in ("sum", "comp"):
+            check_tensor(getattr(acc, nm), f"acc.{nm}", (self.n, self.d), _F32, self.device)
+        for nm in ("wsum", "wcomp"):
+            check_tensor(getattr(acc, nm), f"acc.{nm}", (self.n,), _F32, self.device)
+
+    def _check_grads(self, grads: dict) -> None:
+        n, nb = self.n, (self.sh_degree + 1) ** 2
+        shapes = dict(means=(n, 3), scales=(n, 3), quats=(n, 4), opacity=(n,), sh=(n, nb, 3))
+        for k, shp in shapes.items():
+            check_tensor(grads[k], f"grads[{k!r}]", shp, _F32, self.device)
+
     def project(self, g: Gaussians) -> None:
+        self.generation += 1
         gs = g.struct()
         L.check(self.lib.fh_project(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), _stream()), "fh_project")
 
@@ -163,6 +229,7 @@ class Rasterizer:
         L.check(self.lib.fh_bin_count(ctypes.byref(self.plan), _ptr(self.ws), _stream()), "fh_bin_count")
 
     def bin_sort(self) -> None:
+        self.generation += 1
         L.check(self.lib.fh_bin_sort(ctypes.byref(self.plan), _ptr(self.ws), _stream()), "fh_bin_sort")
 
     def bin_keys(self, n_inst: int):
@@ -182,6 +249,8 @@ class Rasterizer:
 
     def render_fwd(self, g: Gaussians, out: Image | None = None) -> Image:
         out = out or self.new_image()
+        self._check_image(out, "out")
+        self.generation += 1
         gs, im = g.struct(), out.struct()
         L.check(self.lib.fh_render_fwd(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
                                        _stream()), "fh_render_fwd")
@@ -195,12 +264,25 @@ class Rasterizer:
     def render_bwd(self, g: Gaussians, fwd: Image, dC, dF=None, dT=None, target=None, acc: FusionAcc | None = None,
                    grads: dict | None = None) -> dict:
         grads = grads or self.new_grads()
+        P, d, dev = self.n_pixels, self.d, self.device
+        self._check_image(fwd, "fwd")
+        check_tensor(dC, "dC", (P, 3), _F32, dev)
+        if dF is not None and d:
+            check_tensor(dF, "dF", (P, d), _F32, dev)
+        if dT is not None:
+            check_tensor(dT, "dT", (P,), _F32, dev)
+        self._check_grads(grads)
+        tdt = L.FH_F32
+        if target is not None:
+            if acc is None:
+                raise L.FhError("fusion needs an accumulator (acc)")
+            tdt = self._check_target(target)
+            self._check_acc(acc)
         gs, im = g.struct(), fwd.struct()
         up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT))
         gr = L.FhGrads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
                        _ptr(grads["sh"]))
-        tdt = L.FH_BF16 if (target is not None and target.dtype == torch.bfloat16) else L.FH_F32
-        fu = acc.struct() if acc is not None else None
+        fu = acc.struct() if (acc is not None and target is not None) else None
         L.check(self.lib.fh_render_bwd(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
                                        ctypes.byref(up), _ptr(target), tdt,
                                        ctypes.byref(fu) if fu is not None else None, ctypes.byref(gr), _stream()),
@@ -208,8 +290,10 @@ class Rasterizer:
         return grads
 
     def fuse_features(self, g: Gaussians, fwd: Image, target: torch.Tensor, acc: FusionAcc) -> None:
+        self._check_image(fwd, "fwd")
+        tdt = self._check_target(target)
+        self._check_acc(acc)
         gs, im, fu = g.struct(), fwd.struct(), acc.struct()
-        tdt = L.FH_BF16 if target.dtype == torch.bfloat16 else L.FH_F32
         L.check(self.lib.fh_fuse_features(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
                                           _ptr(target), tdt, ctypes.byref(fu), _stream()), "fh_fuse_features")
 
@@ -237,6 +321,7 @@ class Rasterizer:
         synchronisation or launch overhead.  Overflow is checked afterwards with
         `counters()`."""
         grads = grads or self.new_grads()
+        self.generation += 1
         graph = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -279,6 +364,7 @@ class Rasterizer:
         if key in table:
             t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]), int(table[key]["fwd_rows"]))
         else:
+            self.generation += 1
             gs, im = g.struct(), img.struct()
             up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT)) if dC is not None else None
             grads = self.new_grads() if dC is not None else None
@@ -334,11 +420,16 @@ class Rasterizer:
 
 def fuse_finalize(acc: FusionAcc, feat_in: torch.Tensor | None, out_dtype=torch.float32) -> torch.Tensor:
     lib = L.load()
+    if out_dtype not in (torch.float32, torch.bfloat16):
+        raise L.FhError("out_dtype must be float32 or bfloat16")
     n, d = acc.sum.shape
-    out = torch.empty(n, d, dtype=out_dtype, device=acc.sum.device)
+    dev = acc.sum.device
+    for nm, shp in (("sum", (n, d)), ("comp", (n, d)), ("wsum", (n,)), ("wcomp", (n,))):
+        check_tensor(getattr(acc, nm), f"acc.{nm}", shp, _F32, dev)
+    out = torch.empty(n, d, dtype=out_dtype, device=dev)
     dt = L.FH_BF16 if out_dtype == torch.bfloat16 else L.FH_F32
-    if feat_in is not None and feat_in.dtype != out_dtype:
-        raise L.FhError("feat_in must have the output dtype")
+    if feat_in is not None:
+        check_tensor(feat_in, "feat_in", (n, d), (out_dtype,), dev)
     fu = acc.struct()
     L.check(lib.fh_fuse_finalize(ctypes.byref(fu), n, d, _ptr(feat_in), _ptr(out), dt, _stream()), "fh_fuse_finalize")
     return out

@@ -283,3 +283,82 @@ def test_forward_runs_until_every_pixel_stops(form):
     assert U.elementwise(img.T.cpu().numpy(), v["T"], v["T"], mask=ok)[0] <= 1.0
     assert U.elementwise(img.F.cpu().numpy(), v["F"], v["Fmag"], rtol=U.RTOL_FORM[form],
                          mask=ok[:, None].repeat(32, 1))[0] <= 1.0
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_overflow_leaves_zero_gradients_not_stale_ones(form):
+    """A backward whose visits overflow the capacity writes zero gradients and
+    leaves the fusion accumulators alone, although the workspace still holds
+    the per-(view, Gaussian) adjoints of an earlier, complete backward."""
+    from paper_2505_19154_amd.raster import FusionAcc
+    g = scenegen.make_gaussians(600, 1.0, 1, 32, seed=21, feat_dtype="bf16")
+    cams = scenegen.make_cameras("front64x48")
+    few = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    few["means"] = g["means"].copy()
+    few["means"][40:] += np.float32([0.0, -9.0, 0.0])     # all but 40 behind the camera
+    vts = U.view_maps(cams, 32, target_dtype="bf16")
+    dC, dF, dT = U.concat(vts, "dC"), U.concat(vts, "dF"), U.concat(vts, "dT")
+    target = U.concat(vts, "target_bits")
+    dfew, r = _raster(few, cams, form=form)
+    r.forward(dfew)
+    c = r.counters()
+    r.reserve(int(c.n_instances), int(c.n_visited))      # capacities exactly those of the 40
+    img = r.forward(dfew)
+    grads = r.render_bwd(dfew, img, dC, dF, dT)
+    torch.cuda.synchronize()
+    assert any(bool(torch.any(v != 0)) for v in grads.values())
+    dg = U.device_gaussians(g)
+    r.project(dg)
+    r.bin_sort()
+    r.render_fwd(dg, img)
+    acc = FusionAcc.zeros(dg.n, 32, "cuda")
+    grads = {k: torch.full_like(v, float("nan")) for k, v in grads.items()}
+    r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+    torch.cuda.synchronize()
+    c = r.counters()
+    assert c.inst_overflow or c.visit_overflow
+    for k, v in grads.items():
+        assert torch.all(v == 0), k
+    for t_ in (acc.sum, acc.comp, acc.wsum, acc.wcomp):
+        assert torch.all(t_ == 0)
+
+
+def test_backward_after_another_forward_raises():
+    """RasterizeFn.backward needs its own forward's binning in the workspace:
+    a second forward on the same rasterizer in between is refused."""
+    from paper_2505_19154_amd._lib import FhError
+    from paper_2505_19154_amd.autograd import rasterize
+    g = scenegen.make_gaussians(300, 1.0, 0, 8, seed=22)
+    cams = scenegen.make_cameras("front64x48")
+    dg, r = _raster(g, cams)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    p1 = [t(g[k]).requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    p2 = [t(g[k]).requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    C1, _, _, _ = rasterize(r, *p1, t(g["feat"]), 0)
+    C2, _, _, _ = rasterize(r, *p2, t(g["feat"]), 0)
+    with pytest.raises(FhError):
+        C1.sum().backward()
+    C2.sum().backward()          # the latest forward still backpropagates
+    assert p2[3].grad is not None and torch.isfinite(p2[3].grad).all()
+
+
+def test_binding_rejects_misshapen_tensors_before_launch():
+    from paper_2505_19154_amd._lib import FhError
+    g = scenegen.make_gaussians(300, 1.0, 0, 8, seed=23)
+    cams = scenegen.make_cameras("front64x48")
+    dg, r = _raster(g, cams)
+    img = r.forward(dg)
+    P = r.n_pixels
+    dC = torch.zeros(P, 3, device="cuda")
+    with pytest.raises(FhError):
+        r.render_bwd(dg, img, torch.zeros(P - 1, 3, device="cuda"))
+    with pytest.raises(FhError):
+        r.render_bwd(dg, img, dC, dF=torch.zeros(8, P, device="cuda").t())      # not contiguous
+    from paper_2505_19154_amd.raster import FusionAcc
+    acc = FusionAcc.zeros(dg.n, 8, "cuda")
+    with pytest.raises(FhError):
+        r.render_bwd(dg, img, dC, target=torch.zeros(P, 8, dtype=torch.float16, device="cuda"), acc=acc)
+    with pytest.raises(FhError):
+        r.render_bwd(dg, img, dC, target=torch.zeros(P, 8, device="cuda"), acc=FusionAcc.zeros(dg.n - 1, 8, "cuda"))
+    with pytest.raises(FhError):
+        r.fuse_features(dg, img, torch.zeros(P, 8, dtype=torch.float64, device="cuda"), acc)
