@@ -1,0 +1,205 @@
+"""Pins of the oracle's ambiguity bound (g2d_amb, fsum_amb, wsum_amb).
+
+A float decision that decides an integer outcome (a blend skipped because
+alpha < 1/255, a pixel stopped because T' < 1e-4, alpha clamped at 0.99) can go
+the other way in FP32 when it lies close to its threshold.  The oracle bounds,
+per Gaussian, how much any such decision taken the other way can change the
+per-Gaussian sums (screen-space adjoints, fusion sums, weight sums); the parity
+tests add AMB_FACTOR times that bound to their tolerance.
+
+These tests take each decision both ways in FP64 on purpose: the deciding
+Gaussian is centred on a pixel (so alpha there is its opacity exactly) and its
+opacity is set a relative 1e-11 above and below the threshold.  Both runs'
+bounds must cover the difference between the two runs for every Gaussian and
+every component.  Any dropped term of the bound (the decider's own would-be
+blend, its share of a contributor's suffix S, the transmittance scaling q, the
+unclamped power and opacity terms) makes one of these fail.
+"""
+import numpy as np
+import pytest
+
+from oracle import consts, raster
+from tests import gpu_util as U
+
+DELTA = 1e-11
+
+
+class _Cam:
+    def __init__(self, w, h):
+        self.width, self.height = w, h
+
+
+def _scene(seed, n=14, d=6, w=32, h=16):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0, w, n)
+    v = rng.uniform(0, h, n)
+    # conics of covariances with sigmas of 2-7 px and a random orientation
+    th = rng.uniform(0, np.pi, n)
+    s1, s2 = rng.uniform(2, 7, n), rng.uniform(2, 7, n)
+    c, s = np.cos(th), np.sin(th)
+    a = c * c * s1 ** 2 + s * s * s2 ** 2
+    b = c * s * (s1 ** 2 - s2 ** 2)
+    cc = s * s * s1 ** 2 + c * c * s2 ** 2
+    det = a * cc - b * b
+    proj = dict(u=u, v=v, A=cc / det, B=-b / det, C=a / det, opacity=rng.uniform(0.15, 0.6, n),
+                rgb=rng.uniform(0, 1, (n, 3)))
+    feat = rng.normal(size=(n, d))
+    P = w * h
+    maps = dict(dC=rng.normal(size=(P, 3)), dF=rng.normal(size=(P, d)), dT=rng.normal(size=P),
+                target=rng.normal(size=(P, d)))
+    return proj, feat, maps
+
+
+def _render(proj, feat, maps, w=32, h=16):
+    n = proj["u"].size
+    tx = (w + consts.TILE - 1) // consts.TILE
+    ranges = np.array([[0, n]] * tx)      # every Gaussian listed in every tile, index = depth order
+    return raster.render_view(_Cam(w, h), ranges, np.arange(n), proj, feat=feat, **maps)
+
+
+def _alpha_before(proj, m, px, py):
+    """Transmittance at pixel (px, py) in front of list position m (FP64 walk)."""
+    T = 1.0
+    x, y = px + 0.5, py + 0.5
+    for j in range(m):
+        dx, dy = x - proj["u"][j], y - proj["v"][j]
+        pw = -0.5 * (proj["A"][j] * dx * dx + 2 * proj["B"][j] * dx * dy + proj["C"][j] * dy * dy)
+        a = min(consts.ALPHA_MAX, proj["opacity"][j] * np.exp(pw))
+        if a < consts.ALPHA_MIN:
+            continue
+        assert T * (1 - a) >= consts.T_MIN
+        T *= 1 - a
+    return T
+
+
+def _set_decider(proj, m, px, py, kind, sign):
+    """Centre Gaussian m on pixel (px, py) and set its opacity 1e-11 relative
+    above (sign +1) or below (-1) the threshold of decision `kind` there."""
+    p = {k: v.copy() for k, v in proj.items()}
+    p["u"][m], p["v"][m] = px + 0.5, py + 0.5
+    f = 1.0 + sign * DELTA
+    if kind == "skip":
+        p["opacity"][m] = consts.ALPHA_MIN * f
+    elif kind == "clamp":
+        p["opacity"][m] = consts.ALPHA_MAX * f
+    elif kind == "stop":
+        T = _alpha_before(p, m, px, py)
+        assert consts.T_MIN < T < consts.T_MIN / (1 - consts.ALPHA_MAX)
+        # T (1 - alpha) = T_MIN f: above the threshold (sign +1) the blend happens
+        p["opacity"][m] = 1.0 - consts.T_MIN * f / T
+    return p
+
+
+def _front_layers(proj, m, px, py, T_front=0.004):
+    """The Gaussians in front of m centred on pixel (px, py) with equal
+    opacities that leave T_front there, so that a stop decision at m needs an
+    alpha below the clamp (T_MIN / T_front = 0.025 of T_front remains)."""
+    p = {k: v.copy() for k, v in proj.items()}
+    p["u"][:m], p["v"][:m] = px + 0.5, py + 0.5
+    p["opacity"][:m] = 1.0 - T_front ** (1.0 / m)
+    return p
+
+
+KEYS = ("g2d", "fsum", "wsum")
+
+
+def _max_ratio(a, b, factor):
+    """Largest |a - b| / (factor amb + 1e-5 M) over both runs' bounds, per output."""
+    out = {}
+    for key in KEYS:
+        diff = np.abs(a[key] - b[key])
+        worst = 0.0
+        for run in (a, b):
+            mag = run[key + "_mag"] if key != "wsum" else run["wsum"]
+            bound = factor * run[key + "_amb"] + 1e-5 * np.abs(mag) + 1e-300
+            worst = max(worst, float((diff / bound).max()))
+        out[key] = worst
+    return out
+
+
+CASES = [(kind, m, seed) for kind in ("skip", "stop", "clamp") for m in (0, 3, 7, 12) for seed in range(6)
+         if not (kind == "stop" and m == 0)]
+# seeds from 100 on: the decider carries a feature 50 times larger than the
+# others' and dT = 0, so its own would-be blend in the suffix S of the
+# contributors in front of it dominates what a flip changes for them
+CASES += [(kind, m, seed) for kind in ("skip", "stop") for m in (3, 7, 12) for seed in range(100, 104)]
+
+
+def _case(kind, m, seed):
+    proj, feat, maps = _scene(seed % 100)
+    rng = np.random.default_rng(1000 + seed)
+    px, py = int(rng.integers(2, 30)), int(rng.integers(2, 14))
+    if kind == "stop":
+        proj = _front_layers(proj, m, px, py)
+    if seed >= 100:
+        feat = feat.copy()
+        feat[m] *= 50.0
+        maps = dict(maps, dT=np.zeros_like(maps["dT"]))
+    return proj, feat, maps, px, py
+
+
+@pytest.mark.parametrize("kind,m,seed", CASES)
+def test_flipped_decision_stays_within_the_bound(kind, m, seed):
+    proj, feat, maps, px, py = _case(kind, m, seed)
+    hi = _render(_set_decider(proj, m, px, py, kind, +1), feat, maps)
+    lo = _render(_set_decider(proj, m, px, py, kind, -1), feat, maps)
+    pix = py * 32 + px
+    # the decision did flip, and both runs call it ambiguous
+    if kind == "skip":
+        assert hi["niter"][pix] != lo["niter"][pix] or hi["T"][pix] != lo["T"][pix]
+    elif kind == "stop":
+        assert hi["niter"][pix] == m + 1 and lo["niter"][pix] <= m
+    assert (hi["flags"][pix] != 0) and (lo["flags"][pix] != 0)
+    # something changed beyond the smooth effect of a 1e-11 step
+    diff = max(float(np.abs(hi[k] - lo[k]).max()) for k in KEYS)
+    assert diff > 1e-9
+    r = _max_ratio(hi, lo, U.AMB_FACTOR)
+    for key in KEYS:
+        assert r[key] <= 1.0, (key, r)
+
+
+def test_bound_is_tight_enough_for_a_factor_of_one():
+    """The worst case over all flips stays within the bound itself (factor 1),
+    up to the 1e-11 step: the bound is the first-order change, and it is met
+    exactly by the decider's own would-be blend (bounded by that blend) and to
+    within a few percent by the contributors behind a skip (their
+    transmittances scale by 1 - alpha, bounded by alpha / (1 - alpha))."""
+    worst = {k: 0.0 for k in KEYS}
+    for kind, m, seed in CASES:
+        proj, feat, maps, px, py = _case(kind, m, seed)
+        hi = _render(_set_decider(proj, m, px, py, kind, +1), feat, maps)
+        lo = _render(_set_decider(proj, m, px, py, kind, -1), feat, maps)
+        r = _max_ratio(hi, lo, 1.0)
+        for k in KEYS:
+            worst[k] = max(worst[k], r[k])
+    print("[amb] worst |flip difference| / (amb + 1e-5 M):", worst)
+    assert max(worst.values()) <= 1.0 + 1e-9
+
+
+def test_two_skip_deciders_in_one_pixel():
+    """Two near-threshold skips in the same pixel, each flipped alone and both
+    together: q sums over the pixel's deciders, and AMB_FACTOR covers the
+    second-order term of simultaneous flips."""
+    proj, feat, maps = _scene(3)
+    px, py = 10, 7
+    base = {k: v.copy() for k, v in proj.items()}
+    for m in (2, 9):
+        base["u"][m], base["v"][m] = px + 0.5, py + 0.5
+
+    def run(s2, s9):
+        p = {k: v.copy() for k, v in base.items()}
+        p["opacity"][2] = consts.ALPHA_MIN * (1 + s2 * DELTA)
+        p["opacity"][9] = consts.ALPHA_MIN * (1 + s9 * DELTA)
+        return _render(p, feat, maps)
+
+    runs = {s: run(*s) for s in ((1, 1), (1, -1), (-1, 1), (-1, -1))}
+    # one decision flipped: within the bound; both at once: the later decider's
+    # would-be blend sees the earlier one's transmittance factor as well (a
+    # second-order term), within 1 / (1 - 1/255) of the bound
+    for sa in runs:
+        for sb in runs:
+            if sa < sb:
+                flips = sum(x != y for x, y in zip(sa, sb))
+                r = _max_ratio(runs[sa], runs[sb], 1.0)
+                assert max(r.values()) <= (1.0 + 1e-9) / (1.0 - consts.ALPHA_MIN) ** (flips - 1), (sa, sb, r)
+                assert max(r.values()) <= U.AMB_FACTOR
