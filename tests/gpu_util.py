@@ -85,10 +85,17 @@ def split_views(arr, cams):
 
 
 # A near-threshold decision of one Gaussian may go the other way in FP32 and
-# change the other contributors' terms in that pixel; the oracle bounds those
-# terms' magnitudes (grads_amb, fsum_amb, wsum_amb).  The FP32 and FP64 values
-# of such a pixel's terms differ by at most their two magnitudes, with a margin.
-AMB_FACTOR = 3.0
+# change its own and the other contributors' terms in that pixel; the oracle
+# bounds that change to first order (grads_amb, fsum_amb, wsum_amb).  Taking a
+# single decision both ways in FP64 changes the sums by at most the bound itself
+# (tests/test_oracle_ambiguity.py; the decider's own would-be blend meets it
+# exactly).  The factor covers what first order leaves out: FP32 flips happen
+# within ~1e-6 relative of a threshold (second-order terms of that size), the
+# rounding of the terms a flip adds or removes (within 2e-5 of them), and k skip
+# decisions of one pixel flipping together, where a later decider's would-be
+# blend also carries the earlier ones' transmittance factors, up to
+# (1 - 1/255)^-(k-1): 1.05 covers k <= 13.
+AMB_FACTOR = 1.05
 
 
 def checkable(gflags):
