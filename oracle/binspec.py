@@ -32,6 +32,23 @@ The products inside a parenthesised pair are rounded before the add.  The box
 half-extent sqrt(KAPPA Sigma2_ii) bounds every point where
 -1/2 d^T Sigma2^-1 d >= -ln 255 (KAPPA > 2 ln 255 = 11.08), so no pixel where
 alpha can reach 1/255 is outside the rect and tiling never changes a result.
+
+Opacity-aware rule (rule="opacity"): alpha = o G reaches 1/255 only where
+d^T Sigma2^-1 d <= 2 ln(255 o), so each Gaussian gets its own
+  kappa_i = min(KAPPA, 2 ln(255 o_i) + 1/256)       (culled if 255 o_i <= 1)
+in place of KAPPA, with ln evaluated in float32 by basic operations only (so
+that both sides round identically):
+  x = 255 * o;  x = m 2^e with m in [1, 2) (exact, from the float's bits);
+  if m > sqrt2f: m = m * 0.5, e = e + 1 (exact)
+  s = (m - 1) / (m + 1);  z = s * s
+  p = (((z / 9 + 1/7) z + 1/5) z + 1/3) z + 1     (Horner, constants as float32:
+      p = (((c9 z + c7) z + c5) z + c3) z + 1 with c_k = float32(1/k))
+  ln x = float32(e) * ln2f + (s + s) * p            (the atanh series of ln m)
+  kappa = min(KAPPA, (ln x + ln x) + 1/256)
+|s| <= 0.1716 after the range step, so the series' remainder (s^11/11 relative)
+is below float32 resolution; the 1/256 margin exceeds the float32 error of
+2 ln x many times over, so the rect still holds every pixel where alpha can
+reach 1/255.
 """
 from __future__ import annotations
 
@@ -47,8 +64,48 @@ def _dot3(r, x, y, z):
     return ((r[0] * x + r[1] * y) + r[2] * z)
 
 
-def bin_quantities(g: dict, cam) -> dict:
-    """Per-Gaussian float32 depth, rect and tile count for one camera."""
+SQRT2_F32 = f32(1.4142135)
+LN2_F32 = f32(0.6931472)
+C3, C5, C7, C9 = (f32(1.0 / k) for k in (3, 5, 7, 9))
+KAPPA_MARGIN = f32(1.0 / 256.0)
+
+
+def ln_f32(x: np.ndarray) -> np.ndarray:
+    """Natural log of float32 x > 0 (finite, normal), by the fixed sequence of
+    float32 operations in the module docstring."""
+    x = np.asarray(x, f32)
+    bits = x.view(np.uint32)
+    e = (bits >> np.uint32(23)).astype(np.int64) - 127
+    m = ((bits & np.uint32(0x7FFFFF)) | np.uint32(0x3F800000)).view(f32)
+    big = m > SQRT2_F32
+    m = np.where(big, m * f32(0.5), m).astype(f32)
+    e = e + big.astype(np.int64)
+    one = f32(1.0)
+    s = (m - one) / (m + one)
+    z = s * s
+    p = (((C9 * z + C7) * z + C5) * z + C3) * z + one
+    return e.astype(f32) * LN2_F32 + (s + s) * p
+
+
+def opacity_kappa(o: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Per-Gaussian box factor of the opacity-aware rule, and whether the
+    Gaussian can reach alpha = 1/255 at all (255 o > 1)."""
+    x = f32(255.0) * np.asarray(o, f32)
+    live = x > f32(1.0)
+    with np.errstate(all="ignore"):
+        lx = ln_f32(np.where(live, x, f32(2.0)).astype(f32))
+        kap = np.minimum((lx + lx) + KAPPA_MARGIN, consts.KAPPA_F32)
+    return np.where(live, kap, f32(0.0)).astype(f32), live
+
+
+RULES = ("box", "opacity")
+
+
+def bin_quantities(g: dict, cam, rule: str = "box") -> dict:
+    """Per-Gaussian float32 depth, rect and tile count for one camera, under the
+    box rule (one KAPPA for all) or the opacity-aware rule (kappa_i)."""
+    if rule not in RULES:
+        raise ValueError(rule)
     mu = np.asarray(g["means"], f32)
     s = np.asarray(g["scales"], f32)
     q = np.asarray(g["quats"], f32)
@@ -94,8 +151,14 @@ def bin_quantities(g: dict, cam) -> dict:
         W1 = [(T1[0] * M[:, 0, l] + T1[1] * M[:, 1, l]) + T1[2] * M[:, 2, l] for l in range(3)]
         a = ((W0[0] * W0[0] + W0[1] * W0[1]) + W0[2] * W0[2]) + consts.LOWPASS_F32
         c = ((W1[0] * W1[0] + W1[1] * W1[1]) + W1[2] * W1[2]) + consts.LOWPASS_F32
-        ex = np.sqrt(consts.KAPPA_F32 * a)
-        ey = np.sqrt(consts.KAPPA_F32 * c)
+        if rule == "box":
+            ex = np.sqrt(consts.KAPPA_F32 * a)
+            ey = np.sqrt(consts.KAPPA_F32 * c)
+            live = np.ones(mu.shape[0], bool)
+        else:
+            kap, live = opacity_kappa(g["opacity"])
+            ex = np.sqrt(kap * a)
+            ey = np.sqrt(kap * c)
 
         ts = f32(consts.TILE)
         x0f = np.floor((u - ex) / ts)
@@ -103,7 +166,7 @@ def bin_quantities(g: dict, cam) -> dict:
         y0f = np.floor((v - ey) / ts)
         y1f = np.floor((v + ey) / ts)
         finite = np.isfinite(u) & np.isfinite(v) & np.isfinite(ex) & np.isfinite(ey)
-        ok = visible & finite
+        ok = visible & finite & live
         x0 = np.where(ok, np.maximum(x0f, f32(0)), f32(0))
         x1 = np.where(ok, np.minimum(x1f, f32(TX - 1)), f32(-1))
         y0 = np.where(ok, np.maximum(y0f, f32(0)), f32(0))
@@ -111,7 +174,7 @@ def bin_quantities(g: dict, cam) -> dict:
     x0, x1, y0, y1 = (np.asarray(z, np.float64).astype(np.int64) for z in (x0, x1, y0, y1))
     nonempty = ok & (x0 <= x1) & (y0 <= y1)
     ntiles = np.where(nonempty, (x1 - x0 + 1) * (y1 - y0 + 1), 0).astype(np.int64)
-    return dict(depth=depth.astype(f32), visible=visible & finite, binned=nonempty,
+    return dict(depth=depth.astype(f32), visible=visible & finite & live, binned=nonempty,
                 x0=x0, x1=x1, y0=y0, y1=y1, ntiles=ntiles, tiles_x=TX, tiles_y=TY,
                 u32=u.astype(f32), v32=v.astype(f32), ex=ex.astype(f32), ey=ey.astype(f32))
 
@@ -201,9 +264,9 @@ def tile_list(bq: dict, tx: int, ty: int) -> np.ndarray:
     return hit[np.lexsort((hit, dbits))].astype(np.int64)
 
 
-def bin_views(g: dict, cams: list) -> dict:
+def bin_views(g: dict, cams: list, rule: str = "box") -> dict:
     """The whole binning step for a list of cameras."""
-    bq = [bin_quantities(g, c) for c in cams]
+    bq = [bin_quantities(g, c, rule) for c in cams]
     inst = duplicate_with_keys(bq)
     srt = sort_and_ranges(inst)
     return dict(per_view=bq, tile_offsets=inst["tile_offsets"], num_tiles=inst["num_tiles"],

@@ -20,16 +20,17 @@ def view_slice(bins: dict, vi: int, cam) -> np.ndarray:
 
 def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = False,
         tile_sel: list | None = None, want_F: bool = True, want_dfeat: bool = False,
-        want_Fmag: bool = False, magnitudes: bool = True) -> dict:
+        want_Fmag: bool = False, magnitudes: bool = True, bin_rule: str = "box") -> dict:
     """Forward (and adjoint when view_tensors is given) for every camera.
 
     view_tensors[v] holds dC [P,3], dF [P,D], dT [P] and, for fusion, target [P,D].
     tile_sel[v] optionally restricts the traversal to some of view v's tiles.
+    bin_rule: "box" (one KAPPA) or "opacity" (per-Gaussian kappa_i, binspec).
     gflags: bit 0 the Gaussian decides a near-threshold skip/stop decision,
     bit 2 its colour clamp is near-threshold; grads_amb / fsum_amb / wsum_amb
     bound what near-threshold decisions of other Gaussians could change.
     """
-    bins = binspec.bin_views(g, cams)
+    bins = binspec.bin_views(g, cams, bin_rule)
     feat = np.asarray(g["feat"], np.float64) if g["feat"] is not None else None
     n = g["means"].shape[0]
     views = []
