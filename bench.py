@@ -2,13 +2,15 @@
 """Benchmark: one step = project -> bin_sort -> render_fwd -> render_bwd (+ feature
 fusion) over one batch of synthetic views, all through the C ABI on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload c3] [--form f32|bf16]
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--form f32|bf16] [--batched c4]
 
 Prints ONE JSON line: Gaussian-pixel blends per second (sum over pixels of the
 list positions each pixel walks, n_iter) with inputs resident in HBM, the
 roofline position of the dominant kernel (timed live with HIP events on its
 own stream), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+workload.  The line also carries the batched workload ("batched": 16 views
+of uneven size by default), both arithmetic forms, each step captured in one
+HIP graph and timed as graph replays.
 """
 from __future__ import annotations
 
@@ -47,6 +49,9 @@ def parse():
                     help="no GPU: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-calibration run into profiles/traffic_<kernel>_<workload>_<form>.json")
     ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with --traffic-from")
+    ap.add_argument("--batched", default="c4",
+                    help="batched workload timed after the headline as one graph-replayed step per form "
+                         "('' to skip)")
     return ap.parse_args()
 
 
@@ -174,9 +179,33 @@ def measured_traffic(kernel: str, workload: str, form: str):
     return float(t["hbm_bytes_per_launch"])
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _ranges(cpus) -> str:
+    cpus = sorted(cpus)
+    out, i = [], 0
+    while i < len(cpus):
+        j = i
+        while j + 1 < len(cpus) and cpus[j + 1] == cpus[j] + 1:
+            j += 1
+        out.append(str(cpus[i]) if i == j else f"{cpus[i]}-{cpus[j]}")
+        i = j + 1
+    return ",".join(out)
+
+
 def cpu_baseline(g, cams, vts, wl, target_seconds: float):
     """The FP64 oracle on a random sample of tiles (fwd + bwd + fusion), with the
-    O(N) stages (binning, projection, projection adjoint) run in full."""
+    O(N) stages (binning, projection, projection adjoint) run in full; on all
+    the threads OpenMP takes, then on one thread (a smaller sample)."""
     import numpy as np
 
     from oracle import binspec, pipeline, project, raster
@@ -196,28 +225,212 @@ def cpu_baseline(g, cams, vts, wl, target_seconds: float):
     ntiles = int(bins["num_tiles"])
     rng = np.random.default_rng(7)
     perm = rng.permutation(ntiles)
-    # calibrate on a few tiles, then size the sample to the time target
-    probe = perm[:8]
-    tp0 = time.perf_counter()
-    raster.render_view(cam, pipeline.view_slice(bins, 0, cam), bins["gids"], pr, feat=feat, dC=dC, dF=dF, dT=dT,
-                       target=tgt, tile_sel=probe, want_F=True, want_fusion=wl.fusion)
-    per_tile = max((time.perf_counter() - tp0) / len(probe), 1e-4)
-    k = int(min(ntiles, max(16, target_seconds / per_tile)))
-    sel = perm[:k]
-    t3 = time.perf_counter()
-    out = raster.render_view(cam, pipeline.view_slice(bins, 0, cam), bins["gids"], pr, feat=feat, dC=dC, dF=dF,
-                             dT=dT, target=tgt, tile_sel=sel, want_F=True, want_fusion=wl.fusion)
+    ranges = pipeline.view_slice(bins, 0, cam)
+
+    def walk(sel):
+        return raster.render_view(cam, ranges, bins["gids"], pr, feat=feat, dC=dC, dF=dF, dT=dT, target=tgt,
+                                  tile_sel=sel, want_F=True, want_fusion=wl.fusion)
+
+    def sampled(seconds, first):
+        # calibrate on a few tiles, then size the sample to the time target
+        tp0 = time.perf_counter()
+        walk(perm[first:first + 8])
+        per_tile = max((time.perf_counter() - tp0) / 8, 1e-4)
+        k = int(min(ntiles - first, max(16, seconds / per_tile)))
+        sel = perm[first:first + k]
+        ta = time.perf_counter()
+        out = walk(sel)
+        return out, k, time.perf_counter() - ta
+
+    threads = raster.num_threads()
+    out, k, t_walk = sampled(target_seconds, 0)
     t4 = time.perf_counter()
     project.project_bwd(pr, pipeline._unpack(out["g2d"]))
     t5 = time.perf_counter()
     frac = k / ntiles
-    t_equiv = (t1 - t0) + (t2 - t1) + (t5 - t4) + (t4 - t3) / frac
+    t_on = (t1 - t0) + (t2 - t1) + (t5 - t4)        # the O(N) stages (numpy, one thread)
+    t_equiv = t_on + t_walk / frac
     blends = float(out["counts"][0]) / frac
-    return dict(value=blends / t_equiv, unit="Gaussian-pixel blends/s", cores=raster.num_threads(), kind="oracle",
+    raster.set_num_threads(1)
+    try:
+        out1, k1, t_walk1 = sampled(max(2.0, target_seconds / 4), 0)
+    finally:
+        raster.set_num_threads(threads)
+    t_equiv1 = t_on + t_walk1 / (k1 / ntiles)
+    blends1 = float(out1["counts"][0]) / (k1 / ntiles)
+    try:
+        aff = _ranges(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = "unknown"
+    return dict(value=blends / t_equiv, unit="Gaussian-pixel blends/s", cores=threads, kind="oracle",
                 sample=(f"{k} of {ntiles} tiles (random, seed 7) composited fwd+bwd{'+fusion' if wl.fusion else ''} "
-                        f"in FP64 ({t4 - t3:.1f} s), scaled by the tile fraction; binning {t1 - t0:.1f} s, "
-                        f"projection {t2 - t1:.1f} s and its adjoint {t5 - t4:.1f} s run on all Gaussians"),
-                ms_per_view=1000.0 * t_equiv)
+                        f"in FP64 on {threads} threads ({t_walk:.1f} s), scaled by the tile fraction; binning "
+                        f"{t1 - t0:.1f} s, projection {t2 - t1:.1f} s and its adjoint {t5 - t4:.1f} s run on all "
+                        f"Gaussians"),
+                ms_per_view=1000.0 * t_equiv, cpu_model=_cpu_model(), nproc=os.cpu_count(), affinity=aff,
+                one_core=dict(value=blends1 / t_equiv1, ms_per_view=1000.0 * t_equiv1,
+                              sample=f"{k1} of {ntiles} tiles on 1 thread ({t_walk1:.1f} s), same O(N) stages"))
+
+
+DEVICE_MAPS_ABOVE = 4_000_000      # pixels: per-view maps drawn on the device beyond this
+
+
+def load_workload(wl, dev):
+    """Gaussians, cameras and per-view maps of a workload, resident on `dev`.
+    Small workloads draw their maps on the host (the CPU baseline reads them);
+    the batched ones draw them on the device (scenegen.make_view_tensors_device)."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2505_19154_amd.raster import Gaussians
+
+    g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
+    cams = scenegen.make_cameras(wl.views)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    feat = (torch.from_numpy(g["feat_bits"].view(np.int16)).to(dev).view(torch.bfloat16) if wl.feat_dtype == "bf16"
+            else t(g["feat"]))
+    dg = Gaussians(t(g["means"]), t(g["scales"]), t(g["quats"]), t(g["opacity"]), t(g["sh"]), feat, wl.sh_degree)
+    P = sum(c.npix for c in cams)
+    tdt = wl.feat_dtype
+    vts = None
+    if P <= DEVICE_MAPS_ABOVE:
+        vts = [scenegen.make_view_tensors(i, c.npix, wl.d, with_dT=False, target_dtype=tdt) for i, c in enumerate(cams)]
+        cat = lambda k: np.concatenate([v[k] for v in vts])
+        dC, dF, dT = t(cat("dC")), t(cat("dF")), t(cat("dT"))
+        target = None
+        if wl.fusion:
+            target = (torch.from_numpy(cat("target_bits").view(np.int16)).to(dev).view(torch.bfloat16)
+                      if tdt == "bf16" else t(cat("target")))
+    else:
+        dC = torch.empty(P, 3, device=dev)
+        dF = torch.empty(P, wl.d, device=dev)
+        dT = torch.empty(P, device=dev)
+        target = torch.empty(P, wl.d, device=dev, dtype=torch.bfloat16 if tdt == "bf16" else torch.float32)
+        off = 0
+        for i, c in enumerate(cams):
+            m = scenegen.make_view_tensors_device(i, c.npix, wl.d, dev, with_dT=False, target_dtype=tdt)
+            for dst, k in ((dC, "dC"), (dF, "dF"), (dT, "dT"), (target, "target")):
+                dst[off:off + c.npix] = m[k]
+            del m
+            off += c.npix
+        if not wl.fusion:
+            target = None
+    return dict(wl=wl, g=g, cams=cams, dg=dg, vts=vts, dC=dC, dF=dF, dT=dT, target=target)
+
+
+KERNEL_IDS = None
+
+
+def run_form(W, form_name: str, kernel: str, args, dev, graph: bool = False):
+    """Warm up, then time K steps of one arithmetic form.  The chosen kernel is
+    bracketed by HIP events on its own stream over K eager steps.  With graph,
+    the step is captured in one HIP graph and the K timed steps are replays."""
+    import torch
+
+    from paper_2505_19154_amd import _lib as L
+    from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
+
+    kid = {"project": L.FH_K_PROJECT, "bin": L.FH_K_BIN, "render_fwd": L.FH_K_RENDER_FWD,
+           "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}
+    wl, cams, dg = W["wl"], W["cams"], W["dg"]
+    dC, dF, dT, target = W["dC"], W["dF"], W["dT"], W["target"]
+    tag = f"[bench] {wl.name} {form_name}"
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev)
+    img = r.forward(dg, margin=1.02)
+    tuning = r.autotune(dg, img, dC, dF, dT, target=target, reps=2) if args.autotune else None
+    acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
+    grads = r.new_grads()
+
+    def step():
+        r.project(dg)
+        r.bin_sort()
+        r.render_fwd(dg, img)
+        r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    c = r.counters()
+    if c.inst_overflow or c.visit_overflow:
+        raise RuntimeError("capacity overflow during warm-up")
+    print(f"{tag}: warm-up done, {c.n_instances} instances, {c.n_visited} visited", file=sys.stderr, flush=True)
+    K = args.steps
+    ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in ks + ke:
+        e.record()
+    torch.cuda.synchronize()
+    arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
+    arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
+    L.check(r.lib.fh_set_kernel_events(kid[kernel], arr_s, arr_e, K), "fh_set_kernel_events")
+    def timed(fn):
+        """K calls of fn between K + 1 events: (mean, median) ms per call."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(K):
+            fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(K))
+        return ev[0].elapsed_time(ev[K]) / K, per[K // 2] if K % 2 else 0.5 * (per[K // 2 - 1] + per[K // 2])
+
+    eager_ms, eager_med = timed(step)
+    L.check(r.lib.fh_set_kernel_events(kid[kernel], None, None, 0), "fh_set_kernel_events")
+    kms = sum(a.elapsed_time(b) for a, b in zip(ks, ke)) / K
+    ms, med = eager_ms, eager_med
+    if graph:
+        g_obj, grads = r.capture_step(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
+        for _ in range(args.warmup):
+            g_obj.replay()
+        ms, med = timed(g_obj.replay)
+    c = r.counters()
+    if c.inst_overflow or c.visit_overflow:
+        raise RuntimeError("capacity overflow during the timed steps")
+    blends = int(img.n_iter.to(torch.int64).sum().item())
+    print(f"{tag}: {ms:.3f} ms/step{' (graph replay; eager %.3f)' % eager_ms if graph else ''}, "
+          f"{kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
+    return dict(r=r, img=img, c=c, ms=ms, median_ms=med, eager_ms=eager_ms, kms=kms, blends=blends,
+                tuning=tuning or r.tuning_dict())
+
+
+def visible_count(r, wl, n_views) -> int:
+    import torch
+    return int((r.ws_view("depth_key", torch.int32, wl.n * n_views) != -1).sum().item())
+
+
+def batched_leg(args, dev):
+    """Both arithmetic forms of a batched workload, each step one graph replay."""
+    import torch
+
+    import scenegen
+    wl = scenegen.WORKLOADS[args.batched]
+    print(f"[bench] batched workload {wl.name}: {wl.description}", file=sys.stderr, flush=True)
+    W = load_workload(wl, dev)
+    feat_b = 2 if wl.feat_dtype == "bf16" else 4
+    out = dict(workload=f"{wl.name}: {wl.description}", views=len(W["cams"]),
+               pixels=sum(c.npix for c in W["cams"]), graph_replay=True, forms={})
+    for form_name in ("f32", "bf16"):
+        res = run_form(W, form_name, args.kernel, args, dev, graph=True)
+        n_vis = visible_count(res["r"], wl, len(W["cams"]))
+        ab, per_unit = alg_bytes(args.kernel, wl, res["r"].n_pixels, n_vis, int(res["c"].n_instances), feat_b, feat_b)
+        achieved = ab / (res["kms"] * 1e-3) / 1e9
+        out["forms"][form_name] = dict(
+            ms_per_step=res["ms"], ms_per_step_median=res["median_ms"], ms_per_view=res["ms"] / len(W["cams"]),
+            eager_ms_per_step=res["eager_ms"],
+            blends=res["blends"], blends_per_s=res["blends"] / (res["ms"] * 1e-3),
+            instances=int(res["c"].n_instances), visited_instances=int(res["c"].n_visited), visible_gaussians=n_vis,
+            tuning=res["tuning"],
+            roofline=dict(kernel=args.kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=achieved / HBM_PEAK_GBS, kernel_ms=res["kms"], algorithmic_bytes=ab,
+                          per_unit=per_unit))
+        del res
+        torch.cuda.empty_cache()
+    out["bf16_speedup_over_f32"] = out["forms"]["f32"]["ms_per_step"] / out["forms"]["bf16"]["ms_per_step"]
+    del W
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -232,36 +445,19 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus}: runs over several GPUs are not implemented",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import scenegen
-    from paper_2505_19154_amd import _lib as L
-    from paper_2505_19154_amd.raster import FusionAcc, Gaussians, Rasterizer
 
     wl = scenegen.WORKLOADS[args.workload]
     mfma_ok = wl.feat_dtype == "bf16" and (wl.d in (32, 64, 96) or (wl.d > 0 and wl.d % 128 == 0))
     form = args.form if args.form != "auto" else ("bf16" if mfma_ok else "f32")
     print(f"[bench] workload {wl.name}: {wl.description}; form {form}", file=sys.stderr, flush=True)
 
-    g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
-    cams = scenegen.make_cameras(wl.views)
-    tdt = wl.feat_dtype
-    vts = [scenegen.make_view_tensors(i, c.npix, wl.d, with_dT=False, target_dtype=tdt) for i, c in enumerate(cams)]
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
-    feat = (torch.from_numpy(g["feat_bits"].view(np.int16)).to(dev).view(torch.bfloat16) if wl.feat_dtype == "bf16"
-            else t(g["feat"]))
-    dg = Gaussians(t(g["means"]), t(g["scales"]), t(g["quats"]), t(g["opacity"]), t(g["sh"]), feat, wl.sh_degree)
-    cat = lambda k: np.concatenate([v[k] for v in vts])
-    dC, dF, dT = t(cat("dC")), t(cat("dF")), t(cat("dT"))
-    if wl.fusion:
-        target = (torch.from_numpy(cat("target_bits").view(np.int16)).to(dev).view(torch.bfloat16) if tdt == "bf16"
-                  else t(cat("target")))
-    else:
-        target = None
+    W = load_workload(wl, dev)
+    cams = W["cams"]
     print("[bench] inputs resident on the GPU", file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -272,68 +468,15 @@ def main():
         torch.cuda.empty_cache()
         print(f"[bench] calibration copy of {COPY_BYTES} bytes done", file=sys.stderr, flush=True)
 
-    kid = {"project": L.FH_K_PROJECT, "bin": L.FH_K_BIN, "render_fwd": L.FH_K_RENDER_FWD,
-           "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}
-
-    def run_form(form_name: str, kernel: str):
-        """Warm up, then time K steps of one arithmetic form; the chosen kernel is
-        bracketed by HIP events on its own stream."""
-        r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev)
-        img = r.forward(dg, margin=1.02)
-        tuning = r.autotune(dg, img, dC, dF, dT, target=target, reps=2) if args.autotune else None
-        acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
-        grads = r.new_grads()
-
-        def step():
-            r.project(dg)
-            r.bin_sort()
-            r.render_fwd(dg, img)
-            r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc, grads=grads)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        c = r.counters()
-        if c.inst_overflow or c.visit_overflow:
-            raise RuntimeError("capacity overflow during warm-up")
-        print(f"[bench] {form_name}: warm-up done, {c.n_instances} instances, {c.n_visited} visited",
-              file=sys.stderr, flush=True)
-        K = args.steps
-        ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-        ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-        for e in ks + ke:
-            e.record()
-        torch.cuda.synchronize()
-        arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
-        arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
-        L.check(r.lib.fh_set_kernel_events(kid[kernel], arr_s, arr_e, K), "fh_set_kernel_events")
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record()
-        for _ in range(K):
-            step()
-        t1.record()
-        torch.cuda.synchronize()
-        L.check(r.lib.fh_set_kernel_events(kid[kernel], None, None, 0), "fh_set_kernel_events")
-        ms = t0.elapsed_time(t1) / K
-        kms = sum(a.elapsed_time(b) for a, b in zip(ks, ke)) / K
-        c = r.counters()
-        if c.inst_overflow or c.visit_overflow:
-            raise RuntimeError("capacity overflow during the timed steps")
-        blends = int(img.n_iter.to(torch.int64).sum().item())
-        print(f"[bench] {form_name}: {ms:.3f} ms/step, {kernel} {kms:.3f} ms", file=sys.stderr, flush=True)
-        return dict(r=r, img=img, c=c, ms=ms, kms=kms, blends=blends, tuning=tuning or r.tuning_dict())
-
     other = {"bf16": "f32", "f32": "bf16"}[form]
     res_other = None
     if args.compare and (other == "f32" or wl.feat_dtype == "bf16"):
-        res_other = run_form(other, args.kernel)
+        res_other = run_form(W, other, args.kernel, args, dev)
         del res_other["r"], res_other["img"]
         torch.cuda.empty_cache()
-    main_run = run_form(form, args.kernel)
+    main_run = run_form(W, form, args.kernel, args, dev)
     r, img, c, ms, kms, blends = (main_run[k] for k in ("r", "img", "c", "ms", "kms", "blends"))
-    n_vis = int((r.ws_view("depth_key", torch.int32, wl.n * len(cams)) != -1).sum().item())
+    n_vis = visible_count(r, wl, len(cams))
     feat_b = 2 if wl.feat_dtype == "bf16" else 4
     ab, per_unit = alg_bytes(args.kernel, wl, r.n_pixels, n_vis, int(c.n_instances), feat_b, feat_b)
     achieved = ab / (kms * 1e-3) / 1e9
@@ -356,7 +499,8 @@ def main():
             "gaussians": wl.n, "views": len(cams), "resolution": f"{cams[0].width}x{cams[0].height}",
             "d": wl.d, "feat_storage": wl.feat_dtype, "form": form, "fusion": wl.fusion,
             "instances": int(c.n_instances), "visited_instances": int(c.n_visited), "visible_gaussians": n_vis,
-            "blends": blends, "ms_per_view": ms / len(cams), "tuning": main_run["tuning"],
+            "blends": blends, "ms_per_view": ms / len(cams), "ms_per_step_median": main_run["median_ms"],
+            "tuning": main_run["tuning"],
             "other_form": None if res_other is None else {
                 "form": other, "ms_per_step": res_other["ms"], "ms_per_view": res_other["ms"] / len(cams),
                 "blends_per_s": res_other["blends"] / (res_other["ms"] * 1e-3),
@@ -368,11 +512,16 @@ def main():
             "algorithmic_bytes": ab, "per_unit": per_unit,
         },
     }
-    if not args.no_cpu_baseline:
+    del main_run, r, img
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline and W["vts"] is not None:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(g, cams, vts, wl, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(W["g"], cams, W["vts"], wl, args.cpu_seconds)
     else:
         res["cpu_baseline"] = None
+    del W
+    if args.batched:
+        res["batched"] = batched_leg(args, dev)
     print(json.dumps(res), flush=True)
 
 

@@ -64,6 +64,20 @@ typedef enum {
 
 typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
 
+/* Footprint rule of the tile binning (fh_plan.bin_rule).  Both rules give
+ * every tile holding a pixel where alpha = o G can reach 1/255, so no
+ * composited value depends on the rule; only the instance lists (and n_iter,
+ * a list position) do.
+ *   FH_BIN_BOX      half-extents sqrt(11.1 Sigma2_ii) for every Gaussian
+ *                   (11.1 > 2 ln 255)
+ *   FH_BIN_OPACITY  half-extents sqrt(kappa_i Sigma2_ii) with
+ *                   kappa_i = min(11.1, 2 ln(255 o_i) + 1/256): alpha reaches
+ *                   1/255 only where d^T Sigma2^-1 d <= 2 ln(255 o_i);
+ *                   Gaussians with 255 o_i <= 1 get no instances.  ln is a
+ *                   fixed sequence of float32 operations (range reduction
+ *                   to [sqrt(1/2), sqrt 2) and the atanh series to s^9). */
+typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
+
 /* Arithmetic form of the compositing kernels. */
 typedef enum {
     FH_FORM_F32 = 0,        /* FP32 blending; the adjoint and fusion on the FP32 VALU; the forward on MFMA with
@@ -130,6 +144,8 @@ typedef struct {
     int32_t form;                    /* fh_form */
     int32_t rank_bits, tile_bits;    /* key layout of the instance sort */
     int32_t packed_keys;             /* 1: one u32 key (tile << rank_bits | rank); 0: u32 tile + u32 rank */
+    int32_t bin_rule;                /* fh_bin_rule; fh_plan_init sets FH_BIN_BOX, callers may change it */
+    int32_t reserved0;
     int64_t inst_capacity;           /* max (Gaussian, tile) instances over all views */
     int64_t visit_capacity;          /* max instances visited by the backward (per-instance partials) */
     int64_t n_pixels, n_tiles;

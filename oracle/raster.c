@@ -391,3 +391,13 @@ int oracle_num_threads(void) {
     }
     return n;
 }
+
+/* Number of OpenMP threads for later calls (timing on one core or all). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

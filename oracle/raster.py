@@ -60,11 +60,18 @@ def _load():
         _lib.oracle_raster.argtypes = [ctypes.POINTER(_Args)]
         _lib.oracle_raster.restype = ctypes.c_int
         _lib.oracle_num_threads.restype = ctypes.c_int
+        _lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        _lib.oracle_set_num_threads.restype = None
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle_raster calls."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def _ptr(x):

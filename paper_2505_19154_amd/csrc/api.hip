@@ -280,6 +280,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
 
 fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStream_t s) {
     if (!p || !ws || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (p->bin_rule != FH_BIN_BOX && p->bin_rule != FH_BIN_OPACITY) return FH_E_INVALID;
     Counters* c = buf<Counters>(p, ws, WS_COUNTERS);
     hipLaunchKernelGGL(k_reset_all_counters, dim3(1), dim3(64), 0, s, c);
     if (p->n == 0) return launch_status();
@@ -291,6 +292,7 @@ fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStrea
     a.sh = g->sh;
     a.n = (int)p->n;
     a.sh_degree = p->sh_degree;
+    a.bin_rule = p->bin_rule;
     a.rec = buf<float4>(p, ws, WS_REC);
     a.depth_key = buf<uint32_t>(p, ws, WS_DEPTH_KEY);
     a.rect = buf<int4>(p, ws, WS_RECT);

@@ -8,6 +8,7 @@ namespace fh {
 struct ProjectArgs {
     const float *means, *scales, *quats, *opacity, *sh;
     int n, sh_degree;
+    int bin_rule;       // fh_bin_rule
     float4* rec;
     uint32_t* depth_key;
     int4* rect;

@@ -22,10 +22,35 @@ struct BinQ {
     bool binned;
 };
 
+// Natural log of a finite float32 x > 1 by basic float32 operations only, so
+// that the result is reproducible bit for bit: x = m 2^e (exact), m brought
+// into [sqrt(1/2), sqrt 2) (exact halving), then ln m = 2 atanh(s),
+// s = (m - 1)/(m + 1), by the series s (1 + s^2/3 + s^4/5 + s^6/7 + s^8/9)
+// in Horner form (|s| <= 0.1716: the next term is below float32 resolution).
+// The constants are the float32 roundings of the double values.
+__device__ float ln_f32_ops(float x) {
+#pragma clang fp contract(off)
+    const uint32_t bits = __float_as_uint(x);
+    int e = (int)(bits >> 23) - 127;
+    float m = __uint_as_float((bits & 0x7FFFFFu) | 0x3F800000u);
+    if (m > (float)1.4142135) {
+        m = m * 0.5f;
+        e += 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    const float p = ((((float)(1.0 / 9.0) * z + (float)(1.0 / 7.0)) * z + (float)(1.0 / 5.0)) * z +
+                     (float)(1.0 / 3.0)) * z + 1.0f;
+    return (float)e * (float)0.6931472 + (s + s) * p;
+}
+
 // The float32 binning chain.  Every line is one IEEE float32 operation in the
-// written order; contraction into FMA is disabled.
+// written order; contraction into FMA is disabled.  Box factor: 11.1 for every
+// Gaussian (FH_BIN_BOX), or min(11.1, 2 ln(255 o) + 1/256) with no instances
+// where 255 o <= 1 (FH_BIN_OPACITY: alpha = o G reaches 1/255 only where
+// d^T Sigma2^-1 d <= 2 ln(255 o)).
 __device__ BinQ binning_f32(float mx, float my, float mz, float sx, float sy, float sz, float qw, float qx,
-                            float qy, float qz, const fh_camera& c, int tiles_x, int tiles_y) {
+                            float qy, float qz, float op, int rule, const fh_camera& c, int tiles_x, int tiles_y) {
 #pragma clang fp contract(off)
     const float* R = c.R;
     const float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + c.t[0];
@@ -74,8 +99,16 @@ __device__ BinQ binning_f32(float mx, float my, float mz, float sx, float sy, fl
     }
     const float a = ((W0[0] * W0[0] + W0[1] * W0[1]) + W0[2] * W0[2]) + LOWPASS;
     const float cc = ((W1[0] * W1[0] + W1[1] * W1[1]) + W1[2] * W1[2]) + LOWPASS;
-    b.ex = sqrtf(KAPPA * a);
-    b.ey = sqrtf(KAPPA * cc);
+    float kap = KAPPA;
+    bool live = true;
+    if (rule == FH_BIN_OPACITY) {
+        const float x = 255.0f * op;
+        live = x > 1.0f;
+        const float lx = ln_f32_ops(live ? x : 2.0f);
+        kap = live ? fminf((lx + lx) + 0.00390625f, KAPPA) : 0.0f;
+    }
+    b.ex = sqrtf(kap * a);
+    b.ey = sqrtf(kap * cc);
 
     const float ts = (float)TILE;
     const float x0f = floorf((b.u - b.ex) / ts);
@@ -83,7 +116,7 @@ __device__ BinQ binning_f32(float mx, float my, float mz, float sx, float sy, fl
     const float y0f = floorf((b.v - b.ey) / ts);
     const float y1f = floorf((b.v + b.ey) / ts);
     const bool finite = isfinite(b.u) && isfinite(b.v) && isfinite(b.ex) && isfinite(b.ey);
-    const bool ok = visible && finite;
+    const bool ok = visible && finite && live;
     b.x0 = ok ? (int)fmaxf(x0f, 0.0f) : 0;
     b.x1 = ok ? (int)fminf(x1f, (float)(tiles_x - 1)) : -1;
     b.y0 = ok ? (int)fmaxf(y0f, 0.0f) : 0;
@@ -210,10 +243,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, Vie
     const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
     const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
     const float q[4] = {q4.x, q4.y, q4.z, q4.w};
-    const BinQ bq = binning_f32(mu[0], mu[1], mu[2], sc[0], sc[1], sc[2], q[0], q[1], q[2], q[3], cam,
-                                vt.tiles_x[v], vt.tiles_y[v]);
-    const size_t j = (size_t)v * a.n + g;
     const float op = a.opacity[g];
+    const BinQ bq = binning_f32(mu[0], mu[1], mu[2], sc[0], sc[1], sc[2], q[0], q[1], q[2], q[3], op, a.bin_rule,
+                                cam, vt.tiles_x[v], vt.tiles_y[v]);
+    const size_t j = (size_t)v * a.n + g;
     const bool binned = bq.binned;
     float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0;
     if (binned) {

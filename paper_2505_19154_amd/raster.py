@@ -140,13 +140,16 @@ class Rasterizer:
     """Plan + workspace for one batch of cameras and one Gaussian set size."""
 
     def __init__(self, cams, n: int, sh_degree: int, d: int, feat_dtype: str = "f32", form: str = "f32",
-                 device="cuda", inst_capacity: int = 0, visit_capacity: int = 0):
+                 device="cuda", inst_capacity: int = 0, visit_capacity: int = 0, bin_rule: str = "box"):
         self.lib = L.load()
         self.cams = list(cams)
         self.cam_arr = (L.FhCamera * len(self.cams))(*[camera_struct(c) for c in self.cams])
         self.n, self.sh_degree, self.d = int(n), int(sh_degree), int(d)
         self.feat_dtype = L.FH_BF16 if feat_dtype == "bf16" else L.FH_F32
         self.form = L.FH_FORM_BF16 if form == "bf16" else L.FH_FORM_F32
+        if bin_rule not in ("box", "opacity"):
+            raise L.FhError(f"bin_rule must be 'box' or 'opacity', not {bin_rule!r}")
+        self.bin_rule = L.FH_BIN_OPACITY if bin_rule == "opacity" else L.FH_BIN_BOX
         self.device = torch.device(device)
         self.plan = None
         self.ws = None
@@ -164,6 +167,7 @@ class Rasterizer:
                                       self.cam_arr, len(self.cams), int(inst_cap), int(visit_cap)), "fh_plan_init")
         if self.tuning is not None:
             plan.tuning = self.tuning
+        plan.bin_rule = self.bin_rule
         self.plan = plan
         self.ws = torch.empty(max(int(plan.ws_bytes), 256), dtype=torch.uint8, device=self.device)
         self.generation += 1
@@ -344,7 +348,7 @@ class Rasterizer:
         """Autotune cache key: device arch, arithmetic form, feature width and
         dtype, view count, and power-of-two classes of pixels and Gaussians."""
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
-        return (f"{arch}|form{self.form}|d{self.d}|feat{self.feat_dtype}|views{len(self.cams)}|"
+        return (f"{arch}|form{self.form}|d{self.d}|feat{self.feat_dtype}|bin{self.bin_rule}|views{len(self.cams)}|"
                 f"px2^{max(self.n_pixels, 1).bit_length()}|n2^{max(self.n, 1).bit_length()}")
 
     def autotune(self, g: Gaussians, img: Image, dC=None, dF=None, dT=None, target=None, reps: int = 3,

@@ -53,10 +53,11 @@ def concat(vts, key, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(np.concatenate([v[key] for v in vts]), np.float32)).to(device)
 
 
-def run_gpu(g: dict, cams, vts=None, fusion=False, form="f32", margin=1.05):
+def run_gpu(g: dict, cams, vts=None, fusion=False, form="f32", margin=1.05, bin_rule="box"):
     from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
     dg = device_gaussians(g)
-    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=g.get("feat_dtype", "f32"), form=form)
+    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=g.get("feat_dtype", "f32"), form=form,
+                   bin_rule=bin_rule)
     img = r.forward(dg, margin)
     out = dict(r=r, g=dg, img=img)
     if vts is not None:
@@ -75,8 +76,8 @@ def run_gpu(g: dict, cams, vts=None, fusion=False, form="f32", margin=1.05):
     return out
 
 
-def run_oracle(g: dict, cams, vts=None, fusion=False):
-    return pipeline.run(g, cams, vts, fusion=fusion, want_Fmag=True)
+def run_oracle(g: dict, cams, vts=None, fusion=False, bin_rule="box"):
+    return pipeline.run(g, cams, vts, fusion=fusion, want_Fmag=True, bin_rule=bin_rule)
 
 
 def split_views(arr, cams):

@@ -40,10 +40,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "fhgs.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fh_plan), offsetof(fh_plan, cams),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fh_plan), offsetof(fh_plan, cams),
          offsetof(fh_plan, off), offsetof(fh_plan, ws_bytes), sizeof(fh_camera), sizeof(fh_gaussians),
          sizeof(fh_counters), offsetof(fh_plan, tiles_x), offsetof(fh_plan, inst_capacity),
-         offsetof(fh_plan, tuning), sizeof(fh_tuning));
+         offsetof(fh_plan, tuning), sizeof(fh_tuning), offsetof(fh_plan, bin_rule));
   return 0;
 }
 ''')
@@ -54,7 +54,7 @@ int main(void) {
     P = _lib.FhPlan
     want = [ctypes.sizeof(P), P.cams.offset, P.off.offset, P.ws_bytes.offset, ctypes.sizeof(_lib.FhCamera),
             ctypes.sizeof(_lib.FhGaussians), ctypes.sizeof(_lib.FhCounters), P.tiles_x.offset,
-            P.inst_capacity.offset, P.tuning.offset, ctypes.sizeof(_lib.FhTuning)]
+            P.inst_capacity.offset, P.tuning.offset, ctypes.sizeof(_lib.FhTuning), P.bin_rule.offset]
     assert got == want
 
 
@@ -68,7 +68,7 @@ def test_plan_init_validates_on_host():
     plan = _lib.FhPlan()
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 0, cams, 1, 5000, 1000) == 0
     assert plan.n_tiles == 4 * 3 and plan.n_pixels == 64 * 48 and plan.packed_keys == 1
-    assert plan.ws_bytes > 0
+    assert plan.ws_bytes > 0 and plan.bin_rule == _lib.FH_BIN_BOX
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 4, 16, 0, 0, cams, 1, 0, 0) == -2   # sh degree 4
 
 

@@ -5,6 +5,10 @@ oracle computes one by one:
 * 1M Gaussians, SH3, D=128 BF16, 16 views of 640x480 .. 1600x1200 (sphere, r=5);
 * 3M Gaussians, SH3, D=512 BF16, 8 views at 1920x1080.
 
+The 16-view workload's step is also captured in one HIP graph and replayed:
+every replay must reproduce the eager step bit for bit, so the checks above
+hold for the graph-replayed form that the benchmark times.
+
 Binning: the instance count and every tile range of every view, bit for bit
 (per-tile counts from the oracle's float32 rects), and the full sorted key and
 Gaussian lists of every sampled tile.  Forward: every pixel of the sampled
@@ -94,7 +98,7 @@ def run(request):
 
     ora = S.run(g, cams, bqs, cand, views, rows, wl.d, log=lambda m: print(f"{tag} {m}", flush=True))
     return dict(wl=wl, form=form, cams=cams, r=r, img=img, grads=grads, acc=acc, c=c, bqs=bqs, counts=counts,
-                ranges=ranges, views=views, cand=cand, **ora)
+                ranges=ranges, views=views, cand=cand, dg=dg, maps=maps, **ora)
 
 
 def test_binning_counts_and_ranges(run):
@@ -153,3 +157,51 @@ def test_gradients_and_fusion_of_sample(run):
     mw, _ = U.elementwise(w, run["wsum"][idx], run["wsum"][idx], rtol=rt["fuse"], amb=run["wsum_amb"][idx])
     print(f"[batched] fusion ratio max {mx:.3f}, wsum {mw:.3f}", flush=True)
     assert mx <= 1.0 and mw <= 1.0
+
+
+def _digest(t: torch.Tensor, rows: int = 1 << 20) -> tuple:
+    """Two position-weighted sums of a tensor's 32-bit words (chunked), so that
+    replays can be compared with the eager step without a second copy."""
+    w = t.reshape(-1).view(torch.int32)
+    s1 = s2 = 0
+    for off in range(0, w.numel(), rows * 64):
+        c = w[off:off + rows * 64].to(torch.int64)
+        pos = torch.arange(off, off + c.numel(), device=c.device, dtype=torch.int64) % 65521 + 1
+        s1 += int(c.sum().item())
+        s2 += int((c * pos).sum().item())
+    return s1, s2
+
+
+def test_graph_replay_equals_eager(run):
+    """The whole step (project, bin_sort, render_fwd, render_bwd with fusion)
+    captured in one HIP graph and replayed three times, with eager work and
+    host synchronisation between replays: outputs, gradients and fusion sums
+    equal the eager step's bit for bit (runs last: it overwrites the fixture's
+    outputs with identical values)."""
+    from paper_2505_19154_amd.raster import FusionAcc
+    if run["wl"].name != "c4":
+        pytest.skip("graph replay is checked on the 16-view workload")
+    r, img, dg, maps = run["r"], run["img"], run["dg"], run["maps"]
+    ref = {k: _digest(getattr(img, k)) for k in ("C", "F", "T", "n_iter")}
+    ref.update({"g_" + k: _digest(v) for k, v in run["grads"].items()})
+    ref["acc_sum"] = _digest(run["acc"].sum + run["acc"].comp)
+    ref["acc_w"] = _digest(run["acc"].wsum + run["acc"].wcomp)
+    acc = FusionAcc.zeros(dg.n, dg.d, "cuda")
+    graph, grads = r.capture_step(dg, img, maps["dC"], maps["dF"], maps["dT"], target=maps["target"], acc=acc)
+    for rep in range(3):
+        for t_ in (img.C, img.F, img.T, acc.sum, acc.comp, acc.wsum, acc.wcomp):
+            t_.zero_()
+        for t_ in grads.values():
+            t_.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        c = r.counters()
+        assert not c.inst_overflow and not c.visit_overflow
+        got = {k: _digest(getattr(img, k)) for k in ("C", "F", "T", "n_iter")}
+        got.update({"g_" + k: _digest(v) for k, v in grads.items()})
+        got["acc_sum"] = _digest(acc.sum + acc.comp)
+        got["acc_w"] = _digest(acc.wsum + acc.wcomp)
+        assert got == ref, (rep, [k for k in ref if got[k] != ref[k]])
+        _ = (maps["dC"][:1000] * 2).sum().item()    # unrelated eager work between replays
+    print(f"[batched] graph replay x3 equals the eager step", flush=True)

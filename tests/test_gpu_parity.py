@@ -23,6 +23,15 @@ SCENES = {
     "multiview": (1500, 1.2, 1, 8, "f32", "three", "f32"),
     "mfma_d32": (2500, 1.5, 3, 32, "bf16", "front120x90", "bf16"),
     "mfma_d128_multiview": (1500, 1.2, 1, 128, "bf16", "three", "bf16"),
+    # the other BF16-form widths: 64 and 96 (16-row forward, one slice), 256
+    # (8-row forward, one 256-channel slice; the adjoint's widest dF tile)
+    "mfma_d64": (2000, 1.5, 3, 64, "bf16", "front100x70", "bf16"),
+    "mfma_d96": (2000, 1.5, 2, 96, "bf16", "front90x60", "bf16"),
+    "mfma_d256": (1200, 1.5, 3, 256, "bf16", "front96x80", "bf16"),
+    # FP32 form with FP32 features at d = 128 and 256: the MFMA forward with
+    # three-term splits in its 8-row shapes (128- and 256-channel slices)
+    "fsplit_d128": (1500, 1.5, 1, 128, "f32", "front100x70", "f32"),
+    "fsplit_d256": (1200, 1.5, 1, 256, "f32", "front96x80", "f32"),
     # splats of 1-2 tiles: some 2048-instance duplication ranges span more
     # than 1024 ranks (up to 1260) and take the per-instance rank search
     "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
@@ -166,3 +175,30 @@ def test_deterministic_rerun(case):
         assert torch.equal(a["grads"][k], b["grads"][k]), k
     if a["acc"] is not None:
         assert torch.equal(a["acc"].sum, b["acc"].sum)
+
+
+def test_c1_takes_every_decision_as_the_oracle_does(monkeypatch):
+    """The 1k-Gaussian 128x128 workload has no decision within 2e-5 relative of
+    its threshold (well beyond FP32's decision error of ~1e-5 at the longest
+    walks here), so the GPU must agree with the oracle on every pixel and every
+    Gaussian with no pixel masked and no ambiguity allowance: n_iter exactly,
+    C, T, F, gradients and fusion sums under the FP32 rule."""
+    from oracle import consts as oconsts
+    monkeypatch.setattr(oconsts, "AMBIG_REL", 2e-5)
+    g, cams = _scene("c1")
+    vts = U.view_maps(cams, g["d"], with_dT=True)
+    ora = U.run_oracle(g, cams, vts, fusion=True)
+    v = ora["views"][0]
+    assert np.all(v["flags"] == 0) and np.all(ora["gflags"] == 0)
+    gpu = U.run_gpu(g, cams, vts, fusion=True)
+    img = gpu["img"]
+    assert np.array_equal(img.n_iter.cpu().numpy().astype(np.int64), v["niter"])
+    assert U.elementwise(img.C.cpu().numpy(), v["C"], v["Cmag"])[0] <= 1.0
+    assert U.elementwise(img.T.cpu().numpy(), v["T"], v["T"])[0] <= 1.0
+    assert U.elementwise(img.F.cpu().numpy(), v["F"], v["Fmag"])[0] <= 1.0
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        assert U.elementwise(gpu["grads"][k].cpu().numpy(), ora["grads"][k], ora["grads_mag"][k])[0] <= 1.0, k
+    s = (gpu["acc"].sum + gpu["acc"].comp).cpu().numpy()
+    w = (gpu["acc"].wsum + gpu["acc"].wcomp).cpu().numpy()
+    assert U.elementwise(s, ora["fsum"], ora["fsum_mag"])[0] <= 1.0
+    assert U.elementwise(w, ora["wsum"], ora["wsum"])[0] <= 1.0
