@@ -37,9 +37,11 @@ def _rot(qn: torch.Tensor) -> torch.Tensor:
     ], 1)
 
 
-def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
+def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None, keep_w: list | None = None):
     """params: float64 torch leaves means [N,3], scales [N,3], quats [N,4],
-    opacity [N], sh [N,B,3].  Returns C [P,3], F [P,D] or None, T [P], niter [P]."""
+    opacity [N], sh [N,B,3].  Returns C [P,3], F [P,D] or None, T [P], niter [P]
+    and the depth order.  keep_w, if a list, receives the weight map w [P] of
+    every position of the order (zero where the Gaussian did not blend)."""
     bq = binspec.bin_quantities(g_meta, cam)
     vis = np.nonzero(bq["visible"])[0]
     order = vis[np.lexsort((vis, bq["depth"][vis]))]
@@ -93,6 +95,8 @@ def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
         done = done | stop
         contrib = ok & ~stop
         w = torch.where(contrib, alpha * T, torch.zeros_like(T))
+        if keep_w is not None:
+            keep_w.append(w)
         col = col + w[:, None] * rgb[gi][None, :]
         if F is not None:
             F = F + w[:, None] * featt[gi][None, :]
@@ -104,3 +108,34 @@ def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
 def leaves(g: dict) -> dict:
     return {k: torch.tensor(np.asarray(g[k], np.float64), requires_grad=True)
             for k in ("means", "scales", "quats", "opacity", "sh")}
+
+
+def unit_rows(x: np.ndarray) -> np.ndarray:
+    """Rows scaled to unit length (a zero row stays zero)."""
+    x = np.asarray(x, np.float64)
+    n = np.sqrt((x * x).sum(1, keepdims=True))
+    return np.where(n > 0, x / np.where(n > 0, n, 1.0), 0.0)
+
+
+def ndfd_losses(params: dict, g_meta: dict, cam, feat: np.ndarray, gt: np.ndarray, lam: float, k: float):
+    """The NDFD losses of every pixel by their definitions (Section 3.3,
+    Appendix A.1), without the O(N) rearrangement: with unit features and
+    sigma_i = 1 / (1 + exp(k (cos(f_i, F_gt) - lambda))),
+        L_gt = sum_i w_i sigma_i,
+        L_cf = sum_i sum_{j<i} sigma_i w_i w_j (1 - cos(f_i, f_j))   (the double sum).
+    Returns (L_gt [P], L_cf [P]) as differentiable float64 tensors."""
+    ws = []
+    _, _, _, _, order = render(params, g_meta, cam, None, keep_w=ws)
+    if not ws:
+        P = int(cam.width) * int(cam.height)
+        z = torch.zeros(P, dtype=torch.float64)
+        return z, z
+    Wm = torch.stack(ws, 0)                                   # [positions, P]
+    fh = torch.tensor(unit_rows(np.asarray(feat, np.float64)[order]))
+    gh = torch.tensor(unit_rows(gt))
+    sig = 1.0 / (1.0 + torch.exp(k * (fh @ gh.T - lam)))     # [positions, P], constant
+    Lgt = (Wm * sig).sum(0)
+    pair = 1.0 - fh @ fh.T                                    # [positions, positions]
+    lower = torch.tril(pair, diagonal=-1)                     # j < i
+    Lcf = (sig * Wm * (lower @ Wm)).sum(0)
+    return Lgt, Lcf

@@ -20,12 +20,15 @@ def view_slice(bins: dict, vi: int, cam) -> np.ndarray:
 
 def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = False,
         tile_sel: list | None = None, want_F: bool = True, want_dfeat: bool = False,
-        want_Fmag: bool = False, magnitudes: bool = True, bin_rule: str = "box") -> dict:
+        want_Fmag: bool = False, magnitudes: bool = True, bin_rule: str = "box", ndfd: dict | None = None) -> dict:
     """Forward (and adjoint when view_tensors is given) for every camera.
 
     view_tensors[v] holds dC [P,3], dF [P,D], dT [P] and, for fusion, target [P,D].
     tile_sel[v] optionally restricts the traversal to some of view v's tiles.
     bin_rule: "box" (one KAPPA) or "opacity" (per-Gaussian kappa_i, binspec).
+    ndfd: dict(lam, k) switches on the NDFD feature branch (Section 3.3); each
+    view's tensors then hold "gt" [P, D] and, for its gradient, "ndfd_a" and
+    "ndfd_b" [P] (dL/dL_gt, dL/dL_cf per pixel; dC, dF, dT may be zero maps).
     gflags: bit 0 the Gaussian decides a near-threshold skip/stop decision,
     bit 2 its colour clamp is near-threshold; grads_amb / fsum_amb / wsum_amb
     bound what near-threshold decisions of other Gaussians could change.
@@ -49,13 +52,18 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
             dT=None if vt is None else vt["dT"],
             target=None if (vt is None or not fusion) else vt["target"],
             tile_sel=None if tile_sel is None else tile_sel[vi], want_F=want_F,
-            want_Fmag=want_Fmag, want_fusion=fusion, want_dfeat=want_dfeat)
+            want_Fmag=want_Fmag, want_fusion=fusion, want_dfeat=want_dfeat,
+            ndfd=None if (ndfd is None or vt is None) else dict(
+                gt=vt["gt"], lam=ndfd["lam"], k=ndfd["k"], a=vt.get("ndfd_a"), b=vt.get("ndfd_b")))
         counts += out["counts"]
         gflags |= out["gflags"]
         # bit 2: the colour clamp of a Gaussian that this view binned is ambiguous
         gflags |= np.where(pr["clamp_amb"] & bins["per_view"][vi]["binned"], 4, 0).astype(np.int32)
         rec = dict(C=out["C"], Cmag=out["Cmag"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
                    flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"])
+        for key in ("Lgt", "Lcf", "Lcf_mag", "FN", "WN"):
+            if key in out:
+                rec[key] = out[key]
         if vt is not None:
             up = _unpack(out["g2d"])
             gv = project.project_bwd(pr, up)

@@ -25,6 +25,22 @@
  * Fusion (w-weighted transpose of feature rendering): fsum_g += w_g(p) t(p),
  * wsum_g += w_g(p).
  *
+ * NDFD feature branch (Section 3.3, Appendix A.1-A.2; optional): along the
+ * same walk, with unit features fh_i = f_i / |f_i| and fh_gt = F_gt / |F_gt|
+ * (a zero vector's unit vector is taken as zero),
+ *     sigma_i = 1 / (1 + exp(k (phi_i - lambda))),  phi_i = fh_i . fh_gt,
+ *     L_gt = sum_i w_i sigma_i,
+ *     L_cf = sum_i sigma_i w_i (W_{i-1} - F_{i-1} . fh_i),
+ *            W_{i-1} = sum_{j<i} w_j,  F_{i-1} = sum_{j<i} w_j fh_j,
+ * and, for the loss a L_gt + b L_cf of the pixel (a, b per pixel), the
+ * derivative with respect to w_k in its forward-indexed form
+ *     h_k = a sigma_k + b (sigma_k (W_{k-1} - F_{k-1} . fh_k)
+ *                          + sum_{i>k} sigma_i w_i (1 - fh_i . fh_k)),
+ * which joins g_k in the adjoint above.  sigma is a constant of the frozen
+ * features, so gradients flow through w only.  Magnitude companions use
+ * |fh_i . fh_j| <= 1.  The near-threshold bound (*_amb) does not cover these
+ * terms: scenes checked with them have no near-threshold decision.
+ *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
  * absolute values of the same terms) are accumulated alongside.
  *
@@ -94,7 +110,23 @@ typedef struct {
     int32_t *gflags;                 /* [N] or NULL: bit0 decides a near-threshold skip/stop decision
                                         (informational: bounded through the *_amb companions) */
     int64_t *counts;                 /* [3]: sum n_iter, contributing blends, alpha evaluations */
+    /* NDFD feature branch (NULL ndfd_gt: off) */
+    const double *ndfd_gt;           /* [P, d] ground-truth feature map F_gt */
+    const double *feat_inv_norm;     /* [N] 1 / |f_g| (0 for a zero feature) */
+    double ndfd_lambda, ndfd_k;      /* sigmoid threshold and slope */
+    const double *ndfd_a;            /* [P] dL/dL_gt (NULL: 0) */
+    const double *ndfd_b;            /* [P] dL/dL_cf (NULL: 0) */
+    double *out_Lgt, *out_Lcf;       /* [P] */
+    double *out_Lcf_mag;             /* [P] or NULL */
+    double *out_FN;                  /* [P, d] or NULL: sum_i w_i fh_i */
+    double *out_WN;                  /* [P] or NULL: sum_i w_i */
 } oracle_args;
+
+/* per-thread scratch of the NDFD branch */
+typedef struct {
+    double *sig, *h, *hm, *cterm, *cmag;   /* [maxlen] per contributor */
+    double *vec;                           /* [2 d] */
+} ndfd_scratch;
 
 typedef struct {
     int64_t g, pos;
@@ -123,8 +155,64 @@ static double rgbm(const oracle_args *a, int64_t g, int c) {
     return a->rgb_mag ? a->rgb_mag[3 * g + c] : fabs(a->rgb[3 * g + c]);
 }
 
+/* unit feature component fh_g[c] */
+static double fhat(const oracle_args *a, int64_t g, int64_t c) { return a->feat[g * a->d + c] * a->feat_inv_norm[g]; }
+
+/* NDFD of one pixel over its contributing blends recs[0..nrec): the losses
+   (and F_N, W_N), and when a or b is given, h_k for every blend. */
+static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs, int64_t nrec, ndfd_scratch *sc) {
+    const int64_t d = a->d;
+    const double *gt = a->ndfd_gt + pix * d;
+    double gn = 0.0;
+    for (int64_t c = 0; c < d; ++c) gn += gt[c] * gt[c];
+    gn = sqrt(gn);
+    const double ig = gn > 0.0 ? 1.0 / gn : 0.0;
+    double *P = sc->vec, *B = sc->vec + d;
+    memset(P, 0, sizeof(double) * d);
+    double W = 0.0, Lgt = 0.0, Lcf = 0.0, Lcfm = 0.0;
+    for (int64_t i = 0; i < nrec; ++i) {
+        const int64_t g = recs[i].g;
+        const double w = recs[i].alpha * recs[i].T;
+        double phi = 0.0, pf = 0.0;
+        for (int64_t c = 0; c < d; ++c) {
+            phi += fhat(a, g, c) * gt[c];
+            pf += P[c] * fhat(a, g, c);
+        }
+        phi *= ig;
+        const double sg = 1.0 / (1.0 + exp(a->ndfd_k * (phi - a->ndfd_lambda)));
+        sc->sig[i] = sg;
+        sc->cterm[i] = sg * (W - pf);
+        sc->cmag[i] = sg * 2.0 * W;
+        Lgt += w * sg;
+        Lcf += sg * w * (W - pf);
+        Lcfm += sg * w * 2.0 * W;
+        for (int64_t c = 0; c < d; ++c) P[c] += w * fhat(a, g, c);
+        W += w;
+    }
+    a->out_Lgt[pix] = Lgt;
+    a->out_Lcf[pix] = Lcf;
+    if (a->out_Lcf_mag) a->out_Lcf_mag[pix] = Lcfm;
+    if (a->out_FN) memcpy(a->out_FN + pix * d, P, sizeof(double) * d);
+    if (a->out_WN) a->out_WN[pix] = W;
+    if (!a->ndfd_a && !a->ndfd_b) return;
+    const double ca = a->ndfd_a ? a->ndfd_a[pix] : 0.0, cb = a->ndfd_b ? a->ndfd_b[pix] : 0.0;
+    /* sum_{i>k} sigma_i w_i and sum_{i>k} sigma_i w_i fh_i, back to front */
+    double A = 0.0;
+    memset(B, 0, sizeof(double) * d);
+    for (int64_t k = nrec - 1; k >= 0; --k) {
+        const int64_t g = recs[k].g;
+        const double w = recs[k].alpha * recs[k].T;
+        double bf = 0.0;
+        for (int64_t c = 0; c < d; ++c) bf += B[c] * fhat(a, g, c);
+        sc->h[k] = ca * sc->sig[k] + cb * (sc->cterm[k] + (A - bf));
+        sc->hm[k] = fabs(ca) * sc->sig[k] + fabs(cb) * (sc->cmag[k] + 2.0 * A);
+        A += sc->sig[k] * w;
+        for (int64_t c = 0; c < d; ++c) B[c] += sc->sig[k] * w * fhat(a, g, c);
+    }
+}
+
 static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec *amb, double *gvec,
-                    double *gmag) {
+                    double *gmag, ndfd_scratch *sc) {
     const int64_t ty = tile / a->tiles_x, tx = tile % a->tiles_x;
     const int64_t start = a->ranges[2 * tile], end = a->ranges[2 * tile + 1];
     const int64_t d = a->d;
@@ -198,6 +286,8 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     a->gflags[amb[i].g] |= 1;
                 }
             }
+            const int ndfd_grad = a->ndfd_gt && (a->ndfd_a || a->ndfd_b);
+            if (a->ndfd_gt) ndfd_pixel(a, pix, recs, nrec, sc);
             if (!a->dC) continue;
             /* ---- adjoint, back to front over the contributing blends ---- */
             const double *dC = a->dC + 3 * pix;
@@ -237,6 +327,10 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                         gk += a->feat[g * d + k] * dF[k];
                         gkm += fabs(a->feat[g * d + k] * dF[k]);
                     }
+                if (ndfd_grad) {
+                    gk += sc->h[i];
+                    gkm += sc->hm[i];
+                }
                 const double inv1ma = 1.0 / (1.0 - r->alpha);
                 const double dalpha = r->T * gk - (S + Tfin * dT) * inv1ma;
                 const double dalpham = r->T * gkm + (Sm + Tfin * fabs(dT)) * inv1ma;
@@ -363,16 +457,21 @@ int oracle_raster(const oracle_args *a) {
     {
         blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
         amb_rec *amb = (amb_rec *)malloc(sizeof(amb_rec) * (size_t)(2 * maxlen + 2));
+        double *nd = (double *)malloc(sizeof(double) * (size_t)(5 * (maxlen + 1) + 2 * (a->d + 1)));
+        ndfd_scratch sc = {nd, nd + (maxlen + 1), nd + 2 * (maxlen + 1), nd + 3 * (maxlen + 1),
+                           nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1)};
         double gvec[9], gmag[9];
-        if (!recs || !amb) {
+        if (!recs || !amb || !nd) {
 #pragma omp atomic write
             err = 1;
         } else {
 #pragma omp for schedule(dynamic, 1)
-            for (int64_t i = 0; i < nsel; ++i) do_tile(a, a->tile_sel ? a->tile_sel[i] : i, recs, amb, gvec, gmag);
+            for (int64_t i = 0; i < nsel; ++i)
+                do_tile(a, a->tile_sel ? a->tile_sel[i] : i, recs, amb, gvec, gmag, &sc);
         }
         free(recs);
         free(amb);
+        free(nd);
     }
     return err;
 }

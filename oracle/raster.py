@@ -47,6 +47,9 @@ class _Args(ctypes.Structure):
         ("out_flags", _P),
         ("g2d", _P), ("g2d_mag", _P), ("fsum", _P), ("fsum_mag", _P), ("wsum", _P),
         ("dfeat", _P), ("g2d_amb", _P), ("fsum_amb", _P), ("wsum_amb", _P), ("gflags", _P), ("counts", _P),
+        ("ndfd_gt", _P), ("feat_inv_norm", _P), ("ndfd_lambda", ctypes.c_double), ("ndfd_k", ctypes.c_double),
+        ("ndfd_a", _P), ("ndfd_b", _P), ("out_Lgt", _P), ("out_Lcf", _P), ("out_Lcf_mag", _P), ("out_FN", _P),
+        ("out_WN", _P),
     ]
 
 
@@ -83,13 +86,19 @@ def _f64(x):
 
 
 def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, target=None,
-                tile_sel=None, want_F=True, want_Fmag=False, want_fusion=True, want_dfeat=False):
+                tile_sel=None, want_F=True, want_Fmag=False, want_fusion=True, want_dfeat=False,
+                ndfd=None):
     """Composite one view (and its adjoint when dC is given).
 
     ranges [tiles, 2] and glist [M] are this view's slice of the binning (tile
     indices local to the view).  proj holds FP64 per-Gaussian u, v, A, B, C,
     opacity and rgb [N, 3] (and rgb_mag [N, 3], the magnitude companion of rgb,
     when present).  Returns a dict of per-pixel and per-Gaussian arrays.
+
+    ndfd (optional): dict(gt=[P, d] ground-truth feature map, lam, k, and
+    a, b = [P] upstream weights of L_gt and L_cf, or None); adds L_gt, L_cf,
+    Lcf_mag, FN [P, d] and WN to the result and the NDFD terms h_k to the
+    adjoint's g_k (with dC given; pass zero maps for the NDFD gradient alone).
     """
     lib = _load()
     W, H = int(cam.width), int(cam.height)
@@ -130,6 +139,17 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     out["wsum_amb"] = np.zeros(n) if (bwd and target is not None) else None
     out["dfeat"] = np.zeros((n, d)) if (bwd and want_dfeat and d) else None
     out["gflags"] = np.zeros(n, np.int32)
+    nd = {}
+    if ndfd is not None:
+        f64 = np.asarray(feat, np.float64)
+        nrm = np.sqrt((f64 * f64).sum(1))
+        nd["inv"] = k("inv", np.where(nrm > 0, 1.0 / np.where(nrm > 0, nrm, 1.0), 0.0))
+        nd["gt"] = k("gt", _f64(ndfd["gt"]))
+        nd["a"] = k("na", _f64(ndfd.get("a")))
+        nd["b"] = k("nb", _f64(ndfd.get("b")))
+        for key, shape in (("Lgt", P), ("Lcf", P), ("Lcf_mag", P), ("WN", P)):
+            out[key] = np.zeros(shape)
+        out["FN"] = np.zeros((P, d))
 
     args = _Args(
         width=W, height=H, tile=consts.TILE, tiles_x=TX, tiles_y=TY, d=d,
@@ -145,6 +165,11 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         fsum_mag=_ptr(out["fsum_mag"]), wsum=_ptr(out["wsum"]), dfeat=_ptr(out["dfeat"]),
         g2d_amb=_ptr(out["g2d_amb"]), fsum_amb=_ptr(out["fsum_amb"]), wsum_amb=_ptr(out["wsum_amb"]),
         gflags=_ptr(out["gflags"]), counts=_ptr(out["counts"]),
+        ndfd_gt=_ptr(nd.get("gt")), feat_inv_norm=_ptr(nd.get("inv")),
+        ndfd_lambda=float(ndfd["lam"]) if ndfd else 0.0, ndfd_k=float(ndfd["k"]) if ndfd else 0.0,
+        ndfd_a=_ptr(nd.get("a")), ndfd_b=_ptr(nd.get("b")), out_Lgt=_ptr(out.get("Lgt")),
+        out_Lcf=_ptr(out.get("Lcf")), out_Lcf_mag=_ptr(out.get("Lcf_mag")), out_FN=_ptr(out.get("FN")),
+        out_WN=_ptr(out.get("WN")),
     )
     rc = lib.oracle_raster(ctypes.byref(args))
     if rc != 0:
