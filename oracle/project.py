@@ -108,12 +108,14 @@ def project(g: dict, cam) -> dict:
     rgb = np.maximum(raw, 0.0)
     # magnitude companion of the colour sum, and the Gaussians whose clamp
     # decision (raw > 0) sits within rounding reach of its threshold
-    rgb_mag = np.einsum("nb,nbc->nc", np.abs(Y), np.abs(shc)) + 0.5
+    # (Y_b is itself a sum of monomials: its companion sums their magnitudes)
+    Ymag = sh.eval_sh(degree, dirn, magnitude=True)
+    rgb_mag = np.einsum("nb,nbc->nc", Ymag, np.abs(shc)) + 0.5
     clamp_amb = (np.abs(raw) <= consts.AMBIG_REL * rgb_mag).any(axis=1)
 
     return dict(p=p, u=u, v=v, depth=pz, qn=qn, qnorm=qnorm, Rq=Rq, M=M, Sigma3=Sigma3,
                 J=J, T=T, a=a, b=b, c=c, det=det, A=A, B=B, C=C, opacity=op,
-                dirn=dirn, dlen=dlen, Y=Y, raw=raw, rgb=rgb, rgb_mag=rgb_mag, clamp_amb=clamp_amb,
+                dirn=dirn, dlen=dlen, Y=Y, Ymag=Ymag, raw=raw, rgb=rgb, rgb_mag=rgb_mag, clamp_amb=clamp_amb,
                 scales=s, Rc=Rc,
                 fx=fx, fy=fy, sh=shc, degree=degree)
 
@@ -183,7 +185,7 @@ def project_bwd(pr: dict, up: dict, magnitude: bool = False) -> dict:
     mask = (pr["raw"] > 0.0).astype(np.float64)
     up_raw = up["rgb"] * mask
     Y = pr["Y"]
-    up_sh = F(Y)[:, :, None] * up_raw[:, None, :]
+    up_sh = (pr["Ymag"] if magnitude else Y)[:, :, None] * up_raw[:, None, :]
     dY = sh.eval_sh_grad(pr["degree"], pr["dirn"])         # [N,B,3]
     up_dir = np.einsum("nbk,nbc,nc->nk", F(dY), F(pr["sh"]), up_raw)
     dirn, dlen = pr["dirn"], pr["dlen"]

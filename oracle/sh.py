@@ -73,15 +73,24 @@ def num_bases(degree: int) -> int:
     return (degree + 1) ** 2
 
 
-def eval_sh(degree: int, dirs: np.ndarray) -> np.ndarray:
-    """Y_b(d) for unit directions d [..., 3] -> [..., (degree+1)^2] (FP64)."""
+def eval_sh(degree: int, dirs: np.ndarray, magnitude: bool = False) -> np.ndarray:
+    """Y_b(d) for unit directions d [..., 3] -> [..., (degree+1)^2] (FP64).
+
+    magnitude=True: the magnitude companion of each Y_b instead, the sum of the
+    absolute values of its polynomial's terms, sum |c| |x|^i |y|^j |z|^k.  Y_b
+    is itself a sum of terms that cancel near its nodal lines, so a rounding
+    error of a few ulp of those terms is what any evaluation carries there,
+    however small Y_b itself is.
+    """
     d = np.asarray(dirs, dtype=np.float64)
+    if magnitude:
+        d = np.abs(d)
     x, y, z = d[..., 0], d[..., 1], d[..., 2]
     out = np.zeros(d.shape[:-1] + (num_bases(degree),))
     for b in range(num_bases(degree)):
         acc = np.zeros(d.shape[:-1])
         for (i, j, k), c in _POLYS[b].items():
-            acc = acc + c * x ** i * y ** j * z ** k
+            acc = acc + (abs(c) if magnitude else c) * x ** i * y ** j * z ** k
         out[..., b] = acc
     return out
 

@@ -63,3 +63,29 @@ def test_gradient_tangential_fd():
         e[k] = 1.0
         fd = (sh.eval_sh(3, d + h * e) - sh.eval_sh(3, d - h * e)) / (2 * h)
         assert np.allclose(G[:, :, k], fd, atol=1e-8)
+
+
+def test_magnitude_companion_bounds_the_value_and_float32_rounding():
+    # the companion sums |term| of each Y_b's polynomial: it is >= |Y_b|, equal
+    # to it for l <= 1 (one monomial each), and a
+    # float32 evaluation of the same polynomial stays within a few ulp of it
+    # even on nodal lines, where |Y_b| itself gives no scale
+    d = _dirs(4000, 7)
+    Y = sh.eval_sh(3, d)
+    M = sh.eval_sh(3, d, magnitude=True)
+    assert np.all(M >= np.abs(Y) * (1 - 1e-15))
+    assert np.allclose(M[:, :4], np.abs(Y[:, :4]), rtol=1e-15, atol=0)
+    # float32 evaluation: every product and sum rounded to float32
+    d32 = d.astype(np.float32)
+    x, y, z = d32[:, 0], d32[:, 1], d32[:, 2]
+    err_rel_M, err_rel_Y = 0.0, 0.0
+    for b in range(16):
+        acc = np.zeros(d.shape[0], np.float32)
+        for (i, j, k), c in sh._POLYS[b].items():
+            acc = (acc + np.float32(c) * x ** i * y ** j * z ** k).astype(np.float32)
+        e = np.abs(acc.astype(np.float64) - Y[:, b])
+        err_rel_M = max(err_rel_M, float((e / M[:, b]).max()))
+        err_rel_Y = max(err_rel_Y, float((e / np.abs(Y[:, b])).max()))
+    assert err_rel_M < 2e-6
+    # (near nodal lines the error relative to |Y_b| is far larger)
+    assert err_rel_Y > 1e-4
