@@ -10,7 +10,10 @@ Tolerance rule (FP32 path vs FP64 oracle), per output x with reference r:
     1e-4 along the pixel's walk); for per-Gaussian sums, on Gaussians that
     decide no ambiguous decision, with AMB_FACTOR times the oracle's bound of
     what the ambiguous decisions could change added to the bound;
-  * normwise     ||x - r||_2 <= rtol * ||r||_2 over everything.
+  * normwise     ||x - r||_2 <= rtol * ||r||_2 over everything on the small
+    scenes; over the elements free of near-threshold decisions at full frame,
+    where flipped stop decisions (T changes by up to its whole value) are
+    bound to occur, with the all-element value reported beside it.
 """
 from __future__ import annotations
 
