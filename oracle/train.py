@@ -14,10 +14,15 @@ Adam (Kingma and Ba, 2015), per parameter element with gradient g at step t:
 Gradients of the raw parameters from those of the activated ones:
     dL/d log s = s dL/ds,   dL/d logit = o (1 - o) dL/do.
 
+Photometric loss (Algorithm 1, Photometric Loss; the paper leaves the function
+open): the mean squared error over pixels and channels,
+    L = sum (C - C_target)^2 / (3 P),   dL/dC = 2 (C - C_target) / (3 P).
+
 Densification (the adaptive density control the paper inherits; Algorithm 1,
 Densification): per Gaussian, over the views of the iterations since the
 last refinement, the norm of its screen-space mean gradient |dL/d(u, v)| is
-summed over the views that visited it, and the visits counted.  At a
+summed over the views that binned it (at least one tile instance, the
+visibility rule of 3DGS), and those views counted.  At a
 refinement, with avg = sum / count:
     avg >= grad_thr and max log-scale <= log_scale_thr  ->  clone (a copy is
         appended);
@@ -53,6 +58,26 @@ def raw_grads(raw: dict, grads: dict) -> dict:
     o = act["opacity"]
     return dict(means=grads["means"], log_scales=grads["scales"] * act["scales"], quats=grads["quats"],
                 logit_opacity=grads["opacity"] * o * (1.0 - o), sh=grads["sh"])
+
+
+def photometric_loss(C: np.ndarray, C_target: np.ndarray):
+    """(L, dL/dC) of the mean squared error, in FP64."""
+    e = np.asarray(C, np.float64) - np.asarray(C_target, np.float64)
+    return float((e * e).sum() / e.size), 2.0 * e / e.size
+
+
+def densify_stats(g2d_views: list, binned_views: list):
+    """(grad_sum, count) over views: g2d_views[v] [N, >= 2] holds each
+    Gaussian's dL/du, dL/dv in view v, binned_views[v] [N] whether view v binned
+    it; the norms are summed in FP64."""
+    gs = np.zeros(np.asarray(g2d_views[0]).shape[0])
+    cnt = np.zeros(gs.shape[0], np.int64)
+    for g2d, b in zip(g2d_views, binned_views):
+        g2d = np.asarray(g2d, np.float64)
+        b = np.asarray(b, bool)
+        gs += np.where(b, np.hypot(g2d[:, 0], g2d[:, 1]), 0.0)
+        cnt += b
+    return gs, cnt
 
 
 def adam_step(raw: dict, g: dict, m: dict, v: dict, t: int, lr: dict, b1=0.9, b2=0.999, eps=1e-15):

@@ -102,3 +102,28 @@ def test_densify_actions_and_results():
     # moments: kept originals keep theirs, split parents and new ones restart
     assert np.all(om["means"][[0, 1, 3]] == 1.0) and np.all(om["means"][[2, 9, 10, 11]] == 0.0)
     assert keep.sum() == 12 and not keep[7]
+
+
+def test_photometric_loss_and_its_gradient_by_central_differences():
+    rng = np.random.default_rng(9)
+    C, Ct = rng.uniform(size=(7, 3)), rng.uniform(size=(7, 3))
+    L, dC = train.photometric_loss(C, Ct)
+    # hand value for a one-pixel image: ((0.5)^2 + 0 + (-1)^2) / 3
+    assert train.photometric_loss(np.array([[1.0, 2.0, 3.0]]), np.array([[0.5, 2.0, 4.0]]))[0] == 1.25 / 3
+    h = 1e-6
+    for i, c in ((0, 0), (3, 2), (6, 1)):
+        Cp, Cm = C.copy(), C.copy()
+        Cp[i, c] += h
+        Cm[i, c] -= h
+        fd = (train.photometric_loss(Cp, Ct)[0] - train.photometric_loss(Cm, Ct)[0]) / (2 * h)
+        assert abs(fd - dC[i, c]) <= 1e-9
+
+
+def test_densify_stats_hand_case():
+    # three Gaussians, two views: (3, 4) -> 5 in view 0 only where binned
+    g0 = np.array([[3.0, 4.0], [1.0, 0.0], [0.0, 0.0]])
+    g1 = np.array([[0.0, -2.0], [6.0, 8.0], [5.0, 12.0]])
+    b0 = np.array([True, False, True])
+    b1 = np.array([True, True, False])
+    gs, cnt = train.densify_stats([g0, g1], [b0, b1])
+    assert gs.tolist() == [7.0, 10.0, 0.0] and cnt.tolist() == [2, 1, 1]
