@@ -60,8 +60,8 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
         # bit 2: the colour clamp of a Gaussian that this view binned is ambiguous
         gflags |= np.where(pr["clamp_amb"] & bins["per_view"][vi]["binned"], 4, 0).astype(np.int32)
         rec = dict(C=out["C"], Cmag=out["Cmag"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
-                   flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"])
-        for key in ("Lgt", "Lcf", "Lcf_mag", "FN", "WN"):
+                   flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"], g2d_amb=out["g2d_amb"])
+        for key in ("Lgt", "Lcf", "Lcf_mag", "Lgt_mag", "FN", "WN"):
             if key in out:
                 rec[key] = out[key]
         if vt is not None:

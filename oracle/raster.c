@@ -38,7 +38,9 @@
  *                          + sum_{i>k} sigma_i w_i (1 - fh_i . fh_k)),
  * which joins g_k in the adjoint above.  sigma is a constant of the frozen
  * features, so gradients flow through w only.  Magnitude companions use
- * |fh_i . fh_j| <= 1.  The near-threshold bound (*_amb) does not cover these
+ * |fh_i . fh_j| <= 1, and sigma's companion is sigma + k sigma (1 - sigma)
+ * sum_c |fh_i,c fh_gt,c|: the cosine is a sum whose rounding the sigmoid's
+ * slope carries into sigma (first order).  The near-threshold bound (*_amb) does not cover these
  * terms: scenes checked with them have no near-threshold decision.
  *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
@@ -118,13 +120,14 @@ typedef struct {
     const double *ndfd_b;            /* [P] dL/dL_cf (NULL: 0) */
     double *out_Lgt, *out_Lcf;       /* [P] */
     double *out_Lcf_mag;             /* [P] or NULL */
+    double *out_Lgt_mag;             /* [P] or NULL */
     double *out_FN;                  /* [P, d] or NULL: sum_i w_i fh_i */
     double *out_WN;                  /* [P] or NULL: sum_i w_i */
 } oracle_args;
 
 /* per-thread scratch of the NDFD branch */
 typedef struct {
-    double *sig, *h, *hm, *cterm, *cmag;   /* [maxlen] per contributor */
+    double *sig, *sigm, *h, *hm, *cterm, *cmag;   /* [maxlen] per contributor */
     double *vec;                           /* [2 d] */
 } ndfd_scratch;
 
@@ -169,35 +172,43 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
     const double ig = gn > 0.0 ? 1.0 / gn : 0.0;
     double *P = sc->vec, *B = sc->vec + d;
     memset(P, 0, sizeof(double) * d);
-    double W = 0.0, Lgt = 0.0, Lcf = 0.0, Lcfm = 0.0;
+    double W = 0.0, Lgt = 0.0, Lgtm = 0.0, Lcf = 0.0, Lcfm = 0.0;
     for (int64_t i = 0; i < nrec; ++i) {
         const int64_t g = recs[i].g;
         const double w = recs[i].alpha * recs[i].T;
-        double phi = 0.0, pf = 0.0;
+        double phi = 0.0, phim = 0.0, pf = 0.0;
         for (int64_t c = 0; c < d; ++c) {
             phi += fhat(a, g, c) * gt[c];
+            phim += fabs(fhat(a, g, c) * gt[c]);
             pf += P[c] * fhat(a, g, c);
         }
         phi *= ig;
+        phim *= ig;
         const double sg = 1.0 / (1.0 + exp(a->ndfd_k * (phi - a->ndfd_lambda)));
+        /* sigma's companion: sigma itself plus the cosine's companion carried
+           through the sigmoid's slope k sigma (1 - sigma) */
+        const double sgm = sg + a->ndfd_k * sg * (1.0 - sg) * phim;
         sc->sig[i] = sg;
+        sc->sigm[i] = sgm;
         sc->cterm[i] = sg * (W - pf);
-        sc->cmag[i] = sg * 2.0 * W;
+        sc->cmag[i] = sgm * 2.0 * W;
         Lgt += w * sg;
+        Lgtm += w * sgm;
         Lcf += sg * w * (W - pf);
-        Lcfm += sg * w * 2.0 * W;
+        Lcfm += sgm * w * 2.0 * W;
         for (int64_t c = 0; c < d; ++c) P[c] += w * fhat(a, g, c);
         W += w;
     }
     a->out_Lgt[pix] = Lgt;
     a->out_Lcf[pix] = Lcf;
     if (a->out_Lcf_mag) a->out_Lcf_mag[pix] = Lcfm;
+    if (a->out_Lgt_mag) a->out_Lgt_mag[pix] = Lgtm;
     if (a->out_FN) memcpy(a->out_FN + pix * d, P, sizeof(double) * d);
     if (a->out_WN) a->out_WN[pix] = W;
     if (!a->ndfd_a && !a->ndfd_b) return;
     const double ca = a->ndfd_a ? a->ndfd_a[pix] : 0.0, cb = a->ndfd_b ? a->ndfd_b[pix] : 0.0;
     /* sum_{i>k} sigma_i w_i and sum_{i>k} sigma_i w_i fh_i, back to front */
-    double A = 0.0;
+    double A = 0.0, Am = 0.0;
     memset(B, 0, sizeof(double) * d);
     for (int64_t k = nrec - 1; k >= 0; --k) {
         const int64_t g = recs[k].g;
@@ -205,8 +216,9 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
         double bf = 0.0;
         for (int64_t c = 0; c < d; ++c) bf += B[c] * fhat(a, g, c);
         sc->h[k] = ca * sc->sig[k] + cb * (sc->cterm[k] + (A - bf));
-        sc->hm[k] = fabs(ca) * sc->sig[k] + fabs(cb) * (sc->cmag[k] + 2.0 * A);
+        sc->hm[k] = fabs(ca) * sc->sigm[k] + fabs(cb) * (sc->cmag[k] + 2.0 * Am);
         A += sc->sig[k] * w;
+        Am += sc->sigm[k] * w;
         for (int64_t c = 0; c < d; ++c) B[c] += sc->sig[k] * w * fhat(a, g, c);
     }
 }
@@ -457,9 +469,9 @@ int oracle_raster(const oracle_args *a) {
     {
         blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
         amb_rec *amb = (amb_rec *)malloc(sizeof(amb_rec) * (size_t)(2 * maxlen + 2));
-        double *nd = (double *)malloc(sizeof(double) * (size_t)(5 * (maxlen + 1) + 2 * (a->d + 1)));
+        double *nd = (double *)malloc(sizeof(double) * (size_t)(6 * (maxlen + 1) + 2 * (a->d + 1)));
         ndfd_scratch sc = {nd, nd + (maxlen + 1), nd + 2 * (maxlen + 1), nd + 3 * (maxlen + 1),
-                           nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1)};
+                           nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1), nd + 6 * (maxlen + 1)};
         double gvec[9], gmag[9];
         if (!recs || !amb || !nd) {
 #pragma omp atomic write

@@ -48,7 +48,7 @@ class _Args(ctypes.Structure):
         ("g2d", _P), ("g2d_mag", _P), ("fsum", _P), ("fsum_mag", _P), ("wsum", _P),
         ("dfeat", _P), ("g2d_amb", _P), ("fsum_amb", _P), ("wsum_amb", _P), ("gflags", _P), ("counts", _P),
         ("ndfd_gt", _P), ("feat_inv_norm", _P), ("ndfd_lambda", ctypes.c_double), ("ndfd_k", ctypes.c_double),
-        ("ndfd_a", _P), ("ndfd_b", _P), ("out_Lgt", _P), ("out_Lcf", _P), ("out_Lcf_mag", _P), ("out_FN", _P),
+        ("ndfd_a", _P), ("ndfd_b", _P), ("out_Lgt", _P), ("out_Lcf", _P), ("out_Lcf_mag", _P), ("out_Lgt_mag", _P), ("out_FN", _P),
         ("out_WN", _P),
     ]
 
@@ -147,7 +147,7 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         nd["gt"] = k("gt", _f64(ndfd["gt"]))
         nd["a"] = k("na", _f64(ndfd.get("a")))
         nd["b"] = k("nb", _f64(ndfd.get("b")))
-        for key, shape in (("Lgt", P), ("Lcf", P), ("Lcf_mag", P), ("WN", P)):
+        for key, shape in (("Lgt", P), ("Lcf", P), ("Lcf_mag", P), ("Lgt_mag", P), ("WN", P)):
             out[key] = np.zeros(shape)
         out["FN"] = np.zeros((P, d))
 
@@ -168,7 +168,7 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         ndfd_gt=_ptr(nd.get("gt")), feat_inv_norm=_ptr(nd.get("inv")),
         ndfd_lambda=float(ndfd["lam"]) if ndfd else 0.0, ndfd_k=float(ndfd["k"]) if ndfd else 0.0,
         ndfd_a=_ptr(nd.get("a")), ndfd_b=_ptr(nd.get("b")), out_Lgt=_ptr(out.get("Lgt")),
-        out_Lcf=_ptr(out.get("Lcf")), out_Lcf_mag=_ptr(out.get("Lcf_mag")), out_FN=_ptr(out.get("FN")),
+        out_Lcf=_ptr(out.get("Lcf")), out_Lcf_mag=_ptr(out.get("Lcf_mag")), out_Lgt_mag=_ptr(out.get("Lgt_mag")), out_FN=_ptr(out.get("FN")),
         out_WN=_ptr(out.get("WN")),
     )
     rc = lib.oracle_raster(ctypes.byref(args))

@@ -123,3 +123,26 @@ def test_identical_features_closed_form():
     assert np.allclose(v["Lgt"], sig * (1.0 - v["T"]), rtol=1e-12, atol=1e-16)
     for k in ("means", "scales", "quats", "opacity"):
         assert np.allclose(o["grads"][k], 0.0, atol=1e-12 * (1 + np.abs(o["grads_mag"][k]).max())), k
+
+
+def test_sigma_companion_bounds_the_cosine_rounding():
+    """sigma's companion carries the cosine's rounding through the sigmoid's
+    slope: scaling the ground-truth map's components by (1 + eps s), s = +-1,
+    changes every cosine by at most 2 eps sum_c |fh_c gh_c| (the components and
+    the norm), so L_gt and L_cf change by at most 2 eps (M - their slope-free
+    part) to first order; the slope-free companion alone is exceeded."""
+    g, cams, vt = _case(8)
+    eps = 1e-7
+    rng = np.random.default_rng(9)
+    o0 = pipeline.run(g, cams, [vt], ndfd=dict(lam=LAM, k=K))["views"][0]
+    vt2 = dict(vt, gt=vt["gt"] * (1.0 + eps * rng.choice([-1.0, 1.0], size=vt["gt"].shape)))
+    o1 = pipeline.run(g, cams, [vt2], ndfd=dict(lam=LAM, k=K))["views"][0]
+    dgt = np.abs(o1["Lgt"] - o0["Lgt"])
+    slope_gt = o0["Lgt_mag"] - o0["Lgt"]              # sum w k sigma (1 - sigma) phi_mag
+    assert np.all(dgt <= 2.05 * eps * slope_gt + 1e-18)
+    assert np.all(o0["Lgt_mag"] >= o0["Lgt"]) and np.all(o0["Lcf_mag"] >= np.abs(o0["Lcf"]))
+    # the change is real and larger than the slope-free companion allows
+    hit = o0["Lgt"] > 0
+    assert (dgt[hit] / (eps * o0["Lgt"][hit])).max() > 2.05
+    dcf = np.abs(o1["Lcf"] - o0["Lcf"])
+    assert np.all(dcf <= 2.05 * eps * o0["Lcf_mag"] + 1e-18)
