@@ -49,6 +49,8 @@ def parse():
                     help="no GPU: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-calibration run into profiles/traffic_<kernel>_<workload>_<form>.json")
     ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with --traffic-from")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also time the NDFD branch and the training-step kernels on the headline workload")
     ap.add_argument("--batched", default="c4",
                     help="batched workload timed after the headline as one graph-replayed step per form "
                          "('' to skip)")
@@ -433,6 +435,141 @@ def batched_leg(args, dev):
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def _event_ms(fn, K):
+    """Mean ms of K calls of fn between two events on the current stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(K):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K
+
+
+def extras_leg(W, args, dev):
+    """The NDFD branch (Section 3.3) and the training-step kernels (Algorithm 1)
+    on the headline workload, BF16 form.  NDFD: the losses alone
+    (fh_ndfd_losses) and the backward with the NDFD gradient joined, the NDFD
+    kernel bracketed by HIP events on its stream; roofline against the BF16
+    MFMA peak with the algorithmic flops 10 D per walked (pixel, position) for
+    the gradient launch (phi, x, the running F, y, the running sigma-weighted
+    suffix) and 6 D for the losses.  Training: Adam over the raw parameters,
+    the photometric loss, and one whole training step (render, loss, adjoint,
+    densification statistics, Adam) with HBM rooflines for the elementwise
+    kernels."""
+    import torch
+
+    from paper_2505_19154_amd import _lib as L
+    from paper_2505_19154_amd import train as T
+    from paper_2505_19154_amd.raster import Rasterizer
+
+    wl, cams, dg = W["wl"], W["cams"], W["dg"]
+    K = args.steps
+    out = {}
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form="bf16", device=dev)
+    img = r.forward(dg, margin=1.02)
+    blends = int(img.n_iter.to(torch.int64).sum().item())
+    P = r.n_pixels
+    gt = W["target"]                      # a BF16 [P, D] map stands in for F_gt
+    a = torch.full((P,), 1.0 / P, device=dev)
+    b = torch.full((P,), 0.1 / P, device=dev)
+    nd = dict(gt=gt, a=a, b=b, lam=0.5, k=20.0)
+    grads = r.new_grads()
+    for _ in range(args.warmup):
+        r.ndfd_losses(dg, img, gt)
+        r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads, ndfd=nd)
+    ms_loss = _event_ms(lambda: r.ndfd_losses(dg, img, gt), K)
+    ks = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in ks + ke:
+        e.record()
+    torch.cuda.synchronize()
+    arr_s = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ks])
+    arr_e = (ctypes.c_void_p * K)(*[e._as_parameter_ for e in ke])
+    L.check(r.lib.fh_set_kernel_events(L.FH_K_NDFD, arr_s, arr_e, K), "fh_set_kernel_events")
+    ms_bwd_ndfd = _event_ms(lambda: r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads, ndfd=nd), K)
+    L.check(r.lib.fh_set_kernel_events(L.FH_K_NDFD, None, None, 0), "fh_set_kernel_events")
+    kms = sum(x.elapsed_time(y) for x, y in zip(ks, ke)) / K
+    ms_bwd = _event_ms(lambda: r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads), K)
+    flops = 10.0 * wl.d * blends
+    ach = flops / (kms * 1e-3) / 1e12
+    out["ndfd"] = dict(
+        losses_ms=ms_loss, render_bwd_with_ndfd_ms=ms_bwd_ndfd, render_bwd_ms=ms_bwd, ndfd_kernel_ms=kms,
+        walked_positions=blends,
+        roofline=dict(kernel="k_ndfd (gradient)", bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFLOPS,
+                      unit="TFLOP/s", frac=ach / MFMA_BF16_PEAK_TFLOPS, algorithmic_flops=flops,
+                      per_unit=f"10 D = {10 * wl.d} flops per walked (pixel, position)"))
+    print(f"[bench] ndfd: losses {ms_loss:.3f} ms, kernel {kms:.3f} ms, backward {ms_bwd:.3f} -> {ms_bwd_ndfd:.3f} ms",
+          file=sys.stderr, flush=True)
+    # training step kernels, on this workload's Gaussians as raw parameters
+    p = T.Params(dg.means.clone(), torch.log(dg.scales), dg.quats.clone(),
+                 torch.log(dg.opacity) - torch.log1p(-dg.opacity), dg.sh.clone())
+    p = T.activate(p)
+    m, v = T.Params.zeros_like(p), T.Params.zeros_like(p)
+    lr = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, logit_opacity=5e-2, sh=2.5e-3)
+    step = [0]
+
+    def adam():
+        step[0] += 1
+        T.adam_step(p, m, v, grads, step[0], lr)
+
+    for _ in range(args.warmup):
+        adam()
+    ms_adam = _event_ms(adam, K)
+    nb = (wl.sh_degree + 1) ** 2
+    per_g = (3 + 3 + 4 + 1 + 3 * nb) * 28 + 4 * 8
+    adam_bytes = per_g * wl.n
+    pl = T.PhotometricLoss(P, dev)
+    target_img = img.C.flip(0).contiguous()
+    dC = torch.empty_like(img.C)
+    for _ in range(args.warmup):
+        pl(img.C, target_img, dC)
+    ms_pl = _event_ms(lambda: pl(img.C, target_img, dC), K)
+    gsum = torch.zeros(wl.n, dtype=torch.float32, device=dev)
+    cnt = torch.zeros(wl.n, dtype=torch.int32, device=dev)
+    tr_grads = r.new_grads()
+
+    def train_step():
+        g = p.gaussians(dg.feat)
+        r.project(g)
+        r.bin_sort()
+        r.render_fwd(g, img)
+        pl(img.C, target_img, dC)
+        r.render_bwd(g, img, dC, None, None, grads=tr_grads)
+        T.densify_stats(r, gsum, cnt)
+        step[0] += 1
+        T.adam_step(p, m, v, tr_grads, step[0], lr)
+
+    r.reserve(int(r.plan.inst_capacity) * 2, int(r.plan.visit_capacity) * 2)
+    for _ in range(args.warmup):
+        train_step()
+    ms_train = _event_ms(train_step, K)
+    c = r.counters()
+    out["train"] = dict(
+        adam_ms=ms_adam, photometric_loss_ms=ms_pl, step_ms=ms_train,
+        step=("project, bin_sort, render_fwd, photometric loss, render_bwd, densification statistics, Adam "
+              "(BF16 form, no fusion; capacities reserved at twice the first step's counts)"),
+        step_overflow=bool(c.inst_overflow or c.visit_overflow),
+        adam_roofline=dict(kernel="k_adam", bound="hbm", achieved=adam_bytes / (ms_adam * 1e-3) / 1e9,
+                           peak=HBM_PEAK_GBS, unit="GB/s", frac=adam_bytes / (ms_adam * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           algorithmic_bytes=adam_bytes,
+                           per_unit=f"{per_g} B per Gaussian (x, g, m, v read; x, m, v written; 59 floats; "
+                                    f"activated scales and opacity read and written)"),
+        loss_roofline=dict(kernel="k_loss_partial + k_loss_final", bound="hbm",
+                           achieved=36.0 * P / (ms_pl * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=36.0 * P / (ms_pl * 1e-3) / 1e9 / HBM_PEAK_GBS, per_unit="36 B per pixel"))
+    print(f"[bench] train: adam {ms_adam:.3f} ms, loss {ms_pl:.3f} ms, step {ms_train:.3f} ms",
+          file=sys.stderr, flush=True)
+    del r, img
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -514,6 +651,8 @@ def main():
     }
     del main_run, r, img
     torch.cuda.empty_cache()
+    if args.extras and wl.feat_dtype == "bf16" and wl.fusion:
+        res["extras"] = extras_leg(W, args, dev)
     if not args.no_cpu_baseline and W["vts"] is not None:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(W["g"], cams, W["vts"], wl, args.cpu_seconds)

@@ -173,11 +173,30 @@ typedef struct {
 } fh_image;
 
 /* Upstream adjoints for fh_render_bwd: dC [P,3], dF [P,d] (NULL = 0),
- * dT [P] (NULL = 0). FP32. */
+ * dT [P] (NULL = 0). FP32.
+ *
+ * Optional NDFD feature branch (Section 3.3, Appendix A.1-A.2; ndfd_gt NULL:
+ * off).  With unit features fh_i and gh = F_gt(p) / |F_gt(p)|, along each
+ * pixel's walk sigma_i = 1 / (1 + exp(ndfd_k (fh_i . gh - ndfd_lambda))),
+ * L_gt = sum_i w_i sigma_i and L_cf = sum_i sigma_i w_i (W_{i-1} -
+ * F_{i-1} . fh_i) with W, F the running weight and unit-feature sums; the
+ * derivative of sum_p (ndfd_a[p] L_gt(p) + ndfd_b[p] L_cf(p)) through the
+ * blend weights joins the adjoint (sigma is a constant of the frozen
+ * features).  ndfd_gt [P,d] BF16; ndfd_a, ndfd_b [P] FP32 (NULL = 0);
+ * ndfd_Lgt, ndfd_Lcf [P] FP32 outputs of the same sweep (NULL: not written).
+ * Needs BF16 features and d in {32, 64, 96, 128, 256} (FH_E_UNSUPPORTED
+ * otherwise). */
 typedef struct {
     const float *dC;
     const float *dF;
     const float *dT;
+    const void *ndfd_gt;
+    const float *ndfd_a;
+    const float *ndfd_b;
+    float *ndfd_Lgt;
+    float *ndfd_Lcf;
+    float ndfd_lambda;
+    float ndfd_k;
 } fh_upstream;
 
 /* Gradients written by fh_render_bwd (caller-owned, FP32, overwritten):
@@ -273,6 +292,13 @@ fh_status fh_render_bwd(const fh_plan *plan, const fh_gaussians *g, void *ws, co
                         const fh_upstream *up, const void *fusion_target, fh_dtype target_dtype,
                         const fh_fusion *acc, const fh_grads *out, hipStream_t stream);
 
+/* The NDFD losses alone (Section 3.3): L_gt [P] and L_cf [P] of every pixel
+ * (either may be NULL) for the ground-truth map gt [P,d] (BF16), with the
+ * sigmoid's threshold lambda and slope k; needs fh_render_fwd's T and n_iter
+ * for the same views.  BF16 features, d in {32, 64, 96, 128, 256}. */
+fh_status fh_ndfd_losses(const fh_plan *plan, const fh_gaussians *g, void *ws, const fh_image *fwd, const void *gt,
+                         float lambda, float k, float *Lgt, float *Lcf, hipStream_t stream);
+
 /* Feature fusion alone: acc.sum += sum_p w_g(p) target(p), acc.wsum += sum_p
  * w_g(p) for every Gaussian g, Neumaier-compensated; needs fh_render_fwd's
  * T and n_iter for the same views.  BF16 form: target must be BF16. */
@@ -320,7 +346,8 @@ typedef enum {
     FH_K_RENDER_FWD = 2,    /* the compositing kernel of fh_render_fwd */
     FH_K_RENDER_BWD = 3,    /* the adjoint (+ fusion) compositing kernel of fh_render_bwd / fh_fuse_features */
     FH_K_REDUCE = 4,        /* the per-Gaussian reductions of the per-instance partials */
-    FH_K_PROJECT_BWD = 5    /* the projection adjoint of fh_render_bwd */
+    FH_K_PROJECT_BWD = 5,   /* the projection adjoint of fh_render_bwd */
+    FH_K_NDFD = 6           /* the NDFD walk of fh_render_bwd / fh_ndfd_losses */
 } fh_kernel;
 
 /* Profiling hook for benchmarks: for the next n launches of `which`, record
@@ -329,6 +356,118 @@ typedef enum {
  * valid until those launches are issued; n = 0 switches the hook off.
  * Process-wide host state, not thread-safe. */
 fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t *start, hipEvent_t *stop, int32_t n);
+
+/* ------------------------------------------------------------------------
+ * The training step around the rasterizer (Algorithm 1 of the paper:
+ * photometric loss, Adam update of the Gaussians, and periodic adaptive
+ * density control).  Elementwise kernels over pixels or Gaussians; all calls
+ * asynchronous on `stream`, no allocation, no host synchronisation.
+ * ------------------------------------------------------------------------ */
+
+/* Raw trainable parameters (device, FP32, structure of arrays): means [n,3],
+ * log_scales [n,3] (scale = exp), quats [n,4] (raw, normalised inside the
+ * projection), logit_opacity [n] (opacity = sigmoid), sh [n,(L+1)^2,3].  The
+ * same layout holds Adam's first and second moments. */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *logit_opacity;
+    float *sh;
+} fh_params;
+
+/* Adam (Kingma and Ba): per element with raw gradient g at step t >= 1,
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * lr per group in fh_params order (means, log_scales, quats, logit, sh). */
+typedef struct {
+    float lr[5];
+    float beta1, beta2, eps;
+    int32_t step;
+} fh_adam;
+
+/* One Adam step of every group, in place on `param`, `m` and `v`.  `grads`
+ * are fh_render_bwd's gradients of the ACTIVATED parameters; the raw
+ * gradients are taken through the activations at the rendering values held
+ * in `scales` [n,3] and `opacity` [n] (dL/dlog s = s dL/ds, dL/dlogit =
+ * o (1 - o) dL/do), which are then overwritten with the activations of the
+ * updated raw values, ready for the next fh_project.  Errors: FH_E_INVALID for
+ * null pointers, n < 0, sh_degree outside 0..3, step < 1, betas outside
+ * [0, 1) or eps < 0. */
+fh_status fh_adam_step(int64_t n, int32_t sh_degree, const fh_params *param, const fh_params *m,
+                       const fh_params *v, const fh_grads *grads, const fh_adam *cfg, float *scales,
+                       float *opacity, hipStream_t stream);
+
+/* The activated values rendering reads: scales [n,3] = exp(log_scales),
+ * opacity [n] = 1 / (1 + exp(-logit_opacity)). */
+fh_status fh_activate(int64_t n, const float *log_scales, const float *logit_opacity, float *scales, float *opacity,
+                      hipStream_t stream);
+
+/* Densification statistics (Algorithm 1, Densification), accumulated after
+ * each fh_render_bwd of `plan`: for every Gaussian and every view that binned
+ * it (at least one tile instance), grad_sum [n] += |dL/d(u, v)| (the norm of
+ * the screen-space mean gradient of that view) and count [n] += 1, views in
+ * order, FP32.  Caller-owned accumulators, zeroed at each refinement.  After an
+ * instance or visit overflow nothing is added. */
+fh_status fh_densify_stats(const fh_plan *plan, const void *ws, float *grad_sum, int32_t *count, hipStream_t stream);
+
+/* Thresholds of the adaptive density control.  With avg = grad_sum / count
+ * (0 if count = 0) and lmax the largest log-scale, all in float32:
+ * avg >= grad_threshold and lmax <= log_scale_threshold: clone;
+ * avg >= grad_threshold and lmax > log_scale_threshold: split into two;
+ * then every Gaussian (with its clone or second child) whose logit is below
+ * prune_logit is removed. */
+typedef struct {
+    float grad_threshold;
+    float log_scale_threshold;
+    float prune_logit;
+} fh_densify_config;
+
+/* Bytes of the caller workspace fh_densify_plan / fh_densify_apply use for n
+ * Gaussians. */
+size_t fh_densify_workspace_size(int64_t n);
+
+/* Decide every Gaussian's action and its output positions, and write
+ * counts[0] = n_out (kept Gaussians + appended copies) and counts[1] = n_keep
+ * (kept originals) to `counts` (device int64[2]); the caller reads them (a
+ * synchronising read) to allocate the outputs of fh_densify_apply.  dws:
+ * fh_densify_workspace_size(n) bytes, kept until fh_densify_apply. */
+fh_status fh_densify_plan(int64_t n, const float *grad_sum, const int32_t *count, const float *log_scales,
+                          const float *logit_opacity, const fh_densify_config *cfg, void *dws, int64_t *counts,
+                          hipStream_t stream);
+
+/* Write the densified set: the kept Gaussians in index order (a split one
+ * replaced by its first child), then the clones and second children in the
+ * index order of their parents.  Split children: means mu + R(q) diag(s) z_j
+ * (z [n,2,3]: standard normal draws, j = 0, 1; only split Gaussians' rows are
+ * read), log-scales log s - ln 1.6, other parameters copied.  Moments: kept
+ * originals keep theirs, split parents and new Gaussians start at zero.
+ * Outputs hold n_out rows (counts[0] of fh_densify_plan); n_keep = counts[1];
+ * n_out = 0 writes nothing (outputs may then be NULL).  scales_out [n_out,3],
+ * opacity_out [n_out]: the activated values.  Outputs must not alias the
+ * inputs. */
+fh_status fh_densify_apply(int64_t n, int32_t sh_degree, const void *dws, const fh_params *in, const fh_params *m_in,
+                           const fh_params *v_in, const float *z, int64_t n_out, int64_t n_keep, const fh_params *out,
+                           const fh_params *m_out, const fh_params *v_out, float *scales_out, float *opacity_out,
+                           hipStream_t stream);
+
+/* Densify any other per-Gaussian attribute (the frozen features f, which
+ * Algorithm 1's densification carries along): out row k receives the row of
+ * the parent of output Gaussian k, in the order of fh_densify_apply.  in [n,
+ * row_bytes], out [n_out, row_bytes]; dws as left by fh_densify_plan. */
+fh_status fh_densify_copy_rows(int64_t n, const void *dws, const void *in, void *out, int64_t row_bytes,
+                               int64_t n_out, int64_t n_keep, hipStream_t stream);
+
+/* Bytes of the caller workspace fh_photometric_loss uses for n_pixels. */
+size_t fh_loss_workspace_size(int64_t n_pixels);
+
+/* Photometric loss of a rendered image against its target (Algorithm 1,
+ * Photometric Loss; the paper leaves the function open, here the mean squared
+ * error over pixels and channels): *loss (device) = sum (C - C_target)^2 /
+ * (3 P), dC [P,3] = 2 (C - C_target) / (3 P), the upstream adjoint of
+ * fh_render_bwd.  Summed in a fixed order (reproducible). */
+fh_status fh_photometric_loss(int64_t n_pixels, const float *C, const float *C_target, float *dC, float *loss,
+                              void *lws, hipStream_t stream);
 
 const char *fh_status_string(fh_status s);
 int32_t fh_version(void);

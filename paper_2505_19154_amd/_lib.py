@@ -20,7 +20,7 @@ FH_OK, FH_E_INVALID, FH_E_UNSUPPORTED, FH_E_HIP, FH_E_CAPACITY = 0, -1, -2, -3, 
 FH_F32, FH_BF16 = 0, 1
 FH_FORM_F32, FH_FORM_BF16 = 0, 1
 FH_BIN_BOX, FH_BIN_OPACITY = 0, 1
-(FH_K_PROJECT, FH_K_BIN, FH_K_RENDER_FWD, FH_K_RENDER_BWD, FH_K_REDUCE, FH_K_PROJECT_BWD) = range(6)
+(FH_K_PROJECT, FH_K_BIN, FH_K_RENDER_FWD, FH_K_RENDER_BWD, FH_K_REDUCE, FH_K_PROJECT_BWD, FH_K_NDFD) = range(7)
 (FH_BUF_RECORDS, FH_BUF_DEPTH_KEY, FH_BUF_RECT, FH_BUF_DEPTH_ORDER, FH_BUF_RANGES,
  FH_BUF_TILE_NITER, FH_BUF_GRAD2D) = range(7)
 
@@ -57,7 +57,8 @@ class FhImage(ctypes.Structure):
 
 
 class FhUpstream(ctypes.Structure):
-    _fields_ = [("dC", _vp), ("dF", _vp), ("dT", _vp)]
+    _fields_ = [("dC", _vp), ("dF", _vp), ("dT", _vp), ("ndfd_gt", _vp), ("ndfd_a", _vp), ("ndfd_b", _vp),
+                ("ndfd_Lgt", _vp), ("ndfd_Lcf", _vp), ("ndfd_lambda", _f32), ("ndfd_k", _f32)]
 
 
 class FhGrads(ctypes.Structure):
@@ -73,6 +74,18 @@ class FhCounters(ctypes.Structure):
                 ("inst_overflow", _i32), ("visit_overflow", _i32)]
 
 
+class FhParams(ctypes.Structure):
+    _fields_ = [("means", _vp), ("log_scales", _vp), ("quats", _vp), ("logit_opacity", _vp), ("sh", _vp)]
+
+
+class FhAdam(ctypes.Structure):
+    _fields_ = [("lr", _f32 * 5), ("beta1", _f32), ("beta2", _f32), ("eps", _f32), ("step", _i32)]
+
+
+class FhDensifyConfig(ctypes.Structure):
+    _fields_ = [("grad_threshold", _f32), ("log_scale_threshold", _f32), ("prune_logit", _f32)]
+
+
 _P = ctypes.POINTER
 SIGNATURES = {
     "fh_plan_init": (_i32, [_P(FhPlan), _i64, _i32, _i32, _i32, _i32, _P(FhCamera), _i32, _i64, _i64]),
@@ -83,6 +96,7 @@ SIGNATURES = {
     "fh_render_fwd": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _vp]),
     "fh_render_bwd": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _P(FhUpstream), _vp, _i32,
                              _P(FhFusion), _P(FhGrads), _vp]),
+    "fh_ndfd_losses": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _vp, _f32, _f32, _vp, _vp, _vp]),
     "fh_fuse_features": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _vp, _i32, _P(FhFusion), _vp]),
     "fh_fuse_finalize": (_i32, [_P(FhFusion), _i64, _i32, _vp, _vp, _i32, _vp]),
     "fh_read_counters": (_i32, [_P(FhPlan), _vp, _P(FhCounters), _vp]),
@@ -91,6 +105,18 @@ SIGNATURES = {
     "fh_tuning_candidates": (_i32, [_P(FhPlan), _i32, _P(FhTuning), _i32, _P(_i32)]),
     "fh_autotune": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _P(FhUpstream), _vp, _i32, _P(FhFusion),
                            _P(FhGrads), _i32, _vp]),
+    "fh_adam_step": (_i32, [_i64, _i32, _P(FhParams), _P(FhParams), _P(FhParams), _P(FhGrads), _P(FhAdam), _vp, _vp,
+                            _vp]),
+    "fh_activate": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp]),
+    "fh_densify_stats": (_i32, [_P(FhPlan), _vp, _vp, _vp, _vp]),
+    "fh_densify_workspace_size": (_sz, [_i64]),
+    "fh_densify_plan": (_i32, [_i64, _vp, _vp, _vp, _vp, _P(FhDensifyConfig), _vp, _vp, _vp]),
+    "fh_densify_apply": (_i32, [_i64, _i32, _vp, _P(FhParams), _P(FhParams), _P(FhParams), _vp, _i64, _i64,
+                                _P(FhParams),
+                                _P(FhParams), _P(FhParams), _vp, _vp, _vp]),
+    "fh_densify_copy_rows": (_i32, [_i64, _vp, _vp, _vp, _i64, _i64, _i64, _vp]),
+    "fh_loss_workspace_size": (_sz, [_i64]),
+    "fh_photometric_loss": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fh_status_string": (ctypes.c_char_p, [_i32]),
     "fh_version": (_i32, []),
 }

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfhgs.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "render_f32.hip", "reduce.hip", "render_bf16.hip", "render_bwd_bf16.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "render_f32.hip", "reduce.hip", "render_bf16.hip", "render_bwd_bf16.hip",
+           "train.hip", "ndfd.hip"]
 ARCH = "gfx950"
 
 

@@ -267,6 +267,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     sz[WS_RREC] = (size_t)total * 3 * 16;
     sz[WS_UNIT_OWNER] = (size_t)fuse_unit_capacity(visit_capacity) * u4;
     sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
+    sz[WS_PART_NDFD] = (size_t)visit_capacity * 4 * 8 * sizeof(float);
     static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
     size_t off = 0;
     plan->n_ws = WS_COUNT;
@@ -492,6 +493,29 @@ static void fill_reduce_args(const fh_plan* p, void* ws, ReduceArgs& r) {
     r.acc_sum = r.acc_comp = r.acc_wsum = r.acc_wcomp = nullptr;
 }
 
+// NDFD walk over the staged visits (visit_stage must have run)
+static NdfdArgs ndfd_args(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const void* gt) {
+    NdfdArgs n;
+    n.tile_niter = cbuf<uint32_t>(p, ws, WS_TILE_NITER);
+    n.tile_voff = cbuf<uint32_t>(p, ws, WS_TILE_VOFF);
+    n.counters = cbuf<Counters>(p, ws, WS_COUNTERS);
+    n.vrec = cbuf<float4>(p, ws, WS_VREC);
+    n.vgid = cbuf<uint32_t>(p, ws, WS_VGID);
+    n.feat = static_cast<const uint16_t*>(g->feat);
+    n.d = p->d;
+    n.T_final = fwd->T;
+    n.n_iter = fwd->n_iter;
+    n.gt = static_cast<const uint16_t*>(gt);
+    n.a = n.b = nullptr;
+    n.lam = 0.5f;
+    n.kk = 20.0f;
+    n.Lgt = n.Lcf = nullptr;
+    n.part = buf<float>(p, ws, WS_PART_NDFD);
+    return n;
+}
+
+static bool ndfd_ok(const fh_plan* p) { return p->feat_dtype == FH_BF16 && ndfd_supported(p->d); }
+
 fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const fh_upstream* up,
                         const void* fusion_target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* out,
                         hipStream_t s) {
@@ -504,6 +528,8 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     if (fuse && p->form == FH_FORM_BF16 && target_dtype != FH_BF16) return FH_E_UNSUPPORTED;
     if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
     if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
+    const bool ndfd = up->ndfd_gt != nullptr;
+    if (ndfd && !ndfd_ok(p)) return FH_E_UNSUPPORTED;
     BwdArgs a;
     fill_bwd_args(p, g, ws, fwd, a);
     a.dC = up->dC;
@@ -516,6 +542,20 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     visit_stage(p, ws, s);
     launch_bwd(p, a, vt, fuse, s);
     prof_end(FH_K_RENDER_BWD, s);
+    if (ndfd) {
+        // the NDFD terms of the same walk, added to the gradient kernel's partials
+        NdfdArgs n = ndfd_args(p, g, ws, fwd, up->ndfd_gt);
+        n.a = up->ndfd_a;
+        n.b = up->ndfd_b;
+        n.lam = up->ndfd_lambda;
+        n.kk = up->ndfd_k;
+        n.Lgt = up->ndfd_Lgt;
+        n.Lcf = up->ndfd_Lcf;
+        prof_begin(FH_K_NDFD, s);
+        launch_ndfd(n, vt, (int)p->n_tiles, true, s);
+        prof_end(FH_K_NDFD, s);
+        launch_ndfd_combine(n.part, buf<float>(p, ws, WS_PART_GEOM), n.counters, p->visit_capacity, p->d, s);
+    }
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
     prof_begin(FH_K_REDUCE, s);
@@ -548,6 +588,25 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     prof_begin(FH_K_PROJECT_BWD, s);
     if (p->n > 0) launch_project_bwd(pb, cam_table(*p), p->n_views, s);
     prof_end(FH_K_PROJECT_BWD, s);
+    return launch_status();
+}
+
+fh_status fh_ndfd_losses(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const void* gt,
+                         float lambda, float k, float* Lgt, float* Lcf, hipStream_t s) {
+    if (!p || !ws || !fwd || !gt || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (!fwd->T || !fwd->n_iter) return FH_E_INVALID;
+    if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
+    if (!ndfd_ok(p)) return FH_E_UNSUPPORTED;
+    NdfdArgs n = ndfd_args(p, g, ws, fwd, gt);
+    n.lam = lambda;
+    n.kk = k;
+    n.Lgt = Lgt;
+    n.Lcf = Lcf;
+    const ViewTable vt = view_table(*p);
+    visit_stage(p, ws, s);
+    prof_begin(FH_K_NDFD, s);
+    launch_ndfd(n, vt, (int)p->n_tiles, false, s);
+    prof_end(FH_K_NDFD, s);
     return launch_status();
 }
 
@@ -644,7 +703,7 @@ fh_status fh_autotune(fh_plan* p, const fh_gaussians* g, void* ws, const fh_imag
 
 fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t* start, hipEvent_t* stop, int32_t n) {
     if (n < 0 || (n > 0 && (!start || !stop))) return FH_E_INVALID;
-    if ((int)which < FH_K_PROJECT || (int)which > FH_K_PROJECT_BWD) return FH_E_INVALID;
+    if ((int)which < FH_K_PROJECT || (int)which > FH_K_NDFD) return FH_E_INVALID;
     g_prof.which = n > 0 ? (int)which : -1;
     g_prof.start = start;
     g_prof.stop = stop;

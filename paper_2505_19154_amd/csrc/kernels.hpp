@@ -151,6 +151,28 @@ void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
 int64_t fuse_unit_capacity(int64_t visit_capacity);
 void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
                         float4* rrec, hipStream_t s);
+// ndfd.hip
+struct NdfdArgs {
+    const uint32_t* tile_niter;
+    const uint32_t* tile_voff;
+    const Counters* counters;
+    const float4* vrec;         // [visits * 3] staged records, in visit order
+    const uint32_t* vgid;       // [visits] staged Gaussians
+    const uint16_t* feat;       // [n, d] BF16 features
+    int d;
+    const float* T_final;
+    const uint32_t* n_iter;
+    const uint16_t* gt;         // [P, d] BF16 ground-truth feature map
+    const float* a;             // [P] dL/dL_gt (nullable: 0)
+    const float* b;             // [P] dL/dL_cf (nullable: 0)
+    float lam, kk;              // sigmoid threshold and slope
+    float* Lgt;                 // [P] (nullable)
+    float* Lcf;                 // [P] (nullable)
+    float* part;                // [visits][4 parts][8] screen-space partials (gradient)
+};
+bool ndfd_supported(int d);
+void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s);
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int d, hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
                           const void* feat_in, void* feat_out, int bf16, hipStream_t s);
 

@@ -1,0 +1,613 @@
+// NDFD feature branch (Section 3.3; Appendix A.1-A.2): along each pixel's
+// front-to-back walk, with unit features fh_i = f_i / |f_i| and
+// gh = F_gt / |F_gt| (a zero vector's unit vector taken as zero),
+//   phi_i = fh_i . gh,   sigma_i = 1 / (1 + exp(k (phi_i - lambda))),
+//   L_gt  = sum_i w_i sigma_i,
+//   L_cf  = sum_i sigma_i w_i (W_{i-1} - x_i),  x_i = F_{i-1} . fh_i,
+//   W_{i-1} = sum_{j<i} w_j,  F_{i-1} = sum_{j<i} w_j fh_j,
+// and, for a per-pixel loss a L_gt + b L_cf, the derivative with respect to
+// w_k (Appendix A.2, reversed form: the prefix sums from the recorded totals
+// W_N, F_N minus the suffixes a back-to-front walk accumulates)
+//   h_k = a sigma_k + b (sigma_k (W_{k-1} - x_k) + A_k - y_k),
+//   A_k = sum_{i>k} sigma_i w_i,  y_k = sum_{i>k} sigma_i w_i fh_i . fh_k,
+// which joins the adjoint through w: dL/dalpha_k = T_k h_k - (sum_{i>k} w_i
+// h_i) / (1 - alpha_k), chained to the screen-space terms as in the gradient
+// kernel.  sigma is a constant of the frozen features: no gradient flows
+// through it.
+//
+// All per-(pixel, Gaussian) dot products are MFMA contractions
+// (v_mfma_f32_16x16x32_bf16) over the chunk of 32 positions:
+//   phi^T[k x px]  = Feat[k x D] . gh^T[D x px]          (F_gt BF16, resident)
+//   x^T, y^T       = Feat . Q^T, Feat . R^T               (Q = F, R = the sigma-weighted
+//                                                          suffix; FP32 accumulators fed
+//                                                          back as BF16 hi + lo)
+//   Q^T, R^T      += Feat^T[D x k] . (w / |f|)^T[k x px] (weights split hi + lo)
+//   within chunk  : Gh[k x j] . W^T[j x px]               (Gh = the chunk's unit Gram
+//                                                          matrix, masked, hi + lo)
+// Accumulator layout and operand layout agree up to a permutation of the
+// contracted index, so the running vectors never leave registers: lane
+// (xi, q) of a 16-lane row holds channels 16 m + 4 q + r of pixel xi, which is
+// exactly the B operand of the slab 32 s .. 32 s + 31 when the A operand reads
+// its channels in the order (32 s + 4 q + r, 32 s + 16 + 4 q + r); and it walks
+// the positions 4 q + r and 16 + 4 q + r of the chunk, which are both the rows
+// the contractions return to it and the k-slots of its weight operand.
+//
+// Work mapping: 16 / ROWS workgroups per tile, each ROWS pixel rows (64 ROWS
+// threads, wave w = pixel row); pass 1 walks the tile's visited list front to
+// back (losses; F_N stays in the Q registers), pass 2 (gradient) back to
+// front.  Each part of the tile writes its own per-instance screen-space
+// partial (u, v, A, B, C, sum dL/dpower); a second kernel adds the parts into
+// the gradient kernel's partials in a fixed order.  With two running vectors
+// of D = 128 or 256 channels per pixel the gradient takes 4-row workgroups: one
+// wave per SIMD, whose 512 registers hold the accumulators without spilling.
+#include "kernels.hpp"
+
+namespace fh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NK = 32;                       // positions per chunk
+constexpr int NJP = 40;                      // row stride (bf16) of the transposed features and the Gram operands
+constexpr int NSK = NK + 3;                  // padded per-pixel stride of dL/dpower
+constexpr int NRG = 4;                       // record padding group (lane rows read records 4 apart)
+constexpr int NRSLOTS = 3 * NK + NK / NRG;
+constexpr int NDFD_PART = 8;                 // floats per (visit, part) partial (6 used)
+constexpr int NDFD_PARTS = 4;                // parts per visit in the partial array (16 / ROWS used)
+// rows per workgroup of the gradient walk
+constexpr int ndfd_grad_rows(int d) { return d >= 128 ? 4 : 8; }
+
+__device__ __forceinline__ bf16x8 bf16x8_of(uint2 lo, uint2 hi) {
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+__device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const __bf16 hb = (__bf16)v[m];
+        h[m] = hb;
+        l[m] = (__bf16)(v[m] - (float)hb);
+    }
+}
+
+template <int D, bool GRAD, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
+    constexpr int NT = 64 * ROWS;             // threads
+    static_assert(ROWS == 4 || ROWS == 8, "four waves at least: they compute the Gram blocks");
+    constexpr int NS = D / 32;                // 32-channel slabs
+    constexpr int NB = D / 16;                // 16-channel accumulator blocks
+    constexpr int DP = D + 8;                 // row stride (bf16) of the feature tile
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __bf16* sfeat = reinterpret_cast<__bf16*>(smem);          // [NK][DP]
+    __bf16* sfeatT = sfeat + NK * DP;                          // [D][NJP]
+    __bf16* sA = sfeatT + D * NJP;                             // [3 masks][hi, lo][NK][NJP]
+    float* sG = reinterpret_cast<float*>(sA + 6 * NK * NJP);  // [NK][NK + 1]
+    float* sinv = sG + NK * (NK + 1);                          // [NK]
+    float* sdp = sinv + NK;                                    // [16 ROWS][NSK] dL/dpower (gradient)
+    float* sred = sdp + TILE * ROWS * NSK;                     // [ROWS][6][NK] row sums (gradient)
+    __shared__ float4 srec[NRSLOTS];
+
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int t = blockIdx.x, half = blockIdx.y;
+    const uint32_t nt = a.tile_niter[t];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int W = vt.width[v], H = vt.height[v];
+    const uint32_t voff = a.tile_voff[t];
+    const int ry = ROWS * half + w;
+    const int px = tx * TILE + xi, py = ty * TILE + ry;
+    const bool inside = px < W && py < H;
+    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
+    const int64_t p = vt.pix_off[v] + (int64_t)(inside ? py : 0) * W + (inside ? px : 0);
+    const uint32_t nit = inside ? a.n_iter[p] : 0u;
+    const float ca = (GRAD && inside && a.a) ? a.a[p] : 0.0f;
+    const float cb = (GRAD && inside && a.b) ? a.b[p] : 0.0f;
+    const float LN2 = 0.69314718055994531f;
+    if (nt == 0) {
+        // no Gaussian reaches this tile: both losses are zero
+        if (q == 0 && inside) {
+            if (a.Lgt) a.Lgt[p] = 0.0f;
+            if (a.Lcf) a.Lcf[p] = 0.0f;
+        }
+        return;
+    }
+
+    // F_gt of this lane's pixel, channels (32 s + 4 q + m, 32 s + 16 + 4 q + m):
+    // the B operand of phi; its norm over the pixel's four lanes
+    bf16x8 gto[NS];
+    float gn2 = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        uint2 lo = make_uint2(0u, 0u), hi = make_uint2(0u, 0u);
+        if (inside) {
+            lo = *reinterpret_cast<const uint2*>(a.gt + p * D + 32 * s + 4 * q);
+            hi = *reinterpret_cast<const uint2*>(a.gt + p * D + 32 * s + 16 + 4 * q);
+        }
+        gto[s] = bf16x8_of(lo, hi);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const float g = (float)gto[s][m];
+            gn2 = __builtin_fmaf(g, g, gn2);
+        }
+    }
+    const Rows4 gr = rows4(gn2);
+    const float gsum = (gr.r0 + gr.r1) + (gr.r2 + gr.r3);
+    const float ig = gsum > 0.0f ? 1.0f / sqrtf(gsum) : 0.0f;
+
+    // ---- chunk staging: records, features (row-major and transposed) --------
+    constexpr int ITEMS = NK * (D / 8), NI = (ITEMS + NT - 1) / NT;
+    auto stage = [&](int cs, int cnt) {
+        if ((int)threadIdx.x < NK) {
+            const int k = threadIdx.x;
+            Rec r;
+            if (k < cnt) {
+                const int64_t vi = (int64_t)voff + cs + k;
+                r.r0 = a.vrec[3 * vi];
+                r.r1 = a.vrec[3 * vi + 1];
+                r.r2 = a.vrec[3 * vi + 2];
+            } else {
+                r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+                r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            lds_put_rec<NRG>(srec, k, r);
+        }
+        uint4 raw[NI];
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int idx = threadIdx.x + NT * it;
+            raw[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < ITEMS) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                if (k < cnt) {
+                    const uint32_t g = a.vgid[(int64_t)voff + cs + k];
+                    raw[it] = *reinterpret_cast<const uint4*>(a.feat + (int64_t)g * D + dg * 8);
+                }
+            }
+        }
+        uint16_t* f16 = reinterpret_cast<uint16_t*>(sfeat);
+        uint16_t* ft16 = reinterpret_cast<uint16_t*>(sfeatT);
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int idx = threadIdx.x + NT * it;
+            if (idx < ITEMS) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                *reinterpret_cast<uint4*>(&f16[k * DP + dg * 8]) = raw[it];
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw[it]);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) ft16[(dg * 8 + m) * NJP + k] = h[m];
+            }
+        }
+    };
+    // A operand of a contraction over channels: feature row `row`, slab s, in
+    // the channel order of the accumulator layout
+    auto featA = [&](int row, int s) -> bf16x8 {
+        const uint2 lo = *reinterpret_cast<const uint2*>(&sfeat[row * DP + 32 * s + 4 * q]);
+        const uint2 hi = *reinterpret_cast<const uint2*>(&sfeat[row * DP + 32 * s + 16 + 4 * q]);
+        return bf16x8_of(lo, hi);
+    };
+    // A operand of a contraction over positions: channel row d, positions
+    // (4 q + m, 16 + 4 q + m) -- this lane group's walked positions
+    auto featTA = [&](int d) -> bf16x8 {
+        const uint2 lo = *reinterpret_cast<const uint2*>(&sfeatT[d * NJP + 4 * q]);
+        const uint2 hi = *reinterpret_cast<const uint2*>(&sfeatT[d * NJP + 16 + 4 * q]);
+        return bf16x8_of(lo, hi);
+    };
+    // waves 0..3: the chunk's Gram matrix G[j][k] = f_j . f_k, one 16 x 16 block each
+    auto gram = [&]() {
+        if (w < 4) {
+            const int jb = w >> 1, kb = w & 1;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(featA(16 * jb + xi, s), featA(16 * kb + xi, s), acc, 0,
+                                                              0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sG[(16 * jb + 4 * q + r) * (NK + 1) + 16 * kb + xi] = acc[r];
+        }
+    };
+    // unit Gram operands: row k, slot 8 g + m <-> position j(g, m), masked by
+    // mask 0: j < k, 1: j >= k, 2: j > k; and 1 / |f_k| into sinv
+    auto build_masks = [&](int m0, int m1) {
+        if ((int)threadIdx.x < NK) {
+            const float gkk = sG[threadIdx.x * (NK + 2)];
+            sinv[threadIdx.x] = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
+        }
+        uint16_t* a16 = reinterpret_cast<uint16_t*>(sA);
+        for (int e = threadIdx.x; e < NK * NK; e += NT) {
+            const int k = e / NK, sl = e % NK, g = sl >> 3, m = sl & 7;
+            const int j = m < 4 ? 4 * g + m : 16 + 4 * g + (m - 4);
+            const float gjj = sG[j * (NK + 2)], gkk = sG[k * (NK + 2)];
+            const float ij = gjj > 0.0f ? 1.0f / sqrtf(gjj) : 0.0f, ik = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
+            const float gh = (sG[j * (NK + 1) + k] * ij) * ik;
+            for (int mk = m0; mk <= m1; ++mk) {
+                const bool keep = mk == 0 ? j < k : (mk == 1 ? j >= k : j > k);
+                const float val = keep ? gh : 0.0f;
+                const __bf16 hb = (__bf16)val;
+                a16[((2 * mk) * NK + k) * NJP + sl] = __builtin_bit_cast(uint16_t, hb);
+                a16[((2 * mk + 1) * NK + k) * NJP + sl] = __builtin_bit_cast(uint16_t, (__bf16)(val - (float)hb));
+            }
+        }
+    };
+    // out^T[k][px] += sum_j mask[k][j] V^T[j][px] for both 16-row blocks (V = hi + lo)
+    auto masked = [&](int mk, const bf16x8& vh, const bf16x8& vl, f32x4* out) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const int row = 16 * kb + xi;
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sA[((2 * mk) * NK + row) * NJP + 8 * q]);
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sA[((2 * mk + 1) * NK + row) * NJP + 8 * q]);
+            out[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, vh, out[kb], 0, 0, 0);
+            out[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, vl, out[kb], 0, 0, 0);
+            out[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, vh, out[kb], 0, 0, 0);
+        }
+    };
+    // out^T[k][px] = sum_d f_k[d] Acc^T[d][px] (the accumulator as a BF16 hi + lo operand)
+    auto contract_acc = [&](const f32x4* acc, f32x4* out) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float vals[8] = {acc[2 * s][0], acc[2 * s][1], acc[2 * s][2], acc[2 * s][3],
+                                   acc[2 * s + 1][0], acc[2 * s + 1][1], acc[2 * s + 1][2], acc[2 * s + 1][3]};
+            bf16x8 bh, bl;
+            split8(vals, bh, bl);
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 fa = featA(16 * kb + xi, s);
+                out[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, bh, out[kb], 0, 0, 0);
+                out[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, bl, out[kb], 0, 0, 0);
+            }
+        }
+    };
+    // Acc^T[d][px] += sign sum_j f_j[d] V^T[j][px] (V = hi + lo in the walk's slots)
+    auto accumulate = [&](f32x4* acc, const bf16x8& vh, const bf16x8& vl) {
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) {
+            const bf16x8 fa = featTA(16 * mb + xi);
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, vh, acc[mb], 0, 0, 0);
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, vl, acc[mb], 0, 0, 0);
+        }
+    };
+    // phi (raw f . F_gt) for the chunk's positions 16 kb + 4 q + r
+    auto phi_raw = [&](f32x4* ph) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            ph[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                ph[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(featA(16 * kb + xi, s), gto[s], ph[kb], 0, 0, 0);
+        }
+    };
+    auto sigma_of = [&](float phr, int k) {
+        const float phi = (phr * sinv[k]) * ig;
+        return 1.0f / (1.0f + expf(a.kk * (phi - a.lam)));
+    };
+
+    f32x4 Q[NB];   // pass 1: F = sum w fh (running); pass 2: F_{end of chunk} (decremented)
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) Q[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- pass 1: front to back, the losses ------------------------------------
+    float T = 1.0f, Wacc = 0.0f, lgt = 0.0f, lcf = 0.0f;
+    for (int cs = 0; cs < (int)nt; cs += NK) {
+        const int cnt = (int)nt - cs < NK ? (int)nt - cs : NK;
+        __syncthreads();
+        stage(cs, cnt);
+        __syncthreads();
+        gram();
+        f32x4 ph[2];
+        phi_raw(ph);
+        // walk: w, T_k and W_{k-1} of this lane's positions 16 kb + 4 q + r
+        float wv[2][4], Wp[2][4];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            float al[4];
+            bool on[4];
+            float trel = 1.0f, Wr = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * kb + 4 * q + r;
+                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
+                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
+                on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
+                al[r] = ae.alpha;
+                Wr = on[r] ? __builtin_fmaf(al[r], trel, Wr) : Wr;
+                trel = on[r] ? trel * (1.0f - al[r]) : trel;
+            }
+            const Rows4 Pr = rows4(trel), Wrr = rows4(Wr);
+            const float Te0 = T, Te1 = Te0 * Pr.r0, Te2 = Te1 * Pr.r1, Te3 = Te2 * Pr.r2;
+            const float We0 = Wacc, We1 = We0 + Te0 * Wrr.r0, We2 = We1 + Te1 * Wrr.r1, We3 = We2 + Te2 * Wrr.r2;
+            float Tc = q == 0 ? Te0 : (q == 1 ? Te1 : (q == 2 ? Te2 : Te3));
+            float Wc = q == 0 ? We0 : (q == 1 ? We1 : (q == 2 ? We2 : We3));
+            T = Te3 * Pr.r3;
+            Wacc = We3 + Te3 * Wrr.r3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float wk = on[r] ? al[r] * Tc : 0.0f;
+                wv[kb][r] = wk;
+                Wp[kb][r] = Wc;
+                Wc += wk;
+                Tc = on[r] ? Tc * (1.0f - al[r]) : Tc;
+            }
+        }
+        __syncthreads();
+        build_masks(0, 0);
+        __syncthreads();
+        // within-chunk part of x, and the accumulators' part
+        const float wflat[8] = {wv[0][0], wv[0][1], wv[0][2], wv[0][3], wv[1][0], wv[1][1], wv[1][2], wv[1][3]};
+        bf16x8 wh, wl;
+        split8(wflat, wh, wl);
+        f32x4 xw[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        masked(0, wh, wl, xw);
+        f32x4 xa[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        contract_acc(Q, xa);
+        float wsc[8];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * kb + 4 * q + r;
+                const float ik = sinv[k];
+                const float sg = sigma_of(ph[kb][r], k);
+                const float xk = xa[kb][r] * ik + xw[kb][r];
+                const float wk = wv[kb][r];
+                lgt = __builtin_fmaf(wk, sg, lgt);
+                lcf = __builtin_fmaf(sg * wk, Wp[kb][r] - xk, lcf);
+                wsc[4 * kb + r] = wk * ik;
+            }
+        bf16x8 vh, vl;
+        split8(wsc, vh, vl);
+        accumulate(Q, vh, vl);
+    }
+    {
+        const Rows4 a4 = rows4(lgt), b4 = rows4(lcf);
+        if (q == 0 && inside) {
+            if (a.Lgt) a.Lgt[p] = (a4.r0 + a4.r1) + (a4.r2 + a4.r3);
+            if (a.Lcf) a.Lcf[p] = (b4.r0 + b4.r1) + (b4.r2 + b4.r3);
+        }
+    }
+    if constexpr (!GRAD) return;
+
+    // ---- pass 2: back to front, the gradient ---------------------------------
+    const float WN = Wacc;
+    f32x4 R[NB];
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) R[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    T = inside ? a.T_final[p] : 1.0f;
+    float Wsuf = 0.0f, Asuf = 0.0f, Ssuf = 0.0f;
+    for (int ce = (int)nt; ce > 0; ce -= NK) {
+        const int cs = ce - NK > 0 ? ce - NK : 0;
+        const int cnt = ce - cs;
+        __syncthreads();
+        stage(cs, cnt);
+        __syncthreads();
+        gram();
+        f32x4 ph[2];
+        phi_raw(ph);
+        float al[2][4], iv[2][4], wv[2][4], Tk[2][4];
+        bool on[2][4];
+#pragma unroll
+        for (int kb = 1; kb >= 0; --kb) {
+            float P = 1.0f, trel = 1.0f;
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int k = 16 * kb + 4 * q + r;
+                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
+                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
+                on[kb][r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
+                al[kb][r] = ae.alpha;
+                iv[kb][r] = __builtin_amdgcn_rcpf(1.0f - al[kb][r]);
+                const float tn = trel * iv[kb][r];
+                P = on[kb][r] ? P * (1.0f - al[kb][r]) : P;
+                trel = on[kb][r] ? tn : trel;
+            }
+            const Rows4 Pr = rows4(P);
+            const float Te3 = T, Te2 = Te3 * __builtin_amdgcn_rcpf(Pr.r3), Te1 = Te2 * __builtin_amdgcn_rcpf(Pr.r2),
+                        Te0 = Te1 * __builtin_amdgcn_rcpf(Pr.r1);
+            float Tc = q == 3 ? Te3 : (q == 2 ? Te2 : (q == 1 ? Te1 : Te0));
+            T = Te0 * __builtin_amdgcn_rcpf(Pr.r0);
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const float tk = Tc * iv[kb][r];
+                Tk[kb][r] = tk;
+                wv[kb][r] = on[kb][r] ? al[kb][r] * tk : 0.0f;
+                Tc = on[kb][r] ? tk : Tc;
+            }
+        }
+        __syncthreads();
+        build_masks(1, 2);
+        __syncthreads();
+        float sg[2][4];
+        float sw8[8], wsc[8], swsc[8];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * kb + 4 * q + r;
+                sg[kb][r] = sigma_of(ph[kb][r], k);
+                sw8[4 * kb + r] = sg[kb][r] * wv[kb][r];
+                wsc[4 * kb + r] = wv[kb][r] * sinv[k];
+                swsc[4 * kb + r] = sw8[4 * kb + r] * sinv[k];
+            }
+        // x_k = F_end . fh_k - sum_{j >= k, j in chunk} w_j fh_j . fh_k
+        // y_k = R . fh_k + sum_{i > k, i in chunk} sigma_i w_i fh_i . fh_k
+        const float wflat[8] = {wv[0][0], wv[0][1], wv[0][2], wv[0][3], wv[1][0], wv[1][1], wv[1][2], wv[1][3]};
+        bf16x8 wh, wl, sh, sl;
+        split8(wflat, wh, wl);
+        split8(sw8, sh, sl);
+        f32x4 xw[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        f32x4 yw[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        masked(1, wh, wl, xw);
+        masked(2, sh, sl, yw);
+        f32x4 xa[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        f32x4 ya[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        contract_acc(Q, xa);
+        contract_acc(R, ya);
+        // suffix sums over the chunk's positions (index order kb, q, r):
+        // inclusive of w (for W_{k-1} = W_N - sum_{j >= k} w_j), exclusive of
+        // sigma w (A_k)
+        float lw[2], ls[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            lw[kb] = ((wv[kb][3] + wv[kb][2]) + wv[kb][1]) + wv[kb][0];
+            ls[kb] = ((sw8[4 * kb + 3] + sw8[4 * kb + 2]) + sw8[4 * kb + 1]) + sw8[4 * kb];
+        }
+        float hk[2][4];
+        float baseW = Wsuf, baseA = Asuf;
+#pragma unroll
+        for (int kb = 1; kb >= 0; --kb) {
+            const Rows4 LW = rows4(lw[kb]), LS = rows4(ls[kb]);
+            const float aw3 = 0.0f, aw2 = LW.r3, aw1 = LW.r3 + LW.r2, aw0 = (LW.r3 + LW.r2) + LW.r1;
+            const float as3 = 0.0f, as2 = LS.r3, as1 = LS.r3 + LS.r2, as0 = (LS.r3 + LS.r2) + LS.r1;
+            float cw = baseW + (q == 3 ? aw3 : (q == 2 ? aw2 : (q == 1 ? aw1 : aw0)));
+            float cs2 = baseA + (q == 3 ? as3 : (q == 2 ? as2 : (q == 1 ? as1 : as0)));
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int k = 16 * kb + 4 * q + r;
+                cw += wv[kb][r];                              // sum_{j >= k} w_j
+                const float Wprev = WN - cw;
+                const float xk = xa[kb][r] * sinv[k] - xw[kb][r];
+                const float yk = ya[kb][r] * sinv[k] + yw[kb][r];
+                hk[kb][r] = ca * sg[kb][r] + cb * (sg[kb][r] * (Wprev - xk) + cs2 - yk);
+                cs2 += sw8[4 * kb + r];                       // A_{k-1} = A_k + sigma_k w_k
+            }
+            baseW += aw0 + LW.r0;
+            baseA += as0 + LS.r0;
+        }
+        Wsuf = baseW;
+        Asuf = baseA;
+        // adjoint through w: dL/dalpha_k = T_k h_k - S_k / (1 - alpha_k),
+        // S_k = sum_{i > k} w_i h_i
+        float lh[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            lh[kb] = ((wv[kb][3] * hk[kb][3] + wv[kb][2] * hk[kb][2]) + wv[kb][1] * hk[kb][1]) + wv[kb][0] * hk[kb][0];
+        float baseS = Ssuf;
+        const int n = w * TILE + xi;
+#pragma unroll
+        for (int kb = 1; kb >= 0; --kb) {
+            const Rows4 LH = rows4(lh[kb]);
+            const float ah3 = 0.0f, ah2 = LH.r3, ah1 = LH.r3 + LH.r2, ah0 = (LH.r3 + LH.r2) + LH.r1;
+            float Sc = baseS + (q == 3 ? ah3 : (q == 2 ? ah2 : (q == 1 ? ah1 : ah0)));
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int k = 16 * kb + 4 * q + r;
+                const float dalpha = Tk[kb][r] * hk[kb][r] - Sc * iv[kb][r];
+                const float dpow = (on[kb][r] && al[kb][r] < ALPHA_MAX) ? dalpha * al[kb][r] : 0.0f;
+                sdp[n * NSK + k] = dpow;
+                Sc += wv[kb][r] * hk[kb][r];
+            }
+            baseS += ah0 + LH.r0;
+        }
+        Ssuf = baseS;
+        // the suffix accumulators: F_end -= sum w fh, R += sum sigma w fh
+        {
+            float nw[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) nw[m] = -wsc[m];
+            bf16x8 ah, alo;
+            split8(nw, ah, alo);
+            accumulate(Q, ah, alo);
+            split8(swsc, ah, alo);
+            accumulate(R, ah, alo);
+        }
+        __syncthreads();
+        // Gaussian-parallel sums over this part's rows: wave w = row w, lane
+        // = position k (lanes 32..63 the row's right half), moments of
+        // dL/dpower along the row as in the gradient kernel
+        {
+            const int k = lane & 31, hp = lane >> 5;
+            const Rec rc = lds_rec<NRG>(srec, k);
+            const float ex = rc.r1.x, ey = rc.r1.y, q1 = rc.r1.z, q2 = rc.r1.w;
+            const float dy = (((float)(ty * TILE + ry) + 0.5f) - rc.r0.y) - rc.r0.w;
+            const float dx0 = (((float)(tx * TILE + 8 * hp) + 0.5f) - rc.r0.x) - rc.r0.z;
+            float s0 = 0.0f, sx = 0.0f, sxx = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const float dp = sdp[(w * TILE + 8 * hp + m) * NSK + k];
+                const float dx = dx0 + (float)m;
+                const float pdx = dp * dx;
+                s0 += dp;
+                sx += pdx;
+                sxx = __builtin_fmaf(pdx, dx, sxx);
+            }
+            const float A = q1 * ex * ex + q2 * ey * ey, B = (q1 - q2) * ex * ey, C = q1 * ey * ey + q2 * ex * ex;
+            const float sy = dy * s0;
+            float qv[6];
+            qv[0] = -2.0f * LN2 * (A * sx + B * sy);
+            qv[1] = -2.0f * LN2 * (B * sx + C * sy);
+            qv[2] = -0.5f * sxx;
+            qv[3] = -dy * sx;
+            qv[4] = -0.5f * dy * sy;
+            qv[5] = s0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const auto hv = __builtin_amdgcn_permlane32_swap(__float_as_uint(qv[m]), __float_as_uint(qv[m]),
+                                                                 false, false);
+                qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
+                if (lane < 32) sred[(w * 6 + m) * NK + k] = qv[m];
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 6 * NK) {
+            const int k = threadIdx.x % NK, m = threadIdx.x / NK;
+            float sum = 0.0f;
+#pragma unroll
+            for (int ww = 0; ww < ROWS; ++ww) sum += sred[(ww * 6 + m) * NK + k];
+            if (k < cnt) a.part[(((int64_t)voff + cs + k) * NDFD_PARTS + half) * NDFD_PART + m] = sum;
+        }
+    }
+}
+
+// part_geom[v][m] += part[v][0][m] + ... + part[v][nparts - 1][m] for the six
+// screen-space terms of every visited instance (fixed order).
+__global__ __launch_bounds__(256) void k_ndfd_combine(const float* __restrict__ part, float* __restrict__ part_geom,
+                                                      const Counters* c, int64_t cap, int nparts) {
+    if (c->inst_overflow || c->visit_overflow) return;
+    const int64_t nv = (int64_t)c->n_visited < cap ? (int64_t)c->n_visited : cap;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv * 6) return;
+    const int64_t vi = i / 6;
+    const int m = (int)(i % 6);
+    float s = 0.0f;
+    for (int h = 0; h < nparts; ++h) s += part[(vi * NDFD_PARTS + h) * NDFD_PART + m];
+    part_geom[vi * 12 + m] += s;
+}
+
+template <int D, bool GRAD, int ROWS>
+static void launch_ndfd_shape(const NdfdArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
+    const size_t lds = sizeof(__bf16) * ((size_t)NK * (D + 8) + (size_t)D * NJP + 6 * (size_t)NK * NJP) +
+                       sizeof(float) * ((size_t)NK * (NK + 1) + NK + (size_t)TILE * ROWS * NSK + (size_t)ROWS * 6 * NK);
+    hipLaunchKernelGGL((k_ndfd<D, GRAD, ROWS>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
+}
+
+template <int D>
+static void launch_ndfd_d(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
+    if (grad)
+        launch_ndfd_shape<D, true, ndfd_grad_rows(D)>(a, vt, n_tiles, s);
+    else
+        launch_ndfd_shape<D, false, 8>(a, vt, n_tiles, s);
+}
+
+bool ndfd_supported(int d) { return d == 32 || d == 64 || d == 96 || d == 128 || d == 256; }
+
+void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
+    if (n_tiles <= 0) return;
+    switch (a.d) {
+        case 32: launch_ndfd_d<32>(a, vt, n_tiles, grad, s); break;
+        case 64: launch_ndfd_d<64>(a, vt, n_tiles, grad, s); break;
+        case 96: launch_ndfd_d<96>(a, vt, n_tiles, grad, s); break;
+        case 128: launch_ndfd_d<128>(a, vt, n_tiles, grad, s); break;
+        default: launch_ndfd_d<256>(a, vt, n_tiles, grad, s); break;
+    }
+}
+
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int d, hipStream_t s) {
+    const int64_t n = cap * 6;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ndfd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, part_geom, c, cap,
+                       TILE / ndfd_grad_rows(d));
+}
+
+}  // namespace fh

@@ -24,7 +24,7 @@ _WS = {name: i for i, name in enumerate(
     ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
      "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
      "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
-     "long", "vrec", "vgid", "rrec", "unit_owner", "upart"])}
+     "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd"])}
 
 
 def _ptr(t):
@@ -265,8 +265,31 @@ class Rasterizer:
         e = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)
         return dict(means=e(n, 3), scales=e(n, 3), quats=e(n, 4), opacity=e(n), sh=e(n, nb, 3))
 
+    def _check_ndfd(self, g: Gaussians, gt) -> None:
+        if g.feat is None or g.feat.dtype != torch.bfloat16:
+            raise L.FhError("the NDFD branch needs BF16 features")
+        check_tensor(gt, "gt", (self.n_pixels, self.d), (torch.bfloat16,), self.device)
+
+    def ndfd_losses(self, g: Gaussians, fwd: Image, gt, lam: float = 0.5, k: float = 20.0):
+        """(L_gt [P], L_cf [P]) of the NDFD branch for the ground-truth feature
+        map gt [P, d] (BF16), after render_fwd of the same views."""
+        self._check_image(fwd, "fwd")
+        self._check_ndfd(g, gt)
+        P, dev = self.n_pixels, self.device
+        Lgt = torch.empty(P, dtype=torch.float32, device=dev)
+        Lcf = torch.empty(P, dtype=torch.float32, device=dev)
+        gs, im = g.struct(), fwd.struct()
+        L.check(self.lib.fh_ndfd_losses(ctypes.byref(self.plan), ctypes.byref(gs), _ptr(self.ws), ctypes.byref(im),
+                                        _ptr(gt), float(lam), float(k), _ptr(Lgt), _ptr(Lcf), _stream()),
+                "fh_ndfd_losses")
+        return Lgt, Lcf
+
     def render_bwd(self, g: Gaussians, fwd: Image, dC, dF=None, dT=None, target=None, acc: FusionAcc | None = None,
-                   grads: dict | None = None) -> dict:
+                   grads: dict | None = None, ndfd: dict | None = None) -> dict:
+        """The adjoint (and fusion into acc when target is given).  ndfd
+        (optional): dict(gt [P, d] BF16, a [P], b [P] (either may be None),
+        lam, k, and optionally Lgt, Lcf [P] output tensors) adds the NDFD
+        branch's gradient of sum_p (a L_gt + b L_cf) and writes its losses."""
         grads = grads or self.new_grads()
         P, d, dev = self.n_pixels, self.d, self.device
         self._check_image(fwd, "fwd")
@@ -284,6 +307,14 @@ class Rasterizer:
             self._check_acc(acc)
         gs, im = g.struct(), fwd.struct()
         up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT))
+        if ndfd is not None:
+            self._check_ndfd(g, ndfd["gt"])
+            for nm in ("a", "b", "Lgt", "Lcf"):
+                if ndfd.get(nm) is not None:
+                    check_tensor(ndfd[nm], f"ndfd[{nm!r}]", (P,), _F32, dev)
+            up.ndfd_gt, up.ndfd_a, up.ndfd_b = _ptr(ndfd["gt"]), _ptr(ndfd.get("a")), _ptr(ndfd.get("b"))
+            up.ndfd_Lgt, up.ndfd_Lcf = _ptr(ndfd.get("Lgt")), _ptr(ndfd.get("Lcf"))
+            up.ndfd_lambda, up.ndfd_k = float(ndfd.get("lam", 0.5)), float(ndfd.get("k", 20.0))
         gr = L.FhGrads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
                        _ptr(grads["sh"]))
         fu = acc.struct() if (acc is not None and target is not None) else None
