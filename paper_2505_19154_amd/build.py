@@ -37,7 +37,7 @@ def compile_flags(debug: bool = False) -> list:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-fno-gpu-rdc", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
         f"-I{INCLUDE}", f"-I{CSRC}",
-    ] + (["-g", "-DFH_DEBUG"] if debug else [])
+    ] + (["-g"] if debug else [])
 
 
 def build(debug: bool = False, verbose: bool = False) -> str:
