@@ -59,7 +59,8 @@ typedef enum {
     FH_E_INVALID = -1,      /* null pointer, size or layout error */
     FH_E_UNSUPPORTED = -2,  /* e.g. sh_degree > 3, too many views */
     FH_E_HIP = -3,          /* a HIP launch or runtime call failed */
-    FH_E_CAPACITY = -4      /* device-side: instance or visit capacity exceeded */
+    FH_E_CAPACITY = -4,     /* device-side: instance or visit capacity exceeded */
+    FH_E_SCRATCH = -5       /* the plan's workspace exceeds FH_STATIC_SCRATCH_BYTES (fh_render_fwd_static) */
 } fh_status;
 
 typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
@@ -316,6 +317,25 @@ fh_status fh_read_counters(const fh_plan *plan, const void *ws, fh_counters *out
 
 /* Device pointer and element count of a workspace buffer (no device access). */
 fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **ptr, int64_t *count);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): fh_project +
+ * fh_bin_sort + fh_render_fwd of `plan` with the workspace taken from a static
+ * device array of FH_STATIC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends, instead of a caller allocation.  No
+ * hipMalloc or other allocating call is made.  The caller passes the inputs
+ * (g) and the outputs (out, as for fh_render_fwd) and, optionally, counters: a
+ * DEVICE pointer that receives the call's fh_counters (instance count and
+ * overflow flags) on the stream.  Results equal those of the three calls with
+ * a caller workspace.  Errors: FH_E_SCRATCH when plan->ws_bytes exceeds
+ * FH_STATIC_SCRATCH_BYTES (use a plan with smaller capacities, or the calls
+ * with a workspace), and those of the three calls.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * threads or processes' graphs) race, and the array keeps the last call's
+ * contents. */
+#define FH_STATIC_SCRATCH_BYTES (64ull << 20)
+fh_status fh_render_fwd_static(const fh_plan *plan, const fh_gaussians *g, const fh_image *out, fh_counters *counters,
+                               hipStream_t stream);
 
 /* Valid launch shapes for this plan: writes up to `max` settings into out
  * (host array) and their number into *count (host).  Each differs from

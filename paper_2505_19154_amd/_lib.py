@@ -16,7 +16,8 @@ FH_MAX_VIEWS = 32
 FH_WS_SLOTS = 48
 FH_TILE = 16
 
-FH_OK, FH_E_INVALID, FH_E_UNSUPPORTED, FH_E_HIP, FH_E_CAPACITY = 0, -1, -2, -3, -4
+FH_OK, FH_E_INVALID, FH_E_UNSUPPORTED, FH_E_HIP, FH_E_CAPACITY, FH_E_SCRATCH = 0, -1, -2, -3, -4, -5
+FH_STATIC_SCRATCH_BYTES = 64 << 20
 FH_F32, FH_BF16 = 0, 1
 FH_FORM_F32, FH_FORM_BF16 = 0, 1
 FH_BIN_BOX, FH_BIN_OPACITY = 0, 1
@@ -102,6 +103,7 @@ SIGNATURES = {
     "fh_read_counters": (_i32, [_P(FhPlan), _vp, _P(FhCounters), _vp]),
     "fh_get_buffer": (_i32, [_P(FhPlan), _vp, _i32, _P(_vp), _P(_i64)]),
     "fh_set_kernel_events": (_i32, [_i32, _vp, _vp, _i32]),
+    "fh_render_fwd_static": (_i32, [_P(FhPlan), _P(FhGaussians), _P(FhImage), _vp, _vp]),
     "fh_tuning_candidates": (_i32, [_P(FhPlan), _i32, _P(FhTuning), _i32, _P(_i32)]),
     "fh_autotune": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _P(FhUpstream), _vp, _i32, _P(FhFusion),
                            _P(FhGrads), _i32, _vp]),

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -183,6 +184,42 @@ static void bin_count_impl(const fh_plan* p, void* ws, hipStream_t s) {
     launch_check_capacity(c, p->inst_capacity, s);
     launch_rank_tables(cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<float4>(p, ws, WS_REC), p->n, total,
                        buf<uint32_t>(p, ws, WS_RANK_OF), buf<float4>(p, ws, WS_RREC), s);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of fh_render_fwd_static: the workspace of callers that cannot
+// allocate, one copy per device, held until the process ends.  Host code uses
+// the device address hipGetSymbolAddress gives for the current device, never
+// the array's name.
+static __device__ __align__(256) unsigned char scratch[FH_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES];
+
+// The current device's scratch address (looked up once per device).
+static fh_status static_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FH_E_HIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return FH_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FH_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FH_OK;
+}
+
+__global__ void k_export_counters(const Counters* c, fh_counters* out) {
+    if (threadIdx.x == 0) {
+        out->n_instances = (int64_t)c->n_instances;
+        out->n_visited = (int64_t)c->n_visited;
+        out->n_culled_nonfinite = (int64_t)c->n_culled_nonfinite;
+        out->inst_overflow = (int32_t)c->inst_overflow;
+        out->visit_overflow = (int32_t)c->visit_overflow;
+    }
 }
 
 }  // namespace fh
@@ -640,6 +677,22 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     return launch_status();
 }
 
+fh_status fh_render_fwd_static(const fh_plan* p, const fh_gaussians* g, const fh_image* out, fh_counters* counters,
+                               hipStream_t s) {
+    if (!p || !out || !gaussians_ok(p, g)) return FH_E_INVALID;
+    if (p->inst_capacity <= 0) return FH_E_INVALID;
+    if (p->ws_bytes > (size_t)FH_STATIC_SCRATCH_BYTES) return FH_E_SCRATCH;
+    void* ws = nullptr;
+    fh_status st = static_scratch(&ws);
+    if (st != FH_OK) return st;
+    if ((st = fh_project(p, g, ws, s)) != FH_OK) return st;
+    if ((st = fh_bin_sort(p, ws, s)) != FH_OK) return st;
+    if ((st = fh_render_fwd(p, g, ws, out, s)) != FH_OK) return st;
+    if (counters) hipLaunchKernelGGL(k_export_counters, dim3(1), dim3(64), 0, s, cbuf<Counters>(p, ws, WS_COUNTERS),
+                                     counters);
+    return launch_status();
+}
+
 fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, int32_t max, int32_t* count) {
     if (!p || !out || !count || max < 1) return FH_E_INVALID;
     int n = 0;
@@ -758,6 +811,7 @@ const char* fh_status_string(fh_status s) {
         case FH_E_UNSUPPORTED: return "unsupported configuration";
         case FH_E_HIP: return "HIP runtime or launch error";
         case FH_E_CAPACITY: return "capacity exceeded";
+        case FH_E_SCRATCH: return "the plan's workspace exceeds the static scratch (FH_STATIC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }
