@@ -458,7 +458,8 @@ def extras_leg(W, args, dev):
     kernel bracketed by HIP events on its stream; roofline against the BF16
     MFMA peak with the algorithmic flops 10 D per walked (pixel, position) for
     the gradient launch (phi, x, the running F, y, the running sigma-weighted
-    suffix) and 6 D for the losses.  Training: Adam over the raw parameters,
+    suffix) and 6 D for the losses; the gradient launch also records two floats
+    per (position, pixel) in its forward sweep and reads them back.  Training: Adam over the raw parameters,
     the photometric loss, and one whole training step (render, loss, adjoint,
     densification statistics, Adam) with HBM rooflines for the elementwise
     kernels."""
@@ -471,7 +472,7 @@ def extras_leg(W, args, dev):
     wl, cams, dg = W["wl"], W["cams"], W["dg"]
     K = args.steps
     out = {}
-    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form="bf16", device=dev)
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form="bf16", device=dev, ndfd=True)
     img = r.forward(dg, margin=1.02)
     blends = int(img.n_iter.to(torch.int64).sum().item())
     P = r.n_pixels

@@ -146,7 +146,7 @@ typedef struct {
     int32_t rank_bits, tile_bits;    /* key layout of the instance sort */
     int32_t packed_keys;             /* 1: one u32 key (tile << rank_bits | rank); 0: u32 tile + u32 rank */
     int32_t bin_rule;                /* fh_bin_rule; fh_plan_init sets FH_BIN_BOX, callers may change it */
-    int32_t reserved0;
+    int32_t ndfd;                    /* 1: the workspace holds the NDFD gradient storage (fh_plan_set_ndfd) */
     int64_t inst_capacity;           /* max (Gaussian, tile) instances over all views */
     int64_t visit_capacity;          /* max instances visited by the backward (per-instance partials) */
     int64_t n_pixels, n_tiles;
@@ -186,6 +186,7 @@ typedef struct {
  * features).  ndfd_gt [P,d] BF16; ndfd_a, ndfd_b [P] FP32 (NULL = 0);
  * ndfd_Lgt, ndfd_Lcf [P] FP32 outputs of the same sweep (NULL: not written).
  * Needs BF16 features and d in {32, 64, 96, 128, 256} (FH_E_UNSUPPORTED
+ * otherwise) and a plan with the NDFD storage (fh_plan_set_ndfd; FH_E_INVALID
  * otherwise). */
 typedef struct {
     const float *dC;
@@ -249,6 +250,13 @@ typedef enum {
 fh_status fh_plan_init(fh_plan *plan, int64_t n, int32_t sh_degree, int32_t d, fh_dtype feat_dtype,
                        fh_form form, const fh_camera *cams, int32_t n_views,
                        int64_t inst_capacity, int64_t visit_capacity);
+
+/* Add (enable = 1) or drop (0) the workspace storage of the NDFD gradient
+ * (the ndfd_* fields of fh_upstream in fh_render_bwd): two floats per visited
+ * (position, pixel) and the per-half-tile partials, 2 KB + 64 B per unit of
+ * visit_capacity.  Recomputes the workspace layout (ws_bytes); set it before
+ * allocating the workspace.  fh_ndfd_losses needs no storage. */
+fh_status fh_plan_set_ndfd(fh_plan *plan, int32_t enable);
 
 /* Project every (view, Gaussian) (Algorithm 2: Homogenization and
  * 2DScreenGaussians; the screen-space Gaussian of Section 3.1).  Writes the

@@ -46,7 +46,7 @@ class FhTuning(ctypes.Structure):
 class FhPlan(ctypes.Structure):
     _fields_ = [("n", _i64), ("n_views", _i32), ("d", _i32), ("sh_degree", _i32), ("feat_dtype", _i32),
                 ("form", _i32), ("rank_bits", _i32), ("tile_bits", _i32), ("packed_keys", _i32),
-                ("bin_rule", _i32), ("reserved0", _i32), ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
+                ("bin_rule", _i32), ("ndfd", _i32), ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
                 ("cams", FhCamera * FH_MAX_VIEWS), ("pix_off", _i64 * (FH_MAX_VIEWS + 1)),
                 ("tile_off", _i64 * (FH_MAX_VIEWS + 1)), ("tiles_x", _i32 * FH_MAX_VIEWS),
                 ("tiles_y", _i32 * FH_MAX_VIEWS), ("tuning", FhTuning), ("n_ws", _i32), ("off", _sz * FH_WS_SLOTS),
@@ -90,6 +90,7 @@ class FhDensifyConfig(ctypes.Structure):
 _P = ctypes.POINTER
 SIGNATURES = {
     "fh_plan_init": (_i32, [_P(FhPlan), _i64, _i32, _i32, _i32, _i32, _P(FhCamera), _i32, _i64, _i64]),
+    "fh_plan_set_ndfd": (_i32, [_P(FhPlan), _i32]),
     "fh_project": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _vp]),
     "fh_bin_count": (_i32, [_P(FhPlan), _vp, _vp]),
     "fh_bin_sort": (_i32, [_P(FhPlan), _vp, _vp]),

@@ -228,6 +228,58 @@ using namespace fh;
 
 extern "C" {
 
+// Sizes and offsets of the workspace sub-buffers of a plan whose sizes and
+// capacities are set.
+static void plan_layout(fh_plan* plan) {
+    const int64_t n = plan->n, total = (int64_t)n * plan->n_views, tiles = plan->n_tiles;
+    const int64_t inst_capacity = plan->inst_capacity, visit_capacity = plan->visit_capacity;
+    const int32_t n_views = plan->n_views, d = plan->d;
+    size_t sz[WS_COUNT];
+    memset(sz, 0, sizeof(sz));
+    const size_t u4 = sizeof(uint32_t);
+    sz[WS_COUNTERS] = 256;
+    sz[WS_REC] = (size_t)total * 3 * 16;
+    sz[WS_DEPTH_KEY] = (size_t)total * u4;
+    sz[WS_RECT] = (size_t)total * 16;
+    sz[WS_ORDER] = sz[WS_ORDER_TMP] = sz[WS_DKEY_TMP] = sz[WS_DKEY_TMP2] = (size_t)total * u4;
+    sz[WS_INST_OFF] = (size_t)(total + 1) * u4;
+    const size_t hist_depth = radix_hist_u32(n_views, n);
+    const size_t hist_inst = radix_hist_u32(1, inst_capacity);
+    const size_t hist_visit = radix_hist_u32(1, visit_capacity);
+    const size_t hist = std::max(std::max(hist_depth, hist_inst), hist_visit);
+    sz[WS_HIST] = hist * u4;
+    sz[WS_SCAN_TMP] = scan_scratch_u32(std::max<int64_t>({(int64_t)hist, total + 1, tiles + 1})) * u4;
+    sz[WS_RANGES] = (size_t)tiles * 2 * u4;
+    sz[WS_TILE_NITER] = (size_t)tiles * u4;
+    sz[WS_TILE_VOFF] = (size_t)(tiles + 1) * u4;
+    sz[WS_GRAD2D] = (size_t)total * 12 * sizeof(float);
+    sz[WS_RANK_OF] = (size_t)total * u4;
+    sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
+    sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
+    sz[WS_VSEG] = (size_t)total * 2 * u4;
+    sz[WS_LONG] = (size_t)(total + 3 * n) * u4;
+    sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
+    sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
+    sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
+    sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
+    sz[WS_VGID] = (size_t)visit_capacity * u4;
+    sz[WS_RREC] = (size_t)total * 3 * 16;
+    sz[WS_UNIT_OWNER] = (size_t)fuse_unit_capacity(visit_capacity) * u4;
+    sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
+    // NDFD gradient storage (fh_plan_set_ndfd): per-part partials and the
+    // forward sweep's (sigma, prefix term) of every visited (position, pixel)
+    sz[WS_PART_NDFD] = plan->ndfd ? (size_t)visit_capacity * 2 * 8 * sizeof(float) : 0;
+    sz[WS_NDFD_SC] = plan->ndfd ? (size_t)visit_capacity * TILE_PIX * 2 * sizeof(float) : 0;
+    static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
+    size_t off = 0;
+    plan->n_ws = WS_COUNT;
+    for (int i = 0; i < WS_COUNT; ++i) {
+        plan->off[i] = off;
+        off += (sz[i] + 255) & ~(size_t)255;
+    }
+    plan->ws_bytes = off;
+}
+
 fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, fh_dtype feat_dtype, fh_form form,
                        const fh_camera* cams, int32_t n_views, int64_t inst_capacity, int64_t visit_capacity) {
     if (!plan || !cams || n < 0 || d < 0 || n_views < 1 || inst_capacity < 0 || visit_capacity < 0)
@@ -272,47 +324,14 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     plan->packed_keys = (plan->rank_bits + plan->tile_bits) <= 32 ? 1 : 0;
     plan->tuning = default_tuning(d, form, feat_dtype);
 
-    size_t sz[WS_COUNT];
-    memset(sz, 0, sizeof(sz));
-    const size_t u4 = sizeof(uint32_t);
-    sz[WS_COUNTERS] = 256;
-    sz[WS_REC] = (size_t)total * 3 * 16;
-    sz[WS_DEPTH_KEY] = (size_t)total * u4;
-    sz[WS_RECT] = (size_t)total * 16;
-    sz[WS_ORDER] = sz[WS_ORDER_TMP] = sz[WS_DKEY_TMP] = sz[WS_DKEY_TMP2] = (size_t)total * u4;
-    sz[WS_INST_OFF] = (size_t)(total + 1) * u4;
-    const size_t hist_depth = radix_hist_u32(n_views, n);
-    const size_t hist_inst = radix_hist_u32(1, inst_capacity);
-    const size_t hist_visit = radix_hist_u32(1, visit_capacity);
-    const size_t hist = std::max(std::max(hist_depth, hist_inst), hist_visit);
-    sz[WS_HIST] = hist * u4;
-    sz[WS_SCAN_TMP] = scan_scratch_u32(std::max<int64_t>({(int64_t)hist, total + 1, tiles + 1})) * u4;
-    sz[WS_RANGES] = (size_t)tiles * 2 * u4;
-    sz[WS_TILE_NITER] = (size_t)tiles * u4;
-    sz[WS_TILE_VOFF] = (size_t)(tiles + 1) * u4;
-    sz[WS_GRAD2D] = (size_t)total * 12 * sizeof(float);
-    sz[WS_RANK_OF] = (size_t)total * u4;
-    sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
-    sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
-    sz[WS_VSEG] = (size_t)total * 2 * u4;
-    sz[WS_LONG] = (size_t)(total + 3 * n) * u4;
-    sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
-    sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
-    sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
-    sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
-    sz[WS_VGID] = (size_t)visit_capacity * u4;
-    sz[WS_RREC] = (size_t)total * 3 * 16;
-    sz[WS_UNIT_OWNER] = (size_t)fuse_unit_capacity(visit_capacity) * u4;
-    sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
-    sz[WS_PART_NDFD] = (size_t)visit_capacity * 4 * 8 * sizeof(float);
-    static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
-    size_t off = 0;
-    plan->n_ws = WS_COUNT;
-    for (int i = 0; i < WS_COUNT; ++i) {
-        plan->off[i] = off;
-        off += (sz[i] + 255) & ~(size_t)255;
-    }
-    plan->ws_bytes = off;
+    plan_layout(plan);
+    return FH_OK;
+}
+
+fh_status fh_plan_set_ndfd(fh_plan* plan, int32_t enable) {
+    if (!plan) return FH_E_INVALID;
+    plan->ndfd = enable ? 1 : 0;
+    plan_layout(plan);
     return FH_OK;
 }
 
@@ -548,6 +567,7 @@ static NdfdArgs ndfd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     n.kk = 20.0f;
     n.Lgt = n.Lcf = nullptr;
     n.part = buf<float>(p, ws, WS_PART_NDFD);
+    n.sc = buf<float2>(p, ws, WS_NDFD_SC);
     return n;
 }
 
@@ -567,6 +587,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
     const bool ndfd = up->ndfd_gt != nullptr;
     if (ndfd && !ndfd_ok(p)) return FH_E_UNSUPPORTED;
+    if (ndfd && !p->ndfd) return FH_E_INVALID;   // the plan holds no NDFD gradient storage
     BwdArgs a;
     fill_bwd_args(p, g, ws, fwd, a);
     a.dC = up->dC;
@@ -591,7 +612,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
         prof_begin(FH_K_NDFD, s);
         launch_ndfd(n, vt, (int)p->n_tiles, true, s);
         prof_end(FH_K_NDFD, s);
-        launch_ndfd_combine(n.part, buf<float>(p, ws, WS_PART_GEOM), n.counters, p->visit_capacity, p->d, s);
+        launch_ndfd_combine(n.part, buf<float>(p, ws, WS_PART_GEOM), n.counters, p->visit_capacity, s);
     }
     ReduceArgs r;
     fill_reduce_args(p, ws, r);

@@ -60,7 +60,8 @@ enum WsBuf {
     WS_RREC,           // float4 [V*N*3] screen records in depth-rank order
     WS_UNIT_OWNER,     // u32 [unit_cap] long-fusion slot of each unit
     WS_UPART,          // float [unit_cap * (2 d + 2)] compensated partial sums of each unit
-    WS_PART_NDFD,      // float [visit_cap * 4 * 8] NDFD screen-space partials of the tile's parts
+    WS_PART_NDFD,      // float [visit_cap * 2 * 8] NDFD screen-space partials of the two half-tiles (plan.ndfd)
+    WS_NDFD_SC,        // float2 [visit_cap * 256] NDFD (sigma, prefix term) per visited (position, pixel) (plan.ndfd)
     WS_COUNT
 };
 

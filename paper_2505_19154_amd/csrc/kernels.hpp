@@ -168,11 +168,12 @@ struct NdfdArgs {
     float lam, kk;              // sigmoid threshold and slope
     float* Lgt;                 // [P] (nullable)
     float* Lcf;                 // [P] (nullable)
-    float* part;                // [visits][4 parts][8] screen-space partials (gradient)
+    float* part;                // [visits][2 halves][8] screen-space partials (gradient)
+    float2* sc;                 // [visits][256 pixels] (sigma, prefix term) of the forward sweep (gradient)
 };
 bool ndfd_supported(int d);
 void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s);
-void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int d, hipStream_t s);
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
                           const void* feat_in, void* feat_out, int bf16, hipStream_t s);
 

@@ -6,8 +6,9 @@
 //   L_cf  = sum_i sigma_i w_i (W_{i-1} - x_i),  x_i = F_{i-1} . fh_i,
 //   W_{i-1} = sum_{j<i} w_j,  F_{i-1} = sum_{j<i} w_j fh_j,
 // and, for a per-pixel loss a L_gt + b L_cf, the derivative with respect to
-// w_k (Appendix A.2, reversed form: the prefix sums from the recorded totals
-// W_N, F_N minus the suffixes a back-to-front walk accumulates)
+// w_k (Appendix A.2; the prefix part sigma_k (W_{k-1} - x_k) and sigma_k are
+// recorded per (position, pixel) by the front-to-back sweep, the suffix part
+// is accumulated by a back-to-front sweep)
 //   h_k = a sigma_k + b (sigma_k (W_{k-1} - x_k) + A_k - y_k),
 //   A_k = sum_{i>k} sigma_i w_i,  y_k = sum_{i>k} sigma_i w_i fh_i . fh_k,
 // which joins the adjoint through w: dL/dalpha_k = T_k h_k - (sum_{i>k} w_i
@@ -21,7 +22,8 @@
 //   x^T, y^T       = Feat . Q^T, Feat . R^T               (Q = F, R = the sigma-weighted
 //                                                          suffix; FP32 accumulators fed
 //                                                          back as BF16 hi + lo)
-//   Q^T, R^T      += Feat^T[D x k] . (w / |f|)^T[k x px] (weights split hi + lo)
+//   Q^T, R^T      += Feat^T[D x k] . (w / |f|)^T[k x px] (weights split hi + lo;
+//                                                          sigma w / |f| for R)
 //   within chunk  : Gh[k x j] . W^T[j x px]               (Gh = the chunk's unit Gram
 //                                                          matrix, masked, hi + lo)
 // Accumulator layout and operand layout agree up to a permutation of the
@@ -32,14 +34,15 @@
 // the positions 4 q + r and 16 + 4 q + r of the chunk, which are both the rows
 // the contractions return to it and the k-slots of its weight operand.
 //
-// Work mapping: 16 / ROWS workgroups per tile, each ROWS pixel rows (64 ROWS
-// threads, wave w = pixel row); pass 1 walks the tile's visited list front to
-// back (losses; F_N stays in the Q registers), pass 2 (gradient) back to
-// front.  Each part of the tile writes its own per-instance screen-space
-// partial (u, v, A, B, C, sum dL/dpower); a second kernel adds the parts into
-// the gradient kernel's partials in a fixed order.  With two running vectors
-// of D = 128 or 256 channels per pixel the gradient takes 4-row workgroups: one
-// wave per SIMD, whose 512 registers hold the accumulators without spilling.
+// Work mapping: two workgroups per tile (pixel rows 0-7 and 8-15), 512
+// threads, wave w = pixel row; pass 1 walks the tile's visited list front to
+// back (losses, with the running F in the Q registers; for the gradient it
+// records sigma_k and the prefix term of every (position, pixel)), pass 2
+// back to front with the suffix R in registers: one D-channel running vector
+// per pixel at a time, so two waves per SIMD.  Each half writes its own
+// per-instance screen-space partial (u, v, A, B, C, sum dL/dpower); a second
+// kernel adds both halves into the gradient kernel's partials in a fixed
+// order.
 #include "kernels.hpp"
 
 namespace fh {
@@ -53,9 +56,7 @@ constexpr int NSK = NK + 3;                  // padded per-pixel stride of dL/dp
 constexpr int NRG = 4;                       // record padding group (lane rows read records 4 apart)
 constexpr int NRSLOTS = 3 * NK + NK / NRG;
 constexpr int NDFD_PART = 8;                 // floats per (visit, part) partial (6 used)
-constexpr int NDFD_PARTS = 4;                // parts per visit in the partial array (16 / ROWS used)
-// rows per workgroup of the gradient walk
-constexpr int ndfd_grad_rows(int d) { return d >= 128 ? 4 : 8; }
+constexpr int NDFD_PARTS = 2;                // halves per visit in the partial array
 
 __device__ __forceinline__ bf16x8 bf16x8_of(uint2 lo, uint2 hi) {
     return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
@@ -70,10 +71,10 @@ __device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
     }
 }
 
-template <int D, bool GRAD, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
+template <int D, bool GRAD>
+__global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
+    constexpr int ROWS = 8;                   // pixel rows (waves) per workgroup
     constexpr int NT = 64 * ROWS;             // threads
-    static_assert(ROWS == 4 || ROWS == 8, "four waves at least: they compute the Gram blocks");
     constexpr int NS = D / 32;                // 32-channel slabs
     constexpr int NB = D / 16;                // 16-channel accumulator blocks
     constexpr int DP = D + 8;                 // row stride (bf16) of the feature tile
@@ -155,13 +156,15 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
             }
             lds_put_rec<NRG>(srec, k, r);
         }
+        // item = (position k, 8-channel group dg), k fastest: a wave's 2-byte
+        // stores of the transposed tile then fill consecutive bank slots
         uint4 raw[NI];
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
             const int idx = threadIdx.x + NT * it;
             raw[it] = make_uint4(0u, 0u, 0u, 0u);
             if (idx < ITEMS) {
-                const int k = idx / (D / 8), dg = idx % (D / 8);
+                const int k = idx % NK, dg = idx / NK;
                 if (k < cnt) {
                     const uint32_t g = a.vgid[(int64_t)voff + cs + k];
                     raw[it] = *reinterpret_cast<const uint4*>(a.feat + (int64_t)g * D + dg * 8);
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
         for (int it = 0; it < NI; ++it) {
             const int idx = threadIdx.x + NT * it;
             if (idx < ITEMS) {
-                const int k = idx / (D / 8), dg = idx % (D / 8);
+                const int k = idx % NK, dg = idx / NK;
                 *reinterpret_cast<uint4*>(&f16[k * DP + dg * 8]) = raw[it];
                 const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw[it]);
 #pragma unroll
@@ -209,20 +212,21 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
             for (int r = 0; r < 4; ++r) sG[(16 * jb + 4 * q + r) * (NK + 1) + 16 * kb + xi] = acc[r];
         }
     };
-    // unit Gram operands: row k, slot 8 g + m <-> position j(g, m), masked by
-    // mask 0: j < k, 1: j >= k, 2: j > k; and 1 / |f_k| into sinv
-    auto build_masks = [&](int m0, int m1) {
+    // 1 / |f_k| of the chunk's positions from the Gram diagonal
+    auto norms = [&]() {
         if ((int)threadIdx.x < NK) {
             const float gkk = sG[threadIdx.x * (NK + 2)];
             sinv[threadIdx.x] = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
         }
+    };
+    // unit Gram operands: row k, slot 8 g + m <-> position j(g, m), masked by
+    // mask 0: j < k, 1: j >= k, 2: j > k (after norms)
+    auto build_masks = [&](int m0, int m1) {
         uint16_t* a16 = reinterpret_cast<uint16_t*>(sA);
         for (int e = threadIdx.x; e < NK * NK; e += NT) {
             const int k = e / NK, sl = e % NK, g = sl >> 3, m = sl & 7;
             const int j = m < 4 ? 4 * g + m : 16 + 4 * g + (m - 4);
-            const float gjj = sG[j * (NK + 2)], gkk = sG[k * (NK + 2)];
-            const float ij = gjj > 0.0f ? 1.0f / sqrtf(gjj) : 0.0f, ik = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
-            const float gh = (sG[j * (NK + 1) + k] * ij) * ik;
+            const float gh = (sG[j * (NK + 1) + k] * sinv[j]) * sinv[k];
             for (int mk = m0; mk <= m1; ++mk) {
                 const bool keep = mk == 0 ? j < k : (mk == 1 ? j >= k : j > k);
                 const float val = keep ? gh : 0.0f;
@@ -279,12 +283,15 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
                 ph[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(featA(16 * kb + xi, s), gto[s], ph[kb], 0, 0, 0);
         }
     };
+    // sigma = 1 / (1 + e^{k (phi - lambda)}) by the hardware exp2 and
+    // reciprocal (about one ulp each: far inside sigma's companion)
+    const float LOG2E = 1.4426950408889634f;
     auto sigma_of = [&](float phr, int k) {
         const float phi = (phr * sinv[k]) * ig;
-        return 1.0f / (1.0f + expf(a.kk * (phi - a.lam)));
+        return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f((a.kk * (phi - a.lam)) * LOG2E));
     };
 
-    f32x4 Q[NB];   // pass 1: F = sum w fh (running); pass 2: F_{end of chunk} (decremented)
+    f32x4 Q[NB];   // pass 1: F = sum w fh (running)
 #pragma unroll
     for (int mb = 0; mb < NB; ++mb) Q[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -332,6 +339,8 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
             }
         }
         __syncthreads();
+        norms();
+        __syncthreads();
         build_masks(0, 0);
         __syncthreads();
         // within-chunk part of x, and the accumulators' part
@@ -352,9 +361,14 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
                 const float sg = sigma_of(ph[kb][r], k);
                 const float xk = xa[kb][r] * ik + xw[kb][r];
                 const float wk = wv[kb][r];
+                const float ck = sg * (Wp[kb][r] - xk);     // sigma_k (W_{k-1} - x_k)
                 lgt = __builtin_fmaf(wk, sg, lgt);
-                lcf = __builtin_fmaf(sg * wk, Wp[kb][r] - xk, lcf);
+                lcf = __builtin_fmaf(ck, wk, lcf);
                 wsc[4 * kb + r] = wk * ik;
+                // (the gradient sweep reads sigma_k and the prefix term back)
+                if (GRAD && k < cnt)
+                    a.sc[((int64_t)voff + cs + k) * TILE_PIX + ry * TILE + xi] =
+                        inside ? make_float2(sg, ck) : make_float2(0.0f, 0.0f);
             }
         bf16x8 vh, vl;
         split8(wsc, vh, vl);
@@ -370,12 +384,15 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
     if constexpr (!GRAD) return;
 
     // ---- pass 2: back to front, the gradient ---------------------------------
-    const float WN = Wacc;
+    // sigma_k and the prefix term c_k = sigma_k (W_{k-1} - x_k) come back from
+    // pass 1; the back-to-front walk adds the suffix terms:
+    //   h_k = a sigma_k + b (c_k + A_k - y_k)
     f32x4 R[NB];
 #pragma unroll
     for (int mb = 0; mb < NB; ++mb) R[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
     T = inside ? a.T_final[p] : 1.0f;
-    float Wsuf = 0.0f, Asuf = 0.0f, Ssuf = 0.0f;
+    float Asuf = 0.0f, Ssuf = 0.0f;
+    __syncthreads();   // (pass 1's stores of sc are read back by the same lanes)
     for (int ce = (int)nt; ce > 0; ce -= NK) {
         const int cs = ce - NK > 0 ? ce - NK : 0;
         const int cnt = ce - cs;
@@ -383,10 +400,18 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
         stage(cs, cnt);
         __syncthreads();
         gram();
-        f32x4 ph[2];
-        phi_raw(ph);
-        float al[2][4], iv[2][4], wv[2][4], Tk[2][4];
+        float al[2][4], iv[2][4], wv[2][4], Tk[2][4], sg[2][4], ck[2][4];
         bool on[2][4];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * kb + 4 * q + r;
+                float2 v2 = make_float2(0.0f, 0.0f);
+                if (k < cnt && inside) v2 = a.sc[((int64_t)voff + cs + k) * TILE_PIX + ry * TILE + xi];
+                sg[kb][r] = v2.x;
+                ck[kb][r] = v2.y;
+            }
 #pragma unroll
         for (int kb = 1; kb >= 0; --kb) {
             float P = 1.0f, trel = 1.0f;
@@ -416,66 +441,48 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
             }
         }
         __syncthreads();
-        build_masks(1, 2);
+        norms();
         __syncthreads();
-        float sg[2][4];
-        float sw8[8], wsc[8], swsc[8];
+        build_masks(2, 2);
+        __syncthreads();
+        float sw8[8], swsc[8];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = 16 * kb + 4 * q + r;
-                sg[kb][r] = sigma_of(ph[kb][r], k);
                 sw8[4 * kb + r] = sg[kb][r] * wv[kb][r];
-                wsc[4 * kb + r] = wv[kb][r] * sinv[k];
                 swsc[4 * kb + r] = sw8[4 * kb + r] * sinv[k];
             }
-        // x_k = F_end . fh_k - sum_{j >= k, j in chunk} w_j fh_j . fh_k
         // y_k = R . fh_k + sum_{i > k, i in chunk} sigma_i w_i fh_i . fh_k
-        const float wflat[8] = {wv[0][0], wv[0][1], wv[0][2], wv[0][3], wv[1][0], wv[1][1], wv[1][2], wv[1][3]};
-        bf16x8 wh, wl, sh, sl;
-        split8(wflat, wh, wl);
+        bf16x8 sh, sl;
         split8(sw8, sh, sl);
-        f32x4 xw[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
         f32x4 yw[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-        masked(1, wh, wl, xw);
         masked(2, sh, sl, yw);
-        f32x4 xa[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
         f32x4 ya[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-        contract_acc(Q, xa);
         contract_acc(R, ya);
-        // suffix sums over the chunk's positions (index order kb, q, r):
-        // inclusive of w (for W_{k-1} = W_N - sum_{j >= k} w_j), exclusive of
-        // sigma w (A_k)
-        float lw[2], ls[2];
+        // A_k = sum_{i > k} sigma_i w_i: suffix over the chunk's positions
+        // (index order kb, q, r) plus the later chunks'
+        float ls[2];
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            lw[kb] = ((wv[kb][3] + wv[kb][2]) + wv[kb][1]) + wv[kb][0];
+        for (int kb = 0; kb < 2; ++kb)
             ls[kb] = ((sw8[4 * kb + 3] + sw8[4 * kb + 2]) + sw8[4 * kb + 1]) + sw8[4 * kb];
-        }
         float hk[2][4];
-        float baseW = Wsuf, baseA = Asuf;
+        float baseA = Asuf;
 #pragma unroll
         for (int kb = 1; kb >= 0; --kb) {
-            const Rows4 LW = rows4(lw[kb]), LS = rows4(ls[kb]);
-            const float aw3 = 0.0f, aw2 = LW.r3, aw1 = LW.r3 + LW.r2, aw0 = (LW.r3 + LW.r2) + LW.r1;
+            const Rows4 LS = rows4(ls[kb]);
             const float as3 = 0.0f, as2 = LS.r3, as1 = LS.r3 + LS.r2, as0 = (LS.r3 + LS.r2) + LS.r1;
-            float cw = baseW + (q == 3 ? aw3 : (q == 2 ? aw2 : (q == 1 ? aw1 : aw0)));
             float cs2 = baseA + (q == 3 ? as3 : (q == 2 ? as2 : (q == 1 ? as1 : as0)));
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
-                cw += wv[kb][r];                              // sum_{j >= k} w_j
-                const float Wprev = WN - cw;
-                const float xk = xa[kb][r] * sinv[k] - xw[kb][r];
                 const float yk = ya[kb][r] * sinv[k] + yw[kb][r];
-                hk[kb][r] = ca * sg[kb][r] + cb * (sg[kb][r] * (Wprev - xk) + cs2 - yk);
+                hk[kb][r] = ca * sg[kb][r] + cb * ((ck[kb][r] + cs2) - yk);
                 cs2 += sw8[4 * kb + r];                       // A_{k-1} = A_k + sigma_k w_k
             }
-            baseW += aw0 + LW.r0;
             baseA += as0 + LS.r0;
         }
-        Wsuf = baseW;
         Asuf = baseA;
         // adjoint through w: dL/dalpha_k = T_k h_k - S_k / (1 - alpha_k),
         // S_k = sum_{i > k} w_i h_i
@@ -501,14 +508,9 @@ __global__ __launch_bounds__(64 * ROWS) void k_ndfd(NdfdArgs a, ViewTable vt) {
             baseS += ah0 + LH.r0;
         }
         Ssuf = baseS;
-        // the suffix accumulators: F_end -= sum w fh, R += sum sigma w fh
+        // the suffix accumulator: R += sum sigma w fh
         {
-            float nw[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) nw[m] = -wsc[m];
             bf16x8 ah, alo;
-            split8(nw, ah, alo);
-            accumulate(Q, ah, alo);
             split8(swsc, ah, alo);
             accumulate(R, ah, alo);
         }
@@ -575,19 +577,15 @@ __global__ __launch_bounds__(256) void k_ndfd_combine(const float* __restrict__ 
     part_geom[vi * 12 + m] += s;
 }
 
-template <int D, bool GRAD, int ROWS>
-static void launch_ndfd_shape(const NdfdArgs& a, const ViewTable& vt, int n_tiles, hipStream_t s) {
-    const size_t lds = sizeof(__bf16) * ((size_t)NK * (D + 8) + (size_t)D * NJP + 6 * (size_t)NK * NJP) +
-                       sizeof(float) * ((size_t)NK * (NK + 1) + NK + (size_t)TILE * ROWS * NSK + (size_t)ROWS * 6 * NK);
-    hipLaunchKernelGGL((k_ndfd<D, GRAD, ROWS>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
-}
-
 template <int D>
 static void launch_ndfd_d(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
+    constexpr int ROWS = 8;
+    const size_t lds = sizeof(__bf16) * ((size_t)NK * (D + 8) + (size_t)D * NJP + 6 * (size_t)NK * NJP) +
+                       sizeof(float) * ((size_t)NK * (NK + 1) + NK + (size_t)TILE * ROWS * NSK + (size_t)ROWS * 6 * NK);
     if (grad)
-        launch_ndfd_shape<D, true, ndfd_grad_rows(D)>(a, vt, n_tiles, s);
+        hipLaunchKernelGGL((k_ndfd<D, true>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
     else
-        launch_ndfd_shape<D, false, 8>(a, vt, n_tiles, s);
+        hipLaunchKernelGGL((k_ndfd<D, false>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
 }
 
 bool ndfd_supported(int d) { return d == 32 || d == 64 || d == 96 || d == 128 || d == 256; }
@@ -603,11 +601,11 @@ void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad,
     }
 }
 
-void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int d, hipStream_t s) {
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, hipStream_t s) {
     const int64_t n = cap * 6;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_ndfd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, part_geom, c, cap,
-                       TILE / ndfd_grad_rows(d));
+                       NDFD_PARTS);
 }
 
 }  // namespace fh

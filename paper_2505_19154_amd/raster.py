@@ -24,7 +24,7 @@ _WS = {name: i for i, name in enumerate(
     ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
      "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
      "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
-     "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd"])}
+     "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd", "ndfd_sc"])}
 
 
 def _ptr(t):
@@ -140,7 +140,8 @@ class Rasterizer:
     """Plan + workspace for one batch of cameras and one Gaussian set size."""
 
     def __init__(self, cams, n: int, sh_degree: int, d: int, feat_dtype: str = "f32", form: str = "f32",
-                 device="cuda", inst_capacity: int = 0, visit_capacity: int = 0, bin_rule: str = "box"):
+                 device="cuda", inst_capacity: int = 0, visit_capacity: int = 0, bin_rule: str = "box",
+                 ndfd: bool = False):
         self.lib = L.load()
         self.cams = list(cams)
         self.cam_arr = (L.FhCamera * len(self.cams))(*[camera_struct(c) for c in self.cams])
@@ -150,6 +151,7 @@ class Rasterizer:
         if bin_rule not in ("box", "opacity"):
             raise L.FhError(f"bin_rule must be 'box' or 'opacity', not {bin_rule!r}")
         self.bin_rule = L.FH_BIN_OPACITY if bin_rule == "opacity" else L.FH_BIN_BOX
+        self.ndfd = bool(ndfd)         # workspace storage for the NDFD gradient
         self.device = torch.device(device)
         self.plan = None
         self.ws = None
@@ -168,6 +170,8 @@ class Rasterizer:
         if self.tuning is not None:
             plan.tuning = self.tuning
         plan.bin_rule = self.bin_rule
+        if self.ndfd:
+            L.check(self.lib.fh_plan_set_ndfd(ctypes.byref(plan), 1), "fh_plan_set_ndfd")
         self.plan = plan
         self.ws = torch.empty(max(int(plan.ws_bytes), 256), dtype=torch.uint8, device=self.device)
         self.generation += 1
@@ -308,6 +312,8 @@ class Rasterizer:
         gs, im = g.struct(), fwd.struct()
         up = L.FhUpstream(_ptr(dC), _ptr(dF), _ptr(dT))
         if ndfd is not None:
+            if not self.ndfd:
+                raise L.FhError("the NDFD gradient needs a Rasterizer made with ndfd=True (workspace storage)")
             self._check_ndfd(g, ndfd["gt"])
             for nm in ("a", "b", "Lgt", "Lcf"):
                 if ndfd.get(nm) is not None:

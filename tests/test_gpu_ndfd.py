@@ -57,7 +57,7 @@ def _scene(name, with_colour=False):
 def _gpu(g, cams, vts, form):
     from paper_2505_19154_amd.raster import Rasterizer
     dg = U.device_gaussians(g)
-    r = Rasterizer(cams, dg.n, 1, g["d"], feat_dtype="bf16", form=form)
+    r = Rasterizer(cams, dg.n, 1, g["d"], feat_dtype="bf16", form=form, ndfd=True)
     img = r.forward(dg)
     cat = lambda k: torch.from_numpy(np.ascontiguousarray(np.concatenate([v[k] for v in vts]), np.float32)).cuda()
     gt = torch.from_numpy(np.concatenate([v["gt_bits"] for v in vts]).view(np.int16)).cuda().view(torch.bfloat16)
@@ -133,3 +133,19 @@ def test_ndfd_rejects_fp32_features_and_bad_maps():
         rb.ndfd_losses(dgb, imgb, gt[:-1])               # wrong shape
     with pytest.raises(FhError):
         rb.ndfd_losses(dgb, imgb, gt.float())            # not BF16
+    # the gradient needs a plan with the NDFD storage; the losses alone do not
+    Lgt, Lcf = rb.ndfd_losses(dgb, imgb, gt)
+    dC = torch.zeros(rb.n_pixels, 3, device="cuda")
+    with pytest.raises(FhError):
+        rb.render_bwd(dgb, imgb, dC, ndfd=dict(gt=gt))
+    from paper_2505_19154_amd import _lib as L
+    import ctypes
+    from paper_2505_19154_amd.raster import _ptr, _stream
+    gs, im = dgb.struct(), imgb.struct()
+    up = L.FhUpstream(_ptr(dC), None, None)
+    up.ndfd_gt = _ptr(gt)
+    gr = rb.new_grads()
+    grs = L.FhGrads(*[_ptr(gr[k]) for k in ("means", "scales", "quats", "opacity", "sh")])
+    st = rb.lib.fh_render_bwd(ctypes.byref(rb.plan), ctypes.byref(gs), _ptr(rb.ws), ctypes.byref(im), ctypes.byref(up),
+                              None, 0, None, ctypes.byref(grs), _stream())
+    assert st == L.FH_E_INVALID
