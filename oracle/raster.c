@@ -40,10 +40,7 @@
  * features, so gradients flow through w only.  Magnitude companions use
  * |fh_i . fh_j| <= 1, and sigma's companion is sigma + k sigma (1 - sigma)
  * sum_c |fh_i,c fh_gt,c|: the cosine is a sum whose rounding the sigmoid's
- * slope carries into sigma (first order).  In h_k the companion of
- * W_{k-1} - x_k is 4 W_N: the reversed form of the gradient (Appendix A.2)
- * reaches the prefix sums as the recorded totals W_N, F_N minus the suffixes
- * a back-to-front walk accumulates, four terms each at most W_N.  The near-threshold bound (*_amb) does not cover these
+ * slope carries into sigma (first order).  The near-threshold bound (*_amb) does not cover these
  * terms: scenes checked with them have no near-threshold decision.
  *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
@@ -219,9 +216,7 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
         double bf = 0.0;
         for (int64_t c = 0; c < d; ++c) bf += B[c] * fhat(a, g, c);
         sc->h[k] = ca * sc->sig[k] + cb * (sc->cterm[k] + (A - bf));
-        /* (the gradient's companion of W_{k-1} - x_k is 4 W_N: the reversed form
-           evaluates them as the totals W_N, F_N minus back-to-front suffixes) */
-        sc->hm[k] = fabs(ca) * sc->sigm[k] + fabs(cb) * (sc->sigm[k] * 4.0 * W + 2.0 * Am);
+        sc->hm[k] = fabs(ca) * sc->sigm[k] + fabs(cb) * (sc->cmag[k] + 2.0 * Am);
         A += sc->sig[k] * w;
         Am += sc->sigm[k] * w;
         for (int64_t c = 0; c < d; ++c) B[c] += sc->sig[k] * w * fhat(a, g, c);

@@ -148,45 +148,6 @@ def test_sigma_companion_bounds_the_cosine_rounding():
     assert np.all(dcf <= 2.05 * eps * o0["Lcf_mag"] + 1e-18)
 
 
-def test_reversed_form_rounding_needs_the_total_weight_companion():
-    """Why the gradient's companion of W_{k-1} - x_k is 4 W_N: evaluating the
-    reversed form in float32 (totals W_N, F_N minus back-to-front suffixes, as
-    the GPU does) differs from the FP64 forward-indexed h_k by rounding of the
-    totals, which a prefix-sized companion (2 W_{k-1}) cannot bound for the
-    front contributors; 4 W_N does."""
-    worst_new, worst_old = 0.0, 0.0
-    for seed in range(4):
-        f, w, sig = _ray(10 + seed, n=40, d=16)
-        sig[0], sig[1:] = 1.0, 1e-4                       # front sigma 1, the rest tiny
-        n = w.size
-        G = f @ f.T
-        Wp = np.concatenate([[0.0], np.cumsum(w)[:-1]])
-        A = np.array([(sig[k + 1:] * w[k + 1:]).sum() for k in range(n)])
-        ref = np.array([sig[k] * (Wp[k] - (w[:k, None] * f[:k]).sum(0) @ f[k])
-                        + sum(sig[i] * w[i] * (1 - G[i, k]) for i in range(k + 1, n)) for k in range(n)])
-        f32, w32, s32 = f.astype(np.float32), w.astype(np.float32), sig.astype(np.float32)
-        WN, FN = np.float32(0), np.zeros(f.shape[1], np.float32)
-        for k in range(n):
-            WN = np.float32(WN + w32[k])
-            FN = (FN + w32[k] * f32[k]).astype(np.float32)
-        got = np.empty(n)
-        cw, Fs, R, As = np.float32(0), np.zeros_like(FN), np.zeros_like(FN), np.float32(0)
-        for k in range(n - 1, -1, -1):
-            cw = np.float32(cw + w32[k])
-            Fs = (Fs + w32[k] * f32[k]).astype(np.float32)
-            x = np.float32(np.dot((FN - Fs).astype(np.float32), f32[k]))
-            y = np.float32(np.dot(R, f32[k]))
-            got[k] = np.float32(s32[k] * (np.float32(WN - cw) - x) + As - y)
-            R = (R + s32[k] * w32[k] * f32[k]).astype(np.float32)
-            As = np.float32(As + s32[k] * w32[k])
-        err = np.abs(got - ref)
-        new = sig * 4.0 * w.sum() + 2.0 * A
-        old = sig * 2.0 * Wp + 2.0 * A
-        worst_new = max(worst_new, float((err / (1e-5 * new)).max()))
-        worst_old = max(worst_old, float((err / (1e-5 * old)).max()))
-    assert worst_new <= 1.0 and worst_old > 1.0
-
-
 def test_gradient_companion_bounds_the_gradient():
     g, cams, vt = _case(5)
     o = pipeline.run(g, cams, [vt], ndfd=dict(lam=LAM, k=K))
