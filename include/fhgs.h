@@ -129,12 +129,18 @@ typedef struct {
  *   bwd_chunk  Gaussians per back-to-front chunk of the FP32-form adjoint:
  *              16 or 32 (32 needs d <= 512).  The BF16-form adjoint always
  *              takes 32 (the MFMA k).
+ *   schedule   order in which the MFMA walk kernels take the (view, tile)
+ *              work items: 0 tile index order; 1 longest first (tiles sorted
+ *              by their list length for the forward, by their traversal
+ *              length for the adjoint and fusion; ties in index order), so
+ *              that the heaviest tiles of all views start first and the light
+ *              ones fill the tail.
  * fh_plan_init fills defaults; fh_autotune picks the fastest by timing. */
 typedef struct {
     int32_t fwd_slice;
     int32_t bwd_chunk;
     int32_t fwd_rows;
-    int32_t reserved;
+    int32_t schedule;
 } fh_tuning;
 
 /* Host-side description of one batch of views: sizes, capacities and the

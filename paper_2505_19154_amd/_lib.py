@@ -40,7 +40,7 @@ class FhCamera(ctypes.Structure):
 
 
 class FhTuning(ctypes.Structure):
-    _fields_ = [("fwd_slice", _i32), ("bwd_chunk", _i32), ("fwd_rows", _i32), ("reserved", _i32)]
+    _fields_ = [("fwd_slice", _i32), ("bwd_chunk", _i32), ("fwd_rows", _i32), ("schedule", _i32)]
 
 
 class FhPlan(ctypes.Structure):

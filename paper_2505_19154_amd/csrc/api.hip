@@ -149,6 +149,7 @@ static fh_tuning default_tuning(int d, int form, int feat_dtype) {
         }
     }
     t.bwd_chunk = d <= 512 ? 32 : 16;
+    t.schedule = 0;
     return t;
 }
 
@@ -164,7 +165,22 @@ static bool bwd_chunk_ok(int d, int chunk) { return chunk == 16 || (chunk == 32 
 
 static bool tuning_ok(const fh_plan* p) {
     return fwd_shape_ok(p->d, p->form, p->feat_dtype, p->tuning.fwd_slice, p->tuning.fwd_rows) &&
-           bwd_chunk_ok(p->d, p->tuning.bwd_chunk);
+           bwd_chunk_ok(p->d, p->tuning.bwd_chunk) && (p->tuning.schedule == 0 || p->tuning.schedule == 1);
+}
+
+// The work order of the MFMA walk kernels (fh_tuning.schedule): nullptr for
+// tile index order; else the tiles sorted by cost, longest first (a stable
+// sort of 16-bit keys, ties in index order), cost = the list length
+// (by_range) or the traversal length.
+static const uint32_t* tile_schedule(const fh_plan* p, void* ws, bool by_range, hipStream_t s) {
+    if (p->tuning.schedule == 0 || p->n_tiles <= 0) return nullptr;
+    uint32_t* ka = buf<uint32_t>(p, ws, WS_TORDER_KA);
+    launch_tile_cost_keys(by_range ? cbuf<uint32_t>(p, ws, WS_RANGES) : nullptr,
+                          by_range ? nullptr : cbuf<uint32_t>(p, ws, WS_TILE_NITER), p->n_tiles, ka, s);
+    const int passes = radix_sort(ka, nullptr, ka, buf<uint32_t>(p, ws, WS_TORDER_VA), buf<uint32_t>(p, ws, WS_TORDER_KB),
+                                  buf<uint32_t>(p, ws, WS_TORDER_VB), true, 1, p->n_tiles, nullptr, 0, 0, 16,
+                                  buf<uint32_t>(p, ws, WS_HIST), buf<uint32_t>(p, ws, WS_SCAN_TMP), s);
+    return cbuf<uint32_t>(p, ws, (passes % 2) ? WS_TORDER_VB : WS_TORDER_VA);
 }
 
 // depth sort, tiles per rank, their scan, the instance count and the overflow flag
@@ -246,7 +262,8 @@ static void plan_layout(fh_plan* plan) {
     const size_t hist_depth = radix_hist_u32(n_views, n);
     const size_t hist_inst = radix_hist_u32(1, inst_capacity);
     const size_t hist_visit = radix_hist_u32(1, visit_capacity);
-    const size_t hist = std::max(std::max(hist_depth, hist_inst), hist_visit);
+    const size_t hist_tiles = radix_hist_u32(1, tiles);
+    const size_t hist = std::max(std::max(std::max(hist_depth, hist_inst), hist_visit), hist_tiles);
     sz[WS_HIST] = hist * u4;
     sz[WS_SCAN_TMP] = scan_scratch_u32(std::max<int64_t>({(int64_t)hist, total + 1, tiles + 1})) * u4;
     sz[WS_RANGES] = (size_t)tiles * 2 * u4;
@@ -270,6 +287,7 @@ static void plan_layout(fh_plan* plan) {
     // forward sweep's (sigma, prefix term) of every visited (position, pixel)
     sz[WS_PART_NDFD] = plan->ndfd ? (size_t)visit_capacity * 2 * 8 * sizeof(float) : 0;
     sz[WS_NDFD_SC] = plan->ndfd ? (size_t)visit_capacity * TILE_PIX * 2 * sizeof(float) : 0;
+    sz[WS_TORDER_KA] = sz[WS_TORDER_KB] = sz[WS_TORDER_VA] = sz[WS_TORDER_VB] = (size_t)tiles * u4;
     static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
     size_t off = 0;
     plan->n_ws = WS_COUNT;
@@ -440,9 +458,11 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     a.n_iter = out->n_iter;
     uint32_t* tile_niter = buf<uint32_t>(p, ws, WS_TILE_NITER);
     a.tile_niter = tile_niter;
+    a.tile_order = nullptr;
     // several row groups of a tile combine their traversal lengths with atomicMax
     launch_fill_u32(tile_niter, p->n_tiles, 0u, s);
     const ViewTable vt = view_table(*p);
+    if (mfma_forward(p->d, p->form, p->feat_dtype)) a.tile_order = tile_schedule(p, ws, true, s);
     prof_begin(FH_K_RENDER_FWD, s);
     if (mfma_forward(p->d, p->form, p->feat_dtype))
         launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, !a.feat_bf16, s);
@@ -481,17 +501,22 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.vgid = cbuf<uint32_t>(p, ws, WS_VGID);
     a.part_geom = buf<float>(p, ws, WS_PART_GEOM);
     a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
+    a.tile_order = nullptr;
 }
 
 static int visit_sort_passes(const fh_plan* p) { return (p->rank_bits + 7) / 8; }
 
 // The BF16-MFMA backward covers d <= 256; wider features use the FP32-VALU
 // backward with BF16 feature loads.
-static void launch_bwd(const fh_plan* p, const BwdArgs& a, const ViewTable& vt, bool fuse, hipStream_t s) {
-    if (p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d))
+static void launch_bwd(const fh_plan* p, void* ws, const BwdArgs& a0, const ViewTable& vt, bool fuse, hipStream_t s) {
+    if (p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d)) {
+        BwdArgs a = a0;
+        a.tile_order = tile_schedule(p, ws, false, s);
         launch_render_bwd_bf16(a, vt, (int)p->n_tiles, a.dC != nullptr, fuse, s);
-    else
+    } else {
+        const BwdArgs& a = a0;
         launch_render_bwd_f32(a, vt, (int)p->n_tiles, fuse, p->tuning.bwd_chunk, s);
+    }
 }
 
 // Rank, Gaussian and record of every visited instance, in visit order.
@@ -598,7 +623,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
     visit_stage(p, ws, s);
-    launch_bwd(p, a, vt, fuse, s);
+    launch_bwd(p, ws, a, vt, fuse, s);
     prof_end(FH_K_RENDER_BWD, s);
     if (ndfd) {
         // the NDFD terms of the same walk, added to the gradient kernel's partials
@@ -683,7 +708,7 @@ fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, co
     const ViewTable vt = view_table(*p);
     prof_begin(FH_K_RENDER_BWD, s);
     visit_stage(p, ws, s);
-    launch_bwd(p, a, vt, true, s);
+    launch_bwd(p, ws, a, vt, true, s);
     prof_end(FH_K_RENDER_BWD, s);
     ReduceArgs r;
     fill_reduce_args(p, ws, r);
@@ -719,19 +744,30 @@ fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, 
     int n = 0;
     if (which == FH_K_RENDER_FWD && p->d > 0) {
         static const int slices[] = {8, 16, 32, 64, 96, 128, 256};
-        for (int rows : {16, 8})
-            for (int sl : slices)
-                if (fwd_shape_ok(p->d, p->form, p->feat_dtype, sl, rows) && (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
-                    out[n] = p->tuning;
-                    out[n].fwd_slice = sl;
-                    out[n++].fwd_rows = rows;
-                }
+        // (the MFMA forward also takes the two work orders)
+        const int nsched = mfma_forward(p->d, p->form, p->feat_dtype) ? 2 : 1;
+        for (int sc = 0; sc < nsched; ++sc)
+            for (int rows : {16, 8})
+                for (int sl : slices)
+                    if (fwd_shape_ok(p->d, p->form, p->feat_dtype, sl, rows) &&
+                        (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
+                        out[n] = p->tuning;
+                        out[n].fwd_slice = sl;
+                        out[n].fwd_rows = rows;
+                        out[n++].schedule = sc;
+                    }
     } else if (which == FH_K_RENDER_BWD && p->form == FH_FORM_F32) {
         static const int chunks[] = {16, 32};
         for (int ch : chunks)
             if (bwd_chunk_ok(p->d, ch) && n < max) {
                 out[n] = p->tuning;
                 out[n++].bwd_chunk = ch;
+            }
+    } else if (which == FH_K_RENDER_BWD && p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d)) {
+        for (int sc : {0, 1})
+            if (n < max) {
+                out[n] = p->tuning;
+                out[n++].schedule = sc;
             }
     }
     if (n == 0) {
@@ -746,11 +782,11 @@ fh_status fh_autotune(fh_plan* p, const fh_gaussians* g, void* ws, const fh_imag
                       const void* target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* grads,
                       int32_t reps, hipStream_t s) {
     if (!p || !ws || !fwd || reps < 1) return FH_E_INVALID;
-    fh_tuning cand[16];
+    fh_tuning cand[32];
     int32_t nc = 0;
     for (int which : {(int)FH_K_RENDER_FWD, (int)FH_K_RENDER_BWD}) {
         if (which == FH_K_RENDER_BWD && (!up || !grads)) break;
-        fh_status st = fh_tuning_candidates(p, which, cand, 16, &nc);
+        fh_status st = fh_tuning_candidates(p, which, cand, 32, &nc);
         if (st != FH_OK) return st;
         if (nc < 2) continue;
         int best = -1;

@@ -62,6 +62,10 @@ enum WsBuf {
     WS_UPART,          // float [unit_cap * (2 d + 2)] compensated partial sums of each unit
     WS_PART_NDFD,      // float [visit_cap * 2 * 8] NDFD screen-space partials of the two half-tiles (plan.ndfd)
     WS_NDFD_SC,        // float2 [visit_cap * 256] NDFD (sigma, prefix term) per visited (position, pixel) (plan.ndfd)
+    WS_TORDER_KA,      // u32 [tiles] tile schedule: sort keys (ping-pong)
+    WS_TORDER_KB,
+    WS_TORDER_VA,      // u32 [tiles] tile schedule: tile ids (ping-pong; the order ends here)
+    WS_TORDER_VB,
     WS_COUNT
 };
 

@@ -46,6 +46,10 @@ struct DupArgs {
     ViewTable vt;
 };
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// tile schedule keys: 0xFFFF - min(cost, 0xFFFF), cost = the list length
+// (ranges) or the traversal length (tile_niter)
+void launch_tile_cost_keys(const uint32_t* ranges, const uint32_t* tile_niter, int64_t n_tiles, uint32_t* keys,
+                           hipStream_t s);
 void launch_tiles_by_rank(const uint32_t* order, const int4* rect, int64_t n, int64_t total, uint32_t* ntiles,
                           Counters* c, hipStream_t s);
 void launch_check_capacity(Counters* c, int64_t cap, hipStream_t s);
@@ -72,6 +76,7 @@ struct RenderArgs {
     float* T;
     uint32_t* n_iter;
     uint32_t* tile_niter;
+    const uint32_t* tile_order;   // nullable: work item i takes tile tile_order[i]
 };
 struct BwdArgs {
     const float4* rec;
@@ -97,6 +102,7 @@ struct BwdArgs {
     const uint32_t* vgid;      // [visits] staged Gaussians
     float* part_geom;
     float* part_fuse;
+    const uint32_t* tile_order;   // nullable: work item i takes tile tile_order[i]
 };
 struct VisitStageArgs {
     const uint32_t* ranges;

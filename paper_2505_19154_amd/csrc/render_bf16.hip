@@ -62,7 +62,8 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128 && !FS) ? 4 : 1)
     __shared__ __attribute__((aligned(16))) uint8_t sbusy[2][16];   // per wave: a pixel still walking
     if (a.counters->inst_overflow) return;
     constexpr int NG = TILE / ROWS;                      // row groups per tile
-    const int t = blockIdx.x, grp = blockIdx.y % NG, slice = blockIdx.y / NG, d0 = slice * DS;
+    const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const int grp = blockIdx.y % NG, slice = blockIdx.y / NG, d0 = slice * DS;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q = lane >> 4, xi = lane & 15;
     const int v = view_of_tile(vt, t);

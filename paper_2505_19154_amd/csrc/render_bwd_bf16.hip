@@ -98,7 +98,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     __shared__ uint32_t sgb[3][BK];       // those two chunks ahead arrive during this one
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const int t = blockIdx.x;
+    const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     const uint32_t nt = a.tile_niter[t];
     if (nt == 0) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     __shared__ float4 srecb[2][RSLOTS];   // chunk records, double-buffered (the next chunk's fetched ahead)
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
-    const int t = blockIdx.x;
+    const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     const uint32_t nt = a.tile_niter[t];
     if (nt == 0) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;

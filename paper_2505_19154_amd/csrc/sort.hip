@@ -604,6 +604,22 @@ __global__ __launch_bounds__(256) void k_bin_keys(const uint32_t* __restrict__ k
 }
 
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_cost_keys(const uint32_t* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ tile_niter, int64_t n_tiles,
+                                                      uint32_t* __restrict__ keys) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t cost = ranges ? ranges[2 * t + 1] - ranges[2 * t] : tile_niter[t];
+    keys[t] = 0xFFFFu - (cost < 0xFFFFu ? cost : 0xFFFFu);
+}
+
+void launch_tile_cost_keys(const uint32_t* ranges, const uint32_t* tile_niter, int64_t n_tiles, uint32_t* keys,
+                           hipStream_t s) {
+    if (n_tiles <= 0) return;
+    hipLaunchKernelGGL(k_tile_cost_keys, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, ranges, tile_niter,
+                       n_tiles, keys);
+}
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return;
     if (reinterpret_cast<uintptr_t>(p) % 16 == 0) {

@@ -24,7 +24,8 @@ _WS = {name: i for i, name in enumerate(
     ["counters", "rec", "depth_key", "rect", "order", "order_tmp", "dkey_tmp", "dkey_tmp2", "inst_off",
      "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
      "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
-     "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd", "ndfd_sc"])}
+     "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd", "ndfd_sc", "torder_ka", "torder_kb",
+     "torder_va", "torder_vb"])}
 
 
 def _ptr(t):
@@ -394,7 +395,7 @@ class Rasterizer:
         (a JSON file) when it holds this tuning_key, else by timing every
         candidate with fh_autotune (after `forward`, with the step's real
         inputs; outputs are recomputed, fusion goes to a scratch accumulator).
-        Returns the chosen {"fwd_slice", "bwd_chunk", "fwd_rows"}."""
+        Returns the chosen {"fwd_slice", "bwd_chunk", "fwd_rows", "schedule"}."""
         import json
         import os
         key = self.tuning_key()
@@ -403,7 +404,8 @@ class Rasterizer:
             with open(cache) as f:
                 table = json.load(f)
         if key in table:
-            t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]), int(table[key]["fwd_rows"]))
+            t = L.FhTuning(int(table[key]["fwd_slice"]), int(table[key]["bwd_chunk"]), int(table[key]["fwd_rows"]),
+                           int(table[key].get("schedule", 0)))
         else:
             self.generation += 1
             gs, im = g.struct(), img.struct()
@@ -422,30 +424,33 @@ class Rasterizer:
                     "fh_autotune")
             t = self.plan.tuning
             if cache:
-                table[key] = {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows)}
+                table[key] = {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows),
+                              "schedule": int(t.schedule)}
                 os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
                 with open(cache, "w") as f:
                     json.dump(table, f, indent=1, sort_keys=True)
-        self.tuning = L.FhTuning(int(t.fwd_slice), int(t.bwd_chunk), int(t.fwd_rows))
+        self.tuning = L.FhTuning(int(t.fwd_slice), int(t.bwd_chunk), int(t.fwd_rows), int(t.schedule))
         self.plan.tuning = self.tuning
         return self.tuning_dict()
 
     def tuning_dict(self) -> dict:
         t = self.plan.tuning
-        return {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows)}
+        return {"fwd_slice": int(t.fwd_slice), "bwd_chunk": int(t.bwd_chunk), "fwd_rows": int(t.fwd_rows),
+                "schedule": int(t.schedule)}
 
-    def set_tuning(self, fwd_slice: int, bwd_chunk: int, fwd_rows: int = 16) -> None:
+    def set_tuning(self, fwd_slice: int, bwd_chunk: int, fwd_rows: int = 16, schedule: int = 0) -> None:
         """Set the launch shape by hand (validated by the next call)."""
-        self.tuning = L.FhTuning(int(fwd_slice), int(bwd_chunk), int(fwd_rows))
+        self.tuning = L.FhTuning(int(fwd_slice), int(bwd_chunk), int(fwd_rows), int(schedule))
         self.plan.tuning = self.tuning
 
     def tuning_candidates(self, which: int) -> list:
-        """[(fwd_slice, bwd_chunk, fwd_rows), ...] for kernel `which`."""
-        out = (L.FhTuning * 16)()
+        """[(fwd_slice, bwd_chunk, fwd_rows, schedule), ...] for kernel `which`."""
+        out = (L.FhTuning * 32)()
         n = ctypes.c_int32()
-        L.check(self.lib.fh_tuning_candidates(ctypes.byref(self.plan), int(which), out, 16, ctypes.byref(n)),
+        L.check(self.lib.fh_tuning_candidates(ctypes.byref(self.plan), int(which), out, 32, ctypes.byref(n)),
                 "fh_tuning_candidates")
-        return [(int(out[i].fwd_slice), int(out[i].bwd_chunk), int(out[i].fwd_rows)) for i in range(n.value)]
+        return [(int(out[i].fwd_slice), int(out[i].bwd_chunk), int(out[i].fwd_rows), int(out[i].schedule))
+                for i in range(n.value)]
 
     def forward(self, g: Gaussians, margin: float = 1.05) -> Image:
         """prepare + render_fwd, growing the visit capacity until it fits."""

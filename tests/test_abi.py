@@ -107,10 +107,11 @@ def test_tuning_defaults_and_candidates_on_host():
     cams = (_lib.FhCamera * 1)(cam)
 
     def cands(plan, which):
-        out = (_lib.FhTuning * 16)()
+        out = (_lib.FhTuning * 32)()
         n = ctypes.c_int32()
-        assert lib.fh_tuning_candidates(ctypes.byref(plan), which, out, 16, ctypes.byref(n)) == 0
-        return [(out[i].fwd_slice, out[i].bwd_chunk, out[i].fwd_rows) for i in range(n.value)]
+        assert lib.fh_tuning_candidates(ctypes.byref(plan), which, out, 32, ctypes.byref(n)) == 0
+        return [(out[i].fwd_slice, out[i].bwd_chunk, out[i].fwd_rows) + ((out[i].schedule,) if out[i].schedule else ())
+                for i in range(n.value)]
 
     plan = _lib.FhPlan()
     # FP32 form, d = 256, BF16-stored features: the VALU forward's slices 8..64,
@@ -124,18 +125,19 @@ def test_tuning_defaults_and_candidates_on_host():
     # rows of 128 channels)
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 0, 0, cams, 1, 0, 0) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.bwd_chunk, plan.tuning.fwd_rows) == (256, 32, 8)
-    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32, 16), (64, 32, 16), (64, 32, 8), (128, 32, 8),
-                                               (256, 32, 8)]
+    mf = [(32, 32, 16), (64, 32, 16), (64, 32, 8), (128, 32, 8), (256, 32, 8)]
+    # (the MFMA forward in both work orders: tile index order, longest first)
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == mf + [c + (1,) for c in mf]
     assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 16, 8), (256, 32, 8)]
     # BF16 form, d = 256: slices dividing d for 16-row and 8-row workgroups; one backward shape
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 0, 0) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.fwd_rows) == (256, 8)
-    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32, 16), (64, 32, 16), (128, 32, 16), (64, 32, 8),
-                                               (128, 32, 8), (256, 32, 8)]
-    assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 32, 8)]
+    bf = [(32, 32, 16), (64, 32, 16), (128, 32, 16), (64, 32, 8), (128, 32, 8), (256, 32, 8)]
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == bf + [c + (1,) for c in bf]
+    assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 32, 8), (256, 32, 8, 1)]
     # BF16 form, d = 96; FP32 form, d = 16; d = 1024 takes 16-Gaussian chunks
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 96, 1, 1, cams, 1, 0, 0) == 0
-    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32, 16), (96, 32, 16)]
+    assert cands(plan, _lib.FH_K_RENDER_FWD) == [(32, 32, 16), (96, 32, 16), (32, 32, 16, 1), (96, 32, 16, 1)]
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 16, 0, 0, cams, 1, 0, 0) == 0
     assert cands(plan, _lib.FH_K_RENDER_FWD) == [(8, 32, 16), (16, 32, 16)]
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 1024, 0, 0, cams, 1, 0, 0) == 0

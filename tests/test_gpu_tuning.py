@@ -29,22 +29,23 @@ def test_every_launch_shape_gives_identical_results(form, tmp_path):
     acc0 = FusionAcc.zeros(dg.n, 64, "cuda")
     ref_grads = {k: v.clone() for k, v in r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc0).items()}
     torch.cuda.synchronize()
-    default = (int(r.plan.tuning.fwd_slice), int(r.plan.tuning.bwd_chunk), int(r.plan.tuning.fwd_rows))
+    default = (int(r.plan.tuning.fwd_slice), int(r.plan.tuning.bwd_chunk), int(r.plan.tuning.fwd_rows),
+               int(r.plan.tuning.schedule))
     fwd_c = r.tuning_candidates(L.FH_K_RENDER_FWD)
     bwd_c = r.tuning_candidates(L.FH_K_RENDER_BWD)
     print(f"[tuning {form}] default {default}, forward {fwd_c}, backward {bwd_c}", flush=True)
     assert default in fwd_c and default in bwd_c
-    for sl, ch, rows in fwd_c + bwd_c:
-        r.set_tuning(sl, ch, rows)
+    for sl, ch, rows, sc in fwd_c + bwd_c:
+        r.set_tuning(sl, ch, rows, sc)
         out = r.render_fwd(dg)
         for k, v in ref_img.items():
-            assert torch.equal(getattr(out, k), v), (sl, ch, rows, k)
+            assert torch.equal(getattr(out, k), v), (sl, ch, rows, sc, k)
         acc = FusionAcc.zeros(dg.n, 64, "cuda")
         grads = r.render_bwd(dg, out, dC, dF, dT, target=target, acc=acc)
         torch.cuda.synchronize()
         for k, v in ref_grads.items():
-            assert torch.equal(grads[k], v), (sl, ch, rows, k)
-        assert torch.equal(acc.sum, acc0.sum) and torch.equal(acc.wsum, acc0.wsum), (sl, ch, rows)
+            assert torch.equal(grads[k], v), (sl, ch, rows, sc, k)
+        assert torch.equal(acc.sum, acc0.sum) and torch.equal(acc.wsum, acc0.wsum), (sl, ch, rows, sc)
     # the autotuner picks a candidate and caches it under the workload key
     cache = str(tmp_path / "tune.json")
     r.set_tuning(*default)
@@ -52,7 +53,7 @@ def test_every_launch_shape_gives_identical_results(form, tmp_path):
     pick = r.autotune(dg, img, dC, dF, dT, target=target, reps=2, cache=cache)
     print(f"[tuning {form}] picked {pick}", flush=True)
     assert (pick["fwd_slice"], pick["fwd_rows"]) in [(c[0], c[2]) for c in fwd_c]
-    assert pick["bwd_chunk"] in [c[1] for c in bwd_c]
+    assert pick["bwd_chunk"] in [c[1] for c in bwd_c] and pick["schedule"] in (0, 1)
     table = json.load(open(cache))
     assert table[r.tuning_key()] == pick
     # a new plan for the same workload takes the cached pick without timing
