@@ -288,6 +288,9 @@ static void plan_layout(fh_plan* plan) {
     sz[WS_PART_NDFD] = plan->ndfd ? (size_t)visit_capacity * 2 * 8 * sizeof(float) : 0;
     sz[WS_NDFD_SC] = plan->ndfd ? (size_t)visit_capacity * TILE_PIX * 2 * sizeof(float) : 0;
     sz[WS_TORDER_KA] = sz[WS_TORDER_KB] = sz[WS_TORDER_VA] = sz[WS_TORDER_VB] = (size_t)tiles * u4;
+    // the BF16 gradient kernel records w for the fusion kernel of the same call
+    sz[WS_WREC] = (plan->form == FH_FORM_BF16 && d > 0 && render_bwd_bf16_supported(d))
+                      ? (size_t)visit_capacity * TILE_PIX * sizeof(float) : 0;
     static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
     size_t off = 0;
     plan->n_ws = WS_COUNT;
@@ -502,6 +505,7 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.part_geom = buf<float>(p, ws, WS_PART_GEOM);
     a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
     a.tile_order = nullptr;
+    a.wrec = nullptr;
 }
 
 static int visit_sort_passes(const fh_plan* p) { return (p->rank_bits + 7) / 8; }
@@ -512,6 +516,8 @@ static void launch_bwd(const fh_plan* p, void* ws, const BwdArgs& a0, const View
     if (p->form == FH_FORM_BF16 && render_bwd_bf16_supported(p->d)) {
         BwdArgs a = a0;
         a.tile_order = tile_schedule(p, ws, false, s);
+        // the gradient kernel records w when the fusion kernel follows it
+        a.wrec = (fuse && a.dC != nullptr) ? buf<float>(p, ws, WS_WREC) : nullptr;
         launch_render_bwd_bf16(a, vt, (int)p->n_tiles, a.dC != nullptr, fuse, s);
     } else {
         const BwdArgs& a = a0;

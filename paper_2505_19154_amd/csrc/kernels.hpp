@@ -103,6 +103,8 @@ struct BwdArgs {
     float* part_geom;
     float* part_fuse;
     const uint32_t* tile_order;   // nullable: work item i takes tile tile_order[i]
+    float* wrec;                  // nullable: [visits][256] w of every visited (position, pixel), recorded by the
+                                  // BF16 gradient kernel for the fusion kernel of the same call
 };
 struct VisitStageArgs {
     const uint32_t* ranges;

@@ -31,6 +31,7 @@ namespace fh {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;   // positions per chunk
 // padded per-pixel stride of the (pixel, position) LDS arrays: the walk's stores
@@ -375,6 +376,21 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                 if (lane < 32) sred[(w * 10 + m) * BK + k] = qv[m];
             }
         }
+        // w of the chunk, recorded for the fusion kernel of the same call as
+        // W^T [position][pixel]: consecutive lanes store consecutive pixels
+        // (and read LDS at the odd stride SK: no bank conflicts)
+        if (a.wrec) {
+            float* dst = a.wrec + ((int64_t)voff + cs) * TILE_PIX;
+            // (the thread index is made opaque here so that the addresses are
+            // not hoisted out of the chunk loop into registers held across the walk)
+            int tid = (int)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+#pragma unroll 4
+            for (int j = 0; j < BK * TILE_PIX / 512; ++j) {
+                const int e = tid + 512 * j, k = e >> 8, n = e & 255;
+                if (k < cnt) dst[e] = sw[n * SK + k];
+            }
+        }
         __syncthreads();
         if (threadIdx.x < 12 * BK) {
             // terms 10 and 11 of a partial are padding: written as zero
@@ -585,6 +601,133 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fusion from the weights the gradient kernel of the same call recorded
+// (W^T [visit][pixel], FP32): no second walk.  1024 threads; wave w < D/16
+// keeps channel block w of the tile's target in registers (as k_fuse_bf16);
+// every thread loads its share of each chunk's W^T (coalesced float4 rows),
+// splits it into BF16 hi + lo and stores it to LDS, double-buffered by chunk
+// parity (one barrier per chunk; the next chunk's loads are in flight during
+// this chunk's contraction).
+template <int D>
+__global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt) {
+    constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
+    constexpr int NDB = D / 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __bf16* swh2 = reinterpret_cast<__bf16*>(smem);                          // [2][BK][PP] W^T hi
+    __bf16* swl2 = swh2 + 2 * BK * PP;                                       // [2][BK][PP] W^T lo
+
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const uint32_t nt = a.tile_niter[t];
+    if (nt == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int W = vt.width[v], H = vt.height[v];
+    const uint32_t voff = a.tile_voff[t];
+
+    // W^T rows of a chunk: 32 positions x 64 float4 (256 pixels); thread
+    // handles items threadIdx.x and threadIdx.x + 1024 (position = item / 64)
+    const float4* wrec4 = reinterpret_cast<const float4*>(a.wrec);
+    auto load_w = [&](int cs, int cnt, float4* f) {
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = threadIdx.x + 1024 * it, k = idx >> 6, c4 = idx & 63;
+            f[it] = k < cnt ? wrec4[((int64_t)voff + cs + k) * 64 + c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_w = [&](const float4* f, __bf16* swh, __bf16* swl) {
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = threadIdx.x + 1024 * it, k = idx >> 6, n0 = 4 * (idx & 63);
+            const float vals[4] = {f[it].x, f[it].y, f[it].z, f[it].w};
+            bf16x4 hv, lv;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                hv[m] = (__bf16)vals[m];
+                lv[m] = (__bf16)(vals[m] - (float)hv[m]);
+            }
+            *reinterpret_cast<bf16x4*>(&swh[k * PP + n0]) = hv;
+            *reinterpret_cast<bf16x4*>(&swl[k * PP + n0]) = lv;
+        }
+    };
+
+    // target[px = 32 st + 8 q + m][16 w + xi]: B operands of this wave's block
+    // (as in k_fuse_bf16: all 64 loads issued before any is used; addresses of
+    // pixels outside the image clamped into it and the values zeroed after)
+    bf16x8 tgo[8];
+    if (w < NDB) {
+        const uint16_t* tg = static_cast<const uint16_t*>(a.target);
+        u16x8 raw[8];
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int n0 = 32 * st + 8 * q;
+            const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
+            const int64_t row = vt.pix_off[v] + (int64_t)(qy < H ? qy : H - 1) * W;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int qx = qx0 + m < W ? qx0 + m : W - 1;
+                raw[st][m] = tg[(row + qx) * D + 16 * w + xi];
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int n0 = 32 * st + 8 * q;
+            const int qy = ty * TILE + (n0 >> 4), qx0 = tx * TILE + (n0 & 15);
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (qy >= H || qx0 + m >= W) raw[st][m] = 0;
+            tgo[st] = __builtin_bit_cast(bf16x8, raw[st]);
+        }
+    } else {
+#pragma unroll
+        for (int st = 0; st < 8; ++st) tgo[st] = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+    }
+
+    {
+        float4 f[2];
+        load_w(0, (int)nt < BK ? (int)nt : BK, f);
+        store_w(f, swh2, swl2);
+    }
+    __syncthreads();
+    int b = 0;
+    for (int cs = 0; cs < (int)nt; cs += BK, b ^= 1) {
+        const int cnt = (int)nt - cs < BK ? (int)nt - cs : BK;
+        const __bf16* swh = swh2 + b * BK * PP;
+        const __bf16* swl = swl2 + b * BK * PP;
+        // the next chunk's weights, in flight during this chunk's contraction
+        const int ncs = cs + BK, ncnt = (int)nt - ncs < BK ? (int)nt - ncs : BK;
+        float4 fn[2];
+        if (ncs < (int)nt) load_w(ncs, ncnt, fn);
+        // out[k][d] = sum_px W^T[k][px] target[px][d], W = hi + lo
+        if (w < NDB) {
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < 8; ++st) {
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&swh[(16 * kb + xi) * PP + 32 * st + 8 * q]);
+                    const bf16x8 alo = *reinterpret_cast<const bf16x8*>(&swl[(16 * kb + xi) * PP + 32 * st + 8 * q]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, tgo[st], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, tgo[st], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * kb + 4 * q + r;
+                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * D + 16 * w + xi] = acc[r];
+                }
+            }
+        }
+        // the other buffer's last readers (the previous chunk's contraction)
+        // passed the previous barrier
+        if (ncs < (int)nt) store_w(fn, swh2 + (b ^ 1) * BK * PP, swl2 + (b ^ 1) * BK * PP);
+        __syncthreads();
+    }
+}
+
 template <int D>
 static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     if (grads) {
@@ -594,7 +737,9 @@ static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bo
     }
     if (fuse) {
         const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + 8);
-        if (grads)
+        if (grads && a.wrec)
+            hipLaunchKernelGGL(k_fuse_rec_bf16<D>, dim3(n_tiles), dim3(1024), lds, s, a, vt);
+        else if (grads)
             hipLaunchKernelGGL((k_fuse_bf16<D, false>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
         else
             hipLaunchKernelGGL((k_fuse_bf16<D, true>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
