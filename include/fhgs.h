@@ -121,11 +121,13 @@ typedef struct {
  *              BF16 form, and FP32 form with FP32 features and d = 32, 64,
  *              96 or a multiple of 128 (the MFMA forward; the features enter
  *              it as three BF16 terms): dividing d, and 32, 64, 96 or 128 (BF16 form only) with
- *              fwd_rows 16, or 64, 128 or 256 with fwd_rows 8.  Other
- *              FP32-form widths: 8, 16, 32 or 64.  0 when d == 0.
- *   fwd_rows   pixel rows per forward workgroup (BF16 form: 16, or 8 for two
- *              workgroups per tile with twice the registers each; the FP32
- *              VALU forward: 16).
+ *              fwd_rows 16, 64, 128 or 256 with fwd_rows 8, or 128 or 256
+ *              with fwd_rows 4 (BF16 form only).  Other FP32-form widths: 8,
+ *              16, 32 or 64.  0 when d == 0.
+ *   fwd_rows   pixel rows per forward workgroup (BF16 form: 16, 8 for two
+ *              workgroups per tile with twice the registers each, or 4 for
+ *              four workgroups per tile, several resident per CU, each with
+ *              its own barriers; the FP32 VALU forward: 16).
  *   bwd_chunk  Gaussians per back-to-front chunk of the FP32-form adjoint:
  *              16 or 32 (32 needs d <= 512).  The BF16-form adjoint always
  *              takes 32 (the MFMA k).

@@ -157,7 +157,8 @@ static bool fwd_shape_ok(int d, int form, int feat_dtype, int slice, int rows) {
     if (d == 0) return slice == 0 && rows == 16;
     // (FP32 features: 16 rows of 128 channels is not offered, it would spill)
     if (mfma_forward(d, form, feat_dtype))
-        return render_fwd_bf16_shape_ok(d, slice, rows) && !(form == FH_FORM_F32 && rows == 16 && slice == 128);
+        return render_fwd_bf16_shape_ok(d, slice, rows) && !(form == FH_FORM_F32 && rows == 16 && slice == 128) &&
+               !(form == FH_FORM_F32 && rows == 4);
     return rows == 16 && (slice == 8 || slice == 16 || slice == 32 || slice == 64);
 }
 
@@ -753,7 +754,7 @@ fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, 
         // (the MFMA forward also takes the two work orders)
         const int nsched = mfma_forward(p->d, p->form, p->feat_dtype) ? 2 : 1;
         for (int sc = 0; sc < nsched; ++sc)
-            for (int rows : {16, 8})
+            for (int rows : {16, 8, 4})
                 for (int sl : slices)
                     if (fwd_shape_ok(p->d, p->form, p->feat_dtype, sl, rows) &&
                         (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {

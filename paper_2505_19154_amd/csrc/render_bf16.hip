@@ -45,8 +45,9 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
 // l = bf16(x - h - m)) and F takes the six products hh, hm, mh, hl, lh, mm:
 // what is left out is below 2^-24 of w f, so F keeps FP32 accuracy on MFMA.
 template <int DS, int ROWS, bool FS>
-// (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per CU)
-__global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128 && !FS) ? 4 : 1) void k_render_fwd_bf16(
+// (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per
+// CU; 4-row shapes are two or four workgroups per CU, each with its own barriers)
+__global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (ROWS == 4 ? 2 : 1)) void k_render_fwd_bf16(
     RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
     static_assert(NB % 2 == 0, "channel blocks are processed in pairs");
@@ -382,6 +383,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS == 8 && DS <= 128 && !FS) ? 4 : 1)
 bool render_fwd_bf16_shape_ok(int d, int slice, int rows) {
     if (rows == 16) return (slice == 32 || slice == 64 || slice == 96 || slice == 128) && d % slice == 0;
     if (rows == 8) return (slice == 64 || slice == 128 || slice == 256) && d % slice == 0;
+    if (rows == 4) return (slice == 128 || slice == 256) && d % slice == 0;
     return false;
 }
 
@@ -389,7 +391,17 @@ template <bool FS>
 static void launch_fwd_mfma(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, hipStream_t s) {
     // slice and rows form a valid shape for d (checked by the caller)
     const unsigned ns = (unsigned)(a.d / slice);
-    const dim3 g16(n_tiles, ns), g8(n_tiles, 2 * ns);
+    const dim3 g16(n_tiles, ns), g8(n_tiles, 2 * ns), g4(n_tiles, 4 * ns);
+    if (rows == 4) {
+        // (BF16-stored features only)
+        if constexpr (!FS) {
+            if (slice == 128)
+                hipLaunchKernelGGL((k_render_fwd_bf16<128, 4, false>), g4, dim3(256), 0, s, a, vt);
+            else
+                hipLaunchKernelGGL((k_render_fwd_bf16<256, 4, false>), g4, dim3(256), 0, s, a, vt);
+        }
+        return;
+    }
     if (rows == 8) {
         switch (slice) {
             case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8, FS>), g8, dim3(512), 0, s, a, vt); break;

@@ -129,10 +129,11 @@ def test_tuning_defaults_and_candidates_on_host():
     # (the MFMA forward in both work orders: tile index order, longest first)
     assert cands(plan, _lib.FH_K_RENDER_FWD) == mf + [c + (1,) for c in mf]
     assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 16, 8), (256, 32, 8)]
-    # BF16 form, d = 256: slices dividing d for 16-row and 8-row workgroups; one backward shape
+    # BF16 form, d = 256: slices dividing d for 16-, 8- and 4-row workgroups; one backward shape
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 0, 0) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.fwd_rows) == (256, 8)
-    bf = [(32, 32, 16), (64, 32, 16), (128, 32, 16), (64, 32, 8), (128, 32, 8), (256, 32, 8)]
+    bf = [(32, 32, 16), (64, 32, 16), (128, 32, 16), (64, 32, 8), (128, 32, 8), (256, 32, 8), (128, 32, 4),
+          (256, 32, 4)]
     assert cands(plan, _lib.FH_K_RENDER_FWD) == bf + [c + (1,) for c in bf]
     assert cands(plan, _lib.FH_K_RENDER_BWD) == [(256, 32, 8), (256, 32, 8, 1)]
     # BF16 form, d = 96; FP32 form, d = 16; d = 1024 takes 16-Gaussian chunks
