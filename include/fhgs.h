@@ -301,7 +301,9 @@ fh_status fh_render_fwd(const fh_plan *plan, const fh_gaussians *g, void *ws, co
  * If fusion_target (per-pixel [P,d], dtype target_dtype) and acc are given,
  * the same sweep also accumulates feature fusion into acc.  In the BF16 form
  * the target must be BF16 (FH_E_UNSUPPORTED otherwise): it is an MFMA
- * operand as stored.
+ * operand as stored.  BF16 form above 256 channels: the feature contractions
+ * run in channel slices of 256 (or 128 when 256 does not divide d), the part
+ * f_k . dF of the earlier slices carried between launches in the workspace.
  * Gradients are written (not accumulated) into `out`.  After an instance or
  * visit overflow (fh_read_counters) the gradients are all zero and acc is
  * left unchanged. */

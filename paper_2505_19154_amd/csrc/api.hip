@@ -292,6 +292,8 @@ static void plan_layout(fh_plan* plan) {
     // the BF16 gradient kernel records w for the fusion kernel of the same call
     sz[WS_WREC] = (plan->form == FH_FORM_BF16 && d > 0 && render_bwd_bf16_supported(d))
                       ? (size_t)visit_capacity * TILE_PIX * sizeof(float) : 0;
+    sz[WS_GREC] = (plan->form == FH_FORM_BF16 && d > 0 && render_bwd_bf16_sliced(d))
+                      ? (size_t)visit_capacity * TILE_PIX * sizeof(float) : 0;
     static_assert(WS_COUNT <= FH_WS_SLOTS, "fh_plan.off holds the offset of every workspace sub-buffer");
     size_t off = 0;
     plan->n_ws = WS_COUNT;
@@ -507,6 +509,9 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.part_fuse = buf<float>(p, ws, WS_PART_FUSE);
     a.tile_order = nullptr;
     a.wrec = nullptr;
+    a.d0 = 0;
+    a.g_in = nullptr;
+    a.g_out = nullptr;
 }
 
 static int visit_sort_passes(const fh_plan* p) { return (p->rank_bits + 7) / 8; }
@@ -519,6 +524,7 @@ static void launch_bwd(const fh_plan* p, void* ws, const BwdArgs& a0, const View
         a.tile_order = tile_schedule(p, ws, false, s);
         // the gradient kernel records w when the fusion kernel follows it
         a.wrec = (fuse && a.dC != nullptr) ? buf<float>(p, ws, WS_WREC) : nullptr;
+        if (render_bwd_bf16_sliced(p->d)) a.g_out = buf<float>(p, ws, WS_GREC);
         launch_render_bwd_bf16(a, vt, (int)p->n_tiles, a.dC != nullptr, fuse, s);
     } else {
         const BwdArgs& a = a0;

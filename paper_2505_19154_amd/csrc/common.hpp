@@ -67,6 +67,7 @@ enum WsBuf {
     WS_TORDER_VA,      // u32 [tiles] tile schedule: tile ids (ping-pong; the order ends here)
     WS_TORDER_VB,
     WS_WREC,           // float [visit_cap * 256] w per visited (position, pixel), BF16 form (gradient -> fusion)
+    WS_GREC,           // float [visit_cap * 256] f . dF of earlier channel slices, BF16 form above 256 channels
     WS_COUNT
 };
 

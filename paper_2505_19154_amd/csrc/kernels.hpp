@@ -105,6 +105,13 @@ struct BwdArgs {
     const uint32_t* tile_order;   // nullable: work item i takes tile tile_order[i]
     float* wrec;                  // nullable: [visits][256] w of every visited (position, pixel), recorded by the
                                   // BF16 gradient kernel for the fusion kernel of the same call
+    // BF16 kernels at feature widths above 256 work in channel slices: the
+    // slice starts at channel d0 (rows of feat, dF, target and the fusion
+    // partials keep the stride d); g = f . dF of the earlier slices is carried
+    // between launches in [visits][256] rows (g_in added, g_out written)
+    int d0;
+    const float* g_in;
+    float* g_out;
 };
 struct VisitStageArgs {
     const uint32_t* ranges;
@@ -146,6 +153,7 @@ bool render_fwd_bf16_shape_ok(int d, int slice, int rows);
 void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, bool fsplit,
                             hipStream_t s);
 bool render_bwd_bf16_supported(int d);
+bool render_bwd_bf16_sliced(int d);   // above 256 channels: sliced, with a carry of f . dF between slices
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse,
                             hipStream_t s);
 void launch_visit_stage(const VisitStageArgs& a, int n_tiles, hipStream_t s);

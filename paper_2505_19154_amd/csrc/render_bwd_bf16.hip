@@ -83,8 +83,11 @@ __device__ __forceinline__ Rec fetch_record(const BwdArgs& a, uint32_t voff, int
 // Gradient kernel.  512 threads (8 waves; 256 VGPRs per lane so that dF (hi and
 // lo) stays resident); wave w owns pixel rows 2w and 2w + 1; lane (xi, q) = pixel x = xi
 // of both rows, positions 4q..4q+3 of each 16-position half-chunk.
-template <int D>
+// SL: one channel slice of a wider feature (rows of stride a.d from channel
+// a.d0; a.g_in adds the earlier slices' part of f . dF)
+template <int D, bool SL>
 __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt) {
+    const int dstride = SL ? a.d : D, dofs = SL ? a.d0 : 0;
     constexpr int DP = D + 8;            // padded row stride (bf16) of the feature chunk
     constexpr int NS = D / 32;           // MFMA steps over channels
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 #pragma unroll
             for (int m = 0; m < 8; ++m) vals[m] = 0.0f;
             if (has_df && inside) {
-                const float4* src = reinterpret_cast<const float4*>(a.dF + p * D + 32 * st + 8 * q);
+                const float4* src = reinterpret_cast<const float4*>(a.dF + p * dstride + dofs + 32 * st + 8 * q);
                 const float4 lo4 = src[0], hi4 = src[1];
                 vals[0] = lo4.x; vals[1] = lo4.y; vals[2] = lo4.z; vals[3] = lo4.w;
                 vals[4] = hi4.x; vals[5] = hi4.y; vals[6] = hi4.z; vals[7] = hi4.w;
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                 const int k = idx / (D / 8), dg = idx % (D / 8);
                 const uint32_t g = gl[k];
                 const uint32_t ga = g != 0xFFFFFFFFu ? g : 0u;
-                raw[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * D + dg * 8);
+                raw[it] = *reinterpret_cast<const uint4*>(feat + (int64_t)ga * dstride + dofs + dg * 8);
             }
         }
     };
@@ -272,6 +275,8 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                     on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && ae.alpha >= ALPHA_MIN;
                     al[r] = ae.alpha;
                     gg[r] = rc.r2.y * dCp[h][0] + rc.r2.z * dCp[h][1] + rc.r2.w * dCp[h][2] + gk[kb][r];
+                    // the earlier channel slices' part of f_k . dF (positions of the chunk only)
+                    if (SL && a.g_in && k < cnt) gg[r] += a.g_in[((int64_t)voff + cs + k) * TILE_PIX + n];
                     iv[r] = __builtin_amdgcn_rcpf(1.0f - al[r]);
                     // (branch-free: a position that does not blend leaves the state as is)
                     const float tn = trel * iv[r];
@@ -413,6 +418,99 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 }
 
 // ---------------------------------------------------------------------------
+// f_k . dF over one channel slice, for feature widths above 256 (whose dF does
+// not fit in registers at once): the slice's dF (hi + lo) stays resident as in
+// the gradient kernel, and g_out[visit][pixel] = g_in (earlier slices, when
+// given) + this slice's contraction, for every visited position of the tile.
+// 512 threads; wave w owns pixel rows 2w and 2w + 1; chunks of 32 positions
+// front to back, the features staged in LDS.
+template <int D>
+__global__ __launch_bounds__(512) void k_gk_bf16(BwdArgs a, ViewTable vt) {
+    constexpr int DP = D + 8;
+    constexpr int NS = D / 32;
+    __shared__ __attribute__((aligned(16))) __bf16 sfeat[BK * DP];
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const uint32_t nt = a.tile_niter[t];
+    if (nt == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, xi = lane & 15;
+    const int v = view_of_tile(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
+    const int W = vt.width[v], H = vt.height[v];
+    const uint32_t voff = a.tile_voff[t];
+    const uint16_t* feat = static_cast<const uint16_t*>(a.feat);
+    const int px = tx * TILE + xi;
+    bf16x8 dfh[2][NS], dfl[2][NS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int py = ty * TILE + 2 * w + h;
+        const bool inside = px < W && py < H;
+        const int64_t p = vt.pix_off[v] + (int64_t)py * W + px;
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            float vals[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) vals[m] = 0.0f;
+            if (inside) {
+                const float4* src = reinterpret_cast<const float4*>(a.dF + p * a.d + a.d0 + 32 * st + 8 * q);
+                const float4 lo4 = src[0], hi4 = src[1];
+                vals[0] = lo4.x; vals[1] = lo4.y; vals[2] = lo4.z; vals[3] = lo4.w;
+                vals[4] = hi4.x; vals[5] = hi4.y; vals[6] = hi4.z; vals[7] = hi4.w;
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const __bf16 hb = (__bf16)vals[m];
+                dfh[h][st][m] = hb;
+                dfl[h][st][m] = (__bf16)(vals[m] - (float)hb);
+            }
+        }
+    }
+    constexpr int ITEMS = BK * (D / 8), NI = (ITEMS + 511) / 512;
+    for (int cs = 0; cs < (int)nt; cs += BK) {
+        const int cnt = (int)nt - cs < BK ? (int)nt - cs : BK;
+        __syncthreads();   // (the previous chunk's readers are done with sfeat)
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int idx = (int)threadIdx.x + 512 * it;
+            if (idx < ITEMS) {
+                const int k = idx / (D / 8), dg = idx % (D / 8);
+                // positions past the chunk read Gaussian 0; their results are not stored
+                const uint32_t g = k < cnt ? a.vgid[(int64_t)voff + cs + k] : 0u;
+                *reinterpret_cast<uint4*>(&sfeat[k * DP + dg * 8]) =
+                    *reinterpret_cast<const uint4*>(feat + (int64_t)g * a.d + a.d0 + dg * 8);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = (2 * w + h) * TILE + xi;
+            f32x4 gk[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                const bf16x8 fa0 = *reinterpret_cast<const bf16x8*>(&sfeat[xi * DP + 32 * st + 8 * q]);
+                const bf16x8 fa1 = *reinterpret_cast<const bf16x8*>(&sfeat[(16 + xi) * DP + 32 * st + 8 * q]);
+                gk[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, dfh[h][st], gk[0], 0, 0, 0);
+                gk[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, dfh[h][st], gk[1], 0, 0, 0);
+                gk[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, dfl[h][st], gk[0], 0, 0, 0);
+                gk[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, dfl[h][st], gk[1], 0, 0, 0);
+            }
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * kb + 4 * q + r;
+                    if (k < cnt) {
+                        const int64_t o = ((int64_t)voff + cs + k) * TILE_PIX + n;
+                        a.g_out[o] = (a.g_in ? a.g_in[o] : 0.0f) + gk[kb][r];
+                    }
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Fusion kernel.  1024 threads; wave w = pixel row w; lane (xi, q) = pixel
 // x = xi, positions 4q..4q+3 of each half-chunk; wave w < D/16 owns channel
 // block w of the contraction and keeps that block of the tile's target in
@@ -449,6 +547,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     const int64_t p = vt.pix_off[v] + (int64_t)py * W + px;
     const uint32_t nit = inside ? a.n_iter[p] : 0u;
     float T = inside ? a.T_final[p] : 1.0f;
+    const int d0 = (int)blockIdx.y * D;   // channel slice (feature widths above 256)
 
     // target[px = 32 st + 8 q + m][16 w + xi]: B operands of this wave's block
     // (BF16 target).  All 64 loads are issued before any is used: addresses of
@@ -465,7 +564,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int qx = qx0 + m < W ? qx0 + m : W - 1;
-                raw[st][m] = tg[(row + qx) * D + 16 * w + xi];
+                raw[st][m] = tg[(row + qx) * a.d + d0 + 16 * w + xi];
             }
         }
 #pragma unroll
@@ -547,7 +646,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
                 const __bf16 hh = (__bf16)wv;
                 swh[k * PP + n] = hh;
                 swl[k * PP + n] = (__bf16)(wv - (float)hh);
-                if (WS) {
+                if (WS && d0 == 0) {
                     // the row's weight sum of position k: butterfly over the 16 pixels
                     float rs = wv;
 #pragma unroll
@@ -568,7 +667,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         }
         __syncthreads();
         // weight sums per instance: the 16 rows in order
-        if (WS && threadIdx.x < BK) {
+        if (WS && d0 == 0 && threadIdx.x < BK) {
             const int k = threadIdx.x;
             float ws = 0.0f;
 #pragma unroll
@@ -590,7 +689,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int k = 16 * kb + 4 * q + r;
-                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * D + 16 * w + xi] = acc[r];
+                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * a.d + d0 + 16 * w + xi] = acc[r];
                 }
             }
         }
@@ -628,6 +727,7 @@ __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt)
     const int tx = lt % vt.tiles_x[v], ty = lt / vt.tiles_x[v];
     const int W = vt.width[v], H = vt.height[v];
     const uint32_t voff = a.tile_voff[t];
+    const int d0 = (int)blockIdx.y * D;   // channel slice (feature widths above 256)
 
     // W^T rows of a chunk: 32 positions x 64 float4 (256 pixels); thread
     // handles items threadIdx.x and threadIdx.x + 1024 (position = item / 64)
@@ -670,7 +770,7 @@ __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt)
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int qx = qx0 + m < W ? qx0 + m : W - 1;
-                raw[st][m] = tg[(row + qx) * D + 16 * w + xi];
+                raw[st][m] = tg[(row + qx) * a.d + d0 + 16 * w + xi];
             }
         }
 #pragma unroll
@@ -717,7 +817,7 @@ __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int k = 16 * kb + 4 * q + r;
-                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * D + 16 * w + xi] = acc[r];
+                    if (k < cnt) a.part_fuse[((int64_t)voff + cs + k) * a.d + d0 + 16 * w + xi] = acc[r];
                 }
             }
         }
@@ -729,33 +829,77 @@ __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt)
 }
 
 template <int D>
-static void launch_bf16_d(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+static void launch_fuse_bf16(const BwdArgs& a0, const ViewTable& vt, int n_tiles, int ns, bool grads, bool fuse,
+                             hipStream_t s) {
+    if (!fuse) return;
+    // one workgroup per (tile, channel slice)
+    const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + 8);
+    const dim3 grid(n_tiles, ns);
+    if (grads && a0.wrec)
+        hipLaunchKernelGGL(k_fuse_rec_bf16<D>, grid, dim3(1024), lds, s, a0, vt);
+    else if (grads)
+        hipLaunchKernelGGL((k_fuse_bf16<D, false>), grid, dim3(1024), lds, s, a0, vt);
+    else
+        hipLaunchKernelGGL((k_fuse_bf16<D, true>), grid, dim3(1024), lds, s, a0, vt);
+}
+
+// D: the channel slice width (the feature width itself up to 256; above it,
+// 256 when it divides the width, else 128)
+template <int D>
+static void launch_bf16_d(const BwdArgs& a0, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+    const int ns = a0.d / D;   // channel slices
     if (grads) {
         const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (D + 8) +
                            sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * 10 * BK);
-        hipLaunchKernelGGL(k_render_bwd_bf16<D>, dim3(n_tiles), dim3(512), lds, s, a, vt);
+        BwdArgs a = a0;
+        a.d0 = 0;
+        a.g_in = nullptr;
+        bool sliced = false;
+        if constexpr (D == 128 || D == 256) {
+            if (ns > 1) {
+                // f . dF of every slice but the last, summed in a0.g_out; the
+                // gradient kernel takes the last slice and adds the carry
+                sliced = true;
+                if (a0.dF) {
+                    for (int sl = 0; sl + 1 < ns; ++sl) {
+                        BwdArgs g = a0;
+                        g.d0 = sl * D;
+                        g.g_in = sl > 0 ? a0.g_out : nullptr;
+                        hipLaunchKernelGGL(k_gk_bf16<D>, dim3(n_tiles), dim3(512), 0, s, g, vt);
+                    }
+                    a.g_in = a0.g_out;
+                }
+                a.d0 = (ns - 1) * D;
+                hipLaunchKernelGGL((k_render_bwd_bf16<D, true>), dim3(n_tiles), dim3(512), lds, s, a, vt);
+            }
+        }
+        if (!sliced) hipLaunchKernelGGL((k_render_bwd_bf16<D, false>), dim3(n_tiles), dim3(512), lds, s, a, vt);
     }
-    if (fuse) {
-        const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + 8);
-        if (grads && a.wrec)
-            hipLaunchKernelGGL(k_fuse_rec_bf16<D>, dim3(n_tiles), dim3(1024), lds, s, a, vt);
-        else if (grads)
-            hipLaunchKernelGGL((k_fuse_bf16<D, false>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
-        else
-            hipLaunchKernelGGL((k_fuse_bf16<D, true>), dim3(n_tiles), dim3(1024), lds, s, a, vt);
-    }
+    launch_fuse_bf16<D>(a0, vt, n_tiles, ns, grads, fuse, s);
 }
 
-bool render_bwd_bf16_supported(int d) { return d == 32 || d == 64 || d == 96 || d == 128 || d == 256; }
+bool render_bwd_bf16_supported(int d) {
+    return d == 32 || d == 64 || d == 96 || d == 128 || d == 256 || (d > 256 && d % 128 == 0);
+}
 
-// grads: the gradient kernel (needs dC); fuse: the fusion kernel (needs the target)
+bool render_bwd_bf16_sliced(int d) { return d > 256; }
+
+// grads: the gradient kernel (needs dC); fuse: the fusion kernel (needs the
+// target).  Above 256 channels, a.g_out is the [visits][256] carry of f . dF
+// between channel slices (needed when dF is given).
 void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     switch (a.d) {
         case 32: launch_bf16_d<32>(a, vt, n_tiles, grads, fuse, s); break;
         case 64: launch_bf16_d<64>(a, vt, n_tiles, grads, fuse, s); break;
         case 96: launch_bf16_d<96>(a, vt, n_tiles, grads, fuse, s); break;
         case 128: launch_bf16_d<128>(a, vt, n_tiles, grads, fuse, s); break;
-        default: launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s); break;
+        case 256: launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s); break;
+        default:
+            if (a.d % 256 == 0)
+                launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s);
+            else
+                launch_bf16_d<128>(a, vt, n_tiles, grads, fuse, s);
+            break;
     }
 }
 

@@ -25,7 +25,7 @@ _WS = {name: i for i, name in enumerate(
      "scan_tmp", "hist", "ranges", "tile_niter", "tile_voff", "grad2d", "rank_of", "keys_a",
      "keys_b", "vals_a", "vals_b", "vseg", "part_geom", "part_fuse", "vkey_a", "vkey_b", "vval_a", "vval_b",
      "long", "vrec", "vgid", "rrec", "unit_owner", "upart", "part_ndfd", "ndfd_sc", "torder_ka", "torder_kb",
-     "torder_va", "torder_vb", "wrec"])}
+     "torder_va", "torder_vb", "wrec", "grec"])}
 
 
 def _ptr(t):

@@ -85,14 +85,15 @@ def test_capacity_overflow_is_reported_not_faulted():
                          mask=ok[:, None].repeat(3, 1))[0] <= 1.0
 
 
-@pytest.mark.parametrize("form", ["f32", "bf16"])
-def test_fusion_accumulates_across_calls_and_finalises(form):
+@pytest.mark.parametrize("form,d", [("f32", 32), ("bf16", 32), ("bf16", 512)])
+def test_fusion_accumulates_across_calls_and_finalises(form, d):
+    # (d = 512 in the BF16 form: the fusion kernel in two 256-channel slices)
     from paper_2505_19154_amd.raster import FusionAcc, fuse_finalize
-    g = scenegen.make_gaussians(800, 1.0, 1, 32, seed=6, feat_dtype="bf16")
+    g = scenegen.make_gaussians(800, 1.0, 1, d, seed=6, feat_dtype="bf16")
     cams = [scenegen.look_at_camera(p, 48, 40) for p in ((0, -4, 0), (3, -2.5, 1.2))]
     # exactly representable in BF16 (the BF16 form feeds the target to the MFMA in BF16)
-    const = (np.arange(32) * 0.125 - 2.0).astype(np.float32)
-    acc = FusionAcc.zeros(800, 32, "cuda")
+    const = ((np.arange(d) % 32) * 0.125 - 2.0).astype(np.float32)
+    acc = FusionAcc.zeros(800, d, "cuda")
     dg = U.device_gaussians(g)
     for cam in cams:     # one call per view into the same accumulators
         from paper_2505_19154_amd.raster import Rasterizer
@@ -113,7 +114,7 @@ def test_fusion_accumulates_across_calls_and_finalises(form):
     assert np.allclose(f[hit], const[None, :], rtol=rt, atol=rt)
     assert np.array_equal(f[~hit], g["feat"][~hit])
     # the two calls equal one two-view call (oracle sums)
-    vts = [dict(scenegen.make_view_tensors(i, c.npix, 32), target=np.tile(const, (c.npix, 1))) for i, c in enumerate(cams)]
+    vts = [dict(scenegen.make_view_tensors(i, c.npix, d), target=np.tile(const, (c.npix, 1))) for i, c in enumerate(cams)]
     ora = pipeline.run(g, cams, vts, fusion=True)
     keep = U.checkable(ora["gflags"])
     assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=U.RTOL_FORM[form], mask=keep, amb=ora["wsum_amb"])[0] <= 1.0

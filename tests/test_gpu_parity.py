@@ -28,6 +28,10 @@ SCENES = {
     "mfma_d64": (2000, 1.5, 3, 64, "bf16", "front100x70", "bf16"),
     "mfma_d96": (2000, 1.5, 2, 96, "bf16", "front90x60", "bf16"),
     "mfma_d256": (1200, 1.5, 3, 256, "bf16", "front96x80", "bf16"),
+    # wider than 256: the adjoint and fusion in channel slices (d = 512: two of
+    # 256 channels; d = 384: three of 128, so f . dF is carried over two slices)
+    "mfma_d512": (900, 1.5, 1, 512, "bf16", "front64x48", "bf16"),
+    "mfma_d384": (900, 1.5, 2, 384, "bf16", "front64x48", "bf16"),
     # FP32 form with FP32 features at d = 128 and 256: the MFMA forward with
     # three-term splits in its 8-row shapes (128- and 256-channel slices)
     "fsplit_d128": (1500, 1.5, 1, 128, "f32", "front100x70", "f32"),
