@@ -98,7 +98,7 @@ def opacity_kappa(o: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     return np.where(live, kap, f32(0.0)).astype(f32), live
 
 
-RULES = ("box", "opacity")
+RULES = ("box", "opacity", "surfel")
 
 
 def bin_quantities(g: dict, cam, rule: str = "box") -> dict:
@@ -151,6 +151,8 @@ def bin_quantities(g: dict, cam, rule: str = "box") -> dict:
         W1 = [(T1[0] * M[:, 0, l] + T1[1] * M[:, 1, l]) + T1[2] * M[:, 2, l] for l in range(3)]
         a = ((W0[0] * W0[0] + W0[1] * W0[1]) + W0[2] * W0[2]) + consts.LOWPASS_F32
         c = ((W1[0] * W1[0] + W1[1] * W1[1]) + W1[2] * W1[2]) + consts.LOWPASS_F32
+        if rule == "surfel":
+            return _surfel_bins(g, cam, R, s, Rq, px, py, pz, depth, visible, u, v, fx, fy, TX, TY)
         if rule == "box":
             ex = np.sqrt(consts.KAPPA_F32 * a)
             ey = np.sqrt(consts.KAPPA_F32 * c)
@@ -177,6 +179,72 @@ def bin_quantities(g: dict, cam, rule: str = "box") -> dict:
     return dict(depth=depth.astype(f32), visible=visible & finite & live, binned=nonempty,
                 x0=x0, x1=x1, y0=y0, y1=y1, ntiles=ntiles, tiles_x=TX, tiles_y=TY,
                 u32=u.astype(f32), v32=v.astype(f32), ex=ex.astype(f32), ey=ey.astype(f32))
+
+
+def surfel_frame(R, s, Rq, px, py, pz, fx, fy):
+    """Float32 surfel map in pixel offsets from the projected centre (the
+    surfel rule of the module docstring of oracle.surfel): camera-space scaled
+    tangents T_u = s_u R_c Rq[:, 0], T_v = s_v R_c Rq[:, 1], then
+      a = fx (T.x p_z - p_x T.z) / p_z^2,  b = fy (T.y p_z - p_y T.z) / p_z^2,
+      c = T.z / p_z                          for T = T_u (index 0), T_v (index 1).
+    Every step one float32 operation, products rounded before sums."""
+    su, sv = s[:, 0], s[:, 1]
+    tu = [_dot3(R[r], Rq[:, 0, 0], Rq[:, 1, 0], Rq[:, 2, 0]) * su for r in range(3)]
+    tv = [_dot3(R[r], Rq[:, 0, 1], Rq[:, 1, 1], Rq[:, 2, 1]) * sv for r in range(3)]
+    zz = pz * pz
+    a0 = fx * ((tu[0] * pz - px * tu[2]) / zz)
+    a1 = fx * ((tv[0] * pz - px * tv[2]) / zz)
+    b0 = fy * ((tu[1] * pz - py * tu[2]) / zz)
+    b1 = fy * ((tv[1] * pz - py * tv[2]) / zz)
+    c0 = tu[2] / pz
+    c1 = tv[2] / pz
+    return a0, a1, b0, b1, c0, c1
+
+
+def _surfel_bins(g, cam, R, s, Rq, px, py, pz, depth, visible, u, v, fx, fy, TX, TY) -> dict:
+    """Tile rect of a surfel (Section 3.1): the bounding box of the image of
+    its disc u^2 + v^2 <= kappa_i (the opacity-aware kappa_i, so that the disc
+    holds every point where alpha can reach 1/255).  With the surfel map in
+    pixel offsets from the centre, (dx w, dy w, w) = [[a0, a1, 0], [b0, b1, 0],
+    [c0, c1, 1]] (u, v, 1), the disc's dual conic is
+      D = kappa (a a^T, a.b, a.c; b.b, b.c; c.c) - e3 e3^T,
+    the disc lies in front of the camera (its image bounded) iff D22 < 0, and
+    the vertical tangents are dx = (D02 +- sqrt(D02^2 - D00 D22)) / D22 (dy
+    likewise with D12, D11).  Float32, every operation rounded."""
+    a0, a1, b0, b1, c0, c1 = surfel_frame(R, s, Rq, px, py, pz, fx, fy)
+    kap, live = opacity_kappa(g["opacity"])
+    one = f32(1.0)
+    d00 = kap * (a0 * a0 + a1 * a1)
+    d02 = kap * (a0 * c0 + a1 * c1)
+    d11 = kap * (b0 * b0 + b1 * b1)
+    d12 = kap * (b0 * c0 + b1 * c1)
+    d22 = kap * (c0 * c0 + c1 * c1) - one
+    front = d22 < f32(0.0)
+    sx = np.sqrt(d02 * d02 - d00 * d22)
+    sy = np.sqrt(d12 * d12 - d11 * d22)
+    xlo = (d02 + sx) / d22
+    xhi = (d02 - sx) / d22
+    ylo = (d12 + sy) / d22
+    yhi = (d12 - sy) / d22
+    ts = f32(consts.TILE)
+    x0f = np.floor((u + xlo) / ts)
+    x1f = np.floor((u + xhi) / ts)
+    y0f = np.floor((v + ylo) / ts)
+    y1f = np.floor((v + yhi) / ts)
+    finite = (np.isfinite(u) & np.isfinite(v) & np.isfinite(xlo) & np.isfinite(xhi) & np.isfinite(ylo)
+              & np.isfinite(yhi))
+    ok = visible & finite & live & front
+    x0 = np.where(ok, np.maximum(x0f, f32(0)), f32(0))
+    x1 = np.where(ok, np.minimum(x1f, f32(TX - 1)), f32(-1))
+    y0 = np.where(ok, np.maximum(y0f, f32(0)), f32(0))
+    y1 = np.where(ok, np.minimum(y1f, f32(TY - 1)), f32(-1))
+    x0, x1, y0, y1 = (np.asarray(z, np.float64).astype(np.int64) for z in (x0, x1, y0, y1))
+    nonempty = ok & (x0 <= x1) & (y0 <= y1)
+    ntiles = np.where(nonempty, (x1 - x0 + 1) * (y1 - y0 + 1), 0).astype(np.int64)
+    return dict(depth=depth.astype(f32), visible=ok, binned=nonempty,
+                x0=x0, x1=x1, y0=y0, y1=y1, ntiles=ntiles, tiles_x=TX, tiles_y=TY,
+                u32=u.astype(f32), v32=v.astype(f32), xlo=xlo.astype(f32), xhi=xhi.astype(f32),
+                ylo=ylo.astype(f32), yhi=yhi.astype(f32), kappa=kap)
 
 
 def duplicate_with_keys(bq_list: list) -> dict:

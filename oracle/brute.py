@@ -105,6 +105,77 @@ def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None, keep_w: lis
     return col, F, T, niter, order
 
 
+def render_surfel(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
+    """The surfel primitive (Section 3.1) by its definition, without tiles:
+    every pixel's ray c_w + t d_w (camera centre, direction through the pixel
+    centre) meets the plane p + u T_u + v T_v (T_u = s_u t_u, T_v = s_v t_v,
+    world tangents from the quaternion) where, by Cramer's rule on
+    [T_u, T_v, -d_w] (u, v, t) = c_w - p,
+      u = r . (T_v x -d) / det,  v = T_u . (r x -d) / det,  det = T_u . (T_v x -d),
+    r = c_w - p; G = exp(-(u^2 + v^2) / 2) (0 for a parallel ray, det = 0),
+    alpha = min(0.99, o G).  Every surfel that binning keeps visible (float32
+    depth beyond the near plane, opacity above 1/255, its disc in front of the
+    camera) is composited in (depth, index) order with the rasterizer's skip
+    and stop rules.  Torch float64, so autograd gives gradients independent of
+    the hand-written adjoint.  Returns C [P,3], F [P,D] or None, T [P], niter [P]."""
+    bq = binspec.bin_quantities(g_meta, cam, "surfel")
+    vis = np.nonzero(bq["visible"])[0]
+    order = vis[np.lexsort((vis, bq["depth"][vis]))]
+    mu, s, q, op, shc = (params[k] for k in ("means", "scales", "quats", "opacity", "sh"))
+    Rc = torch.tensor(np.asarray(cam.R, np.float64))
+    tc = torch.tensor(np.asarray(cam.t, np.float64))
+    fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    qn = q / q.norm(dim=1, keepdim=True)
+    Rq = _rot(qn)
+    Tu = Rq[:, :, 0] * s[:, 0:1]
+    Tv = Rq[:, :, 1] * s[:, 1:2]
+    campos = -Rc.T @ tc
+    dv = mu - campos
+    dirn = dv / dv.norm(dim=1, keepdim=True)
+    Y = _sh_torch(int(g_meta["sh_degree"]), dirn)
+    rgb = torch.clamp(torch.einsum("nb,nbc->nc", Y, shc) + 0.5, min=0.0)
+
+    W, H = int(cam.width), int(cam.height)
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64), torch.arange(W, dtype=torch.float64),
+                            indexing="ij")
+    x = xx.reshape(-1) + 0.5
+    y = yy.reshape(-1) + 0.5
+    P = W * H
+    dcam = torch.stack([(x - cx) / fx, (y - cy) / fy, torch.ones_like(x)], 1)     # [P, 3]
+    dw = dcam @ Rc                                                              # R_c^T d
+    T = torch.ones(P, dtype=torch.float64)
+    col = torch.zeros(P, 3, dtype=torch.float64)
+    featt = None if feat is None else torch.tensor(np.asarray(feat, np.float64))
+    F = None if featt is None else torch.zeros(P, featt.shape[1], dtype=torch.float64)
+    done = torch.zeros(P, dtype=torch.bool)
+    niter = torch.zeros(P, dtype=torch.int64)
+    for pos, gi in enumerate(order.tolist()):
+        r = (campos - mu[gi])[None, :].expand(P, 3)
+        nd = -dw
+        tvxd = torch.cross(Tv[gi][None, :].expand(P, 3), nd, dim=1)
+        det = (Tu[gi][None, :] * tvxd).sum(1)
+        uu = (r * tvxd).sum(1)
+        vv = (Tu[gi][None, :] * torch.cross(r, nd, dim=1)).sum(1)
+        live = det != 0
+        dsafe = torch.where(live, det, torch.ones_like(det))
+        u = uu / dsafe
+        v = vv / dsafe
+        G = torch.where(live, torch.exp(-0.5 * (u * u + v * v)), torch.zeros_like(u))
+        alpha = torch.clamp(op[gi] * G, max=consts.ALPHA_MAX)
+        ok = (alpha.detach() >= consts.ALPHA_MIN) & ~done
+        Tn = T * (1.0 - alpha)
+        stop = ok & (Tn.detach() < consts.T_MIN)
+        done = done | stop
+        contrib = ok & ~stop
+        w = torch.where(contrib, alpha * T, torch.zeros_like(T))
+        col = col + w[:, None] * rgb[gi][None, :]
+        if F is not None:
+            F = F + w[:, None] * featt[gi][None, :]
+        T = torch.where(contrib, Tn, T)
+        niter = torch.where(contrib, torch.full_like(niter, pos + 1), niter)
+    return col, F, T, niter, order
+
+
 def leaves(g: dict) -> dict:
     return {k: torch.tensor(np.asarray(g[k], np.float64), requires_grad=True)
             for k in ("means", "scales", "quats", "opacity", "sh")}

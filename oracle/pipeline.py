@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import binspec, project, raster
+from . import binspec, project, raster, surfel
 
 
 def view_slice(bins: dict, vi: int, cam) -> np.ndarray:
@@ -25,7 +25,9 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
 
     view_tensors[v] holds dC [P,3], dF [P,D], dT [P] and, for fusion, target [P,D].
     tile_sel[v] optionally restricts the traversal to some of view v's tiles.
-    bin_rule: "box" (one KAPPA) or "opacity" (per-Gaussian kappa_i, binspec).
+    bin_rule: "box" (one KAPPA) or "opacity" (per-Gaussian kappa_i, binspec),
+    or "surfel": the primitives are surfels (Section 3.1, oracle.surfel),
+    binned by the image of their disc (binspec's surfel rule).
     ndfd: dict(lam, k) switches on the NDFD feature branch (Section 3.3); each
     view's tensors then hold "gt" [P, D] and, for its gradient, "ndfd_a" and
     "ndfd_b" [P] (dL/dL_gt, dL/dL_cf per pixel; dC, dF, dT may be zero maps).
@@ -43,8 +45,12 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
     fsum = wsum = fsum_mag = dfeat = fsum_amb = wsum_amb = None
     gflags = np.zeros(n, np.int32)
     counts = np.zeros(3, np.int64)
+    surf = bin_rule == "surfel"
+    proj_fn = surfel.project_surfel if surf else project.project
+    bwd_fn = surfel.project_surfel_bwd if surf else project.project_bwd
+    unpack = _unpack_surfel if surf else _unpack
     for vi, cam in enumerate(cams):
-        pr = project.project(g, cam)
+        pr = proj_fn(g, cam)
         vt = view_tensors[vi] if view_tensors is not None else None
         out = raster.render_view(
             cam, view_slice(bins, vi, cam), bins["gids"], pr, feat=feat,
@@ -65,14 +71,14 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
             if key in out:
                 rec[key] = out[key]
         if vt is not None:
-            up = _unpack(out["g2d"])
-            gv = project.project_bwd(pr, up)
+            up = unpack(out["g2d"])
+            gv = bwd_fn(pr, up)
             grads = gv if grads is None else {k: grads[k] + gv[k] for k in grads}
             if magnitudes:
-                upm = _unpack(out["g2d_mag"])
-                gm = project.project_bwd(pr, upm, magnitude=True)
+                upm = unpack(out["g2d_mag"])
+                gm = bwd_fn(pr, upm, magnitude=True)
                 grads_mag = gm if grads_mag is None else {k: grads_mag[k] + gm[k] for k in grads_mag}
-                ga = project.project_bwd(pr, _unpack(out["g2d_amb"]), magnitude=True)
+                ga = bwd_fn(pr, unpack(out["g2d_amb"]), magnitude=True)
                 grads_amb = ga if grads_amb is None else {k: grads_amb[k] + ga[k] for k in grads_amb}
             if fusion:
                 fsum = out["fsum"] if fsum is None else fsum + out["fsum"]
@@ -91,6 +97,10 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
 def _unpack(g2d: np.ndarray) -> dict:
     return dict(u=g2d[:, 0], v=g2d[:, 1], A=g2d[:, 2], B=g2d[:, 3], C=g2d[:, 4],
                 opacity=g2d[:, 5], rgb=g2d[:, 6:9])
+
+
+def _unpack_surfel(g2d: np.ndarray) -> dict:
+    return dict(srf=g2d[:, 0:9], opacity=g2d[:, 9], rgb=g2d[:, 10:13])
 
 
 def finalize_fusion(fsum: np.ndarray, wsum: np.ndarray, feat_in: np.ndarray) -> np.ndarray:

@@ -43,6 +43,19 @@
  * slope carries into sigma (first order).  The near-threshold bound (*_amb) does not cover these
  * terms: scenes checked with them have no near-threshold decision.
  *
+ * Surfel primitive (prim = 1; oracle/surfel.py): the density is that of the
+ * point of the surfel's plane that the pixel's ray meets, from the per-view
+ * record (x_c, y_c, a0, a1, b0, b1, D, e1, e2):
+ *     dx = x - x_c, dy = y - y_c,  k0 = dx b1 - dy a1,  k1 = dy a0 - dx b0,
+ *     k2 = D - dy e1 - dx e2,  (u, v) = (k0, k1) / k2,
+ *     G = exp(-(u^2 + v^2) / 2)  (0 where k2 = 0),
+ * and the per-Gaussian adjoint rows hold the nine record entries, then o,
+ * r, g, b (13 entries instead of 9).  With power = -(u^2 + v^2) / 2 and
+ * lam = dL/dpower (-u / k2, -v / k2, (u^2 + v^2) / k2) = dL/dk:
+ *     dL/dx_c = -(lam0 b1 - lam1 b0 - lam2 e2), dL/dy_c = -(lam1 a0 - lam0 a1 - lam2 e1),
+ *     dL/da0 = lam1 dy, dL/da1 = -lam0 dy, dL/db0 = -lam1 dx, dL/db1 = lam0 dx,
+ *     dL/dD = lam2, dL/de1 = -lam2 dy, dL/de2 = -lam2 dx.
+ *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
  * absolute values of the same terms) are accumulated alongside.
  *
@@ -123,7 +136,13 @@ typedef struct {
     double *out_Lgt_mag;             /* [P] or NULL */
     double *out_FN;                  /* [P, d] or NULL: sum_i w_i fh_i */
     double *out_WN;                  /* [P] or NULL: sum_i w_i */
+    /* primitive: 0 Gaussian (u, v, A, B, C above), 1 surfel (srf below) */
+    int64_t prim;
+    const double *srf;               /* [N, 9] surfel records (prim 1) */
 } oracle_args;
+
+/* entries of a per-Gaussian adjoint row: (u v A B C | 9 surfel entries), o, r, g, b */
+static int64_t gw_of(const oracle_args *a) { return a->prim ? 13 : 9; }
 
 /* per-thread scratch of the NDFD branch */
 typedef struct {
@@ -134,6 +153,7 @@ typedef struct {
 typedef struct {
     int64_t g, pos;
     double alpha, T, G, dx, dy;
+    double su, sv, sk2;      /* surfel: plane coordinates and k2 */
     int clamped, near_clamp;
 } blend_rec;
 
@@ -142,9 +162,91 @@ typedef struct {
 typedef struct {
     int64_t g, pos;
     double alpha, T, G, dx, dy;
+    double su, sv, sk2;
     int stop;
     double gkm;      /* magnitude of its g_k in this pixel (filled by the adjoint) */
 } amb_rec;
+
+/* density of primitive g at pixel centre (x, y); the pixel offsets and (for
+   surfels) the plane coordinates go to *dx, *dy, *su, *sv, *sk2 */
+static double density(const oracle_args *a, int64_t g, double x, double y, double *dx, double *dy, double *su,
+                      double *sv, double *sk2) {
+    if (!a->prim) {
+        *dx = x - a->u[g];
+        *dy = y - a->v[g];
+        *su = *sv = *sk2 = 0.0;
+        const double power =
+            -0.5 * (a->A[g] * *dx * *dx + 2.0 * a->B[g] * *dx * *dy + a->C[g] * *dy * *dy);
+        return exp(power);
+    }
+    const double *r = a->srf + 9 * g;
+    *dx = x - r[0];
+    *dy = y - r[1];
+    const double k0 = *dx * r[5] - *dy * r[3];
+    const double k1 = *dy * r[2] - *dx * r[4];
+    const double k2 = r[6] - *dy * r[7] - *dx * r[8];
+    *sk2 = k2;
+    if (k2 == 0.0) {
+        *su = *sv = 0.0;
+        return 0.0;
+    }
+    *su = k0 / k2;
+    *sv = k1 / k2;
+    return exp(-0.5 * (*su * *su + *sv * *sv));
+}
+
+/* geometry entries of g's adjoint row for dL/dpower = dp at a blend (pixel
+   offsets dx, dy, plane state su, sv, sk2): values into out (when dp_is_mag is
+   0) or magnitudes for |dL/dpower| <= dp (when 1); 5 entries for a Gaussian,
+   9 for a surfel */
+static void geom_terms(const oracle_args *a, int64_t g, double dx, double dy, double su, double sv, double sk2,
+                       double dp, int dp_is_mag, double *out) {
+    if (!a->prim) {
+        const double A = a->A[g], B = a->B[g], Cc = a->C[g];
+        if (!dp_is_mag) {
+            out[0] = dp * (A * dx + B * dy);
+            out[1] = dp * (B * dx + Cc * dy);
+            out[2] = dp * (-0.5 * dx * dx);
+            out[3] = dp * (-dx * dy);
+            out[4] = dp * (-0.5 * dy * dy);
+        } else {
+            out[0] = dp * (fabs(A * dx) + fabs(B * dy));
+            out[1] = dp * (fabs(B * dx) + fabs(Cc * dy));
+            out[2] = dp * 0.5 * dx * dx;
+            out[3] = dp * fabs(dx * dy);
+            out[4] = dp * 0.5 * dy * dy;
+        }
+        return;
+    }
+    const double *r = a->srf + 9 * g;
+    const double a0 = r[2], a1 = r[3], b0 = r[4], b1 = r[5], e1 = r[7], e2 = r[8];
+    if (sk2 == 0.0) {
+        for (int k = 0; k < 9; ++k) out[k] = 0.0;
+        return;
+    }
+    const double l0 = -su / sk2, l1 = -sv / sk2, l2 = (su * su + sv * sv) / sk2;
+    if (!dp_is_mag) {
+        out[0] = -dp * (l0 * b1 - l1 * b0 - l2 * e2);
+        out[1] = -dp * (l1 * a0 - l0 * a1 - l2 * e1);
+        out[2] = dp * l1 * dy;
+        out[3] = -dp * l0 * dy;
+        out[4] = -dp * l1 * dx;
+        out[5] = dp * l0 * dx;
+        out[6] = dp * l2;
+        out[7] = -dp * l2 * dy;
+        out[8] = -dp * l2 * dx;
+    } else {
+        out[0] = dp * (fabs(l0 * b1) + fabs(l1 * b0) + fabs(l2 * e2));
+        out[1] = dp * (fabs(l1 * a0) + fabs(l0 * a1) + fabs(l2 * e1));
+        out[2] = dp * fabs(l1 * dy);
+        out[3] = dp * fabs(l0 * dy);
+        out[4] = dp * fabs(l1 * dx);
+        out[5] = dp * fabs(l0 * dx);
+        out[6] = dp * fabs(l2);
+        out[7] = dp * fabs(l2 * dy);
+        out[8] = dp * fabs(l2 * dx);
+    }
+}
 
 static void atomic_add(double *p, double x) {
 #pragma omp atomic
@@ -243,9 +345,8 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             /* ---- forward, front to back ---- */
             for (int64_t pos = start; pos < end; ++pos) {
                 const int64_t g = a->list[pos];
-                const double dx = x - a->u[g], dy = y - a->v[g];
-                const double power = -0.5 * (a->A[g] * dx * dx + 2.0 * a->B[g] * dx * dy + a->C[g] * dy * dy);
-                const double G = exp(power);
+                double dx, dy, su, sv, sk2;
+                const double G = density(a, g, x, y, &dx, &dy, &su, &sv, &sk2);
                 const double raw = a->opac[g] * G;
                 const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
                 local_counts[2]++;
@@ -256,13 +357,13 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 if (near_rel(raw, ALPHA_MAX, a->ambig_rel)) flags |= 2;
                 if (near_rel(alpha, ALPHA_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, 0, 0.0};
+                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, su, sv, sk2, 0, 0.0};
                 }
                 if (alpha < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - alpha);
                 if (near_rel(Tn, T_MIN, a->ambig_rel)) {
                     flags |= 1;
-                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, 1, 0.0};
+                    amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, su, sv, sk2, 1, 0.0};
                 }
                 if (Tn < T_MIN) break;
                 const double w = alpha * T;
@@ -276,6 +377,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     for (int64_t k = 0; k < d; ++k) Fm[k] += w * fabs(a->feat[g * d + k]);
                 blend_rec *r = &recs[nrec++];
                 r->g = g; r->pos = pos; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
+                r->su = su; r->sv = sv; r->sk2 = sk2;
                 r->clamped = raw >= ALPHA_MAX;
                 r->near_clamp = near_rel(raw, ALPHA_MAX, a->ambig_rel);
                 T = Tn;
@@ -355,29 +457,21 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     dop = dalpha * r->G;
                     dopm = dalpham * r->G;
                 }
-                const double dx = r->dx, dy = r->dy;
-                const double A = a->A[g], B = a->B[g], Cc = a->C[g];
-                /* power = -1/2 (A dx^2 + 2 B dx dy + C dy^2), dx = x - u */
-                gvec[0] = dpow * (A * dx + B * dy);
-                gvec[1] = dpow * (B * dx + Cc * dy);
-                gvec[2] = dpow * (-0.5 * dx * dx);
-                gvec[3] = dpow * (-dx * dy);
-                gvec[4] = dpow * (-0.5 * dy * dy);
-                gvec[5] = dop;
-                gmag[0] = dpowm * (fabs(A * dx) + fabs(B * dy));
-                gmag[1] = dpowm * (fabs(B * dx) + fabs(Cc * dy));
-                gmag[2] = dpowm * 0.5 * dx * dx;
-                gmag[3] = dpowm * fabs(dx * dy);
-                gmag[4] = dpowm * 0.5 * dy * dy;
-                gmag[5] = dopm;
+                /* power's partials (Gaussian: power = -1/2 (A dx^2 + 2 B dx dy + C dy^2),
+                   dx = x - u; surfel: see the header), then o and the colour */
+                const int64_t gw = gw_of(a), ng = gw - 4;
+                geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, dpow, 0, gvec);
+                geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, dpowm, 1, gmag);
+                gvec[ng] = dop;
+                gmag[ng] = dopm;
                 for (int c = 0; c < 3; ++c) {
-                    gvec[6 + c] = w * dC[c];
-                    gmag[6 + c] = fabs(w * dC[c]);
+                    gvec[ng + 1 + c] = w * dC[c];
+                    gmag[ng + 1 + c] = fabs(w * dC[c]);
                 }
                 if (a->g2d)
-                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d[9 * g + k], gvec[k]);
+                    for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d[gw * g + k], gvec[k]);
                 if (a->g2d_mag)
-                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_mag[9 * g + k], gmag[k]);
+                    for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_mag[gw * g + k], gmag[k]);
                 /* what a decision taken the other way in FP32 can change in this
                    contributor's terms: in an ambiguous pixel, q of its dL/dalpha
                    magnitude plus the blend each decider behind it would add to its
@@ -393,15 +487,11 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     }
                     if (r->near_clamp) damb += dalpham;
                     const double um = damb * r->alpha, om = damb * r->G;
-                    double am[9];
-                    am[0] = um * (fabs(A * dx) + fabs(B * dy));
-                    am[1] = um * (fabs(B * dx) + fabs(Cc * dy));
-                    am[2] = um * 0.5 * dx * dx;
-                    am[3] = um * fabs(dx * dy);
-                    am[4] = um * 0.5 * dy * dy;
-                    am[5] = om;
-                    for (int c = 0; c < 3; ++c) am[6 + c] = (flags & 1) ? q * gmag[6 + c] : 0.0;
-                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_amb[9 * g + k], am[k]);
+                    double am[13];
+                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, um, 1, am);
+                    am[ng] = om;
+                    for (int c = 0; c < 3; ++c) am[ng + 1 + c] = (flags & 1) ? q * gmag[ng + 1 + c] : 0.0;
+                    for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
                 }
                 if (a->dfeat && dF)
                     for (int64_t k = 0; k < d; ++k) atomic_add(&a->dfeat[g * d + k], w * dF[k]);
@@ -428,17 +518,13 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 const double w = e->alpha * e->T;
                 const double dalpham = e->T * gkm + (Sm + Tfin * fabs(dT)) / (1.0 - e->alpha);
                 const double um = dalpham * e->alpha, om = dalpham * e->G;
-                const double A = a->A[g], B = a->B[g], Cc = a->C[g], dx = e->dx, dy = e->dy;
                 if (a->g2d_amb) {
-                    double am[9];
-                    am[0] = um * (fabs(A * dx) + fabs(B * dy));
-                    am[1] = um * (fabs(B * dx) + fabs(Cc * dy));
-                    am[2] = um * 0.5 * dx * dx;
-                    am[3] = um * fabs(dx * dy);
-                    am[4] = um * 0.5 * dy * dy;
-                    am[5] = om;
-                    for (int c = 0; c < 3; ++c) am[6 + c] = w * fabs(dC[c]);
-                    for (int k = 0; k < 9; ++k) atomic_add(&a->g2d_amb[9 * g + k], am[k]);
+                    const int64_t gw = gw_of(a), ng = gw - 4;
+                    double am[13];
+                    geom_terms(a, g, e->dx, e->dy, e->su, e->sv, e->sk2, um, 1, am);
+                    am[ng] = om;
+                    for (int c = 0; c < 3; ++c) am[ng + 1 + c] = w * fabs(dC[c]);
+                    for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
                 }
                 if (tgt) {
                     if (a->fsum_amb)
@@ -472,7 +558,7 @@ int oracle_raster(const oracle_args *a) {
         double *nd = (double *)malloc(sizeof(double) * (size_t)(6 * (maxlen + 1) + 2 * (a->d + 1)));
         ndfd_scratch sc = {nd, nd + (maxlen + 1), nd + 2 * (maxlen + 1), nd + 3 * (maxlen + 1),
                            nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1), nd + 6 * (maxlen + 1)};
-        double gvec[9], gmag[9];
+        double gvec[13], gmag[13];
         if (!recs || !amb || !nd) {
 #pragma omp atomic write
             err = 1;

@@ -50,6 +50,7 @@ class _Args(ctypes.Structure):
         ("ndfd_gt", _P), ("feat_inv_norm", _P), ("ndfd_lambda", ctypes.c_double), ("ndfd_k", ctypes.c_double),
         ("ndfd_a", _P), ("ndfd_b", _P), ("out_Lgt", _P), ("out_Lcf", _P), ("out_Lcf_mag", _P), ("out_Lgt_mag", _P), ("out_FN", _P),
         ("out_WN", _P),
+        ("prim", _I), ("srf", _P),
     ]
 
 
@@ -93,7 +94,9 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     ranges [tiles, 2] and glist [M] are this view's slice of the binning (tile
     indices local to the view).  proj holds FP64 per-Gaussian u, v, A, B, C,
     opacity and rgb [N, 3] (and rgb_mag [N, 3], the magnitude companion of rgb,
-    when present).  Returns a dict of per-pixel and per-Gaussian arrays.
+    when present); for surfels (oracle.surfel) "srf" [N, 9] in place of u..C,
+    and the per-Gaussian adjoint rows have 13 entries instead of 9.  Returns a
+    dict of per-pixel and per-Gaussian arrays.
 
     ndfd (optional): dict(gt=[P, d] ground-truth feature map, lam, k, and
     a, b = [P] upstream weights of L_gt and L_cf, or None); adds L_gt, L_cf,
@@ -105,7 +108,9 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     TX = (W + consts.TILE - 1) // consts.TILE
     TY = (H + consts.TILE - 1) // consts.TILE
     P = W * H
-    n = proj["u"].shape[0]
+    surf = "srf" in proj
+    n = proj["opacity"].shape[0]
+    gw = 13 if surf else 9
     d = 0 if feat is None else int(feat.shape[1])
     keep = {}
 
@@ -115,8 +120,13 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
 
     ranges = k("ranges", np.ascontiguousarray(ranges, np.int64))
     glist = k("glist", np.ascontiguousarray(glist, np.int64))
-    u, v, A, B, C, op = (k(nm, _f64(proj[src])) for nm, src in
-                         (("u", "u"), ("v", "v"), ("A", "A"), ("B", "B"), ("C", "C"), ("op", "opacity")))
+    if surf:
+        u = v = A = B = C = None
+        srf = k("srf", _f64(proj["srf"]))
+    else:
+        u, v, A, B, C = (k(nm, _f64(proj[nm])) for nm in ("u", "v", "A", "B", "C"))
+        srf = None
+    op = k("op", _f64(proj["opacity"]))
     rgb = k("rgb", _f64(proj["rgb"]))
     rgbm = k("rgbm", _f64(proj.get("rgb_mag")))
     featd = k("feat", _f64(feat))
@@ -128,13 +138,13 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     out["F"] = np.zeros((P, d)) if (want_F and d) else None
     out["Fmag"] = np.zeros((P, d)) if (want_Fmag and d) else None
     bwd = dC is not None
-    out["g2d"] = np.zeros((n, 9)) if bwd else None
-    out["g2d_mag"] = np.zeros((n, 9)) if bwd else None
+    out["g2d"] = np.zeros((n, gw)) if bwd else None
+    out["g2d_mag"] = np.zeros((n, gw)) if bwd else None
     fus = bwd and target is not None and want_fusion and d > 0
     out["fsum"] = np.zeros((n, d)) if fus else None
     out["fsum_mag"] = np.zeros((n, d)) if fus else None
     out["wsum"] = np.zeros(n) if (bwd and target is not None) else None
-    out["g2d_amb"] = np.zeros((n, 9)) if bwd else None
+    out["g2d_amb"] = np.zeros((n, gw)) if bwd else None
     out["fsum_amb"] = np.zeros((n, d)) if fus else None
     out["wsum_amb"] = np.zeros(n) if (bwd and target is not None) else None
     out["dfeat"] = np.zeros((n, d)) if (bwd and want_dfeat and d) else None
@@ -170,6 +180,7 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         ndfd_a=_ptr(nd.get("a")), ndfd_b=_ptr(nd.get("b")), out_Lgt=_ptr(out.get("Lgt")),
         out_Lcf=_ptr(out.get("Lcf")), out_Lcf_mag=_ptr(out.get("Lcf_mag")), out_Lgt_mag=_ptr(out.get("Lgt_mag")), out_FN=_ptr(out.get("FN")),
         out_WN=_ptr(out.get("WN")),
+        prim=1 if surf else 0, srf=_ptr(srf),
     )
     rc = lib.oracle_raster(ctypes.byref(args))
     if rc != 0:

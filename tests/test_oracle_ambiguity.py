@@ -51,7 +51,7 @@ def _scene(seed, n=14, d=6, w=32, h=16):
 
 
 def _render(proj, feat, maps, w=32, h=16):
-    n = proj["u"].size
+    n = proj["opacity"].size
     tx = (w + consts.TILE - 1) // consts.TILE
     ranges = np.array([[0, n]] * tx)      # every Gaussian listed in every tile, index = depth order
     return raster.render_view(_Cam(w, h), ranges, np.arange(n), proj, feat=feat, **maps)
