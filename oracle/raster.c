@@ -50,7 +50,9 @@
  *     k2 = D - dy e1 - dx e2,  (u, v) = (k0, k1) / k2,
  *     G = exp(-(u^2 + v^2) / 2)  (0 where k2 = 0),
  * and the per-Gaussian adjoint rows hold the nine record entries, then o,
- * r, g, b (13 entries instead of 9).  With power = -(u^2 + v^2) / 2 and
+ * r, g, b (13 entries instead of 9).  Their magnitude companions carry the
+ * rounding of the intersection: k0, k1, k2 by the sums of their terms'
+ * magnitudes, and every division by k2 by a factor companion(k2) / k2^2.  With power = -(u^2 + v^2) / 2 and
  * lam = dL/dpower (-u / k2, -v / k2, (u^2 + v^2) / k2) = dL/dk:
  *     dL/dx_c = -(lam0 b1 - lam1 b0 - lam2 e2), dL/dy_c = -(lam1 a0 - lam0 a1 - lam2 e1),
  *     dL/da0 = lam1 dy, dL/da1 = -lam0 dy, dL/db0 = -lam1 dx, dL/db1 = lam0 dx,
@@ -236,15 +238,24 @@ static void geom_terms(const oracle_args *a, int64_t g, double dx, double dy, do
         out[7] = -dp * l2 * dy;
         out[8] = -dp * l2 * dx;
     } else {
-        out[0] = dp * (fabs(l0 * b1) + fabs(l1 * b0) + fabs(l2 * e2));
-        out[1] = dp * (fabs(l1 * a0) + fabs(l0 * a1) + fabs(l2 * e1));
-        out[2] = dp * fabs(l1 * dy);
-        out[3] = dp * fabs(l0 * dy);
-        out[4] = dp * fabs(l1 * dx);
-        out[5] = dp * fabs(l0 * dx);
-        out[6] = dp * fabs(l2);
-        out[7] = dp * fabs(l2 * dy);
-        out[8] = dp * fabs(l2 * dx);
+        /* companions of the intersection: k0, k1, k2 are sums (companion: the
+           sum of their terms' magnitudes) and every division by k2 carries
+           k2's relative rounding, so it multiplies by rr / |k2| with
+           rr = companion(k2) / |k2| (first order of a quotient, x/y: xm ym / y^2) */
+        const double k0m = fabs(dx * b1) + fabs(dy * a1), k1m = fabs(dy * a0) + fabs(dx * b0);
+        const double k2a = fabs(sk2), rr = (fabs(r[6]) + fabs(dy * e1) + fabs(dx * e2)) / k2a;
+        const double um = k0m * rr / k2a, vm = k1m * rr / k2a;
+        const double l0m = um * rr / k2a, l1m = vm * rr / k2a, l2m = (um * um + vm * vm) * rr / k2a;
+        (void)l0; (void)l1; (void)l2;
+        out[0] = dp * (l0m * fabs(b1) + l1m * fabs(b0) + l2m * fabs(e2));
+        out[1] = dp * (l1m * fabs(a0) + l0m * fabs(a1) + l2m * fabs(e1));
+        out[2] = dp * l1m * fabs(dy);
+        out[3] = dp * l0m * fabs(dy);
+        out[4] = dp * l1m * fabs(dx);
+        out[5] = dp * l0m * fabs(dx);
+        out[6] = dp * l2m;
+        out[7] = dp * l2m * fabs(dy);
+        out[8] = dp * l2m * fabs(dx);
     }
 }
 
