@@ -25,3 +25,11 @@ KAPPA_F32 = np.float32(KAPPA)
 # relative distance to a threshold below which a float32-vs-FP64 decision is
 # called ambiguous (alpha >= ALPHA_MIN, T' < T_MIN, the ALPHA_MAX clamp)
 AMBIG_REL = 1e-4
+
+# density-rounding allowance of the surfel primitive, per unit of its
+# first-order sensitivity (oracle/raster.c's header): an FP32 implementation
+# rounds each record entry once and each product and sum of k0, k1, k2 once
+# more (at most 3 roundings of each term's magnitude), and the quotient
+# u = k0 / k2 adds the relative errors of both, so 6 units of FP32 roundoff
+# bound u's error by 6 u32 um to first order
+DEN_ROUND = 6.0 * 2.0 ** -24

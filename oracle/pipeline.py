@@ -34,6 +34,9 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
     gflags: bit 0 the Gaussian decides a near-threshold skip/stop decision,
     bit 2 its colour clamp is near-threshold; grads_amb / fsum_amb / wsum_amb
     bound what near-threshold decisions of other Gaussians could change.
+    Every view carries Cden, Tden and Fden: the allowance for the surfel
+    density's rounding through the ray-plane intersection (zero for
+    Gaussians); the adjoint's share of it is in grads_amb, fsum_amb, wsum_amb.
     """
     bins = binspec.bin_views(g, cams, bin_rule)
     feat = np.asarray(g["feat"], np.float64) if g["feat"] is not None else None
@@ -65,7 +68,8 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
         gflags |= out["gflags"]
         # bit 2: the colour clamp of a Gaussian that this view binned is ambiguous
         gflags |= np.where(pr["clamp_amb"] & bins["per_view"][vi]["binned"], 4, 0).astype(np.int32)
-        rec = dict(C=out["C"], Cmag=out["Cmag"], F=out["F"], Fmag=out["Fmag"], T=out["T"], niter=out["niter"],
+        rec = dict(C=out["C"], Cmag=out["Cmag"], Cden=out["Cden"], F=out["F"], Fmag=out["Fmag"], Fden=out["Fden"],
+                   T=out["T"], Tden=out["Tden"], niter=out["niter"],
                    flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"], g2d_amb=out["g2d_amb"])
         for key in ("Lgt", "Lcf", "Lcf_mag", "Lgt_mag", "FN", "WN"):
             if key in out:

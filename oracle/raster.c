@@ -58,6 +58,24 @@
  *     dL/da0 = lam1 dy, dL/da1 = -lam0 dy, dL/db0 = -lam1 dx, dL/db1 = lam0 dx,
  *     dL/dD = lam2, dL/de1 = -lam2 dy, dL/de2 = -lam2 dx.
  *
+ * Density rounding (surfels): an FP32 implementation rounds each record entry
+ * once, and near a grazing ray k2's cancellation amplifies that without bound.
+ * To first order the density's relative error is den_round * gr with
+ *     gr = (u^2 + v^2) / 2 + |u| um + |v| vm
+ * (um, vm the companions of u, v above; den_round = a stated multiple of the
+ * FP32 unit roundoff, oracle/consts.py).  An unclamped alpha inherits gr, the
+ * transmittance in front of a blend tr = sum over the earlier blends of
+ * alpha gr / (1 - alpha) (first order of the product of the 1 - alpha), a
+ * blend weight w = alpha T the sum gr + tr.  The resulting first-order changes
+ * of everything built from alpha, T and w are an absolute allowance, like the
+ * near-threshold one: den_round times these sensitivities go to out_Cden,
+ * out_Fden, out_Tden (forward) and are added into g2d_amb, fsum_amb and
+ * wsum_amb (adjoint: the dL/dalpha, power, opacity and colour terms and the
+ * fusion sums).  gr reaches 1e5 and more next to a grazing ray and stays near
+ * (u^2 + v^2) / 2 for a surfel seen face-on.  A Gaussian's power is a short
+ * quadratic form whose rounding stays within a few units of |power| and inside
+ * the tolerance: gr = 0 there.
+ *
  * Every floating-point operation is FP64.  Magnitude companions (sums of the
  * absolute values of the same terms) are accumulated alongside.
  *
@@ -141,6 +159,11 @@ typedef struct {
     /* primitive: 0 Gaussian (u, v, A, B, C above), 1 surfel (srf below) */
     int64_t prim;
     const double *srf;               /* [N, 9] surfel records (prim 1) */
+    /* density-rounding allowance (header): den_round 0 switches it off */
+    double den_round;
+    double *out_Cden;                /* [P, 3] or NULL */
+    double *out_Fden;                /* [P, d] or NULL */
+    double *out_Tden;                /* [P] or NULL */
 } oracle_args;
 
 /* entries of a per-Gaussian adjoint row: (u v A B C | 9 surfel entries), o, r, g, b */
@@ -156,6 +179,7 @@ typedef struct {
     int64_t g, pos;
     double alpha, T, G, dx, dy;
     double su, sv, sk2;      /* surfel: plane coordinates and k2 */
+    double ar, tr;           /* density-rounding sensitivities of alpha and of T at the blend (header) */
     int clamped, near_clamp;
 } blend_rec;
 
@@ -169,10 +193,24 @@ typedef struct {
     double gkm;      /* magnitude of its g_k in this pixel (filled by the adjoint) */
 } amb_rec;
 
+/* companions of a surfel's intersection at pixel offsets (dx, dy): k0, k1, k2
+   are sums (companion: the sum of their terms' magnitudes) and every division
+   by k2 carries k2's relative rounding, rr = companion(k2) / |k2| (first order
+   of a quotient x / y: xm ym / y^2); um, vm are the companions of u, v */
+static void surfel_comp(const double *r, double dx, double dy, double sk2, double *um, double *vm, double *rr) {
+    const double k0m = fabs(dx * r[5]) + fabs(dy * r[3]), k1m = fabs(dy * r[2]) + fabs(dx * r[4]);
+    const double k2a = fabs(sk2);
+    *rr = (fabs(r[6]) + fabs(dy * r[7]) + fabs(dx * r[8])) / k2a;
+    *um = k0m * *rr / k2a;
+    *vm = k1m * *rr / k2a;
+}
+
 /* density of primitive g at pixel centre (x, y); the pixel offsets and (for
-   surfels) the plane coordinates go to *dx, *dy, *su, *sv, *sk2 */
+   surfels) the plane coordinates go to *dx, *dy, *su, *sv, *sk2, and the
+   density's rounding sensitivity to *gr (0 for a Gaussian: see the header) */
 static double density(const oracle_args *a, int64_t g, double x, double y, double *dx, double *dy, double *su,
-                      double *sv, double *sk2) {
+                      double *sv, double *sk2, double *gr) {
+    *gr = 0.0;
     if (!a->prim) {
         *dx = x - a->u[g];
         *dy = y - a->v[g];
@@ -194,6 +232,9 @@ static double density(const oracle_args *a, int64_t g, double x, double y, doubl
     }
     *su = k0 / k2;
     *sv = k1 / k2;
+    double um, vm, rr;
+    surfel_comp(r, *dx, *dy, k2, &um, &vm, &rr);
+    *gr = 0.5 * (*su * *su + *sv * *sv) + fabs(*su) * um + fabs(*sv) * vm;
     return exp(-0.5 * (*su * *su + *sv * *sv));
 }
 
@@ -238,13 +279,11 @@ static void geom_terms(const oracle_args *a, int64_t g, double dx, double dy, do
         out[7] = -dp * l2 * dy;
         out[8] = -dp * l2 * dx;
     } else {
-        /* companions of the intersection: k0, k1, k2 are sums (companion: the
-           sum of their terms' magnitudes) and every division by k2 carries
-           k2's relative rounding, so it multiplies by rr / |k2| with
-           rr = companion(k2) / |k2| (first order of a quotient, x/y: xm ym / y^2) */
-        const double k0m = fabs(dx * b1) + fabs(dy * a1), k1m = fabs(dy * a0) + fabs(dx * b0);
-        const double k2a = fabs(sk2), rr = (fabs(r[6]) + fabs(dy * e1) + fabs(dx * e2)) / k2a;
-        const double um = k0m * rr / k2a, vm = k1m * rr / k2a;
+        /* the intersection's companions; the lam's divisions by k2 carry
+           k2's relative rounding rr once more */
+        double um, vm, rr;
+        surfel_comp(r, dx, dy, sk2, &um, &vm, &rr);
+        const double k2a = fabs(sk2);
         const double l0m = um * rr / k2a, l1m = vm * rr / k2a, l2m = (um * um + vm * vm) * rr / k2a;
         (void)l0; (void)l1; (void)l2;
         out[0] = dp * (l0m * fabs(b1) + l1m * fabs(b0) + l2m * fabs(e2));
@@ -353,13 +392,18 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             if (Fm) memset(Fm, 0, sizeof(double) * d);
             int64_t niter = 0, nrec = 0, namb = 0;
             int32_t flags = 0;
+            double tau = 0.0;   /* density-rounding sensitivity of T (header) */
+            double cden[3] = {0, 0, 0};
+            double *Fd = a->out_Fden ? a->out_Fden + pix * d : NULL;
+            if (Fd) memset(Fd, 0, sizeof(double) * d);
             /* ---- forward, front to back ---- */
             for (int64_t pos = start; pos < end; ++pos) {
                 const int64_t g = a->list[pos];
-                double dx, dy, su, sv, sk2;
-                const double G = density(a, g, x, y, &dx, &dy, &su, &sv, &sk2);
+                double dx, dy, su, sv, sk2, gr;
+                const double G = density(a, g, x, y, &dx, &dy, &su, &sv, &sk2, &gr);
                 const double raw = a->opac[g] * G;
                 const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
+                const double ar = raw < ALPHA_MAX ? gr : 0.0;
                 local_counts[2]++;
                 /* a decision this close to its threshold may go either way in FP32:
                    the clamp only changes g's own terms in this pixel (pixel bit 1,
@@ -377,18 +421,22 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     amb[namb++] = (amb_rec){g, pos, alpha, T, G, dx, dy, su, sv, sk2, 1, 0.0};
                 }
                 if (Tn < T_MIN) break;
-                const double w = alpha * T;
+                const double w = alpha * T, wd = w * (ar + tau);
                 for (int c = 0; c < 3; ++c) {
                     col[c] += w * a->rgb[3 * g + c];
                     colm[c] += w * rgbm(a, g, c);
+                    cden[c] += wd * rgbm(a, g, c);
                 }
                 if (F && a->feat)
                     for (int64_t k = 0; k < d; ++k) F[k] += w * a->feat[g * d + k];
                 if (Fm && a->feat)
                     for (int64_t k = 0; k < d; ++k) Fm[k] += w * fabs(a->feat[g * d + k]);
+                if (Fd && a->feat)
+                    for (int64_t k = 0; k < d; ++k) Fd[k] += wd * fabs(a->feat[g * d + k]) * a->den_round;
                 blend_rec *r = &recs[nrec++];
                 r->g = g; r->pos = pos; r->alpha = alpha; r->T = T; r->G = G; r->dx = dx; r->dy = dy;
-                r->su = su; r->sv = sv; r->sk2 = sk2;
+                r->su = su; r->sv = sv; r->sk2 = sk2; r->ar = ar; r->tr = tau;
+                tau += alpha * ar / (1.0 - alpha);
                 r->clamped = raw >= ALPHA_MAX;
                 r->near_clamp = near_rel(raw, ALPHA_MAX, a->ambig_rel);
                 T = Tn;
@@ -400,6 +448,9 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             if (a->out_Cmag)
                 for (int c = 0; c < 3; ++c) a->out_Cmag[3 * pix + c] = colm[c];
             a->out_T[pix] = T;
+            if (a->out_Tden) a->out_Tden[pix] = a->den_round * T * tau;
+            if (a->out_Cden)
+                for (int c = 0; c < 3; ++c) a->out_Cden[3 * pix + c] = a->den_round * cden[c];
             a->out_niter[pix] = niter;
             if (a->out_flags) a->out_flags[pix] = flags;
             /* the Gaussians that decide a near-threshold skip/stop may gain or lose
@@ -420,7 +471,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
             const double dT = a->dT ? a->dT[pix] : 0.0;
             const double *tgt = a->target ? a->target + pix * d : NULL;
             const double Tfin = T;
-            double S = 0.0, Sm = 0.0;
+            double S = 0.0, Sm = 0.0, Sd = 0.0;
             /* another skip decision by decider j scales every later T (and T_final)
                by (1 - alpha_j), i.e. changes them by at most alpha_j / (1 - alpha_j)
                relative; another stop decision changes T_final by up to 100%; q is
@@ -459,14 +510,22 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 const double inv1ma = 1.0 / (1.0 - r->alpha);
                 const double dalpha = r->T * gk - (S + Tfin * dT) * inv1ma;
                 const double dalpham = r->T * gkm + (Sm + Tfin * fabs(dT)) * inv1ma;
+                /* density-rounding sensitivity of dL/dalpha: T's, S's and Tfin's,
+                   and that of 1 / (1 - alpha) */
+                const double dalphad = r->T * r->tr * gkm + (Sd + Tfin * tau * fabs(dT)) * inv1ma +
+                                       (Sm + Tfin * fabs(dT)) * inv1ma * r->alpha * r->ar * inv1ma;
+                const double wd = w * (r->ar + r->tr);
                 S += w * gk;
                 Sm += w * gkm;
-                double dpow = 0.0, dpowm = 0.0, dop = 0.0, dopm = 0.0;
+                Sd += wd * gkm;
+                double dpow = 0.0, dpowm = 0.0, dop = 0.0, dopm = 0.0, dpowd = 0.0, dopd = 0.0;
                 if (!r->clamped) {
                     dpow = dalpha * r->alpha;
                     dpowm = dalpham * r->alpha;
                     dop = dalpha * r->G;
                     dopm = dalpham * r->G;
+                    dpowd = (dalphad + dalpham * r->ar) * r->alpha;
+                    dopd = (dalphad + dalpham * r->ar) * r->G;
                 }
                 /* power's partials (Gaussian: power = -1/2 (A dx^2 + 2 B dx dy + C dy^2),
                    dx = x - u; surfel: see the header), then o and the colour */
@@ -483,6 +542,13 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d[gw * g + k], gvec[k]);
                 if (a->g2d_mag)
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_mag[gw * g + k], gmag[k]);
+                if (a->g2d_amb && a->den_round > 0.0 && (dalphad > 0.0 || wd > 0.0)) {
+                    double am[13];
+                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, a->den_round * dpowd, 1, am);
+                    am[ng] = a->den_round * dopd;
+                    for (int c = 0; c < 3; ++c) am[ng + 1 + c] = a->den_round * fabs(wd * dC[c]);
+                    for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
+                }
                 /* what a decision taken the other way in FP32 can change in this
                    contributor's terms: in an ambiguous pixel, q of its dL/dalpha
                    magnitude plus the blend each decider behind it would add to its
@@ -512,6 +578,12 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     if (a->fsum_mag)
                         for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_mag[g * d + k], fabs(w * tgt[k]));
                     if (a->wsum) atomic_add(&a->wsum[g], w);
+                    if (wd > 0.0 && a->den_round > 0.0) {
+                        if (a->fsum_amb)
+                            for (int64_t k = 0; k < d; ++k)
+                                atomic_add(&a->fsum_amb[g * d + k], a->den_round * fabs(wd * tgt[k]));
+                        if (a->wsum_amb) atomic_add(&a->wsum_amb[g], a->den_round * wd);
+                    }
                     if (flags & 1) {
                         if (a->fsum_amb)
                             for (int64_t k = 0; k < d; ++k) atomic_add(&a->fsum_amb[g * d + k], q * fabs(w * tgt[k]));

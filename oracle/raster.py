@@ -51,6 +51,7 @@ class _Args(ctypes.Structure):
         ("ndfd_a", _P), ("ndfd_b", _P), ("out_Lgt", _P), ("out_Lcf", _P), ("out_Lcf_mag", _P), ("out_Lgt_mag", _P), ("out_FN", _P),
         ("out_WN", _P),
         ("prim", _I), ("srf", _P),
+        ("den_round", ctypes.c_double), ("out_Cden", _P), ("out_Fden", _P), ("out_Tden", _P),
     ]
 
 
@@ -96,7 +97,8 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     opacity and rgb [N, 3] (and rgb_mag [N, 3], the magnitude companion of rgb,
     when present); for surfels (oracle.surfel) "srf" [N, 9] in place of u..C,
     and the per-Gaussian adjoint rows have 13 entries instead of 9.  Returns a
-    dict of per-pixel and per-Gaussian arrays.
+    dict of per-pixel and per-Gaussian arrays; Cden, Tden and Fden (with Fmag)
+    are the surfel density's rounding allowance (zero for Gaussians).
 
     ndfd (optional): dict(gt=[P, d] ground-truth feature map, lam, k, and
     a, b = [P] upstream weights of L_gt and L_cf, or None); adds L_gt, L_cf,
@@ -133,10 +135,12 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
     dCd, dFd, dTd, tg = (k(nm, _f64(x)) for nm, x in (("dC", dC), ("dF", dF), ("dT", dT), ("tg", target)))
     sel = k("sel", None if tile_sel is None else np.ascontiguousarray(tile_sel, np.int64))
 
-    out = dict(C=np.zeros((P, 3)), Cmag=np.zeros((P, 3)), T=np.zeros(P), niter=np.zeros(P, np.int64),
+    out = dict(C=np.zeros((P, 3)), Cmag=np.zeros((P, 3)), Cden=np.zeros((P, 3)), T=np.zeros(P),
+               Tden=np.zeros(P), niter=np.zeros(P, np.int64),
                flags=np.zeros(P, np.int32), counts=np.zeros(3, np.int64))
     out["F"] = np.zeros((P, d)) if (want_F and d) else None
     out["Fmag"] = np.zeros((P, d)) if (want_Fmag and d) else None
+    out["Fden"] = np.zeros((P, d)) if (want_Fmag and d) else None
     bwd = dC is not None
     out["g2d"] = np.zeros((n, gw)) if bwd else None
     out["g2d_mag"] = np.zeros((n, gw)) if bwd else None
@@ -181,6 +185,8 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         out_Lcf=_ptr(out.get("Lcf")), out_Lcf_mag=_ptr(out.get("Lcf_mag")), out_Lgt_mag=_ptr(out.get("Lgt_mag")), out_FN=_ptr(out.get("FN")),
         out_WN=_ptr(out.get("WN")),
         prim=1 if surf else 0, srf=_ptr(srf),
+        den_round=consts.DEN_ROUND, out_Cden=_ptr(out["Cden"]), out_Fden=_ptr(out["Fden"]),
+        out_Tden=_ptr(out["Tden"]),
     )
     rc = lib.oracle_raster(ctypes.byref(args))
     if rc != 0:
