@@ -79,6 +79,24 @@ typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
  *                   to [sqrt(1/2), sqrt 2) and the atanh series to s^9). */
 typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
 
+/* Primitive (fh_plan.primitive, set by fh_plan_set_primitive).
+ *   FH_PRIM_GAUSSIAN  3D Gaussians with the EWA screen-space projection
+ *   FH_PRIM_SURFEL    the paper's planar primitives (Section 3.1): centre
+ *                     (means), tangents t_u, t_v = the first two columns of
+ *                     the quaternion's rotation, planar scales s_u, s_v =
+ *                     scales[:, 0:2] (scales[:, 2] takes no part and gets a
+ *                     zero gradient); a pixel takes the density
+ *                     exp(-(u^2 + v^2)/2) of the point (u, v) of the
+ *                     surfel's plane that its ray meets (the ray-plane
+ *                     intersection x = W H (u, v, 1, 1)^T); depth order by
+ *                     the centre's camera depth; tile rects bound the image
+ *                     of the disc u^2 + v^2 <= kappa_i (the opacity-aware
+ *                     kappa_i of FH_BIN_OPACITY, whatever bin_rule says),
+ *                     and surfels whose disc reaches the camera plane are
+ *                     culled.  FP32 form only (FH_E_UNSUPPORTED otherwise);
+ *                     no NDFD branch. */
+typedef enum { FH_PRIM_GAUSSIAN = 0, FH_PRIM_SURFEL = 1 } fh_primitive;
+
 /* Arithmetic form of the compositing kernels. */
 typedef enum {
     FH_FORM_F32 = 0,        /* FP32 blending; the adjoint and fusion on the FP32 VALU; the forward on MFMA with
@@ -155,6 +173,7 @@ typedef struct {
     int32_t packed_keys;             /* 1: one u32 key (tile << rank_bits | rank); 0: u32 tile + u32 rank */
     int32_t bin_rule;                /* fh_bin_rule; fh_plan_init sets FH_BIN_BOX, callers may change it */
     int32_t ndfd;                    /* 1: the workspace holds the NDFD gradient storage (fh_plan_set_ndfd) */
+    int32_t primitive;               /* fh_primitive; fh_plan_init sets FH_PRIM_GAUSSIAN (fh_plan_set_primitive) */
     int64_t inst_capacity;           /* max (Gaussian, tile) instances over all views */
     int64_t visit_capacity;          /* max instances visited by the backward (per-instance partials) */
     int64_t n_pixels, n_tiles;
@@ -240,13 +259,14 @@ typedef struct {
 
 /* Buffers inside the workspace that callers may inspect (fh_get_buffer). */
 typedef enum {
-    FH_BUF_RECORDS = 0,      /* float4 [V*n*3] screen-space records */
+    FH_BUF_RECORDS = 0,      /* float4 [V*n*3] screen-space records (surfels: [V*n*4]) */
     FH_BUF_DEPTH_KEY = 1,    /* u32 [V*n] float32 depth bits, 0xFFFFFFFF if culled */
     FH_BUF_RECT = 2,         /* i32 [V*n*4] tile rect x0, y0, x1, y1 (inclusive; x0 > x1 if culled) */
     FH_BUF_DEPTH_ORDER = 3,  /* u32 [V*n] Gaussian index, per view sorted by (depth, index) */
     FH_BUF_RANGES = 4,       /* u32 [tiles,2] [start, end) into the sorted instances */
     FH_BUF_TILE_NITER = 5,   /* u32 [tiles] max n_iter over the tile's pixels (after render_fwd) */
-    FH_BUF_GRAD2D = 6        /* float [V*n,12] per-(view, Gaussian) screen-space adjoints (after render_bwd) */
+    FH_BUF_GRAD2D = 6        /* float [V*n,12] per-(view, Gaussian) screen-space adjoints (after render_bwd;
+                                surfels: [V*n,16]) */
 } fh_buffer;
 
 /* Fill `plan` for n Gaussians and n_views cameras (host array `cams`).
@@ -265,6 +285,14 @@ fh_status fh_plan_init(fh_plan *plan, int64_t n, int32_t sh_degree, int32_t d, f
  * visit_capacity.  Recomputes the workspace layout (ws_bytes); set it before
  * allocating the workspace.  fh_ndfd_losses needs no storage. */
 fh_status fh_plan_set_ndfd(fh_plan *plan, int32_t enable);
+
+/* Choose the primitive (fh_primitive; Section 3.1's surfels or 3D Gaussians)
+ * of a plan from fh_plan_init.  Surfels need the FP32 form and a plan without
+ * the NDFD storage (FH_E_UNSUPPORTED otherwise); their records take 64 B per
+ * (view, primitive) and their per-instance partials 64 B per visited
+ * instance.  Resets the launch shape to the primitive's default and
+ * recomputes the workspace layout; set it before allocating the workspace. */
+fh_status fh_plan_set_primitive(fh_plan *plan, int32_t primitive);
 
 /* Project every (view, Gaussian) (Algorithm 2: Homogenization and
  * 2DScreenGaussians; the screen-space Gaussian of Section 3.1).  Writes the

@@ -21,6 +21,7 @@ FH_STATIC_SCRATCH_BYTES = 64 << 20
 FH_F32, FH_BF16 = 0, 1
 FH_FORM_F32, FH_FORM_BF16 = 0, 1
 FH_BIN_BOX, FH_BIN_OPACITY = 0, 1
+FH_PRIM_GAUSSIAN, FH_PRIM_SURFEL = 0, 1
 (FH_K_PROJECT, FH_K_BIN, FH_K_RENDER_FWD, FH_K_RENDER_BWD, FH_K_REDUCE, FH_K_PROJECT_BWD, FH_K_NDFD) = range(7)
 (FH_BUF_RECORDS, FH_BUF_DEPTH_KEY, FH_BUF_RECT, FH_BUF_DEPTH_ORDER, FH_BUF_RANGES,
  FH_BUF_TILE_NITER, FH_BUF_GRAD2D) = range(7)
@@ -46,7 +47,7 @@ class FhTuning(ctypes.Structure):
 class FhPlan(ctypes.Structure):
     _fields_ = [("n", _i64), ("n_views", _i32), ("d", _i32), ("sh_degree", _i32), ("feat_dtype", _i32),
                 ("form", _i32), ("rank_bits", _i32), ("tile_bits", _i32), ("packed_keys", _i32),
-                ("bin_rule", _i32), ("ndfd", _i32), ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
+                ("bin_rule", _i32), ("ndfd", _i32), ("primitive", _i32), ("inst_capacity", _i64), ("visit_capacity", _i64), ("n_pixels", _i64), ("n_tiles", _i64),
                 ("cams", FhCamera * FH_MAX_VIEWS), ("pix_off", _i64 * (FH_MAX_VIEWS + 1)),
                 ("tile_off", _i64 * (FH_MAX_VIEWS + 1)), ("tiles_x", _i32 * FH_MAX_VIEWS),
                 ("tiles_y", _i32 * FH_MAX_VIEWS), ("tuning", FhTuning), ("n_ws", _i32), ("off", _sz * FH_WS_SLOTS),
@@ -91,6 +92,7 @@ _P = ctypes.POINTER
 SIGNATURES = {
     "fh_plan_init": (_i32, [_P(FhPlan), _i64, _i32, _i32, _i32, _i32, _P(FhCamera), _i32, _i64, _i64]),
     "fh_plan_set_ndfd": (_i32, [_P(FhPlan), _i32]),
+    "fh_plan_set_primitive": (_i32, [_P(FhPlan), _i32]),
     "fh_project": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _vp]),
     "fh_bin_count": (_i32, [_P(FhPlan), _vp, _vp]),
     "fh_bin_sort": (_i32, [_P(FhPlan), _vp, _vp]),

@@ -127,17 +127,23 @@ static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
 // at the widths its channel slices divide (the features enter as three BF16
 // terms).  FP32-form runs with BF16-stored features keep the VALU forward: with
 // only the weights split the error would reach ~0.8 of the FP32 rule.
-static bool mfma_forward(int d, int form, int feat_dtype) {
+// float4 per screen record and floats per per-instance partial row
+static int rec_w(const fh_plan* p) { return p->primitive == FH_PRIM_SURFEL ? 4 : 3; }
+static int geom_w(const fh_plan* p) { return p->primitive == FH_PRIM_SURFEL ? 16 : 12; }
+
+// (Surfels, FP32 form only, composite on the VALU forward.)
+static bool mfma_forward(int d, int form, int feat_dtype, int prim) {
+    if (prim == FH_PRIM_SURFEL) return false;
     return form == FH_FORM_BF16 ||
            (feat_dtype == FH_F32 && (d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0)));
 }
 
-static fh_tuning default_tuning(int d, int form, int feat_dtype) {
+static fh_tuning default_tuning(int d, int form, int feat_dtype, int prim) {
     fh_tuning t;
     memset(&t, 0, sizeof(t));
     t.fwd_rows = 16;
     if (d > 0) {
-        if (mfma_forward(d, form, feat_dtype)) {
+        if (mfma_forward(d, form, feat_dtype, prim)) {
             if (d == 32 || d == 64 || d == 96) {
                 t.fwd_slice = d;
             } else {
@@ -153,10 +159,10 @@ static fh_tuning default_tuning(int d, int form, int feat_dtype) {
     return t;
 }
 
-static bool fwd_shape_ok(int d, int form, int feat_dtype, int slice, int rows) {
+static bool fwd_shape_ok(int d, int form, int feat_dtype, int prim, int slice, int rows) {
     if (d == 0) return slice == 0 && rows == 16;
     // (FP32 features: 16 rows of 128 channels is not offered, it would spill)
-    if (mfma_forward(d, form, feat_dtype))
+    if (mfma_forward(d, form, feat_dtype, prim))
         return render_fwd_bf16_shape_ok(d, slice, rows) && !(form == FH_FORM_F32 && rows == 16 && slice == 128) &&
                !(form == FH_FORM_F32 && rows == 4);
     return rows == 16 && (slice == 8 || slice == 16 || slice == 32 || slice == 64);
@@ -165,7 +171,7 @@ static bool fwd_shape_ok(int d, int form, int feat_dtype, int slice, int rows) {
 static bool bwd_chunk_ok(int d, int chunk) { return chunk == 16 || (chunk == 32 && d <= 512); }
 
 static bool tuning_ok(const fh_plan* p) {
-    return fwd_shape_ok(p->d, p->form, p->feat_dtype, p->tuning.fwd_slice, p->tuning.fwd_rows) &&
+    return fwd_shape_ok(p->d, p->form, p->feat_dtype, p->primitive, p->tuning.fwd_slice, p->tuning.fwd_rows) &&
            bwd_chunk_ok(p->d, p->tuning.bwd_chunk) && (p->tuning.schedule == 0 || p->tuning.schedule == 1);
 }
 
@@ -200,7 +206,7 @@ static void bin_count_impl(const fh_plan* p, void* ws, hipStream_t s) {
     device_exclusive_scan(ntiles, buf<uint32_t>(p, ws, WS_INST_OFF), total, scan_tmp, 1, s);
     launch_check_capacity(c, p->inst_capacity, s);
     launch_rank_tables(cbuf<uint32_t>(p, ws, WS_ORDER), cbuf<float4>(p, ws, WS_REC), p->n, total,
-                       buf<uint32_t>(p, ws, WS_RANK_OF), buf<float4>(p, ws, WS_RREC), s);
+                       buf<uint32_t>(p, ws, WS_RANK_OF), buf<float4>(p, ws, WS_RREC), rec_w(p), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +261,8 @@ static void plan_layout(fh_plan* plan) {
     memset(sz, 0, sizeof(sz));
     const size_t u4 = sizeof(uint32_t);
     sz[WS_COUNTERS] = 256;
-    sz[WS_REC] = (size_t)total * 3 * 16;
+    const size_t rw = (size_t)rec_w(plan), gw = (size_t)geom_w(plan);
+    sz[WS_REC] = (size_t)total * rw * 16;
     sz[WS_DEPTH_KEY] = (size_t)total * u4;
     sz[WS_RECT] = (size_t)total * 16;
     sz[WS_ORDER] = sz[WS_ORDER_TMP] = sz[WS_DKEY_TMP] = sz[WS_DKEY_TMP2] = (size_t)total * u4;
@@ -270,18 +277,18 @@ static void plan_layout(fh_plan* plan) {
     sz[WS_RANGES] = (size_t)tiles * 2 * u4;
     sz[WS_TILE_NITER] = (size_t)tiles * u4;
     sz[WS_TILE_VOFF] = (size_t)(tiles + 1) * u4;
-    sz[WS_GRAD2D] = (size_t)total * 12 * sizeof(float);
+    sz[WS_GRAD2D] = (size_t)total * gw * sizeof(float);
     sz[WS_RANK_OF] = (size_t)total * u4;
     sz[WS_KEYS_A] = sz[WS_KEYS_B] = (size_t)inst_capacity * u4;
     sz[WS_VALS_A] = sz[WS_VALS_B] = plan->packed_keys ? 0 : (size_t)inst_capacity * u4;
     sz[WS_VSEG] = (size_t)total * 2 * u4;
     sz[WS_LONG] = (size_t)(total + 3 * n) * u4;
     sz[WS_VKEY_A] = sz[WS_VKEY_B] = sz[WS_VVAL_A] = sz[WS_VVAL_B] = (size_t)visit_capacity * u4;
-    sz[WS_PART_GEOM] = (size_t)visit_capacity * 12 * sizeof(float);
+    sz[WS_PART_GEOM] = (size_t)visit_capacity * gw * sizeof(float);
     sz[WS_PART_FUSE] = (size_t)visit_capacity * d * sizeof(float);
-    sz[WS_VREC] = (size_t)visit_capacity * 3 * 16;
+    sz[WS_VREC] = (size_t)visit_capacity * rw * 16;
     sz[WS_VGID] = (size_t)visit_capacity * u4;
-    sz[WS_RREC] = (size_t)total * 3 * 16;
+    sz[WS_RREC] = (size_t)total * rw * 16;
     sz[WS_UNIT_OWNER] = (size_t)fuse_unit_capacity(visit_capacity) * u4;
     sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
     // NDFD gradient storage (fh_plan_set_ndfd): per-part partials and the
@@ -346,7 +353,7 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
     plan->rank_bits = ceil_log2(total > 1 ? total : 2);
     plan->tile_bits = ceil_log2(tiles > 1 ? tiles : 2);
     plan->packed_keys = (plan->rank_bits + plan->tile_bits) <= 32 ? 1 : 0;
-    plan->tuning = default_tuning(d, form, feat_dtype);
+    plan->tuning = default_tuning(d, form, feat_dtype, FH_PRIM_GAUSSIAN);
 
     plan_layout(plan);
     return FH_OK;
@@ -354,7 +361,18 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
 
 fh_status fh_plan_set_ndfd(fh_plan* plan, int32_t enable) {
     if (!plan) return FH_E_INVALID;
+    if (enable && plan->primitive == FH_PRIM_SURFEL) return FH_E_UNSUPPORTED;
     plan->ndfd = enable ? 1 : 0;
+    plan_layout(plan);
+    return FH_OK;
+}
+
+fh_status fh_plan_set_primitive(fh_plan* plan, int32_t primitive) {
+    if (!plan) return FH_E_INVALID;
+    if (primitive != FH_PRIM_GAUSSIAN && primitive != FH_PRIM_SURFEL) return FH_E_INVALID;
+    if (primitive == FH_PRIM_SURFEL && (plan->form != FH_FORM_F32 || plan->ndfd)) return FH_E_UNSUPPORTED;
+    plan->primitive = primitive;
+    plan->tuning = default_tuning(plan->d, plan->form, plan->feat_dtype, primitive);
     plan_layout(plan);
     return FH_OK;
 }
@@ -374,6 +392,7 @@ fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStrea
     a.n = (int)p->n;
     a.sh_degree = p->sh_degree;
     a.bin_rule = p->bin_rule;
+    a.prim = p->primitive;
     a.rec = buf<float4>(p, ws, WS_REC);
     a.depth_key = buf<uint32_t>(p, ws, WS_DEPTH_KEY);
     a.rect = buf<int4>(p, ws, WS_RECT);
@@ -465,12 +484,13 @@ fh_status fh_render_fwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     uint32_t* tile_niter = buf<uint32_t>(p, ws, WS_TILE_NITER);
     a.tile_niter = tile_niter;
     a.tile_order = nullptr;
+    a.prim = p->primitive;
     // several row groups of a tile combine their traversal lengths with atomicMax
     launch_fill_u32(tile_niter, p->n_tiles, 0u, s);
     const ViewTable vt = view_table(*p);
-    if (mfma_forward(p->d, p->form, p->feat_dtype)) a.tile_order = tile_schedule(p, ws, true, s);
+    if (mfma_forward(p->d, p->form, p->feat_dtype, p->primitive)) a.tile_order = tile_schedule(p, ws, true, s);
     prof_begin(FH_K_RENDER_FWD, s);
-    if (mfma_forward(p->d, p->form, p->feat_dtype))
+    if (mfma_forward(p->d, p->form, p->feat_dtype, p->primitive))
         launch_render_fwd_bf16(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, p->tuning.fwd_rows, !a.feat_bf16, s);
     else
         launch_render_fwd_f32(a, vt, (int)p->n_tiles, p->tuning.fwd_slice, s);
@@ -512,6 +532,7 @@ static void fill_bwd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     a.d0 = 0;
     a.g_in = nullptr;
     a.g_out = nullptr;
+    a.prim = p->primitive;
 }
 
 static int visit_sort_passes(const fh_plan* p) { return (p->rank_bits + 7) / 8; }
@@ -548,6 +569,7 @@ static void visit_stage(const fh_plan* p, void* ws, hipStream_t s) {
     a.vkey = buf<uint32_t>(p, ws, WS_VKEY_A);
     a.vgid = buf<uint32_t>(p, ws, WS_VGID);
     a.vrec = buf<float4>(p, ws, WS_VREC);
+    a.rw = rec_w(p);
     launch_visit_stage(a, (int)p->n_tiles, s);
 }
 
@@ -579,6 +601,7 @@ static void fill_reduce_args(const fh_plan* p, void* ws, ReduceArgs& r) {
     r.n = p->n;
     r.total = (int64_t)p->n * p->n_views;
     r.part_geom = cbuf<float>(p, ws, WS_PART_GEOM);
+    r.wslot = p->primitive == FH_PRIM_SURFEL ? 13 : 9;
     r.grad2d = buf<float>(p, ws, WS_GRAD2D);
     r.rank_of = cbuf<uint32_t>(p, ws, WS_RANK_OF);
     r.part_fuse = cbuf<float>(p, ws, WS_PART_FUSE);
@@ -609,7 +632,9 @@ static NdfdArgs ndfd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     return n;
 }
 
-static bool ndfd_ok(const fh_plan* p) { return p->feat_dtype == FH_BF16 && ndfd_supported(p->d); }
+static bool ndfd_ok(const fh_plan* p) {
+    return p->feat_dtype == FH_BF16 && ndfd_supported(p->d) && p->primitive == FH_PRIM_GAUSSIAN;
+}
 
 fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const fh_upstream* up,
                         const void* fusion_target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* out,
@@ -656,7 +681,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     fill_reduce_args(p, ws, r);
     prof_begin(FH_K_REDUCE, s);
     visit_sort(p, ws, s);
-    launch_reduce_geom(r, s);
+    launch_reduce_geom(r, geom_w(p), s);
     if (fuse) {
         r.acc_sum = acc->sum;
         r.acc_comp = acc->comp;
@@ -666,6 +691,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     }
     prof_end(FH_K_REDUCE, s);
     ProjectBwdArgs pb;
+    pb.prim = p->primitive;
     pb.means = g->means;
     pb.scales = g->scales;
     pb.quats = g->quats;
@@ -758,11 +784,11 @@ fh_status fh_tuning_candidates(const fh_plan* p, int32_t which, fh_tuning* out, 
     if (which == FH_K_RENDER_FWD && p->d > 0) {
         static const int slices[] = {8, 16, 32, 64, 96, 128, 256};
         // (the MFMA forward also takes the two work orders)
-        const int nsched = mfma_forward(p->d, p->form, p->feat_dtype) ? 2 : 1;
+        const int nsched = mfma_forward(p->d, p->form, p->feat_dtype, p->primitive) ? 2 : 1;
         for (int sc = 0; sc < nsched; ++sc)
             for (int rows : {16, 8, 4})
                 for (int sl : slices)
-                    if (fwd_shape_ok(p->d, p->form, p->feat_dtype, sl, rows) &&
+                    if (fwd_shape_ok(p->d, p->form, p->feat_dtype, p->primitive, sl, rows) &&
                         (p->form == FH_FORM_BF16 || sl < 2 * p->d) && n < max) {
                         out[n] = p->tuning;
                         out[n].fwd_slice = sl;
@@ -862,13 +888,13 @@ fh_status fh_get_buffer(const fh_plan* p, void* ws, fh_buffer which, void** ptr,
     if (!p || !ws || !ptr || !count) return FH_E_INVALID;
     const int64_t total = (int64_t)p->n * p->n_views;
     switch (which) {
-        case FH_BUF_RECORDS: *ptr = buf<void>(p, ws, WS_REC); *count = total * 3; break;
+        case FH_BUF_RECORDS: *ptr = buf<void>(p, ws, WS_REC); *count = total * rec_w(p); break;
         case FH_BUF_DEPTH_KEY: *ptr = buf<void>(p, ws, WS_DEPTH_KEY); *count = total; break;
         case FH_BUF_RECT: *ptr = buf<void>(p, ws, WS_RECT); *count = total * 4; break;
         case FH_BUF_DEPTH_ORDER: *ptr = buf<void>(p, ws, WS_ORDER); *count = total; break;
         case FH_BUF_RANGES: *ptr = buf<void>(p, ws, WS_RANGES); *count = p->n_tiles * 2; break;
         case FH_BUF_TILE_NITER: *ptr = buf<void>(p, ws, WS_TILE_NITER); *count = p->n_tiles; break;
-        case FH_BUF_GRAD2D: *ptr = buf<void>(p, ws, WS_GRAD2D); *count = total * 12; break;
+        case FH_BUF_GRAD2D: *ptr = buf<void>(p, ws, WS_GRAD2D); *count = total * geom_w(p); break;
         default: return FH_E_INVALID;
     }
     return FH_OK;

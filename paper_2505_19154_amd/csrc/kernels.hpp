@@ -9,6 +9,7 @@ struct ProjectArgs {
     const float *means, *scales, *quats, *opacity, *sh;
     int n, sh_degree;
     int bin_rule;       // fh_bin_rule
+    int prim;           // fh_primitive (surfel records: 4 float4)
     float4* rec;
     uint32_t* depth_key;
     int4* rect;
@@ -21,6 +22,7 @@ struct ProjectBwdArgs {
     const uint32_t* depth_key;
     const Counters* counters;   // an instance or visit overflow leaves the (zero-filled) outputs zero
     float *g_means, *g_scales, *g_quats, *g_opacity, *g_sh;
+    int prim;                   // fh_primitive (surfel adjoint rows: 16 floats)
 };
 void launch_project(const ProjectArgs&, const CamTable&, const ViewTable&, int, hipStream_t);
 void launch_project_bwd(const ProjectBwdArgs&, const CamTable&, int, hipStream_t);
@@ -77,6 +79,7 @@ struct RenderArgs {
     uint32_t* n_iter;
     uint32_t* tile_niter;
     const uint32_t* tile_order;   // nullable: work item i takes tile tile_order[i]
+    int prim;                     // fh_primitive (FP32 VALU kernels)
 };
 struct BwdArgs {
     const float4* rec;
@@ -112,6 +115,7 @@ struct BwdArgs {
     int d0;
     const float* g_in;
     float* g_out;
+    int prim;                     // fh_primitive (FP32 VALU kernels)
 };
 struct VisitStageArgs {
     const uint32_t* ranges;
@@ -125,7 +129,8 @@ struct VisitStageArgs {
     Counters* counters;
     uint32_t* vkey;     // [visits] rank of the visited instance
     uint32_t* vgid;     // [visits] its Gaussian
-    float4* vrec;       // [visits * 3] its screen record
+    float4* vrec;       // [visits * rw] its screen record
+    int rw;             // float4 per record: 3 (Gaussians) or 4 (surfels)
 };
 struct ReduceArgs {
     const uint32_t* order;
@@ -145,6 +150,7 @@ struct ReduceArgs {
     int d;
     int n_views;
     float *acc_sum, *acc_comp, *acc_wsum, *acc_wcomp;
+    int wslot;                 // per-instance partial row (12 floats, surfels 16): weight sum at entry 9 (surfels 13)
 };
 // slice: channels per workgroup (8, 16, 32 or 64)
 void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s);
@@ -161,12 +167,14 @@ void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s);
 // chunk: Gaussians per back-to-front chunk (16, or 32 when d <= 512)
 void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s);
-void launch_reduce_geom(const ReduceArgs& a, hipStream_t s);
+// gp: floats per partial row, 12 (Gaussians: 10 used) or 16 (surfels: 14 used)
+void launch_reduce_geom(const ReduceArgs& a, int gp, hipStream_t s);
 void launch_reduce_fuse(const ReduceArgs& a, hipStream_t s);
 // units available for the long fusion reduction at a visit capacity (see reduce.hip)
 int64_t fuse_unit_capacity(int64_t visit_capacity);
+// rw: float4 per record (3, surfels 4)
 void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
-                        float4* rrec, hipStream_t s);
+                        float4* rrec, int rw, hipStream_t s);
 // ndfd.hip
 struct NdfdArgs {
     const uint32_t* tile_niter;

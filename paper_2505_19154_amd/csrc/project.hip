@@ -125,6 +125,77 @@ __device__ BinQ binning_f32(float mx, float my, float mz, float sx, float sy, fl
     return b;
 }
 
+// Surfel binning (Section 3.1's planar primitive), float32 chain, contraction
+// disabled, every line one IEEE operation in the written order.  Camera-space
+// scaled tangents T_u = s_u R_c t_u, T_v = s_v R_c t_v (t_u, t_v: columns 0
+// and 1 of R_q); the surfel map in pixel offsets from the projected centre,
+//   a_i = fx (T_i.x p_z - p_x T_i.z) / p_z^2,  b_i = fy (T_i.y p_z - p_y T_i.z) / p_z^2,
+//   c_i = T_i.z / p_z,
+// and the bounding box of the image of the disc u^2 + v^2 <= kappa (the
+// opacity-aware kappa) from its dual conic D = kappa (a a, a.b, a.c; b b,
+// b.c; c c) - e3 e3^T: dx = (D02 -+ sqrt(D02^2 - D00 D22)) / D22, dy likewise;
+// the disc lies in front of the camera iff D22 < 0 (else culled).
+__device__ BinQ binning_surfel_f32(float mx, float my, float mz, float sx, float sy, float qw, float qx, float qy,
+                                   float qz, float op, const fh_camera& c, int tiles_x, int tiles_y) {
+#pragma clang fp contract(off)
+    const float* R = c.R;
+    const float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + c.t[0];
+    const float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + c.t[1];
+    const float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + c.t[2];
+    BinQ b;
+    b.depth = pz;
+    const bool visible = pz > Z_NEAR;
+    b.u = (c.fx * px) / pz + c.cx;
+    b.v = (c.fy * py) / pz + c.cy;
+    const float n = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    const float k = 2.0f / n;
+    // columns 0 and 1 of R_q
+    const float r00 = 1.0f - k * (qy * qy + qz * qz), r10 = k * (qx * qy + qw * qz), r20 = k * (qx * qz - qw * qy);
+    const float r01 = k * (qx * qy - qw * qz), r11 = 1.0f - k * (qx * qx + qz * qz), r21 = k * (qy * qz + qw * qx);
+    float tu[3], tv[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        tu[r] = ((R[3 * r] * r00 + R[3 * r + 1] * r10) + R[3 * r + 2] * r20) * sx;
+        tv[r] = ((R[3 * r] * r01 + R[3 * r + 1] * r11) + R[3 * r + 2] * r21) * sy;
+    }
+    const float zz = pz * pz;
+    const float a0 = c.fx * ((tu[0] * pz - px * tu[2]) / zz);
+    const float a1 = c.fx * ((tv[0] * pz - px * tv[2]) / zz);
+    const float b0 = c.fy * ((tu[1] * pz - py * tu[2]) / zz);
+    const float b1 = c.fy * ((tv[1] * pz - py * tv[2]) / zz);
+    const float c0 = tu[2] / pz;
+    const float c1 = tv[2] / pz;
+    const float x = 255.0f * op;
+    const bool live = x > 1.0f;
+    const float lx = ln_f32_ops(live ? x : 2.0f);
+    const float kap = live ? fminf((lx + lx) + 0.00390625f, KAPPA) : 0.0f;
+    const float d00 = kap * (a0 * a0 + a1 * a1);
+    const float d02 = kap * (a0 * c0 + a1 * c1);
+    const float d11 = kap * (b0 * b0 + b1 * b1);
+    const float d12 = kap * (b0 * c0 + b1 * c1);
+    const float d22 = kap * (c0 * c0 + c1 * c1) - 1.0f;
+    const bool front = d22 < 0.0f;
+    const float sxr = sqrtf(d02 * d02 - d00 * d22);
+    const float syr = sqrtf(d12 * d12 - d11 * d22);
+    const float xlo = (d02 + sxr) / d22, xhi = (d02 - sxr) / d22;
+    const float ylo = (d12 + syr) / d22, yhi = (d12 - syr) / d22;
+    const float ts = (float)TILE;
+    const float x0f = floorf((b.u + xlo) / ts);
+    const float x1f = floorf((b.u + xhi) / ts);
+    const float y0f = floorf((b.v + ylo) / ts);
+    const float y1f = floorf((b.v + yhi) / ts);
+    const bool finite = isfinite(b.u) && isfinite(b.v) && isfinite(xlo) && isfinite(xhi) && isfinite(ylo) &&
+                        isfinite(yhi);
+    const bool ok = visible && finite && live && front;
+    b.ex = b.ey = 0.0f;
+    b.x0 = ok ? (int)fmaxf(x0f, 0.0f) : 0;
+    b.x1 = ok ? (int)fminf(x1f, (float)(tiles_x - 1)) : -1;
+    b.y0 = ok ? (int)fmaxf(y0f, 0.0f) : 0;
+    b.y1 = ok ? (int)fminf(y1f, (float)(tiles_y - 1)) : -1;
+    b.binned = ok && b.x0 <= b.x1 && b.y0 <= b.y1;
+    return b;
+}
+
 // Real spherical harmonics (orthonormal, Condon-Shortley phase, index
 // l*l + m + l) as Cartesian polynomials of the unit direction (x, y, z).
 __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
@@ -232,6 +303,111 @@ __device__ __forceinline__ void cam_centre(const fh_camera& c, float* cp) {
     for (int k = 0; k < 3; ++k) cp[k] = -(R[k] * c.t[0] + R[3 + k] * c.t[1] + R[6 + k] * c.t[2]);
 }
 
+// FP64 surfel frame for one (camera, surfel): camera-space centre p, the
+// camera-space tangent directions du = R_c t_u, dv = R_c t_v, the scaled
+// tangents T_u = s_u du, T_v = s_v dv, and the record entries a, b, c of the
+// surfel map in pixel offsets from the projected centre (see binning_surfel_f32).
+struct Srf64 {
+    double p[3], du[3], dv[3], Tu[3], Tv[3];
+    double qn[4], qnorm;
+    double a0, a1, b0, b1, c0, c1;
+};
+
+__device__ Srf64 srf64(const float* mu, const float* sc, const float* q, const fh_camera& cam) {
+    Srf64 o;
+    const float* R = cam.R;
+    for (int r = 0; r < 3; ++r)
+        o.p[r] = (double)R[3 * r] * mu[0] + (double)R[3 * r + 1] * mu[1] + (double)R[3 * r + 2] * mu[2] + (double)cam.t[r];
+    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    o.qnorm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / o.qnorm, x = qx / o.qnorm, y = qy / o.qnorm, z = qz / o.qnorm;
+    o.qn[0] = w; o.qn[1] = x; o.qn[2] = y; o.qn[3] = z;
+    const double tu[3] = {1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)};
+    const double tv[3] = {2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)};
+    for (int r = 0; r < 3; ++r) {
+        o.du[r] = (double)R[3 * r] * tu[0] + (double)R[3 * r + 1] * tu[1] + (double)R[3 * r + 2] * tu[2];
+        o.dv[r] = (double)R[3 * r] * tv[0] + (double)R[3 * r + 1] * tv[1] + (double)R[3 * r + 2] * tv[2];
+        o.Tu[r] = (double)sc[0] * o.du[r];
+        o.Tv[r] = (double)sc[1] * o.dv[r];
+    }
+    const double fx = cam.fx, fy = cam.fy, pz = o.p[2], z2 = pz * pz;
+    o.a0 = fx * (o.Tu[0] * pz - o.p[0] * o.Tu[2]) / z2;
+    o.a1 = fx * (o.Tv[0] * pz - o.p[0] * o.Tv[2]) / z2;
+    o.b0 = fy * (o.Tu[1] * pz - o.p[1] * o.Tu[2]) / z2;
+    o.b1 = fy * (o.Tv[1] * pz - o.p[1] * o.Tv[2]) / z2;
+    o.c0 = o.Tu[2] / pz;
+    o.c1 = o.Tv[2] / pz;
+    return o;
+}
+
+// SH colour of a primitive at centre mu seen from camera `cam` (clamped at 0)
+__device__ __forceinline__ void sh_colour(const ProjectArgs& a, int g, const fh_camera& cam, const float* mu,
+                                          float* col) {
+    float cp[3];
+    cam_centre(cam, cp);
+    float dx = mu[0] - cp[0], dy = mu[1] - cp[1], dz = mu[2] - cp[2];
+    const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= il; dy *= il; dz *= il;
+    float Y[16];
+    sh_basis(a.sh_degree, dx, dy, dz, Y);
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    const float* shg = a.sh + (size_t)g * nb * 3;
+    col[0] = col[1] = col[2] = 0.5f;
+    for (int b = 0; b < nb; ++b)
+        for (int ch = 0; ch < 3; ++ch) col[ch] += shg[3 * b + ch] * Y[b];
+    for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.0f);
+}
+
+// Surfel records, four float4: (x_c hi, y_c hi, x_c lo, y_c lo), (a0, a1, b0,
+// b1), (opacity, r, g, b), (D, e1, e2, 0) with D = a0 b1 - a1 b0,
+// e1 = a0 c1 - a1 c0, e2 = c0 b1 - c1 b0: for pixel offsets (dx, dy) the ray
+// meets the plane at (u, v) = (dx b1 - dy a1, dy a0 - dx b0) / (D - dy e1 - dx e2).
+__global__ __launch_bounds__(256) void k_project_surfel(ProjectArgs a, CamTable ct, ViewTable vt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (g >= a.n) return;
+    const fh_camera& cam = ct.cam[v];
+    const float mu[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
+    const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
+    const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float op = a.opacity[g];
+    const BinQ bq = binning_surfel_f32(mu[0], mu[1], mu[2], sc[0], sc[1], q[0], q[1], q[2], q[3], op, cam,
+                                       vt.tiles_x[v], vt.tiles_y[v]);
+    const size_t j = (size_t)v * a.n + g;
+    const bool binned = bq.binned;
+    float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
+    if (binned) {
+        const Srf64 f = srf64(mu, sc, q, cam);
+        const double xc = (double)cam.fx * f.p[0] / f.p[2] + (double)cam.cx;
+        const double yc = (double)cam.fy * f.p[1] / f.p[2] + (double)cam.cy;
+        const double D = f.a0 * f.b1 - f.a1 * f.b0;
+        const double e1 = f.a0 * f.c1 - f.a1 * f.c0;
+        const double e2 = f.c0 * f.b1 - f.c1 * f.b0;
+        const float xh = (float)xc, yh = (float)yc;
+        // a non-finite frame keeps its instances but never blends (opacity 0)
+        const bool fin = isfinite(D) && isfinite(e1) && isfinite(e2) && isfinite(xc) && isfinite(yc);
+        r0 = make_float4(xh, yh, (float)(xc - (double)xh), (float)(yc - (double)yh));
+        r1 = make_float4((float)f.a0, (float)f.a1, (float)f.b0, (float)f.b1);
+        float col[3];
+        sh_colour(a, g, cam, mu, col);
+        r2 = make_float4(fin ? op : 0.0f, col[0], col[1], col[2]);
+        r3 = make_float4((float)D, (float)e1, (float)e2, 0.0f);
+    }
+    if (v == 0) {
+        bool bad = !(isfinite(op));
+        for (int k = 0; k < 3; ++k) bad |= !isfinite(mu[k]) || !isfinite(sc[k]);
+        for (int k = 0; k < 4; ++k) bad |= !isfinite(q[k]);
+        if (bad) atomicAdd(&a.counters->n_culled_nonfinite, 1ull);
+    }
+    a.rec[4 * j] = r0;
+    a.rec[4 * j + 1] = r1;
+    a.rec[4 * j + 2] = r2;
+    a.rec[4 * j + 3] = r3;
+    a.depth_key[j] = binned ? __float_as_uint(bq.depth) : CULLED_KEY;
+    a.rect[j] = binned ? make_int4(bq.x0, bq.y0, bq.x1, bq.y1) : make_int4(0, 0, -1, -1);
+}
+
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, ViewTable vt) {
@@ -266,20 +442,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, Vie
         const bool fin = isfinite(det) && det > 0.0 && isfinite(l1) && isfinite(l2) && l2 > 0.0;
         r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
         r1 = make_float4((float)cos(th), (float)sin(th), (float)(-0.5 * LOG2E * l1), (float)(-0.5 * LOG2E * l2));
-        // colour
-        float cp[3];
-        cam_centre(cam, cp);
-        float dx = mu[0] - cp[0], dy = mu[1] - cp[1], dz = mu[2] - cp[2];
-        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= il; dy *= il; dz *= il;
-        float Y[16];
-        sh_basis(a.sh_degree, dx, dy, dz, Y);
-        const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-        const float* shg = a.sh + (size_t)g * nb * 3;
-        float col[3] = {0.5f, 0.5f, 0.5f};
-        for (int b = 0; b < nb; ++b)
-            for (int ch = 0; ch < 3; ++ch) col[ch] += shg[3 * b + ch] * Y[b];
-        r2 = make_float4(fin ? op : 0.0f, fmaxf(col[0], 0.0f), fmaxf(col[1], 0.0f), fmaxf(col[2], 0.0f));
+        float col[3];
+        sh_colour(a, g, cam, mu, col);
+        r2 = make_float4(fin ? op : 0.0f, col[0], col[1], col[2]);
     }
     if (v == 0) {
         bool bad = !(isfinite(op));
@@ -295,15 +460,99 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable ct, Vie
 }
 
 // ---------------------------------------------------------------------------
+// Pieces of the projection adjoint shared by both primitives.
+
+// R_q(qn) with qn = q / |q|: upR (adjoint of R_q) -> gq (adjoint of q)
+__device__ __forceinline__ void quat_adjoint(const double* qn, double qnorm, const float (*upR)[3], float* gq) {
+    const float w = (float)qn[0], x = (float)qn[1], y = (float)qn[2], z = (float)qn[3];
+    const float gw = 2.0f * (-z * upR[0][1] + y * upR[0][2] + z * upR[1][0] - x * upR[1][2] - y * upR[2][0] + x * upR[2][1]);
+    const float gx = 2.0f * (y * upR[0][1] + z * upR[0][2] + y * upR[1][0] - 2.0f * x * upR[1][1] - w * upR[1][2]
+                             + z * upR[2][0] + w * upR[2][1] - 2.0f * x * upR[2][2]);
+    const float gy = 2.0f * (-2.0f * y * upR[0][0] + x * upR[0][1] + w * upR[0][2] + x * upR[1][0] + z * upR[1][2]
+                             - w * upR[2][0] + z * upR[2][1] - 2.0f * y * upR[2][2]);
+    const float gz = 2.0f * (-2.0f * z * upR[0][0] - w * upR[0][1] + x * upR[0][2] + w * upR[1][0] - 2.0f * z * upR[1][1]
+                             + y * upR[1][2] + x * upR[2][0] + y * upR[2][1]);
+    // qn = q / |q|
+    const float dotq = w * gw + x * gx + y * gy + z * gz;
+    const float iq = (float)(1.0 / qnorm);
+    gq[0] += (gw - w * dotq) * iq;
+    gq[1] += (gx - x * dotq) * iq;
+    gq[2] += (gy - y * dotq) * iq;
+    gq[3] += (gz - z * dotq) * iq;
+}
+
+// colour: rgb = max(0, sum_b sh_b Y_b(dir) + 1/2), dir = (mu - cam) / |mu - cam|;
+// urgb_in: the view's adjoint of rgb
+__device__ __forceinline__ void colour_adjoint(const ProjectBwdArgs& a, const fh_camera& cam, const float* mu,
+                                               const float* shg, int nb, const float* urgb_in, float* gmu,
+                                               float (*gsh)[3]) {
+    float cp[3];
+    cam_centre(cam, cp);
+    float ddx = mu[0] - cp[0], ddy = mu[1] - cp[1], ddz = mu[2] - cp[2];
+    const float il = 1.0f / sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+    const float dx = ddx * il, dy = ddy * il, dz = ddz * il;
+    float Y[16];
+    sh_basis(a.sh_degree, dx, dy, dz, Y);
+    float raw[3] = {0.5f, 0.5f, 0.5f};
+    for (int b = 0; b < nb; ++b)
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += shg[3 * b + ch] * Y[b];
+    float urgb[3];
+    for (int ch = 0; ch < 3; ++ch) urgb[ch] = raw[ch] > 0.0f ? urgb_in[ch] : 0.0f;
+    for (int b = 0; b < nb; ++b)
+        for (int ch = 0; ch < 3; ++ch) gsh[b][ch] += Y[b] * urgb[ch];
+    if (a.sh_degree > 0) {
+        float GY[16][3];
+        sh_basis_grad(a.sh_degree, dx, dy, dz, GY);
+        float udir[3] = {0, 0, 0};
+        for (int b = 1; b < nb; ++b) {
+            const float s = shg[3 * b] * urgb[0] + shg[3 * b + 1] * urgb[1] + shg[3 * b + 2] * urgb[2];
+            udir[0] += GY[b][0] * s;
+            udir[1] += GY[b][1] * s;
+            udir[2] += GY[b][2] * s;
+        }
+        const float dd = dx * udir[0] + dy * udir[1] + dz * udir[2];
+        gmu[0] += (udir[0] - dx * dd) * il;
+        gmu[1] += (udir[1] - dy * dd) * il;
+        gmu[2] += (udir[2] - dz * dd) * il;
+    }
+}
+
+__device__ __forceinline__ void store_grads(const ProjectBwdArgs& a, int g, int nb, const float* gmu, const float* gs,
+                                            const float* gq, float gop, const float (*gsh)[3]) {
+    for (int k = 0; k < 3; ++k) {
+        a.g_means[3 * g + k] = gmu[k];
+        a.g_scales[3 * g + k] = gs[k];
+    }
+    reinterpret_cast<float4*>(a.g_quats)[g] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    a.g_opacity[g] = gop;
+    float* gsho = a.g_sh + (size_t)g * nb * 3;
+    if (nb == 16) {
+        // 48 floats per Gaussian (192 B, 16-B aligned): as twelve float4
+        const float* f = &gsh[0][0];
+        float4* o4 = reinterpret_cast<float4*>(gsho);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o4[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+    } else {
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) gsho[3 * b + ch] = gsh[b][ch];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint of the projection, summed over views in view order (deterministic).
 // grad2d[(v*N + g)*12 + k], k: 0 u, 1 v, 2 A, 3 B, 4 C, 5 sum dL/dpower,
 // 6..8 rgb, 9 sum w.
 
+template <int GP = 12>
 __device__ __forceinline__ bool upstream_zero(const float* grad2d, size_t j) {
-    const float4* g4 = reinterpret_cast<const float4*>(grad2d + j * 12);
-    const float4 z0 = g4[0], z1 = g4[1], z2 = g4[2];
-    return z0.x == 0.f && z0.y == 0.f && z0.z == 0.f && z0.w == 0.f && z1.x == 0.f && z1.y == 0.f && z1.z == 0.f &&
-           z1.w == 0.f && z2.x == 0.f && z2.y == 0.f && z2.z == 0.f && z2.w == 0.f;
+    const float4* g4 = reinterpret_cast<const float4*>(grad2d + j * GP);
+    bool z = true;
+#pragma unroll
+    for (int k = 0; k < GP / 4; ++k) {
+        const float4 q = g4[k];
+        z = z && q.x == 0.f && q.y == 0.f && q.z == 0.f && q.w == 0.f;
+    }
+    return z;
 }
 
 // The outputs are zero-filled before the launch; a Gaussian whose views all
@@ -394,77 +643,94 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a, CamTable 
         for (int l = 0; l < 3; ++l)
             gs[l] += upM[0][l] * (float)cv.Rq[0][l] + upM[1][l] * (float)cv.Rq[1][l] + upM[2][l] * (float)cv.Rq[2][l];
 
-        // R_q(qn)
-        const float w = (float)cv.qn[0], x = (float)cv.qn[1], y = (float)cv.qn[2], z = (float)cv.qn[3];
-        const float gw = 2.0f * (-z * upR[0][1] + y * upR[0][2] + z * upR[1][0] - x * upR[1][2] - y * upR[2][0] + x * upR[2][1]);
-        const float gx = 2.0f * (y * upR[0][1] + z * upR[0][2] + y * upR[1][0] - 2.0f * x * upR[1][1] - w * upR[1][2]
-                                 + z * upR[2][0] + w * upR[2][1] - 2.0f * x * upR[2][2]);
-        const float gy = 2.0f * (-2.0f * y * upR[0][0] + x * upR[0][1] + w * upR[0][2] + x * upR[1][0] + z * upR[1][2]
-                                 - w * upR[2][0] + z * upR[2][1] - 2.0f * y * upR[2][2]);
-        const float gz = 2.0f * (-2.0f * z * upR[0][0] - w * upR[0][1] + x * upR[0][2] + w * upR[1][0] - 2.0f * z * upR[1][1]
-                                 + y * upR[1][2] + x * upR[2][0] + y * upR[2][1]);
-        // qn = q / |q|
-        const float dotq = w * gw + x * gx + y * gy + z * gz;
-        const float iq = (float)(1.0 / cv.qnorm);
-        gq[0] += (gw - w * dotq) * iq;
-        gq[1] += (gx - x * dotq) * iq;
-        gq[2] += (gy - y * dotq) * iq;
-        gq[3] += (gz - z * dotq) * iq;
+        quat_adjoint(cv.qn, cv.qnorm, upR, gq);
+        colour_adjoint(a, cam, mu, shg, nb, g2 + 6, gmu, gsh);
+    }
+    store_grads(a, g, nb, gmu, gs, gq, gop, gsh);
+}
 
-        // colour: rgb = max(0, sum_b sh_b Y_b(dir) + 1/2), dir = (mu - cam) / |mu - cam|
-        float cp[3];
-        cam_centre(cam, cp);
-        float ddx = mu[0] - cp[0], ddy = mu[1] - cp[1], ddz = mu[2] - cp[2];
-        const float il = 1.0f / sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
-        const float dx = ddx * il, dy = ddy * il, dz = ddz * il;
-        float Y[16];
-        sh_basis(a.sh_degree, dx, dy, dz, Y);
-        float raw[3] = {0.5f, 0.5f, 0.5f};
-        for (int b = 0; b < nb; ++b)
-            for (int ch = 0; ch < 3; ++ch) raw[ch] += shg[3 * b + ch] * Y[b];
-        float urgb[3];
-        for (int ch = 0; ch < 3; ++ch) urgb[ch] = raw[ch] > 0.0f ? g2[6 + ch] : 0.0f;
-        for (int b = 0; b < nb; ++b)
-            for (int ch = 0; ch < 3; ++ch) gsh[b][ch] += Y[b] * urgb[ch];
-        if (a.sh_degree > 0) {
-            float GY[16][3];
-            sh_basis_grad(a.sh_degree, dx, dy, dz, GY);
-            float udir[3] = {0, 0, 0};
-            for (int b = 1; b < nb; ++b) {
-                const float s = shg[3 * b] * urgb[0] + shg[3 * b + 1] * urgb[1] + shg[3 * b + 2] * urgb[2];
-                udir[0] += GY[b][0] * s;
-                udir[1] += GY[b][1] * s;
-                udir[2] += GY[b][2] * s;
-            }
-            const float dd = dx * udir[0] + dy * udir[1] + dz * udir[2];
-            gmu[0] += (udir[0] - dx * dd) * il;
-            gmu[1] += (udir[1] - dy * dd) * il;
-            gmu[2] += (udir[2] - dz * dd) * il;
+// Surfel adjoint, views in view order.  grad2d[(v*N + g)*16 + k], k: 0..8
+// the record entries (x_c, y_c, a0, a1, b0, b1, D, e1, e2), 9 sum dL/dpower,
+// 10..12 rgb, 13 sum w.  The chain in FP64: (D, e1, e2) -> (a, b, c), then
+// (x_c, y_c, a, b, c) -> (p, T_u, T_v) -> (mu, s_u, s_v, q).
+__global__ __launch_bounds__(256) void k_project_bwd_surfel(ProjectBwdArgs a, CamTable ct, int n_views) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    if (a.counters->inst_overflow || a.counters->visit_overflow) return;
+    bool any = false;
+    for (int v = 0; v < n_views && !any; ++v) {
+        const size_t j = (size_t)v * a.n + g;
+        any = a.depth_key[j] != CULLED_KEY && !upstream_zero<16>(a.grad2d, j);
+    }
+    if (!any) return;
+    const float mu[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
+    const float sc[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
+    const float4 q4 = reinterpret_cast<const float4*>(a.quats)[g];
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float op = a.opacity[g];
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    const float* shg = a.sh + (size_t)g * nb * 3;
+    float gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f;
+    float gsh[16][3];
+    for (int b = 0; b < 16; ++b) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
+    for (int v = 0; v < n_views; ++v) {
+        const size_t j = (size_t)v * a.n + g;
+        if (a.depth_key[j] == CULLED_KEY || upstream_zero<16>(a.grad2d, j)) continue;
+        const float* g2 = a.grad2d + j * 16;
+        const fh_camera& cam = ct.cam[v];
+        const Srf64 f = srf64(mu, sc, q, cam);
+        gop += g2[9] / op;
+        // (D, e1, e2) -> (a, b, c)
+        const double gD = g2[6], ge1 = g2[7], ge2 = g2[8];
+        const double ga0 = g2[2] + f.b1 * gD + f.c1 * ge1;
+        const double ga1 = g2[3] - f.b0 * gD - f.c0 * ge1;
+        const double gb0 = g2[4] - f.a1 * gD - f.c1 * ge2;
+        const double gb1 = g2[5] + f.a0 * gD + f.c0 * ge2;
+        const double gc0 = -f.a1 * ge1 + f.b1 * ge2;
+        const double gc1 = f.a0 * ge1 - f.b0 * ge2;
+        // (x_c, y_c, a, b, c) -> (p, T_u, T_v)
+        const double fx = cam.fx, fy = cam.fy, px = f.p[0], py = f.p[1], z = f.p[2];
+        const double z2 = z * z, z3 = z2 * z;
+        const double gxc = g2[0], gyc = g2[1];
+        double gp[3] = {fx / z * gxc, fy / z * gyc, -fx * px / z2 * gxc - fy * py / z2 * gyc};
+        double gT[2][3];
+        const double* Ts[2] = {f.Tu, f.Tv};
+        const double gas[2] = {ga0, ga1}, gbs[2] = {gb0, gb1}, gcs[2] = {gc0, gc1};
+        for (int i = 0; i < 2; ++i) {
+            const double* T = Ts[i];
+            gT[i][0] = fx / z * gas[i];
+            gT[i][1] = fy / z * gbs[i];
+            gT[i][2] = -fx * px / z2 * gas[i] - fy * py / z2 * gbs[i] + gcs[i] / z;
+            gp[0] += -fx * T[2] / z2 * gas[i];
+            gp[1] += -fy * T[2] / z2 * gbs[i];
+            gp[2] += (-fx * T[0] / z2 + 2.0 * fx * px * T[2] / z3) * gas[i] +
+                     (-fy * T[1] / z2 + 2.0 * fy * py * T[2] / z3) * gbs[i] - T[2] / z2 * gcs[i];
         }
+        // p = R_c mu + t
+        const float* R = cam.R;
+        for (int k = 0; k < 3; ++k) gmu[k] += (float)((double)R[k] * gp[0] + (double)R[3 + k] * gp[1] + (double)R[6 + k] * gp[2]);
+        // T_u = s_u R_c t_u, T_v = s_v R_c t_v
+        gs[0] += (float)(gT[0][0] * f.du[0] + gT[0][1] * f.du[1] + gT[0][2] * f.du[2]);
+        gs[1] += (float)(gT[1][0] * f.dv[0] + gT[1][1] * f.dv[1] + gT[1][2] * f.dv[2]);
+        float upR[3][3];
+        for (int k = 0; k < 3; ++k) {
+            upR[k][0] = (float)(((double)R[k] * gT[0][0] + (double)R[3 + k] * gT[0][1] + (double)R[6 + k] * gT[0][2]) * sc[0]);
+            upR[k][1] = (float)(((double)R[k] * gT[1][0] + (double)R[3 + k] * gT[1][1] + (double)R[6 + k] * gT[1][2]) * sc[1]);
+            upR[k][2] = 0.0f;
+        }
+        quat_adjoint(f.qn, f.qnorm, upR, gq);
+        colour_adjoint(a, cam, mu, shg, nb, g2 + 10, gmu, gsh);
     }
-    for (int k = 0; k < 3; ++k) {
-        a.g_means[3 * g + k] = gmu[k];
-        a.g_scales[3 * g + k] = gs[k];
-    }
-    reinterpret_cast<float4*>(a.g_quats)[g] = make_float4(gq[0], gq[1], gq[2], gq[3]);
-    a.g_opacity[g] = gop;
-    float* gsho = a.g_sh + (size_t)g * nb * 3;
-    if (nb == 16) {
-        // 48 floats per Gaussian (192 B, 16-B aligned): as twelve float4
-        const float* f = &gsh[0][0];
-        float4* o4 = reinterpret_cast<float4*>(gsho);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) o4[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
-    } else {
-        for (int b = 0; b < nb; ++b)
-            for (int ch = 0; ch < 3; ++ch) gsho[3 * b + ch] = gsh[b][ch];
-    }
+    store_grads(a, g, nb, gmu, gs, gq, gop, gsh);
 }
 
 // ---------------------------------------------------------------------------
 void launch_project(const ProjectArgs& a, const CamTable& ct, const ViewTable& vt, int n_views, hipStream_t s) {
     dim3 grid((a.n + 255) / 256, n_views);
-    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, a, ct, vt);
+    if (a.prim == FH_PRIM_SURFEL)
+        hipLaunchKernelGGL(k_project_surfel, grid, dim3(256), 0, s, a, ct, vt);
+    else
+        hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, a, ct, vt);
 }
 
 void launch_project_bwd(const ProjectBwdArgs& a, const CamTable& ct, int n_views, hipStream_t s) {
@@ -474,7 +740,10 @@ void launch_project_bwd(const ProjectBwdArgs& a, const CamTable& ct, int n_views
     launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_quats), (int64_t)a.n * 4, 0u, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_opacity), (int64_t)a.n, 0u, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(a.g_sh), (int64_t)a.n * nsh, 0u, s);
-    hipLaunchKernelGGL(k_project_bwd, dim3((a.n + 255) / 256), dim3(256), 0, s, a, ct, n_views);
+    if (a.prim == FH_PRIM_SURFEL)
+        hipLaunchKernelGGL(k_project_bwd_surfel, dim3((a.n + 255) / 256), dim3(256), 0, s, a, ct, n_views);
+    else
+        hipLaunchKernelGGL(k_project_bwd, dim3((a.n + 255) / 256), dim3(256), 0, s, a, ct, n_views);
 }
 
 }  // namespace fh

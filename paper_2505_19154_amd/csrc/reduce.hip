@@ -47,9 +47,7 @@ __global__ __launch_bounds__(256) void k_visit_stage(VisitStageArgs a) {
         const int64_t vi = (int64_t)vo + pos;
         a.vkey[vi] = j;
         a.vgid[vi] = a.order[j];
-        a.vrec[3 * vi] = a.rrec[3 * (int64_t)j];
-        a.vrec[3 * vi + 1] = a.rrec[3 * (int64_t)j + 1];
-        a.vrec[3 * vi + 2] = a.rrec[3 * (int64_t)j + 2];
+        for (int k = 0; k < a.rw; ++k) a.vrec[a.rw * vi + k] = a.rrec[a.rw * (int64_t)j + k];
     }
 }
 
@@ -94,49 +92,61 @@ __device__ __forceinline__ uint32_t wave_slots(unsigned int* counter, uint32_t n
     return base + incl - n;
 }
 
+// Partial rows of GP floats (Gaussians 12, 10 used; surfels 16, 14 used).
+template <int GP>
 __device__ __forceinline__ void add_geom(float* acc, const float* part_geom, uint32_t idx) {
-    const float4* pg = reinterpret_cast<const float4*>(part_geom + (int64_t)idx * 12);
-    const float4 q0 = pg[0], q1 = pg[1], q2 = pg[2];
-    acc[0] += q0.x; acc[1] += q0.y; acc[2] += q0.z; acc[3] += q0.w;
-    acc[4] += q1.x; acc[5] += q1.y; acc[6] += q1.z; acc[7] += q1.w;
-    acc[8] += q2.x; acc[9] += q2.y;
+    constexpr int NV = GP - 2;
+    const float4* pg = reinterpret_cast<const float4*>(part_geom + (int64_t)idx * GP);
+    float4 q[GP / 4];
+#pragma unroll
+    for (int k = 0; k < GP / 4; ++k) q[k] = pg[k];
+    const float* f = reinterpret_cast<const float*>(q);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) acc[m] += f[m];
 }
 
 // acc += the partials of visits k0, k0 + st, k0 + 2 st, ... below k1 (of the
 // rank-sorted list), added in that order; their indices and rows are loaded
 // four at a time, so that the loads do not wait for one another.
+template <int GP>
 __device__ __forceinline__ void add_geom_run(float* acc, const ReduceArgs& a, uint32_t k0, uint32_t k1, uint32_t st) {
+    constexpr int NV = GP - 2;
     uint32_t k = k0;
     for (; k + 3 * st < k1; k += 4 * st) {
         uint32_t idx[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) idx[i] = a.vsorted[k + (uint32_t)i * st];
-        float4 r[4][3];
+        float4 r[4][GP / 4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float4* pg = reinterpret_cast<const float4*>(a.part_geom + (int64_t)idx[i] * 12);
-            r[i][0] = pg[0];
-            r[i][1] = pg[1];
-            r[i][2] = pg[2];
+            const float4* pg = reinterpret_cast<const float4*>(a.part_geom + (int64_t)idx[i] * GP);
+#pragma unroll
+            for (int c = 0; c < GP / 4; ++c) r[i][c] = pg[c];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            acc[0] += r[i][0].x; acc[1] += r[i][0].y; acc[2] += r[i][0].z; acc[3] += r[i][0].w;
-            acc[4] += r[i][1].x; acc[5] += r[i][1].y; acc[6] += r[i][1].z; acc[7] += r[i][1].w;
-            acc[8] += r[i][2].x; acc[9] += r[i][2].y;
+            const float* f = reinterpret_cast<const float*>(r[i]);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) acc[m] += f[m];
         }
     }
-    for (; k < k1; k += st) add_geom(acc, a.part_geom, a.vsorted[k]);
+    for (; k < k1; k += st) add_geom<GP>(acc, a.part_geom, a.vsorted[k]);
 }
 
+template <int GP>
 __device__ __forceinline__ void store_geom(float* grad2d, int64_t row, const float* acc) {
-    float4* o = reinterpret_cast<float4*>(grad2d + row * 12);
-    o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-    o[2] = make_float4(acc[8], acc[9], 0.0f, 0.0f);
+    constexpr int NV = GP - 2;
+    float4* o = reinterpret_cast<float4*>(grad2d + row * GP);
+#pragma unroll
+    for (int c = 0; c < GP / 4; ++c) {
+        const int m = 4 * c;
+        o[c] = make_float4(m < NV ? acc[m] : 0.0f, m + 1 < NV ? acc[m + 1] : 0.0f, m + 2 < NV ? acc[m + 2] : 0.0f,
+                           m + 3 < NV ? acc[m + 3] : 0.0f);
+    }
 }
 
 // One thread per (view, rank): the screen-space adjoint of that (view, Gaussian).
+template <int GP>
 __global__ __launch_bounds__(256) void k_reduce_geom(ReduceArgs a) {
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;   // (uniform)
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -152,39 +162,41 @@ __global__ __launch_bounds__(256) void k_reduce_geom(ReduceArgs a) {
     }
     const int64_t v = j / a.n;
     const uint32_t g = a.order[j];
-    float acc[12];
+    float acc[GP];
 #pragma unroll
-    for (int m = 0; m < 12; ++m) acc[m] = 0.0f;
-    add_geom_run(acc, a, b0, b1, 1u);
-    store_geom(a.grad2d, v * a.n + g, acc);
+    for (int m = 0; m < GP; ++m) acc[m] = 0.0f;
+    add_geom_run<GP>(acc, a, b0, b1, 1u);
+    store_geom<GP>(a.grad2d, v * a.n + g, acc);
 }
 
 // One workgroup per long rank (grid-stride over the queue): thread t sums
 // entries t, t + 256, ... of the segment, then a fixed-order tree.
+template <int GP>
 __global__ __launch_bounds__(256) void k_reduce_geom_long(ReduceArgs a) {
-    __shared__ float red[256][11];
+    constexpr int NV = GP - 2;
+    __shared__ float red[256][NV + 1];
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const uint32_t nlong = a.counters->n_long_geom;
     for (uint32_t li = blockIdx.x; li < nlong; li += gridDim.x) {
         const int64_t j = a.long_list[li];
         const uint32_t b0 = a.vseg[2 * j], b1 = a.vseg[2 * j + 1];
-        float acc[12];
+        float acc[GP];
 #pragma unroll
-        for (int m = 0; m < 12; ++m) acc[m] = 0.0f;
-        add_geom_run(acc, a, b0 + threadIdx.x, b1, 256u);
+        for (int m = 0; m < GP; ++m) acc[m] = 0.0f;
+        add_geom_run<GP>(acc, a, b0 + threadIdx.x, b1, 256u);
 #pragma unroll
-        for (int m = 0; m < 10; ++m) red[threadIdx.x][m] = acc[m];
+        for (int m = 0; m < NV; ++m) red[threadIdx.x][m] = acc[m];
         __syncthreads();
         for (int st = 128; st >= 1; st >>= 1) {
             if ((int)threadIdx.x < st)
 #pragma unroll
-                for (int m = 0; m < 10; ++m) red[threadIdx.x][m] += red[threadIdx.x + st][m];
+                for (int m = 0; m < NV; ++m) red[threadIdx.x][m] += red[threadIdx.x + st][m];
             __syncthreads();
         }
         if (threadIdx.x == 0) {
 #pragma unroll
-            for (int m = 0; m < 10; ++m) acc[m] = red[0][m];
-            store_geom(a.grad2d, (j / a.n) * a.n + a.order[j], acc);
+            for (int m = 0; m < NV; ++m) acc[m] = red[0][m];
+            store_geom<GP>(a.grad2d, (j / a.n) * a.n + a.order[j], acc);
         }
         __syncthreads();
     }
@@ -206,7 +218,7 @@ __device__ __forceinline__ void accumulate_span(const ReduceArgs& a, int lane, u
             const uint32_t k = kb + (uint32_t)lane;
             if (k < k1) {
                 my = a.vsorted[k];
-                myw = a.part_geom[my * 12 + 9];
+                myw = a.part_geom[my * (a.wslot == 9 ? 12 : 16) + a.wslot];
             }
         }
         float rows[B][NC];
@@ -436,10 +448,15 @@ void launch_vseg(const uint32_t* skeys, const Counters* c, int64_t cap, uint32_t
     if (cap > 0) hipLaunchKernelGGL(k_vseg, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, skeys, c, cap, vseg);
 }
 
-void launch_reduce_geom(const ReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_geom, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, s, a);
+void launch_reduce_geom(const ReduceArgs& a, int gp, hipStream_t s) {
     // (long ranks are few: at 500k Gaussians at 1080p about 1,900, one per workgroup)
-    hipLaunchKernelGGL(k_reduce_geom_long, dim3(4096), dim3(256), 0, s, a);
+    if (gp == 16) {
+        hipLaunchKernelGGL(k_reduce_geom<16>, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reduce_geom_long<16>, dim3(4096), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_reduce_geom<12>, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reduce_geom_long<12>, dim3(4096), dim3(256), 0, s, a);
+    }
 }
 
 template <int NC, int B>

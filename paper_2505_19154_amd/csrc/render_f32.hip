@@ -12,6 +12,11 @@
 //   g_k = rgb_k . dC + f_k . dF,  S_k = sum_{i>k} w_i g_i,
 // reduced over the tile's pixels into per-instance partials (no atomics);
 // optionally the fusion partials sum_p w(p) target(p) in the same sweep.
+//
+// Both kernels also take the surfel primitive (Section 3.1; SURF = true):
+// four-float4 records (see k_project_surfel), the density at the ray-plane
+// intersection, and 14 per-instance partials (the nine record entries' terms,
+// sum dL/dpower, rgb, sum w) in rows of 16 floats.
 #include "kernels.hpp"
 
 namespace fh {
@@ -26,9 +31,69 @@ __device__ __forceinline__ float load_feat(const void* f, int bf16, int64_t idx)
     return bf16 ? bf16_to_f32(static_cast<const uint16_t*>(f)[idx]) : static_cast<const float*>(f)[idx];
 }
 
-template <int DS>
+// Surfel record: (x_c hi, y_c hi, x_c lo, y_c lo), (a0, a1, b0, b1),
+// (opacity, r, g, b), (D, e1, e2, 0).
+struct SRec {
+    float4 r0, r1, r2, r3;
+};
+template <bool SURF>
+struct PrimRec {
+    using T = Rec;
+    static constexpr int RW = 3;
+};
+template <>
+struct PrimRec<true> {
+    using T = SRec;
+    static constexpr int RW = 4;
+};
+template <bool SURF>
+__device__ __forceinline__ typename PrimRec<SURF>::T load_rec(const float4* base, int64_t j) {
+    typename PrimRec<SURF>::T r;
+    r.r0 = base[PrimRec<SURF>::RW * j];
+    r.r1 = base[PrimRec<SURF>::RW * j + 1];
+    r.r2 = base[PrimRec<SURF>::RW * j + 2];
+    if constexpr (SURF) r.r3 = base[PrimRec<SURF>::RW * j + 3];
+    return r;
+}
+
+// A surfel at pixel centre (x, y): pixel offsets from the projected centre,
+// the plane point (u, v) = (k0, k1) / k2 its ray meets, G = exp(-(u^2 + v^2)/2)
+// (0 for a ray parallel to the plane), alpha = min(0.99, o G).
+struct SurfEval {
+    float dx, dy, u, v, ik2, raw, alpha;
+};
+__device__ __forceinline__ SurfEval eval_surfel(const SRec& r, float x, float y) {
+#pragma clang fp contract(off)
+    SurfEval e;
+    e.dx = (x - r.r0.x) - r.r0.z;
+    e.dy = (y - r.r0.y) - r.r0.w;
+    const float a0 = r.r1.x, a1 = r.r1.y, b0 = r.r1.z, b1 = r.r1.w;
+    const float k0 = __builtin_fmaf(e.dx, b1, -(e.dy * a1));
+    const float k1 = __builtin_fmaf(e.dy, a0, -(e.dx * b0));
+    const float k2 = __builtin_fmaf(-e.dx, r.r3.z, __builtin_fmaf(-e.dy, r.r3.y, r.r3.x));
+    const bool hit = k2 != 0.0f;
+    e.ik2 = hit ? 1.0f / k2 : 0.0f;
+    e.u = k0 * e.ik2;
+    e.v = k1 * e.ik2;
+    // exp(-r2 / 2) = exp2(-(log2 e / 2) r2)
+    const float G = hit ? __builtin_amdgcn_exp2f(-0.72134752044448170f * (e.u * e.u + e.v * e.v)) : 0.0f;
+    e.raw = r.r2.x * G;
+    e.alpha = fminf(ALPHA_MAX, e.raw);
+    return e;
+}
+
+template <bool SURF>
+__device__ __forceinline__ float prim_alpha(const typename PrimRec<SURF>::T& r, float x, float y) {
+    if constexpr (SURF)
+        return eval_surfel(r, x, y).alpha;
+    else
+        return eval_alpha(r, x, y).alpha;
+}
+
+template <int DS, bool SURF>
 __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable vt) {
-    __shared__ Rec srec[256];
+    using RecT = typename PrimRec<SURF>::T;
+    __shared__ RecT srec[256];
     __shared__ float sfeat[256][DS > 0 ? DS : 1];
     __shared__ uint32_t smax[4];
     if (a.counters->inst_overflow) return;
@@ -55,9 +120,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable 
             const int64_t i = base + threadIdx.x;
             const uint32_t j = inst_rank(a.keys, a.vals, i, a.rank_bits, a.packed);
             const uint32_t g = a.order[j];
-            srec[threadIdx.x].r0 = a.rrec[3 * (int64_t)j];
-            srec[threadIdx.x].r1 = a.rrec[3 * (int64_t)j + 1];
-            srec[threadIdx.x].r2 = a.rrec[3 * (int64_t)j + 2];
+            srec[threadIdx.x] = load_rec<SURF>(a.rrec, j);
             if (DS > 0) {
 #pragma unroll
                 for (int c = 0; c < DS; ++c)
@@ -67,15 +130,15 @@ __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable 
         __syncthreads();
         if (!done) {
             for (uint32_t k = 0; k < cnt; ++k) {
-                const Rec r = srec[k];
-                const AlphaEval ae = eval_alpha(r, x, y);
-                if (ae.alpha < ALPHA_MIN) continue;
-                const float Tn = T * (1.0f - ae.alpha);
+                const RecT r = srec[k];
+                const float alpha = prim_alpha<SURF>(r, x, y);
+                if (alpha < ALPHA_MIN) continue;
+                const float Tn = T * (1.0f - alpha);
                 if (Tn < T_MIN) {
                     done = true;
                     break;
                 }
-                const float w = ae.alpha * T;
+                const float w = alpha * T;
                 c0 += w * r.r2.y;
                 c1 += w * r.r2.z;
                 c2 += w * r.r2.w;
@@ -127,12 +190,15 @@ __global__ void k_check_visits(const uint32_t* tile_voff, int n_tiles, Counters*
 
 // ---------------------------------------------------------------------------
 
-template <int K, bool FUSE>
+template <int K, bool FUSE, bool SURF>
 __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt) {
+    using RecT = typename PrimRec<SURF>::T;
+    constexpr int NQ = SURF ? 14 : 10;    // per-instance partial terms
+    constexpr int GP = SURF ? 16 : 12;    // floats per partial row
     extern __shared__ float dyn[];
-    __shared__ Rec srec[K];
+    __shared__ RecT srec[K];
     __shared__ uint32_t sg[K];
-    __shared__ float sred[4][K][10];
+    __shared__ float sred[4][K][NQ];
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = blockIdx.x;
     const uint32_t nt = a.tile_niter[t];
@@ -168,9 +234,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
         const int cnt = ce - cs;
         if (threadIdx.x < cnt) {
             const int64_t vi = (int64_t)voff + cs + threadIdx.x;
-            srec[threadIdx.x].r0 = a.vrec[3 * vi];
-            srec[threadIdx.x].r1 = a.vrec[3 * vi + 1];
-            srec[threadIdx.x].r2 = a.vrec[3 * vi + 2];
+            srec[threadIdx.x] = load_rec<SURF>(a.vrec, vi);
             sg[threadIdx.x] = a.vgid[vi];
         }
         __syncthreads();
@@ -211,59 +275,87 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
         for (int k = K - 1; k >= 0; --k) {
             if (k >= cnt) continue;
             const int pos = cs + k;
-            float q[10];
+            float q[NQ];
 #pragma unroll
-            for (int m = 0; m < 10; ++m) q[m] = 0.0f;
+            for (int m = 0; m < NQ; ++m) q[m] = 0.0f;
             float w = 0.0f;
             bool contrib = false;
             if (inside && (uint32_t)pos < nit) {
-                const Rec r = srec[k];
-                const AlphaEval ae = eval_alpha(r, x, y);
-                if (ae.alpha >= ALPHA_MIN) {
+                const RecT r = srec[k];
+                float alpha, raw;
+                [[maybe_unused]] AlphaEval ae;
+                [[maybe_unused]] SurfEval se;
+                if constexpr (SURF) {
+                    se = eval_surfel(r, x, y);
+                    alpha = se.alpha;
+                    raw = se.raw;
+                } else {
+                    ae = eval_alpha(r, x, y);
+                    alpha = ae.alpha;
+                    raw = ae.raw;
+                }
+                if (alpha >= ALPHA_MIN) {
                     contrib = true;
-                    const float inv = 1.0f / (1.0f - ae.alpha);
+                    const float inv = 1.0f / (1.0f - alpha);
                     const float Tk = T * inv;
-                    w = ae.alpha * Tk;
+                    w = alpha * Tk;
                     const float gk = r.r2.y * dCp[0] + r.r2.z * dCp[1] + r.r2.w * dCp[2] + gacc[k];
                     const float dalpha = Tk * gk - (S + Tfin * dTp) * inv;
                     S += w * gk;
                     T = Tk;
-                    const float dpow = (ae.raw < ALPHA_MAX) ? dalpha * ae.alpha : 0.0f;
-                    // d power / d(u, v) = Sigma2^-1 d, from the eigenframe:
-                    // Sigma2^-1 d = -2 ln2 (q1 a e1 + q2 b e2), e2 = (-e_y, e_x)
-                    const float ex = r.r1.x, ey = r.r1.y;
-                    const float qa = r.r1.z * ae.a, qb = r.r1.w * ae.b;
-                    const float sdx = -2.0f * LN2 * (qa * ex - qb * ey);
-                    const float sdy = -2.0f * LN2 * (qa * ey + qb * ex);
-                    q[0] = dpow * sdx;
-                    q[1] = dpow * sdy;
-                    q[2] = dpow * (-0.5f * ae.dx * ae.dx);
-                    q[3] = dpow * (-ae.dx * ae.dy);
-                    q[4] = dpow * (-0.5f * ae.dy * ae.dy);
-                    q[5] = dpow;
-                    q[6] = w * dCp[0];
-                    q[7] = w * dCp[1];
-                    q[8] = w * dCp[2];
-                    q[9] = w;
+                    const float dpow = (raw < ALPHA_MAX) ? dalpha * alpha : 0.0f;
+                    if constexpr (SURF) {
+                        // dL/dk = dpow (-u / k2, -v / k2, (u^2 + v^2) / k2), k linear in the record
+                        const float l0 = -dpow * se.u * se.ik2, l1 = -dpow * se.v * se.ik2;
+                        const float l2 = dpow * (se.u * se.u + se.v * se.v) * se.ik2;
+                        const float a0 = r.r1.x, a1 = r.r1.y, b0 = r.r1.z, b1 = r.r1.w;
+                        const float e1 = r.r3.y, e2 = r.r3.z;
+                        q[0] = -(l0 * b1 - l1 * b0 - l2 * e2);
+                        q[1] = -(l1 * a0 - l0 * a1 - l2 * e1);
+                        q[2] = l1 * se.dy;
+                        q[3] = -l0 * se.dy;
+                        q[4] = -l1 * se.dx;
+                        q[5] = l0 * se.dx;
+                        q[6] = l2;
+                        q[7] = -l2 * se.dy;
+                        q[8] = -l2 * se.dx;
+                    } else {
+                        // d power / d(u, v) = Sigma2^-1 d, from the eigenframe:
+                        // Sigma2^-1 d = -2 ln2 (q1 a e1 + q2 b e2), e2 = (-e_y, e_x)
+                        const float ex = r.r1.x, ey = r.r1.y;
+                        const float qa = r.r1.z * ae.a, qb = r.r1.w * ae.b;
+                        const float sdx = -2.0f * LN2 * (qa * ex - qb * ey);
+                        const float sdy = -2.0f * LN2 * (qa * ey + qb * ex);
+                        q[0] = dpow * sdx;
+                        q[1] = dpow * sdy;
+                        q[2] = dpow * (-0.5f * ae.dx * ae.dx);
+                        q[3] = dpow * (-ae.dx * ae.dy);
+                        q[4] = dpow * (-0.5f * ae.dy * ae.dy);
+                    }
+                    q[NQ - 5] = dpow;
+                    q[NQ - 4] = w * dCp[0];
+                    q[NQ - 3] = w * dCp[1];
+                    q[NQ - 2] = w * dCp[2];
+                    q[NQ - 1] = w;
                 }
             }
             if (FUSE) sW[threadIdx.x * (K + 1) + k] = w;
             if (__any(contrib)) {
 #pragma unroll
-                for (int m = 0; m < 10; ++m) {
+                for (int m = 0; m < NQ; ++m) {
                     const float r = wave_sum(q[m]);
                     if (lane == 0) sred[wv][k][m] = r;
                 }
             } else if (lane == 0) {
 #pragma unroll
-                for (int m = 0; m < 10; ++m) sred[wv][k][m] = 0.0f;
+                for (int m = 0; m < NQ; ++m) sred[wv][k][m] = 0.0f;
             }
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cnt * 12; idx += 256) {
-            const int k = idx / 12, m = idx - k * 12;
-            const float val = m < 10 ? (sred[0][k][m] + sred[1][k][m]) + (sred[2][k][m] + sred[3][k][m]) : 0.0f;
-            a.part_geom[((int64_t)voff + cs + k) * 12 + m] = val;
+        for (int idx = threadIdx.x; idx < cnt * GP; idx += 256) {
+            const int k = idx / GP, m = idx - k * GP;
+            const float val = m < NQ ? (sred[0][k][m] + sred[1][k][m]) + (sred[2][k][m] + sred[3][k][m]) : 0.0f;
+            a.part_geom[((int64_t)voff + cs + k) * GP + m] = val;
         }
         if (FUSE && D > 0) {
             // sum_p w(p) target(p) for the chunk's instances; pixels outside the image have w = 0
@@ -305,15 +397,13 @@ __global__ __launch_bounds__(256) void k_render_bwd_f32(BwdArgs a, ViewTable vt)
 // record with one load.
 __global__ __launch_bounds__(256) void k_rank_tables(const uint32_t* __restrict__ order, const float4* __restrict__ rec,
                                                      int64_t n, int64_t total, uint32_t* __restrict__ rank_of,
-                                                     float4* __restrict__ rrec) {
+                                                     float4* __restrict__ rrec, int rw) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= total) return;
     const int64_t v = j / n;
     const int64_t i = v * n + order[j];
     rank_of[i] = (uint32_t)(j - v * n);
-    rrec[3 * j] = rec[3 * i];
-    rrec[3 * j + 1] = rec[3 * i + 1];
-    rrec[3 * j + 2] = rec[3 * i + 2];
+    for (int k = 0; k < rw; ++k) rrec[rw * j + k] = rec[rw * i + k];
 }
 
 __global__ __launch_bounds__(256) void k_fuse_finalize(const float* sum, const float* comp, const float* wsum,
@@ -339,31 +429,47 @@ __global__ __launch_bounds__(256) void k_fuse_finalize(const float* sum, const f
 }
 
 // ---------------------------------------------------------------------------
-void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
+template <bool SURF>
+static void launch_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
     if (a.d == 0) {
-        hipLaunchKernelGGL(k_render_fwd_f32<0>, dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
+        hipLaunchKernelGGL((k_render_fwd_f32<0, SURF>), dim3(n_tiles, 1), dim3(256), 0, s, a, vt);
         return;
     }
     const unsigned ns = (unsigned)((a.d + slice - 1) / slice);
     switch (slice) {
-        case 8: hipLaunchKernelGGL(k_render_fwd_f32<8>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
-        case 16: hipLaunchKernelGGL(k_render_fwd_f32<16>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
-        case 32: hipLaunchKernelGGL(k_render_fwd_f32<32>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
-        default: hipLaunchKernelGGL(k_render_fwd_f32<64>, dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        case 8: hipLaunchKernelGGL((k_render_fwd_f32<8, SURF>), dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        case 16: hipLaunchKernelGGL((k_render_fwd_f32<16, SURF>), dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        case 32: hipLaunchKernelGGL((k_render_fwd_f32<32, SURF>), dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
+        default: hipLaunchKernelGGL((k_render_fwd_f32<64, SURF>), dim3(n_tiles, ns), dim3(256), 0, s, a, vt); break;
     }
+}
+
+void launch_render_fwd_f32(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, hipStream_t s) {
+    if (a.prim == FH_PRIM_SURFEL)
+        launch_fwd_f32<true>(a, vt, n_tiles, slice, s);
+    else
+        launch_fwd_f32<false>(a, vt, n_tiles, slice, s);
 }
 
 void launch_check_visits(const uint32_t* tile_voff, int n_tiles, Counters* c, int64_t cap, hipStream_t s) {
     hipLaunchKernelGGL(k_check_visits, dim3(1), dim3(64), 0, s, tile_voff, n_tiles, c, cap);
 }
 
-template <int K>
-static void launch_bwd_k(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s) {
+template <int K, bool SURF>
+static void launch_bwd_ks(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s) {
     const size_t dyn = sizeof(float) * ((size_t)K * (a.d > 0 ? a.d : 1) + (fuse ? (size_t)256 * (K + 1) : 0));
     if (fuse)
-        hipLaunchKernelGGL((k_render_bwd_f32<K, true>), dim3(n_tiles), dim3(256), dyn, s, a, vt);
+        hipLaunchKernelGGL((k_render_bwd_f32<K, true, SURF>), dim3(n_tiles), dim3(256), dyn, s, a, vt);
     else
-        hipLaunchKernelGGL((k_render_bwd_f32<K, false>), dim3(n_tiles), dim3(256), dyn, s, a, vt);
+        hipLaunchKernelGGL((k_render_bwd_f32<K, false, SURF>), dim3(n_tiles), dim3(256), dyn, s, a, vt);
+}
+
+template <int K>
+static void launch_bwd_k(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, hipStream_t s) {
+    if (a.prim == FH_PRIM_SURFEL)
+        launch_bwd_ks<K, true>(a, vt, n_tiles, fuse, s);
+    else
+        launch_bwd_ks<K, false>(a, vt, n_tiles, fuse, s);
 }
 
 void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool fuse, int chunk, hipStream_t s) {
@@ -374,9 +480,9 @@ void launch_render_bwd_f32(const BwdArgs& a, const ViewTable& vt, int n_tiles, b
 }
 
 void launch_rank_tables(const uint32_t* order, const float4* rec, int64_t n, int64_t total, uint32_t* rank_of,
-                        float4* rrec, hipStream_t s) {
+                        float4* rrec, int rw, hipStream_t s) {
     hipLaunchKernelGGL(k_rank_tables, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, order, rec, n, total,
-                       rank_of, rrec);
+                       rank_of, rrec, rw);
 }
 
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,

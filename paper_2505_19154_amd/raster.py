@@ -142,7 +142,7 @@ class Rasterizer:
 
     def __init__(self, cams, n: int, sh_degree: int, d: int, feat_dtype: str = "f32", form: str = "f32",
                  device="cuda", inst_capacity: int = 0, visit_capacity: int = 0, bin_rule: str = "box",
-                 ndfd: bool = False):
+                 ndfd: bool = False, primitive: str = "gaussian"):
         self.lib = L.load()
         self.cams = list(cams)
         self.cam_arr = (L.FhCamera * len(self.cams))(*[camera_struct(c) for c in self.cams])
@@ -153,6 +153,10 @@ class Rasterizer:
             raise L.FhError(f"bin_rule must be 'box' or 'opacity', not {bin_rule!r}")
         self.bin_rule = L.FH_BIN_OPACITY if bin_rule == "opacity" else L.FH_BIN_BOX
         self.ndfd = bool(ndfd)         # workspace storage for the NDFD gradient
+        if primitive not in ("gaussian", "surfel"):
+            raise L.FhError(f"primitive must be 'gaussian' or 'surfel', not {primitive!r}")
+        # surfels (Section 3.1's planar primitives): FP32 form only
+        self.primitive = L.FH_PRIM_SURFEL if primitive == "surfel" else L.FH_PRIM_GAUSSIAN
         self.device = torch.device(device)
         self.plan = None
         self.ws = None
@@ -168,6 +172,8 @@ class Rasterizer:
         plan = L.FhPlan()
         L.check(self.lib.fh_plan_init(ctypes.byref(plan), self.n, self.sh_degree, self.d, self.feat_dtype, self.form,
                                       self.cam_arr, len(self.cams), int(inst_cap), int(visit_cap)), "fh_plan_init")
+        if self.primitive != L.FH_PRIM_GAUSSIAN:
+            L.check(self.lib.fh_plan_set_primitive(ctypes.byref(plan), self.primitive), "fh_plan_set_primitive")
         if self.tuning is not None:
             plan.tuning = self.tuning
         plan.bin_rule = self.bin_rule

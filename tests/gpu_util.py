@@ -57,10 +57,12 @@ def concat(vts, key, device="cuda"):
 
 
 def run_gpu(g: dict, cams, vts=None, fusion=False, form="f32", margin=1.05, bin_rule="box"):
+    """bin_rule "surfel" renders the primitives as surfels (with their own binning rule)."""
     from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
     dg = device_gaussians(g)
+    surf = bin_rule == "surfel"
     r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=g.get("feat_dtype", "f32"), form=form,
-                   bin_rule=bin_rule)
+                   bin_rule="box" if surf else bin_rule, primitive="surfel" if surf else "gaussian")
     img = r.forward(dg, margin)
     out = dict(r=r, g=dg, img=img)
     if vts is not None:

@@ -39,15 +39,25 @@ SCENES = {
     # splats of 1-2 tiles: some 2048-instance duplication ranges span more
     # than 1024 ranks (up to 1260) and take the per-instance rank search
     "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
+    # surfels (Section 3.1's planar primitive; FP32 form): ray-plane
+    # intersection, disc-image binning; scales x3 so that most span pixels
+    "surfel_sh2": (2000, 1.5, 2, 16, "f32", "front120x90", "f32", "surfel"),
+    "surfel_multiview_bf16feat": (1500, 1.2, 1, 32, "bf16", "three", "f32", "surfel"),
 }
 # BF16-MFMA form: F, the feature part of the adjoint and the fusion sums are
 # contractions over two-term BF16 splits (tests/gpu_util.py: RTOL_FORM).
 F_RTOL = U.RTOL_FORM
 
 
+def _rule(name):
+    return SCENES[name][7] if len(SCENES[name]) > 7 else "box"
+
+
 def _scene(name, seed=0):
-    n, h, deg, d, fdt, camr, _ = SCENES[name]
+    n, h, deg, d, fdt, camr, _ = SCENES[name][:7]
     g = scenegen.make_gaussians(n, h, deg, d, seed=seed, feat_dtype=fdt)
+    if _rule(name) == "surfel":
+        g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
     if camr == "three":
         cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in
                 (((0, -4, 0), 96, 80), ((3, -2.5, 1.2), 130, 70), ((-2, 1.5, 3.2), 64, 64))]
@@ -63,8 +73,9 @@ def case(request):
     # the BF16 form takes a BF16 fusion target (an MFMA operand as stored)
     vts = U.view_maps(cams, g["d"], with_dT=True, target_dtype="bf16" if form == "bf16" else "f32")
     print(f"\n[case {request.param}] n={g['means'].shape[0]} views={len(cams)}", flush=True)
-    gpu = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=form)
-    ora = U.run_oracle(g, cams, vts, fusion=g["d"] > 0)
+    rule = _rule(request.param)
+    gpu = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=form, bin_rule=rule)
+    ora = U.run_oracle(g, cams, vts, fusion=g["d"] > 0, bin_rule=rule)
     return dict(name=request.param, g=g, cams=cams, vts=vts, gpu=gpu, ora=ora, form=form)
 
 
@@ -110,14 +121,16 @@ def test_forward_parity(case):
     Cr = np.concatenate([v["C"] for v in ora["views"]])
     Cm = np.concatenate([v["Cmag"] for v in ora["views"]])
     Tr = np.concatenate([v["T"] for v in ora["views"]])
+    Cd = np.concatenate([v["Cden"] for v in ora["views"]])
+    Td = np.concatenate([v["Tden"] for v in ora["views"]])
     nr = np.concatenate([v["niter"] for v in ora["views"]])
     ok, flags = _pixel_masks(case)
     amb = 1.0 - ok.mean()
     print(f"[{case['name']}] ambiguous pixels {amb:.2e}", flush=True)
     assert amb < 1e-2
     assert np.array_equal(nit[ok], nr[ok])
-    mC, aC = U.elementwise(C, Cr, Cm, mask=ok[:, None].repeat(3, 1))
-    mT, aT = U.elementwise(T, Tr, Tr, mask=ok)
+    mC, aC = U.elementwise(C, Cr, Cm, mask=ok[:, None].repeat(3, 1), amb=Cd)
+    mT, aT = U.elementwise(T, Tr, Tr, mask=ok, amb=Td)
     print(f"[{case['name']}] C max/mean ratio {mC:.3f}/{aC:.3f}  T {mT:.3f}/{aT:.3f}  "
           f"norm C {U.normwise(C, Cr):.2e} T {U.normwise(T, Tr):.2e}", flush=True)
     assert mC <= 1.0 and mT <= 1.0
@@ -126,8 +139,9 @@ def test_forward_parity(case):
         F = img.F.cpu().numpy()
         Fr = np.concatenate([v["F"] for v in ora["views"]])
         Fm = np.concatenate([v["Fmag"] for v in ora["views"]])
+        Fd = np.concatenate([v["Fden"] for v in ora["views"]])
         rt = F_RTOL[case["form"]]
-        mF, aF = U.elementwise(F, Fr, Fm, rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1))
+        mF, aF = U.elementwise(F, Fr, Fm, rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1), amb=Fd)
         err = np.abs(F - Fr)[ok] / np.maximum(Fm[ok], 1e-30)
         print(f"[{case['name']}] F max/mean ratio {mF:.3f}/{aF:.3f} (rtol {rt:g}) norm {U.normwise(F, Fr):.2e} "
               f"max/mean |dF|/M {err.max():.2e}/{err.mean():.2e}", flush=True)
@@ -172,7 +186,7 @@ def test_fusion_parity(case):
 
 def test_deterministic_rerun(case):
     g, cams, vts = case["g"], case["cams"], case["vts"]
-    again = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=case["form"])
+    again = U.run_gpu(g, cams, vts, fusion=g["d"] > 0, form=case["form"], bin_rule=_rule(case["name"]))
     a, b = case["gpu"], again
     assert torch.equal(a["img"].C, b["img"].C) and torch.equal(a["img"].T, b["img"].T)
     for k in a["grads"]:
