@@ -109,7 +109,7 @@ BRACKET_KERNELS = {
     ("project", "f32"): ("k_project",), ("project", "bf16"): ("k_project",),
     ("render_fwd", "f32"): ("k_render_fwd_f32",), ("render_fwd", "bf16"): ("k_render_fwd_bf16",),
     ("render_bwd", "f32"): ("k_visit_stage", "k_render_bwd_f32"),
-    ("render_bwd", "bf16"): ("k_visit_stage", "k_render_bwd_bf16", "k_fuse_bf16"),
+    ("render_bwd", "bf16"): ("k_visit_stage", "k_render_bwd_bf16", "k_fuse_bf16", "k_fuse_rec_bf16", "k_gk_bf16"),
     ("project_bwd", "f32"): ("k_project_bwd",), ("project_bwd", "bf16"): ("k_project_bwd",),
 }
 COPY_BYTES = 1 << 30       # the calibration kernel reads and writes this many bytes
@@ -324,10 +324,12 @@ def load_workload(wl, dev):
 KERNEL_IDS = None
 
 
-def run_form(W, form_name: str, kernel: str, args, dev, graph: bool = False):
+def run_form(W, form_name: str, kernel: str, args, dev, graph: bool = False, primitive: str = "gaussian"):
     """Warm up, then time K steps of one arithmetic form.  The chosen kernel is
     bracketed by HIP events on its own stream over K eager steps.  With graph,
-    the step is captured in one HIP graph and the K timed steps are replays."""
+    the step is captured in one HIP graph and the K timed steps are replays.
+    primitive: "gaussian" or "surfel" (the workload's parameters taken as
+    surfels: scales[:, 0:2] the planar scales)."""
     import torch
 
     from paper_2505_19154_amd import _lib as L
@@ -337,8 +339,9 @@ def run_form(W, form_name: str, kernel: str, args, dev, graph: bool = False):
            "render_bwd": L.FH_K_RENDER_BWD, "reduce": L.FH_K_REDUCE, "project_bwd": L.FH_K_PROJECT_BWD}
     wl, cams, dg = W["wl"], W["cams"], W["dg"]
     dC, dF, dT, target = W["dC"], W["dF"], W["dT"], W["target"]
-    tag = f"[bench] {wl.name} {form_name}"
-    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev)
+    tag = f"[bench] {wl.name} {form_name}" + ("" if primitive == "gaussian" else f" {primitive}")
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form=form_name, device=dev,
+                   primitive=primitive)
     img = r.forward(dg, margin=1.02)
     tuning = r.autotune(dg, img, dC, dF, dT, target=target, reps=2) if args.autotune else None
     acc = FusionAcc.zeros(wl.n, wl.d, dev) if wl.fusion else None
@@ -567,6 +570,35 @@ def extras_leg(W, args, dev):
     print(f"[bench] train: adam {ms_adam:.3f} ms, loss {ms_pl:.3f} ms, step {ms_train:.3f} ms",
           file=sys.stderr, flush=True)
     del r, img
+    torch.cuda.empty_cache()
+    out["surfel"] = surfel_leg(W, args, dev)
+    return out
+
+
+def surfel_leg(W, args, dev):
+    """The surfel primitive (Section 3.1) on the headline workload: the same
+    parameters taken as surfels (scales[:, 0:2] the planar scales), the whole
+    step (project, bin_sort, render_fwd, render_bwd with fusion) in the FP32
+    form, the only one with surfel kernels.  The gradient launch's roofline
+    counts the surfel record (64 B) and partial row (64 B) per visited
+    Gaussian in place of the Gaussian's 48 B each."""
+    import torch
+
+    wl = W["wl"]
+    res = run_form(W, "f32", "render_bwd", args, dev, primitive="surfel")
+    n_vis = visible_count(res["r"], wl, len(W["cams"]))
+    feat_b = 2 if wl.feat_dtype == "bf16" else 4
+    ab, per_unit = alg_bytes("render_bwd", wl, res["r"].n_pixels, n_vis, int(res["c"].n_instances), feat_b, feat_b)
+    ab += 32 * n_vis
+    achieved = ab / (res["kms"] * 1e-3) / 1e9
+    out = dict(form="f32", ms_per_step=res["ms"], ms_per_step_median=res["median_ms"],
+               blends=res["blends"], blends_per_s=res["blends"] / (res["ms"] * 1e-3),
+               instances=int(res["c"].n_instances), visited_instances=int(res["c"].n_visited),
+               visible_surfels=n_vis, tuning=res["tuning"],
+               roofline=dict(kernel="render_bwd", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, kernel_ms=res["kms"], algorithmic_bytes=ab,
+                             per_unit=per_unit + " (+32 B per visible surfel: larger record and partial row)"))
+    del res
     torch.cuda.empty_cache()
     return out
 
