@@ -93,8 +93,7 @@ typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
  *                     of the disc u^2 + v^2 <= kappa_i (the opacity-aware
  *                     kappa_i of FH_BIN_OPACITY, whatever bin_rule says),
  *                     and surfels whose disc reaches the camera plane are
- *                     culled.  FP32 form only (FH_E_UNSUPPORTED otherwise);
- *                     no NDFD branch. */
+ *                     culled.  Both arithmetic forms; no NDFD branch. */
 typedef enum { FH_PRIM_GAUSSIAN = 0, FH_PRIM_SURFEL = 1 } fh_primitive;
 
 /* Arithmetic form of the compositing kernels. */
@@ -287,8 +286,8 @@ fh_status fh_plan_init(fh_plan *plan, int64_t n, int32_t sh_degree, int32_t d, f
 fh_status fh_plan_set_ndfd(fh_plan *plan, int32_t enable);
 
 /* Choose the primitive (fh_primitive; Section 3.1's surfels or 3D Gaussians)
- * of a plan from fh_plan_init.  Surfels need the FP32 form and a plan without
- * the NDFD storage (FH_E_UNSUPPORTED otherwise); their records take 64 B per
+ * of a plan from fh_plan_init.  Surfels need a plan without the NDFD storage
+ * (FH_E_UNSUPPORTED otherwise); their records take 64 B per
  * (view, primitive) and their per-instance partials 64 B per visited
  * instance.  Resets the launch shape to the primitive's default and
  * recomputes the workspace layout; set it before allocating the workspace. */

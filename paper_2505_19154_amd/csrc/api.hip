@@ -131,9 +131,10 @@ static fh_status time_calls(Fn f, int reps, hipStream_t s, float* ms) {
 static int rec_w(const fh_plan* p) { return p->primitive == FH_PRIM_SURFEL ? 4 : 3; }
 static int geom_w(const fh_plan* p) { return p->primitive == FH_PRIM_SURFEL ? 16 : 12; }
 
-// (Surfels, FP32 form only, composite on the VALU forward.)
+// (Surfels take the MFMA forward in the BF16 form only; in the FP32 form they
+// composite on the VALU forward.)
 static bool mfma_forward(int d, int form, int feat_dtype, int prim) {
-    if (prim == FH_PRIM_SURFEL) return false;
+    if (prim == FH_PRIM_SURFEL) return form == FH_FORM_BF16;
     return form == FH_FORM_BF16 ||
            (feat_dtype == FH_F32 && (d == 32 || d == 64 || d == 96 || (d > 0 && d % 128 == 0)));
 }
@@ -370,7 +371,7 @@ fh_status fh_plan_set_ndfd(fh_plan* plan, int32_t enable) {
 fh_status fh_plan_set_primitive(fh_plan* plan, int32_t primitive) {
     if (!plan) return FH_E_INVALID;
     if (primitive != FH_PRIM_GAUSSIAN && primitive != FH_PRIM_SURFEL) return FH_E_INVALID;
-    if (primitive == FH_PRIM_SURFEL && (plan->form != FH_FORM_F32 || plan->ndfd)) return FH_E_UNSUPPORTED;
+    if (primitive == FH_PRIM_SURFEL && plan->ndfd) return FH_E_UNSUPPORTED;
     plan->primitive = primitive;
     plan->tuning = default_tuning(plan->d, plan->form, plan->feat_dtype, primitive);
     plan_layout(plan);

@@ -166,6 +166,133 @@ __device__ __forceinline__ AlphaEval eval_alpha(const Rec& r, float x, float y) 
 }
 
 // ---------------------------------------------------------------------------
+// Surfel record of one (view, surfel) (Section 3.1), four float4:
+//   r0 = (x_c hi, y_c hi, x_c lo, y_c lo)   projected centre, a float pair
+//   r1 = (a0, a1, b0, b1)                   plane map rows: pixel offsets
+//   r3 = (D, e1, e2, 0)                     (dx w, dy w) = (a0 u + a1 v, b0 u + b1 v),
+//                                           w = 1 + c0 u + c1 v, D = a0 b1 - a1 b0,
+//                                           e1 = a0 c1 - a1 c0, e2 = c0 b1 - c1 b0
+//   r2 = (opacity, r, g, b)                 (the same slot as a Gaussian's)
+struct SRec {
+    float4 r0, r1, r2, r3;
+};
+static_assert(sizeof(SRec) == 64, "surfel records are read and written as 16 consecutive dwords");
+
+// The plane point (u, v) = (k0, k1) / k2 that the ray of pixel offsets
+// (dx, dy) meets: k0 = dx b1 - dy a1, k1 = dy a0 - dx b0, k2 = D - dy e1 - dx e2;
+// ik2 = 1 / k2 by the hardware reciprocal, 0 for a ray parallel to the plane.
+struct SurfPlane {
+    float u, v, ik2;
+    bool hit;
+};
+__device__ __forceinline__ SurfPlane surfel_plane(const SRec& r, float dx, float dy) {
+#pragma clang fp contract(off)
+    SurfPlane s;
+    const float a0 = r.r1.x, a1 = r.r1.y, b0 = r.r1.z, b1 = r.r1.w;
+    const float k0 = __builtin_fmaf(dx, b1, -(dy * a1));
+    const float k1 = __builtin_fmaf(dy, a0, -(dx * b0));
+    const float k2 = __builtin_fmaf(-dx, r.r3.z, __builtin_fmaf(-dy, r.r3.y, r.r3.x));
+    s.hit = k2 != 0.0f;
+    s.ik2 = s.hit ? __builtin_amdgcn_rcpf(k2) : 0.0f;
+    s.u = k0 * s.ik2;
+    s.v = k1 * s.ik2;
+    return s;
+}
+
+// A surfel at pixel centre (x, y): pixel offsets from the projected centre,
+// the plane point its ray meets, G = exp(-(u^2 + v^2)/2) (0 for a ray parallel
+// to the plane), alpha = min(0.99, o G).  Every kernel evaluates alpha with
+// this function, so forward and backward take the same decisions.
+struct SurfEval {
+    float dx, dy, u, v, ik2, raw, alpha;
+};
+__device__ __forceinline__ SurfEval eval_surfel(const SRec& r, float x, float y) {
+#pragma clang fp contract(off)
+    SurfEval e;
+    e.dx = (x - r.r0.x) - r.r0.z;
+    e.dy = (y - r.r0.y) - r.r0.w;
+    const SurfPlane sp = surfel_plane(r, e.dx, e.dy);
+    e.ik2 = sp.ik2;
+    e.u = sp.u;
+    e.v = sp.v;
+    // exp(-r2 / 2) = exp2(-(log2 e / 2) r2)
+    const float G = sp.hit ? __builtin_amdgcn_exp2f(-0.72134752044448170f * (e.u * e.u + e.v * e.v)) : 0.0f;
+    e.raw = r.r2.x * G;
+    e.alpha = fminf(ALPHA_MAX, e.raw);
+    return e;
+}
+
+// Per-primitive record type, width and per-instance partial row:
+// NQ terms in rows of GP floats, the weight sum at WSLOT.
+template <bool SURF>
+struct PrimRec {
+    using T = Rec;
+    static constexpr int RW = 3;
+    static constexpr int NQ = 10, GP = 12, WSLOT = 9;
+};
+template <>
+struct PrimRec<true> {
+    using T = SRec;
+    static constexpr int RW = 4;
+    static constexpr int NQ = 14, GP = 16, WSLOT = 13;
+};
+template <bool SURF>
+__device__ __forceinline__ typename PrimRec<SURF>::T load_rec(const float4* base, int64_t j) {
+    typename PrimRec<SURF>::T r;
+    r.r0 = base[PrimRec<SURF>::RW * j];
+    r.r1 = base[PrimRec<SURF>::RW * j + 1];
+    r.r2 = base[PrimRec<SURF>::RW * j + 2];
+    if constexpr (SURF) r.r3 = base[PrimRec<SURF>::RW * j + 3];
+    return r;
+}
+// A record that never blends (opacity 0), for the padding positions of a chunk.
+template <bool SURF>
+__device__ __forceinline__ typename PrimRec<SURF>::T pad_rec() {
+    typename PrimRec<SURF>::T r;
+    r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (SURF) {
+        r.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.r3 = make_float4(1.f, 0.f, 0.f, 0.f);
+    } else {
+        r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
+    }
+    return r;
+}
+template <bool SURF>
+__device__ __forceinline__ float prim_alpha(const typename PrimRec<SURF>::T& r, float x, float y) {
+    if constexpr (SURF)
+        return eval_surfel(r, x, y).alpha;
+    else
+        return eval_alpha(r, x, y).alpha;
+}
+
+// Chunk records staged in LDS as RW float4 each, with one float4 of padding
+// after every G records (as rec_slot for the three-float4 records).
+template <bool SURF, int G>
+__device__ __forceinline__ int prec_slot(int k) {
+    return PrimRec<SURF>::RW * k + k / G;
+}
+template <bool SURF, int G>
+__device__ __forceinline__ typename PrimRec<SURF>::T lds_prec(const float4* base, int k) {
+    const float4* p = base + prec_slot<SURF, G>(k);
+    typename PrimRec<SURF>::T r;
+    r.r0 = p[0];
+    r.r1 = p[1];
+    r.r2 = p[2];
+    if constexpr (SURF) r.r3 = p[3];
+    return r;
+}
+template <bool SURF, int G>
+__device__ __forceinline__ void lds_put_prec(float4* base, int k, const typename PrimRec<SURF>::T& r) {
+    float4* p = base + prec_slot<SURF, G>(k);
+    p[0] = r.r0;
+    p[1] = r.r1;
+    p[2] = r.r2;
+    if constexpr (SURF) p[3] = r.r3;
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront helpers (64 lanes).
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

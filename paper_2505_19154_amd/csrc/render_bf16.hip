@@ -7,6 +7,9 @@
 // bits of w; the features are BF16 already.  Everything else (alpha, the
 // transmittance walk, colour) stays on the VALU in FP32.
 //
+// SURF: the surfel primitive (Section 3.1): four-float4 records, alpha at the
+// ray-plane intersection; the rest is the same.
+//
 // Work mapping: one workgroup per (tile, group of ROWS pixel rows, channel
 // slice of DS); wave w is pixel row w of its group; lane l handles pixel
 // x = l % 16 and Gaussians 8 (l / 16) .. 8 (l / 16) + 7 of each 32-Gaussian
@@ -44,7 +47,7 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
 // into three BF16 terms (x = h + m + l, h = bf16(x), m = bf16(x - h),
 // l = bf16(x - h - m)) and F takes the six products hh, hm, mh, hl, lh, mm:
 // what is left out is below 2^-24 of w f, so F keeps FP32 accuracy on MFMA.
-template <int DS, int ROWS, bool FS>
+template <int DS, int ROWS, bool FS, bool SURF>
 // (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per
 // CU; 4-row shapes are two or four workgroups per CU, each with its own barriers)
 __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (ROWS == 4 ? 2 : 1)) void k_render_fwd_bf16(
@@ -54,7 +57,9 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
     constexpr int NT = 64 * ROWS;                        // threads
     constexpr int NIT = (FK * (DS / 8) + NT - 1) / NT;   // feature items per thread
     constexpr int RG = 8;                                 // record padding group (lanes read records 8 apart)
-    __shared__ float4 srec4[3][3 * FK + FK / RG];
+    using RecT = typename PrimRec<SURF>::T;
+    constexpr int RW = PrimRec<SURF>::RW;                 // float4 per record
+    __shared__ float4 srec4[3][RW * FK + FK / RG];
     __shared__ uint32_t sg[3][FK];
     constexpr int NFT = FS ? 3 : 1;                       // feature tiles: h (+ m, l)
     constexpr int NFR = FS ? 2 * NIT : NIT;               // 16-byte registers of one chunk's feature items
@@ -84,26 +89,18 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
     const uint32_t rmask = a.packed ? ((1u << a.rank_bits) - 1u) : 0xFFFFFFFFu;
     const int k = (int)threadIdx.x;   // list position within a chunk (threads 0..FK-1)
 
-    auto put_rec = [&](int buf, uint32_t pos, const Rec& r, uint32_t g) {
+    auto put_rec = [&](int buf, uint32_t pos, const RecT& r, uint32_t g) {
         const bool real = pos < len;
-        Rec o = r;
-        if (!real) {
-            // padding: opacity 0 never blends
-            o.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            o.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-            o.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        lds_put_rec<RG>(srec4[buf], k, o);
+        // padding: opacity 0 never blends
+        const RecT o = real ? r : pad_rec<SURF>();
+        lds_put_prec<SURF, RG>(srec4[buf], k, o);
         sg[buf][k] = real ? g : 0xFFFFFFFFu;
     };
     // e: a raw list entry (masked here, where it is used, so that its load is
     // not waited for where it is issued)
-    auto get_rec = [&](uint32_t e, Rec& r, uint32_t& g) {
+    auto get_rec = [&](uint32_t e, RecT& r, uint32_t& g) {
         const uint32_t j = e & rmask;
-        const float4* src = a.rrec + 3 * (int64_t)j;
-        r.r0 = src[0];
-        r.r1 = src[1];
-        r.r2 = src[2];
+        r = load_rec<SURF>(a.rrec, j);
         g = a.order[j];
     };
     // feature items of one chunk: item = k + FK * dg, 8 channels each; padding
@@ -168,7 +165,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
         const uint32_t j0 = list_load(list_rs, (uint32_t)k);
         const uint32_t j1 = list_load(list_rs, (uint32_t)(FK + k));
         rk2 = list_load(list_rs, (uint32_t)(2 * FK + k));
-        Rec r0, r1;
+        RecT r0, r1;
         uint32_t g0, g1;
         get_rec(j0, r0, g0);
         get_rec(j1, r1, g1);
@@ -195,7 +192,7 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
     for (uint32_t cpos = 0; cpos < len; cpos += FK) {
         const int n3 = b3 == 2 ? 0 : b3 + 1, nn3 = n3 == 2 ? 0 : n3 + 1;
         // chunk c+2's records and Gaussians, chunk c+3's ranks, chunk c+1's features: all in flight now
-        Rec r2;
+        RecT r2;
         uint32_t g2 = 0u, rk3 = 0u;
         if (k < FK) {
             get_rec(rk2, r2, g2);
@@ -209,8 +206,8 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
         float P = 1.0f;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const AlphaEval ae = eval_alpha(lds_rec<RG>(srec4[b3], 8 * q + m), x, y);
-            al[m] = ae.alpha >= ALPHA_MIN ? ae.alpha : 0.0f;
+            const float alpha = prim_alpha<SURF>(lds_prec<SURF, RG>(srec4[b3], 8 * q + m), x, y);
+            al[m] = alpha >= ALPHA_MIN ? alpha : 0.0f;
             P *= (1.0f - al[m]);
         }
         const Rows4 Pr = rows4(P);
@@ -229,16 +226,16 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
             // exactly).  The branch-free form needs more registers than the
             // shapes that keep four waves per SIMD have.
             float wv = 0.0f;
-            const Rec r = lds_rec<RG>(srec4[b3], 8 * q + m);
+            const float4 col = srec4[b3][prec_slot<SURF, RG>(8 * q + m) + 2];   // (opacity, r, g, b)
             if constexpr (ROWS == 8 && DS > 128) {
                 const float Tn = Tl * (1.0f - al[m]);
                 const bool act = !dl && al[m] > 0.0f;
                 const bool stop = act && Tn < T_MIN;
                 const bool blend = act && !stop;
                 wv = blend ? al[m] * Tl : 0.0f;
-                c0 = __builtin_fmaf(wv, r.r2.y, c0);
-                c1 = __builtin_fmaf(wv, r.r2.z, c1);
-                c2 = __builtin_fmaf(wv, r.r2.w, c2);
+                c0 = __builtin_fmaf(wv, col.y, c0);
+                c1 = __builtin_fmaf(wv, col.z, c1);
+                c2 = __builtin_fmaf(wv, col.w, c2);
                 Tl = blend ? Tn : Tl;
                 mylast = blend ? cpos + 8 * q + m + 1 : mylast;
                 dl = dl || stop;
@@ -251,9 +248,9 @@ __global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (R
                         term = true;
                     } else {
                         wv = al[m] * Tl;
-                        c0 = __builtin_fmaf(wv, r.r2.y, c0);
-                        c1 = __builtin_fmaf(wv, r.r2.z, c1);
-                        c2 = __builtin_fmaf(wv, r.r2.w, c2);
+                        c0 = __builtin_fmaf(wv, col.y, c0);
+                        c1 = __builtin_fmaf(wv, col.z, c1);
+                        c2 = __builtin_fmaf(wv, col.w, c2);
                         Tl = Tn;
                         mylast = cpos + 8 * q + m + 1;
                     }
@@ -387,7 +384,7 @@ bool render_fwd_bf16_shape_ok(int d, int slice, int rows) {
     return false;
 }
 
-template <bool FS>
+template <bool FS, bool SURF>
 static void launch_fwd_mfma(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, hipStream_t s) {
     // slice and rows form a valid shape for d (checked by the caller)
     const unsigned ns = (unsigned)(a.d / slice);
@@ -396,38 +393,41 @@ static void launch_fwd_mfma(const RenderArgs& a, const ViewTable& vt, int n_tile
         // (BF16-stored features only)
         if constexpr (!FS) {
             if (slice == 128)
-                hipLaunchKernelGGL((k_render_fwd_bf16<128, 4, false>), g4, dim3(256), 0, s, a, vt);
+                hipLaunchKernelGGL((k_render_fwd_bf16<128, 4, false, SURF>), g4, dim3(256), 0, s, a, vt);
             else
-                hipLaunchKernelGGL((k_render_fwd_bf16<256, 4, false>), g4, dim3(256), 0, s, a, vt);
+                hipLaunchKernelGGL((k_render_fwd_bf16<256, 4, false, SURF>), g4, dim3(256), 0, s, a, vt);
         }
         return;
     }
     if (rows == 8) {
         switch (slice) {
-            case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
-            case 128: hipLaunchKernelGGL((k_render_fwd_bf16<128, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
-            default: hipLaunchKernelGGL((k_render_fwd_bf16<256, 8, FS>), g8, dim3(512), 0, s, a, vt); break;
+            case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 8, FS, SURF>), g8, dim3(512), 0, s, a, vt); break;
+            case 128: hipLaunchKernelGGL((k_render_fwd_bf16<128, 8, FS, SURF>), g8, dim3(512), 0, s, a, vt); break;
+            default: hipLaunchKernelGGL((k_render_fwd_bf16<256, 8, FS, SURF>), g8, dim3(512), 0, s, a, vt); break;
         }
         return;
     }
     switch (slice) {
-        case 32: hipLaunchKernelGGL((k_render_fwd_bf16<32, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
-        case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
-        case 96: hipLaunchKernelGGL((k_render_fwd_bf16<96, 16, FS>), g16, dim3(1024), 0, s, a, vt); break;
+        case 32: hipLaunchKernelGGL((k_render_fwd_bf16<32, 16, FS, SURF>), g16, dim3(1024), 0, s, a, vt); break;
+        case 64: hipLaunchKernelGGL((k_render_fwd_bf16<64, 16, FS, SURF>), g16, dim3(1024), 0, s, a, vt); break;
+        case 96: hipLaunchKernelGGL((k_render_fwd_bf16<96, 16, FS, SURF>), g16, dim3(1024), 0, s, a, vt); break;
         default:
             // (16 rows of 128 channels is not an FP32-feature shape: it would spill)
-            if constexpr (!FS) hipLaunchKernelGGL((k_render_fwd_bf16<128, 16, false>), g16, dim3(1024), 0, s, a, vt);
+            if constexpr (!FS) hipLaunchKernelGGL((k_render_fwd_bf16<128, 16, false, SURF>), g16, dim3(1024), 0, s, a, vt);
             break;
     }
 }
 
-// BF16 features enter the MFMA as stored; FP32 features (fsplit) as three terms
+// BF16 features enter the MFMA as stored; FP32 features (fsplit) as three terms.
+// Surfels (a.prim): BF16 features only.
 void launch_render_fwd_bf16(const RenderArgs& a, const ViewTable& vt, int n_tiles, int slice, int rows, bool fsplit,
                             hipStream_t s) {
-    if (fsplit)
-        launch_fwd_mfma<true>(a, vt, n_tiles, slice, rows, s);
+    if (a.prim == FH_PRIM_SURFEL)
+        launch_fwd_mfma<false, true>(a, vt, n_tiles, slice, rows, s);
+    else if (fsplit)
+        launch_fwd_mfma<true, false>(a, vt, n_tiles, slice, rows, s);
     else
-        launch_fwd_mfma<false>(a, vt, n_tiles, slice, rows, s);
+        launch_fwd_mfma<false, false>(a, vt, n_tiles, slice, rows, s);
 }
 
 }  // namespace fh

@@ -24,6 +24,10 @@
 // kernel so that each keeps its own per-tile operand (dF or the target)
 // resident without spilling; when both run, the per-instance weight sums come
 // from the gradient kernel alone.
+//
+// SURF: the surfel primitive (Section 3.1): four-float4 records, alpha at the
+// ray-plane intersection, and 14 screen-space terms per instance (the nine
+// record entries', sum dL/dpower, rgb, sum w) in rows of 16 floats.
 #include "kernels.hpp"
 
 namespace fh {
@@ -39,44 +43,37 @@ constexpr int BK = 32;   // positions per chunk
 // Gaussian-parallel reads (consecutive positions per lane) twice
 constexpr int SK = BK + 3;
 constexpr int RG = 4;        // record padding group: the walk's lane rows read records 4 apart
-constexpr int RSLOTS = 3 * BK + BK / RG;   // float4 slots of one chunk's staged records
+// float4 slots of one chunk's staged records
+template <bool SURF>
+constexpr int rslots() {
+    return PrimRec<SURF>::RW * BK + BK / RG;
+}
 
 // Stage the chunk's records (threads 0..31) from the visit-ordered copies;
 // padding records never blend.
+template <bool SURF>
 __device__ __forceinline__ void stage_records(const BwdArgs& a, uint32_t voff, int cs, int cnt, float4* srec,
                                               uint32_t* sg) {
     if (threadIdx.x < BK) {
-        Rec r;
+        typename PrimRec<SURF>::T r;
         if ((int)threadIdx.x < cnt) {
             const int64_t vi = (int64_t)voff + cs + threadIdx.x;
-            r.r0 = a.vrec[3 * vi];
-            r.r1 = a.vrec[3 * vi + 1];
-            r.r2 = a.vrec[3 * vi + 2];
+            r = load_rec<SURF>(a.vrec, vi);
             if (sg) sg[threadIdx.x] = a.vgid[vi];
         } else {
-            r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-            r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            r = pad_rec<SURF>();
             if (sg) sg[threadIdx.x] = 0xFFFFFFFFu;
         }
-        lds_put_rec<RG>(srec, threadIdx.x, r);
+        lds_put_prec<SURF, RG>(srec, threadIdx.x, r);
     }
 }
 
 // One chunk record (position cs + k of the tile's list, or padding past cnt).
-__device__ __forceinline__ Rec fetch_record(const BwdArgs& a, uint32_t voff, int cs, int cnt, int k) {
-    Rec r;
-    if (k < cnt) {
-        const int64_t vi = (int64_t)voff + cs + k;
-        r.r0 = a.vrec[3 * vi];
-        r.r1 = a.vrec[3 * vi + 1];
-        r.r2 = a.vrec[3 * vi + 2];
-    } else {
-        r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-        r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    return r;
+template <bool SURF>
+__device__ __forceinline__ typename PrimRec<SURF>::T fetch_record(const BwdArgs& a, uint32_t voff, int cs, int cnt,
+                                                                  int k) {
+    if (k < cnt) return load_rec<SURF>(a.vrec, (int64_t)voff + cs + k);
+    return pad_rec<SURF>();
 }
 
 // ---------------------------------------------------------------------------
@@ -85,8 +82,11 @@ __device__ __forceinline__ Rec fetch_record(const BwdArgs& a, uint32_t voff, int
 // of both rows, positions 4q..4q+3 of each 16-position half-chunk.
 // SL: one channel slice of a wider feature (rows of stride a.d from channel
 // a.d0; a.g_in adds the earlier slices' part of f . dF)
-template <int D, bool SL>
+template <int D, bool SL, bool SURF>
 __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt) {
+    using RecT = typename PrimRec<SURF>::T;
+    constexpr int RW = PrimRec<SURF>::RW, NQ = PrimRec<SURF>::NQ, GP = PrimRec<SURF>::GP;
+    constexpr int RSLOTS = rslots<SURF>();
     const int dstride = SL ? a.d : D, dofs = SL ? a.d0 : 0;
     constexpr int DP = D + 8;            // padded row stride (bf16) of the feature chunk
     constexpr int NS = D / 32;           // MFMA steps over channels
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     float* sw = reinterpret_cast<float*>(sfeat2 + 2 * BK * DP);              // [256][SK] w
     float* sdp = sw + TILE_PIX * SK;                                         // [256][SK] dL/dpower
     float* sdc = sdp + TILE_PIX * SK;                                        // [256][3] dC of the tile
-    float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][10][BK] partial sums
+    float* sred = sdc + 3 * TILE_PIX;                                        // [8 waves][NQ][BK] partial sums
     __shared__ float4 srecb[3][RSLOTS];   // chunk records and Gaussians, triple-buffered:
     __shared__ uint32_t sgb[3][BK];       // those two chunks ahead arrive during this one
 
@@ -194,10 +194,10 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     // prologue: records and Gaussians of the first two chunks, features of the first
     {
         const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
-        stage_records(a, voff, cs0, (int)nt - cs0, srecb[0], sgb[0]);
+        stage_records<SURF>(a, voff, cs0, (int)nt - cs0, srecb[0], sgb[0]);
         if (cs0 > 0) {
             const int cs1 = cs0 - BK > 0 ? cs0 - BK : 0;
-            stage_records(a, voff, cs1, cs0 - cs1, srecb[1], sgb[1]);
+            stage_records<SURF>(a, voff, cs1, cs0 - cs1, srecb[1], sgb[1]);
         }
     }
     __syncthreads();
@@ -214,22 +214,26 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         const int n3 = b3 == 2 ? 0 : b3 + 1, nn3 = n3 == 2 ? 0 : n3 + 1;
         const float4* srec = srecb[b3];
         const __bf16* sfeat = sfeat2 + f2 * BK * DP;
-        // records (12 dwords each, threads 0..12 BK-1) and Gaussians (threads
-        // 12 BK..13 BK-1) of the chunk after next: one dword per thread, stored
-        // after this chunk's walk; padding positions get the padding record.
-        // (Positions nncs .. nncs + BK - 1 all lie in this tile's visits: that
-        // chunk exists only when this one and the next are full.)
+        // records (RD = 4 RW dwords each, threads 0..RD BK-1) and Gaussians
+        // (threads RD BK..RD BK+BK-1, or for surfels, whose records take all
+        // 512 threads, a second load of threads 0..BK-1) of the chunk after
+        // next: one dword per load, stored after this chunk's walk; padding
+        // positions get the padding record.  (Positions nncs .. nncs + BK - 1
+        // all lie in this tile's visits: that chunk exists only when this one
+        // and the next are full.)
+        constexpr int RD = 4 * RW;
         const int ncs = cs - BK > 0 ? cs - BK : 0;
         const int nncs = ncs - BK > 0 ? ncs - BK : 0;
         const int nncnt = ncs - nncs;
-        const bool pre_on = ncs > 0 && threadIdx.x < 13 * BK;
-        const bool pre_g = threadIdx.x >= 12 * BK;
-        const int pre_k = pre_g ? (int)threadIdx.x - 12 * BK : (int)threadIdx.x / 12;
-        uint32_t pre = 0u;
+        const bool pre_on = ncs > 0 && threadIdx.x < (SURF ? RD * BK : (RD + 1) * BK);
+        const bool pre_g = !SURF && threadIdx.x >= RD * BK;
+        const int pre_k = pre_g ? (int)threadIdx.x - RD * BK : (int)threadIdx.x / RD;
+        uint32_t pre = 0u, pre_gid = 0u;
         if (pre_on) {
             const uint32_t* src = pre_g ? a.vgid + ((int64_t)voff + nncs)
-                                        : reinterpret_cast<const uint32_t*>(a.vrec) + ((int64_t)voff + nncs) * 12;
+                                        : reinterpret_cast<const uint32_t*>(a.vrec) + ((int64_t)voff + nncs) * RD;
             pre = src[pre_g ? pre_k : (int)threadIdx.x];
+            if (SURF && threadIdx.x < BK) pre_gid = a.vgid[(int64_t)voff + nncs + threadIdx.x];
         }
         // the next chunk's features, stored after this chunk's walk
         uint4 fnext[NI];
@@ -268,12 +272,16 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 #pragma unroll
                 for (int r = 3; r >= 0; --r) {
                     const int k = 16 * kb + 4 * q + r;
-                    // (slot of k = 16 kb + 4 q + r: 52 kb + 13 q + 3 r)
-                    const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
-                    const Rec rc = {rp[0], rp[1], rp[2]};
-                    const AlphaEval ae = eval_alpha(rc, x, y);
-                    on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && ae.alpha >= ALPHA_MIN;
-                    al[r] = ae.alpha;
+                    // (slot of k = 16 kb + 4 q + r: (16 RW + 4) kb + (4 RW + 1) q + RW r)
+                    const float4* rp = srec + (4 * RW + 1) * q + (16 * RW + 4) * kb + RW * r;
+                    RecT rc;
+                    rc.r0 = rp[0];
+                    rc.r1 = rp[1];
+                    rc.r2 = rp[2];
+                    if constexpr (SURF) rc.r3 = rp[3];
+                    const float alpha = prim_alpha<SURF>(rc, x, y);
+                    on[r] = k < cnt && (uint32_t)(cs + k) < nit[h] && alpha >= ALPHA_MIN;
+                    al[r] = alpha;
                     gg[r] = rc.r2.y * dCp[h][0] + rc.r2.z * dCp[h][1] + rc.r2.w * dCp[h][2] + gk[kb][r];
                     // the earlier channel slices' part of f_k . dF (positions of the chunk only)
                     if (SL && a.g_in && k < cnt) gg[r] += a.g_in[((int64_t)voff + cs + k) * TILE_PIX + n];
@@ -317,13 +325,19 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         // before this chunk's partial stores are issued (a wait for the
         // prefetch placed after them would also wait for the stores)
         if (pre_on) {
-            const int j = (int)threadIdx.x % 12;
-            const uint32_t pad = pre_g ? 0xFFFFFFFFu : (j == 4 ? 0x3f800000u : ((j == 6 || j == 7) ? 0xbf800000u : 0u));
+            // padding dwords: the padding record (opacity 0; a Gaussian's unit
+            // eigenframe, a surfel's D = 1) and no Gaussian
+            const int j = (int)threadIdx.x % RD;
+            const uint32_t pad = pre_g ? 0xFFFFFFFFu
+                                 : SURF ? (j == 12 ? 0x3f800000u : 0u)
+                                        : (j == 4 ? 0x3f800000u : ((j == 6 || j == 7) ? 0xbf800000u : 0u));
             const uint32_t val = pre_k < nncnt ? pre : pad;
             if (pre_g)
                 sgb[nn3][pre_k] = val;
             else
-                reinterpret_cast<uint32_t*>(srecb[nn3])[4 * rec_slot<RG>(pre_k) + j] = val;
+                reinterpret_cast<uint32_t*>(srecb[nn3])[4 * prec_slot<SURF, RG>(pre_k) + j] = val;
+            if (SURF && threadIdx.x < BK)
+                sgb[nn3][threadIdx.x] = (int)threadIdx.x < nncnt ? pre_gid : 0xFFFFFFFFu;
         }
         if (fnext_on) store_feats(fnext, sfeat2 + (f2 ^ 1) * BK * DP);
         __syncthreads();
@@ -338,7 +352,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
         //      sum dp (q1 a e_y + q2 b e_x) = B Sx + C dy S0,
         //    A = q1 e_x^2 + q2 e_y^2, B = (q1 - q2) e_x e_y, C = q1 e_y^2 + q2 e_x^2,
         //    S0 = sum dp, Sx = sum dp dx, Sxx = sum dp dx^2.
-        {
+        if constexpr (!SURF) {
             const int k = lane & 31, pg = 2 * w + (lane >> 5);
             const Rec rc = lds_rec<RG>(srec, k);
             const float ex = rc.r1.x, ey = rc.r1.y, q1 = rc.r1.z, q2 = rc.r1.w;
@@ -380,6 +394,63 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
                 qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
                 if (lane < 32) sred[(w * 10 + m) * BK + k] = qv[m];
             }
+        } else {
+            // Surfel: dL/dk = dp (-u/k2, -v/k2, (u^2 + v^2)/k2) = (l0, l1, l2) per
+            // pixel (the intersection recomputed from the record, as in the
+            // walk); the nine record terms are linear in l with coefficients
+            // from the record and (dx, dy), so along a row (dy fixed) they need
+            // the sums of l and of l dx:
+            //   dx_c: -b1 L0 + b0 L1 + e2 L2,  dy_c: a1 L0 - a0 L1 + e1 L2,
+            //   a0: dy L1, a1: -dy L0, b0: -L1x, b1: L0x, D: L2, e1: -dy L2, e2: -L2x.
+            const int k = lane & 31, pg = 2 * w + (lane >> 5);
+            const SRec rc = lds_prec<true, RG>(srec, k);
+            const float dy = (((float)(ty * TILE + pg) + 0.5f) - rc.r0.y) - rc.r0.w;
+            float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, L0x = 0.0f, L1x = 0.0f, L2x = 0.0f;
+            float s0 = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, ws = 0.0f;
+#pragma unroll 2
+            for (int m = 0; m < 16; ++m) {
+                const int n = pg * 16 + m;
+                const float dp = sdp[n * SK + k], wv = sw[n * SK + k];
+                const float dx = (((float)(tx * TILE + m) + 0.5f) - rc.r0.x) - rc.r0.z;
+                const SurfPlane sp = surfel_plane(rc, dx, dy);
+                const float pk = dp * sp.ik2;
+                const float l0 = -(pk * sp.u), l1 = -(pk * sp.v);
+                const float l2 = pk * __builtin_fmaf(sp.u, sp.u, sp.v * sp.v);
+                L0 += l0;
+                L1 += l1;
+                L2 += l2;
+                L0x = __builtin_fmaf(l0, dx, L0x);
+                L1x = __builtin_fmaf(l1, dx, L1x);
+                L2x = __builtin_fmaf(l2, dx, L2x);
+                s0 += dp;
+                c0 = __builtin_fmaf(wv, sdc[3 * n], c0);
+                c1 = __builtin_fmaf(wv, sdc[3 * n + 1], c1);
+                c2 = __builtin_fmaf(wv, sdc[3 * n + 2], c2);
+                ws += wv;
+            }
+            const float a0 = rc.r1.x, a1 = rc.r1.y, b0 = rc.r1.z, b1 = rc.r1.w, e1 = rc.r3.y, e2 = rc.r3.z;
+            float qv[14];
+            qv[0] = __builtin_fmaf(-b1, L0, __builtin_fmaf(b0, L1, e2 * L2));
+            qv[1] = __builtin_fmaf(a1, L0, __builtin_fmaf(-a0, L1, e1 * L2));
+            qv[2] = dy * L1;
+            qv[3] = -dy * L0;
+            qv[4] = -L1x;
+            qv[5] = L0x;
+            qv[6] = L2;
+            qv[7] = -dy * L2;
+            qv[8] = -L2x;
+            qv[9] = s0;
+            qv[10] = c0;
+            qv[11] = c1;
+            qv[12] = c2;
+            qv[13] = ws;
+#pragma unroll
+            for (int m = 0; m < 14; ++m) {
+                const auto hv = __builtin_amdgcn_permlane32_swap(__float_as_uint(qv[m]), __float_as_uint(qv[m]),
+                                                                 false, false);
+                qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
+                if (lane < 32) sred[(w * 14 + m) * BK + k] = qv[m];
+            }
         }
         // w of the chunk, recorded for the fusion kernel of the same call as
         // W^T [position][pixel]: consecutive lanes store consecutive pixels
@@ -397,15 +468,15 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
             }
         }
         __syncthreads();
-        if (threadIdx.x < 12 * BK) {
-            // terms 10 and 11 of a partial are padding: written as zero
+        if (threadIdx.x < GP * BK) {
+            // terms NQ..GP-1 of a partial are padding: written as zero
             const int k = threadIdx.x % BK, m = threadIdx.x / BK;
             float sum = 0.0f;
-            if (m < 10) {
+            if (m < NQ) {
 #pragma unroll
-                for (int ww = 0; ww < 8; ++ww) sum += sred[(ww * 10 + m) * BK + k];
+                for (int ww = 0; ww < 8; ++ww) sum += sred[(ww * NQ + m) * BK + k];
             }
-            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + m] = sum;
+            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * GP + m] = sum;
         }
         // No barrier here: the next chunk's LDS writes before its first
         // barrier (w and dL/dpower, the chunk after next's records and
@@ -517,8 +588,10 @@ __global__ __launch_bounds__(512) void k_gk_bf16(BwdArgs a, ViewTable vt) {
 // registers.  Writes the fusion partial row of every visited instance and,
 // with WS, its weight sum (the tenth geometry partial; without WS the gradient
 // kernel of the same call has written it).
-template <int D, bool WS>
+template <int D, bool WS, bool SURF>
 __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
+    using RecT = typename PrimRec<SURF>::T;
+    constexpr int RW = PrimRec<SURF>::RW;
     constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
     constexpr int NDB = D / 16;
     // W^T and the weight sums are double-buffered by chunk parity, so that one
@@ -528,7 +601,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     __bf16* swh2 = reinterpret_cast<__bf16*>(smem);                          // [2][BK][PP] W^T hi
     __bf16* swl2 = swh2 + 2 * BK * PP;                                       // [2][BK][PP] W^T lo
     __shared__ float swsum2[2][16][BK];   // per wave (pixel row): sum over its pixels of w, per position
-    __shared__ float4 srecb[2][RSLOTS];   // chunk records, double-buffered (the next chunk's fetched ahead)
+    __shared__ float4 srecb[2][rslots<SURF>()];   // chunk records, double-buffered (the next chunk's fetched ahead)
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
     const int t = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
@@ -583,13 +656,14 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 
     if (threadIdx.x < BK) {
         const int cs0 = (int)nt - BK > 0 ? (int)nt - BK : 0;
-        lds_put_rec<RG>(srecb[0], threadIdx.x, fetch_record(a, voff, cs0, (int)nt - cs0, threadIdx.x));
+        lds_put_prec<SURF, RG>(srecb[0], threadIdx.x, fetch_record<SURF>(a, voff, cs0, (int)nt - cs0, threadIdx.x));
     }
     // the tile's staged records as a buffer (raw, dword data format): reads
     // past its nt visits return zero instead of touching other memory
+    constexpr uint32_t RB = 16u * RW;   // bytes per record
     const __amdgpu_buffer_rsrc_t vrec_rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float4*>(a.vrec + 3 * (int64_t)voff), (short)0,
-        (int)(nt < 0x7fffffffu / 48u ? nt * 48u : 0x7fffffffu), 0x00020000);
+        const_cast<float4*>(a.vrec + RW * (int64_t)voff), (short)0,
+        (int)(nt < 0x7fffffffu / RB ? nt * RB : 0x7fffffffu), 0x00020000);
     // the pixel's state is complete before the loop (its loads are not
     // carried into the loop's waits)
     asm volatile("" ::"v"(nit), "v"(T));
@@ -607,14 +681,16 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         // (positions ncs .. ncs + BK - 1 all lie in this tile's visits when
         // there is a next chunk, as the current one is then full; padding is
         // selected when the record is stored)
-        Rec nxt;
+        RecT nxt;
         if (threadIdx.x < BK && cs > 0) {
             // buffer loads: a uniform chunk offset and a fixed lane offset, so the
             // loop needs no address registers that could alias the pending loads
-            const int lo = (int)threadIdx.x * 48, so = ncs * 48;
+            const int lo = (int)threadIdx.x * (int)RB, so = ncs * (int)RB;
             nxt.r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo, so, 0));
             nxt.r1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo + 16, so, 0));
             nxt.r2 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo + 32, so, 0));
+            if constexpr (SURF)
+                nxt.r3 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrec_rs, lo + 48, so, 0));
         }
         const int n = w * TILE + xi;
 #pragma unroll
@@ -625,10 +701,15 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
-                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;   // slot of k
-                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
-                on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
-                al[r] = ae.alpha;
+                const float4* rp = srec + (4 * RW + 1) * q + (16 * RW + 4) * kb + RW * r;   // slot of k
+                RecT rc;
+                rc.r0 = rp[0];
+                rc.r1 = rp[1];
+                rc.r2 = rp[2];
+                if constexpr (SURF) rc.r3 = rp[3];
+                const float alpha = prim_alpha<SURF>(rc, x, y);
+                on[r] = k < cnt && (uint32_t)(cs + k) < nit && alpha >= ALPHA_MIN;
+                al[r] = alpha;
                 P = on[r] ? P * (1.0f - al[r]) : P;
             }
             const Rows4 Pr = rows4(P);
@@ -658,12 +739,8 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
         // the next chunk's records go to the other buffer before this chunk's
         // stores are issued (a wait placed after them would also wait for those)
         if (threadIdx.x < BK && cs > 0) {
-            if ((int)threadIdx.x >= cs - ncs) {
-                nxt.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-                nxt.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-                nxt.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            lds_put_rec<RG>(srecb[b ^ 1], threadIdx.x, nxt);
+            if ((int)threadIdx.x >= cs - ncs) nxt = pad_rec<SURF>();
+            lds_put_prec<SURF, RG>(srecb[b ^ 1], threadIdx.x, nxt);
         }
         __syncthreads();
         // weight sums per instance: the 16 rows in order
@@ -672,7 +749,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
             float ws = 0.0f;
 #pragma unroll
             for (int ww = 0; ww < 16; ++ww) ws += swsum[ww][k];
-            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * 12 + 9] = ws;
+            if (k < cnt) a.part_geom[((int64_t)voff + cs + k) * PrimRec<SURF>::GP + PrimRec<SURF>::WSLOT] = ws;
         }
         // out[k][d] = sum_px W^T[k][px] target[px][d], W = hi + lo
         if (w < NDB) {
@@ -828,7 +905,7 @@ __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt)
     }
 }
 
-template <int D>
+template <int D, bool SURF>
 static void launch_fuse_bf16(const BwdArgs& a0, const ViewTable& vt, int n_tiles, int ns, bool grads, bool fuse,
                              hipStream_t s) {
     if (!fuse) return;
@@ -838,19 +915,19 @@ static void launch_fuse_bf16(const BwdArgs& a0, const ViewTable& vt, int n_tiles
     if (grads && a0.wrec)
         hipLaunchKernelGGL(k_fuse_rec_bf16<D>, grid, dim3(1024), lds, s, a0, vt);
     else if (grads)
-        hipLaunchKernelGGL((k_fuse_bf16<D, false>), grid, dim3(1024), lds, s, a0, vt);
+        hipLaunchKernelGGL((k_fuse_bf16<D, false, SURF>), grid, dim3(1024), lds, s, a0, vt);
     else
-        hipLaunchKernelGGL((k_fuse_bf16<D, true>), grid, dim3(1024), lds, s, a0, vt);
+        hipLaunchKernelGGL((k_fuse_bf16<D, true, SURF>), grid, dim3(1024), lds, s, a0, vt);
 }
 
 // D: the channel slice width (the feature width itself up to 256; above it,
 // 256 when it divides the width, else 128)
-template <int D>
+template <int D, bool SURF>
 static void launch_bf16_d(const BwdArgs& a0, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     const int ns = a0.d / D;   // channel slices
     if (grads) {
         const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (D + 8) +
-                           sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * 10 * BK);
+                           sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * PrimRec<SURF>::NQ * BK);
         BwdArgs a = a0;
         a.d0 = 0;
         a.g_in = nullptr;
@@ -870,12 +947,12 @@ static void launch_bf16_d(const BwdArgs& a0, const ViewTable& vt, int n_tiles, b
                     a.g_in = a0.g_out;
                 }
                 a.d0 = (ns - 1) * D;
-                hipLaunchKernelGGL((k_render_bwd_bf16<D, true>), dim3(n_tiles), dim3(512), lds, s, a, vt);
+                hipLaunchKernelGGL((k_render_bwd_bf16<D, true, SURF>), dim3(n_tiles), dim3(512), lds, s, a, vt);
             }
         }
-        if (!sliced) hipLaunchKernelGGL((k_render_bwd_bf16<D, false>), dim3(n_tiles), dim3(512), lds, s, a, vt);
+        if (!sliced) hipLaunchKernelGGL((k_render_bwd_bf16<D, false, SURF>), dim3(n_tiles), dim3(512), lds, s, a, vt);
     }
-    launch_fuse_bf16<D>(a0, vt, n_tiles, ns, grads, fuse, s);
+    launch_fuse_bf16<D, SURF>(a0, vt, n_tiles, ns, grads, fuse, s);
 }
 
 bool render_bwd_bf16_supported(int d) {
@@ -887,20 +964,28 @@ bool render_bwd_bf16_sliced(int d) { return d > 256; }
 // grads: the gradient kernel (needs dC); fuse: the fusion kernel (needs the
 // target).  Above 256 channels, a.g_out is the [visits][256] carry of f . dF
 // between channel slices (needed when dF is given).
-void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+template <bool SURF>
+static void launch_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     switch (a.d) {
-        case 32: launch_bf16_d<32>(a, vt, n_tiles, grads, fuse, s); break;
-        case 64: launch_bf16_d<64>(a, vt, n_tiles, grads, fuse, s); break;
-        case 96: launch_bf16_d<96>(a, vt, n_tiles, grads, fuse, s); break;
-        case 128: launch_bf16_d<128>(a, vt, n_tiles, grads, fuse, s); break;
-        case 256: launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s); break;
+        case 32: launch_bf16_d<32, SURF>(a, vt, n_tiles, grads, fuse, s); break;
+        case 64: launch_bf16_d<64, SURF>(a, vt, n_tiles, grads, fuse, s); break;
+        case 96: launch_bf16_d<96, SURF>(a, vt, n_tiles, grads, fuse, s); break;
+        case 128: launch_bf16_d<128, SURF>(a, vt, n_tiles, grads, fuse, s); break;
+        case 256: launch_bf16_d<256, SURF>(a, vt, n_tiles, grads, fuse, s); break;
         default:
             if (a.d % 256 == 0)
-                launch_bf16_d<256>(a, vt, n_tiles, grads, fuse, s);
+                launch_bf16_d<256, SURF>(a, vt, n_tiles, grads, fuse, s);
             else
-                launch_bf16_d<128>(a, vt, n_tiles, grads, fuse, s);
+                launch_bf16_d<128, SURF>(a, vt, n_tiles, grads, fuse, s);
             break;
     }
+}
+
+void launch_render_bwd_bf16(const BwdArgs& a, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
+    if (a.prim == FH_PRIM_SURFEL)
+        launch_bf16<true>(a, vt, n_tiles, grads, fuse, s);
+    else
+        launch_bf16<false>(a, vt, n_tiles, grads, fuse, s);
 }
 
 }  // namespace fh

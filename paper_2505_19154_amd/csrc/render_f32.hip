@@ -31,65 +31,6 @@ __device__ __forceinline__ float load_feat(const void* f, int bf16, int64_t idx)
     return bf16 ? bf16_to_f32(static_cast<const uint16_t*>(f)[idx]) : static_cast<const float*>(f)[idx];
 }
 
-// Surfel record: (x_c hi, y_c hi, x_c lo, y_c lo), (a0, a1, b0, b1),
-// (opacity, r, g, b), (D, e1, e2, 0).
-struct SRec {
-    float4 r0, r1, r2, r3;
-};
-template <bool SURF>
-struct PrimRec {
-    using T = Rec;
-    static constexpr int RW = 3;
-};
-template <>
-struct PrimRec<true> {
-    using T = SRec;
-    static constexpr int RW = 4;
-};
-template <bool SURF>
-__device__ __forceinline__ typename PrimRec<SURF>::T load_rec(const float4* base, int64_t j) {
-    typename PrimRec<SURF>::T r;
-    r.r0 = base[PrimRec<SURF>::RW * j];
-    r.r1 = base[PrimRec<SURF>::RW * j + 1];
-    r.r2 = base[PrimRec<SURF>::RW * j + 2];
-    if constexpr (SURF) r.r3 = base[PrimRec<SURF>::RW * j + 3];
-    return r;
-}
-
-// A surfel at pixel centre (x, y): pixel offsets from the projected centre,
-// the plane point (u, v) = (k0, k1) / k2 its ray meets, G = exp(-(u^2 + v^2)/2)
-// (0 for a ray parallel to the plane), alpha = min(0.99, o G).
-struct SurfEval {
-    float dx, dy, u, v, ik2, raw, alpha;
-};
-__device__ __forceinline__ SurfEval eval_surfel(const SRec& r, float x, float y) {
-#pragma clang fp contract(off)
-    SurfEval e;
-    e.dx = (x - r.r0.x) - r.r0.z;
-    e.dy = (y - r.r0.y) - r.r0.w;
-    const float a0 = r.r1.x, a1 = r.r1.y, b0 = r.r1.z, b1 = r.r1.w;
-    const float k0 = __builtin_fmaf(e.dx, b1, -(e.dy * a1));
-    const float k1 = __builtin_fmaf(e.dy, a0, -(e.dx * b0));
-    const float k2 = __builtin_fmaf(-e.dx, r.r3.z, __builtin_fmaf(-e.dy, r.r3.y, r.r3.x));
-    const bool hit = k2 != 0.0f;
-    e.ik2 = hit ? 1.0f / k2 : 0.0f;
-    e.u = k0 * e.ik2;
-    e.v = k1 * e.ik2;
-    // exp(-r2 / 2) = exp2(-(log2 e / 2) r2)
-    const float G = hit ? __builtin_amdgcn_exp2f(-0.72134752044448170f * (e.u * e.u + e.v * e.v)) : 0.0f;
-    e.raw = r.r2.x * G;
-    e.alpha = fminf(ALPHA_MAX, e.raw);
-    return e;
-}
-
-template <bool SURF>
-__device__ __forceinline__ float prim_alpha(const typename PrimRec<SURF>::T& r, float x, float y) {
-    if constexpr (SURF)
-        return eval_surfel(r, x, y).alpha;
-    else
-        return eval_alpha(r, x, y).alpha;
-}
-
 template <int DS, bool SURF>
 __global__ __launch_bounds__(256) void k_render_fwd_f32(RenderArgs a, ViewTable vt) {
     using RecT = typename PrimRec<SURF>::T;

@@ -155,7 +155,7 @@ class Rasterizer:
         self.ndfd = bool(ndfd)         # workspace storage for the NDFD gradient
         if primitive not in ("gaussian", "surfel"):
             raise L.FhError(f"primitive must be 'gaussian' or 'surfel', not {primitive!r}")
-        # surfels (Section 3.1's planar primitives): FP32 form only
+        # surfels (Section 3.1's planar primitives): no NDFD branch
         self.primitive = L.FH_PRIM_SURFEL if primitive == "surfel" else L.FH_PRIM_GAUSSIAN
         self.device = torch.device(device)
         self.plan = None

@@ -168,9 +168,10 @@ def test_plan_set_primitive_on_host():
     assert lib.fh_plan_set_primitive(ctypes.byref(plan), 2) == -1
     assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_GAUSSIAN) == 0
     assert plan.ws_bytes == ws_gauss and plan.tuning.fwd_slice == 256
-    # the BF16-MFMA form has no surfel kernels
+    # the BF16-MFMA form: surfels take the MFMA forward's shapes
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 5000, 1000) == 0
-    assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_SURFEL) == -2
+    assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_SURFEL) == 0
+    assert (plan.tuning.fwd_slice, plan.tuning.fwd_rows) == (256, 8)
     # nor a plan that holds the NDFD storage
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 0, cams, 1, 5000, 1000) == 0
     assert lib.fh_plan_set_ndfd(ctypes.byref(plan), 1) == 0

@@ -85,11 +85,15 @@ def test_capacity_overflow_is_reported_not_faulted():
                          mask=ok[:, None].repeat(3, 1))[0] <= 1.0
 
 
-@pytest.mark.parametrize("form,d", [("f32", 32), ("bf16", 32), ("bf16", 512)])
-def test_fusion_accumulates_across_calls_and_finalises(form, d):
-    # (d = 512 in the BF16 form: the fusion kernel in two 256-channel slices)
+@pytest.mark.parametrize("form,d,prim", [("f32", 32, "gaussian"), ("bf16", 32, "gaussian"), ("bf16", 512, "gaussian"),
+                                         ("f32", 32, "surfel"), ("bf16", 64, "surfel")])
+def test_fusion_accumulates_across_calls_and_finalises(form, d, prim):
+    # (d = 512 in the BF16 form: the fusion kernel in two 256-channel slices;
+    # surfels: the fusion kernel's own walk with surfel records)
     from paper_2505_19154_amd.raster import FusionAcc, fuse_finalize
     g = scenegen.make_gaussians(800, 1.0, 1, d, seed=6, feat_dtype="bf16")
+    if prim == "surfel":
+        g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
     cams = [scenegen.look_at_camera(p, 48, 40) for p in ((0, -4, 0), (3, -2.5, 1.2))]
     # exactly representable in BF16 (the BF16 form feeds the target to the MFMA in BF16)
     const = ((np.arange(d) % 32) * 0.125 - 2.0).astype(np.float32)
@@ -97,7 +101,7 @@ def test_fusion_accumulates_across_calls_and_finalises(form, d):
     dg = U.device_gaussians(g)
     for cam in cams:     # one call per view into the same accumulators
         from paper_2505_19154_amd.raster import Rasterizer
-        r = Rasterizer([cam], dg.n, dg.sh_degree, dg.d, feat_dtype="bf16", form=form)
+        r = Rasterizer([cam], dg.n, dg.sh_degree, dg.d, feat_dtype="bf16", form=form, primitive=prim)
         img = r.forward(dg)
         tgt = torch.from_numpy(np.tile(const, (cam.npix, 1))).cuda()
         if form == "bf16":
@@ -115,7 +119,7 @@ def test_fusion_accumulates_across_calls_and_finalises(form, d):
     assert np.array_equal(f[~hit], g["feat"][~hit])
     # the two calls equal one two-view call (oracle sums)
     vts = [dict(scenegen.make_view_tensors(i, c.npix, d), target=np.tile(const, (c.npix, 1))) for i, c in enumerate(cams)]
-    ora = pipeline.run(g, cams, vts, fusion=True)
+    ora = pipeline.run(g, cams, vts, fusion=True, bin_rule="surfel" if prim == "surfel" else "box")
     keep = U.checkable(ora["gflags"])
     assert U.elementwise(w, ora["wsum"], ora["wsum"], rtol=U.RTOL_FORM[form], mask=keep, amb=ora["wsum_amb"])[0] <= 1.0
 

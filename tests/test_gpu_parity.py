@@ -39,10 +39,16 @@ SCENES = {
     # splats of 1-2 tiles: some 2048-instance duplication ranges span more
     # than 1024 ranks (up to 1260) and take the per-instance rank search
     "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
-    # surfels (Section 3.1's planar primitive; FP32 form): ray-plane
-    # intersection, disc-image binning; scales x3 so that most span pixels
+    # surfels (Section 3.1's planar primitive): ray-plane intersection,
+    # disc-image binning; scales x3 so that most span pixels.  FP32 form (VALU
+    # kernels), then the BF16-MFMA form: 16-row forward at d = 64, the 8-row
+    # 256-channel forward and the widest resident dF tile at d = 256 over three
+    # views, two 256-channel slices at d = 512
     "surfel_sh2": (2000, 1.5, 2, 16, "f32", "front120x90", "f32", "surfel"),
     "surfel_multiview_bf16feat": (1500, 1.2, 1, 32, "bf16", "three", "f32", "surfel"),
+    "surfel_mfma_d64": (2000, 1.5, 2, 64, "bf16", "front120x90", "bf16", "surfel"),
+    "surfel_mfma_d256_multiview": (1200, 1.2, 1, 256, "bf16", "three", "bf16", "surfel"),
+    "surfel_mfma_d512": (900, 1.5, 1, 512, "bf16", "front64x48", "bf16", "surfel"),
 }
 # BF16-MFMA form: F, the feature part of the adjoint and the fusion sums are
 # contractions over two-term BF16 splits (tests/gpu_util.py: RTOL_FORM).
