@@ -578,28 +578,32 @@ def extras_leg(W, args, dev):
 def surfel_leg(W, args, dev):
     """The surfel primitive (Section 3.1) on the headline workload: the same
     parameters taken as surfels (scales[:, 0:2] the planar scales), the whole
-    step (project, bin_sort, render_fwd, render_bwd with fusion) in the FP32
-    form, the only one with surfel kernels.  The gradient launch's roofline
-    counts the surfel record (64 B) and partial row (64 B) per visited
-    Gaussian in place of the Gaussian's 48 B each."""
+    step (project, bin_sort, render_fwd, render_bwd with fusion), autotuned,
+    in both arithmetic forms.  The gradient launch's roofline counts the
+    surfel record (64 B) and partial row (64 B) per visited Gaussian in place
+    of the Gaussian's 48 B each."""
     import torch
 
     wl = W["wl"]
-    res = run_form(W, "f32", "render_bwd", args, dev, primitive="surfel")
-    n_vis = visible_count(res["r"], wl, len(W["cams"]))
-    feat_b = 2 if wl.feat_dtype == "bf16" else 4
-    ab, per_unit = alg_bytes("render_bwd", wl, res["r"].n_pixels, n_vis, int(res["c"].n_instances), feat_b, feat_b)
-    ab += 32 * n_vis
-    achieved = ab / (res["kms"] * 1e-3) / 1e9
-    out = dict(form="f32", ms_per_step=res["ms"], ms_per_step_median=res["median_ms"],
-               blends=res["blends"], blends_per_s=res["blends"] / (res["ms"] * 1e-3),
-               instances=int(res["c"].n_instances), visited_instances=int(res["c"].n_visited),
-               visible_surfels=n_vis, tuning=res["tuning"],
-               roofline=dict(kernel="render_bwd", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=achieved / HBM_PEAK_GBS, kernel_ms=res["kms"], algorithmic_bytes=ab,
-                             per_unit=per_unit + " (+32 B per visible surfel: larger record and partial row)"))
-    del res
-    torch.cuda.empty_cache()
+    out = {}
+    for form in ("bf16", "f32"):
+        res = run_form(W, form, "render_bwd", args, dev, primitive="surfel")
+        n_vis = visible_count(res["r"], wl, len(W["cams"]))
+        feat_b = 2 if wl.feat_dtype == "bf16" else 4
+        ab, per_unit = alg_bytes("render_bwd", wl, res["r"].n_pixels, n_vis, int(res["c"].n_instances), feat_b,
+                                 feat_b)
+        ab += 32 * n_vis
+        achieved = ab / (res["kms"] * 1e-3) / 1e9
+        out[form] = dict(
+            ms_per_step=res["ms"], ms_per_step_median=res["median_ms"], blends=res["blends"],
+            blends_per_s=res["blends"] / (res["ms"] * 1e-3), instances=int(res["c"].n_instances),
+            visited_instances=int(res["c"].n_visited), visible_surfels=n_vis, tuning=res["tuning"],
+            roofline=dict(kernel="render_bwd", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=achieved / HBM_PEAK_GBS, kernel_ms=res["kms"], algorithmic_bytes=ab,
+                          per_unit=per_unit + " (+32 B per visible surfel: larger record and partial row)"))
+        del res
+        torch.cuda.empty_cache()
+    out["bf16_speedup_over_f32"] = out["f32"]["ms_per_step"] / out["bf16"]["ms_per_step"]
     return out
 
 
