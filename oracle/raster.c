@@ -240,8 +240,11 @@ static double density(const oracle_args *a, int64_t g, double x, double y, doubl
 
 /* geometry entries of g's adjoint row for dL/dpower = dp at a blend (pixel
    offsets dx, dy, plane state su, sv, sk2): values into out (when dp_is_mag is
-   0) or magnitudes for |dL/dpower| <= dp (when 1); 5 entries for a Gaussian,
-   9 for a surfel */
+   0); else, for |dL/dpower| <= dp, the magnitudes of the terms (2: the sum of
+   the absolute values of each entry's parts, what a change of dp can move)
+   or their rounding companions (1: for a surfel the intersection's rounding
+   carried through its quotients; for a Gaussian the same as 2); 5 entries
+   for a Gaussian, 9 for a surfel */
 static void geom_terms(const oracle_args *a, int64_t g, double dx, double dy, double su, double sv, double sk2,
                        double dp, int dp_is_mag, double *out) {
     if (!a->prim) {
@@ -268,7 +271,18 @@ static void geom_terms(const oracle_args *a, int64_t g, double dx, double dy, do
         return;
     }
     const double l0 = -su / sk2, l1 = -sv / sk2, l2 = (su * su + sv * sv) / sk2;
-    if (!dp_is_mag) {
+    if (dp_is_mag == 2) {
+        const double l0a = fabs(l0), l1a = fabs(l1), l2a = fabs(l2);
+        out[0] = dp * (l0a * fabs(b1) + l1a * fabs(b0) + l2a * fabs(e2));
+        out[1] = dp * (l1a * fabs(a0) + l0a * fabs(a1) + l2a * fabs(e1));
+        out[2] = dp * l1a * fabs(dy);
+        out[3] = dp * l0a * fabs(dy);
+        out[4] = dp * l1a * fabs(dx);
+        out[5] = dp * l0a * fabs(dx);
+        out[6] = dp * l2a;
+        out[7] = dp * l2a * fabs(dy);
+        out[8] = dp * l2a * fabs(dx);
+    } else if (!dp_is_mag) {
         out[0] = -dp * (l0 * b1 - l1 * b0 - l2 * e2);
         out[1] = -dp * (l1 * a0 - l0 * a1 - l2 * e1);
         out[2] = dp * l1 * dy;
@@ -544,7 +558,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_mag[gw * g + k], gmag[k]);
                 if (a->g2d_amb && a->den_round > 0.0 && (dalphad > 0.0 || wd > 0.0)) {
                     double am[13];
-                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, a->den_round * dpowd, 1, am);
+                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, a->den_round * dpowd, 2, am);
                     am[ng] = a->den_round * dopd;
                     for (int c = 0; c < 3; ++c) am[ng + 1 + c] = a->den_round * fabs(wd * dC[c]);
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
@@ -565,7 +579,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                     if (r->near_clamp) damb += dalpham;
                     const double um = damb * r->alpha, om = damb * r->G;
                     double am[13];
-                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, um, 1, am);
+                    geom_terms(a, g, r->dx, r->dy, r->su, r->sv, r->sk2, um, 2, am);
                     am[ng] = om;
                     for (int c = 0; c < 3; ++c) am[ng + 1 + c] = (flags & 1) ? q * gmag[ng + 1 + c] : 0.0;
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
@@ -604,7 +618,7 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                 if (a->g2d_amb) {
                     const int64_t gw = gw_of(a), ng = gw - 4;
                     double am[13];
-                    geom_terms(a, g, e->dx, e->dy, e->su, e->sv, e->sk2, um, 1, am);
+                    geom_terms(a, g, e->dx, e->dy, e->su, e->sv, e->sk2, um, 2, am);
                     am[ng] = om;
                     for (int c = 0; c < 3; ++c) am[ng + 1 + c] = w * fabs(dC[c]);
                     for (int64_t k = 0; k < gw; ++k) atomic_add(&a->g2d_amb[gw * g + k], am[k]);
