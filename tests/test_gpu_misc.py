@@ -203,18 +203,20 @@ def test_autograd_function_against_central_differences():
     assert worst <= 1.0 and tight >= 0.75 * total
 
 
-@pytest.mark.parametrize("form", ["f32", "bf16"])
-def test_graph_replay_matches_eager(form):
+@pytest.mark.parametrize("form,prim", [("f32", "gaussian"), ("bf16", "gaussian"), ("f32", "surfel"), ("bf16", "surfel")])
+def test_graph_replay_matches_eager(form, prim):
     """A captured step replayed several times, with eager work and host
     synchronisation between replays, reproduces the eager results bit for bit."""
     from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
     g = scenegen.make_gaussians(3000, 1.5, 3, 32, seed=7, feat_dtype="bf16")
+    if prim == "surfel":
+        g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
     cams = [scenegen.look_at_camera(p, w, h) for p, w, h in (((0, -4, 0), 96, 80), ((3, -2.5, 1.2), 130, 70))]
     vts = U.view_maps(cams, 32, target_dtype="bf16")
     dg = U.device_gaussians(g)
     dC, dF, dT = U.concat(vts, "dC"), U.concat(vts, "dF"), U.concat(vts, "dT")
     target = U.concat(vts, "target_bits")
-    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype="bf16", form=form)
+    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype="bf16", form=form, primitive=prim)
     img = r.forward(dg)
     acc_e = FusionAcc.zeros(dg.n, 32, "cuda")
     grads_e = r.render_bwd(dg, img, dC, dF, dT, target=target, acc=acc_e)
@@ -367,3 +369,40 @@ def test_binding_rejects_misshapen_tensors_before_launch():
         r.render_bwd(dg, img, dC, target=torch.zeros(P, 8, device="cuda"), acc=FusionAcc.zeros(dg.n - 1, 8, "cuda"))
     with pytest.raises(FhError):
         r.fuse_features(dg, img, torch.zeros(P, 8, dtype=torch.float64, device="cuda"), acc)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_autograd_function_with_surfels(form):
+    """RasterizeFn with a surfel rasterizer: autograd gradients of
+    L = sum dC . C + dF . F + dT . T equal the oracle's surfel adjoint (Section
+    3.1) under the parity rule, and C, T the oracle's images."""
+    from paper_2505_19154_amd.autograd import rasterize
+    from paper_2505_19154_amd.raster import Rasterizer
+    d = 64 if form == "bf16" else 16
+    g = scenegen.make_gaussians(700, 1.0, 1, d, seed=23, feat_dtype="bf16")
+    g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
+    cams = scenegen.make_cameras("front64x48")
+    vts = U.view_maps(cams, d, with_dT=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    params = [t(g[k]).requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    feat = U.device_gaussians(g).feat
+    r = Rasterizer(cams, len(g["opacity"]), 1, d, feat_dtype="bf16", form=form, primitive="surfel")
+    C, F, T, _ = rasterize(r, *params, feat, 1)
+    loss = ((C.double() * t(vts[0]["dC"]).double()).sum() + (F.double() * t(vts[0]["dF"]).double()).sum()
+            + (T.double() * t(vts[0]["dT"]).double()).sum())
+    loss.backward()
+    ora = U.run_oracle(g, cams, vts, bin_rule="surfel")
+    v = ora["views"][0]
+    ok = (v["flags"] & 1) == 0
+    assert U.elementwise(C.detach().cpu().numpy(), v["C"], v["Cmag"], mask=ok[:, None].repeat(3, 1),
+                         amb=v["Cden"])[0] <= 1.0
+    assert U.elementwise(T.detach().cpu().numpy(), v["T"], v["T"], mask=ok, amb=v["Tden"])[0] <= 1.0
+    keep = U.checkable(ora["gflags"])
+    rt = U.RTOL_FORM[form]
+    for k, p in zip(("means", "scales", "quats", "opacity", "sh"), params):
+        got = p.grad.cpu().numpy()
+        m = keep.reshape((-1,) + (1,) * (got.ndim - 1)) & np.ones(got.shape, bool)
+        assert U.elementwise(got, ora["grads"][k], ora["grads_mag"][k], rtol=rt, mask=m,
+                             amb=ora["grads_amb"][k])[0] <= 1.0, k
+    # the third scale takes no part in a surfel
+    assert torch.all(params[1].grad[:, 2] == 0)
