@@ -50,7 +50,7 @@ __device__ __forceinline__ uint32_t list_load(__amdgpu_buffer_rsrc_t rs, uint32_
 template <int DS, int ROWS, bool FS, bool SURF>
 // (8-row shapes up to 128 channels keep four waves per SIMD: two workgroups per
 // CU; 4-row shapes are two or four workgroups per CU, each with its own barriers)
-__global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (ROWS == 4 ? 2 : 1)) void k_render_fwd_bf16(
+__global__ __launch_bounds__(64 * ROWS, (ROWS <= 8 && DS <= 128 && !FS) ? 4 : (ROWS == 4 ? (SURF ? 3 : 2) : 1)) void k_render_fwd_bf16(
     RenderArgs a, ViewTable vt) {
     constexpr int NB = DS / 16;
     static_assert(NB % 2 == 0, "channel blocks are processed in pairs");

@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import binspec, pipeline, project, raster
+from oracle import binspec, pipeline, project, raster, surfel
 
 GRAD_KEYS = ("means", "scales", "quats", "opacity", "sh")
 
@@ -87,8 +87,10 @@ def tile_pixels(cam, tx_n: int, tiles: np.ndarray) -> np.ndarray:
     return np.concatenate(pix).astype(np.int64) if pix else np.zeros(0, np.int64)
 
 
-def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: int, log=None) -> dict:
-    """The oracle over the planned tiles of every view.
+def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: int, log=None,
+        surfels: bool = False) -> dict:
+    """The oracle over the planned tiles of every view (surfels: the
+    primitives are surfels, bqs from binspec's surfel rule).
 
     rows(vi, key, pix) -> float rows of map `key` in ("dC", "dF", "dT", "target")
     of view vi at view-local pixels pix, or None for a map not given (no dT:
@@ -125,7 +127,7 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
             pos += loc.size
         glist = np.concatenate(glist) if glist else np.zeros(0, np.int64)
         gsub = {k: (v[need] if isinstance(v, np.ndarray) and v.shape[:1] == (n,) else v) for k, v in g.items()}
-        pr = project.project(gsub, cam)
+        pr = (surfel.project_surfel if surfels else project.project)(gsub, cam)
         pix = tile_pixels(cam, tx_n, vw["tiles"])
         maps = {}
         for key, width in (("dC", 3), ("dF", d), ("dT", 0), ("target", d)):
@@ -140,7 +142,8 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
                                  dF=maps["dF"], dT=maps["dT"], target=maps["target"], tile_sel=vw["tiles"],
                                  want_F=True, want_Fmag=True, want_fusion=maps["target"] is not None)
         vw["fwd"] = dict(pix=pix, C=out["C"][pix], Cmag=out["Cmag"][pix], T=out["T"][pix],
-                         niter=out["niter"][pix], F=out["F"][pix], Fmag=out["Fmag"][pix], flags=out["flags"][pix])
+                         niter=out["niter"][pix], F=out["F"][pix], Fmag=out["Fmag"][pix], flags=out["flags"][pix],
+                         Cden=out["Cden"][pix], Tden=out["Tden"][pix], Fden=out["Fden"][pix])
         li = np.searchsorted(need, cand)
         present = (li < need.size) & (need[np.minimum(li, max(need.size - 1, 0))] == cand) if need.size else \
             np.zeros(cand.size, bool)
@@ -148,9 +151,11 @@ def run(g: dict, cams: list, bqs: list, cand: np.ndarray, views: list, rows, d: 
             sel = li[present]
             sub = {k: (v[sel] if isinstance(v, np.ndarray) and v.shape[:1] == (need.size,) else v)
                    for k, v in pr.items()}
-            ref = project.project_bwd(sub, pipeline._unpack(out["g2d"][sel]))
-            mag = project.project_bwd(sub, pipeline._unpack(out["g2d_mag"][sel]), magnitude=True)
-            amb = project.project_bwd(sub, pipeline._unpack(out["g2d_amb"][sel]), magnitude=True)
+            bwd = surfel.project_surfel_bwd if surfels else project.project_bwd
+            unpack = pipeline._unpack_surfel if surfels else pipeline._unpack
+            ref = bwd(sub, unpack(out["g2d"][sel]))
+            mag = bwd(sub, unpack(out["g2d_mag"][sel]), magnitude=True)
+            amb = bwd(sub, unpack(out["g2d_amb"][sel]), magnitude=True)
             for k in GRAD_KEYS:
                 sums[k][present] += ref[k]
                 mags[k][present] += mag[k]
