@@ -105,7 +105,7 @@ def render(params: dict, g_meta: dict, cam, feat: np.ndarray | None, keep_w: lis
     return col, F, T, niter, order
 
 
-def render_surfel(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
+def render_surfel(params: dict, g_meta: dict, cam, feat: np.ndarray | None, keep_w: list | None = None):
     """The surfel primitive (Section 3.1) by its definition, without tiles:
     every pixel's ray c_w + t d_w (camera centre, direction through the pixel
     centre) meets the plane p + u T_u + v T_v (T_u = s_u t_u, T_v = s_v t_v,
@@ -117,7 +117,8 @@ def render_surfel(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
     depth beyond the near plane, opacity above 1/255, its disc in front of the
     camera) is composited in (depth, index) order with the rasterizer's skip
     and stop rules.  Torch float64, so autograd gives gradients independent of
-    the hand-written adjoint.  Returns C [P,3], F [P,D] or None, T [P], niter [P]."""
+    the hand-written adjoint.  Returns C [P,3], F [P,D] or None, T [P], niter [P]
+    and the depth order; keep_w as for render."""
     bq = binspec.bin_quantities(g_meta, cam, "surfel")
     vis = np.nonzero(bq["visible"])[0]
     order = vis[np.lexsort((vis, bq["depth"][vis]))]
@@ -168,6 +169,8 @@ def render_surfel(params: dict, g_meta: dict, cam, feat: np.ndarray | None):
         done = done | stop
         contrib = ok & ~stop
         w = torch.where(contrib, alpha * T, torch.zeros_like(T))
+        if keep_w is not None:
+            keep_w.append(w)
         col = col + w[:, None] * rgb[gi][None, :]
         if F is not None:
             F = F + w[:, None] * featt[gi][None, :]
@@ -188,15 +191,17 @@ def unit_rows(x: np.ndarray) -> np.ndarray:
     return np.where(n > 0, x / np.where(n > 0, n, 1.0), 0.0)
 
 
-def ndfd_losses(params: dict, g_meta: dict, cam, feat: np.ndarray, gt: np.ndarray, lam: float, k: float):
+def ndfd_losses(params: dict, g_meta: dict, cam, feat: np.ndarray, gt: np.ndarray, lam: float, k: float,
+                surfels: bool = False):
     """The NDFD losses of every pixel by their definitions (Section 3.3,
     Appendix A.1), without the O(N) rearrangement: with unit features and
     sigma_i = 1 / (1 + exp(k (cos(f_i, F_gt) - lambda))),
         L_gt = sum_i w_i sigma_i,
         L_cf = sum_i sum_{j<i} sigma_i w_i w_j (1 - cos(f_i, f_j))   (the double sum).
-    Returns (L_gt [P], L_cf [P]) as differentiable float64 tensors."""
+    Returns (L_gt [P], L_cf [P]) as differentiable float64 tensors.  surfels:
+    the blend weights of the surfel primitive (render_surfel)."""
     ws = []
-    _, _, _, _, order = render(params, g_meta, cam, None, keep_w=ws)
+    _, _, _, _, order = (render_surfel if surfels else render)(params, g_meta, cam, None, keep_w=ws)
     if not ws:
         P = int(cam.width) * int(cam.height)
         z = torch.zeros(P, dtype=torch.float64)

@@ -71,7 +71,7 @@ def run(g: dict, cams: list, view_tensors: list | None = None, fusion: bool = Fa
         rec = dict(C=out["C"], Cmag=out["Cmag"], Cden=out["Cden"], F=out["F"], Fmag=out["Fmag"], Fden=out["Fden"],
                    T=out["T"], Tden=out["Tden"], niter=out["niter"],
                    flags=out["flags"], proj=pr, g2d=out["g2d"], g2d_mag=out["g2d_mag"], g2d_amb=out["g2d_amb"])
-        for key in ("Lgt", "Lcf", "Lcf_mag", "Lgt_mag", "FN", "WN"):
+        for key in ("Lgt", "Lcf", "Lcf_mag", "Lgt_mag", "FN", "WN", "Lgt_den", "Lcf_den"):
             if key in out:
                 rec[key] = out[key]
         if vt is not None:

@@ -71,7 +71,9 @@
  * near-threshold one: den_round times these sensitivities go to out_Cden,
  * out_Fden, out_Tden (forward) and are added into g2d_amb, fsum_amb and
  * wsum_amb (adjoint: the dL/dalpha, power, opacity and colour terms and the
- * fusion sums).  gr reaches 1e5 and more next to a grazing ray and stays near
+ * fusion sums); with the NDFD branch, L_gt and L_cf get theirs
+ * (out_Lgt_den, out_Lcf_den: through w_i, W_{i-1} and x_i) and the NDFD term
+ * h_k of g_k its sensitivity through the other blends' w.  gr reaches 1e5 and more next to a grazing ray and stays near
  * (u^2 + v^2) / 2 for a surfel seen face-on.  A Gaussian's power is a short
  * quadratic form whose rounding stays within a few units of |power| and inside
  * the tolerance: gr = 0 there.
@@ -164,6 +166,8 @@ typedef struct {
     double *out_Cden;                /* [P, 3] or NULL */
     double *out_Fden;                /* [P, d] or NULL */
     double *out_Tden;                /* [P] or NULL */
+    double *out_Lgt_den;             /* [P] or NULL: density-rounding allowance of L_gt (surfels) */
+    double *out_Lcf_den;             /* [P] or NULL: of L_cf */
 } oracle_args;
 
 /* entries of a per-Gaussian adjoint row: (u v A B C | 9 surfel entries), o, r, g, b */
@@ -173,6 +177,7 @@ static int64_t gw_of(const oracle_args *a) { return a->prim ? 13 : 9; }
 typedef struct {
     double *sig, *sigm, *h, *hm, *cterm, *cmag;   /* [maxlen] per contributor */
     double *vec;                           /* [2 d] */
+    double *hd;                            /* [maxlen] density-rounding sensitivity of h (surfels) */
 } ndfd_scratch;
 
 typedef struct {
@@ -339,9 +344,13 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
     double *P = sc->vec, *B = sc->vec + d;
     memset(P, 0, sizeof(double) * d);
     double W = 0.0, Lgt = 0.0, Lgtm = 0.0, Lcf = 0.0, Lcfm = 0.0;
+    /* density rounding (surfels, header): w_i moves by wd_i = w_i (ar_i + tr_i)
+       to first order, W_{i-1} by Wd = the sum of the earlier wd */
+    double Wd = 0.0, Lgtd = 0.0, Lcfd = 0.0;
     for (int64_t i = 0; i < nrec; ++i) {
         const int64_t g = recs[i].g;
         const double w = recs[i].alpha * recs[i].T;
+        const double wd = w * (recs[i].ar + recs[i].tr);
         double phi = 0.0, phim = 0.0, pf = 0.0;
         for (int64_t c = 0; c < d; ++c) {
             phi += fhat(a, g, c) * gt[c];
@@ -362,9 +371,14 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
         Lgtm += w * sgm;
         Lcf += sg * w * (W - pf);
         Lcfm += sgm * w * 2.0 * W;
+        Lgtd += wd * sgm;
+        Lcfd += sgm * 2.0 * (wd * W + w * Wd);
         for (int64_t c = 0; c < d; ++c) P[c] += w * fhat(a, g, c);
         W += w;
+        Wd += wd;
     }
+    if (a->out_Lgt_den) a->out_Lgt_den[pix] = a->den_round * Lgtd;
+    if (a->out_Lcf_den) a->out_Lcf_den[pix] = a->den_round * Lcfd;
     a->out_Lgt[pix] = Lgt;
     a->out_Lcf[pix] = Lcf;
     if (a->out_Lcf_mag) a->out_Lcf_mag[pix] = Lcfm;
@@ -373,18 +387,24 @@ static void ndfd_pixel(const oracle_args *a, int64_t pix, const blend_rec *recs,
     if (a->out_WN) a->out_WN[pix] = W;
     if (!a->ndfd_a && !a->ndfd_b) return;
     const double ca = a->ndfd_a ? a->ndfd_a[pix] : 0.0, cb = a->ndfd_b ? a->ndfd_b[pix] : 0.0;
-    /* sum_{i>k} sigma_i w_i and sum_{i>k} sigma_i w_i fh_i, back to front */
-    double A = 0.0, Am = 0.0;
+    /* sum_{i>k} sigma_i w_i and sum_{i>k} sigma_i w_i fh_i, back to front; hd_k
+       is h_k's density-rounding sensitivity through the other blends' w
+       (W_{k-1} - x_k and A_k - y_k: 2 Wd_{k-1} and 2 sum_{i>k} sigma_i wd_i) */
+    double A = 0.0, Am = 0.0, Ad = 0.0;
     memset(B, 0, sizeof(double) * d);
     for (int64_t k = nrec - 1; k >= 0; --k) {
         const int64_t g = recs[k].g;
         const double w = recs[k].alpha * recs[k].T;
+        const double wd = w * (recs[k].ar + recs[k].tr);
+        Wd -= wd;   /* now the sum of wd over the blends in front of k */
         double bf = 0.0;
         for (int64_t c = 0; c < d; ++c) bf += B[c] * fhat(a, g, c);
         sc->h[k] = ca * sc->sig[k] + cb * (sc->cterm[k] + (A - bf));
         sc->hm[k] = fabs(ca) * sc->sigm[k] + fabs(cb) * (sc->cmag[k] + 2.0 * Am);
+        sc->hd[k] = fabs(cb) * 2.0 * (sc->sigm[k] * Wd + Ad);
         A += sc->sig[k] * w;
         Am += sc->sigm[k] * w;
+        Ad += sc->sigm[k] * wd;
         for (int64_t c = 0; c < d; ++c) B[c] += sc->sig[k] * w * fhat(a, g, c);
     }
 }
@@ -517,21 +537,23 @@ static void do_tile(const oracle_args *a, int64_t tile, blend_rec *recs, amb_rec
                         gk += a->feat[g * d + k] * dF[k];
                         gkm += fabs(a->feat[g * d + k] * dF[k]);
                     }
+                double gkd = 0.0;   /* density-rounding sensitivity of g_k itself (NDFD terms) */
                 if (ndfd_grad) {
                     gk += sc->h[i];
                     gkm += sc->hm[i];
+                    gkd = sc->hd[i];
                 }
                 const double inv1ma = 1.0 / (1.0 - r->alpha);
                 const double dalpha = r->T * gk - (S + Tfin * dT) * inv1ma;
                 const double dalpham = r->T * gkm + (Sm + Tfin * fabs(dT)) * inv1ma;
                 /* density-rounding sensitivity of dL/dalpha: T's, S's and Tfin's,
                    and that of 1 / (1 - alpha) */
-                const double dalphad = r->T * r->tr * gkm + (Sd + Tfin * tau * fabs(dT)) * inv1ma +
+                const double dalphad = r->T * (r->tr * gkm + gkd) + (Sd + Tfin * tau * fabs(dT)) * inv1ma +
                                        (Sm + Tfin * fabs(dT)) * inv1ma * r->alpha * r->ar * inv1ma;
                 const double wd = w * (r->ar + r->tr);
                 S += w * gk;
                 Sm += w * gkm;
-                Sd += wd * gkm;
+                Sd += wd * gkm + w * gkd;
                 double dpow = 0.0, dpowm = 0.0, dop = 0.0, dopm = 0.0, dpowd = 0.0, dopd = 0.0;
                 if (!r->clamped) {
                     dpow = dalpha * r->alpha;
@@ -652,9 +674,10 @@ int oracle_raster(const oracle_args *a) {
     {
         blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(maxlen + 1));
         amb_rec *amb = (amb_rec *)malloc(sizeof(amb_rec) * (size_t)(2 * maxlen + 2));
-        double *nd = (double *)malloc(sizeof(double) * (size_t)(6 * (maxlen + 1) + 2 * (a->d + 1)));
+        double *nd = (double *)malloc(sizeof(double) * (size_t)(7 * (maxlen + 1) + 2 * (a->d + 1)));
         ndfd_scratch sc = {nd, nd + (maxlen + 1), nd + 2 * (maxlen + 1), nd + 3 * (maxlen + 1),
-                           nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1), nd + 6 * (maxlen + 1)};
+                           nd + 4 * (maxlen + 1), nd + 5 * (maxlen + 1), nd + 6 * (maxlen + 1),
+                           nd + 6 * (maxlen + 1) + 2 * (a->d + 1)};
         double gvec[13], gmag[13];
         if (!recs || !amb || !nd) {
 #pragma omp atomic write

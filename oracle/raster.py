@@ -52,6 +52,7 @@ class _Args(ctypes.Structure):
         ("out_WN", _P),
         ("prim", _I), ("srf", _P),
         ("den_round", ctypes.c_double), ("out_Cden", _P), ("out_Fden", _P), ("out_Tden", _P),
+        ("out_Lgt_den", _P), ("out_Lcf_den", _P),
     ]
 
 
@@ -102,7 +103,8 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
 
     ndfd (optional): dict(gt=[P, d] ground-truth feature map, lam, k, and
     a, b = [P] upstream weights of L_gt and L_cf, or None); adds L_gt, L_cf,
-    Lcf_mag, FN [P, d] and WN to the result and the NDFD terms h_k to the
+    their companions Lgt_mag, Lcf_mag and surfel density allowances Lgt_den,
+    Lcf_den, FN [P, d] and WN to the result and the NDFD terms h_k to the
     adjoint's g_k (with dC given; pass zero maps for the NDFD gradient alone).
     """
     lib = _load()
@@ -161,7 +163,8 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         nd["gt"] = k("gt", _f64(ndfd["gt"]))
         nd["a"] = k("na", _f64(ndfd.get("a")))
         nd["b"] = k("nb", _f64(ndfd.get("b")))
-        for key, shape in (("Lgt", P), ("Lcf", P), ("Lcf_mag", P), ("Lgt_mag", P), ("WN", P)):
+        for key, shape in (("Lgt", P), ("Lcf", P), ("Lcf_mag", P), ("Lgt_mag", P), ("WN", P), ("Lgt_den", P),
+                           ("Lcf_den", P)):
             out[key] = np.zeros(shape)
         out["FN"] = np.zeros((P, d))
 
@@ -186,7 +189,7 @@ def render_view(cam, ranges, glist, proj, feat=None, dC=None, dF=None, dT=None, 
         out_WN=_ptr(out.get("WN")),
         prim=1 if surf else 0, srf=_ptr(srf),
         den_round=consts.DEN_ROUND, out_Cden=_ptr(out["Cden"]), out_Fden=_ptr(out["Fden"]),
-        out_Tden=_ptr(out["Tden"]),
+        out_Tden=_ptr(out["Tden"]), out_Lgt_den=_ptr(out.get("Lgt_den")), out_Lcf_den=_ptr(out.get("Lcf_den")),
     )
     rc = lib.oracle_raster(ctypes.byref(args))
     if rc != 0:

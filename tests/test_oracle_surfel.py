@@ -243,11 +243,12 @@ def test_surfel_flipped_decision_stays_within_the_bound(kind, m, seed):
 
 # --- the density-rounding allowance (the surfel branch of oracle/raster.c) ---
 
-def _composite_f32_density(g, cam, vt):
+def _composite_f32_density(g, cam, vt, ndfd=None):
     """The untiled composite with every surfel density evaluated from the
     record rounded to float32 and the intersection in float32 (the rest in
     torch float64, opacity a leaf): C, T and dL/dopacity for the loss
-    dC . C + dF . F + dT . T."""
+    dC . C + dF . F + dT . T, or with ndfd = (lam, k) the NDFD losses by
+    their double-sum definition and dL/dopacity of sum a L_gt + b L_cf."""
     pr = surfel.project_surfel(g, cam)
     bq = binspec.bin_quantities(g, cam, "surfel")
     vis = np.nonzero(bq["visible"])[0]
@@ -264,6 +265,7 @@ def _composite_f32_density(g, cam, vt):
     C = torch.zeros(P, 3, dtype=torch.float64)
     F = torch.zeros(P, feat.shape[1], dtype=torch.float64)
     done = torch.zeros(P, dtype=torch.bool)
+    ws = []
     for gi in order.tolist():
         r = pr["srf"][gi].astype(np.float32)
         dx = (x - pr["srf"][gi][0]).astype(np.float32)
@@ -283,13 +285,25 @@ def _composite_f32_density(g, cam, vt):
         done = done | stop
         c = ok & ~stop
         w = torch.where(c, alpha * T, torch.zeros_like(T))
+        ws.append(w)
         C = C + w[:, None] * rgb[gi][None]
         F = F + w[:, None] * feat[gi][None]
         T = torch.where(c, Tn, T)
-    loss = ((torch.tensor(vt["dC"]) * C).sum() + (torch.tensor(vt["dF"]) * F).sum()
-            + (torch.tensor(vt["dT"]) * T).sum())
+    if ndfd is None:
+        loss = ((torch.tensor(vt["dC"]) * C).sum() + (torch.tensor(vt["dF"]) * F).sum()
+                + (torch.tensor(vt["dT"]) * T).sum())
+        loss.backward()
+        return C.detach().numpy(), T.detach().numpy(), op.grad.numpy()
+    lam, k = ndfd
+    Wm = torch.stack(ws, 0)
+    fh = torch.tensor(brute.unit_rows(np.asarray(g["feat"], np.float64)[order]))
+    gh = torch.tensor(brute.unit_rows(vt["gt"]))
+    sig = 1.0 / (1.0 + torch.exp(k * (fh @ gh.T - lam)))
+    Lgt = (Wm * sig).sum(0)
+    Lcf = (sig * Wm * (torch.tril(1.0 - fh @ fh.T, diagonal=-1) @ Wm)).sum(0)
+    loss = (torch.tensor(vt["ndfd_a"]) * Lgt).sum() + (torch.tensor(vt["ndfd_b"]) * Lcf).sum()
     loss.backward()
-    return C.detach().numpy(), T.detach().numpy(), op.grad.numpy()
+    return Lgt.detach().numpy(), Lcf.detach().numpy(), op.grad.numpy()
 
 
 @pytest.mark.parametrize("n,deg,d,seed", [(1500, 1, 5, 2), (2000, 2, 16, 0)])
@@ -321,3 +335,65 @@ def test_density_allowance_covers_a_float32_density(n, deg, d, seed):
     ref = np.abs(o["grads"]["opacity"])
     hit = keep & (ref > 0)
     assert np.median((o["grads_amb"]["opacity"] + 1e-5 * o["grads_mag"]["opacity"])[hit] / ref[hit]) < 1e-2
+
+
+# --- the NDFD branch with surfels (Section 3.3 along the surfel walk) ---
+
+def test_surfel_ndfd_losses_and_gradient_equal_the_definition():
+    """L_gt and L_cf of the surfel walk (the oracle's forward-indexed O(N)
+    form) equal the double-sum definition over the untiled surfel composite,
+    and their gradient through w equals torch autograd of that definition."""
+    lam, k = 0.5, 20.0
+    for seed in (4, 6):
+        g, cams = _scene(seed, n=90, d=8)
+        cam = cams[0]
+        P = cam.npix
+        rng = np.random.default_rng(700 + seed)
+        F = pipeline.run(g, cams, bin_rule="surfel")["views"][0]["F"]
+        gt = F + 0.3 * rng.normal(size=F.shape) * np.abs(F).mean()
+        vt = dict(dC=np.zeros((P, 3)), dF=np.zeros((P, g["d"])), dT=np.zeros(P), gt=gt,
+                  ndfd_a=rng.normal(size=P), ndfd_b=rng.normal(size=P))
+        o = pipeline.run(g, cams, [vt], ndfd=dict(lam=lam, k=k), bin_rule="surfel")
+        v = o["views"][0]
+        L = brute.leaves(g)
+        Lgt, Lcf = brute.ndfd_losses(L, g, cam, g["feat"], gt, lam, k, surfels=True)
+        assert np.allclose(v["Lgt"], Lgt.detach().numpy(), rtol=1e-12, atol=1e-14)
+        assert np.allclose(v["Lcf"], Lcf.detach().numpy(), rtol=1e-11, atol=1e-13)
+        assert v["Lgt"].max() > 0 and np.abs(v["Lcf"]).max() > 0
+        loss = (torch.tensor(vt["ndfd_a"]) * Lgt).sum() + (torch.tensor(vt["ndfd_b"]) * Lcf).sum()
+        loss.backward()
+        for key in ("means", "scales", "quats", "opacity"):
+            ref = L[key].grad.numpy()
+            got, mag = o["grads"][key], o["grads_mag"][key]
+            assert np.all(np.abs(got - ref) <= 1e-10 * mag + 1e-13), key
+        assert np.abs(o["grads"]["means"]).max() > 0
+        assert np.all(o["grads"]["sh"] == 0)      # colour does not enter NDFD
+
+
+def test_density_allowance_covers_the_ndfd_losses_and_gradient():
+    """With the density evaluated in float32, the NDFD losses and the opacity
+    gradient of sum a L_gt + b L_cf stay within the oracle's density
+    allowance (Lgt_den, Lcf_den, grads_amb) wherever no near-threshold
+    decision is involved."""
+    lam, k = 0.5, 20.0
+    g = scenegen.make_gaussians(1500, 1.5, 1, 5, seed=2)
+    g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
+    cams = scenegen.make_cameras("front120x90")
+    cam = cams[0]
+    P = cam.npix
+    rng = np.random.default_rng(31)
+    F = pipeline.run(g, cams, bin_rule="surfel")["views"][0]["F"]
+    gt = F + 0.3 * rng.normal(size=F.shape) * np.abs(F).mean()
+    vt = dict(dC=np.zeros((P, 3)), dF=np.zeros((P, g["d"])), dT=np.zeros(P), gt=gt,
+              ndfd_a=rng.normal(size=P), ndfd_b=rng.normal(size=P))
+    o = pipeline.run(g, cams, [vt], ndfd=dict(lam=lam, k=k), bin_rule="surfel")
+    v = o["views"][0]
+    Lgt32, Lcf32, gop32 = _composite_f32_density(g, cam, vt, ndfd=(lam, k))
+    px = (v["flags"] & 1) == 0
+    assert np.all((np.abs(Lgt32 - v["Lgt"]) <= 1.05 * v["Lgt_den"] + 1e-13)[px])
+    assert np.all((np.abs(Lcf32 - v["Lcf"]) <= 1.05 * v["Lcf_den"] + 1e-13)[px])
+    keep = o["gflags"] == 0
+    dd = np.abs(gop32 - o["grads"]["opacity"])
+    assert np.all((dd <= 1.05 * o["grads_amb"]["opacity"] + 1e-10 * o["grads_mag"]["opacity"])[keep])
+    # the allowance is needed: the plain relative tolerance fails for the gradient somewhere
+    assert np.any((dd > 1e-5 * o["grads_mag"]["opacity"])[keep])
