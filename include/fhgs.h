@@ -93,7 +93,7 @@ typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
  *                     of the disc u^2 + v^2 <= kappa_i (the opacity-aware
  *                     kappa_i of FH_BIN_OPACITY, whatever bin_rule says),
  *                     and surfels whose disc reaches the camera plane are
- *                     culled.  Both arithmetic forms; no NDFD branch. */
+ *                     culled.  Both arithmetic forms and the NDFD branch. */
 typedef enum { FH_PRIM_GAUSSIAN = 0, FH_PRIM_SURFEL = 1 } fh_primitive;
 
 /* Arithmetic form of the compositing kernels. */
@@ -280,14 +280,13 @@ fh_status fh_plan_init(fh_plan *plan, int64_t n, int32_t sh_degree, int32_t d, f
 
 /* Add (enable = 1) or drop (0) the workspace storage of the NDFD gradient
  * (the ndfd_* fields of fh_upstream in fh_render_bwd): two floats per visited
- * (position, pixel) and the per-half-tile partials, 2 KB + 64 B per unit of
- * visit_capacity.  Recomputes the workspace layout (ws_bytes); set it before
+ * (position, pixel) and the per-half-tile partials, 2 KB + 64 B (surfels:
+ * 2 KB + 128 B) per unit of visit_capacity.  Recomputes the workspace layout (ws_bytes); set it before
  * allocating the workspace.  fh_ndfd_losses needs no storage. */
 fh_status fh_plan_set_ndfd(fh_plan *plan, int32_t enable);
 
 /* Choose the primitive (fh_primitive; Section 3.1's surfels or 3D Gaussians)
- * of a plan from fh_plan_init.  Surfels need a plan without the NDFD storage
- * (FH_E_UNSUPPORTED otherwise); their records take 64 B per
+ * of a plan from fh_plan_init.  Surfel records take 64 B per
  * (view, primitive) and their per-instance partials 64 B per visited
  * instance.  Resets the launch shape to the primitive's default and
  * recomputes the workspace layout; set it before allocating the workspace. */

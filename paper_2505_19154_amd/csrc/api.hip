@@ -294,7 +294,7 @@ static void plan_layout(fh_plan* plan) {
     sz[WS_UPART] = (size_t)fuse_unit_capacity(visit_capacity) * (2 * (size_t)d + 2) * sizeof(float);
     // NDFD gradient storage (fh_plan_set_ndfd): per-part partials and the
     // forward sweep's (sigma, prefix term) of every visited (position, pixel)
-    sz[WS_PART_NDFD] = plan->ndfd ? (size_t)visit_capacity * 2 * 8 * sizeof(float) : 0;
+    sz[WS_PART_NDFD] = plan->ndfd ? (size_t)visit_capacity * 2 * ndfd_part_floats(plan->primitive) * sizeof(float) : 0;
     sz[WS_NDFD_SC] = plan->ndfd ? (size_t)visit_capacity * TILE_PIX * 2 * sizeof(float) : 0;
     sz[WS_TORDER_KA] = sz[WS_TORDER_KB] = sz[WS_TORDER_VA] = sz[WS_TORDER_VB] = (size_t)tiles * u4;
     // the BF16 gradient kernel records w for the fusion kernel of the same call
@@ -362,7 +362,6 @@ fh_status fh_plan_init(fh_plan* plan, int64_t n, int32_t sh_degree, int32_t d, f
 
 fh_status fh_plan_set_ndfd(fh_plan* plan, int32_t enable) {
     if (!plan) return FH_E_INVALID;
-    if (enable && plan->primitive == FH_PRIM_SURFEL) return FH_E_UNSUPPORTED;
     plan->ndfd = enable ? 1 : 0;
     plan_layout(plan);
     return FH_OK;
@@ -371,7 +370,6 @@ fh_status fh_plan_set_ndfd(fh_plan* plan, int32_t enable) {
 fh_status fh_plan_set_primitive(fh_plan* plan, int32_t primitive) {
     if (!plan) return FH_E_INVALID;
     if (primitive != FH_PRIM_GAUSSIAN && primitive != FH_PRIM_SURFEL) return FH_E_INVALID;
-    if (primitive == FH_PRIM_SURFEL && plan->ndfd) return FH_E_UNSUPPORTED;
     plan->primitive = primitive;
     plan->tuning = default_tuning(plan->d, plan->form, plan->feat_dtype, primitive);
     plan_layout(plan);
@@ -630,12 +628,11 @@ static NdfdArgs ndfd_args(const fh_plan* p, const fh_gaussians* g, void* ws, con
     n.Lgt = n.Lcf = nullptr;
     n.part = buf<float>(p, ws, WS_PART_NDFD);
     n.sc = buf<float2>(p, ws, WS_NDFD_SC);
+    n.prim = p->primitive;
     return n;
 }
 
-static bool ndfd_ok(const fh_plan* p) {
-    return p->feat_dtype == FH_BF16 && ndfd_supported(p->d) && p->primitive == FH_PRIM_GAUSSIAN;
-}
+static bool ndfd_ok(const fh_plan* p) { return p->feat_dtype == FH_BF16 && ndfd_supported(p->d); }
 
 fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const fh_upstream* up,
                         const void* fusion_target, fh_dtype target_dtype, const fh_fusion* acc, const fh_grads* out,
@@ -676,7 +673,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
         prof_begin(FH_K_NDFD, s);
         launch_ndfd(n, vt, (int)p->n_tiles, true, s);
         prof_end(FH_K_NDFD, s);
-        launch_ndfd_combine(n.part, buf<float>(p, ws, WS_PART_GEOM), n.counters, p->visit_capacity, s);
+        launch_ndfd_combine(n.part, buf<float>(p, ws, WS_PART_GEOM), n.counters, p->visit_capacity, p->primitive, s);
     }
     ReduceArgs r;
     fill_reduce_args(p, ws, r);

@@ -180,7 +180,7 @@ struct NdfdArgs {
     const uint32_t* tile_niter;
     const uint32_t* tile_voff;
     const Counters* counters;
-    const float4* vrec;         // [visits * 3] staged records, in visit order
+    const float4* vrec;         // [visits * rw] staged records, in visit order
     const uint32_t* vgid;       // [visits] staged Gaussians
     const uint16_t* feat;       // [n, d] BF16 features
     int d;
@@ -192,12 +192,15 @@ struct NdfdArgs {
     float lam, kk;              // sigmoid threshold and slope
     float* Lgt;                 // [P] (nullable)
     float* Lcf;                 // [P] (nullable)
-    float* part;                // [visits][2 halves][8] screen-space partials (gradient)
+    float* part;                // [visits][2 halves][ndfd_part_floats] screen-space partials (gradient)
     float2* sc;                 // [visits][256 pixels] (sigma, prefix term) of the forward sweep (gradient)
+    int prim;                   // fh_primitive (surfel records: 4 float4)
 };
 bool ndfd_supported(int d);
+int ndfd_part_floats(int prim);   // floats per (visit, half) partial: 8 (Gaussians), 16 (surfels)
 void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s);
-void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, hipStream_t s);
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int prim,
+                         hipStream_t s);
 void launch_fuse_finalize(const float* sum, const float* comp, const float* wsum, const float* wcomp, int64_t n, int d,
                           const void* feat_in, void* feat_out, int bf16, hipStream_t s);
 

@@ -43,6 +43,11 @@
 // per-instance screen-space partial (u, v, A, B, C, sum dL/dpower); a second
 // kernel adds both halves into the gradient kernel's partials in a fixed
 // order.
+//
+// SURF: the surfel primitive (Section 3.1): four-float4 records, alpha at the
+// ray-plane intersection, and per half the nine record entries' terms and
+// sum dL/dpower (rows of 16 floats), from the sums of dL/dk and dL/dk dx
+// along each row as in the gradient kernel.
 #include "kernels.hpp"
 
 namespace fh {
@@ -54,9 +59,16 @@ constexpr int NK = 32;                       // positions per chunk
 constexpr int NJP = 40;                      // row stride (bf16) of the transposed features and the Gram operands
 constexpr int NSK = NK + 3;                  // padded per-pixel stride of dL/dpower
 constexpr int NRG = 4;                       // record padding group (lane rows read records 4 apart)
-constexpr int NRSLOTS = 3 * NK + NK / NRG;
-constexpr int NDFD_PART = 8;                 // floats per (visit, part) partial (6 used)
 constexpr int NDFD_PARTS = 2;                // halves per visit in the partial array
+// per primitive: terms of a (visit, part) partial, and floats per partial row
+template <bool SURF>
+struct NdfdPart {
+    static constexpr int NQ = 6, W = 8;      // u, v, A, B, C, sum dL/dpower
+};
+template <>
+struct NdfdPart<true> {
+    static constexpr int NQ = 10, W = 16;    // the nine record entries, sum dL/dpower
+};
 
 __device__ __forceinline__ bf16x8 bf16x8_of(uint2 lo, uint2 hi) {
     return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
@@ -71,8 +83,12 @@ __device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
     }
 }
 
-template <int D, bool GRAD>
+template <int D, bool GRAD, bool SURF>
 __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
+    using RecT = typename PrimRec<SURF>::T;
+    constexpr int RW = PrimRec<SURF>::RW;
+    constexpr int NRSLOTS = RW * NK + NK / NRG;
+    constexpr int NQN = NdfdPart<SURF>::NQ, NDP = NdfdPart<SURF>::W;
     constexpr int ROWS = 8;                   // pixel rows (waves) per workgroup
     constexpr int NT = 64 * ROWS;             // threads
     constexpr int NS = D / 32;                // 32-channel slabs
@@ -85,7 +101,7 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
     float* sG = reinterpret_cast<float*>(sA + 6 * NK * NJP);  // [NK][NK + 1]
     float* sinv = sG + NK * (NK + 1);                          // [NK]
     float* sdp = sinv + NK;                                    // [16 ROWS][NSK] dL/dpower (gradient)
-    float* sred = sdp + TILE * ROWS * NSK;                     // [ROWS][6][NK] row sums (gradient)
+    float* sred = sdp + TILE * ROWS * NSK;                     // [ROWS][NQN][NK] row sums (gradient)
     __shared__ float4 srec[NRSLOTS];
 
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
@@ -143,18 +159,8 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
     auto stage = [&](int cs, int cnt) {
         if ((int)threadIdx.x < NK) {
             const int k = threadIdx.x;
-            Rec r;
-            if (k < cnt) {
-                const int64_t vi = (int64_t)voff + cs + k;
-                r.r0 = a.vrec[3 * vi];
-                r.r1 = a.vrec[3 * vi + 1];
-                r.r2 = a.vrec[3 * vi + 2];
-            } else {
-                r.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-                r.r1 = make_float4(1.f, 0.f, -1.f, -1.f);
-                r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            lds_put_rec<NRG>(srec, k, r);
+            const RecT r = k < cnt ? load_rec<SURF>(a.vrec, (int64_t)voff + cs + k) : pad_rec<SURF>();
+            lds_put_prec<SURF, NRG>(srec, k, r);
         }
         // item = (position k, 8-channel group dg), k fastest: a wave's 2-byte
         // stores of the transposed tile then fill consecutive bank slots
@@ -315,10 +321,15 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = 16 * kb + 4 * q + r;
-                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
-                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
-                on[r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
-                al[r] = ae.alpha;
+                const float4* rp = srec + (4 * RW + 1) * q + (16 * RW + 4) * kb + RW * r;   // slot of k
+                RecT rc;
+                rc.r0 = rp[0];
+                rc.r1 = rp[1];
+                rc.r2 = rp[2];
+                if constexpr (SURF) rc.r3 = rp[3];
+                const float alpha = prim_alpha<SURF>(rc, x, y);
+                on[r] = k < cnt && (uint32_t)(cs + k) < nit && alpha >= ALPHA_MIN;
+                al[r] = alpha;
                 Wr = on[r] ? __builtin_fmaf(al[r], trel, Wr) : Wr;
                 trel = on[r] ? trel * (1.0f - al[r]) : trel;
             }
@@ -418,10 +429,15 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
 #pragma unroll
             for (int r = 3; r >= 0; --r) {
                 const int k = 16 * kb + 4 * q + r;
-                const float4* rp = srec + 13 * q + 52 * kb + 3 * r;
-                const AlphaEval ae = eval_alpha(Rec{rp[0], rp[1], rp[2]}, x, y);
-                on[kb][r] = k < cnt && (uint32_t)(cs + k) < nit && ae.alpha >= ALPHA_MIN;
-                al[kb][r] = ae.alpha;
+                const float4* rp = srec + (4 * RW + 1) * q + (16 * RW + 4) * kb + RW * r;   // slot of k
+                RecT rc;
+                rc.r0 = rp[0];
+                rc.r1 = rp[1];
+                rc.r2 = rp[2];
+                if constexpr (SURF) rc.r3 = rp[3];
+                const float alpha = prim_alpha<SURF>(rc, x, y);
+                on[kb][r] = k < cnt && (uint32_t)(cs + k) < nit && alpha >= ALPHA_MIN;
+                al[kb][r] = alpha;
                 iv[kb][r] = __builtin_amdgcn_rcpf(1.0f - al[kb][r]);
                 const float tn = trel * iv[kb][r];
                 P = on[kb][r] ? P * (1.0f - al[kb][r]) : P;
@@ -518,7 +534,7 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
         // Gaussian-parallel sums over this part's rows: wave w = row w, lane
         // = position k (lanes 32..63 the row's right half), moments of
         // dL/dpower along the row as in the gradient kernel
-        {
+        if constexpr (!SURF) {
             const int k = lane & 31, hp = lane >> 5;
             const Rec rc = lds_rec<NRG>(srec, k);
             const float ex = rc.r1.x, ey = rc.r1.y, q1 = rc.r1.z, q2 = rc.r1.w;
@@ -550,62 +566,124 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
                 qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
                 if (lane < 32) sred[(w * 6 + m) * NK + k] = qv[m];
             }
+        } else {
+            // surfel: per pixel l = dL/dk = dp (-u/k2, -v/k2, (u^2 + v^2)/k2)
+            // from the staged record, summed with l dx along the row (dy fixed)
+            const int k = lane & 31, hp = lane >> 5;
+            const SRec rc = lds_prec<true, NRG>(srec, k);
+            const float dy = (((float)(ty * TILE + ry) + 0.5f) - rc.r0.y) - rc.r0.w;
+            float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, L0x = 0.0f, L1x = 0.0f, L2x = 0.0f, s0 = 0.0f;
+#pragma unroll 2
+            for (int m = 0; m < 8; ++m) {
+                const float dp = sdp[(w * TILE + 8 * hp + m) * NSK + k];
+                const float dx = (((float)(tx * TILE + 8 * hp + m) + 0.5f) - rc.r0.x) - rc.r0.z;
+                const SurfPlane sp = surfel_plane(rc, dx, dy);
+                const float pk = dp * sp.ik2;
+                const float l0 = -(pk * sp.u), l1 = -(pk * sp.v);
+                const float l2 = pk * __builtin_fmaf(sp.u, sp.u, sp.v * sp.v);
+                L0 += l0;
+                L1 += l1;
+                L2 += l2;
+                L0x = __builtin_fmaf(l0, dx, L0x);
+                L1x = __builtin_fmaf(l1, dx, L1x);
+                L2x = __builtin_fmaf(l2, dx, L2x);
+                s0 += dp;
+            }
+            const float a0 = rc.r1.x, a1 = rc.r1.y, b0 = rc.r1.z, b1 = rc.r1.w, e1 = rc.r3.y, e2 = rc.r3.z;
+            float qv[10];
+            qv[0] = __builtin_fmaf(-b1, L0, __builtin_fmaf(b0, L1, e2 * L2));
+            qv[1] = __builtin_fmaf(a1, L0, __builtin_fmaf(-a0, L1, e1 * L2));
+            qv[2] = dy * L1;
+            qv[3] = -dy * L0;
+            qv[4] = -L1x;
+            qv[5] = L0x;
+            qv[6] = L2;
+            qv[7] = -dy * L2;
+            qv[8] = -L2x;
+            qv[9] = s0;
+#pragma unroll
+            for (int m = 0; m < 10; ++m) {
+                const auto hv = __builtin_amdgcn_permlane32_swap(__float_as_uint(qv[m]), __float_as_uint(qv[m]),
+                                                                 false, false);
+                qv[m] = __uint_as_float(hv[0]) + __uint_as_float(hv[1]);
+                if (lane < 32) sred[(w * 10 + m) * NK + k] = qv[m];
+            }
         }
         __syncthreads();
-        if ((int)threadIdx.x < 6 * NK) {
+        if ((int)threadIdx.x < NQN * NK) {
             const int k = threadIdx.x % NK, m = threadIdx.x / NK;
             float sum = 0.0f;
 #pragma unroll
-            for (int ww = 0; ww < ROWS; ++ww) sum += sred[(ww * 6 + m) * NK + k];
-            if (k < cnt) a.part[(((int64_t)voff + cs + k) * NDFD_PARTS + half) * NDFD_PART + m] = sum;
+            for (int ww = 0; ww < ROWS; ++ww) sum += sred[(ww * NQN + m) * NK + k];
+            if (k < cnt) a.part[(((int64_t)voff + cs + k) * NDFD_PARTS + half) * NDP + m] = sum;
         }
     }
 }
 
-// part_geom[v][m] += part[v][0][m] + ... + part[v][nparts - 1][m] for the six
-// screen-space terms of every visited instance (fixed order).
+// part_geom[v][m] += part[v][0][m] + ... + part[v][nparts - 1][m] for the
+// screen-space terms of every visited instance (fixed order): six for a
+// Gaussian (rows of 12), ten for a surfel (rows of 16), the first entries of
+// the gradient kernel's partial row in both.
+template <bool SURF>
 __global__ __launch_bounds__(256) void k_ndfd_combine(const float* __restrict__ part, float* __restrict__ part_geom,
                                                       const Counters* c, int64_t cap, int nparts) {
+    constexpr int NQN = NdfdPart<SURF>::NQ, NDP = NdfdPart<SURF>::W, GP = PrimRec<SURF>::GP;
     if (c->inst_overflow || c->visit_overflow) return;
     const int64_t nv = (int64_t)c->n_visited < cap ? (int64_t)c->n_visited : cap;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nv * 6) return;
-    const int64_t vi = i / 6;
-    const int m = (int)(i % 6);
+    if (i >= nv * NQN) return;
+    const int64_t vi = i / NQN;
+    const int m = (int)(i % NQN);
     float s = 0.0f;
-    for (int h = 0; h < nparts; ++h) s += part[(vi * NDFD_PARTS + h) * NDFD_PART + m];
-    part_geom[vi * 12 + m] += s;
+    for (int h = 0; h < nparts; ++h) s += part[(vi * NDFD_PARTS + h) * NDP + m];
+    part_geom[vi * GP + m] += s;
 }
 
-template <int D>
+template <int D, bool SURF>
 static void launch_ndfd_d(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
     constexpr int ROWS = 8;
     const size_t lds = sizeof(__bf16) * ((size_t)NK * (D + 8) + (size_t)D * NJP + 6 * (size_t)NK * NJP) +
-                       sizeof(float) * ((size_t)NK * (NK + 1) + NK + (size_t)TILE * ROWS * NSK + (size_t)ROWS * 6 * NK);
+                       sizeof(float) * ((size_t)NK * (NK + 1) + NK + (size_t)TILE * ROWS * NSK +
+                                        (size_t)ROWS * NdfdPart<SURF>::NQ * NK);
     if (grad)
-        hipLaunchKernelGGL((k_ndfd<D, true>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
+        hipLaunchKernelGGL((k_ndfd<D, true, SURF>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
     else
-        hipLaunchKernelGGL((k_ndfd<D, false>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
+        hipLaunchKernelGGL((k_ndfd<D, false, SURF>), dim3(n_tiles, TILE / ROWS), dim3(64 * ROWS), lds, s, a, vt);
+}
+
+template <bool SURF>
+static void launch_ndfd_p(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
+    switch (a.d) {
+        case 32: launch_ndfd_d<32, SURF>(a, vt, n_tiles, grad, s); break;
+        case 64: launch_ndfd_d<64, SURF>(a, vt, n_tiles, grad, s); break;
+        case 96: launch_ndfd_d<96, SURF>(a, vt, n_tiles, grad, s); break;
+        case 128: launch_ndfd_d<128, SURF>(a, vt, n_tiles, grad, s); break;
+        default: launch_ndfd_d<256, SURF>(a, vt, n_tiles, grad, s); break;
+    }
 }
 
 bool ndfd_supported(int d) { return d == 32 || d == 64 || d == 96 || d == 128 || d == 256; }
 
 void launch_ndfd(const NdfdArgs& a, const ViewTable& vt, int n_tiles, bool grad, hipStream_t s) {
     if (n_tiles <= 0) return;
-    switch (a.d) {
-        case 32: launch_ndfd_d<32>(a, vt, n_tiles, grad, s); break;
-        case 64: launch_ndfd_d<64>(a, vt, n_tiles, grad, s); break;
-        case 96: launch_ndfd_d<96>(a, vt, n_tiles, grad, s); break;
-        case 128: launch_ndfd_d<128>(a, vt, n_tiles, grad, s); break;
-        default: launch_ndfd_d<256>(a, vt, n_tiles, grad, s); break;
-    }
+    if (a.prim == FH_PRIM_SURFEL)
+        launch_ndfd_p<true>(a, vt, n_tiles, grad, s);
+    else
+        launch_ndfd_p<false>(a, vt, n_tiles, grad, s);
 }
 
-void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, hipStream_t s) {
-    const int64_t n = cap * 6;
+int ndfd_part_floats(int prim) { return prim == FH_PRIM_SURFEL ? NdfdPart<true>::W : NdfdPart<false>::W; }
+
+void launch_ndfd_combine(const float* part, float* part_geom, const Counters* c, int64_t cap, int prim,
+                         hipStream_t s) {
+    const bool surf = prim == FH_PRIM_SURFEL;
+    const int64_t n = cap * (surf ? NdfdPart<true>::NQ : NdfdPart<false>::NQ);
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_ndfd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, part_geom, c, cap,
-                       NDFD_PARTS);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (surf)
+        hipLaunchKernelGGL(k_ndfd_combine<true>, grid, dim3(256), 0, s, part, part_geom, c, cap, NDFD_PARTS);
+    else
+        hipLaunchKernelGGL(k_ndfd_combine<false>, grid, dim3(256), 0, s, part, part_geom, c, cap, NDFD_PARTS);
 }
 
 }  // namespace fh

@@ -150,7 +150,7 @@ def test_tuning_defaults_and_candidates_on_host():
 
 
 def test_plan_set_primitive_on_host():
-    # surfels: FP32 form only, no NDFD storage; records and partials grow the workspace
+    # surfels: records and partials grow the workspace
     from paper_2505_19154_amd import _lib
     lib = _lib.load()
     cam = _lib.FhCamera(64, 48, 50.0, 50.0, 32.0, 24.0, (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1),
@@ -164,7 +164,6 @@ def test_plan_set_primitive_on_host():
     assert plan.primitive == _lib.FH_PRIM_SURFEL and plan.ws_bytes > ws_gauss
     # the surfel density runs on the VALU forward (slices of at most 64 channels)
     assert plan.tuning.fwd_slice <= 64
-    assert lib.fh_plan_set_ndfd(ctypes.byref(plan), 1) == -2
     assert lib.fh_plan_set_primitive(ctypes.byref(plan), 2) == -1
     assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_GAUSSIAN) == 0
     assert plan.ws_bytes == ws_gauss and plan.tuning.fwd_slice == 256
@@ -172,7 +171,13 @@ def test_plan_set_primitive_on_host():
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 1, cams, 1, 5000, 1000) == 0
     assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_SURFEL) == 0
     assert (plan.tuning.fwd_slice, plan.tuning.fwd_rows) == (256, 8)
-    # nor a plan that holds the NDFD storage
+    # the NDFD storage: surfel partials are 16 floats per (visit, half) instead of 8
     assert lib.fh_plan_init(ctypes.byref(plan), 100, 3, 256, 1, 0, cams, 1, 5000, 1000) == 0
+    ws0 = plan.ws_bytes
     assert lib.fh_plan_set_ndfd(ctypes.byref(plan), 1) == 0
-    assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_SURFEL) == -2
+    nd_gauss = plan.ws_bytes - ws0
+    assert lib.fh_plan_set_primitive(ctypes.byref(plan), _lib.FH_PRIM_SURFEL) == 0
+    ws_nd_s = plan.ws_bytes
+    assert lib.fh_plan_set_ndfd(ctypes.byref(plan), 0) == 0
+    nd_surf = ws_nd_s - plan.ws_bytes
+    assert abs((nd_surf - nd_gauss) - 1000 * 2 * 8 * 4) <= 256

@@ -6,7 +6,9 @@ adjoint.  Scenes: BF16 features at every supported width, the ground-truth
 map the oracle's rendered features plus noise (so that sigma spreads over
 (0, 1)), rounded to BF16 and fed to both sides; seeds whose walks hold no
 near-threshold decision (the oracle's ambiguity bound does not cover the NDFD
-terms), which the test asserts."""
+terms), which the test asserts.  The surfel scenes (Section 3.1's primitive,
+the configuration the paper trains) add the oracle's density-rounding
+allowance of the losses and the gradient."""
 import numpy as np
 import pytest
 import torch
@@ -23,20 +25,31 @@ LAM, K = 0.5, 20.0
 RT = U.RTOL_FORM["bf16"]
 
 SCENES = {
-    # name: (n, half extent, d, seed, [(camera position, width, height)])
+    # name: (n, half extent, d, seed, [(camera position, width, height)][, primitive])
     "d32": (900, 1.5, 32, 13, [((0, -4, 0), 72, 56)]),
     "d64_two_views": (1200, 1.2, 64, 17, [((0, -4, 0), 64, 48), ((3, -2.5, 1.2), 50, 40)]),
     "d96": (1000, 1.5, 96, 5, [((0, -4, 0), 56, 40)]),
     "d128": (900, 1.5, 128, 12, [((0, -4, 0), 60, 44)]),
     "d256": (800, 1.5, 256, 7, [((0, -4, 0), 48, 40)]),
+    # surfels (scales x3 so that most span pixels)
+    "surfel_d64": (700, 1.5, 64, 2, [((0, -4, 0), 56, 44)], "surfel"),
+    "surfel_d256": (600, 1.5, 256, 1, [((0, -4, 0), 48, 40)], "surfel"),
+    "surfel_d32_two_views": (700, 1.5, 32, 7, [((0, -4, 0), 64, 48), ((3, -2.5, 1.2), 50, 40)], "surfel"),
 }
 
 
+def _prim(name):
+    return SCENES[name][5] if len(SCENES[name]) > 5 else "gaussian"
+
+
 def _scene(name, with_colour=False):
-    n, h, d, seed, camspec = SCENES[name]
+    n, h, d, seed, camspec = SCENES[name][:5]
     g = scenegen.make_gaussians(n, h, 1, d, seed=seed, feat_dtype="bf16")
+    if _prim(name) == "surfel":
+        g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
+    g["primitive"] = _prim(name)
     cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in camspec]
-    F = pipeline.run(g, cams)["views"]
+    F = pipeline.run(g, cams, bin_rule=_rule(g))["views"]
     rng = np.random.default_rng(700 + seed)
     vts = []
     for vi, c in enumerate(cams):
@@ -54,10 +67,15 @@ def _scene(name, with_colour=False):
     return g, cams, vts
 
 
+def _rule(g):
+    return "surfel" if g.get("primitive") == "surfel" else "box"
+
+
 def _gpu(g, cams, vts, form):
     from paper_2505_19154_amd.raster import Rasterizer
     dg = U.device_gaussians(g)
-    r = Rasterizer(cams, dg.n, 1, g["d"], feat_dtype="bf16", form=form, ndfd=True)
+    r = Rasterizer(cams, dg.n, 1, g["d"], feat_dtype="bf16", form=form, ndfd=True,
+                   primitive=g.get("primitive", "gaussian"))
     img = r.forward(dg)
     cat = lambda k: torch.from_numpy(np.ascontiguousarray(np.concatenate([v[k] for v in vts]), np.float32)).cuda()
     gt = torch.from_numpy(np.concatenate([v["gt_bits"] for v in vts]).view(np.int16)).cuda().view(torch.bfloat16)
@@ -73,15 +91,15 @@ def _gpu(g, cams, vts, form):
 
 
 def _check(name, g, cams, vts, gpu):
-    ora = pipeline.run(g, cams, vts, ndfd=dict(lam=LAM, k=K))
+    ora = pipeline.run(g, cams, vts, ndfd=dict(lam=LAM, k=K), bin_rule=_rule(g))
     # precondition: no near-threshold decision anywhere (see the module docstring)
     assert all(int((v["flags"] != 0).sum()) == 0 for v in ora["views"]) and int((ora["gflags"] != 0).sum()) == 0
     ref = lambda k: np.concatenate([v[k] for v in ora["views"]])
     # the losses: elementwise against their companions, normwise
     for nm in ("Lgt", "Lcf"):
-        r_, m_ = ref(nm), ref(nm + "_mag")
+        r_, m_, den = ref(nm), ref(nm + "_mag"), ref(nm + "_den")
         for got in (gpu[nm + "0"], gpu[nm]):
-            ratio = U.elementwise(got, r_, m_, rtol=RT)[0]
+            ratio = U.elementwise(got, r_, m_, rtol=RT, amb=den)[0]
             nw = U.normwise(got, r_)
             print(f"[ndfd {name}] {nm} ratio {ratio:.3f} norm {nw:.2e}", flush=True)
             assert ratio <= 1.0 and nw <= RT, nm
@@ -90,7 +108,8 @@ def _check(name, g, cams, vts, gpu):
     assert ref("Lgt").max() > 0 and np.std(ref("Lgt") / np.maximum(ref("WN"), 1e-12)) > 0.05
     for k in ("means", "scales", "quats", "opacity", "sh"):
         got, r_, m_ = gpu["grads"][k], ora["grads"][k], ora["grads_mag"][k]
-        ratio = U.elementwise(got, r_, m_, rtol=RT)[0]
+        # (no near-threshold decision: the bound holds only the surfel density allowance)
+        ratio = U.elementwise(got, r_, m_, rtol=RT, amb=ora["grads_amb"][k])[0]
         nw = U.normwise(got, r_)
         print(f"[ndfd {name}] grad {k} ratio {ratio:.3f} norm {nw:.2e}", flush=True)
         assert ratio <= 1.0 and nw <= RT, k
@@ -105,7 +124,8 @@ def test_ndfd_losses_and_gradient_match_oracle(name):
     _check(name, g, cams, vts, gpu)
 
 
-@pytest.mark.parametrize("name,form", [("d64_two_views", "bf16"), ("d128", "f32")])
+@pytest.mark.parametrize("name,form", [("d64_two_views", "bf16"), ("d128", "f32"), ("surfel_d64", "bf16"),
+                                       ("surfel_d32_two_views", "f32")])
 def test_ndfd_joins_the_colour_and_feature_adjoint(name, form):
     # g_k = rgb_k . dC + f_k . dF + h_k: the NDFD partials are added to the
     # gradient kernel's (either form) before the per-Gaussian reduction
