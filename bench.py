@@ -604,7 +604,40 @@ def surfel_leg(W, args, dev):
         del res
         torch.cuda.empty_cache()
     out["bf16_speedup_over_f32"] = out["f32"]["ms_per_step"] / out["bf16"]["ms_per_step"]
+    out["bf16"]["ndfd"] = _surfel_ndfd(W, args, dev)
     return out
+
+
+def _surfel_ndfd(W, args, dev):
+    """The NDFD branch (Section 3.3) along the surfel walk, BF16 form: the
+    losses alone and the backward with the NDFD gradient joined, against the
+    backward without it (the configuration the paper trains)."""
+    import torch
+
+    from paper_2505_19154_amd.raster import Rasterizer
+
+    wl, cams, dg = W["wl"], W["cams"], W["dg"]
+    K = args.steps
+    r = Rasterizer(cams, wl.n, wl.sh_degree, wl.d, feat_dtype=wl.feat_dtype, form="bf16", device=dev, ndfd=True,
+                   primitive="surfel")
+    img = r.forward(dg, margin=1.02)
+    P = r.n_pixels
+    gt = W["target"]
+    nd = dict(gt=gt, a=torch.full((P,), 1.0 / P, device=dev), b=torch.full((P,), 0.1 / P, device=dev),
+              lam=0.5, k=20.0)
+    grads = r.new_grads()
+    for _ in range(args.warmup):
+        r.ndfd_losses(dg, img, gt)
+        r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads, ndfd=nd)
+    res = dict(losses_ms=_event_ms(lambda: r.ndfd_losses(dg, img, gt), K),
+               render_bwd_with_ndfd_ms=_event_ms(
+                   lambda: r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads, ndfd=nd), K),
+               render_bwd_ms=_event_ms(lambda: r.render_bwd(dg, img, W["dC"], W["dF"], None, grads=grads), K))
+    print(f"[bench] surfel ndfd: losses {res['losses_ms']:.3f} ms, backward {res['render_bwd_ms']:.3f} -> "
+          f"{res['render_bwd_with_ndfd_ms']:.3f} ms", file=sys.stderr, flush=True)
+    del r, img
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():

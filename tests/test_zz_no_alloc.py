@@ -17,9 +17,10 @@ from tests import gpu_util as U
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # n, half extent, SH degree, d, feature dtype, form, (width, height)
-    (3000, 1.5, 2, 32, "bf16", "bf16", (120, 90)),
-    (600, 1.0, 0, 16, "f32", "f32", (50, 38)),
+    # n, half extent, SH degree, d, feature dtype, form, (width, height), primitive
+    (3000, 1.5, 2, 32, "bf16", "bf16", (120, 90), "gaussian"),
+    (1200, 1.2, 1, 64, "bf16", "bf16", (96, 72), "surfel"),
+    (600, 1.0, 0, 16, "f32", "f32", (50, 38), "gaussian"),
 ]
 
 
@@ -34,11 +35,13 @@ def _static_render(r: Rasterizer, dg):
 
 
 def test_static_entry_point_equals_the_workspace_path_on_two_calls():
-    for n, h, deg, d, fdt, form, (w, hh) in CASES:
+    for n, h, deg, d, fdt, form, (w, hh), prim in CASES:
         g = scenegen.make_gaussians(n, h, deg, d, seed=n, feat_dtype=fdt)
+        if prim == "surfel":
+            g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
         cams = [scenegen.look_at_camera((0.0, -4.0, 0.0), w, hh)]
         dg = U.device_gaussians(g)
-        r = Rasterizer(cams, n, deg, d, feat_dtype=fdt, form=form)
+        r = Rasterizer(cams, n, deg, d, feat_dtype=fdt, form=form, primitive=prim)
         ref = r.forward(dg)                      # caller workspace; sizes the capacities
         c_ref = r.counters()
         torch.cuda.synchronize()
@@ -52,7 +55,7 @@ def test_static_entry_point_equals_the_workspace_path_on_two_calls():
         assert int(cnt[0]) == c_ref.n_instances and int(cnt[1]) == c_ref.n_visited
         flags = cnt[3:4].view(np.int32)
         assert flags[0] == 0 and flags[1] == 0
-        print(f"[no-alloc] n={n} {w}x{hh}: equal, {int(cnt[0])} instances", flush=True)
+        print(f"[no-alloc] n={n} {w}x{hh} {prim}: equal, {int(cnt[0])} instances", flush=True)
 
 
 def test_static_entry_point_rejects_a_plan_beyond_the_scratch():
