@@ -43,6 +43,13 @@ constexpr int BK = 32;   // positions per chunk
 // Gaussian-parallel reads (consecutive positions per lane) twice
 constexpr int SK = BK + 3;
 constexpr int RG = 4;        // record padding group: the walk's lane rows read records 4 apart
+// Row padding (bf16) of the LDS tiles that MFMA operands are read from as
+// 16-byte rows, lane (xi, q) at row xi, column 8 q: rows of D + 16 (or 256 +
+// 16) bf16 start an odd multiple of 8 dwords apart, so that the lanes served
+// together (xi = 0..7 of two adjacent q) fall in distinct banks; with 8 bf16
+// of padding (rows an odd multiple of 4 dwords apart) they meet in pairs,
+// which measures 1.8x slower on this read pattern.
+constexpr int OPAD = 16;
 // float4 slots of one chunk's staged records
 template <bool SURF>
 constexpr int rslots() {
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
     constexpr int RW = PrimRec<SURF>::RW, NQ = PrimRec<SURF>::NQ, GP = PrimRec<SURF>::GP;
     constexpr int RSLOTS = rslots<SURF>();
     const int dstride = SL ? a.d : D, dofs = SL ? a.d0 : 0;
-    constexpr int DP = D + 8;            // padded row stride (bf16) of the feature chunk
+    constexpr int DP = D + OPAD;         // padded row stride (bf16) of the feature chunk
     constexpr int NS = D / 32;           // MFMA steps over channels
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16* sfeat2 = reinterpret_cast<__bf16*>(smem);                        // [2][BK][DP], double-buffered
@@ -497,7 +504,7 @@ __global__ __launch_bounds__(512) void k_render_bwd_bf16(BwdArgs a, ViewTable vt
 // front to back, the features staged in LDS.
 template <int D>
 __global__ __launch_bounds__(512) void k_gk_bf16(BwdArgs a, ViewTable vt) {
-    constexpr int DP = D + 8;
+    constexpr int DP = D + OPAD;
     constexpr int NS = D / 32;
     __shared__ __attribute__((aligned(16))) __bf16 sfeat[BK * DP];
     if (a.counters->inst_overflow || a.counters->visit_overflow) return;
@@ -592,7 +599,7 @@ template <int D, bool WS, bool SURF>
 __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
     using RecT = typename PrimRec<SURF>::T;
     constexpr int RW = PrimRec<SURF>::RW;
-    constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
+    constexpr int PP = TILE_PIX + OPAD;  // padded row stride (bf16) of W^T
     constexpr int NDB = D / 16;
     // W^T and the weight sums are double-buffered by chunk parity, so that one
     // barrier per chunk suffices: a wave may walk chunk c + 1 while others
@@ -787,7 +794,7 @@ __global__ __launch_bounds__(1024) void k_fuse_bf16(BwdArgs a, ViewTable vt) {
 // this chunk's contraction).
 template <int D>
 __global__ __launch_bounds__(1024) void k_fuse_rec_bf16(BwdArgs a, ViewTable vt) {
-    constexpr int PP = TILE_PIX + 8;     // padded row stride (bf16) of W^T
+    constexpr int PP = TILE_PIX + OPAD;  // padded row stride (bf16) of W^T
     constexpr int NDB = D / 16;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16* swh2 = reinterpret_cast<__bf16*>(smem);                          // [2][BK][PP] W^T hi
@@ -910,7 +917,7 @@ static void launch_fuse_bf16(const BwdArgs& a0, const ViewTable& vt, int n_tiles
                              hipStream_t s) {
     if (!fuse) return;
     // one workgroup per (tile, channel slice)
-    const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + 8);
+    const size_t lds = sizeof(__bf16) * 4 * (size_t)BK * (TILE_PIX + OPAD);
     const dim3 grid(n_tiles, ns);
     if (grads && a0.wrec)
         hipLaunchKernelGGL(k_fuse_rec_bf16<D>, grid, dim3(1024), lds, s, a0, vt);
@@ -926,7 +933,7 @@ template <int D, bool SURF>
 static void launch_bf16_d(const BwdArgs& a0, const ViewTable& vt, int n_tiles, bool grads, bool fuse, hipStream_t s) {
     const int ns = a0.d / D;   // channel slices
     if (grads) {
-        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (D + 8) +
+        const size_t lds = sizeof(__bf16) * 2 * (size_t)BK * (D + OPAD) +
                            sizeof(float) * (2 * (size_t)TILE_PIX * SK + 3 * TILE_PIX + 8 * PrimRec<SURF>::NQ * BK);
         BwdArgs a = a0;
         a.d0 = 0;
