@@ -6,16 +6,19 @@ paper: the adjoint through w_i = alpha_i T_i, transmittance recovered back to
 front from the stored final T and last-contributor index) and returns the
 gradients of the five differentiable inputs.  Backward reads the binning and
 traversal state its forward left in the rasterizer's workspace, so it raises if
-the rasterizer ran another forward (or re-planned) in between.  The feature
-tensor is frozen
-(Section 3.2: f_i is non-differentiable) and gets no gradient.
+the rasterizer ran another forward (or re-planned) in between.  The paper
+freezes the features (Section 3.2: f_i is non-differentiable); when a caller
+asks for their gradient anyway (feat.requires_grad), dL/df_i = sum_p w_i(p)
+dF(p) is the unnormalised fusion of the map dF, computed by fh_fuse_features
+(in the BF16 form, which fuses BF16 targets, as the fusion of dF's BF16 hi
+part plus that of its lo part into the same compensated accumulators).
 """
 from __future__ import annotations
 
 import torch
 
-from ._lib import FhError
-from .raster import Gaussians, Rasterizer
+from ._lib import FH_FORM_BF16, FhError
+from .raster import FusionAcc, Gaussians, Rasterizer
 
 
 class RasterizeFn(torch.autograd.Function):
@@ -43,7 +46,26 @@ class RasterizeFn(torch.autograd.Function):
         dF = None if (dF is None or ctx.img.F is None) else dF.contiguous().float()
         dT = None if dT is None else dT.contiguous().float()
         grads = r.render_bwd(ctx.g, ctx.img, dC, dF, dT)
-        return grads["means"], grads["scales"], grads["quats"], grads["opacity"], grads["sh"], None, None, None
+        dfeat = None
+        if ctx.needs_input_grad[5] and ctx.g.feat is not None:
+            dfeat = _feature_grad(r, ctx.g, ctx.img, dF)
+        return grads["means"], grads["scales"], grads["quats"], grads["opacity"], grads["sh"], dfeat, None, None
+
+
+def _feature_grad(r: Rasterizer, g: Gaussians, img, dF) -> torch.Tensor:
+    """dL/df = sum_p w(p) dF(p) per Gaussian (zero without dF)."""
+    feat = g.feat
+    if dF is None:
+        return torch.zeros_like(feat)
+    acc = FusionAcc.zeros(feat.shape[0], feat.shape[1], feat.device)
+    if r.plan.form == FH_FORM_BF16:
+        hi = dF.to(torch.bfloat16)
+        lo = (dF - hi.float()).to(torch.bfloat16)
+        r.fuse_features(g, img, hi.contiguous(), acc)
+        r.fuse_features(g, img, lo.contiguous(), acc)
+    else:
+        r.fuse_features(g, img, dF.contiguous(), acc)
+    return (acc.sum + acc.comp).to(feat.dtype)
 
 
 def rasterize(rasterizer: Rasterizer, means, scales, quats, opacity, sh, feat, sh_degree: int):

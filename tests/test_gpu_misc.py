@@ -406,3 +406,37 @@ def test_autograd_function_with_surfels(form):
                              amb=ora["grads_amb"][k])[0] <= 1.0, k
     # the third scale takes no part in a surfel
     assert torch.all(params[1].grad[:, 2] == 0)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_autograd_feature_gradient_is_the_fusion_of_dF(form):
+    """With feat.requires_grad, RasterizeFn returns dL/df_i = sum_p w_i(p) dF(p)
+    (the unnormalised fusion of dF; the paper's features are frozen, so this is
+    asked for explicitly), against the oracle's fusion sums of the map dF."""
+    from paper_2505_19154_amd.autograd import rasterize
+    from paper_2505_19154_amd.raster import Rasterizer
+    d = 32
+    fdt = "bf16" if form == "bf16" else "f32"
+    g = scenegen.make_gaussians(900, 1.2, 1, d, seed=24, feat_dtype=fdt)
+    cams = scenegen.make_cameras("front64x48")
+    vt = scenegen.make_view_tensors(0, cams[0].npix, d, with_dT=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    params = [t(g[k]).requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    feat = U.device_gaussians(g).feat.clone().requires_grad_(True)
+    r = Rasterizer(cams, len(g["opacity"]), 1, d, feat_dtype=fdt, form=form)
+    C, F, T, _ = rasterize(r, *params, feat, 1)
+    loss = (F.double() * t(vt["dF"]).double()).sum() + (C.double() * t(vt["dC"]).double()).sum()
+    loss.backward()
+    got = feat.grad.float().cpu().numpy()
+    # the oracle: fusion of the target map dF, unnormalised
+    ora = pipeline.run(g, cams, [dict(vt, target=vt["dF"])], fusion=True)
+    keep = U.checkable(ora["gflags"])
+    m = keep[:, None] & np.ones(got.shape, bool)
+    if form == "f32":
+        assert U.elementwise(got, ora["fsum"], ora["fsum_mag"], rtol=U.RTOL_FORM[form], mask=m,
+                             amb=ora["fsum_amb"])[0] <= 1.0
+    else:
+        # returned in the features' BF16: within half a BF16 unit of the magnitude, plus the form's rule
+        assert U.elementwise(got, ora["fsum"], ora["fsum_mag"], rtol=2.0 ** -8 + U.RTOL_FORM[form], mask=m,
+                             amb=ora["fsum_amb"])[0] <= 1.0
+    assert np.abs(got).max() > 0
