@@ -25,12 +25,14 @@
  *     no device state between calls.
  *   - All calls are asynchronous on the given HIP stream (NULL = the default
  *     stream) and never synchronise the host, except fh_read_counters, which
- *     waits for the stream.  Calls that only launch kernels can be captured
+ *     waits for the stream (fh_get_status copies the same counters on the
+ *     stream without waiting).  Calls that only launch kernels can be captured
  *     into a HIP graph.
  *   - Return value: FH_OK, or a negative fh_status for errors detected on the
  *     host (bad arguments, launch failure).  Conditions only known on the
  *     device (instance capacity exceeded, non-finite Gaussians culled) are
- *     recorded in the workspace and read back by fh_read_counters.
+ *     recorded in the workspace and read back by fh_read_counters or
+ *     fh_get_status.
  *   - Cameras: pinhole, OpenCV axes (x right, y down, z forward);
  *     p_cam = R p_world + t with R row-major.  Pixel (px, py) samples the
  *     point (px + 1/2, py + 1/2).
@@ -358,6 +360,14 @@ fh_status fh_fuse_finalize(const fh_fusion *acc, int64_t n, int32_t d, const voi
 
 /* Wait for `stream` and copy the device counters into *out (host). */
 fh_status fh_read_counters(const fh_plan *plan, const void *ws, fh_counters *out, hipStream_t stream);
+
+/* The device counters (the status word of the calls so far on `stream`:
+ * instance and visit counts, overflow flags, non-finite culls) copied by a
+ * kernel on `stream` into *out, a DEVICE-accessible pointer (device memory or
+ * pinned host memory), without synchronising the host; capturable in a HIP
+ * graph.  The values are there once `stream` has reached the copy.
+ * FH_E_INVALID for a null argument. */
+fh_status fh_get_status(const fh_plan *plan, const void *ws, fh_counters *out, hipStream_t stream);
 
 /* Device pointer and element count of a workspace buffer (no device access). */
 fh_status fh_get_buffer(const fh_plan *plan, void *ws, fh_buffer which, void **ptr, int64_t *count);

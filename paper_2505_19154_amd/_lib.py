@@ -104,6 +104,7 @@ SIGNATURES = {
     "fh_fuse_features": (_i32, [_P(FhPlan), _P(FhGaussians), _vp, _P(FhImage), _vp, _i32, _P(FhFusion), _vp]),
     "fh_fuse_finalize": (_i32, [_P(FhFusion), _i64, _i32, _vp, _vp, _i32, _vp]),
     "fh_read_counters": (_i32, [_P(FhPlan), _vp, _P(FhCounters), _vp]),
+    "fh_get_status": (_i32, [_P(FhPlan), _vp, _vp, _vp]),
     "fh_get_buffer": (_i32, [_P(FhPlan), _vp, _i32, _P(_vp), _P(_i64)]),
     "fh_set_kernel_events": (_i32, [_i32, _vp, _vp, _i32]),
     "fh_render_fwd_static": (_i32, [_P(FhPlan), _P(FhGaussians), _P(FhImage), _vp, _vp]),

@@ -882,6 +882,12 @@ fh_status fh_read_counters(const fh_plan* p, const void* ws, fh_counters* out, h
     return FH_OK;
 }
 
+fh_status fh_get_status(const fh_plan* p, const void* ws, fh_counters* out, hipStream_t s) {
+    if (!p || !ws || !out) return FH_E_INVALID;
+    hipLaunchKernelGGL(k_export_counters, dim3(1), dim3(64), 0, s, cbuf<Counters>(p, ws, WS_COUNTERS), out);
+    return launch_status();
+}
+
 fh_status fh_get_buffer(const fh_plan* p, void* ws, fh_buffer which, void** ptr, int64_t* count) {
     if (!p || !ws || !ptr || !count) return FH_E_INVALID;
     const int64_t total = (int64_t)p->n * p->n_views;

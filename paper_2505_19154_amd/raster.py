@@ -206,6 +206,13 @@ class Rasterizer:
                 "fh_read_counters")
         return c
 
+    def status_async(self, out: torch.Tensor) -> None:
+        """fh_get_status into `out` (int64 [4] on the device, the fh_counters
+        layout: three int64 counts, then the two int32 overflow flags), on the
+        current stream without synchronising."""
+        check_tensor(out, "out", (4,), (torch.int64,), self.device)
+        L.check(self.lib.fh_get_status(ctypes.byref(self.plan), _ptr(self.ws), _ptr(out), _stream()), "fh_get_status")
+
     # -- the C-ABI calls ----------------------------------------------------
     def _check_image(self, img: "Image", name: str) -> None:
         P, d, dev = self.n_pixels, self.d, self.device

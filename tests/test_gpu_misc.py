@@ -440,3 +440,20 @@ def test_autograd_feature_gradient_is_the_fusion_of_dF(form):
         assert U.elementwise(got, ora["fsum"], ora["fsum_mag"], rtol=2.0 ** -8 + U.RTOL_FORM[form], mask=m,
                              amb=ora["fsum_amb"])[0] <= 1.0
     assert np.abs(got).max() > 0
+
+
+def test_get_status_matches_read_counters_without_a_sync():
+    """fh_get_status copies the counters on the stream (device destination,
+    no host synchronisation) and agrees with fh_read_counters."""
+    g = scenegen.make_gaussians(500, 1.0, 0, 8, seed=25)
+    cams = scenegen.make_cameras("front64x48")
+    dg, r = _raster(g, cams)
+    img = r.forward(dg)
+    out = torch.full((4,), -1, dtype=torch.int64, device="cuda")
+    r.status_async(out)
+    c = r.counters()      # (synchronises)
+    got = out.cpu().numpy()
+    flags = got[3:4].view(np.int32)
+    assert got[0] == c.n_instances and got[1] == c.n_visited and got[2] == c.n_culled_nonfinite
+    assert flags[0] == c.inst_overflow and flags[1] == c.visit_overflow
+    assert c.n_instances > 0 and c.n_visited > 0
