@@ -5,7 +5,8 @@ oracle computes one by one:
 * 1M Gaussians, SH3, D=128 BF16, 16 views of 640x480 .. 1600x1200 (sphere, r=5);
 * 3M Gaussians, SH3, D=512 BF16, 8 views at 1920x1080.
 
-The 16-view workload's step is also captured in one HIP graph and replayed:
+The 16-view workload is also checked with its parameters as surfels (Section
+3.1) in the BF16 form.  Its step is also captured in one HIP graph and replayed:
 every replay must reproduce the eager step bit for bit, so the checks above
 hold for the graph-replayed form that the benchmark times.
 
@@ -29,7 +30,7 @@ from tests import sampled as S
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("c4", "bf16"), ("c4", "f32"), ("c5", "bf16")]
+CASES = [("c4", "bf16", "gaussian"), ("c4", "f32", "gaussian"), ("c5", "bf16", "gaussian"), ("c4", "bf16", "surfel")]
 RT = {f: dict(F=r, grad=r, fuse=r) for f, r in U.RTOL_FORM.items()}
 N_SAMPLE = 32          # Gaussians whose gradients and fusion sums are checked (at most)
 EXTRA_TILES = 2        # further random non-empty tiles per view for the forward check
@@ -51,19 +52,21 @@ def _device_maps(cams, d, dev, target_dtype):
     return dC, dF, dT, tg
 
 
-@pytest.fixture(scope="module", params=CASES, ids=[f"{w}-{f}" for w, f in CASES])
+@pytest.fixture(scope="module", params=CASES, ids=[f"{w}-{f}" + ("" if p == "gaussian" else f"-{p}")
+                                                    for w, f, p in CASES])
 def run(request):
     from paper_2505_19154_amd.raster import FusionAcc, Rasterizer
-    wname, form = request.param
+    wname, form, prim = request.param
+    surf = prim == "surfel"
     wl = scenegen.WORKLOADS[wname]
     dev = torch.device("cuda:0")
-    tag = f"[batched {wname} {form}]"
+    tag = f"[batched {wname} {form} {prim}]"
     print(f"\n{tag} generating", flush=True)
     g = scenegen.make_gaussians(wl.n, wl.half_extent, wl.sh_degree, wl.d, seed=0, feat_dtype=wl.feat_dtype)
     cams = scenegen.make_cameras(wl.views)
     dg = U.device_gaussians(g)
     dC, dF, dT, tg = _device_maps(cams, wl.d, dev, wl.feat_dtype)
-    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=wl.feat_dtype, form=form)
+    r = Rasterizer(cams, dg.n, dg.sh_degree, dg.d, feat_dtype=wl.feat_dtype, form=form, primitive=prim)
     img = r.forward(dg, margin=1.02)
     acc = FusionAcc.zeros(dg.n, dg.d, dev)
     grads = r.render_bwd(dg, img, dC, dF, dT, target=tg, acc=acc)
@@ -72,7 +75,7 @@ def run(request):
     print(f"{tag} gpu done: {c.n_instances} instances, {c.n_visited} visited", flush=True)
     assert not c.inst_overflow and not c.visit_overflow
 
-    bqs = [binspec.bin_quantities(g, cam) for cam in cams]
+    bqs = [binspec.bin_quantities(g, cam, "surfel" if surf else "box") for cam in cams]
     counts = [binspec.tile_counts(bq) for bq in bqs]
     print(f"{tag} oracle binning quantities done", flush=True)
     # the front layer of view 0 (the only Gaussians its walk reaches at this density)
@@ -96,7 +99,7 @@ def run(request):
         gp = torch.from_numpy(pix + views[vi]["pix_off"]).to(dev)
         return maps[key][gp].float().cpu().numpy()
 
-    ora = S.run(g, cams, bqs, cand, views, rows, wl.d, log=lambda m: print(f"{tag} {m}", flush=True))
+    ora = S.run(g, cams, bqs, cand, views, rows, wl.d, log=lambda m: print(f"{tag} {m}", flush=True), surfels=surf)
     return dict(wl=wl, form=form, cams=cams, r=r, img=img, grads=grads, acc=acc, c=c, bqs=bqs, counts=counts,
                 ranges=ranges, views=views, cand=cand, dg=dg, maps=maps, **ora)
 
@@ -128,9 +131,10 @@ def test_forward_sampled_tiles(run):
         gp = torch.from_numpy(f["pix"] + vw["pix_off"]).cuda()
         assert np.array_equal(img.n_iter[gp].cpu().numpy().astype(np.int64)[ok], f["niter"][ok])
         C, T, F = img.C[gp].cpu().numpy(), img.T[gp].cpu().numpy(), img.F[gp].cpu().numpy()
-        assert U.elementwise(C, f["C"], f["Cmag"], mask=ok[:, None].repeat(3, 1))[0] <= 1.0
-        assert U.elementwise(T, f["T"], f["T"], mask=ok)[0] <= 1.0
-        mF, _ = U.elementwise(F, f["F"], f["Fmag"], rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1))
+        # (Cden, Tden, Fden: the surfel density allowance, zero for Gaussians)
+        assert U.elementwise(C, f["C"], f["Cmag"], mask=ok[:, None].repeat(3, 1), amb=f["Cden"])[0] <= 1.0
+        assert U.elementwise(T, f["T"], f["T"], mask=ok, amb=f["Tden"])[0] <= 1.0
+        mF, _ = U.elementwise(F, f["F"], f["Fmag"], rtol=rt, mask=ok[:, None].repeat(F.shape[1], 1), amb=f["Fden"])
         worst = max(worst, mF)
     print(f"[batched] F ratio max {worst:.3f} (rtol {rt:g})", flush=True)
     assert worst <= 1.0
