@@ -56,16 +56,23 @@ extern "C" {
 #define FH_WS_SLOTS 48   /* capacity of fh_plan.off (workspace sub-buffers in use: fh_plan.n_ws) */
 #define FH_TILE 16
 
+/* Every enum of this interface spans the whole int32 range (its two _RANGE_
+ * enumerators are bounds, not values): callers pass enums as plain integers,
+ * and the library's rejection of an unknown one (FH_E_INVALID, or "unknown"
+ * from fh_status_string) is then well defined in C and C++ alike. */
+#define FH_ENUM_RANGE(P) P##_RANGE_MIN_ = -0x7fffffff - 1, P##_RANGE_MAX_ = 0x7fffffff
+
 typedef enum {
     FH_OK = 0,
     FH_E_INVALID = -1,      /* null pointer, size or layout error */
     FH_E_UNSUPPORTED = -2,  /* e.g. sh_degree > 3, too many views */
     FH_E_HIP = -3,          /* a HIP launch or runtime call failed */
     FH_E_CAPACITY = -4,     /* device-side: instance or visit capacity exceeded */
-    FH_E_SCRATCH = -5       /* the plan's workspace exceeds FH_STATIC_SCRATCH_BYTES (fh_render_fwd_static) */
+    FH_E_SCRATCH = -5,      /* the plan's workspace exceeds FH_STATIC_SCRATCH_BYTES (fh_render_fwd_static) */
+    FH_ENUM_RANGE(FH_STATUS)
 } fh_status;
 
-typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
+typedef enum { FH_F32 = 0, FH_BF16 = 1, FH_ENUM_RANGE(FH_DTYPE) } fh_dtype;
 
 /* Footprint rule of the tile binning (fh_plan.bin_rule).  Both rules give
  * every tile holding a pixel where alpha = o G can reach 1/255, so no
@@ -79,7 +86,7 @@ typedef enum { FH_F32 = 0, FH_BF16 = 1 } fh_dtype;
  *                   Gaussians with 255 o_i <= 1 get no instances.  ln is a
  *                   fixed sequence of float32 operations (range reduction
  *                   to [sqrt(1/2), sqrt 2) and the atanh series to s^9). */
-typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
+typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1, FH_ENUM_RANGE(FH_BIN) } fh_bin_rule;
 
 /* Primitive (fh_plan.primitive, set by fh_plan_set_primitive).
  *   FH_PRIM_GAUSSIAN  3D Gaussians with the EWA screen-space projection
@@ -96,13 +103,14 @@ typedef enum { FH_BIN_BOX = 0, FH_BIN_OPACITY = 1 } fh_bin_rule;
  *                     kappa_i of FH_BIN_OPACITY, whatever bin_rule says),
  *                     and surfels whose disc reaches the camera plane are
  *                     culled.  Both arithmetic forms and the NDFD branch. */
-typedef enum { FH_PRIM_GAUSSIAN = 0, FH_PRIM_SURFEL = 1 } fh_primitive;
+typedef enum { FH_PRIM_GAUSSIAN = 0, FH_PRIM_SURFEL = 1, FH_ENUM_RANGE(FH_PRIM) } fh_primitive;
 
 /* Arithmetic form of the compositing kernels. */
 typedef enum {
     FH_FORM_F32 = 0,        /* FP32 blending; the adjoint and fusion on the FP32 VALU; the forward on MFMA with
                                three-term BF16 splits of w and f for FP32 features where d allows, else on the VALU */
-    FH_FORM_BF16 = 1        /* BF16 features, (pixels x K)(K x D) blends on MFMA, FP32 accumulation */
+    FH_FORM_BF16 = 1,       /* BF16 features, (pixels x K)(K x D) blends on MFMA, FP32 accumulation */
+    FH_ENUM_RANGE(FH_FORM)
 } fh_form;
 
 /* The Gaussians theta_i (Section 3.1), structure of arrays, activated values.
@@ -266,8 +274,9 @@ typedef enum {
     FH_BUF_DEPTH_ORDER = 3,  /* u32 [V*n] Gaussian index, per view sorted by (depth, index) */
     FH_BUF_RANGES = 4,       /* u32 [tiles,2] [start, end) into the sorted instances */
     FH_BUF_TILE_NITER = 5,   /* u32 [tiles] max n_iter over the tile's pixels (after render_fwd) */
-    FH_BUF_GRAD2D = 6        /* float [V*n,12] per-(view, Gaussian) screen-space adjoints (after render_bwd;
+    FH_BUF_GRAD2D = 6,       /* float [V*n,12] per-(view, Gaussian) screen-space adjoints (after render_bwd;
                                 surfels: [V*n,16]) */
+    FH_ENUM_RANGE(FH_BUF)
 } fh_buffer;
 
 /* Fill `plan` for n Gaussians and n_views cameras (host array `cams`).
@@ -421,7 +430,8 @@ typedef enum {
     FH_K_RENDER_BWD = 3,    /* the adjoint (+ fusion) compositing kernel of fh_render_bwd / fh_fuse_features */
     FH_K_REDUCE = 4,        /* the per-Gaussian reductions of the per-instance partials */
     FH_K_PROJECT_BWD = 5,   /* the projection adjoint of fh_render_bwd */
-    FH_K_NDFD = 6           /* the NDFD walk of fh_render_bwd / fh_ndfd_losses */
+    FH_K_NDFD = 6,          /* the NDFD walk of fh_render_bwd / fh_ndfd_losses */
+    FH_ENUM_RANGE(FH_K)
 } fh_kernel;
 
 /* Profiling hook for benchmarks: for the next n launches of `which`, record

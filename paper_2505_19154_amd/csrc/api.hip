@@ -912,6 +912,7 @@ const char* fh_status_string(fh_status s) {
         case FH_E_HIP: return "HIP runtime or launch error";
         case FH_E_CAPACITY: return "capacity exceeded";
         case FH_E_SCRATCH: return "the plan's workspace exceeds the static scratch (FH_STATIC_SCRATCH_BYTES)";
+        default: break;
     }
     return "unknown status";
 }

@@ -334,11 +334,12 @@ size_t densify_ws_layout(int64_t n, char* base, DensifyWs* w) {
     const size_t u = sizeof(uint32_t);
     const size_t sizes[6] = {n * u, n * u, n * u, (n + 1) * u, (n + 1) * u, scan_scratch_u32(n + 1) * u};
     size_t off = 0;
-    uint32_t** slots[6] = {&w->action, &w->keep, &w->extra, &w->keep_off, &w->extra_off, &w->scratch};
+    uint32_t* at[6];
     for (int i = 0; i < 6; ++i) {
-        if (base) *slots[i] = reinterpret_cast<uint32_t*>(base + off);
+        at[i] = base ? reinterpret_cast<uint32_t*>(base + off) : nullptr;
         off += al256(sizes[i]);
     }
+    if (w) *w = DensifyWs{at[0], at[1], at[2], at[3], at[4], at[5]};
     return off;
 }
 bool params_ok(const fh_params* p) {
