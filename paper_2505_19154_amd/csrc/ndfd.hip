@@ -155,41 +155,91 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
     const float ig = gsum > 0.0f ? 1.0f / sqrtf(gsum) : 0.0f;
 
     // ---- chunk staging: records, features (row-major and transposed) --------
+    // Chunk i of a pass: front to back, positions 32 i .. ; back to front, the
+    // 32 positions ending at nt - 32 i.  Pipelined: the Gaussian of this
+    // thread's position (k = thread % NK, the same for all its items) two
+    // chunks ahead, and the feature rows and one record dword of the next
+    // chunk, are held in registers while the current chunk is processed, and
+    // stored to LDS at the next chunk's staging point.
     constexpr int ITEMS = NK * (D / 8), NI = (ITEMS + NT - 1) / NT;
-    auto stage = [&](int cs, int cnt) {
-        if ((int)threadIdx.x < NK) {
-            const int k = threadIdx.x;
-            const RecT r = k < cnt ? load_rec<SURF>(a.vrec, (int64_t)voff + cs + k) : pad_rec<SURF>();
-            lds_put_prec<SURF, NRG>(srec, k, r);
+    constexpr int RD = 4 * RW;                // record dwords (one per thread, threads 0 .. RD NK - 1)
+    static_assert(NT % NK == 0 && RD * NK <= NT, "staging layout");
+    auto chunk = [&](bool fwd, int i, int& cs, int& cnt) -> bool {
+        if (fwd) {
+            cs = NK * i;
+            cnt = (int)nt - cs < NK ? (int)nt - cs : NK;
+            return cs < (int)nt;
         }
-        // item = (position k, 8-channel group dg), k fastest: a wave's 2-byte
-        // stores of the transposed tile then fill consecutive bank slots
-        uint4 raw[NI];
+        const int ce = (int)nt - NK * i;
+        cs = ce - NK > 0 ? ce - NK : 0;
+        cnt = ce - cs;
+        return ce > 0;
+    };
+    const int kk = (int)threadIdx.x % NK;     // this thread's position in every staged chunk
+    const int rk = (int)threadIdx.x / RD, rj = (int)threadIdx.x % RD;   // its record and dword
+    float pad_dw = 0.0f;                      // the padding record's dword rj
+    {
+        const RecT pr = pad_rec<SURF>();
+        float4 f4[4] = {pr.r0, pr.r1, pr.r2, pr.r0};
+        if constexpr (SURF) f4[3] = pr.r3;
+#pragma unroll
+        for (int i = 0; i < RD; ++i) {
+            const float4 c = f4[i / 4];
+            const float e = (i % 4) == 0 ? c.x : ((i % 4) == 1 ? c.y : ((i % 4) == 2 ? c.z : c.w));
+            pad_dw = rj == i ? e : pad_dw;
+        }
+    }
+    uint32_t pgid = 0xFFFFFFFFu;              // Gaussian at position kk of the chunk after the next one
+    uint4 praw[NI];                           // feature rows of the next chunk
+    float prec = 0.0f;                        // record dword of the next chunk
+    auto fetch_gid = [&](bool fwd, int i) {
+        int cs, cnt;
+        pgid = 0xFFFFFFFFu;
+        if (chunk(fwd, i, cs, cnt) && kk < cnt) pgid = a.vgid[(int64_t)voff + cs + kk];
+    };
+    auto fetch_data = [&](bool fwd, int i) {   // chunk i, whose Gaussians pgid holds
+        int cs, cnt;
+        const bool ok = chunk(fwd, i, cs, cnt);
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
             const int idx = threadIdx.x + NT * it;
-            raw[it] = make_uint4(0u, 0u, 0u, 0u);
-            if (idx < ITEMS) {
-                const int k = idx % NK, dg = idx / NK;
-                if (k < cnt) {
-                    const uint32_t g = a.vgid[(int64_t)voff + cs + k];
-                    raw[it] = *reinterpret_cast<const uint4*>(a.feat + (int64_t)g * D + dg * 8);
-                }
-            }
+            praw[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (ok && idx < ITEMS && pgid != 0xFFFFFFFFu)
+                praw[it] = *reinterpret_cast<const uint4*>(a.feat + (int64_t)pgid * D + (idx / NK) * 8);
         }
+        prec = pad_dw;
+        if (ok && (int)threadIdx.x < RD * NK && rk < cnt)
+            prec = reinterpret_cast<const float*>(a.vrec)[((int64_t)voff + cs + rk) * RD + rj];
+    };
+    auto commit = [&]() {
+        if ((int)threadIdx.x < RD * NK) reinterpret_cast<float*>(srec)[4 * prec_slot<SURF, NRG>(rk) + rj] = prec;
+        // item = (position k, 8-channel group dg), k fastest: a wave's 2-byte
+        // stores of the transposed tile then fill consecutive bank slots
         uint16_t* f16 = reinterpret_cast<uint16_t*>(sfeat);
         uint16_t* ft16 = reinterpret_cast<uint16_t*>(sfeatT);
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
             const int idx = threadIdx.x + NT * it;
             if (idx < ITEMS) {
-                const int k = idx % NK, dg = idx / NK;
-                *reinterpret_cast<uint4*>(&f16[k * DP + dg * 8]) = raw[it];
-                const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw[it]);
+                const int dg = idx / NK;
+                *reinterpret_cast<uint4*>(&f16[kk * DP + dg * 8]) = praw[it];
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&praw[it]);
 #pragma unroll
-                for (int m = 0; m < 8; ++m) ft16[(dg * 8 + m) * NJP + k] = h[m];
+                for (int m = 0; m < 8; ++m) ft16[(dg * 8 + m) * NJP + kk] = h[m];
             }
         }
+    };
+    // first chunk of a pass in flight, the second one's Gaussians requested
+    auto pipeline_start = [&](bool fwd) {
+        fetch_gid(fwd, 0);
+        fetch_data(fwd, 0);
+        fetch_gid(fwd, 1);
+    };
+    // chunk i to LDS (between the two barriers), chunk i + 1 in flight
+    auto stage = [&](bool fwd, int i) {
+        commit();
+        fetch_data(fwd, i + 1);
+        fetch_gid(fwd, i + 2);
     };
     // A operand of a contraction over channels: feature row `row`, slab s, in
     // the channel order of the accumulator layout
@@ -303,10 +353,11 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
 
     // ---- pass 1: front to back, the losses ------------------------------------
     float T = 1.0f, Wacc = 0.0f, lgt = 0.0f, lcf = 0.0f;
+    pipeline_start(true);
     for (int cs = 0; cs < (int)nt; cs += NK) {
         const int cnt = (int)nt - cs < NK ? (int)nt - cs : NK;
         __syncthreads();
-        stage(cs, cnt);
+        stage(true, cs / NK);
         __syncthreads();
         gram();
         f32x4 ph[2];
@@ -404,11 +455,12 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
     T = inside ? a.T_final[p] : 1.0f;
     float Asuf = 0.0f, Ssuf = 0.0f;
     __syncthreads();   // (pass 1's stores of sc are read back by the same lanes)
+    pipeline_start(false);
     for (int ce = (int)nt; ce > 0; ce -= NK) {
         const int cs = ce - NK > 0 ? ce - NK : 0;
         const int cnt = ce - cs;
         __syncthreads();
-        stage(cs, cnt);
+        stage(false, ((int)nt - ce) / NK);
         __syncthreads();
         gram();
         float al[2][4], iv[2][4], wv[2][4], Tk[2][4], sg[2][4], ck[2][4];
