@@ -255,7 +255,8 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
         const uint2 hi = *reinterpret_cast<const uint2*>(&sfeatT[d * NJP + 16 + 4 * q]);
         return bf16x8_of(lo, hi);
     };
-    // waves 0..3: the chunk's Gram matrix G[j][k] = f_j . f_k, one 16 x 16 block each
+    // waves 0..3: the chunk's Gram matrix G[j][k] = f_j . f_k, one 16 x 16 block
+    // each, and the inverse norms of the chunk's features
     auto gram = [&]() {
         if (w < 4) {
             const int jb = w >> 1, kb = w & 1;
@@ -266,17 +267,16 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
                                                               0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) sG[(16 * jb + 4 * q + r) * (NK + 1) + 16 * kb + xi] = acc[r];
-        }
-    };
-    // 1 / |f_k| of the chunk's positions from the Gram diagonal
-    auto norms = [&]() {
-        if ((int)threadIdx.x < NK) {
-            const float gkk = sG[threadIdx.x * (NK + 2)];
-            sinv[threadIdx.x] = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
+            // 1 / |f_k| from the diagonal blocks' diagonal (row 4 q + r = column xi)
+            if (jb == kb && (xi >> 2) == q) {
+                const int r = xi & 3;
+                const float gkk = r == 0 ? acc[0] : (r == 1 ? acc[1] : (r == 2 ? acc[2] : acc[3]));
+                sinv[16 * jb + xi] = gkk > 0.0f ? 1.0f / sqrtf(gkk) : 0.0f;
+            }
         }
     };
     // unit Gram operands: row k, slot 8 g + m <-> position j(g, m), masked by
-    // mask 0: j < k, 1: j >= k, 2: j > k (after norms)
+    // mask 0: j < k, 1: j >= k, 2: j > k (after gram)
     auto build_masks = [&](int m0, int m1) {
         uint16_t* a16 = reinterpret_cast<uint16_t*>(sA);
         for (int e = threadIdx.x; e < NK * NK; e += NT) {
@@ -401,8 +401,6 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
             }
         }
         __syncthreads();
-        norms();
-        __syncthreads();
         build_masks(0, 0);
         __syncthreads();
         // within-chunk part of x, and the accumulators' part
@@ -508,8 +506,6 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
                 Tc = on[kb][r] ? tk : Tc;
             }
         }
-        __syncthreads();
-        norms();
         __syncthreads();
         build_masks(2, 2);
         __syncthreads();
