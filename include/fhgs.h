@@ -117,7 +117,10 @@ typedef enum {
  * means [n,3], scales [n,3] (> 0), quats [n,4] (w, x, y, z; normalised inside,
  * gradients include the normalisation), opacity [n] in (0, 1),
  * sh [n, (sh_degree+1)^2, 3], feat [n, d] (FP32 or BF16 per feat_dtype; the
- * frozen semantic feature f_i, never differentiated). */
+ * frozen semantic feature f_i, never differentiated).  With n = 0 (an empty
+ * scene: every pixel keeps C = 0, T = 1, n_iter = 0, F = 0) these arrays, and
+ * the per-Gaussian gradient and fusion accumulator arrays of fh_render_bwd,
+ * fh_fuse_features and fh_fuse_finalize, may be NULL. */
 typedef struct {
     const float *means;
     const float *scales;

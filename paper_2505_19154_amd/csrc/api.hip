@@ -75,9 +75,11 @@ static void prof_end(int which, hipStream_t s) {
 }
 
 static bool gaussians_ok(const fh_plan* p, const fh_gaussians* g) {
-    if (!g || !g->means || !g->scales || !g->quats || !g->opacity || !g->sh) return false;
+    if (!g) return false;
     if (g->n != p->n || g->sh_degree != p->sh_degree || g->d != p->d) return false;
-    if (p->d > 0 && !g->feat) return false;
+    // (an empty scene may pass NULL arrays: nothing is read from them)
+    if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh)) return false;
+    if (g->n > 0 && p->d > 0 && !g->feat) return false;
     if (g->feat_dtype != p->feat_dtype) return false;
     return true;
 }
@@ -397,7 +399,7 @@ fh_status fh_project(const fh_plan* p, const fh_gaussians* g, void* ws, hipStrea
     a.rect = buf<int4>(p, ws, WS_RECT);
     a.counters = c;
     prof_begin(FH_K_PROJECT, s);
-    launch_project(a, cam_table(*p), view_table(*p), p->n_views, s);
+    if (p->n > 0) launch_project(a, cam_table(*p), view_table(*p), p->n_views, s);
     prof_end(FH_K_PROJECT, s);
     return launch_status();
 }
@@ -639,9 +641,11 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
                         hipStream_t s) {
     if (!p || !ws || !fwd || !up || !out || !gaussians_ok(p, g)) return FH_E_INVALID;
     if (!fwd->T || !fwd->n_iter || !up->dC) return FH_E_INVALID;
-    if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh) return FH_E_INVALID;
+    // (per-Gaussian arrays may be NULL for an empty scene)
+    if (p->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)) return FH_E_INVALID;
     const bool fuse = fusion_target != nullptr;
-    if (fuse && (!acc || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)) return FH_E_INVALID;
+    if (fuse && (!acc || p->d == 0)) return FH_E_INVALID;
+    if (fuse && p->n > 0 && (!acc->sum || !acc->comp || !acc->wsum || !acc->wcomp)) return FH_E_INVALID;
     // the BF16 form feeds the target to the MFMA as is: it must be BF16
     if (fuse && p->form == FH_FORM_BF16 && target_dtype != FH_BF16) return FH_E_UNSUPPORTED;
     if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
@@ -679,7 +683,7 @@ fh_status fh_render_bwd(const fh_plan* p, const fh_gaussians* g, void* ws, const
     fill_reduce_args(p, ws, r);
     prof_begin(FH_K_REDUCE, s);
     visit_sort(p, ws, s);
-    launch_reduce_geom(r, geom_w(p), s);
+    if (p->n > 0) launch_reduce_geom(r, geom_w(p), s);
     if (fuse) {
         r.acc_sum = acc->sum;
         r.acc_comp = acc->comp;
@@ -733,8 +737,8 @@ fh_status fh_ndfd_losses(const fh_plan* p, const fh_gaussians* g, void* ws, cons
 fh_status fh_fuse_features(const fh_plan* p, const fh_gaussians* g, void* ws, const fh_image* fwd, const void* target,
                            fh_dtype target_dtype, const fh_fusion* acc, hipStream_t s) {
     if (!p || !ws || !fwd || !target || !acc || !gaussians_ok(p, g)) return FH_E_INVALID;
-    if (!fwd->T || !fwd->n_iter || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || p->d == 0)
-        return FH_E_INVALID;
+    if (!fwd->T || !fwd->n_iter || p->d == 0) return FH_E_INVALID;
+    if (p->n > 0 && (!acc->sum || !acc->comp || !acc->wsum || !acc->wcomp)) return FH_E_INVALID;
     if (p->form == FH_FORM_BF16 && target_dtype != FH_BF16) return FH_E_UNSUPPORTED;
     if (p->inst_capacity <= 0 || p->visit_capacity <= 0) return FH_E_INVALID;
     if (!tuning_ok(p)) return FH_E_UNSUPPORTED;
@@ -861,8 +865,8 @@ fh_status fh_set_kernel_events(fh_kernel which, hipEvent_t* start, hipEvent_t* s
 
 fh_status fh_fuse_finalize(const fh_fusion* acc, int64_t n, int32_t d, const void* feat_in, void* feat_out,
                            fh_dtype dtype, hipStream_t s) {
-    if (!acc || !acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || !feat_out || n < 0 || d <= 0)
-        return FH_E_INVALID;
+    if (!acc || n < 0 || d <= 0) return FH_E_INVALID;
+    if (n > 0 && (!acc->sum || !acc->comp || !acc->wsum || !acc->wcomp || !feat_out)) return FH_E_INVALID;
     if (dtype != FH_F32 && dtype != FH_BF16) return FH_E_INVALID;
     launch_fuse_finalize(acc->sum, acc->comp, acc->wsum, acc->wcomp, n, d, feat_in, feat_out, dtype == FH_BF16, s);
     return launch_status();

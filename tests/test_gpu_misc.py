@@ -34,6 +34,42 @@ def test_all_culled_scene():
         assert torch.all(v == 0), k
 
 
+@pytest.mark.parametrize("form,prim", [("f32", "gaussian"), ("bf16", "gaussian"), ("bf16", "surfel")])
+def test_empty_scene(form, prim):
+    """No Gaussians at all (n = 0, the arrays empty): every pixel of both views
+    keeps C = 0, T = 1, n_iter = 0, F = 0; the adjoint with fusion and the NDFD
+    gradient, the NDFD losses and the finalisation run and return empty
+    per-Gaussian results and zero losses."""
+    from paper_2505_19154_amd.raster import FusionAcc, Rasterizer, fuse_finalize
+    d = 32
+    g = scenegen.make_gaussians(0, 1.0, 1, d, seed=0, feat_dtype="bf16")
+    cams = [scenegen.look_at_camera((0, -4, 0), 40, 24), scenegen.look_at_camera((3, -2.5, 1.2), 23, 17)]
+    dg = U.device_gaussians(g)
+    print(f"\n[empty scene {form} {prim}]", flush=True)
+    r = Rasterizer(cams, 0, 1, d, feat_dtype="bf16", form=form, primitive=prim, ndfd=True)
+    img = r.forward(dg)
+    torch.cuda.synchronize()
+    c = r.counters()
+    assert c.n_instances == 0 and c.n_visited == 0
+    assert torch.all(img.C == 0) and torch.all(img.T == 1) and torch.all(img.n_iter == 0) and torch.all(img.F == 0)
+    vts = U.view_maps(cams, d, with_dT=True, target_dtype="bf16")
+    tg = U.concat(vts, "target_bits")
+    P = r.n_pixels
+    ab = torch.ones(P, device="cuda")
+    Lgt = torch.full((P,), float("nan"), device="cuda")
+    Lcf = torch.full((P,), float("nan"), device="cuda")
+    acc = FusionAcc.zeros(0, d, "cuda")
+    grads = r.render_bwd(dg, img, U.concat(vts, "dC"), U.concat(vts, "dF"), U.concat(vts, "dT"), target=tg, acc=acc,
+                         ndfd=dict(gt=tg, a=ab, b=ab, lam=0.5, k=20.0, Lgt=Lgt, Lcf=Lcf))
+    l_gt, l_cf = r.ndfd_losses(dg, img, tg)
+    out = fuse_finalize(acc, None)
+    torch.cuda.synchronize()
+    for k, v in grads.items():
+        assert v.shape[0] == 0, k
+    assert torch.all(Lgt == 0) and torch.all(Lcf == 0) and torch.all(l_gt == 0) and torch.all(l_cf == 0)
+    assert tuple(out.shape) == (0, d)
+
+
 def test_single_gaussian_matches_oracle():
     g = scenegen.make_gaussians(1, 0.1, 2, 16, seed=3)
     g["opacity"][:] = 0.8

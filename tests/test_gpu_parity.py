@@ -36,6 +36,13 @@ SCENES = {
     # three-term splits in its 8-row shapes (128- and 256-channel slices)
     "fsplit_d128": (1500, 1.5, 1, 128, "f32", "front100x70", "f32"),
     "fsplit_d256": (1200, 1.5, 1, 256, "f32", "front96x80", "f32"),
+    # images smaller than one tile (the only tile ragged in both directions):
+    # 7 x 5 pixels in the BF16-MFMA form, a single pixel in the FP32 form, and
+    # 13 x 3 pixels of surfels at d = 64 (none of their pixels decides a
+    # near-threshold skip or stop)
+    "subtile_7x5_mfma": (400, 1.0, 2, 32, "bf16", "front7x5", "bf16"),
+    "one_pixel": (300, 1.0, 1, 8, "f32", "front1x1", "f32"),
+    "subtile_surfel_13x3": (400, 1.0, 1, 64, "bf16", "front13x3", "bf16", "surfel"),
     # splats of 1-2 tiles: some 2048-instance duplication ranges span more
     # than 1024 ranks (up to 1260) and take the per-instance rank search
     "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
