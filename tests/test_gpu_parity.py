@@ -43,6 +43,11 @@ SCENES = {
     "subtile_7x5_mfma": (400, 1.0, 2, 32, "bf16", "front7x5", "bf16"),
     "one_pixel": (300, 1.0, 1, 8, "f32", "front1x1", "f32"),
     "subtile_surfel_13x3": (400, 1.0, 1, 64, "bf16", "front13x3", "bf16", "surfel"),
+    # the largest sizes the plan accepts: d = 1024 (BF16 form: the adjoint and
+    # fusion in four 256-channel slices) and 32 views (a ring of small cameras
+    # of 20 different sizes, one plan, one sort)
+    "max_d1024": (600, 1.5, 1, 1024, "bf16", "front48x40", "bf16"),
+    "max_views32": (800, 1.2, 1, 8, "f32", "ring32", "f32"),
     # splats of 1-2 tiles: some 2048-instance duplication ranges span more
     # than 1024 ranks (up to 1260) and take the per-instance rank search
     "tiny_splats": (4000, 1.5, 0, 8, "f32", "front40x40", "f32"),
@@ -74,6 +79,10 @@ def _scene(name, seed=0):
     if camr == "three":
         cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in
                 (((0, -4, 0), 96, 80), ((3, -2.5, 1.2), 130, 70), ((-2, 1.5, 3.2), 64, 64))]
+    elif camr == "ring32":
+        cams = [scenegen.look_at_camera((4.0 * np.cos(a), 4.0 * np.sin(a), 0.8 * np.sin(3 * a)),
+                                        20 + (i % 5) * 3, 16 + (i % 4) * 5)
+                for i, a in enumerate(np.linspace(0.0, 2.0 * np.pi, 32, endpoint=False))]
     else:
         cams = scenegen.make_cameras(camr)
     return g, cams
