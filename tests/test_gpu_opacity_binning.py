@@ -17,13 +17,28 @@ SCENES = {
     # name: (n, half_extent, sh_degree, d, feat_dtype, cameras, form)
     "sh3_ragged": (3000, 1.5, 3, 32, "f32", [((0, -4, 0), 200, 150)], "f32"),
     "mfma_d64_multiview": (2000, 1.2, 2, 64, "bf16", [((0, -4, 0), 96, 80), ((3, -2.5, 1.2), 130, 70)], "bf16"),
+    # every third Gaussian's opacity straddles the rule's cut-off 255 o = 1
+    # (no instances at or below it; tiny boxes just above): uniform in
+    # [0.5/255, 2/255], plus float32(1/255) and its two neighbours
+    "low_opacity": (2400, 1.2, 1, 32, "bf16", [((0, -4, 0), 112, 88)], "bf16", "low_opacity"),
 }
+
+
+def _low_opacity(g):
+    op = np.asarray(g["opacity"], np.float32).copy()
+    idx = np.arange(0, op.size, 3)
+    op[idx] = np.random.default_rng(11).uniform(0.5 / 255, 2.0 / 255, idx.size).astype(np.float32)
+    c = np.float32(1.0 / 255.0)
+    op[idx[:3]] = [np.nextafter(c, np.float32(0)), c, np.nextafter(c, np.float32(1))]
+    g["opacity"] = op
 
 
 @pytest.fixture(scope="module", params=list(SCENES))
 def case(request):
-    n, h, deg, d, fdt, cams_spec, form = SCENES[request.param]
+    n, h, deg, d, fdt, cams_spec, form = SCENES[request.param][:7]
     g = scenegen.make_gaussians(n, h, deg, d, seed=0, feat_dtype=fdt)
+    if SCENES[request.param][7:] == ("low_opacity",):
+        _low_opacity(g)
     cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in cams_spec]
     vts = U.view_maps(cams, d, with_dT=True, target_dtype="bf16" if form == "bf16" else "f32")
     print(f"\n[opacity-binning {request.param}]", flush=True)
@@ -44,6 +59,15 @@ def test_binning_bit_exact(case):
     assert np.array_equal(gids.cpu().numpy().astype(np.int64), ora["bins"]["gids"])
     ranges = gpu["r"].ws_view("ranges", torch.int32, gpu["r"].n_tiles * 2).cpu().numpy().reshape(-1, 2)
     assert np.array_equal(ranges.astype(np.int64), ora["bins"]["ranges"])
+    if case["name"] == "low_opacity":
+        # the cut-off itself: no instance at or below 255 o = 1, boxes just above
+        op = np.asarray(case["g"]["opacity"])
+        has = np.zeros(op.size, bool)
+        has[np.unique(gids.cpu().numpy().astype(np.int64))] = True
+        below, above = op < 0.99 / 255, (op > 1.01 / 255) & (op < 2.0 / 255)
+        assert below.sum() > 100 and not has[below].any()
+        assert above.sum() > 100 and has[above].all()
+        assert has[[0, 3, 6]].tolist() == [False, False, True]   # 1/255's neighbour below, 1/255, neighbour above
     n = case["g"]["means"].shape[0]
     rect = gpu["r"].ws_view("rect", torch.int32, 4 * n * len(case["cams"])).cpu().numpy().reshape(-1, 4)
     for vi, bq in enumerate(ora["bins"]["per_view"]):
