@@ -61,6 +61,11 @@ SCENES = {
     "surfel_mfma_d64": (2000, 1.5, 2, 64, "bf16", "front120x90", "bf16", "surfel"),
     "surfel_mfma_d256_multiview": (1200, 1.2, 1, 256, "bf16", "three", "bf16", "surfel"),
     "surfel_mfma_d512": (900, 1.5, 1, 512, "bf16", "front64x48", "bf16", "surfel"),
+    # every tenth surfel edge-on (the plane z = 0 holds the view direction):
+    # the middle pixel row (odd height) casts rays inside those planes, where
+    # the intersection does not exist and the density is zero, and their
+    # disc images bin as one row of tiles
+    "surfel_edge_on": (1500, 1.5, 1, 32, "bf16", "front96x81", "bf16", "surfel", "edge_on"),
 }
 # BF16-MFMA form: F, the feature part of the adjoint and the fusion sums are
 # contractions over two-term BF16 splits (tests/gpu_util.py: RTOL_FORM).
@@ -76,6 +81,12 @@ def _scene(name, seed=0):
     g = scenegen.make_gaussians(n, h, deg, d, seed=seed, feat_dtype=fdt)
     if _rule(name) == "surfel":
         g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
+    if SCENES[name][8:] == ("edge_on",):
+        idx = np.arange(0, n, 10)
+        q, m = np.asarray(g["quats"]).copy(), np.asarray(g["means"]).copy()
+        q[idx] = [1.0, 0.0, 0.0, 0.0]   # tangents x and y: the plane z = const
+        m[idx, 2] = 0.0                 # through the camera centre's height
+        g["quats"], g["means"] = q.astype(np.float32), m.astype(np.float32)
     if camr == "three":
         cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in
                 (((0, -4, 0), 96, 80), ((3, -2.5, 1.2), 130, 70), ((-2, 1.5, 3.2), 64, 64))]
