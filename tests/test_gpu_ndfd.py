@@ -35,6 +35,9 @@ SCENES = {
     "surfel_d64": (700, 1.5, 64, 2, [((0, -4, 0), 56, 44)], "surfel"),
     "surfel_d256": (600, 1.5, 256, 1, [((0, -4, 0), 48, 40)], "surfel"),
     "surfel_d32_two_views": (700, 1.5, 32, 7, [((0, -4, 0), 64, 48), ((3, -2.5, 1.2), 50, 40)], "surfel"),
+    # zero vectors, whose unit vector is taken as zero: the features of every
+    # seventh Gaussian and F_gt of every fifth pixel
+    "d64_zero_vectors": (1200, 1.2, 64, 17, [((0, -4, 0), 64, 48)], "gaussian", "zeros"),
 }
 
 
@@ -48,6 +51,11 @@ def _scene(name, with_colour=False):
     if _prim(name) == "surfel":
         g["scales"] = (np.asarray(g["scales"]) * 3.0).astype(np.float32)
     g["primitive"] = _prim(name)
+    zeros = SCENES[name][6:] == ("zeros",)
+    if zeros:
+        g["feat_bits"] = np.asarray(g["feat_bits"]).copy()
+        g["feat_bits"][::7] = 0
+        g["feat"] = scenegen.bf16_bits_to_f32(g["feat_bits"]).astype(np.asarray(g["feat"]).dtype)
     cams = [scenegen.look_at_camera(p, w, hh) for p, w, hh in camspec]
     F = pipeline.run(g, cams, bin_rule=_rule(g))["views"]
     rng = np.random.default_rng(700 + seed)
@@ -56,6 +64,8 @@ def _scene(name, with_colour=False):
         Fv = F[vi]["F"]
         gt = Fv + 0.5 * rng.normal(size=Fv.shape) * (np.abs(Fv).mean() + 1e-3)
         gtb = scenegen.to_bf16_bits(gt.astype(np.float32))
+        if zeros:
+            gtb[::5] = 0
         P = c.npix
         vt = dict(dC=np.zeros((P, 3)), dF=np.zeros((P, d)), dT=np.zeros(P),
                   gt=scenegen.bf16_bits_to_f32(gtb).astype(np.float64), gt_bits=gtb,
