@@ -213,19 +213,34 @@ __global__ __launch_bounds__(512) void k_ndfd(NdfdArgs a, ViewTable vt) {
     };
     auto commit = [&]() {
         if ((int)threadIdx.x < RD * NK) reinterpret_cast<float*>(srec)[4 * prec_slot<SURF, NRG>(rk) + rj] = prec;
-        // item = (position k, 8-channel group dg), k fastest: a wave's 2-byte
-        // stores of the transposed tile then fill consecutive bank slots
+        // item = (position k, 8-channel group dg), k fastest.  The transposed
+        // tile is written in 4-byte words holding positions (2p, 2p + 1) of one
+        // channel: the neighbouring lane (k ^ 1, same dg) passes its row, the
+        // even lane writes channels 0-3 of the group and the odd lane 4-7, so
+        // that a store's four lane groups (even / odd, two dg) meet disjoint
+        // bank ranges (rows 8 channels apart are 160 words apart).
         uint16_t* f16 = reinterpret_cast<uint16_t*>(sfeat);
-        uint16_t* ft16 = reinterpret_cast<uint16_t*>(sfeatT);
+        uint32_t* ft32 = reinterpret_cast<uint32_t*>(sfeatT);
+        const bool odd = (kk & 1) != 0;
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
             const int idx = threadIdx.x + NT * it;
+            // (every lane of a wave takes part in the exchange; NT is a multiple of 64)
+            const uint4 nb = make_uint4(__shfl_xor(praw[it].x, 1), __shfl_xor(praw[it].y, 1),
+                                        __shfl_xor(praw[it].z, 1), __shfl_xor(praw[it].w, 1));
             if (idx < ITEMS) {
                 const int dg = idx / NK;
                 *reinterpret_cast<uint4*>(&f16[kk * DP + dg * 8]) = praw[it];
-                const uint16_t* h = reinterpret_cast<const uint16_t*>(&praw[it]);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) ft16[(dg * 8 + m) * NJP + kk] = h[m];
+                // words of channels 2j, 2j + 1 (j = 0, 1 even lanes; 2, 3 odd lanes)
+                const uint4 lo4 = odd ? nb : praw[it], hi4 = odd ? praw[it] : nb;   // positions 2p, 2p + 1
+                const uint32_t wl0 = odd ? lo4.z : lo4.x, wl1 = odd ? lo4.w : lo4.y;
+                const uint32_t wh0 = odd ? hi4.z : hi4.x, wh1 = odd ? hi4.w : hi4.y;
+                const int m0 = odd ? 4 : 0;
+                uint32_t* row = ft32 + (dg * 8 + m0) * (NJP / 2) + (kk >> 1);
+                row[0 * (NJP / 2)] = (wl0 & 0xFFFFu) | (wh0 << 16);
+                row[1 * (NJP / 2)] = (wl0 >> 16) | (wh0 & 0xFFFF0000u);
+                row[2 * (NJP / 2)] = (wl1 & 0xFFFFu) | (wh1 << 16);
+                row[3 * (NJP / 2)] = (wl1 >> 16) | (wh1 & 0xFFFF0000u);
             }
         }
     };
